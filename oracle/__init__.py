@@ -1,0 +1,207 @@
+"""CPU oracle for xGETT (plain FP64 nested loops) -- test infrastructure only.
+
+Only the tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` use this package.  It never imports the GPU library and the GPU
+library never imports it.  The arithmetic lives in ``gett_oracle.c`` (built to
+``liboracle.so`` by :func:`build`); this module only marshals numpy buffers.
+
+Every tensor argument is a *view*: a 1-D numpy parent buffer, the element
+index of coordinate (0,...,0) in it, extents and element increments
+(Section 5.4, Tensor multiplication: increments are the memory jumps between
+neighbouring data points; Section 5.7 gives the argument order).
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gett_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+I64P = ct.POINTER(ct.c_int64)
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (OpenMP over output elements, no FMA
+    contraction, IEEE semantics)."""
+    if not force and os.path.exists(_LIB):
+        return _LIB
+    tmp = _LIB + ".tmp"
+    cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+           "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
+    subprocess.check_call(cmd)
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = ct.CDLL(_LIB)
+        vp = ct.c_void_p
+        i64 = ct.c_int64
+        args14 = [i64, I64P, I64P, vp, i64, I64P, I64P, vp, i64, I64P, I64P, I64P, I64P, vp]
+        L.gett_ref_check.argtypes = args14
+        L.gett_ref_check.restype = ct.c_int
+        L.gett_ref_dgett.argtypes = args14
+        L.gett_ref_dgett.restype = ct.c_int
+        L.gett_ref_sgett_f64.argtypes = args14 + [vp, vp, i64, i64]
+        L.gett_ref_sgett_f64.restype = ct.c_int
+        L.gett_ref_dgett_range.argtypes = args14 + [vp, vp, i64, i64]
+        L.gett_ref_dgett_range.restype = ct.c_int
+        L.gett_ref_num_threads.restype = ct.c_int
+        L.gett_ref_set_num_threads.argtypes = [ct.c_int]
+        L.gett_ref_output_offsets.argtypes = [i64, I64P, I64P, i64, I64P, I64P, i64, I64P, I64P,
+                                              I64P, I64P, i64, I64P, I64P]
+        L.gett_ref_bf16_split.argtypes = [i64, vp, vp, vp]
+        L.gett_ref_e4m3_decode.argtypes = [ct.c_uint8]
+        L.gett_ref_e4m3_decode.restype = ct.c_double
+        L.gett_ref_e4m3_encode.argtypes = [ct.c_double]
+        L.gett_ref_e4m3_encode.restype = ct.c_uint8
+        L.gett_ref_fp8_scale_exp.argtypes = [ct.c_double]
+        L.gett_ref_fp8_scale_exp.restype = ct.c_int
+        L.gett_ref_fp8_quantize.argtypes = [vp, i64, vp, i64, vp, vp, vp]
+        L.gett_ref_fp8_gemm.argtypes = [i64, i64, i64, vp, vp, vp, vp, vp]
+        _lib = L
+    return _lib
+
+
+def _arr(v):
+    v = [int(x) for x in (v or [])]
+    if not v:
+        return None
+    return (ct.c_int64 * len(v))(*v)
+
+
+def _ptr(buf: np.ndarray | None, base: int):
+    if buf is None:
+        return None
+    return ct.c_void_p(buf.ctypes.data + int(base) * buf.itemsize)
+
+
+def check(ranka, exta, inca, rankb, extb, incb, conts, conta, contb, perm, incc,
+          A=1, B=1, C=1) -> int:
+    """INFO code of the oracle's own argument checks (0 = valid).  A, B, C are
+    only tested for NULL (pass 0 / None for a NULL pointer)."""
+    p = lambda x: None if not x else ct.c_void_p(8)
+    return lib().gett_ref_check(ranka, _arr(exta), _arr(inca), p(A), rankb, _arr(extb),
+                                _arr(incb), p(B), conts, _arr(conta), _arr(contb), _arr(perm),
+                                _arr(incc), p(C))
+
+
+def dgett(pr, A, B, C) -> int:
+    """FP64 xGETT in place on the oracle: C <- C + sum A*B (Algorithm 1).
+    ``pr`` carries the integer arguments; A, B, C are views over float64."""
+    return lib().gett_ref_dgett(pr.ranka, _arr(pr.exta), _arr(pr.inca), _ptr(A.buf, A.base),
+                                pr.rankb, _arr(pr.extb), _arr(pr.incb), _ptr(B.buf, B.base),
+                                pr.conts, _arr(pr.conta), _arr(pr.contb), _arr(pr.perm),
+                                _arr(pr.incc), _ptr(C.buf, C.base))
+
+
+def exact(pr, A, B, C, first: int = 0, last: int = -1):
+    """Exact-in-double contraction of the views' values (float32 or float64):
+    returns (Cout, Cabs) as float64 parent buffers shaped like C's parent,
+    Cout = C_in + sum a*b and Cabs = |C_in| + sum |a||b| at every output
+    position of [first, last) of the free odometer; other entries are NaN."""
+    cout = np.full(C.buf.shape, np.nan, dtype=np.float64)
+    cabs = np.full(C.buf.shape, np.nan, dtype=np.float64)
+    args = (pr.ranka, _arr(pr.exta), _arr(pr.inca), _ptr(A.buf, A.base),
+            pr.rankb, _arr(pr.extb), _arr(pr.incb), _ptr(B.buf, B.base),
+            pr.conts, _arr(pr.conta), _arr(pr.contb), _arr(pr.perm),
+            _arr(pr.incc), _ptr(C.buf, C.base), _ptr(cout, C.base), _ptr(cabs, C.base),
+            int(first), int(last))
+    if A.buf.dtype == np.float32:
+        assert B.buf.dtype == np.float32 and C.buf.dtype == np.float32
+        info = lib().gett_ref_sgett_f64(*args)
+    else:
+        assert A.buf.dtype == np.float64 and B.buf.dtype == np.float64 and C.buf.dtype == np.float64
+        info = lib().gett_ref_dgett_range(*args)
+    if info:
+        raise ValueError(f"oracle rejected the arguments: INFO={info}")
+    return cout, cabs
+
+
+def num_threads() -> int:
+    return int(lib().gett_ref_num_threads())
+
+
+# --------------------------------------------------------------------------
+# Canonical orders used by the quantised path: rows of A are A's free modes in
+# ascending order (first mode fastest), rows of B likewise for B, and the
+# contracted positions follow the pairs in CONTA/CONTB order, first pair
+# fastest (the order of Algorithm 1's contracted odometer).
+# --------------------------------------------------------------------------
+def _odometer_offsets(ext, inc):
+    off = np.zeros(1, dtype=np.int64)
+    for e, s in zip(ext, inc):            # first mode fastest: index c*len(off) + old
+        off = (off[None, :] + (np.arange(e, dtype=np.int64) * s)[:, None]).reshape(-1)
+    return off
+
+
+def canonical_offsets(pr):
+    """(rowsA, rowsB, kA, kB): element offsets of the canonical row and
+    contracted orders described above."""
+    ca, cb = list(pr.conta), list(pr.contb)
+    fa = [i for i in range(pr.ranka) if i not in ca]
+    fb = [j for j in range(pr.rankb) if j not in cb]
+    rowsA = _odometer_offsets([pr.exta[i] for i in fa], [pr.inca[i] for i in fa])
+    rowsB = _odometer_offsets([pr.extb[j] for j in fb], [pr.incb[j] for j in fb])
+    kA = _odometer_offsets([pr.exta[i] for i in ca], [pr.inca[i] for i in ca])
+    kB = _odometer_offsets([pr.extb[j] for j in cb], [pr.incb[j] for j in cb])
+    return rowsA, rowsB, kA, kB
+
+
+def fp8_quantize(X, rows_off, k_off):
+    """Quantise a float32 view (buffer + base) into E4M3 codes with one
+    power-of-two scale per row per 128 contracted positions.  Returns
+    (codes uint8 [rows, Kp], exponents int32 [rows, blocks])."""
+    rows = len(rows_off)
+    K = len(k_off)
+    nb = (K + 127) // 128
+    Q = np.zeros((rows, nb * 128), dtype=np.uint8)
+    E = np.zeros((rows, nb), dtype=np.int32)
+    ro = np.ascontiguousarray(rows_off, dtype=np.int64)
+    ko = np.ascontiguousarray(k_off, dtype=np.int64)
+    lib().gett_ref_fp8_quantize(_ptr(X.buf, X.base), rows, ro.ctypes.data, K, ko.ctypes.data,
+                                Q.ctypes.data, E.ctypes.data)
+    return Q, E
+
+
+def fp8_gemm(QA, EA, QB, EB, K):
+    """Exact double value of the quantised product, out[m, n]."""
+    M, N = QA.shape[0], QB.shape[0]
+    out = np.zeros((N, M), dtype=np.float64)
+    lib().gett_ref_fp8_gemm(M, N, K, np.ascontiguousarray(QA).ctypes.data,
+                            np.ascontiguousarray(EA).ctypes.data,
+                            np.ascontiguousarray(QB).ctypes.data,
+                            np.ascontiguousarray(EB).ctypes.data, out.ctypes.data)
+    return out.T
+
+
+def e4m3_decode(code: int) -> float:
+    return float(lib().gett_ref_e4m3_decode(code))
+
+
+def e4m3_encode(v: float) -> int:
+    return int(lib().gett_ref_e4m3_encode(float(v)))
+
+
+def fp8_scale_exp(amax: float) -> int:
+    return int(lib().gett_ref_fp8_scale_exp(float(amax)))
+
+
+def bf16_split(x: np.ndarray):
+    """(hi, lo) float32 arrays: hi = bf16(x), lo = bf16(x - hi), round to
+    nearest even."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    hi = np.empty_like(x)
+    lo = np.empty_like(x)
+    lib().gett_ref_bf16_split(x.size, x.ctypes.data, hi.ctypes.data, lo.ctypes.data)
+    return hi, lo
