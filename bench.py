@@ -1,0 +1,207 @@
+#!/usr/bin/env python3
+"""Benchmark of the xGETT hot path on one MI355X.
+
+Workload: the strided + permuted contraction
+    C[b,e,a,d] = sum_{c,f} A[a,b,c,f] B[f,d,c,e]
+with A of extents (48,64,96,40) read with step 2 on every mode of a packed
+(96,128,192,80) parent, B (40,56,96,72) dense, C dense (M, N, K = 3072,
+4032, 3840; 2MNK = 9.513e10 flops), values normal(0,1) from a fixed seed.
+Inputs are resident in HBM before the timed region starts.
+
+One step = one xGETT call of the primary path (DGETT, FP64).  The same
+workload also runs through SGETT (FP32 MFMA), split BF16x3 SGETT and FP8
+SGETT; their rates and errors against the FP64 oracle (on a sample of
+outputs) are reported under "paths".  Kernel durations come from HIP events
+recorded on the library's stream around every call.
+
+    python bench.py [--gpus 1] [--steps 20] [--warmup 3]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+METRIC = "xGETT TFLOP/s & % MFMA peak: plain FP64/FP32 vs split-BF16 at stated rel err"
+PEAK = {"f64": 78.6, "f32": 157.3, "bf16": 2516.6, "fp8": 5033.2}   # dense MFMA TFLOP/s
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--paths", default="f64,f32,bf16x3,fp8")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-check", action="store_true", help="skip the sampled error check")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target duration of the CPU oracle sample")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; the contraction is "
+                                   "not sharded across GPUs in this build (see DESIGN.md)",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(2)
+    from paper_2410_06770_amd import gett, workloads as W
+
+    gett.lib()
+    stream = torch.cuda.current_stream()
+    gett.gett_set_stream(stream.cuda_stream)
+
+    paths = [p for p in args.paths.split(",") if p]
+    entry = {"f64": gett.dgett, "f32": gett.sgett, "bf16x3": gett.sgett_bf16x3,
+             "fp8": gett.sgett_fp8}
+    results = {}
+    problems = {}
+    for path in paths:
+        dtype = np.float64 if path == "f64" else np.float32
+        if dtype not in problems:
+            problems[dtype] = W.config_strided_perm(dtype=dtype)
+    pr64 = problems.get(np.float64) or W.config_strided_perm(dtype=np.float64)
+    M, N, K = pr64.mnk()
+    flops = 2.0 * M * N * K
+    print(f"[bench] workload M={M} N={N} K={K} flops={flops:.4e}", file=sys.stderr, flush=True)
+
+    primary = None
+    for path in paths:
+        dtype = np.float64 if path == "f64" else np.float32
+        pr = problems[dtype]
+        tdt = torch.float64 if dtype == np.float64 else torch.float32
+        At = torch.from_numpy(pr.A.buf).to("cuda")
+        Bt = torch.from_numpy(pr.B.buf).to("cuda")
+        Ct = torch.zeros(pr.C.buf.shape, dtype=tdt, device="cuda")
+        esz = At.element_size()
+        a = At.data_ptr() + pr.A.base * esz
+        b = Bt.data_ptr() + pr.B.base * esz
+        c = Ct.data_ptr() + pr.C.base * esz
+        fn = entry[path]
+
+        def call():
+            rc = fn(pr.ranka, pr.exta, pr.inca, a, pr.rankb, pr.extb, pr.incb, b, pr.conts,
+                    pr.conta, pr.contb, pr.perm, pr.incc, c)
+            if rc:
+                raise RuntimeError(f"{path}: {gett.strerror(rc)}")
+
+        print(f"[bench] path {path}: first call", file=sys.stderr, flush=True)
+        call()                      # also builds the plan
+        torch.cuda.synchronize()
+        err = {}
+        if not args.no_check:
+            err = sampled_error(pr, Ct.cpu().numpy())
+        sched = gett.gett_last_schedule()
+        for _ in range(args.warmup):
+            call()
+        torch.cuda.synchronize()
+        starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+        ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            starts[i].record(stream)
+            call()
+            ends[i].record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        durs = [s.elapsed_time(e) for s, e in zip(starts, ends)]
+        ms = float(np.mean(durs))
+        tflops = flops / (ms * 1e-3) / 1e12
+        peak = {"f64": PEAK["f64"], "f32": PEAK["f32"], "bf16x3": PEAK["f32"],
+                "fp8": PEAK["fp8"]}[path]
+        res = {"tflops": round(tflops, 3), "ms": round(ms, 4), "ms_min": round(min(durs), 4),
+               "pct_peak": round(100 * tflops / peak, 2), "peak_tflops": peak,
+               "schedule": int(sched), "wall_ms_per_step": round(1e3 * wall / args.steps, 4)}
+        if path == "bf16x3":
+            res["bf16_mfma_util_pct"] = round(100 * 3 * tflops / PEAK["bf16"], 2)
+        res.update(err)
+        results[path] = res
+        print(f"[bench] {path}: {json.dumps(res)}", file=sys.stderr, flush=True)
+        if primary is None:
+            primary = (path, ms, tflops, peak, wall)
+        del At, Bt, Ct
+        torch.cuda.empty_cache()
+
+    if "f32" in results and "bf16x3" in results:
+        results["bf16x3"]["speedup_vs_f32"] = round(results["f32"]["ms"] / results["bf16x3"]["ms"], 3)
+
+    path, ms, tflops, peak, wall = primary
+    out = {
+        "metric": METRIC,
+        "value": round(tflops, 3),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"f64": "f64", "f32": "f32", "bf16x3": "bf16x3(f32 acc, f64 sum)",
+                  "fp8": "e4m3(f32 acc)"}[path],
+        "data": "synthetic (seeded normal(0,1))",
+        "config": {"workload": "strided_perm: C[b,e,a,d] = sum_{c,f} A[a,b,c,f] B[f,d,c,e]; "
+                               "A (48,64,96,40) step 2 in a (96,128,192,80) parent, "
+                               "B (40,56,96,72) dense, C dense",
+                   "M": M, "N": N, "K": K, "flops_per_step": flops, "path": path},
+        "roofline": {"bound": "mfma", "achieved": round(tflops, 3), "peak": peak,
+                     "unit": "TFLOP/s", "frac": round(tflops / peak, 4), "traffic": None},
+        "paths": results,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(pr64, args.cpu_seconds, flops)
+    print(json.dumps(out))
+
+
+def sampled_error(pr, got, width=1500):
+    """e_nrm / e_cw of the GPU result against the FP64 oracle on three output
+    ranges of the free odometer."""
+    import oracle
+    total = int(np.prod(pr.extc()))
+    num = den = 0.0
+    ecw = 0.0
+    for s in (0, total // 2, total - width):
+        ref, cabs = oracle.exact(pr, pr.A, pr.B, pr.C, s, s + width)
+        sel = ~np.isnan(ref)
+        d = got[sel].astype(np.float64) - ref[sel]
+        num += float(np.sum(d * d))
+        den += float(np.sum(ref[sel] ** 2))
+        with np.errstate(invalid="ignore", divide="ignore"):
+            q = np.where(d == 0, 0.0, np.abs(d) / cabs[sel])
+        ecw = max(ecw, float(np.max(q)))
+    return {"e_nrm": float(np.sqrt(num / den)), "e_cw": ecw, "err_sample": 3 * width}
+
+
+def cpu_baseline(pr, seconds, flops_full):
+    """The oracle as it stands, on the host cores, on the first n outputs of
+    the same workload (n chosen so the run takes about `seconds`)."""
+    import oracle
+    K = pr.mnk()[2]
+    n = 256
+    t = time.perf_counter()
+    oracle.exact(pr, pr.A, pr.B, pr.C, 0, n)
+    dt = time.perf_counter() - t
+    n = int(min(max(n * seconds / max(dt, 1e-3), 512), int(np.prod(pr.extc()))))
+    t = time.perf_counter()
+    oracle.exact(pr, pr.A, pr.B, pr.C, 0, n)
+    dt = time.perf_counter() - t
+    tflops = 2.0 * K * n / dt / 1e12
+    return {"value": tflops, "unit": "TFLOP/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"first {n} of {int(np.prod(pr.extc()))} outputs (x K={K} terms), "
+                      f"FP64, {dt:.2f} s",
+            "est_full_seconds": round(flops_full / (tflops * 1e12), 1)}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,276 @@
+/*
+ * gett.h -- C ABI of libgett.so: binary tensor contraction (xGETT) on AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The operation and its argument list are those of "BLAS-like Interface for
+ * Binary Tensor Contractions" (arXiv 2410.06770):
+ *   - Section 2.2 defines the binary tensor contraction: each value of C is
+ *     the sum, over every coordinate of the contracted indices, of the product
+ *     of the matching values of A and B; paired contracted indices must have
+ *     equal extents; the free indices may appear in C in any order.
+ *   - Section 5.7 fixes the argument order used by every xGETT entry point:
+ *       xGETT(RANKA, EXTA, INCA, A, RANKB, EXTB, INCB, B,
+ *             CONTS, CONTA, CONTB, PERM, INCC, C)
+ *   - Section 6, Algorithm 1 updates C as C <- C + A*B; C is never cleared,
+ *     so these routines ACCUMULATE into C (clear C first for C = A*B).
+ *
+ * Arguments (all integers int64_t, all arrays host memory, read before the
+ * call returns; the library keeps no pointer to them):
+ *   RANKA        rank of A (>= 0).
+ *   EXTA[RANKA]  extents of A (>= 0).  May be NULL when RANKA == 0.
+ *   INCA[RANKA]  element increments of A, any sign (Section 5.4: the memory
+ *                jump between neighbouring data points of each mode).  Units
+ *                are elements, not bytes.  Zero is allowed for inputs.
+ *   A            DEVICE pointer to the element whose coordinates are all zero
+ *                ("the first used data point"); with negative increments the
+ *                other elements lie below it.
+ *   RANKB, EXTB, INCB, B   the same for B.
+ *   CONTS        number of contracted index pairs, 0 <= CONTS <= min(RANKA, RANKB).
+ *   CONTA[CONTS] 0-based modes of A to contract; CONTB[CONTS] the 0-based
+ *                modes of B they pair with (CONTA[k] with CONTB[k]).
+ *   PERM[RC]     RC = RANKA + RANKB - 2*CONTS.  Section 5.6, fourth option:
+ *                entry p describes the p-th free index, counting A's free
+ *                modes in ascending order and then B's; its value is that
+ *                index's 0-based position in C.
+ *   INCC[RC]     element increments of C by OUTPUT position q (the
+ *                "increments of C" of Section 6).  C's rank and extents are
+ *                derived from A, B, CONTA/CONTB and PERM, never passed.
+ *   C            DEVICE pointer to C's element with all-zero coordinates.
+ *
+ * Return value (LAPACK-style INFO):
+ *    0   success (work queued on the calling thread's stream; asynchronous).
+ *   -i   the i-th argument in the order above is invalid:
+ *        -1 RANKA < 0 or > 64; -2 EXTA NULL or an extent < 0; -3 INCA NULL or
+ *        an offset overflows int64; -4 A NULL while A has elements; -5..-8
+ *        the same for B; -9 CONTS out of range; -10 CONTA NULL, out of range
+ *        or repeated; -11 the same for CONTB, or EXTA[CONTA[k]] !=
+ *        EXTB[CONTB[k]]; -12 PERM NULL, out of range or not a permutation;
+ *        -13 INCC NULL, a zero increment on a mode of extent > 1, or an
+ *        overflowing offset; -14 C NULL while C has elements.
+ *        Argument checks run before any HIP call and change nothing.
+ *   >0   runtime error: GETT_ERR_HIP (HIP runtime failure), GETT_ERR_ALLOC
+ *        (device allocation failed), GETT_ERR_DEVICE (current device is not
+ *        gfx950), GETT_ERR_INTERNAL (planner limit, e.g. a group's offset
+ *        table would exceed 2^31 entries), GETT_ERR_STATE (bad control call).
+ *        gett_strerror() names every code.
+ *
+ * Aliasing: A and B may overlap each other and themselves (they are only
+ * read).  C must not overlap itself, A or B (undefined results, as in BLAS).
+ * Extents of zero make the call a no-op.
+ *
+ * Ownership: the caller owns A, B, C and every host array and keeps A, B and
+ * C alive until the stream has reached the queued work.  The library owns its
+ * plan cache (per signature: offset tables in device memory), split-K
+ * workspaces (stream-ordered allocations) and captured batch graphs; all of
+ * it is released by gett_finalize().
+ *
+ * Threads and streams: each host thread has its own current stream
+ * (gett_set_stream; default = the null stream).  The plan cache is shared and
+ * locked.  Calls that overlap on the same C race, as any two writers would.
+ */
+#ifndef GETT_H
+#define GETT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Precision codes (batch calls, schedules, features). */
+#define GETT_FP64   0
+#define GETT_FP32   1
+#define GETT_BF16X3 2
+#define GETT_FP8    3
+
+/* Schedule policies (gett_set_policy). */
+#define GETT_HEURISTIC 0   /* built-in rules (default) */
+#define GETT_PREDICT   1   /* MLP schedule predictor (gett_load_predictor) */
+#define GETT_AUTOTUNE  2   /* time the whole schedule menu on a plan-cache miss */
+
+/* Runtime error codes (> 0). */
+#define GETT_ERR_HIP      1
+#define GETT_ERR_ALLOC    2
+#define GETT_ERR_DEVICE   3
+#define GETT_ERR_INTERNAL 4
+#define GETT_ERR_STATE    5
+
+/* ---------------------------------------------------------------------- */
+/* xGETT entry points (Section 5.7 argument list; semantics above).         */
+/* ---------------------------------------------------------------------- */
+
+/* DGETT: FP64 data, FP64 matrix-core (MFMA) products, FP64 accumulation. */
+int dgett(int64_t ranka, const int64_t *exta, const int64_t *inca, const double *A,
+          int64_t rankb, const int64_t *extb, const int64_t *incb, const double *B,
+          int64_t conts, const int64_t *conta, const int64_t *contb, const int64_t *perm,
+          const int64_t *incc, double *C);
+
+/* SGETT: FP32 data, FP32 MFMA products, FP32 accumulation, C_in added in FP32. */
+int sgett(int64_t ranka, const int64_t *exta, const int64_t *inca, const float *A,
+          int64_t rankb, const int64_t *extb, const int64_t *incb, const float *B,
+          int64_t conts, const int64_t *conta, const int64_t *contb, const int64_t *perm,
+          const int64_t *incc, float *C);
+
+/* SGETT with split BF16x3 products: every FP32 value x is split into
+   hi = bf16(x) and lo = bf16(x - hi) (round to nearest even); the product
+   a*b is formed as hi_a*hi_b + hi_a*lo_b + lo_a*hi_b on BF16 MFMA with FP32
+   accumulation, the hi*hi and cross terms in separate accumulators, which are
+   summed with C_in in FP64 and rounded once to FP32.  Finite inputs only. */
+int sgett_bf16x3(int64_t ranka, const int64_t *exta, const int64_t *inca, const float *A,
+                 int64_t rankb, const int64_t *extb, const int64_t *incb, const float *B,
+                 int64_t conts, const int64_t *conta, const int64_t *contb, const int64_t *perm,
+                 const int64_t *incc, float *C);
+
+/* SGETT on FP8 (OCP E4M3) MFMA.  Rows of A are A's free modes in ascending
+   order (first fastest), rows of B likewise, and the contracted positions
+   follow the CONTA/CONTB pairs, first pair fastest.  Each row is cut into
+   blocks of 128 contracted positions; a block with largest magnitude amax
+   gets the scale 2^e, e the smallest integer >= -127 with amax/2^e <= 448
+   (e = 0 for an all-zero block), and its values are rounded to nearest-even
+   E4M3 after division by 2^e.  Products accumulate in FP32 with the block
+   scales applied; C_in is added in FP32.  Finite inputs only; the error
+   against the exact result is that of the quantisation (report only). */
+int sgett_fp8(int64_t ranka, const int64_t *exta, const int64_t *inca, const float *A,
+              int64_t rankb, const int64_t *extb, const int64_t *incb, const float *B,
+              int64_t conts, const int64_t *conta, const int64_t *contb, const int64_t *perm,
+              const int64_t *incc, float *C);
+
+/* The quantisation step of sgett_fp8 on its own, for one operand: X is a
+   device tensor of rank RANKX with extents/increments EXTX/INCX, CONTS of
+   whose modes (CONTX) are contracted.  Writes codes to QX (device,
+   rows x 128*ceil(K/128) bytes, row-major, zero codes in the padding) and
+   exponents e to EX (device, int32, rows x ceil(K/128)), rows = product of
+   the free extents, K = product of the contracted extents.  Same INFO rules
+   (-1 rank, -2 extents, -3 increments, -4 X, -5 CONTS, -6 CONTX, -7 QX,
+   -8 EX). */
+int sgett_fp8_quantize(int64_t rankx, const int64_t *extx, const int64_t *incx, const float *X,
+                       int64_t conts, const int64_t *contx, uint8_t *QX, int32_t *EX);
+
+/* Batched xGETT: COUNT independent problems run as one persistent kernel
+   launch captured in a HIP graph (replayed when the same batch signature
+   comes again).  Every per-problem argument becomes an array over problems;
+   array arguments become arrays of pointers (primitive types only).  PREC is
+   GETT_FP32 or GETT_BF16X3 for sgett_batch (dgett_batch ignores it).
+   INFO (host array, may be NULL) receives each problem's INFO.  Returns 0;
+   -1 for COUNT < 0; -2 for a bad PREC; -1000*(p+1) + INFO_p for the first
+   problem p whose INFO_p is non-zero (nothing is queued then); or a runtime
+   error code > 0.  Outputs of different problems must not overlap. */
+int sgett_batch(int64_t count, int64_t prec,
+                const int64_t *ranka, const int64_t *const *exta, const int64_t *const *inca,
+                const float *const *A,
+                const int64_t *rankb, const int64_t *const *extb, const int64_t *const *incb,
+                const float *const *B,
+                const int64_t *conts, const int64_t *const *conta, const int64_t *const *contb,
+                const int64_t *const *perm, const int64_t *const *incc, float *const *C,
+                int64_t *info);
+int dgett_batch(int64_t count, int64_t prec,
+                const int64_t *ranka, const int64_t *const *exta, const int64_t *const *inca,
+                const double *const *A,
+                const int64_t *rankb, const int64_t *const *extb, const int64_t *const *incb,
+                const double *const *B,
+                const int64_t *conts, const int64_t *const *conta, const int64_t *const *contb,
+                const int64_t *const *perm, const int64_t *const *incc, double *const *C,
+                int64_t *info);
+
+/* ---------------------------------------------------------------------- */
+/* Control plane (not part of xGETT's argument list).                       */
+/* ---------------------------------------------------------------------- */
+
+/* Current stream of the calling thread (a hipStream_t; NULL = null stream). */
+int   gett_set_stream(void *hip_stream);
+void *gett_get_stream(void);
+
+/* Schedule policy for plan-cache misses (GETT_HEURISTIC/PREDICT/AUTOTUNE). */
+int gett_set_policy(int policy);
+int gett_get_policy(void);
+
+/* Load MLP predictor weights written by the trainer (binary file, see
+   gett_mlp_* below).  Returns 0, or GETT_ERR_STATE for a bad file. */
+int gett_load_predictor(const char *path);
+
+/* Schedules.  A schedule is (tile, order, split): tile indexes the tile menu
+   of the precision, order picks one of GETT_NUM_ORDERS mode orderings, split
+   is the split-K factor index (1, 2, 4, 8).  The flat id is
+   tile + NT*(order + GETT_NUM_ORDERS*split).  A schedule never changes what
+   is computed, only how (the summation order of the contracted sum). */
+#define GETT_NUM_ORDERS 4
+#define GETT_NUM_SPLITS 4
+int64_t gett_num_tiles(int prec);
+/* Describe tile t of precision prec: out[0..2] = BM, BN, BK. */
+int gett_tile_shape(int prec, int64_t t, int64_t *out);
+/* Force one schedule for every following call on any thread (id < 0 clears). */
+int gett_set_schedule(int64_t id);
+/* Schedule chosen for the last plan built by the calling thread (or -1). */
+int64_t gett_last_schedule(void);
+
+/* Autotuner: time every valid schedule of the menu for one problem of
+   precision PREC (the 14 xGETT arguments, device data; C is overwritten by
+   the timing runs), WARMUP untimed runs then the median of REPS runs, each
+   timed with HIP events on the current stream.  times_us[id] receives the
+   median (or -1 for an invalid schedule); returns the best id (>= 0) or
+   INFO/runtime error as a negative/positive code via *status. */
+int64_t gett_autotune(int prec, int64_t ranka, const int64_t *exta, const int64_t *inca,
+                      const void *A, int64_t rankb, const int64_t *extb, const int64_t *incb,
+                      const void *B, int64_t conts, const int64_t *conta, const int64_t *contb,
+                      const int64_t *perm, const int64_t *incc, void *C, int64_t warmup,
+                      int64_t reps, double *times_us, int64_t ntimes, int *status);
+
+/* Feature vector of a signature (host only, no HIP call): 64 floats. */
+#define GETT_NUM_FEATURES 64
+int gett_features(int prec, int64_t ranka, const int64_t *exta, const int64_t *inca,
+                  int64_t rankb, const int64_t *extb, const int64_t *incb, int64_t conts,
+                  const int64_t *conta, const int64_t *contb, const int64_t *perm,
+                  const int64_t *incc, float *out);
+
+/* Planner introspection (host only, no HIP call): canonical groups for the
+   heuristic schedule with order ORDER and tile T.  out receives
+   [swapped, M, N, K, nM, nN, nK, aFastK, bFastK, bBoxX, then per group mode
+   (ext, inc_1, inc_2) for M (incA, incC), N (incB, incC), K (incA, incB)];
+   returns the number of values written or a negative INFO. */
+int64_t gett_plan_describe(int prec, int64_t order, int64_t tile, int64_t ranka,
+                           const int64_t *exta, const int64_t *inca, int64_t rankb,
+                           const int64_t *extb, const int64_t *incb, int64_t conts,
+                           const int64_t *conta, const int64_t *contb, const int64_t *perm,
+                           const int64_t *incc, int64_t *out, int64_t nout);
+
+/* Offset tables of that plan (host only): writes offAM, offCM (M each),
+   offBN, offCN (N each), offAK, offBK (K each) into out in that order. */
+int64_t gett_plan_tables(int prec, int64_t order, int64_t tile, int64_t ranka,
+                         const int64_t *exta, const int64_t *inca, int64_t rankb,
+                         const int64_t *extb, const int64_t *incb, int64_t conts,
+                         const int64_t *conta, const int64_t *contb, const int64_t *perm,
+                         const int64_t *incc, int64_t *out, int64_t nout);
+
+const char *gett_strerror(int code);
+
+/* Release the plan cache, device tables, graphs and predictor. */
+int gett_finalize(void);
+
+/* ---------------------------------------------------------------------- */
+/* Kernels of the MLP schedule predictor (device pointers, FP32, row-major, */
+/* asynchronous on the current stream).  Layer l maps d_in -> d_out with     */
+/* W[d_out][d_in] and b[d_out]; activations are [batch][d].                  */
+/* ---------------------------------------------------------------------- */
+
+/* Y = act(X W^T + b); act = ReLU when relu != 0, identity otherwise. */
+int gett_mlp_linear_fwd(const float *X, const float *W, const float *b, float *Y,
+                        int64_t batch, int64_t d_in, int64_t d_out, int relu);
+/* Backward of the layer above given dY and the layer's output Y (for the
+   ReLU mask): dZ = dY * (Y > 0 when relu), dW = dZ^T X, db = sum_rows dZ,
+   dX = dZ W (dX may be NULL for the first layer).  dW, db are overwritten. */
+int gett_mlp_linear_bwd(const float *X, const float *W, const float *Y, const float *dY,
+                        float *dX, float *dW, float *db, int64_t batch, int64_t d_in,
+                        int64_t d_out, int relu);
+/* Softmax cross-entropy of logits [batch][total] split into heads of the
+   given sizes against soft targets T of the same shape; writes dL/dlogits
+   (mean over the batch) to dZ and the mean loss to loss[0]. */
+int gett_mlp_softmax_xent(const float *Z, const float *T, float *dZ, float *loss,
+                          int64_t batch, int64_t nheads, const int64_t *head_sizes);
+/* Adam (Kingma & Ba 2015) with bias correction, step t >= 1, over n params. */
+int gett_mlp_adam(float *P, const float *G, float *m, float *v, int64_t n, float lr,
+                  float beta1, float beta2, float eps, int64_t t);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GETT_H */

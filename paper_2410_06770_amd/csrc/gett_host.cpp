@@ -1,0 +1,1074 @@
+// gett_host.cpp -- the C ABI of libgett.so: xGETT entry points, plan cache,
+// schedule policies (heuristic, MLP predictor, autotuner) and launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "gett.h"
+#include "gett_internal.h"
+#include "gett_plan.h"
+
+namespace gett {
+
+// ---------------------------------------------------------------------------
+// Per-thread and global state
+// ---------------------------------------------------------------------------
+static thread_local hipStream_t t_stream = nullptr;
+static thread_local int64_t t_last_schedule = -1;
+static std::atomic<int> g_policy{GETT_HEURISTIC};
+static std::atomic<int64_t> g_forced{-1};
+static std::mutex g_mu;   // guards the caches below
+
+static bool g_log = [] {
+    const char *e = getenv("GETT_LOG");
+    return e && e[0] == '1';
+}();
+
+// Device check: the kernels are built for gfx950 only.
+static std::map<int, bool> g_device_ok;
+static int check_device(int *dev_out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return GETT_ERR_HIP;
+    *dev_out = dev;
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_device_ok.find(dev);
+    if (it == g_device_ok.end()) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return GETT_ERR_HIP;
+        const bool ok = strncmp(prop.gcnArchName, "gfx950", 6) == 0;
+        it = g_device_ok.emplace(dev, ok).first;
+    }
+    return it->second ? 0 : GETT_ERR_DEVICE;
+}
+
+// ---------------------------------------------------------------------------
+// Schedules
+// ---------------------------------------------------------------------------
+struct Sched {
+    int tile, order, split;
+};
+static int64_t sched_id(const Sched &s) {
+    return s.tile + kNumTiles * (s.order + kNumOrders * s.split);
+}
+static Sched sched_of(int64_t id) {
+    Sched s;
+    s.tile = (int)(id % kNumTiles);
+    id /= kNumTiles;
+    s.order = (int)(id % kNumOrders);
+    s.split = (int)(id / kNumOrders);
+    return s;
+}
+static const int64_t kNumSched = (int64_t)kNumTiles * kNumOrders * kNumSplits;
+
+// A schedule is usable when every split gets at least one K step.
+static bool sched_valid(int prec, const Sched &s, int64_t K) {
+    if (s.tile < 0 || s.tile >= kNumTiles || s.order < 0 || s.order >= kNumOrders || s.split < 0 ||
+        s.split >= kNumSplits)
+        return false;
+    const int S = kSplitFactor[s.split];
+    const int bk = kTiles[prec][s.tile].bk;
+    if (S > 1 && K < (int64_t)S * bk) return false;
+    if (prec == kFP8 && s.split != 0) return false;
+    return true;
+}
+
+// Built-in rules (the default policy, and the baseline of the predictor):
+// fill the 256 CUs with whole waves of tiles, prefer larger tiles, and split
+// K only when there are too few tiles to occupy the chip.
+static Sched heuristic(int prec, int64_t M, int64_t N, int64_t K) {
+    static const double kTileSpeed[kNumTiles] = {0.55, 0.8, 0.8, 1.0, 0.97};
+    double best = -1;
+    Sched bs{3, 0, 0};
+    for (int t = 0; t < kNumTiles; ++t) {
+        const TileShape ts = kTiles[prec][t];
+        const double tm = std::ceil((double)M / ts.bm), tn = std::ceil((double)N / ts.bn);
+        const double tiles = tm * tn;
+        const double slots = 256.0 * ((ts.bm * ts.bn >= 128 * 128) ? 1.0 : 2.0);
+        const double waves = std::ceil(tiles / slots);
+        const double util = tiles / (waves * slots);
+        const double pad = ((double)M / (tm * ts.bm)) * ((double)N / (tn * ts.bn));
+        const double score = util * pad * kTileSpeed[t];
+        if (score > best + 1e-9) {
+            best = score;
+            bs.tile = t;
+        }
+    }
+    const TileShape ts = kTiles[prec][bs.tile];
+    const double tiles = std::ceil((double)M / ts.bm) * std::ceil((double)N / ts.bn);
+    bs.split = 0;
+    if (prec != kFP8) {
+        for (int s = kNumSplits - 1; s > 0; --s) {
+            const int S = kSplitFactor[s];
+            if (tiles * S <= 512 && tiles < 192 && K >= (int64_t)S * 256) {
+                bs.split = s;
+                break;
+            }
+        }
+    }
+    return bs;
+}
+
+// ---------------------------------------------------------------------------
+// Plans
+// ---------------------------------------------------------------------------
+struct Plan {
+    int prec = 0;
+    Sched sched{};
+    Canon cn;
+    int64_t Mp = 0, Np = 0, Kp = 0;
+    int64_t *d_tab = nullptr;   // offAM, offCM [Mp]; offBN, offCN [Np]; offAK, offBK [Kp]
+    // FP8: canonical tables (rowsA [MpA], kA [Kc], rowsB [NpB], kB [Kc], offCM, offCN)
+    int64_t fpM = 0, fpN = 0, fpK = 0;
+    ~Plan() {
+        if (d_tab) (void)hipFree(d_tab);
+    }
+};
+
+static std::unordered_map<std::string, std::unique_ptr<Plan>> g_plans;
+
+static int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+// Build host tables for canonical form cn and upload them.
+static int upload_tables(Plan &pl) {
+    const Canon &c = pl.cn;
+    const TileShape ts = kTiles[pl.prec][pl.sched.tile];
+    pl.Mp = round_up(std::max<int64_t>(c.M, 1), kTablePad);
+    pl.Np = round_up(std::max<int64_t>(c.N, 1), kTablePad);
+    // K tables: zero padding past K covers the kernel's look-ahead loads
+    // (up to three steps of at most 64 positions past the last one).
+    (void)ts;
+    pl.Kp = round_up(std::max<int64_t>(c.K, 1), 128) + 256;
+    std::vector<int64_t> h(2 * (pl.Mp + pl.Np + pl.Kp));
+    int64_t *p = h.data();
+    group_offsets(c.m, 0, pl.Mp, p);
+    group_offsets(c.m, 1, pl.Mp, p + pl.Mp);
+    p += 2 * pl.Mp;
+    group_offsets(c.n, 0, pl.Np, p);
+    group_offsets(c.n, 1, pl.Np, p + pl.Np);
+    p += 2 * pl.Np;
+    group_offsets(c.k, 0, pl.Kp, p);
+    group_offsets(c.k, 1, pl.Kp, p + pl.Kp);
+    const size_t bytes = h.size() * sizeof(int64_t);
+    if (hipMalloc(&pl.d_tab, bytes) != hipSuccess) return GETT_ERR_ALLOC;
+    if (hipMemcpy(pl.d_tab, h.data(), bytes, hipMemcpyHostToDevice) != hipSuccess)
+        return GETT_ERR_HIP;
+    return 0;
+}
+
+static Sched choose_schedule(int prec, const Args &a, int64_t M, int64_t N, int64_t K);
+
+static int get_plan(int prec, const Args &a, int dev, int64_t forced, Plan **out) {
+    const std::string key = signature_key(a, prec, dev, forced);
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_plans.find(key);
+        if (it != g_plans.end()) {
+            *out = it->second.get();
+            t_last_schedule = sched_id(it->second->sched);
+            return 0;
+        }
+    }
+    // Plan outside the lock (the predictor/autotuner may launch kernels).
+    Canon c0 = canonicalise(a, 0, 128);
+    Sched s;
+    if (forced >= 0) {
+        s = sched_of(forced);
+        if (!sched_valid(prec, s, c0.K)) return GETT_ERR_STATE;
+    } else {
+        s = choose_schedule(prec, a, c0.M, c0.N, c0.K);
+    }
+    auto pl = std::make_unique<Plan>();
+    pl->prec = prec;
+    pl->sched = s;
+    pl->cn = canonicalise(a, s.order, kTiles[prec][s.tile].bn);
+    if (pl->cn.M > INT32_MAX || pl->cn.N > INT32_MAX) return GETT_ERR_INTERNAL;
+    const TileShape ts = kTiles[prec][s.tile];
+    const int64_t tiles = ((pl->cn.M + ts.bm - 1) / ts.bm) * ((pl->cn.N + ts.bn - 1) / ts.bn) *
+                          kSplitFactor[s.split];
+    if (tiles > INT32_MAX) return GETT_ERR_INTERNAL;
+    int rc = upload_tables(*pl);
+    if (rc) return rc;
+    if (g_log)
+        fprintf(stderr, "[gett] plan prec=%d M=%lld N=%lld K=%lld tile=%d order=%d split=%d "
+                        "swapped=%d aFastK=%d bFastK=%d boxX=%d\n",
+                prec, (long long)pl->cn.M, (long long)pl->cn.N, (long long)pl->cn.K, s.tile,
+                s.order, kSplitFactor[s.split], (int)pl->cn.swapped, (int)pl->cn.aFastK,
+                (int)pl->cn.bFastK, pl->cn.boxX);
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto &slot = g_plans[key];
+    if (!slot) slot = std::move(pl);   // another thread may have won the race
+    *out = slot.get();
+    t_last_schedule = sched_id(slot->sched);
+    return 0;
+}
+
+// Fill the launch parameters of a plan for concrete pointers.
+static TileParams make_params(const Plan &pl, const void *A, const void *B, void *C) {
+    const Canon &c = pl.cn;
+    const TileShape ts = kTiles[pl.prec][pl.sched.tile];
+    TileParams p;
+    p.A = c.swapped ? B : A;
+    p.B = c.swapped ? A : B;
+    p.C = C;
+    p.offAM = pl.d_tab;
+    p.offCM = pl.d_tab + pl.Mp;
+    p.offBN = pl.d_tab + 2 * pl.Mp;
+    p.offCN = pl.d_tab + 2 * pl.Mp + pl.Np;
+    p.offAK = pl.d_tab + 2 * pl.Mp + 2 * pl.Np;
+    p.offBK = pl.d_tab + 2 * pl.Mp + 2 * pl.Np + pl.Kp;
+    p.M = c.M;
+    p.N = c.N;
+    p.K = c.K;
+    const int S = kSplitFactor[pl.sched.split];
+    p.splits = S;
+    p.kPerSplit = round_up((c.K + S - 1) / S, ts.bk);
+    p.tilesM = (int32_t)((c.M + ts.bm - 1) / ts.bm);
+    p.tilesN = (int32_t)((c.N + ts.bn - 1) / ts.bn);
+    p.bBoxX = c.boxX > 0 ? c.boxX : ts.bn;
+    p.ws = nullptr;
+    return p;
+}
+
+static int run_plan(const Plan &pl, const void *A, const void *B, void *C, hipStream_t s) {
+    TileParams p = make_params(pl, A, B, C);
+    if (p.splits > 1) {
+        const size_t bytes = (size_t)p.splits * p.M * p.N * sizeof(double);
+        void *ws = nullptr;
+        if (hipMallocAsync(&ws, bytes, s) != hipSuccess) return GETT_ERR_ALLOC;
+        p.ws = static_cast<double *>(ws);
+        int rc = launch_tile(pl.prec, pl.sched.tile, pl.cn.aFastK, pl.cn.bFastK, p, s);
+        if (!rc) rc = launch_splitk_reduce(pl.prec, p, s);
+        if (hipFreeAsync(ws, s) != hipSuccess && !rc) rc = GETT_ERR_HIP;
+        return rc;
+    }
+    return launch_tile(pl.prec, pl.sched.tile, pl.cn.aFastK, pl.cn.bFastK, p, s);
+}
+
+// ---------------------------------------------------------------------------
+// FP8 path
+// ---------------------------------------------------------------------------
+struct Fp8Plan {
+    int64_t M = 0, N = 0, K = 0, nb = 0, Kp = 0;
+    int64_t *d_tab = nullptr;  // rowsA [M], kA [K], rowsB [N], kB [K], offCM [M], offCN [N]
+    int tile = 3;
+    ~Fp8Plan() {
+        if (d_tab) (void)hipFree(d_tab);
+    }
+};
+static std::unordered_map<std::string, std::unique_ptr<Fp8Plan>> g_fp8;
+
+static int get_fp8_plan(const Args &a, int dev, Fp8Plan **out) {
+    const std::string key = signature_key(a, kFP8, dev, -7);
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_fp8.find(key);
+        if (it != g_fp8.end()) {
+            *out = it->second.get();
+            return 0;
+        }
+    }
+    std::vector<GMode> ra, rb, k;
+    canonical_groups(a, ra, rb, k);
+    auto pl = std::make_unique<Fp8Plan>();
+    auto size = [](const std::vector<GMode> &g) {
+        int64_t s = 1;
+        for (auto &x : g) s *= x.ext;
+        return s;
+    };
+    pl->M = size(ra);
+    pl->N = size(rb);
+    pl->K = size(k);
+    pl->nb = (pl->K + 127) / 128;
+    pl->Kp = pl->nb * 128;
+    // C offsets of the canonical rows: slot 1 of the raw M/N groups is INCC.
+    std::vector<int64_t> h(2 * pl->M + 2 * pl->N + 2 * pl->K);
+    int64_t *p = h.data();
+    group_offsets(ra, 0, pl->M, p); p += pl->M;
+    group_offsets(k, 0, pl->K, p); p += pl->K;
+    group_offsets(rb, 0, pl->N, p); p += pl->N;
+    group_offsets(k, 1, pl->K, p); p += pl->K;
+    group_offsets(ra, 1, pl->M, p); p += pl->M;
+    group_offsets(rb, 1, pl->N, p);
+    const size_t bytes = h.size() * sizeof(int64_t);
+    if (hipMalloc(&pl->d_tab, std::max<size_t>(bytes, 8)) != hipSuccess) return GETT_ERR_ALLOC;
+    if (bytes && hipMemcpy(pl->d_tab, h.data(), bytes, hipMemcpyHostToDevice) != hipSuccess)
+        return GETT_ERR_HIP;
+    const int64_t tilesBig = ((pl->M + 127) / 128) * ((pl->N + 127) / 128);
+    pl->tile = tilesBig >= 256 ? 3 : 0;
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto &slot = g_fp8[key];
+    if (!slot) slot = std::move(pl);
+    *out = slot.get();
+    return 0;
+}
+
+static int run_fp8(const Args &a, const float *A, const float *B, float *C, hipStream_t s, int dev) {
+    Fp8Plan *pl = nullptr;
+    int rc = get_fp8_plan(a, dev, &pl);
+    if (rc) return rc;
+    const int64_t M = pl->M, N = pl->N, K = pl->K, nb = pl->nb, Kp = pl->Kp;
+    const int64_t *rowsA = pl->d_tab, *kA = rowsA + M, *rowsB = kA + K, *kB = rowsB + N;
+    const int64_t *offCM = kB + K, *offCN = offCM + M;
+    const int64_t Mq = round_up(M, 128), Nq = round_up(N, 128);
+    const size_t bytes = (size_t)(Mq + Nq) * Kp + (size_t)(Mq + Nq) * nb * sizeof(int32_t) + 256;
+    void *ws = nullptr;
+    if (hipMallocAsync(&ws, bytes, s) != hipSuccess) return GETT_ERR_ALLOC;
+    uint8_t *QA = static_cast<uint8_t *>(ws);
+    uint8_t *QB = QA + (size_t)Mq * Kp;
+    int32_t *EA = reinterpret_cast<int32_t *>(QB + (size_t)Nq * Kp);
+    int32_t *EB = EA + (size_t)Mq * nb;
+    rc = launch_fp8_quant(A, rowsA, M, Mq, kA, K, QA, EA, s);
+    if (!rc) rc = launch_fp8_quant(B, rowsB, N, Nq, kB, K, QB, EB, s);
+    if (!rc) rc = launch_fp8_gemm(pl->tile, QA, EA, QB, EB, C, offCM, offCN, M, N, K, s);
+    if (hipFreeAsync(ws, s) != hipSuccess && !rc) rc = GETT_ERR_HIP;
+    return rc;
+}
+
+// ---------------------------------------------------------------------------
+// Predictor (MLP 64 -> 128 -> 128 -> heads tile | order | split)
+// ---------------------------------------------------------------------------
+struct Predictor {
+    int din = 0, h1 = 0, h2 = 0, dout = 0;
+    std::vector<int64_t> heads;
+    std::vector<float> mean, stdv;
+    float *d_w = nullptr;   // W1 b1 W2 b2 W3 b3 contiguous
+    float *d_io = nullptr;  // x [din], y1 [h1], y2 [h2], z [dout]
+    size_t off[6] = {0, 0, 0, 0, 0, 0};
+    int dev = -1;
+    ~Predictor() {
+        if (d_w) (void)hipFree(d_w);
+        if (d_io) (void)hipFree(d_io);
+    }
+};
+static std::unique_ptr<Predictor> g_pred;
+static std::mutex g_pred_mu;
+
+static int load_predictor(const char *path) {
+    FILE *f = fopen(path, "rb");
+    if (!f) return GETT_ERR_STATE;
+    char magic[8];
+    int32_t dims[5];
+    auto pred = std::make_unique<Predictor>();
+    bool ok = fread(magic, 1, 8, f) == 8 && memcmp(magic, "GETTMLP1", 8) == 0 &&
+              fread(dims, 4, 5, f) == 5;
+    if (ok) {
+        pred->din = dims[0];
+        pred->h1 = dims[1];
+        pred->h2 = dims[2];
+        pred->dout = dims[3];
+        const int nh = dims[4];
+        ok = pred->din == GETT_NUM_FEATURES && nh == 3 && pred->h1 > 0 && pred->h2 > 0 &&
+             pred->h1 <= 4096 && pred->h2 <= 4096;
+        std::vector<int32_t> hs(3);
+        ok = ok && fread(hs.data(), 4, 3, f) == 3;
+        if (ok) {
+            pred->heads.assign(hs.begin(), hs.end());
+            ok = hs[0] == kNumTiles && hs[1] == kNumOrders && hs[2] == kNumSplits &&
+                 hs[0] + hs[1] + hs[2] == pred->dout;
+        }
+    }
+    std::vector<float> w;
+    if (ok) {
+        pred->mean.resize(pred->din);
+        pred->stdv.resize(pred->din);
+        ok = fread(pred->mean.data(), 4, pred->din, f) == (size_t)pred->din &&
+             fread(pred->stdv.data(), 4, pred->din, f) == (size_t)pred->din;
+        const size_t sizes[6] = {(size_t)pred->h1 * pred->din, (size_t)pred->h1,
+                                 (size_t)pred->h2 * pred->h1, (size_t)pred->h2,
+                                 (size_t)pred->dout * pred->h2, (size_t)pred->dout};
+        size_t total = 0;
+        for (int i = 0; i < 6; ++i) {
+            pred->off[i] = total;
+            total += sizes[i];
+        }
+        w.resize(total);
+        ok = ok && fread(w.data(), 4, total, f) == total;
+    }
+    fclose(f);
+    if (!ok) return GETT_ERR_STATE;
+    if (hipGetDevice(&pred->dev) != hipSuccess) return GETT_ERR_HIP;
+    if (hipMalloc(&pred->d_w, w.size() * 4) != hipSuccess) return GETT_ERR_ALLOC;
+    if (hipMemcpy(pred->d_w, w.data(), w.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
+        return GETT_ERR_HIP;
+    if (hipMalloc(&pred->d_io, (size_t)(pred->din + pred->h1 + pred->h2 + pred->dout) * 4) !=
+        hipSuccess)
+        return GETT_ERR_ALLOC;
+    std::lock_guard<std::mutex> lk(g_pred_mu);
+    g_pred = std::move(pred);
+    return 0;
+}
+
+// Run the network on one feature vector with the library's own kernels and
+// return the best valid joint schedule under the summed log-probabilities.
+static bool predict(int prec, const Args &a, int64_t K, Sched *out) {
+    std::lock_guard<std::mutex> lk(g_pred_mu);
+    Predictor *pr = g_pred.get();
+    if (!pr) return false;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev != pr->dev) return false;
+    float feat[GETT_NUM_FEATURES];
+    features(a, prec, feat);
+    for (int i = 0; i < pr->din; ++i)
+        feat[i] = (feat[i] - pr->mean[i]) / (pr->stdv[i] > 0 ? pr->stdv[i] : 1.f);
+    float *x = pr->d_io, *y1 = x + pr->din, *y2 = y1 + pr->h1, *z = y2 + pr->h2;
+    hipStream_t s = t_stream;
+    if (hipMemcpyAsync(x, feat, pr->din * 4, hipMemcpyHostToDevice, s) != hipSuccess) return false;
+    const float *W = pr->d_w;
+    if (launch_mlp_linear_fwd(x, W + pr->off[0], W + pr->off[1], y1, 1, pr->din, pr->h1, 1, s) ||
+        launch_mlp_linear_fwd(y1, W + pr->off[2], W + pr->off[3], y2, 1, pr->h1, pr->h2, 1, s) ||
+        launch_mlp_linear_fwd(y2, W + pr->off[4], W + pr->off[5], z, 1, pr->h2, pr->dout, 0, s))
+        return false;
+    std::vector<float> logits(pr->dout);
+    if (hipMemcpyAsync(logits.data(), z, pr->dout * 4, hipMemcpyDeviceToHost, s) != hipSuccess)
+        return false;
+    if (hipStreamSynchronize(s) != hipSuccess) return false;
+    // log-softmax per head
+    std::vector<double> lp(pr->dout);
+    int o = 0;
+    for (int h = 0; h < 3; ++h) {
+        const int n = (int)pr->heads[h];
+        double mx = -1e300;
+        for (int i = 0; i < n; ++i) mx = std::max(mx, (double)logits[o + i]);
+        double se = 0;
+        for (int i = 0; i < n; ++i) se += std::exp((double)logits[o + i] - mx);
+        for (int i = 0; i < n; ++i) lp[o + i] = (double)logits[o + i] - mx - std::log(se);
+        o += n;
+    }
+    double best = -1e300;
+    bool found = false;
+    for (int64_t id = 0; id < kNumSched; ++id) {
+        Sched sc = sched_of(id);
+        if (!sched_valid(prec, sc, K)) continue;
+        const double v = lp[sc.tile] + lp[kNumTiles + sc.order] + lp[kNumTiles + kNumOrders + sc.split];
+        if (v > best) {
+            best = v;
+            *out = sc;
+            found = true;
+        }
+    }
+    return found;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner
+// ---------------------------------------------------------------------------
+static int time_schedule(int prec, const Args &a, const void *A, const void *B, void *C, int dev,
+                         int64_t id, int warmup, int reps, double *us) {
+    Plan *pl = nullptr;
+    int rc = get_plan(prec, a, dev, id, &pl);
+    if (rc) return rc;
+    hipStream_t s = t_stream;
+    for (int i = 0; i < warmup; ++i)
+        if ((rc = run_plan(*pl, A, B, C, s))) return rc;
+    std::vector<double> t(reps);
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return GETT_ERR_HIP;
+    for (int r = 0; r < reps; ++r) {
+        (void)hipEventRecord(e0, s);
+        rc = run_plan(*pl, A, B, C, s);
+        (void)hipEventRecord(e1, s);
+        if (rc) break;
+        if (hipEventSynchronize(e1) != hipSuccess) { rc = GETT_ERR_HIP; break; }
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        t[r] = ms * 1e3;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    std::sort(t.begin(), t.end());
+    *us = t[reps / 2];
+    return 0;
+}
+
+static int64_t autotune(int prec, const Args &a, const void *A, const void *B, void *C, int dev,
+                        int warmup, int reps, double *times, int64_t ntimes, int *status) {
+    Canon c0 = canonicalise(a, 0, 128);
+    double best = 1e300;
+    int64_t best_id = -1;
+    *status = 0;
+    for (int64_t id = 0; id < kNumSched; ++id) {
+        double us = -1;
+        if (sched_valid(prec, sched_of(id), c0.K)) {
+            int rc = time_schedule(prec, a, A, B, C, dev, id, warmup, reps, &us);
+            if (rc) {
+                *status = rc;
+                return -1;
+            }
+            if (us < best) {
+                best = us;
+                best_id = id;
+            }
+        }
+        if (times && id < ntimes) times[id] = us;
+    }
+    return best_id;
+}
+
+// Tuned choices found by the AUTOTUNE policy (signature -> schedule).
+static std::unordered_map<std::string, Sched> g_tuned;
+
+static thread_local const void *t_tune_ptrs[3] = {nullptr, nullptr, nullptr};
+static thread_local int t_tune_dev = 0;
+
+static Sched choose_schedule(int prec, const Args &a, int64_t M, int64_t N, int64_t K) {
+    const int pol = g_policy.load();
+    Sched s = heuristic(prec, M, N, K);
+    if (pol == GETT_PREDICT) {
+        Sched p;
+        if (predict(prec, a, K, &p)) s = p;
+    } else if (pol == GETT_AUTOTUNE && t_tune_ptrs[0]) {
+        const std::string key = signature_key(a, prec, t_tune_dev, -3);
+        {
+            std::lock_guard<std::mutex> lk(g_mu);
+            auto it = g_tuned.find(key);
+            if (it != g_tuned.end()) return it->second;
+        }
+        int st = 0;
+        // The tuning runs overwrite C; the caller's C is restored by the final run
+        // only if C started at zero, so the policy saves and restores C itself.
+        const int64_t id = autotune(prec, a, t_tune_ptrs[0], t_tune_ptrs[1],
+                                    const_cast<void *>(t_tune_ptrs[2]), t_tune_dev, 1, 3, nullptr,
+                                    0, &st);
+        if (!st && id >= 0) {
+            s = sched_of(id);
+            std::lock_guard<std::mutex> lk(g_mu);
+            g_tuned[key] = s;
+        }
+    }
+    return s;
+}
+
+// ---------------------------------------------------------------------------
+// Entry point shared by the single-problem calls
+// ---------------------------------------------------------------------------
+static int64_t c_span_elems(const Args &a, int64_t *lo_out) {
+    // extent of C's footprint in elements: [lo, hi]
+    bool contA[64] = {false}, contB[64] = {false};
+    for (int64_t x = 0; x < a.conts; ++x) {
+        contA[a.conta[x]] = true;
+        contB[a.contb[x]] = true;
+    }
+    std::vector<int64_t> extc(a.ranka + a.rankb - 2 * a.conts);
+    int64_t p = 0;
+    for (int64_t i = 0; i < a.ranka; ++i)
+        if (!contA[i]) extc[a.perm[p++]] = a.exta[i];
+    for (int64_t j = 0; j < a.rankb; ++j)
+        if (!contB[j]) extc[a.perm[p++]] = a.extb[j];
+    int64_t lo = 0, hi = 0;
+    for (size_t q = 0; q < extc.size(); ++q) {
+        if (extc[q] <= 1) continue;
+        const int64_t d = a.incc[q] * (extc[q] - 1);
+        if (d < 0) lo += d;
+        else hi += d;
+    }
+    *lo_out = lo;
+    return hi - lo + 1;
+}
+
+static int run(int prec, const Args &a, const void *A, const void *B, void *C) {
+    int info = validate(a, A, B, C);
+    if (info) return info;
+    Canon probe = canonicalise(a, 0, 128);
+    if (probe.empty || probe.M == 0 || probe.N == 0 || probe.K == 0) return 0;
+    int dev = 0;
+    int rc = check_device(&dev);
+    if (rc) return rc;
+    hipStream_t s = t_stream;
+    if (prec == kFP8)
+        return run_fp8(a, static_cast<const float *>(A), static_cast<const float *>(B),
+                       static_cast<float *>(C), s, dev);
+    const int64_t forced = g_forced.load();
+    Plan *pl = nullptr;
+    // Under the AUTOTUNE policy a plan-cache miss times the menu; the timing
+    // runs accumulate into C, so C's footprint is saved and restored around it.
+    void *saved = nullptr;
+    int64_t lo = 0, span = 0;
+    const size_t esz = prec == kF64 ? 8 : 4;
+    if (g_policy.load() == GETT_AUTOTUNE && forced < 0) {
+        span = c_span_elems(a, &lo);
+        char *cbase = static_cast<char *>(C) + lo * (int64_t)esz;
+        if (hipMallocAsync(&saved, span * esz, s) != hipSuccess) return GETT_ERR_ALLOC;
+        if (hipMemcpyAsync(saved, cbase, span * esz, hipMemcpyDeviceToDevice, s) != hipSuccess)
+            return GETT_ERR_HIP;
+        t_tune_ptrs[0] = A;
+        t_tune_ptrs[1] = B;
+        t_tune_ptrs[2] = C;
+        t_tune_dev = dev;
+    }
+    rc = get_plan(prec, a, dev, forced, &pl);
+    t_tune_ptrs[0] = nullptr;
+    if (saved) {
+        char *cbase = static_cast<char *>(C) + lo * (int64_t)esz;
+        if (hipMemcpyAsync(cbase, saved, span * esz, hipMemcpyDeviceToDevice, s) != hipSuccess &&
+            !rc)
+            rc = GETT_ERR_HIP;
+        (void)hipFreeAsync(saved, s);
+    }
+    if (rc) return rc;
+    return run_plan(*pl, A, B, C, s);
+}
+
+// ---------------------------------------------------------------------------
+// Batches
+// ---------------------------------------------------------------------------
+struct BatchGraph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    BatchProblem *h_desc = nullptr;   // pinned host descriptors (copied by the graph)
+    BatchProblem *d_desc = nullptr;
+    int32_t *d_items = nullptr;
+    int32_t nprobs = 0, nitems = 0;
+    hipEvent_t done = nullptr;
+    std::vector<Plan *> plans;
+    ~BatchGraph() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (h_desc) (void)hipHostFree(h_desc);
+        if (d_desc) (void)hipFree(d_desc);
+        if (d_items) (void)hipFree(d_items);
+        if (done) (void)hipEventDestroy(done);
+    }
+};
+static std::unordered_map<std::string, std::unique_ptr<BatchGraph>> g_graphs;
+
+// Run a batch: per-problem plans with the batch tile (64x64 of the precision,
+// no split), one work list ordered longest contraction first, and a graph of
+// {descriptor copy, persistent kernel} captured once per batch signature and
+// replayed.  Pointers may change between calls: the descriptors are rewritten
+// in pinned memory (after the previous replay has finished) before each
+// replay, and the graph's copy node moves them to the device.
+static int run_batch(int prec, int64_t count, const Args *args, const void *const *A,
+                     const void *const *B, void *const *C, int dev, hipStream_t s) {
+    const int64_t forced = sched_id(Sched{0, 0, 0});
+    std::string key;
+    key.reserve(64 * count);
+    key.append(reinterpret_cast<const char *>(&prec), sizeof prec);
+    key.append(reinterpret_cast<const char *>(&dev), sizeof dev);
+    std::vector<char> live(count, 0);
+    for (int64_t i = 0; i < count; ++i) {
+        Canon c = canonicalise(args[i], 0, 64);
+        live[i] = !(c.empty || c.M == 0 || c.N == 0 || c.K == 0);
+        key += signature_key(args[i], prec, live[i], 0);
+    }
+    BatchGraph *bg = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_graphs.find(key);
+        if (it != g_graphs.end()) bg = it->second.get();
+    }
+    if (!bg) {
+        auto nb = std::make_unique<BatchGraph>();
+        nb->plans.assign(count, nullptr);
+        struct Work { int64_t K; int32_t prob, ntiles; };
+        std::vector<Work> work;
+        for (int64_t i = 0; i < count; ++i) {
+            if (!live[i]) continue;
+            Plan *pl = nullptr;
+            int rc = get_plan(prec, args[i], dev, forced, &pl);
+            if (rc) return rc;
+            nb->plans[i] = pl;
+            TileParams p = make_params(*pl, nullptr, nullptr, nullptr);
+            work.push_back({p.K, (int32_t)i, p.tilesM * p.tilesN});
+        }
+        std::stable_sort(work.begin(), work.end(),
+                         [](const Work &a, const Work &b) { return a.K > b.K; });
+        std::vector<int32_t> items;
+        for (auto &w : work)
+            for (int32_t t = 0; t < w.ntiles; ++t) {
+                items.push_back(w.prob);
+                items.push_back(t);
+            }
+        nb->nprobs = (int32_t)count;
+        nb->nitems = (int32_t)(items.size() / 2);
+        const size_t dbytes = sizeof(BatchProblem) * std::max<int64_t>(count, 1);
+        if (hipHostMalloc(reinterpret_cast<void **>(&nb->h_desc), dbytes, hipHostMallocDefault) !=
+                hipSuccess ||
+            hipMalloc(reinterpret_cast<void **>(&nb->d_desc), dbytes) != hipSuccess ||
+            hipMalloc(reinterpret_cast<void **>(&nb->d_items),
+                      std::max<size_t>(items.size(), 2) * sizeof(int32_t)) != hipSuccess)
+            return GETT_ERR_ALLOC;
+        memset(nb->h_desc, 0, dbytes);
+        if (!items.empty() &&
+            hipMemcpy(nb->d_items, items.data(), items.size() * sizeof(int32_t),
+                      hipMemcpyHostToDevice) != hipSuccess)
+            return GETT_ERR_HIP;
+        if (hipEventCreateWithFlags(&nb->done, hipEventDisableTiming) != hipSuccess)
+            return GETT_ERR_HIP;
+        const int grid = std::min<int64_t>(std::max(batch_grid_size(prec), 1),
+                                           std::max<int32_t>(nb->nitems, 1));
+        hipStream_t cs;
+        if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return GETT_ERR_HIP;
+        int rc = 0;
+        if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) rc = GETT_ERR_HIP;
+        if (!rc && hipMemcpyAsync(nb->d_desc, nb->h_desc, dbytes, hipMemcpyHostToDevice, cs) !=
+                       hipSuccess)
+            rc = GETT_ERR_HIP;
+        if (!rc && nb->nitems > 0)
+            rc = launch_batch(prec, nb->d_desc, nb->nprobs, nb->d_items, nb->nitems, grid, cs);
+        hipGraph_t g = nullptr;
+        if (hipStreamEndCapture(cs, &g) != hipSuccess && !rc) rc = GETT_ERR_HIP;
+        nb->graph = g;
+        if (!rc && hipGraphInstantiate(&nb->exec, g, nullptr, nullptr, 0) != hipSuccess)
+            rc = GETT_ERR_HIP;
+        (void)hipStreamDestroy(cs);
+        if (rc) return rc;
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto &slot = g_graphs[key];
+        if (!slot) slot = std::move(nb);
+        bg = slot.get();
+    }
+    // previous replay must have consumed the pinned descriptors
+    if (hipEventSynchronize(bg->done) != hipSuccess) return GETT_ERR_HIP;
+    for (int64_t i = 0; i < count; ++i) {
+        if (!bg->plans[i]) continue;
+        const Plan &pl = *bg->plans[i];
+        bg->h_desc[i].p = make_params(pl, A[i], B[i], C[i]);
+        bg->h_desc[i].aFastK = pl.cn.aFastK;
+        bg->h_desc[i].bFastK = pl.cn.bFastK;
+    }
+    if (hipGraphLaunch(bg->exec, s) != hipSuccess) return GETT_ERR_HIP;
+    if (hipEventRecord(bg->done, s) != hipSuccess) return GETT_ERR_HIP;
+    return 0;
+}
+
+static int batch_entry(int prec, int64_t count, const int64_t *ranka, const int64_t *const *exta,
+                       const int64_t *const *inca, const void *const *A, const int64_t *rankb,
+                       const int64_t *const *extb, const int64_t *const *incb,
+                       const void *const *B, const int64_t *conts,
+                       const int64_t *const *conta, const int64_t *const *contb,
+                       const int64_t *const *perm, const int64_t *const *incc, void *const *C,
+                       int64_t *info) {
+    if (count < 0) return -1;
+    if (prec != kF64 && prec != kF32 && prec != kBF3) return -2;
+    if (count == 0) return 0;
+    if (!ranka || !exta || !inca || !A || !rankb || !extb || !incb || !B || !conts || !conta ||
+        !contb || !perm || !incc || !C)
+        return -1;
+    std::vector<Args> args(count);
+    int first_bad = 0;
+    for (int64_t i = 0; i < count; ++i) {
+        args[i] = Args{ranka[i], exta[i], inca[i], rankb[i], extb[i], incb[i], conts[i],
+                       conta[i], contb[i], perm[i], incc[i]};
+        const int v = validate(args[i], A[i], B[i], C[i]);
+        if (info) info[i] = v;
+        if (v && !first_bad) first_bad = (int)(-1000 * (i + 1) + v);
+    }
+    if (first_bad) return first_bad;
+    int dev = 0;
+    int rc = check_device(&dev);
+    if (rc) return rc;
+    return run_batch(prec, count, args.data(), A, B, C, dev, t_stream);
+}
+
+}  // namespace gett
+
+using namespace gett;
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+#define GETT_ARGS_DECL                                                                          \
+    int64_t ranka, const int64_t *exta, const int64_t *inca, int64_t rankb,                     \
+        const int64_t *extb, const int64_t *incb, int64_t conts, const int64_t *conta,          \
+        const int64_t *contb, const int64_t *perm, const int64_t *incc
+#define GETT_ARGS_MAKE Args{ranka, exta, inca, rankb, extb, incb, conts, conta, contb, perm, incc}
+
+extern "C" {
+
+int dgett(int64_t ranka, const int64_t *exta, const int64_t *inca, const double *A, int64_t rankb,
+          const int64_t *extb, const int64_t *incb, const double *B, int64_t conts,
+          const int64_t *conta, const int64_t *contb, const int64_t *perm, const int64_t *incc,
+          double *C) {
+    return run(kF64, GETT_ARGS_MAKE, A, B, C);
+}
+
+int sgett(int64_t ranka, const int64_t *exta, const int64_t *inca, const float *A, int64_t rankb,
+          const int64_t *extb, const int64_t *incb, const float *B, int64_t conts,
+          const int64_t *conta, const int64_t *contb, const int64_t *perm, const int64_t *incc,
+          float *C) {
+    return run(kF32, GETT_ARGS_MAKE, A, B, C);
+}
+
+int sgett_bf16x3(int64_t ranka, const int64_t *exta, const int64_t *inca, const float *A,
+                 int64_t rankb, const int64_t *extb, const int64_t *incb, const float *B,
+                 int64_t conts, const int64_t *conta, const int64_t *contb, const int64_t *perm,
+                 const int64_t *incc, float *C) {
+    return run(kBF3, GETT_ARGS_MAKE, A, B, C);
+}
+
+int sgett_fp8(int64_t ranka, const int64_t *exta, const int64_t *inca, const float *A,
+              int64_t rankb, const int64_t *extb, const int64_t *incb, const float *B,
+              int64_t conts, const int64_t *conta, const int64_t *contb, const int64_t *perm,
+              const int64_t *incc, float *C) {
+    return run(kFP8, GETT_ARGS_MAKE, A, B, C);
+}
+
+int sgett_fp8_quantize(int64_t rankx, const int64_t *extx, const int64_t *incx, const float *X,
+                       int64_t conts, const int64_t *contx, uint8_t *QX, int32_t *EX) {
+    if (rankx < 0 || rankx > 64) return -1;
+    if (rankx > 0 && !extx) return -2;
+    int64_t n = 1;
+    for (int64_t i = 0; i < rankx; ++i) {
+        if (extx[i] < 0) return -2;
+        n *= extx[i];
+    }
+    if (rankx > 0 && !incx) return -3;
+    if (n > 0 && !X) return -4;
+    if (conts < 0 || conts > rankx) return -5;
+    if (conts > 0 && !contx) return -6;
+    bool used[64] = {false};
+    for (int64_t k = 0; k < conts; ++k) {
+        if (contx[k] < 0 || contx[k] >= rankx || used[contx[k]]) return -6;
+        used[contx[k]] = true;
+    }
+    std::vector<GMode> rows, kk;
+    for (int64_t i = 0; i < rankx; ++i)
+        if (!used[i]) rows.push_back({extx[i], incx[i], 0});
+    for (int64_t k = 0; k < conts; ++k) kk.push_back({extx[contx[k]], incx[contx[k]], 0});
+    int64_t R = 1, K = 1;
+    for (auto &x : rows) R *= x.ext;
+    for (auto &x : kk) K *= x.ext;
+    if (R * K > 0 && (!QX)) return -7;
+    if (R * K > 0 && (!EX)) return -8;
+    if (R == 0 || K == 0) return 0;
+    int dev = 0;
+    int rc = check_device(&dev);
+    if (rc) return rc;
+    std::vector<int64_t> h(R + K);
+    group_offsets(rows, 0, R, h.data());
+    group_offsets(kk, 0, K, h.data() + R);
+    int64_t *d = nullptr;
+    hipStream_t s = t_stream;
+    if (hipMallocAsync(reinterpret_cast<void **>(&d), h.size() * 8, s) != hipSuccess)
+        return GETT_ERR_ALLOC;
+    if (hipMemcpyAsync(d, h.data(), h.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess)
+        return GETT_ERR_HIP;
+    rc = launch_fp8_quant(X, d, R, R, d + R, K, QX, EX, s);
+    (void)hipFreeAsync(d, s);
+    // h must outlive the copy: wait for it
+    if (hipStreamSynchronize(s) != hipSuccess && !rc) rc = GETT_ERR_HIP;
+    return rc;
+}
+
+int sgett_batch(int64_t count, int64_t prec, const int64_t *ranka, const int64_t *const *exta,
+                const int64_t *const *inca, const float *const *A, const int64_t *rankb,
+                const int64_t *const *extb, const int64_t *const *incb, const float *const *B,
+                const int64_t *conts, const int64_t *const *conta, const int64_t *const *contb,
+                const int64_t *const *perm, const int64_t *const *incc, float *const *C,
+                int64_t *info) {
+    if (prec != GETT_FP32 && prec != GETT_BF16X3) return count < 0 ? -1 : -2;
+    return batch_entry((int)prec, count, ranka, exta, inca, reinterpret_cast<const void *const *>(A),
+                       rankb, extb, incb, reinterpret_cast<const void *const *>(B), conts, conta,
+                       contb, perm, incc, reinterpret_cast<void *const *>(C), info);
+}
+
+int dgett_batch(int64_t count, int64_t prec, const int64_t *ranka, const int64_t *const *exta,
+                const int64_t *const *inca, const double *const *A, const int64_t *rankb,
+                const int64_t *const *extb, const int64_t *const *incb, const double *const *B,
+                const int64_t *conts, const int64_t *const *conta, const int64_t *const *contb,
+                const int64_t *const *perm, const int64_t *const *incc, double *const *C,
+                int64_t *info) {
+    (void)prec;
+    return batch_entry(kF64, count, ranka, exta, inca, reinterpret_cast<const void *const *>(A),
+                       rankb, extb, incb, reinterpret_cast<const void *const *>(B), conts, conta,
+                       contb, perm, incc, reinterpret_cast<void *const *>(C), info);
+}
+
+int gett_set_stream(void *hip_stream) {
+    t_stream = static_cast<hipStream_t>(hip_stream);
+    return 0;
+}
+void *gett_get_stream(void) { return t_stream; }
+
+int gett_set_policy(int policy) {
+    if (policy < GETT_HEURISTIC || policy > GETT_AUTOTUNE) return GETT_ERR_STATE;
+    g_policy.store(policy);
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_plans.clear();     // plans were chosen under the old policy
+    return 0;
+}
+int gett_get_policy(void) { return g_policy.load(); }
+
+int gett_load_predictor(const char *path) { return path ? load_predictor(path) : GETT_ERR_STATE; }
+
+int64_t gett_num_tiles(int prec) { return (prec >= 0 && prec <= 3) ? kNumTiles : 0; }
+
+int gett_tile_shape(int prec, int64_t t, int64_t *out) {
+    if (prec < 0 || prec > 3 || t < 0 || t >= kNumTiles || !out) return GETT_ERR_STATE;
+    out[0] = kTiles[prec][t].bm;
+    out[1] = kTiles[prec][t].bn;
+    out[2] = kTiles[prec][t].bk;
+    return 0;
+}
+
+int gett_set_schedule(int64_t id) {
+    if (id >= kNumSched) return GETT_ERR_STATE;
+    g_forced.store(id < 0 ? -1 : id);
+    return 0;
+}
+int64_t gett_last_schedule(void) { return t_last_schedule; }
+
+int64_t gett_autotune(int prec, int64_t ranka, const int64_t *exta, const int64_t *inca,
+                      const void *A, int64_t rankb, const int64_t *extb, const int64_t *incb,
+                      const void *B, int64_t conts, const int64_t *conta, const int64_t *contb,
+                      const int64_t *perm, const int64_t *incc, void *C, int64_t warmup,
+                      int64_t reps, double *times_us, int64_t ntimes, int *status) {
+    int st = 0;
+    if (!status) status = &st;
+    if (prec < 0 || prec > 2 || reps < 1 || warmup < 0) {
+        *status = GETT_ERR_STATE;
+        return -1;
+    }
+    Args a = GETT_ARGS_MAKE;
+    int info = validate(a, A, B, C);
+    if (info) {
+        *status = info;
+        return -1;
+    }
+    Canon c = canonicalise(a, 0, 128);
+    if (c.empty || c.M * c.N * c.K == 0) {
+        *status = GETT_ERR_STATE;
+        return -1;
+    }
+    int dev = 0;
+    int rc = check_device(&dev);
+    if (rc) {
+        *status = rc;
+        return -1;
+    }
+    return autotune(prec, a, A, B, C, dev, (int)warmup, (int)reps, times_us, ntimes, status);
+}
+
+int gett_features(int prec, GETT_ARGS_DECL, float *out) {
+    Args a = GETT_ARGS_MAKE;
+    const int info = validate(a, reinterpret_cast<void *>(1), reinterpret_cast<void *>(1),
+                              reinterpret_cast<void *>(1));
+    if (info) return info;
+    if (!out) return GETT_ERR_STATE;
+    features(a, prec, out);
+    return 0;
+}
+
+static int64_t describe(int prec, int64_t order, int64_t tile, const Args &a, int64_t *out,
+                        int64_t nout, bool tables) {
+    const int info = validate(a, reinterpret_cast<void *>(1), reinterpret_cast<void *>(1),
+                              reinterpret_cast<void *>(1));
+    if (info) return info;
+    if (prec < 0 || prec > 2 || order < 0 || order >= kNumOrders || tile < 0 || tile >= kNumTiles)
+        return GETT_ERR_STATE;
+    Canon c = canonicalise(a, (int)order, kTiles[prec][tile].bn);
+    std::vector<int64_t> v;
+    if (!tables) {
+        v = {c.swapped, c.M, c.N, c.K, (int64_t)c.m.size(), (int64_t)c.n.size(),
+             (int64_t)c.k.size(), c.aFastK, c.bFastK, c.boxX};
+        for (auto *g : {&c.m, &c.n, &c.k})
+            for (auto &x : *g) {
+                v.push_back(x.ext);
+                v.push_back(x.i0);
+                v.push_back(x.i1);
+            }
+    } else {
+        if (c.empty) return 0;
+        v.resize(2 * (c.M + c.N + c.K));
+        int64_t *p = v.data();
+        group_offsets(c.m, 0, c.M, p); p += c.M;
+        group_offsets(c.m, 1, c.M, p); p += c.M;
+        group_offsets(c.n, 0, c.N, p); p += c.N;
+        group_offsets(c.n, 1, c.N, p); p += c.N;
+        group_offsets(c.k, 0, c.K, p); p += c.K;
+        group_offsets(c.k, 1, c.K, p);
+    }
+    if (out) {
+        if ((int64_t)v.size() > nout) return GETT_ERR_STATE;
+        std::copy(v.begin(), v.end(), out);
+    }
+    return (int64_t)v.size();
+}
+
+int64_t gett_plan_describe(int prec, int64_t order, int64_t tile, GETT_ARGS_DECL, int64_t *out,
+                           int64_t nout) {
+    return describe(prec, order, tile, GETT_ARGS_MAKE, out, nout, false);
+}
+
+int64_t gett_plan_tables(int prec, int64_t order, int64_t tile, GETT_ARGS_DECL, int64_t *out,
+                         int64_t nout) {
+    return describe(prec, order, tile, GETT_ARGS_MAKE, out, nout, true);
+}
+
+const char *gett_strerror(int code) {
+    if (code == 0) return "success";
+    if (code < 0) {
+        static const char *names[] = {"RANKA", "EXTA", "INCA", "A", "RANKB", "EXTB", "INCB",
+                                      "B", "CONTS", "CONTA", "CONTB", "PERM", "INCC", "C"};
+        static thread_local char buf[64];
+        if (code >= -14) {
+            snprintf(buf, sizeof buf, "invalid argument %d (%s)", -code, names[-code - 1]);
+            return buf;
+        }
+        return "invalid argument";
+    }
+    switch (code) {
+    case GETT_ERR_HIP: return "HIP runtime error";
+    case GETT_ERR_ALLOC: return "device allocation failed";
+    case GETT_ERR_DEVICE: return "device is not gfx950 (MI355X)";
+    case GETT_ERR_INTERNAL: return "internal planner limit";
+    case GETT_ERR_STATE: return "invalid control call or state";
+    default: return "unknown error";
+    }
+}
+
+int gett_finalize(void) {
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_graphs.clear();
+        g_plans.clear();
+        g_fp8.clear();
+        g_tuned.clear();
+    }
+    std::lock_guard<std::mutex> lk(g_pred_mu);
+    g_pred.reset();
+    return 0;
+}
+
+int gett_mlp_linear_fwd(const float *X, const float *W, const float *b, float *Y, int64_t batch,
+                        int64_t d_in, int64_t d_out, int relu) {
+    if (!X || !W || !b || !Y || batch < 1 || d_in < 1 || d_out < 1) return GETT_ERR_STATE;
+    return launch_mlp_linear_fwd(X, W, b, Y, batch, d_in, d_out, relu, t_stream);
+}
+int gett_mlp_linear_bwd(const float *X, const float *W, const float *Y, const float *dY,
+                        float *dX, float *dW, float *db, int64_t batch, int64_t d_in,
+                        int64_t d_out, int relu) {
+    if (!X || !W || !Y || !dY || !dW || !db || batch < 1 || d_in < 1 || d_out < 1)
+        return GETT_ERR_STATE;
+    return launch_mlp_linear_bwd(X, W, Y, dY, dX, dW, db, batch, d_in, d_out, relu, t_stream);
+}
+int gett_mlp_softmax_xent(const float *Z, const float *T, float *dZ, float *loss, int64_t batch,
+                          int64_t nheads, const int64_t *head_sizes) {
+    if (!Z || !T || !dZ || !loss || batch < 1 || nheads < 1 || nheads > 8 || !head_sizes)
+        return GETT_ERR_STATE;
+    int64_t total = 0;
+    for (int64_t h = 0; h < nheads; ++h) {
+        if (head_sizes[h] < 1 || head_sizes[h] > 64) return GETT_ERR_STATE;
+        total += head_sizes[h];
+    }
+    return launch_mlp_xent(Z, T, dZ, loss, batch, total, nheads, head_sizes, t_stream);
+}
+int gett_mlp_adam(float *P, const float *G, float *m, float *v, int64_t n, float lr, float beta1,
+                  float beta2, float eps, int64_t t) {
+    if (!P || !G || !m || !v || n < 1 || t < 1) return GETT_ERR_STATE;
+    return launch_mlp_adam(P, G, m, v, n, lr, beta1, beta2, eps, t, t_stream);
+}
+
+}  // extern "C"

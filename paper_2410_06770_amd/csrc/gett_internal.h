@@ -1,0 +1,92 @@
+// gett_internal.h -- types shared by the host planner and the gfx950 kernels.
+//
+// A planned contraction is a GEMM over three linearised index spaces:
+//   M = free modes of the (possibly swapped) A operand,
+//   N = free modes of the B operand,
+//   K = contracted pairs,
+// and every element address comes from per-group offset tables:
+//   C[offCM[m] + offCN[n]] += sum_k A[offAM[m] + offAK[k]] * B[offBK[k] + offBN[n]].
+// Section 6 of the paper computes the same sums by walking the free and the
+// contracted coordinates with odometers (Algorithms 1 and 2); the tables hold
+// exactly the increment-times-coordinate sums those walks produce, once per
+// group instead of once per term.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gett.h"
+
+namespace gett {
+
+enum Prec : int { kF64 = 0, kF32 = 1, kBF3 = 2, kFP8 = 3 };
+
+constexpr int kThreads = 256;       // 4 waves of 64 per workgroup
+constexpr int kNumTiles = 5;        // tile menu size per precision
+constexpr int kNumOrders = 4;
+constexpr int kNumSplits = 4;       // split-K factors 1, 2, 4, 8
+constexpr int kSplitFactor[kNumSplits] = {1, 2, 4, 8};
+constexpr int kTablePad = 256;      // M/N tables padded to a multiple of this
+
+struct TileShape { int bm, bn, bk; };
+
+// Tile menus.  FP64/FP32 run 16x16x4 MFMA steps (BK multiple of 4), the BF16x3
+// path 16x16x32 BF16 MFMA steps (BK multiple of 32).  Each workgroup is a 2x2
+// grid of waves, so BM and BN are multiples of 32.
+constexpr TileShape kTiles[4][kNumTiles] = {
+    /* FP64   */ {{64, 64, 16}, {64, 128, 16}, {128, 64, 16}, {128, 128, 16}, {128, 128, 8}},
+    /* FP32   */ {{64, 64, 16}, {64, 128, 16}, {128, 64, 16}, {128, 128, 16}, {128, 128, 32}},
+    /* BF16x3 */ {{64, 64, 32}, {64, 128, 32}, {128, 64, 32}, {128, 128, 32}, {128, 128, 64}},
+    /* FP8    */ {{64, 64, 128}, {64, 128, 128}, {128, 64, 128}, {128, 128, 128}, {128, 128, 128}},
+};
+
+// Arguments of one tile kernel launch (passed by value in the kernarg segment).
+struct TileParams {
+    const void *A;
+    const void *B;
+    void *C;
+    const int64_t *offAM, *offCM;   // M tables (padded)
+    const int64_t *offBN, *offCN;   // N tables (padded)
+    const int64_t *offAK, *offBK;   // K tables (padded to a multiple of BK)
+    int64_t M, N, K;
+    int64_t kPerSplit;              // contracted positions per split (multiple of BK)
+    int32_t tilesM, tilesN, splits;
+    int32_t bBoxX;                  // B loader sub-box width along its fast free mode
+    double *ws;                     // split-K partials [split][M][N], n fastest; null = direct
+};
+
+// One problem of a batched launch (device-resident descriptor).
+struct BatchProblem {
+    TileParams p;
+    int32_t aFastK, bFastK;
+    int32_t tileBase;               // first work item of this problem
+    int32_t pad_;
+};
+
+// Kernel launchers (defined in the .hip files).
+int launch_tile(int prec, int tile, bool aFastK, bool bFastK, const TileParams &p,
+                hipStream_t s);
+int launch_splitk_reduce(int prec, const TileParams &p, hipStream_t s);
+int launch_batch(int prec, const BatchProblem *d_probs, int32_t nprobs, const int32_t *d_items,
+                 int32_t nitems, int32_t grid, hipStream_t s);
+int batch_grid_size(int prec);
+
+// FP8 path: quantisation into canonical K-contiguous rows and the GEMM on them.
+int launch_fp8_quant(const float *X, const int64_t *offR, int64_t rows, int64_t rowsPad,
+                     const int64_t *offK, int64_t K, uint8_t *Q, int32_t *E, hipStream_t s);
+int launch_fp8_gemm(int tile, const uint8_t *QA, const int32_t *EA, const uint8_t *QB,
+                    const int32_t *EB, float *C, const int64_t *offCM, const int64_t *offCN,
+                    int64_t M, int64_t N, int64_t K, hipStream_t s);
+
+// MLP kernels.
+int launch_mlp_linear_fwd(const float *X, const float *W, const float *b, float *Y, int64_t batch,
+                          int64_t din, int64_t dout, int relu, hipStream_t s);
+int launch_mlp_linear_bwd(const float *X, const float *W, const float *Y, const float *dY,
+                          float *dX, float *dW, float *db, int64_t batch, int64_t din,
+                          int64_t dout, int relu, hipStream_t s);
+int launch_mlp_xent(const float *Z, const float *T, float *dZ, float *loss, int64_t batch,
+                    int64_t total, int64_t nheads, const int64_t *head_sizes, hipStream_t s);
+int launch_mlp_adam(float *P, const float *G, float *m, float *v, int64_t n, float lr, float b1,
+                    float b2, float eps, int64_t t, hipStream_t s);
+
+}  // namespace gett

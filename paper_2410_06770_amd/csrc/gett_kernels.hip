@@ -1,0 +1,516 @@
+// gett_kernels.hip -- table-driven contraction tiles for gfx950 (MI355X).
+//
+// One workgroup (4 waves, 2x2) owns a BM x BN tile of the planned GEMM
+//   C[offCM[m] + offCN[n]] += sum_k A[offAM[m] + offAK[k]] * B[offBK[k] + offBN[n]]
+// and walks K in steps of BK:
+//   gather:  each thread reads its share of the A and B sub-tiles straight
+//            from the strided tensors (no packed copy is ever written).  For
+//            each operand the planner says whether its cheapest direction in
+//            memory is the free axis or the contracted axis; consecutive
+//            threads run along that axis so that a wave's loads share cache
+//            lines.  The free offsets a thread needs are fixed for the whole
+//            tile and held in registers; the contracted offsets of a step are
+//            either wave-uniform (scalar loads) or one vector load.
+//   stage:   values go to LDS (double-buffered; the next step's global loads
+//            are in flight while the current step runs on the matrix cores).
+//            The BF16x3 path splits each FP32 value into hi/lo bfloat16 planes
+//            on the way into LDS.
+//   MFMA:    FP64 and FP32 use the 16x16x4 MFMA, BF16x3 the 16x16x32 BF16 MFMA
+//            (hi*hi into one FP32 accumulator, hi*lo + lo*hi into another).
+//   epilogue: the planner puts C's fastest mode on the N axis, which is the
+//            lane axis of the MFMA result, so 16 lanes update 16 neighbouring
+//            outputs; PERM and INCC live entirely in the offC tables.  With
+//            split-K the partial sums go to a workspace instead and a second
+//            kernel adds them to C_in in a fixed order, in FP64.
+// The sum is Algorithm 1's inner loop (Section 6) for every output of the
+// tile at once; only the summation order differs.
+#include "gett_internal.h"
+
+namespace gett {
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+__device__ __forceinline__ int wave_id() {
+    return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2).  Renumber them so that each XCD receives a contiguous run of logical
+// tiles: neighbouring tiles share A rows or B columns in that XCD's L2.
+__device__ __forceinline__ int xcd_remap(int bid, int total) {
+    const int xcd = bid & 7, local = bid >> 3;
+    const int base = total >> 3, rem = total & 7;
+    return xcd * base + (xcd < rem ? xcd : rem) + local;
+}
+
+// Logical tile -> (tm, tn): groups of 8 tile-rows swept along N.
+__device__ __forceinline__ void tile_coords(int tile, int tilesM, int tilesN, int &tm, int &tn) {
+    constexpr int GM = 8;
+    const int per = GM * tilesN;
+    const int g = tile / per;
+    const int first = g * GM;
+    const int gsz = min(tilesM - first, GM);
+    const int r = tile - g * per;
+    tm = first + r % gsz;
+    tn = r / gsz;
+}
+
+template <int PREC> struct PrecT;
+template <> struct PrecT<kF64> { using T = double; using Acc = d4_t; };
+template <> struct PrecT<kF32> { using T = float; using Acc = f4_t; };
+template <> struct PrecT<kBF3> { using T = float; using Acc = f4_t; };
+
+// Shared-memory layout of one operand tile (ROWS free positions x BK).
+//   FP64/FP32: [BK][ROWS + 1]  (k-major; a 16x4 MFMA operand is 16 neighbours
+//              in one k row; the +1 keeps column writes off one bank)
+//   BF16x3:    hi and lo planes, each [ROWS][BK + 8] bfloat16 (k contiguous;
+//              one 16-byte read gives a lane its 8 k values)
+template <int PREC, int ROWS, int BK> struct OpLds {
+    static constexpr bool kSplit = PREC == kBF3;
+    static constexpr int kLd = kSplit ? BK + 8 : ROWS + 1;
+    static constexpr int kElems = kSplit ? 2 * ROWS * kLd : BK * kLd;
+    static constexpr int kBytes = kSplit ? kElems * 2 : kElems * (PREC == kF64 ? 8 : 4);
+};
+
+// Zeros read in place of masked-off elements (rows past the tile's extent,
+// contracted positions past the range): a load from here needs no select
+// afterwards, so the loaded value can go straight to LDS.
+__device__ __align__(16) double g_gett_zero[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+
+__device__ __forceinline__ int64_t readlane64(int64_t v, int lane) {
+    const int lo = __builtin_amdgcn_readlane((int)(v & 0xffffffff), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(v >> 32), lane);
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// Gather of one operand's ROWS x BK sub-tile into registers.
+template <int PREC, int ROWS, int BK, bool FASTK> struct Gather {
+    using T = typename PrecT<PREC>::T;
+    static constexpr int PER = ROWS * BK / kThreads;   // values per thread
+    static constexpr int NF = FASTK ? PER : 1;
+    static_assert(ROWS * BK % kThreads == 0, "tile too small for the workgroup");
+    static_assert(FASTK ? (kThreads % BK == 0) : (kThreads % ROWS == 0), "loader shape");
+    static_assert(BK <= 64, "one wave holds a step's contracted offsets");
+
+    const T *base[NF];  // X + free offset of each row this thread reads
+    bool okF[NF];
+    int row[NF];        // tile row of each free offset
+    int j0;             // first contracted index of this thread (wave-uniform when !FASTK)
+    int64_t koff;       // contracted offset held by this lane for the current step
+
+    __device__ void init(const T *X, int t, int64_t r0, int64_t nrows,
+                         const int64_t *__restrict__ offFree, int boxX) {
+        if constexpr (!FASTK) {
+            const int il = t % ROWS;                 // consecutive threads: consecutive il
+            const int x = il % boxX, y = il / boxX;  // loader walks the box's x side
+            const int r = y + (ROWS / boxX) * x;     // tile row (C-fast side first)
+            const int64_t g = r0 + r;
+            row[0] = r;
+            okF[0] = g < nrows;
+            base[0] = X + offFree[g];
+            j0 = __builtin_amdgcn_readfirstlane(t / ROWS);
+        } else {
+            j0 = t % BK;
+#pragma unroll
+            for (int i = 0; i < PER; ++i) {
+                const int r = t / BK + i * (kThreads / BK);
+                const int64_t g = r0 + r;
+                row[i] = r;
+                okF[i] = g < nrows;
+                base[i] = X + offFree[g];
+            }
+        }
+    }
+
+    // One vector load per step: lane l holds offK[k0 + (l % BK)] (or
+    // offK[k0 + j0] when threads run along K).
+    __device__ __forceinline__ void load_koffs(const int64_t *__restrict__ offK, int64_t k0) {
+        if constexpr (!FASTK) koff = offK[k0 + (threadIdx.x & 63) % BK];
+        else koff = offK[k0 + j0];
+    }
+
+    __device__ __forceinline__ void load(int64_t k0, int64_t kend, T (&v)[PER]) const {
+        const T *zero = reinterpret_cast<const T *>(g_gett_zero);
+        if constexpr (!FASTK) {
+#pragma unroll
+            for (int i = 0; i < PER; ++i) {
+                const int j = j0 + i * (kThreads / ROWS);   // uniform
+                const int64_t ko = readlane64(koff, j % BK);
+                const T *ptr = (okF[0] && k0 + j < kend) ? base[0] + ko : zero;
+                v[i] = *ptr;
+            }
+        } else {
+            const bool kk = k0 + j0 < kend;
+#pragma unroll
+            for (int i = 0; i < PER; ++i) {
+                const T *ptr = (okF[i] && kk) ? base[i] + koff : zero;
+                v[i] = *ptr;
+            }
+        }
+    }
+
+    // Write the registers into the LDS tile.
+    __device__ __forceinline__ void store(void *lds, const T (&v)[PER]) const {
+        using L = OpLds<PREC, ROWS, BK>;
+        if constexpr (PREC == kBF3) {
+            __bf16 *hi = reinterpret_cast<__bf16 *>(lds);
+            __bf16 *lo = hi + ROWS * L::kLd;
+#pragma unroll
+            for (int i = 0; i < PER; ++i) {
+                const int r = FASTK ? row[i] : row[0];
+                const int j = FASTK ? j0 : j0 + i * (kThreads / ROWS);
+                const float x = v[i];
+                const __bf16 h = (__bf16)x;                 // round to nearest even
+                const float rest = x - (float)h;            // exact
+                hi[r * L::kLd + j] = h;
+                lo[r * L::kLd + j] = (__bf16)rest;
+            }
+        } else {
+            T *s = reinterpret_cast<T *>(lds);
+#pragma unroll
+            for (int i = 0; i < PER; ++i) {
+                const int r = FASTK ? row[i] : row[0];
+                const int j = FASTK ? j0 : j0 + i * (kThreads / ROWS);
+                s[j * L::kLd + r] = v[i];
+            }
+        }
+    }
+};
+
+template <int PREC, int BM, int BN, int BK> struct TileCfg {
+    static constexpr int WTM = BM / 2, WTN = BN / 2;   // per-wave sub-tile
+    static constexpr int FM = WTM / 16, FN = WTN / 16; // 16x16 fragments per wave
+    using LA = OpLds<PREC, BM, BK>;
+    using LB = OpLds<PREC, BN, BK>;
+    static constexpr int kStageBytes = LA::kBytes + LB::kBytes;
+    static constexpr int kLdsBytes = 2 * kStageBytes;
+    static_assert(BK % (PREC == kBF3 ? 32 : 4) == 0, "BK");
+};
+
+// One BM x BN tile over contracted range [kbeg, kend).
+template <int PREC, int BM, int BN, int BK, bool AFK, bool BFK>
+__device__ __forceinline__ void gett_tile(const TileParams &p, int64_t m0, int64_t n0, int64_t kbeg,
+                                          int64_t kend, int split, unsigned char *smem) {
+    using Cfg = TileCfg<PREC, BM, BN, BK>;
+    using T = typename PrecT<PREC>::T;
+    using Acc = typename PrecT<PREC>::Acc;
+    constexpr int FM = Cfg::FM, FN = Cfg::FN;
+    constexpr bool kSplit = PREC == kBF3;
+
+    const int t = threadIdx.x;
+    const int lane = lane_id();
+    const int w = wave_id();
+    const int wm = w >> 1, wn = w & 1;
+
+    Gather<PREC, BM, BK, AFK> ga;
+    Gather<PREC, BN, BK, BFK> gb;
+    const T *__restrict__ A = static_cast<const T *>(p.A);
+    const T *__restrict__ B = static_cast<const T *>(p.B);
+    ga.init(A, t, m0, p.M, p.offAM, BM);
+    gb.init(B, t, n0, p.N, p.offBN, p.bBoxX);
+
+    Acc acc[FM][FN];
+    Acc acx[kSplit ? FM : 1][kSplit ? FN : 1];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+            acc[i][j] = Acc{};
+            if constexpr (kSplit) acx[i][j] = Acc{};
+        }
+
+    T va[Gather<PREC, BM, BK, AFK>::PER];
+    T vb[Gather<PREC, BN, BK, BFK>::PER];
+
+    auto stageA = [&](int buf) { return smem + buf * Cfg::kStageBytes; };
+    auto stageB = [&](int buf) { return smem + buf * Cfg::kStageBytes + Cfg::LA::kBytes; };
+
+    // The K loop is branch-free: every step loads the next step's values
+    // (masked to zero past kend) and the offsets of the step after that.
+    // The contracted tables carry enough zero padding past K for both, so
+    // the extra loads of the last steps stay in bounds.  A loop without
+    // branches lets the accumulators live in the MFMA registers throughout.
+    const int64_t nsteps = (kend - kbeg + BK - 1) / BK;
+    ga.load_koffs(p.offAK, kbeg);
+    gb.load_koffs(p.offBK, kbeg);
+    ga.load(kbeg, kend, va);
+    gb.load(kbeg, kend, vb);
+    ga.load_koffs(p.offAK, kbeg + BK);
+    gb.load_koffs(p.offBK, kbeg + BK);
+    ga.store(stageA(0), va);
+    gb.store(stageB(0), vb);
+    __syncthreads();
+
+    for (int64_t s = 0; s < nsteps; ++s) {
+        const int cur = static_cast<int>(s & 1);
+        const int64_t k1 = kbeg + (s + 1) * BK;
+        // issue the next step's loads first; they land while the MFMAs run
+        ga.load(k1, kend, va);
+        gb.load(k1, kend, vb);
+        ga.load_koffs(p.offAK, k1 + BK);
+        gb.load_koffs(p.offBK, k1 + BK);
+        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (!kSplit) {
+            const T *sa = reinterpret_cast<const T *>(stageA(cur));
+            const T *sb = reinterpret_cast<const T *>(stageB(cur));
+#pragma unroll
+            for (int ks = 0; ks < BK / 4; ++ks) {
+                const int kr = ks * 4 + (lane >> 4);
+                T a[FM], b[FN];
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+                    a[i] = sa[kr * Cfg::LA::kLd + wm * Cfg::WTM + i * 16 + (lane & 15)];
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+                    b[j] = sb[kr * Cfg::LB::kLd + wn * Cfg::WTN + j * 16 + (lane & 15)];
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j) {
+                        if constexpr (PREC == kF64)
+                            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+                        else
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+                    }
+            }
+        } else {
+            const __bf16 *ahi = reinterpret_cast<const __bf16 *>(stageA(cur));
+            const __bf16 *alo = ahi + BM * Cfg::LA::kLd;
+            const __bf16 *bhi = reinterpret_cast<const __bf16 *>(stageB(cur));
+            const __bf16 *blo = bhi + BN * Cfg::LB::kLd;
+#pragma unroll
+            for (int ks = 0; ks < BK / 32; ++ks) {
+                const int kc = ks * 32 + 8 * (lane >> 4);
+                bf8_t ah[FM], al[FM], bh[FN], bl[FN];
+#pragma unroll
+                for (int i = 0; i < FM; ++i) {
+                    const int r = wm * Cfg::WTM + i * 16 + (lane & 15);
+                    ah[i] = *reinterpret_cast<const bf8_t *>(ahi + r * Cfg::LA::kLd + kc);
+                    al[i] = *reinterpret_cast<const bf8_t *>(alo + r * Cfg::LA::kLd + kc);
+                }
+#pragma unroll
+                for (int j = 0; j < FN; ++j) {
+                    const int r = wn * Cfg::WTN + j * 16 + (lane & 15);
+                    bh[j] = *reinterpret_cast<const bf8_t *>(bhi + r * Cfg::LB::kLd + kc);
+                    bl[j] = *reinterpret_cast<const bf8_t *>(blo + r * Cfg::LB::kLd + kc);
+                }
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j) {
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+                        acx[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acx[i][j], 0, 0, 0);
+                        acx[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acx[i][j], 0, 0, 0);
+                    }
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        ga.store(stageA(cur ^ 1), va);
+        gb.store(stageB(cur ^ 1), vb);
+        __syncthreads();
+    }
+
+    // Epilogue.  Fragment (i, j), register v of lane l holds D[row][l%16]
+    // (row = M position, column = N position) with row = 4*(l/16) + v for
+    // the FP32 and BF16 MFMA but row = l/16 + 4*v for the FP64 MFMA.
+    T *__restrict__ Cp = static_cast<T *>(p.C);
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+        const int64_t n = n0 + wn * Cfg::WTN + j * 16 + (lane & 15);
+        const bool nok = n < p.N;
+        const int64_t ocn = p.offCN[n];
+#pragma unroll
+        for (int i = 0; i < FM; ++i) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int rr = PREC == kF64 ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v;
+                const int64_t m = m0 + wm * Cfg::WTM + i * 16 + rr;
+                if (!(nok && m < p.M)) continue;
+                if (p.ws) {
+                    double part;
+                    if constexpr (kSplit) part = (double)acc[i][j][v] + (double)acx[i][j][v];
+                    else part = (double)acc[i][j][v];
+                    p.ws[((int64_t)split * p.M + m) * p.N + n] = part;
+                } else {
+                    const int64_t off = p.offCM[m] + ocn;
+                    if constexpr (PREC == kF64) {
+                        Cp[off] = Cp[off] + acc[i][j][v];
+                    } else if constexpr (PREC == kF32) {
+                        Cp[off] = Cp[off] + acc[i][j][v];
+                    } else {
+                        const double sum = (double)acc[i][j][v] + (double)acx[i][j][v] + (double)Cp[off];
+                        Cp[off] = (float)sum;
+                    }
+                }
+            }
+        }
+    }
+}
+
+template <int PREC, int BM, int BN, int BK, bool AFK, bool BFK>
+__global__ __launch_bounds__(kThreads) void gett_tile_kernel(TileParams p) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int tiles = p.tilesM * p.tilesN;
+    const int total = tiles * p.splits;
+    const int logical = xcd_remap(blockIdx.x, total);
+    const int split = logical / tiles;
+    int tm, tn;
+    tile_coords(logical - split * tiles, p.tilesM, p.tilesN, tm, tn);
+    const int64_t kbeg = (int64_t)split * p.kPerSplit;
+    int64_t kend = kbeg + p.kPerSplit;
+    if (kend > p.K) kend = p.K;
+    gett_tile<PREC, BM, BN, BK, AFK, BFK>(p, (int64_t)tm * BM, (int64_t)tn * BN, kbeg, kend, split,
+                                          smem);
+}
+
+// C[off(m,n)] = C_in + sum_s ws[s][m][n], in FP64, s in order.
+template <int PREC>
+__global__ __launch_bounds__(256) void splitk_reduce_kernel(TileParams p) {
+    using T = typename PrecT<PREC>::T;
+    const int64_t MN = p.M * p.N;
+    T *Cp = static_cast<T *>(p.C);
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < MN;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t m = idx / p.N, n = idx - m * p.N;
+        const int64_t off = p.offCM[m] + p.offCN[n];
+        double s = (double)Cp[off];
+        for (int z = 0; z < p.splits; ++z) s += p.ws[(int64_t)z * MN + idx];
+        Cp[off] = (T)s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Batched launch: one persistent grid walks a work list of (problem, tile)
+// items, longest contraction first; every item runs the same tile code as a
+// single call with the 64x64 tile of the precision.  Each problem's
+// descriptor says which operands read along K, and a uniform switch picks the
+// matching compiled loader variant.
+// ---------------------------------------------------------------------------
+template <int PREC>
+__global__ __launch_bounds__(kThreads) void gett_batch_kernel(const BatchProblem *__restrict__ probs,
+                                                              const int32_t *__restrict__ items,
+                                                              int32_t nitems) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr TileShape ts = kTiles[PREC][0];
+    for (int32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const int32_t pi = items[2 * it];
+        const int32_t tile = items[2 * it + 1];
+        const BatchProblem &bp = probs[pi];
+        const TileParams p = bp.p;
+        int tm, tn;
+        tile_coords(tile, p.tilesM, p.tilesN, tm, tn);
+        const int64_t m0 = (int64_t)tm * ts.bm, n0 = (int64_t)tn * ts.bn;
+        const int variant = bp.aFastK * 2 + bp.bFastK;
+        if (variant == 0)
+            gett_tile<PREC, ts.bm, ts.bn, ts.bk, false, false>(p, m0, n0, 0, p.K, 0, smem);
+        else if (variant == 1)
+            gett_tile<PREC, ts.bm, ts.bn, ts.bk, false, true>(p, m0, n0, 0, p.K, 0, smem);
+        else if (variant == 2)
+            gett_tile<PREC, ts.bm, ts.bn, ts.bk, true, false>(p, m0, n0, 0, p.K, 0, smem);
+        else
+            gett_tile<PREC, ts.bm, ts.bn, ts.bk, true, true>(p, m0, n0, 0, p.K, 0, smem);
+        __syncthreads();   // the next item reuses the LDS stages
+    }
+}
+
+template <int PREC> static int batch_lds() { return TileCfg<PREC, kTiles[PREC][0].bm, kTiles[PREC][0].bn, kTiles[PREC][0].bk>::kLdsBytes; }
+
+int batch_grid_size(int prec) {
+    int dev = 0, cus = 0, occ = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return -1;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return -1;
+    hipError_t e = hipErrorInvalidValue;
+    switch (prec) {
+    case kF64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, gett_batch_kernel<kF64>, kThreads, batch_lds<kF64>()); break;
+    case kF32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, gett_batch_kernel<kF32>, kThreads, batch_lds<kF32>()); break;
+    case kBF3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, gett_batch_kernel<kBF3>, kThreads, batch_lds<kBF3>()); break;
+    default: return -1;
+    }
+    if (e != hipSuccess || occ < 1) occ = 1;
+    return cus * occ;
+}
+
+int launch_batch(int prec, const BatchProblem *d_probs, int32_t nprobs, const int32_t *d_items,
+                 int32_t nitems, int32_t grid, hipStream_t s) {
+    (void)nprobs;
+    if (grid < 1 || nitems < 1) return 0;
+    switch (prec) {
+    case kF64: hipLaunchKernelGGL(gett_batch_kernel<kF64>, dim3(grid), dim3(kThreads), batch_lds<kF64>(), s, d_probs, d_items, nitems); break;
+    case kF32: hipLaunchKernelGGL(gett_batch_kernel<kF32>, dim3(grid), dim3(kThreads), batch_lds<kF32>(), s, d_probs, d_items, nitems); break;
+    case kBF3: hipLaunchKernelGGL(gett_batch_kernel<kBF3>, dim3(grid), dim3(kThreads), batch_lds<kBF3>(), s, d_probs, d_items, nitems); break;
+    default: return GETT_ERR_INTERNAL;
+    }
+    return hipGetLastError() == hipSuccess ? 0 : GETT_ERR_HIP;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+template <int PREC, int BM, int BN, int BK, bool AFK, bool BFK>
+static int launch_one(const TileParams &p, hipStream_t s) {
+    using Cfg = TileCfg<PREC, BM, BN, BK>;
+    auto kern = gett_tile_kernel<PREC, BM, BN, BK, AFK, BFK>;
+    static bool attr_set = false;   // per instantiation; LDS above 64 KB needs opting in
+    if (!attr_set) {
+        if (hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                Cfg::kLdsBytes) != hipSuccess)
+            return GETT_ERR_HIP;
+        attr_set = true;
+    }
+    const int total = p.tilesM * p.tilesN * p.splits;
+    hipLaunchKernelGGL(kern, dim3(total), dim3(kThreads), Cfg::kLdsBytes, s, p);
+    return hipGetLastError() == hipSuccess ? 0 : GETT_ERR_HIP;
+}
+
+template <int PREC, int BM, int BN, int BK>
+static int launch_fast(bool afk, bool bfk, const TileParams &p, hipStream_t s) {
+    if (afk) {
+        if (bfk) return launch_one<PREC, BM, BN, BK, true, true>(p, s);
+        return launch_one<PREC, BM, BN, BK, true, false>(p, s);
+    }
+    if (bfk) return launch_one<PREC, BM, BN, BK, false, true>(p, s);
+    return launch_one<PREC, BM, BN, BK, false, false>(p, s);
+}
+
+template <int PREC>
+static int launch_prec(int tile, bool afk, bool bfk, const TileParams &p, hipStream_t s) {
+    constexpr TileShape t0 = kTiles[PREC][0], t1 = kTiles[PREC][1], t2 = kTiles[PREC][2],
+                        t3 = kTiles[PREC][3], t4 = kTiles[PREC][4];
+    switch (tile) {
+    case 0: return launch_fast<PREC, t0.bm, t0.bn, t0.bk>(afk, bfk, p, s);
+    case 1: return launch_fast<PREC, t1.bm, t1.bn, t1.bk>(afk, bfk, p, s);
+    case 2: return launch_fast<PREC, t2.bm, t2.bn, t2.bk>(afk, bfk, p, s);
+    case 3: return launch_fast<PREC, t3.bm, t3.bn, t3.bk>(afk, bfk, p, s);
+    case 4: return launch_fast<PREC, t4.bm, t4.bn, t4.bk>(afk, bfk, p, s);
+    default: return GETT_ERR_INTERNAL;
+    }
+}
+
+int launch_tile(int prec, int tile, bool aFastK, bool bFastK, const TileParams &p, hipStream_t s) {
+    switch (prec) {
+    case kF64: return launch_prec<kF64>(tile, aFastK, bFastK, p, s);
+    case kF32: return launch_prec<kF32>(tile, aFastK, bFastK, p, s);
+    case kBF3: return launch_prec<kBF3>(tile, aFastK, bFastK, p, s);
+    default: return GETT_ERR_INTERNAL;
+    }
+}
+
+int launch_splitk_reduce(int prec, const TileParams &p, hipStream_t s) {
+    const int64_t MN = p.M * p.N;
+    int64_t blocks = (MN + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    if (blocks < 1) blocks = 1;
+    switch (prec) {
+    case kF64: hipLaunchKernelGGL(splitk_reduce_kernel<kF64>, dim3(blocks), dim3(256), 0, s, p); break;
+    case kF32: hipLaunchKernelGGL(splitk_reduce_kernel<kF32>, dim3(blocks), dim3(256), 0, s, p); break;
+    case kBF3: hipLaunchKernelGGL(splitk_reduce_kernel<kBF3>, dim3(blocks), dim3(256), 0, s, p); break;
+    default: return GETT_ERR_INTERNAL;
+    }
+    return hipGetLastError() == hipSuccess ? 0 : GETT_ERR_HIP;
+}
+
+}  // namespace gett

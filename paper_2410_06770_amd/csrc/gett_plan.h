@@ -1,0 +1,66 @@
+// gett_plan.h -- host planner: argument checks, M/N/K grouping, offset tables.
+#pragma once
+
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+namespace gett {
+
+// The 14 xGETT arguments (Section 5.7), pointers excluded.
+struct Args {
+    int64_t ranka;
+    const int64_t *exta, *inca;
+    int64_t rankb;
+    const int64_t *extb, *incb;
+    int64_t conts;
+    const int64_t *conta, *contb, *perm, *incc;
+};
+
+// LAPACK-style INFO (0 or -i).  Pointers are only tested against NULL.
+int validate(const Args &a, const void *A, const void *B, const void *C);
+
+// One mode of a group: extent and the increments of the two tensors that
+// carry the group (M: A and C; N: B and C; K: A and B).
+struct GMode {
+    int64_t ext;
+    int64_t i0, i1;
+};
+
+// The contraction as a GEMM over three mode groups.
+struct Canon {
+    bool empty = false;          // a zero extent: nothing to do
+    bool swapped = false;        // A and B exchanged (so that C's fastest mode is in N)
+    std::vector<GMode> m, n, k;  // ordered, first mode fastest
+    int64_t M = 1, N = 1, K = 1;
+    bool aFastK = false, bFastK = false;
+    int boxX = 0;                // B loader box width (0: none)
+};
+
+// Canonicalise for mode-ordering option `order` (0..3) and tile width bn.
+//   0: heuristic -- swap, merge, M by A strides, N boxed when B's and C's
+//      fastest N modes differ, K by the operand that reads along K;
+//   1: as 0, N ordered by C strides (no box);
+//   2: as 0, N ordered by B strides (no box);
+//   3: as 0 with the K order taken from the other operand.
+Canon canonicalise(const Args &a, int order, int bn);
+
+// Offsets of a group for tensor slot s (0: i0, 1: i1), padded with zeros to
+// `padded` entries; first mode fastest.
+void group_offsets(const std::vector<GMode> &g, int slot, int64_t padded, int64_t *out);
+
+// Canonical (schedule-independent) orders used by the FP8 path: rows of A are
+// A's free modes in ascending order, rows of B likewise, contracted positions
+// follow the pairs in CONTA order; first fastest.  Extent-1 and zero extents
+// are kept (they do not change the linear order).
+void canonical_groups(const Args &a, std::vector<GMode> &rowsA, std::vector<GMode> &rowsB,
+                      std::vector<GMode> &kAB);
+
+// 64-entry feature vector of a signature for precision prec.
+void features(const Args &a, int prec, float *out);
+
+// Plan-cache key of a signature.
+std::string signature_key(const Args &a, int prec, int64_t extra0, int64_t extra1);
+
+}  // namespace gett

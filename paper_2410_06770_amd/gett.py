@@ -1,0 +1,342 @@
+"""ctypes binding of libgett.so (see include/gett.h) -- argument marshalling only.
+
+Every function here has the name and argument order of the C entry point it
+calls: xGETT(RANKA, EXTA, INCA, A, RANKB, EXTB, INCB, B, CONTS, CONTA, CONTB,
+PERM, INCC, C) (Section 5.7 of the paper).  Integer arrays are Python
+sequences; A, B and C are device addresses (ints), e.g. ``t.data_ptr()`` of a
+torch CUDA tensor, plus ``base * t.element_size()`` for a view whose
+coordinate 0 is not the first element.  All computation happens in the HIP
+kernels of the library; if the library is missing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.environ.get("GETT_LIB") or os.path.join(_HERE, "libgett.so")
+
+GETT_FP64, GETT_FP32, GETT_BF16X3, GETT_FP8 = 0, 1, 2, 3
+GETT_HEURISTIC, GETT_PREDICT, GETT_AUTOTUNE = 0, 1, 2
+NUM_FEATURES = 64
+NUM_ORDERS = 4
+NUM_SPLITS = 4
+SPLIT_FACTORS = (1, 2, 4, 8)
+
+_lib = None
+i64 = ct.c_int64
+I64P = ct.POINTER(ct.c_int64)
+vp = ct.c_void_p
+
+
+class GettError(RuntimeError):
+    def __init__(self, code: int, where: str = ""):
+        self.code = code
+        super().__init__(f"{where}: {strerror(code)} (code {code})")
+
+
+def lib():
+    """Load libgett.so (built by ``python -m paper_2410_06770_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_2410_06770_amd.build` (there is no fallback)")
+    L = ct.CDLL(LIB_PATH)
+    a14 = [i64, I64P, I64P, vp, i64, I64P, I64P, vp, i64, I64P, I64P, I64P, I64P, vp]
+    for name in ("dgett", "sgett", "sgett_bf16x3", "sgett_fp8"):
+        getattr(L, name).argtypes = a14
+        getattr(L, name).restype = ct.c_int
+    L.sgett_fp8_quantize.argtypes = [i64, I64P, I64P, vp, i64, I64P, vp, vp]
+    L.sgett_fp8_quantize.restype = ct.c_int
+    PP = ct.POINTER(ct.c_void_p)
+    for name in ("sgett_batch", "dgett_batch"):
+        getattr(L, name).argtypes = [i64, i64, I64P, PP, PP, PP, I64P, PP, PP, PP, I64P, PP, PP,
+                                     PP, PP, PP, I64P]
+        getattr(L, name).restype = ct.c_int
+    L.gett_set_stream.argtypes = [vp]
+    L.gett_get_stream.restype = vp
+    L.gett_set_policy.argtypes = [ct.c_int]
+    L.gett_load_predictor.argtypes = [ct.c_char_p]
+    L.gett_num_tiles.argtypes = [ct.c_int]
+    L.gett_num_tiles.restype = i64
+    L.gett_tile_shape.argtypes = [ct.c_int, i64, I64P]
+    L.gett_set_schedule.argtypes = [i64]
+    L.gett_last_schedule.restype = i64
+    L.gett_autotune.argtypes = [ct.c_int, i64, I64P, I64P, vp, i64, I64P, I64P, vp, i64, I64P,
+                                I64P, I64P, I64P, vp, i64, i64, ct.POINTER(ct.c_double), i64,
+                                ct.POINTER(ct.c_int)]
+    L.gett_autotune.restype = i64
+    a11 = [i64, I64P, I64P, i64, I64P, I64P, i64, I64P, I64P, I64P, I64P]
+    L.gett_features.argtypes = [ct.c_int] + a11 + [ct.POINTER(ct.c_float)]
+    L.gett_plan_describe.argtypes = [ct.c_int, i64, i64] + a11 + [I64P, i64]
+    L.gett_plan_describe.restype = i64
+    L.gett_plan_tables.argtypes = [ct.c_int, i64, i64] + a11 + [I64P, i64]
+    L.gett_plan_tables.restype = i64
+    L.gett_strerror.argtypes = [ct.c_int]
+    L.gett_strerror.restype = ct.c_char_p
+    L.gett_mlp_linear_fwd.argtypes = [vp, vp, vp, vp, i64, i64, i64, ct.c_int]
+    L.gett_mlp_linear_bwd.argtypes = [vp, vp, vp, vp, vp, vp, vp, i64, i64, i64, ct.c_int]
+    L.gett_mlp_softmax_xent.argtypes = [vp, vp, vp, vp, i64, i64, I64P]
+    L.gett_mlp_adam.argtypes = [vp, vp, vp, vp, i64, ct.c_float, ct.c_float, ct.c_float,
+                                ct.c_float, i64]
+    _lib = L
+    return L
+
+
+def _arr(v: Optional[Sequence[int]]):
+    if v is None:
+        return None
+    v = [int(x) for x in v]
+    if not v:
+        return None
+    return (ct.c_int64 * len(v))(*v)
+
+
+def strerror(code: int) -> str:
+    try:
+        return lib().gett_strerror(int(code)).decode()
+    except RuntimeError:
+        return f"error {code}"
+
+
+def _call14(name, ranka, exta, inca, A, rankb, extb, incb, B, conts, conta, contb, perm, incc, C):
+    return getattr(lib(), name)(int(ranka), _arr(exta), _arr(inca), vp(A) if A else None,
+                                int(rankb), _arr(extb), _arr(incb), vp(B) if B else None,
+                                int(conts), _arr(conta), _arr(contb), _arr(perm), _arr(incc),
+                                vp(C) if C else None)
+
+
+def dgett(ranka, exta, inca, A, rankb, extb, incb, B, conts, conta, contb, perm, incc, C) -> int:
+    return _call14("dgett", ranka, exta, inca, A, rankb, extb, incb, B, conts, conta, contb,
+                   perm, incc, C)
+
+
+def sgett(ranka, exta, inca, A, rankb, extb, incb, B, conts, conta, contb, perm, incc, C) -> int:
+    return _call14("sgett", ranka, exta, inca, A, rankb, extb, incb, B, conts, conta, contb,
+                   perm, incc, C)
+
+
+def sgett_bf16x3(ranka, exta, inca, A, rankb, extb, incb, B, conts, conta, contb, perm, incc,
+                 C) -> int:
+    return _call14("sgett_bf16x3", ranka, exta, inca, A, rankb, extb, incb, B, conts, conta,
+                   contb, perm, incc, C)
+
+
+def sgett_fp8(ranka, exta, inca, A, rankb, extb, incb, B, conts, conta, contb, perm, incc,
+              C) -> int:
+    return _call14("sgett_fp8", ranka, exta, inca, A, rankb, extb, incb, B, conts, conta,
+                   contb, perm, incc, C)
+
+
+ENTRY = {GETT_FP64: dgett, GETT_FP32: sgett, GETT_BF16X3: sgett_bf16x3, GETT_FP8: sgett_fp8}
+
+
+def sgett_fp8_quantize(rankx, extx, incx, X, conts, contx, QX, EX) -> int:
+    return lib().sgett_fp8_quantize(int(rankx), _arr(extx), _arr(incx), vp(X) if X else None,
+                                    int(conts), _arr(contx), vp(QX) if QX else None,
+                                    vp(EX) if EX else None)
+
+
+def _batch(name, count, prec, ranka, exta, inca, A, rankb, extb, incb, B, conts, conta, contb,
+           perm, incc, C, info=None):
+    n = int(count)
+    keep = []
+
+    def ptrs(lists):
+        arrs = [_arr(x) for x in lists]
+        keep.extend(arrs)
+        out = (ct.c_void_p * max(n, 1))()
+        for i, a in enumerate(arrs):
+            out[i] = ct.cast(a, ct.c_void_p).value if a is not None else None
+        return out
+
+    def addrs(v):
+        out = (ct.c_void_p * max(n, 1))()
+        for i, x in enumerate(v):
+            out[i] = int(x) if x else None
+        return out
+
+    infos = (ct.c_int64 * max(n, 1))()
+    rc = getattr(lib(), name)(n, int(prec), _arr(ranka) or (ct.c_int64 * 1)(), ptrs(exta),
+                              ptrs(inca), addrs(A), _arr(rankb) or (ct.c_int64 * 1)(), ptrs(extb),
+                              ptrs(incb), addrs(B), _arr(conts) or (ct.c_int64 * 1)(), ptrs(conta),
+                              ptrs(contb), ptrs(perm), ptrs(incc), addrs(C), infos)
+    if info is not None:
+        info[:] = [int(infos[i]) for i in range(n)]
+    return rc
+
+
+def sgett_batch(count, prec, ranka, exta, inca, A, rankb, extb, incb, B, conts, conta, contb,
+                perm, incc, C, info=None) -> int:
+    return _batch("sgett_batch", count, prec, ranka, exta, inca, A, rankb, extb, incb, B, conts,
+                  conta, contb, perm, incc, C, info)
+
+
+def dgett_batch(count, prec, ranka, exta, inca, A, rankb, extb, incb, B, conts, conta, contb,
+                perm, incc, C, info=None) -> int:
+    return _batch("dgett_batch", count, prec, ranka, exta, inca, A, rankb, extb, incb, B, conts,
+                  conta, contb, perm, incc, C, info)
+
+
+# --------------------------------------------------------------------- control
+def gett_set_stream(stream_handle: int) -> int:
+    return lib().gett_set_stream(vp(stream_handle) if stream_handle else None)
+
+
+def gett_set_policy(policy: int) -> int:
+    return lib().gett_set_policy(int(policy))
+
+
+def gett_get_policy() -> int:
+    return lib().gett_get_policy()
+
+
+def gett_load_predictor(path: str) -> int:
+    return lib().gett_load_predictor(path.encode())
+
+
+def gett_num_tiles(prec: int) -> int:
+    return int(lib().gett_num_tiles(prec))
+
+
+def gett_tile_shape(prec: int, t: int):
+    out = (ct.c_int64 * 3)()
+    rc = lib().gett_tile_shape(prec, t, out)
+    if rc:
+        raise GettError(rc, "gett_tile_shape")
+    return tuple(int(x) for x in out)
+
+
+def gett_set_schedule(sched_id: int) -> int:
+    return lib().gett_set_schedule(int(sched_id))
+
+
+def gett_last_schedule() -> int:
+    return int(lib().gett_last_schedule())
+
+
+def num_schedules() -> int:
+    return gett_num_tiles(0) * NUM_ORDERS * NUM_SPLITS
+
+
+def schedule_id(tile: int, order: int, split: int) -> int:
+    return tile + gett_num_tiles(0) * (order + NUM_ORDERS * split)
+
+
+def schedule_of(sid: int):
+    nt = gett_num_tiles(0)
+    return sid % nt, (sid // nt) % NUM_ORDERS, sid // (nt * NUM_ORDERS)
+
+
+def gett_autotune(prec, ranka, exta, inca, A, rankb, extb, incb, B, conts, conta, contb, perm,
+                  incc, C, warmup=2, reps=5):
+    n = num_schedules()
+    times = (ct.c_double * n)()
+    status = ct.c_int(0)
+    best = lib().gett_autotune(int(prec), int(ranka), _arr(exta), _arr(inca), vp(A), int(rankb),
+                               _arr(extb), _arr(incb), vp(B), int(conts), _arr(conta),
+                               _arr(contb), _arr(perm), _arr(incc), vp(C), int(warmup), int(reps),
+                               times, n, ct.byref(status))
+    if status.value:
+        raise GettError(status.value, "gett_autotune")
+    return int(best), [float(t) for t in times]
+
+
+def gett_features(prec, ranka, exta, inca, rankb, extb, incb, conts, conta, contb, perm, incc):
+    out = (ct.c_float * NUM_FEATURES)()
+    rc = lib().gett_features(int(prec), int(ranka), _arr(exta), _arr(inca), int(rankb),
+                             _arr(extb), _arr(incb), int(conts), _arr(conta), _arr(contb),
+                             _arr(perm), _arr(incc), out)
+    if rc:
+        raise GettError(rc, "gett_features")
+    return np.array(out[:], dtype=np.float32)
+
+
+def _describe(fn, prec, order, tile, args):
+    ranka, exta, inca, rankb, extb, incb, conts, conta, contb, perm, incc = args
+    call = lambda out, n: fn(int(prec), int(order), int(tile), int(ranka), _arr(exta), _arr(inca),
+                             int(rankb), _arr(extb), _arr(incb), int(conts), _arr(conta),
+                             _arr(contb), _arr(perm), _arr(incc), out, n)
+    n = call(None, 0)
+    if n < 0:
+        return int(n)
+    out = (ct.c_int64 * max(int(n), 1))()
+    n2 = call(out, n)
+    if n2 != n:
+        raise GettError(int(n2), "plan introspection")
+    return [int(x) for x in out[:n]]
+
+
+def gett_plan_describe(prec, order, tile, *args):
+    """Canonical groups: dict(swapped, M, N, K, m, n, k, aFastK, bFastK, boxX)
+    with each group a list of (ext, inc0, inc1); or a negative INFO."""
+    v = _describe(lib().gett_plan_describe, prec, order, tile, args)
+    if isinstance(v, int):
+        return v
+    nm, nn, nk = v[4], v[5], v[6]
+    modes = [tuple(v[10 + 3 * i: 13 + 3 * i]) for i in range(nm + nn + nk)]
+    return dict(swapped=bool(v[0]), M=v[1], N=v[2], K=v[3], m=modes[:nm], n=modes[nm:nm + nn],
+                k=modes[nm + nn:], aFastK=bool(v[7]), bFastK=bool(v[8]), boxX=v[9])
+
+
+def gett_plan_tables(prec, order, tile, *args):
+    """(offAM, offCM, offBN, offCN, offAK, offBK) as numpy int64 arrays."""
+    d = gett_plan_describe(prec, order, tile, *args)
+    if isinstance(d, int):
+        return d
+    v = _describe(lib().gett_plan_tables, prec, order, tile, args)
+    M, N, K = d["M"], d["N"], d["K"]
+    a = np.array(v, dtype=np.int64)
+    cuts = np.cumsum([M, M, N, N, K])
+    return tuple(np.split(a, cuts)), d
+
+
+# ------------------------------------------------------------------ MLP kernels
+def gett_mlp_linear_fwd(X, W, b, Y, batch, d_in, d_out, relu) -> int:
+    return lib().gett_mlp_linear_fwd(vp(X), vp(W), vp(b), vp(Y), batch, d_in, d_out, int(relu))
+
+
+def gett_mlp_linear_bwd(X, W, Y, dY, dX, dW, db, batch, d_in, d_out, relu) -> int:
+    return lib().gett_mlp_linear_bwd(vp(X), vp(W), vp(Y), vp(dY), vp(dX) if dX else None,
+                                     vp(dW), vp(db), batch, d_in, d_out, int(relu))
+
+
+def gett_mlp_softmax_xent(Z, T, dZ, loss, batch, head_sizes) -> int:
+    return lib().gett_mlp_softmax_xent(vp(Z), vp(T), vp(dZ), vp(loss), batch, len(head_sizes),
+                                       _arr(head_sizes))
+
+
+def gett_mlp_adam(P, G, m, v, n, lr, beta1, beta2, eps, t) -> int:
+    return lib().gett_mlp_adam(vp(P), vp(G), vp(m), vp(v), n, lr, beta1, beta2, eps, t)
+
+
+def gett_finalize() -> int:
+    return lib().gett_finalize()
+
+
+# ------------------------------------------------------------ torch helpers
+def use_torch_stream():
+    """Make the library queue work on torch's current CUDA (HIP) stream."""
+    import torch
+    gett_set_stream(torch.cuda.current_stream().cuda_stream)
+
+
+def contract(A, B, C, conta, contb, perm, prec: int = None) -> None:
+    """C += contraction of torch CUDA tensors A and B (extents = shape,
+    increments = stride() in elements) over modes CONTA/CONTB, free indices
+    placed in C by PERM.  Raises GettError on a non-zero INFO."""
+    import torch
+    if prec is None:
+        prec = GETT_FP64 if A.dtype == torch.float64 else GETT_FP32
+    use_torch_stream()
+    fn = ENTRY[prec]
+    rc = fn(A.dim(), list(A.shape), list(A.stride()), A.data_ptr(), B.dim(), list(B.shape),
+            list(B.stride()), B.data_ptr(), len(conta), list(conta), list(contb), list(perm),
+            list(C.stride()), C.data_ptr())
+    if rc:
+        raise GettError(rc, fn.__name__)

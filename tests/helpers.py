@@ -95,3 +95,21 @@ def outside_mask(view):
     m = np.ones(view.buf.shape, dtype=bool)
     m[view.element_index()] = False
     return m
+
+
+def to_device(view, device="cuda"):
+    """Copy a view's parent buffer to the GPU: returns (tensor, address of
+    coordinate 0)."""
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(view.buf)).to(device)
+    return t, t.data_ptr() + int(view.base) * t.element_size()
+
+
+def problem_args(pr):
+    return (pr.ranka, pr.exta, pr.inca, pr.rankb, pr.extb, pr.incb, pr.conts, pr.conta,
+            pr.contb, pr.perm, pr.incc)
+
+
+def call14(fn, pr, a, b, c):
+    return fn(pr.ranka, pr.exta, pr.inca, a, pr.rankb, pr.extb, pr.incb, b, pr.conts, pr.conta,
+              pr.contb, pr.perm, pr.incc, c)

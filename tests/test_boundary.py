@@ -1,0 +1,116 @@
+"""The C-ABI library without a GPU: it loads, exports what include/gett.h
+declares, and rejects bad arguments with the documented INFO codes before any
+HIP call."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2410_06770_amd import gett, workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "gett.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w[\w\s\*]*?\b(\w+)\s*\(", src, flags=re.M))
+                  - {"if", "while", "for"})
+
+
+def test_exports_every_declared_symbol():
+    L = gett.lib()
+    names = declared_functions()
+    assert len(names) >= 26, names
+    for n in names:
+        assert hasattr(L, n), f"{n} declared in gett.h but not exported"
+
+
+def test_schedule_menu_introspection():
+    for prec in range(4):
+        assert gett.gett_num_tiles(prec) == 5
+        for t in range(5):
+            bm, bn, bk = gett.gett_tile_shape(prec, t)
+            assert bm % 32 == 0 and bn % 32 == 0 and bk % 4 == 0
+    sid = gett.schedule_id(3, 2, 1)
+    assert gett.schedule_of(sid) == (3, 2, 1)
+
+
+OK = dict(ranka=2, exta=[3, 4], inca=[1, 3], rankb=2, extb=[4, 5], incb=[1, 4], conts=1,
+          conta=[1], contb=[0], perm=[0, 1], incc=[1, 3])
+
+
+def call(fn, A=8, B=8, C=8, **kw):
+    d = dict(OK)
+    d.update(kw)
+    return fn(d["ranka"], d["exta"], d["inca"], A, d["rankb"], d["extb"], d["incb"], B,
+              d["conts"], d["conta"], d["contb"], d["perm"], d["incc"], C)
+
+
+BAD = [(-1, dict(ranka=-1)), (-1, dict(ranka=65)), (-2, dict(exta=[3, -1])),
+       (-3, dict(inca=[1, 2 ** 62])), (-4, dict(A=0)), (-5, dict(rankb=-2)),
+       (-6, dict(extb=[4, -5])), (-7, dict(incb=[2 ** 62, 1])), (-8, dict(B=0)),
+       (-9, dict(conts=3)), (-9, dict(conts=-1)), (-10, dict(conta=[2])),
+       (-10, dict(conts=2, conta=[0, 0], contb=[0, 1])), (-11, dict(contb=[1])),
+       (-11, dict(contb=[5])), (-12, dict(perm=[0, 0])), (-12, dict(perm=[0, 2])),
+       (-13, dict(incc=[0, 3])), (-13, dict(incc=[1, 2 ** 62])), (-14, dict(C=0))]
+
+
+@pytest.mark.parametrize("code,kw", BAD)
+@pytest.mark.parametrize("fn", ["dgett", "sgett", "sgett_bf16x3", "sgett_fp8"])
+def test_info_codes(fn, code, kw):
+    assert call(getattr(gett, fn), **kw) == code
+    # the oracle's independent checks agree
+    d = dict(OK)
+    d.update(kw)
+    A, B, C = d.pop("A", 8), d.pop("B", 8), d.pop("C", 8)
+    assert oracle.check(**d, A=A, B=B, C=C) == code
+
+
+def test_info_codes_agree_with_oracle_on_random_mutations():
+    rng = np.random.default_rng(0)
+    mismatches = 0
+    for i in range(400):
+        sig = W.random_signature(rng, (0, 4), (0, 4), (0, 4), (0, 3))
+        ra, exta, rb, extb, cs, conta, contb, perm = sig
+        args = dict(ranka=ra, exta=list(exta), inca=W.packed_incs(exta), rankb=rb,
+                    extb=list(extb), incb=W.packed_incs(extb), conts=cs, conta=list(conta),
+                    contb=list(contb), perm=list(perm))
+        pr = W.Problem(ra, exta, [], rb, extb, [], cs, conta, contb, perm, [])
+        args["incc"] = W.packed_incs(pr.extc())
+        # one random mutation
+        key = rng.choice(["exta", "conta", "contb", "perm", "incc", "conts", "none"])
+        if key in ("exta", "conta", "contb", "perm", "incc") and args[key]:
+            j = int(rng.integers(len(args[key])))
+            args[key][j] = int(args[key][j] + rng.choice([-2, -1, 1, 2]))
+        elif key == "conts":
+            args["conts"] += int(rng.choice([-1, 1]))
+        expect = oracle.check(**args)
+        if expect == 0:
+            continue          # a valid call would launch a kernel; not on the CPU
+        got = call(gett.dgett, **{k: v for k, v in args.items()})
+        mismatches += got != expect
+    assert mismatches == 0
+
+
+def test_zero_extent_is_a_noop_without_hip():
+    # zero extents return before any HIP call
+    assert call(gett.dgett, exta=[0, 4]) == 0
+    assert call(gett.sgett, extb=[4, 0], exta=[3, 4]) == 0
+
+
+def test_strerror():
+    assert "INCC" in gett.strerror(-13)
+    assert "gfx950" in gett.strerror(3)
+
+
+def test_batch_validation():
+    one = lambda v: [v]
+    rc = gett.sgett_batch(1, gett.GETT_BF16X3, [2], [OK["exta"]], [OK["inca"]], [8], [2],
+                          [OK["extb"]], [OK["incb"]], [8], [1], [[5]], [[0]], [[0, 1]],
+                          [OK["incc"]], [8])
+    assert rc == -1000 - 10
+    assert gett.sgett_batch(1, 7, [2], [[1]], [[1]], [8], [2], [[1]], [[1]], [8], [1], [[0]],
+                            [[0]], [[0, 1]], [[1, 1]], [8]) == -2

@@ -1,0 +1,294 @@
+"""GPU parity: every xGETT entry point against the CPU oracle.
+
+Bars (each derived from the arithmetic of the path, stated per test):
+  * integer-valued inputs in [-4, 4]: every path is exact, so GPU == oracle
+    bit for bit (all partial sums are integers far below 2^24);
+  * FP64: e_nrm <= 1e-12 and, per element, |err| <= (K+2) u64 (|C_in| + sum|a||b|);
+  * FP32: e_nrm <= 1e-5 and |err| <= (K+2) u32 (|C_in| + sum|a||b|);
+  * BF16x3: e_nrm <= 1e-5 and |err| <= (3 * 2^-16 + (K+2) u32) (|C_in| + sum|a||b|)
+    (the split drops lo*lo and the bf16 rounding of the residual, each below
+    2^-16 |a||b|);
+  * FP8: against the exact value of the quantised operands (codes and
+    exponents checked bit for bit against the oracle's quantiser), with the
+    FP32 accumulation bound; its error against the exact FP64 result is
+    reported, not gated.
+Parent elements outside C's view must keep their sentinel; NaN fills outside
+A's and B's views must never reach C.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2410_06770_amd import gett, workloads as W
+from tests.helpers import call14, e_cw, e_nrm, outside_mask, to_device, view_values
+
+pytestmark = pytest.mark.gpu
+
+U64, U32 = 2.0 ** -53, 2.0 ** -24
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    gett.lib()
+    gett.use_torch_stream()
+    yield
+    torch.cuda.synchronize()
+
+
+def as_dtype(pr, dtype):
+    cv = lambda v: W.View(v.buf.astype(dtype), v.base, v.ext, v.inc)
+    return pr.with_views(cv(pr.A), cv(pr.B), cv(pr.C))
+
+
+def run_gpu(pr, prec, tag=""):
+    import torch
+    print(f"\n[gpu] {tag} {pr.name} prec={prec} sig={pr.signature()}", flush=True)
+    At, a = to_device(pr.A)
+    Bt, b = to_device(pr.B)
+    Ct, c = to_device(pr.C)
+    rc = call14(gett.ENTRY[prec], pr, a, b, c)
+    assert rc == 0, gett.strerror(rc)
+    torch.cuda.synchronize()
+    out = Ct.cpu().numpy()
+    del At, Bt, Ct
+    return out
+
+
+def bound(prec, K):
+    if prec == gett.GETT_FP64:
+        return (K + 2) * U64
+    if prec == gett.GETT_FP32:
+        return (K + 2) * U32
+    if prec == gett.GETT_BF16X3:
+        return 3 * 2.0 ** -16 + (K + 2) * U32
+    raise ValueError(prec)
+
+
+def check_against_oracle(pr, prec, got_buf, first=0, last=-1, nrm_tol=None, gate_nrm=True):
+    ref, cabs = oracle.exact(pr, pr.A, pr.B, pr.C, first, last)
+    sel = ~np.isnan(ref)
+    got = got_buf[sel].astype(np.float64)
+    K = pr.mnk()[2]
+    en = e_nrm(got, ref[sel])
+    ec = e_cw(got, ref[sel], cabs[sel])
+    tol = nrm_tol if nrm_tol is not None else (1e-12 if prec == gett.GETT_FP64 else 1e-5)
+    if gate_nrm:
+        assert en <= tol, (pr.name, prec, en)
+    assert ec <= bound(prec, K), (pr.name, prec, ec, bound(prec, K))
+    return en, ec
+
+
+def check_outside(pr, got_buf):
+    m = outside_mask(pr.C)
+    assert np.array_equal(got_buf[m], pr.C.buf[m])
+
+
+PRECS = [gett.GETT_FP64, gett.GETT_FP32, gett.GETT_BF16X3]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("case", W.PAPER_CASES)
+def test_paper_cases(case, prec):
+    rng = np.random.default_rng(abs(hash(case)) % 2 ** 31 + 17 * prec)
+    dtype = np.float64 if prec == gett.GETT_FP64 else np.float32
+    for rep in range(3):
+        pr = W.paper_case(case, rng, dtype=dtype)
+        got = run_gpu(pr, prec, f"rep{rep}")
+        # BF16x3 on a handful of cancelling terms: the element-wise bound is the
+        # gate (the normwise 1e-5 target is for the large contractions)
+        check_against_oracle(pr, prec, got, gate_nrm=prec != gett.GETT_BF16X3)
+        check_outside(pr, got)
+
+
+@pytest.mark.parametrize("prec", PRECS + [gett.GETT_FP8])
+@pytest.mark.parametrize("case", W.PAPER_CASES)
+def test_paper_cases_integers_bitwise(case, prec):
+    rng = np.random.default_rng(abs(hash(case)) % 2 ** 31 + 101 + prec)
+    dtype = np.float64 if prec == gett.GETT_FP64 else np.float32
+    for rep in range(2):
+        pr = W.paper_case(case, rng, dtype=dtype, dist="int")
+        got = run_gpu(pr, prec, f"int rep{rep}")
+        ref, _ = oracle.exact(pr, pr.A, pr.B, pr.C)
+        sel = ~np.isnan(ref)
+        assert np.array_equal(got[sel].astype(np.float64), ref[sel]), (case, prec)
+        check_outside(pr, got)
+
+
+def test_small_dgett_config():
+    for order in ((1, 2), (2, 1)):
+        pr = W.config_small_dgett(contract_order=order)
+        got = run_gpu(pr, gett.GETT_FP64, f"order{order}")
+        check_against_oracle(pr, gett.GETT_FP64, got)
+        pri = W.config_small_dgett(integer=True, contract_order=order)
+        goti = run_gpu(pri, gett.GETT_FP64, "int")
+        ref, _ = oracle.exact(pri, pri.A, pri.B, pri.C)
+        assert np.array_equal(view_values(pri.C, goti), view_values(pri.C, ref))
+
+
+def test_accumulates_onto_nonzero_c():
+    rng = np.random.default_rng(5)
+    for prec in PRECS:
+        dtype = np.float64 if prec == gett.GETT_FP64 else np.float32
+        pr = W.paper_case("basic", rng, dtype=dtype)
+        pr.C.buf[pr.C.element_index()] = rng.standard_normal(pr.C.element_index().size)
+        got = run_gpu(pr, prec, "accumulate")
+        check_against_oracle(pr, prec, got, gate_nrm=prec != gett.GETT_BF16X3)
+
+
+def _samples(total, n=3, width=1500):
+    starts = [0, total // 2 - width // 2, total - width]
+    return [(max(s, 0), min(s + width, total)) for s in starts[:n]]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_strided_permuted_full_size(prec):
+    """The strided + permuted workload at full size, in the launch the
+    benchmark times; outputs checked on sampled ranges of the free odometer."""
+    dtype = np.float64 if prec == gett.GETT_FP64 else np.float32
+    pr = W.config_strided_perm(dtype=dtype)
+    got = run_gpu(pr, prec, "full")
+    total = int(np.prod(pr.extc()))
+    for first, last in _samples(total):
+        check_against_oracle(pr, prec, got, first, last)
+    assert not np.isnan(got[pr.C.element_index()]).any()
+
+
+@pytest.mark.parametrize("reading", ["ii", "iii"])
+def test_strided_permuted_other_readings(reading):
+    for prec in PRECS:
+        dtype = np.float64 if prec == gett.GETT_FP64 else np.float32
+        pr = W.config_strided_perm(dtype=dtype, reading=reading)
+        got = run_gpu(pr, prec, reading)
+        total = int(np.prod(pr.extc()))
+        for first, last in _samples(total, 2):
+            check_against_oracle(pr, prec, got, first, last)
+
+
+@pytest.mark.parametrize("prec", [gett.GETT_FP32, gett.GETT_BF16X3])
+def test_cc_full_size(prec):
+    pr = W.config_cc()
+    got = run_gpu(pr, prec, "cc")
+    total = int(np.prod(pr.extc()))
+    for first, last in _samples(total):
+        check_against_oracle(pr, prec, got, first, last)
+
+
+def test_every_schedule_matches(capsys):
+    """Each (tile, order, split) schedule on a ragged strided problem."""
+    import torch
+    rng = np.random.default_rng(77)
+    sig = (4, [13, 17, 9, 6], 3, [6, 21, 9], 2, [2, 3], [2, 0], [2, 0, 1])
+    for prec in PRECS:
+        dtype = np.float64 if prec == gett.GETT_FP64 else np.float32
+        pr = W.build_problem(rng, sig, dtype, "sub", "step2", "sub")
+        K = pr.mnk()[2]
+        for sid in range(gett.num_schedules()):
+            tile, order, split = gett.schedule_of(sid)
+            bk = gett.gett_tile_shape(prec, tile)[2]
+            if gett.SPLIT_FACTORS[split] > 1 and K < gett.SPLIT_FACTORS[split] * bk:
+                continue
+            assert gett.gett_set_schedule(sid) == 0
+            try:
+                got = run_gpu(pr, prec, f"sched{sid}")
+            finally:
+                gett.gett_set_schedule(-1)
+            check_against_oracle(pr, prec, got, gate_nrm=prec != gett.GETT_BF16X3)
+            check_outside(pr, got)
+
+
+def test_splitk_deterministic():
+    import torch
+    pr = W.config_strided_perm(dtype=np.float64, reading="ii")
+    sid = gett.schedule_id(3, 0, 2)      # split 4
+    gett.gett_set_schedule(sid)
+    try:
+        g1 = run_gpu(pr, gett.GETT_FP64, "split4 a")
+        g2 = run_gpu(pr, gett.GETT_FP64, "split4 b")
+    finally:
+        gett.gett_set_schedule(-1)
+    assert np.array_equal(g1, g2)
+    check_against_oracle(pr, gett.GETT_FP64, g1, 0, 3000)
+
+
+# ----------------------------------------------------------------------- FP8
+def _fp8_reference(pr):
+    A32, B32 = pr.A, pr.B
+    rA, rB, kA, kB = oracle.canonical_offsets(pr)
+    QA, EA = oracle.fp8_quantize(A32, rA, kA)
+    QB, EB = oracle.fp8_quantize(B32, rB, kB)
+    return QA, EA, QB, EB, len(kA)
+
+
+def test_fp8_quantizer_codes_bitwise():
+    import torch
+    rng = np.random.default_rng(31)
+    for shape, cont in (([40, 300], [1]), ([7, 5, 33, 6], [2, 0]), ([130, 129], [0])):
+        X = W.make_view(shape, rng, np.float32, layout="sub", dist="normal")
+        X.buf[X.element_index()] *= (10.0 ** rng.uniform(-3, 3, X.element_index().size)).astype(np.float32)
+        free = [i for i in range(len(shape)) if i not in cont]
+        rows = W.View(X.buf, X.base, [shape[i] for i in free], [X.inc[i] for i in free])
+        ks = W.View(X.buf, 0, [shape[i] for i in cont], [X.inc[i] for i in cont])
+        r_off = rows.element_index() - X.base
+        k_off = ks.element_index()
+        Q, E = oracle.fp8_quantize(X, r_off, k_off)
+        Xt, x = to_device(X)
+        Qt = torch.zeros(Q.shape, dtype=torch.uint8, device="cuda")
+        Et = torch.zeros(E.shape, dtype=torch.int32, device="cuda")
+        print(f"\n[gpu] fp8 quantize shape={shape} cont={cont}", flush=True)
+        rc = gett.sgett_fp8_quantize(len(shape), shape, X.inc, x, len(cont), cont,
+                                     Qt.data_ptr(), Et.data_ptr())
+        assert rc == 0
+        torch.cuda.synchronize()
+        assert np.array_equal(Et.cpu().numpy(), E)
+        assert np.array_equal(Qt.cpu().numpy(), Q)
+
+
+@pytest.mark.parametrize("case", ["basic", "subtensor", "negative", "cube_2", "hypercube_3",
+                                  "scalar", "nothing", "lowerrank"])
+def test_fp8_against_quantised_model(case):
+    rng = np.random.default_rng(abs(hash(case)) % 2 ** 31 + 9)
+    for rep in range(3):
+        pr = W.paper_case(case, rng, dtype=np.float32, dist="normal")
+        got = run_gpu(pr, gett.GETT_FP8, f"fp8 rep{rep}")
+        QA, EA, QB, EB, K = _fp8_reference(pr)
+        model = oracle.fp8_gemm(QA, EA, QB, EB, K)          # [rowsA, rowsB] in canonical orders
+        # place the model into C's layout: canonical rows are the free lists in order
+        ref, cabs = oracle.exact(pr, pr.A, pr.B, pr.C)
+        fa, fb = pr.free_modes()
+        extc = pr.extc()
+        idx = pr.C.element_index()                         # C positions, column-major over C modes
+        cvals = got[idx].astype(np.float64).reshape(extc, order="F") if extc else got[idx]
+        # output coordinates -> (row of A, row of B)
+        grid = np.indices(extc) if extc else np.zeros((0,), dtype=np.int64)
+        pos = {q: p for p, q in enumerate(pr.perm)}
+        ra = np.zeros(extc, dtype=np.int64) if extc else np.int64(0)
+        rb = np.zeros(extc, dtype=np.int64) if extc else np.int64(0)
+        s = 1
+        for p, i in enumerate(fa):
+            ra = ra + grid[pr.perm[p]] * s
+            s *= pr.exta[i]
+        s = 1
+        for p, j in enumerate(fb):
+            rb = rb + grid[pr.perm[len(fa) + p]] * s
+            s *= pr.extb[j]
+        mval = model[ra, rb]
+        cin = pr.C.buf[idx].astype(np.float64).reshape(extc, order="F") if extc else pr.C.buf[idx]
+        exp = mval + cin
+        bnd = view_values(pr.C, cabs) * 1.3 * (K + 2) * U32 + 1e-30
+        assert np.all(np.abs(cvals - exp) <= bnd), case
+        check_outside(pr, got)
+
+
+def test_fp8_cc_error_is_reported():
+    """FP8 on the precision-study workload: quantisation error against the
+    exact result is reported (not gated); codes follow the model."""
+    pr = W.config_cc()
+    got = run_gpu(pr, gett.GETT_FP8, "cc fp8")
+    ref, cabs = oracle.exact(pr, pr.A, pr.B, pr.C, 0, 3000)
+    sel = ~np.isnan(ref)
+    en = e_nrm(got[sel], ref[sel])
+    print(f"\n[fp8] cc e_nrm={en:.3e} e_cw={e_cw(got[sel], ref[sel], cabs[sel]):.3e}")
+    assert en < 0.1
