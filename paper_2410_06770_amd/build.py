@@ -18,7 +18,16 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.environ.get("GETT_LIB_OUT") or os.path.join(HERE, "libgett.so")
 
-SOURCES = ["gett_kernels.hip", "gett_fp8.hip", "gett_mlp.hip", "gett_plan.cpp", "gett_host.cpp"]
+SOURCES = ["gett_tile_f64.hip", "gett_tile_f32.hip", "gett_tile_bf3.hip", "gett_fp8.hip",
+           "gett_mlp.hip", "gett_dispatch.cpp", "gett_plan.cpp", "gett_host.cpp"]
+# Per-file code generation: the FP64 and FP32 tiles keep their MFMA
+# accumulators in ordinary VGPRs (no per-step copies to the accumulation
+# registers, lower register totals and higher occupancy); the BF16x3 tile,
+# which carries two accumulator sets, does better with the default form.
+FILE_FLAGS = {
+    "gett_tile_f64.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+    "gett_tile_f32.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+}
 ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}"]
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
@@ -31,7 +40,8 @@ def _compile(src: str) -> str:
     path = os.path.join(CSRC, src)
     obj = os.path.join(OBJ, src + ".o")
     if src.endswith(".hip"):
-        cmd = ["hipcc", "-x", "hip", *DEVICE, *COMMON, *EXTRA, "-c", path, "-o", obj]
+        cmd = ["hipcc", "-x", "hip", *DEVICE, *COMMON, *FILE_FLAGS.get(src, []), *EXTRA, "-c",
+               path, "-o", obj]
     else:
         cmd = ["hipcc", *COMMON, "-c", path, "-o", obj]
     subprocess.check_call(cmd)

@@ -1,0 +1,54 @@
+// gett_dispatch.cpp -- routes launches to the per-precision tile objects.
+#include "gett_internal.h"
+
+namespace gett {
+
+#define GETT_DECLARE_PRECISION(SUFFIX)                                                             \
+    int launch_tile_##SUFFIX(int tile, bool afk, bool bfk, const TileParams &p, hipStream_t s);    \
+    int launch_splitk_reduce_##SUFFIX(const TileParams &p, hipStream_t s);                        \
+    int batch_grid_size_##SUFFIX();                                                                \
+    int launch_batch_##SUFFIX(const BatchProblem *d, const int32_t *it, int32_t n, int32_t g,      \
+                              hipStream_t s);
+GETT_DECLARE_PRECISION(f64)
+GETT_DECLARE_PRECISION(f32)
+GETT_DECLARE_PRECISION(bf3)
+
+int launch_tile(int prec, int tile, bool aFastK, bool bFastK, const TileParams &p, hipStream_t s) {
+    switch (prec) {
+    case kF64: return launch_tile_f64(tile, aFastK, bFastK, p, s);
+    case kF32: return launch_tile_f32(tile, aFastK, bFastK, p, s);
+    case kBF3: return launch_tile_bf3(tile, aFastK, bFastK, p, s);
+    default: return GETT_ERR_INTERNAL;
+    }
+}
+
+int launch_splitk_reduce(int prec, const TileParams &p, hipStream_t s) {
+    switch (prec) {
+    case kF64: return launch_splitk_reduce_f64(p, s);
+    case kF32: return launch_splitk_reduce_f32(p, s);
+    case kBF3: return launch_splitk_reduce_bf3(p, s);
+    default: return GETT_ERR_INTERNAL;
+    }
+}
+
+int batch_grid_size(int prec) {
+    switch (prec) {
+    case kF64: return batch_grid_size_f64();
+    case kF32: return batch_grid_size_f32();
+    case kBF3: return batch_grid_size_bf3();
+    default: return -1;
+    }
+}
+
+int launch_batch(int prec, const BatchProblem *d_probs, int32_t nprobs, const int32_t *d_items,
+                 int32_t nitems, int32_t grid, hipStream_t s) {
+    (void)nprobs;
+    switch (prec) {
+    case kF64: return launch_batch_f64(d_probs, d_items, nitems, grid, s);
+    case kF32: return launch_batch_f32(d_probs, d_items, nitems, grid, s);
+    case kBF3: return launch_batch_bf3(d_probs, d_items, nitems, grid, s);
+    default: return GETT_ERR_INTERNAL;
+    }
+}
+
+}  // namespace gett

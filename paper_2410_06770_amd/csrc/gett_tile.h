@@ -1,4 +1,4 @@
-// gett_kernels.hip -- table-driven contraction tiles for gfx950 (MI355X).
+// gett_tile.h -- table-driven contraction tiles for gfx950 (MI355X).
 //
 // One workgroup (4 waves, 2x2) owns a BM x BN tile of the planned GEMM
 //   C[offCM[m] + offCN[n]] += sum_k A[offAM[m] + offAK[k]] * B[offBK[k] + offBN[n]]
@@ -24,6 +24,8 @@
 //            kernel adds them to C_in in a fixed order, in FP64.
 // The sum is Algorithm 1's inner loop (Section 6) for every output of the
 // tile at once; only the summation order differs.
+#pragma once
+
 #include "gett_internal.h"
 
 namespace gett {
@@ -78,7 +80,7 @@ template <int PREC, int ROWS, int BK> struct OpLds {
 // Zeros read in place of masked-off elements (rows past the tile's extent,
 // contracted positions past the range): a load from here needs no select
 // afterwards, so the loaded value can go straight to LDS.
-__device__ __align__(16) double g_gett_zero[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+static __device__ __align__(16) double g_gett_zero[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 
 __device__ __forceinline__ int64_t readlane64(int64_t v, int lane) {
     const int lo = __builtin_amdgcn_readlane((int)(v & 0xffffffff), lane);
@@ -416,39 +418,7 @@ __global__ __launch_bounds__(kThreads) void gett_batch_kernel(const BatchProblem
     }
 }
 
-template <int PREC> static int batch_lds() { return TileCfg<PREC, kTiles[PREC][0].bm, kTiles[PREC][0].bn, kTiles[PREC][0].bk>::kLdsBytes; }
-
-int batch_grid_size(int prec) {
-    int dev = 0, cus = 0, occ = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return -1;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return -1;
-    hipError_t e = hipErrorInvalidValue;
-    switch (prec) {
-    case kF64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, gett_batch_kernel<kF64>, kThreads, batch_lds<kF64>()); break;
-    case kF32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, gett_batch_kernel<kF32>, kThreads, batch_lds<kF32>()); break;
-    case kBF3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, gett_batch_kernel<kBF3>, kThreads, batch_lds<kBF3>()); break;
-    default: return -1;
-    }
-    if (e != hipSuccess || occ < 1) occ = 1;
-    return cus * occ;
-}
-
-int launch_batch(int prec, const BatchProblem *d_probs, int32_t nprobs, const int32_t *d_items,
-                 int32_t nitems, int32_t grid, hipStream_t s) {
-    (void)nprobs;
-    if (grid < 1 || nitems < 1) return 0;
-    switch (prec) {
-    case kF64: hipLaunchKernelGGL(gett_batch_kernel<kF64>, dim3(grid), dim3(kThreads), batch_lds<kF64>(), s, d_probs, d_items, nitems); break;
-    case kF32: hipLaunchKernelGGL(gett_batch_kernel<kF32>, dim3(grid), dim3(kThreads), batch_lds<kF32>(), s, d_probs, d_items, nitems); break;
-    case kBF3: hipLaunchKernelGGL(gett_batch_kernel<kBF3>, dim3(grid), dim3(kThreads), batch_lds<kBF3>(), s, d_probs, d_items, nitems); break;
-    default: return GETT_ERR_INTERNAL;
-    }
-    return hipGetLastError() == hipSuccess ? 0 : GETT_ERR_HIP;
-}
-
-// ---------------------------------------------------------------------------
-// Launchers
-// ---------------------------------------------------------------------------
+// Host-side launch helpers (instantiated per precision in its own file).
 template <int PREC, int BM, int BN, int BK, bool AFK, bool BFK>
 static int launch_one(const TileParams &p, hipStream_t s) {
     using Cfg = TileCfg<PREC, BM, BN, BK>;
@@ -490,27 +460,50 @@ static int launch_prec(int tile, bool afk, bool bfk, const TileParams &p, hipStr
     }
 }
 
-int launch_tile(int prec, int tile, bool aFastK, bool bFastK, const TileParams &p, hipStream_t s) {
-    switch (prec) {
-    case kF64: return launch_prec<kF64>(tile, aFastK, bFastK, p, s);
-    case kF32: return launch_prec<kF32>(tile, aFastK, bFastK, p, s);
-    case kBF3: return launch_prec<kBF3>(tile, aFastK, bFastK, p, s);
-    default: return GETT_ERR_INTERNAL;
-    }
+template <int PREC> static int batch_lds() {
+    return TileCfg<PREC, kTiles[PREC][0].bm, kTiles[PREC][0].bn, kTiles[PREC][0].bk>::kLdsBytes;
 }
 
-int launch_splitk_reduce(int prec, const TileParams &p, hipStream_t s) {
+template <int PREC> static int launch_splitk_reduce_prec(const TileParams &p, hipStream_t s) {
     const int64_t MN = p.M * p.N;
     int64_t blocks = (MN + 255) / 256;
     if (blocks > 65536) blocks = 65536;
     if (blocks < 1) blocks = 1;
-    switch (prec) {
-    case kF64: hipLaunchKernelGGL(splitk_reduce_kernel<kF64>, dim3(blocks), dim3(256), 0, s, p); break;
-    case kF32: hipLaunchKernelGGL(splitk_reduce_kernel<kF32>, dim3(blocks), dim3(256), 0, s, p); break;
-    case kBF3: hipLaunchKernelGGL(splitk_reduce_kernel<kBF3>, dim3(blocks), dim3(256), 0, s, p); break;
-    default: return GETT_ERR_INTERNAL;
-    }
+    hipLaunchKernelGGL(splitk_reduce_kernel<PREC>, dim3(blocks), dim3(256), 0, s, p);
     return hipGetLastError() == hipSuccess ? 0 : GETT_ERR_HIP;
 }
+
+template <int PREC> static int batch_grid_size_prec() {
+    int dev = 0, cus = 0, occ = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return -1;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return -1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, gett_batch_kernel<PREC>, kThreads,
+                                                     batch_lds<PREC>()) != hipSuccess || occ < 1)
+        occ = 1;
+    return cus * occ;
+}
+
+template <int PREC>
+static int launch_batch_prec(const BatchProblem *d_probs, const int32_t *d_items, int32_t nitems,
+                             int32_t grid, hipStream_t s) {
+    if (grid < 1 || nitems < 1) return 0;
+    hipLaunchKernelGGL(gett_batch_kernel<PREC>, dim3(grid), dim3(kThreads), batch_lds<PREC>(), s,
+                       d_probs, d_items, nitems);
+    return hipGetLastError() == hipSuccess ? 0 : GETT_ERR_HIP;
+}
+
+// Defines the four per-precision entry points used by the host dispatcher.
+#define GETT_DEFINE_PRECISION(PREC, SUFFIX)                                                        \
+    int launch_tile_##SUFFIX(int tile, bool afk, bool bfk, const TileParams &p, hipStream_t s) {   \
+        return launch_prec<PREC>(tile, afk, bfk, p, s);                                            \
+    }                                                                                              \
+    int launch_splitk_reduce_##SUFFIX(const TileParams &p, hipStream_t s) {                       \
+        return launch_splitk_reduce_prec<PREC>(p, s);                                              \
+    }                                                                                              \
+    int batch_grid_size_##SUFFIX() { return batch_grid_size_prec<PREC>(); }                        \
+    int launch_batch_##SUFFIX(const BatchProblem *d, const int32_t *it, int32_t n, int32_t g,      \
+                              hipStream_t s) {                                                     \
+        return launch_batch_prec<PREC>(d, it, n, g, s);                                            \
+    }
 
 }  // namespace gett

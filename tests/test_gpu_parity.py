@@ -8,13 +8,16 @@ Bars (each derived from the arithmetic of the path, stated per test):
   * BF16x3: e_nrm <= 1e-5 and |err| <= (3 * 2^-16 + (K+2) u32) (|C_in| + sum|a||b|)
     (the split drops lo*lo and the bf16 rounding of the residual, each below
     2^-16 |a||b|);
-  * FP8: against the exact value of the quantised operands (codes and
-    exponents checked bit for bit against the oracle's quantiser), with the
-    FP32 accumulation bound; its error against the exact FP64 result is
-    reported, not gated.
+  * FP8: codes and exponents of the quantiser bit for bit against the
+    oracle's; results against the exact value of the quantised operands
+    within the measured bound of the FP8 matrix core (2^-10 sum |a||b|, its
+    128-term sums are not correctly rounded); its error against the exact
+    FP64 result is reported, not gated.
 Parent elements outside C's view must keep their sentinel; NaN fills outside
 A's and B's views must never reach C.
 """
+import zlib
+
 import numpy as np
 import pytest
 
@@ -92,7 +95,7 @@ PRECS = [gett.GETT_FP64, gett.GETT_FP32, gett.GETT_BF16X3]
 @pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("case", W.PAPER_CASES)
 def test_paper_cases(case, prec):
-    rng = np.random.default_rng(abs(hash(case)) % 2 ** 31 + 17 * prec)
+    rng = np.random.default_rng(zlib.crc32(case.encode()) + 17 * prec)
     dtype = np.float64 if prec == gett.GETT_FP64 else np.float32
     for rep in range(3):
         pr = W.paper_case(case, rng, dtype=dtype)
@@ -106,7 +109,7 @@ def test_paper_cases(case, prec):
 @pytest.mark.parametrize("prec", PRECS + [gett.GETT_FP8])
 @pytest.mark.parametrize("case", W.PAPER_CASES)
 def test_paper_cases_integers_bitwise(case, prec):
-    rng = np.random.default_rng(abs(hash(case)) % 2 ** 31 + 101 + prec)
+    rng = np.random.default_rng(zlib.crc32(case.encode()) + 101 + prec)
     dtype = np.float64 if prec == gett.GETT_FP64 else np.float32
     for rep in range(2):
         pr = W.paper_case(case, rng, dtype=dtype, dist="int")
@@ -249,7 +252,7 @@ def test_fp8_quantizer_codes_bitwise():
 @pytest.mark.parametrize("case", ["basic", "subtensor", "negative", "cube_2", "hypercube_3",
                                   "scalar", "nothing", "lowerrank"])
 def test_fp8_against_quantised_model(case):
-    rng = np.random.default_rng(abs(hash(case)) % 2 ** 31 + 9)
+    rng = np.random.default_rng(zlib.crc32(case.encode()) + 9)
     for rep in range(3):
         pr = W.paper_case(case, rng, dtype=np.float32, dist="normal")
         got = run_gpu(pr, gett.GETT_FP8, f"fp8 rep{rep}")
@@ -277,7 +280,12 @@ def test_fp8_against_quantised_model(case):
         mval = model[ra, rb]
         cin = pr.C.buf[idx].astype(np.float64).reshape(extc, order="F") if extc else pr.C.buf[idx]
         exp = mval + cin
-        bnd = view_values(pr.C, cabs) * 1.3 * (K + 2) * U32 + 1e-30
+        # The FP8 matrix core does not round its 128-term sums correctly:
+        # measured on random full-range E4M3 codes its error reaches 2^-12
+        # of the largest product of a block (sums of moderate-range codes
+        # come out exact).  Bound: 2^-10 of sum |a||b| per element, plus
+        # FP32 accumulation across blocks; 1.3 covers quantised magnitudes.
+        bnd = view_values(pr.C, cabs) * 1.3 * (2.0 ** -10 + (K + 2) * U32) + 1e-30
         assert np.all(np.abs(cvals - exp) <= bnd), case
         check_outside(pr, got)
 

@@ -4,6 +4,8 @@ A table-driven evaluator written here (not the oracle, not the kernels)
 computes C[offCM[m] + offCN[n]] += sum_k A[offAM[m] + offAK[k]] B[offBK[k] + offBN[n]]
 from the planner's tables; on integer data it must equal the oracle exactly.
 """
+import zlib
+
 import numpy as np
 import pytest
 
@@ -33,7 +35,7 @@ def oracle_result(pr):
 
 @pytest.mark.parametrize("case", W.PAPER_CASES)
 def test_tables_reproduce_the_contraction(case):
-    rng = np.random.default_rng(abs(hash(case)) % 2 ** 31)
+    rng = np.random.default_rng(zlib.crc32(case.encode()))
     for rep in range(3):
         pr = W.paper_case(case, rng, dist="int")
         ref = oracle_result(pr)
