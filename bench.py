@@ -40,6 +40,14 @@ def parse():
     ap.add_argument("--no-check", action="store_true", help="skip the sampled error check")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target duration of the CPU oracle sample")
+    ap.add_argument("--policy", choices=["autotune", "heuristic"], default="autotune",
+                    help="schedule choice on the first call (autotune times the whole menu "
+                         "before the timed region)")
+    ap.add_argument("--schedule", type=int, default=-1, help="force one schedule id")
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--traffic-json", default="profiles/traffic.json",
+                    help="HBM traffic per launch measured with rocprofv3 counters")
     return ap.parse_args()
 
 
@@ -61,6 +69,20 @@ def main():
     gett.lib()
     stream = torch.cuda.current_stream()
     gett.gett_set_stream(stream.cuda_stream)
+    if args.schedule >= 0:
+        gett.gett_set_schedule(args.schedule)
+    else:
+        gett.gett_set_policy(gett.GETT_AUTOTUNE if args.policy == "autotune" else gett.GETT_HEURISTIC)
+    if args.copy_calib_mib > 0:
+        n = args.copy_calib_mib * 2 ** 20 // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] copy calibration: {args.copy_calib_mib} MiB read + written x3",
+              file=sys.stderr, flush=True)
+        del src, dst
 
     paths = [p for p in args.paths.split(",") if p]
     entry = {"f64": gett.dgett, "f32": gett.sgett, "bf16x3": gett.sgett_bf16x3,
@@ -156,12 +178,41 @@ def main():
                                "B (40,56,96,72) dense, C dense",
                    "M": M, "N": N, "K": K, "flops_per_step": flops, "path": path},
         "roofline": {"bound": "mfma", "achieved": round(tflops, 3), "peak": peak,
-                     "unit": "TFLOP/s", "frac": round(tflops / peak, 4), "traffic": None},
+                     "unit": "TFLOP/s", "frac": round(tflops / peak, 4),
+                     "traffic": load_traffic(args.traffic_json, path, results[path]["schedule"])},
         "paths": results,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pr64, args.cpu_seconds, flops)
     print(json.dumps(out))
+
+
+def load_traffic(path, prec_path, schedule):
+    """HBM bytes per launch of the timed kernel, from the rocprofv3 counter
+    runs summarised in profiles/ (FETCH_SIZE and WRITE_SIZE scaled by the
+    same counters on a plain copy of known size); None when they were taken
+    for another schedule or are missing."""
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    e = t.get(prec_path)
+    if not e or e.get("schedule") != schedule or e.get("kernel_source_hash") != kernel_hash():
+        return None
+    return {"read_bytes": e["read_bytes"], "write_bytes": e["write_bytes"],
+            "algorithmic_bytes": e["algorithmic_bytes"], "unit": "bytes/launch"}
+
+
+def kernel_hash():
+    import hashlib
+    h = hashlib.sha256()
+    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2410_06770_amd", "csrc")
+    for name in sorted(os.listdir(src)):
+        if name.startswith("gett_tile"):
+            with open(os.path.join(src, name), "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def sampled_error(pr, got, width=1500):
@@ -188,14 +239,15 @@ def cpu_baseline(pr, seconds, flops_full):
     the same workload (n chosen so the run takes about `seconds`)."""
     import oracle
     K = pr.mnk()[2]
-    n = 256
-    t = time.perf_counter()
-    oracle.exact(pr, pr.A, pr.B, pr.C, 0, n)
-    dt = time.perf_counter() - t
-    n = int(min(max(n * seconds / max(dt, 1e-3), 512), int(np.prod(pr.extc()))))
-    t = time.perf_counter()
-    oracle.exact(pr, pr.A, pr.B, pr.C, 0, n)
-    dt = time.perf_counter() - t
+    total = int(np.prod(pr.extc()))
+    n = 2048
+    while True:
+        t = time.perf_counter()
+        oracle.exact(pr, pr.A, pr.B, pr.C, 0, n)
+        dt = time.perf_counter() - t
+        if dt >= 0.5 * seconds or n >= total:
+            break
+        n = int(min(n * min(max(seconds / max(dt, 1e-3), 2.0), 64.0), total))
     tflops = 2.0 * K * n / dt / 1e12
     return {"value": tflops, "unit": "TFLOP/s", "cores": oracle.num_threads(), "kind": "oracle",
             "sample": f"first {n} of {int(np.prod(pr.extc()))} outputs (x K={K} terms), "

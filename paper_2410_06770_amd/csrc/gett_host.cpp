@@ -87,7 +87,14 @@ static bool sched_valid(int prec, const Sched &s, int64_t K) {
 // fill the 256 CUs with whole waves of tiles, prefer larger tiles, and split
 // K only when there are too few tiles to occupy the chip.
 static Sched heuristic(int prec, int64_t M, int64_t N, int64_t K) {
-    static const double kTileSpeed[kNumTiles] = {0.55, 0.8, 0.8, 1.0, 0.97};
+    // Relative per-CU throughput of each tile once the chip is full, from
+    // timings of the menu on large strided and dense contractions.
+    static const double kSpeed[4][kNumTiles] = {
+        {0.85, 0.95, 1.0, 0.93, 0.9},   // FP64: 128x64 keeps two workgroups per CU
+        {0.8, 0.9, 0.9, 1.0, 0.95},     // FP32
+        {0.95, 0.9, 1.0, 0.85, 0.8},    // BF16x3
+        {0.8, 0.9, 0.9, 1.0, 1.0}};     // FP8 (its own kernel)
+    const double *kTileSpeed = kSpeed[prec];
     double best = -1;
     Sched bs{3, 0, 0};
     for (int t = 0; t < kNumTiles; ++t) {

@@ -209,23 +209,24 @@ Canon canonicalise(const Args &a, int order, int bn) {
     // K: read along K by the operand whose smallest stride is contracted.
     const bool aPrefK = !k.empty() && (m.empty() || min_abs(k, 0) < min_abs(m, 0));
     const bool bPrefK = !k.empty() && (n.empty() || min_abs(k, 1) < min_abs(n, 0));
-    int kslot = aPrefK ? 0 : (bPrefK ? 1 : 0);
-    if (order == 3) kslot ^= 1;
-    sort_by(k, kslot);
+    sort_by(k, aPrefK ? 0 : (bPrefK ? 1 : 0));
 
     c.aFastK = !k.empty() && (m.empty() || iabs(k[0].i0) < iabs(m[0].i0));
     c.bFastK = !k.empty() && (n.empty() || iabs(k[0].i1) < iabs(n[0].i0));
 
-    // Box the N tile when B's fastest N mode x is not C's fastest N mode y:
-    // a tile of Y (from y) times X (from x) positions, y first, so the
-    // epilogue's lanes run along y while B's loader runs along x.
-    if ((order == 0 || order == 3) && !c.bFastK && n.size() >= 2 && bn > 0) {
+    // Orders 2 and 3 box the N tile when B's fastest N mode x is not C's
+    // fastest N mode y: a tile of Y positions of y times X of x, y first, so
+    // the epilogue's lanes run along y while B's loader runs along x.  Order
+    // 2 favours the loads (Y = 4), order 3 the stores (Y = 16).
+    if ((order == 2 || order == 3) && !c.bFastK && n.size() >= 2 && bn > 0) {
         size_t yi = 0;
         for (size_t i = 1; i < n.size(); ++i)
             if (iabs(n[i].i1) < iabs(n[yi].i1)) yi = i;
         if (yi != 0 && iabs(n[yi].i1) < iabs(n[0].i1)) {
-            const int cand[4] = {16, 8, 4, 32};
-            for (int Y : cand) {
+            const int cand2[3] = {4, 8, 2}, cand3[3] = {16, 8, 32};
+            const int *cand = order == 2 ? cand2 : cand3;
+            for (int ci = 0; ci < 3; ++ci) {
+                const int Y = cand[ci];
                 const int X = bn / Y;
                 if (X < 1 || X * Y != bn) continue;
                 if (n[yi].ext % Y != 0 || n[0].ext % X != 0) continue;

@@ -39,11 +39,14 @@ struct Canon {
 };
 
 // Canonicalise for mode-ordering option `order` (0..3) and tile width bn.
-//   0: heuristic -- swap, merge, M by A strides, N boxed when B's and C's
-//      fastest N modes differ, K by the operand that reads along K;
-//   1: as 0, N ordered by C strides (no box);
-//   2: as 0, N ordered by B strides (no box);
-//   3: as 0 with the K order taken from the other operand.
+// Every order swaps A and B when C's fastest mode belongs to A, merges
+// jointly contiguous modes, orders M by A's strides and K by the operand
+// that reads along K; they differ in the N order:
+//   0: N by B's strides (the B loads coalesce);
+//   1: N by C's strides (the epilogue's stores coalesce);
+//   2: N boxed, 4 positions of C's fastest N mode by bn/4 of B's;
+//   3: N boxed, 16 positions of C's fastest N mode by bn/16 of B's.
+// Boxes fall back to order 0 when the extents do not divide.
 Canon canonicalise(const Args &a, int order, int bn);
 
 // Offsets of a group for tensor slot s (0: i0, 1: i1), padded with zeros to

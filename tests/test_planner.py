@@ -59,13 +59,17 @@ def test_strided_permuted_config_grouping():
     belongs to A, so the planner swaps; N = {a, b} is boxed (b side first for
     C, a side for the loads); K puts B's unit-stride f first."""
     pr = W.config_strided_perm(with_data=False)
-    d = gett.gett_plan_describe(0, 0, 3, *problem_args(pr))
+    d = gett.gett_plan_describe(0, 3, 3, *problem_args(pr))
     assert d["swapped"]
     assert (d["M"], d["N"], d["K"]) == (56 * 72, 48 * 64, 96 * 40)
     assert d["boxX"] == 8
     assert d["n"][0] == (16, 192, 1) and d["n"][1] == (8, 2, 4608)
     assert d["k"][0][0] == 40 and d["k"][0][1] == 1        # f, unit stride in (old) B
     assert d["aFastK"] and not d["bFastK"]
+    d2 = gett.gett_plan_describe(0, 2, 3, *problem_args(pr))
+    assert d2["boxX"] == 16 and d2["n"][0] == (8, 192, 1) and d2["n"][1] == (16, 2, 4608)
+    d0 = gett.gett_plan_describe(0, 0, 3, *problem_args(pr))
+    assert d0["boxX"] == 0 and d0["n"][0] == (48, 2, 4608)  # ordered by B
     d1 = gett.gett_plan_describe(0, 1, 3, *problem_args(pr))
     assert d1["boxX"] == 0 and d1["n"][0][2] == 1            # ordered by C
 
