@@ -190,7 +190,10 @@ int gett_load_predictor(const char *path);
 
 /* Schedules.  A schedule is (tile, order, split): tile indexes the tile menu
    of the precision, order picks one of GETT_NUM_ORDERS mode orderings, split
-   is the split-K factor index (1, 2, 4, 8).  The flat id is
+   is the split-K option: 1, 2 or 4 slices of the contracted range, or (3)
+   as many slices as it takes to give the chip about 2048 workgroups (at
+   least two K steps each).  Partial sums go to a stream-ordered FP64
+   workspace and are added to C in a fixed order.  The flat id is
    tile + NT*(order + GETT_NUM_ORDERS*split).  A schedule never changes what
    is computed, only how (the summation order of the contracted sum). */
 #define GETT_NUM_ORDERS 4
@@ -205,15 +208,24 @@ int64_t gett_last_schedule(void);
 
 /* Autotuner: time every valid schedule of the menu for one problem of
    precision PREC (the 14 xGETT arguments, device data; C is overwritten by
-   the timing runs), WARMUP untimed runs then the median of REPS runs, each
-   timed with HIP events on the current stream.  times_us[id] receives the
-   median (or -1 for an invalid schedule); returns the best id (>= 0) or
-   INFO/runtime error as a negative/positive code via *status. */
+   the timing runs) with HIP events on the current stream: each valid
+   schedule once after WARMUP untimed runs, then the six fastest again, REPS
+   timed runs each.  times_us[id] receives the median of the re-timed ones,
+   the single time of the others and -1 for invalid schedules; returns the
+   best id (>= 0), or -1 with *status set to a negative INFO or a positive
+   runtime error. */
 int64_t gett_autotune(int prec, int64_t ranka, const int64_t *exta, const int64_t *inca,
                       const void *A, int64_t rankb, const int64_t *extb, const int64_t *incb,
                       const void *B, int64_t conts, const int64_t *conta, const int64_t *contb,
                       const int64_t *perm, const int64_t *incc, void *C, int64_t warmup,
                       int64_t reps, double *times_us, int64_t ntimes, int *status);
+
+/* Schedule the built-in heuristic picks for a signature (host only, no HIP
+   call): the predictor's baseline.  Returns the id or a negative INFO. */
+int64_t gett_heuristic_schedule(int prec, int64_t ranka, const int64_t *exta,
+                                const int64_t *inca, int64_t rankb, const int64_t *extb,
+                                const int64_t *incb, int64_t conts, const int64_t *conta,
+                                const int64_t *contb, const int64_t *perm, const int64_t *incc);
 
 /* Feature vector of a signature (host only, no HIP call): 64 floats. */
 #define GETT_NUM_FEATURES 64

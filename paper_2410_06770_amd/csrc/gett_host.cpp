@@ -79,6 +79,7 @@ static bool sched_valid(int prec, const Sched &s, int64_t K) {
     const int S = kSplitFactor[s.split];
     const int bk = kTiles[prec][s.tile].bk;
     if (S > 1 && K < (int64_t)S * bk) return false;
+    if (S == 0 && K < 4 * (int64_t)bk) return false;     // "fill" needs a few K steps
     if (prec == kFP8 && s.split != 0) return false;
     return true;
 }
@@ -114,14 +115,11 @@ static Sched heuristic(int prec, int64_t M, int64_t N, int64_t K) {
     const TileShape ts = kTiles[prec][bs.tile];
     const double tiles = std::ceil((double)M / ts.bm) * std::ceil((double)N / ts.bn);
     bs.split = 0;
-    if (prec != kFP8) {
-        for (int s = kNumSplits - 1; s > 0; --s) {
-            const int S = kSplitFactor[s];
-            if (tiles * S <= 512 && tiles < 192 && K >= (int64_t)S * 256) {
-                bs.split = s;
-                break;
-            }
-        }
+    if (prec != kFP8 && tiles < 192) {
+        // too few tiles for 256 CUs: split K, as far as the contraction allows
+        if (tiles <= 32 && K >= 64 * (int64_t)ts.bk) bs.split = 3;             // fill
+        else if (tiles * 4 <= 512 && K >= 4 * 256) bs.split = 2;
+        else if (K >= 2 * 256) bs.split = 1;
     }
     return bs;
 }
@@ -129,47 +127,73 @@ static Sched heuristic(int prec, int64_t M, int64_t N, int64_t K) {
 // ---------------------------------------------------------------------------
 // Plans
 // ---------------------------------------------------------------------------
-struct Plan {
-    int prec = 0;
-    Sched sched{};
+// Offset tables of one canonical form.  They depend only on the signature,
+// the N-mode order and the tile width, so plans that differ in tile height,
+// K step or split share them.
+struct TableSet {
     Canon cn;
     int64_t Mp = 0, Np = 0, Kp = 0;
     int64_t *d_tab = nullptr;   // offAM, offCM [Mp]; offBN, offCN [Np]; offAK, offBK [Kp]
-    // FP8: canonical tables (rowsA [MpA], kA [Kc], rowsB [NpB], kB [Kc], offCM, offCN)
-    int64_t fpM = 0, fpN = 0, fpK = 0;
-    ~Plan() {
+    ~TableSet() {
         if (d_tab) (void)hipFree(d_tab);
     }
 };
 
+struct Plan {
+    int prec = 0;
+    Sched sched{};
+    TableSet *tab = nullptr;    // owned by g_tables
+};
+
+static std::unordered_map<std::string, std::unique_ptr<TableSet>> g_tables;
 static std::unordered_map<std::string, std::unique_ptr<Plan>> g_plans;
 
 static int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
-// Build host tables for canonical form cn and upload them.
-static int upload_tables(Plan &pl) {
-    const Canon &c = pl.cn;
-    const TileShape ts = kTiles[pl.prec][pl.sched.tile];
-    pl.Mp = round_up(std::max<int64_t>(c.M, 1), kTablePad);
-    pl.Np = round_up(std::max<int64_t>(c.N, 1), kTablePad);
-    // K tables: zero padding past K covers the kernel's look-ahead loads
-    // (up to three steps of at most 64 positions past the last one).
-    (void)ts;
-    pl.Kp = round_up(std::max<int64_t>(c.K, 1), 128) + 256;
-    std::vector<int64_t> h(2 * (pl.Mp + pl.Np + pl.Kp));
+// Build the host tables of a canonical form and upload them.
+static int upload_tables(TableSet &t) {
+    const Canon &c = t.cn;
+    t.Mp = round_up(std::max<int64_t>(c.M, 1), kTablePad);
+    t.Np = round_up(std::max<int64_t>(c.N, 1), kTablePad);
+    // K tables: zero padding past K covers the kernel's look-ahead loads (two
+    // steps of at most 64 positions past the last slice start, which is < K).
+    t.Kp = round_up(std::max<int64_t>(c.K, 1), 128) + 256;
+    std::vector<int64_t> h(2 * (t.Mp + t.Np + t.Kp));
     int64_t *p = h.data();
-    group_offsets(c.m, 0, pl.Mp, p);
-    group_offsets(c.m, 1, pl.Mp, p + pl.Mp);
-    p += 2 * pl.Mp;
-    group_offsets(c.n, 0, pl.Np, p);
-    group_offsets(c.n, 1, pl.Np, p + pl.Np);
-    p += 2 * pl.Np;
-    group_offsets(c.k, 0, pl.Kp, p);
-    group_offsets(c.k, 1, pl.Kp, p + pl.Kp);
+    group_offsets(c.m, 0, t.Mp, p);
+    group_offsets(c.m, 1, t.Mp, p + t.Mp);
+    p += 2 * t.Mp;
+    group_offsets(c.n, 0, t.Np, p);
+    group_offsets(c.n, 1, t.Np, p + t.Np);
+    p += 2 * t.Np;
+    group_offsets(c.k, 0, t.Kp, p);
+    group_offsets(c.k, 1, t.Kp, p + t.Kp);
     const size_t bytes = h.size() * sizeof(int64_t);
-    if (hipMalloc(&pl.d_tab, bytes) != hipSuccess) return GETT_ERR_ALLOC;
-    if (hipMemcpy(pl.d_tab, h.data(), bytes, hipMemcpyHostToDevice) != hipSuccess)
+    if (hipMalloc(&t.d_tab, bytes) != hipSuccess) return GETT_ERR_ALLOC;
+    if (hipMemcpy(t.d_tab, h.data(), bytes, hipMemcpyHostToDevice) != hipSuccess)
         return GETT_ERR_HIP;
+    return 0;
+}
+
+static int get_tables(const Args &a, int order, int bn, int dev, TableSet **out) {
+    const std::string key = signature_key(a, -1, dev, order * 1024 + bn);
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_tables.find(key);
+        if (it != g_tables.end()) {
+            *out = it->second.get();
+            return 0;
+        }
+    }
+    auto t = std::make_unique<TableSet>();
+    t->cn = canonicalise(a, order, bn);
+    if (t->cn.M > INT32_MAX || t->cn.N > INT32_MAX) return GETT_ERR_INTERNAL;
+    int rc = upload_tables(*t);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto &slot = g_tables[key];
+    if (!slot) slot = std::move(t);
+    *out = slot.get();
     return 0;
 }
 
@@ -198,20 +222,19 @@ static int get_plan(int prec, const Args &a, int dev, int64_t forced, Plan **out
     auto pl = std::make_unique<Plan>();
     pl->prec = prec;
     pl->sched = s;
-    pl->cn = canonicalise(a, s.order, kTiles[prec][s.tile].bn);
-    if (pl->cn.M > INT32_MAX || pl->cn.N > INT32_MAX) return GETT_ERR_INTERNAL;
     const TileShape ts = kTiles[prec][s.tile];
-    const int64_t tiles = ((pl->cn.M + ts.bm - 1) / ts.bm) * ((pl->cn.N + ts.bn - 1) / ts.bn) *
-                          kSplitFactor[s.split];
-    if (tiles > INT32_MAX) return GETT_ERR_INTERNAL;
-    int rc = upload_tables(*pl);
+    int rc = get_tables(a, s.order, ts.bn, dev, &pl->tab);
     if (rc) return rc;
+    const Canon &cn = pl->tab->cn;
+    const int64_t tiles = ((cn.M + ts.bm - 1) / ts.bm) * ((cn.N + ts.bn - 1) / ts.bn);
+    if (tiles * split_count(s.split, tiles, std::max<int64_t>(cn.K, 1), ts.bk, nullptr) >
+        INT32_MAX)
+        return GETT_ERR_INTERNAL;
     if (g_log)
         fprintf(stderr, "[gett] plan prec=%d M=%lld N=%lld K=%lld tile=%d order=%d split=%d "
                         "swapped=%d aFastK=%d bFastK=%d boxX=%d\n",
-                prec, (long long)pl->cn.M, (long long)pl->cn.N, (long long)pl->cn.K, s.tile,
-                s.order, kSplitFactor[s.split], (int)pl->cn.swapped, (int)pl->cn.aFastK,
-                (int)pl->cn.bFastK, pl->cn.boxX);
+                prec, (long long)cn.M, (long long)cn.N, (long long)cn.K, s.tile, s.order, s.split,
+                (int)cn.swapped, (int)cn.aFastK, (int)cn.bFastK, cn.boxX);
     std::lock_guard<std::mutex> lk(g_mu);
     auto &slot = g_plans[key];
     if (!slot) slot = std::move(pl);   // another thread may have won the race
@@ -222,26 +245,28 @@ static int get_plan(int prec, const Args &a, int dev, int64_t forced, Plan **out
 
 // Fill the launch parameters of a plan for concrete pointers.
 static TileParams make_params(const Plan &pl, const void *A, const void *B, void *C) {
-    const Canon &c = pl.cn;
+    const TableSet &t = *pl.tab;
+    const Canon &c = t.cn;
     const TileShape ts = kTiles[pl.prec][pl.sched.tile];
     TileParams p;
     p.A = c.swapped ? B : A;
     p.B = c.swapped ? A : B;
     p.C = C;
-    p.offAM = pl.d_tab;
-    p.offCM = pl.d_tab + pl.Mp;
-    p.offBN = pl.d_tab + 2 * pl.Mp;
-    p.offCN = pl.d_tab + 2 * pl.Mp + pl.Np;
-    p.offAK = pl.d_tab + 2 * pl.Mp + 2 * pl.Np;
-    p.offBK = pl.d_tab + 2 * pl.Mp + 2 * pl.Np + pl.Kp;
+    p.offAM = t.d_tab;
+    p.offCM = t.d_tab + t.Mp;
+    p.offBN = t.d_tab + 2 * t.Mp;
+    p.offCN = t.d_tab + 2 * t.Mp + t.Np;
+    p.offAK = t.d_tab + 2 * t.Mp + 2 * t.Np;
+    p.offBK = t.d_tab + 2 * t.Mp + 2 * t.Np + t.Kp;
     p.M = c.M;
     p.N = c.N;
     p.K = c.K;
-    const int S = kSplitFactor[pl.sched.split];
-    p.splits = S;
-    p.kPerSplit = round_up((c.K + S - 1) / S, ts.bk);
     p.tilesM = (int32_t)((c.M + ts.bm - 1) / ts.bm);
     p.tilesN = (int32_t)((c.N + ts.bn - 1) / ts.bn);
+    int64_t per = 0;
+    p.splits = split_count(pl.sched.split, (int64_t)p.tilesM * p.tilesN,
+                           std::max<int64_t>(c.K, 1), ts.bk, &per);
+    p.kPerSplit = per;
     p.bBoxX = c.boxX > 0 ? c.boxX : ts.bn;
     p.ws = nullptr;
     return p;
@@ -254,12 +279,12 @@ static int run_plan(const Plan &pl, const void *A, const void *B, void *C, hipSt
         void *ws = nullptr;
         if (hipMallocAsync(&ws, bytes, s) != hipSuccess) return GETT_ERR_ALLOC;
         p.ws = static_cast<double *>(ws);
-        int rc = launch_tile(pl.prec, pl.sched.tile, pl.cn.aFastK, pl.cn.bFastK, p, s);
+        int rc = launch_tile(pl.prec, pl.sched.tile, pl.tab->cn.aFastK, pl.tab->cn.bFastK, p, s);
         if (!rc) rc = launch_splitk_reduce(pl.prec, p, s);
         if (hipFreeAsync(ws, s) != hipSuccess && !rc) rc = GETT_ERR_HIP;
         return rc;
     }
-    return launch_tile(pl.prec, pl.sched.tile, pl.cn.aFastK, pl.cn.bFastK, p, s);
+    return launch_tile(pl.prec, pl.sched.tile, pl.tab->cn.aFastK, pl.tab->cn.bFastK, p, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -499,27 +524,45 @@ static int time_schedule(int prec, const Args &a, const void *A, const void *B, 
     return 0;
 }
 
+// Two passes: every valid schedule once (after `warmup` untimed runs), then
+// the fastest few again with `reps` timed runs each; their medians decide.
+// times[] receives the median for re-timed schedules, the single time for
+// the others, and -1 for invalid ones.
 static int64_t autotune(int prec, const Args &a, const void *A, const void *B, void *C, int dev,
                         int warmup, int reps, double *times, int64_t ntimes, int *status) {
     Canon c0 = canonicalise(a, 0, 128);
+    *status = 0;
+    std::vector<double> t1(kNumSched, -1.0);
+    for (int64_t id = 0; id < kNumSched; ++id) {
+        if (!sched_valid(prec, sched_of(id), c0.K)) continue;
+        int rc = time_schedule(prec, a, A, B, C, dev, id, warmup, 1, &t1[id]);
+        if (rc) {
+            *status = rc;
+            return -1;
+        }
+    }
+    std::vector<int64_t> order;
+    for (int64_t id = 0; id < kNumSched; ++id)
+        if (t1[id] > 0) order.push_back(id);
+    std::sort(order.begin(), order.end(), [&](int64_t x, int64_t y) { return t1[x] < t1[y]; });
+    const size_t top = std::min<size_t>(order.size(), 6);
     double best = 1e300;
     int64_t best_id = -1;
-    *status = 0;
-    for (int64_t id = 0; id < kNumSched; ++id) {
-        double us = -1;
-        if (sched_valid(prec, sched_of(id), c0.K)) {
-            int rc = time_schedule(prec, a, A, B, C, dev, id, warmup, reps, &us);
-            if (rc) {
-                *status = rc;
-                return -1;
-            }
-            if (us < best) {
-                best = us;
-                best_id = id;
-            }
+    for (size_t i = 0; i < top; ++i) {
+        double us = 0;
+        int rc = time_schedule(prec, a, A, B, C, dev, order[i], 0, reps, &us);
+        if (rc) {
+            *status = rc;
+            return -1;
         }
-        if (times && id < ntimes) times[id] = us;
+        t1[order[i]] = us;
+        if (us < best) {
+            best = us;
+            best_id = order[i];
+        }
     }
+    if (times)
+        for (int64_t id = 0; id < kNumSched && id < ntimes; ++id) times[id] = t1[id];
     return best_id;
 }
 
@@ -742,8 +785,8 @@ static int run_batch(int prec, int64_t count, const Args *args, const void *cons
         if (!bg->plans[i]) continue;
         const Plan &pl = *bg->plans[i];
         bg->h_desc[i].p = make_params(pl, A[i], B[i], C[i]);
-        bg->h_desc[i].aFastK = pl.cn.aFastK;
-        bg->h_desc[i].bFastK = pl.cn.bFastK;
+        bg->h_desc[i].aFastK = pl.tab->cn.aFastK;
+        bg->h_desc[i].bFastK = pl.tab->cn.bFastK;
     }
     if (hipGraphLaunch(bg->exec, s) != hipSuccess) return GETT_ERR_HIP;
     if (hipEventRecord(bg->done, s) != hipSuccess) return GETT_ERR_HIP;
@@ -958,6 +1001,16 @@ int64_t gett_autotune(int prec, int64_t ranka, const int64_t *exta, const int64_
     return autotune(prec, a, A, B, C, dev, (int)warmup, (int)reps, times_us, ntimes, status);
 }
 
+int64_t gett_heuristic_schedule(int prec, GETT_ARGS_DECL) {
+    Args a = GETT_ARGS_MAKE;
+    const int info = validate(a, reinterpret_cast<void *>(1), reinterpret_cast<void *>(1),
+                              reinterpret_cast<void *>(1));
+    if (info) return info;
+    if (prec < 0 || prec > 3) return GETT_ERR_STATE;
+    Canon c = canonicalise(a, 0, 128);
+    return sched_id(heuristic(prec, c.M, c.N, c.K));
+}
+
 int gett_features(int prec, GETT_ARGS_DECL, float *out) {
     Args a = GETT_ARGS_MAKE;
     const int info = validate(a, reinterpret_cast<void *>(1), reinterpret_cast<void *>(1),
@@ -1041,6 +1094,7 @@ int gett_finalize(void) {
         std::lock_guard<std::mutex> lk(g_mu);
         g_graphs.clear();
         g_plans.clear();
+        g_tables.clear();
         g_fp8.clear();
         g_tuned.clear();
     }

@@ -24,8 +24,29 @@ enum Prec : int { kF64 = 0, kF32 = 1, kBF3 = 2, kFP8 = 3 };
 constexpr int kThreads = 256;       // 4 waves of 64 per workgroup
 constexpr int kNumTiles = 5;        // tile menu size per precision
 constexpr int kNumOrders = 4;
-constexpr int kNumSplits = 4;       // split-K factors 1, 2, 4, 8
-constexpr int kSplitFactor[kNumSplits] = {1, 2, 4, 8};
+constexpr int kNumSplits = 4;       // split-K options: 1, 2, 4 slices, or "fill"
+constexpr int kSplitFactor[kNumSplits] = {1, 2, 4, 0};   // 0 = enough slices to fill the chip
+constexpr int kFillTarget = 2048;   // workgroups the "fill" option aims at
+constexpr int kMaxSplits = 4096;
+
+// Number of K slices actually launched for split option `split`: every slice
+// starts below K (so the kernel's look-ahead loads stay inside the padded
+// contracted tables) and gets at least two K steps.
+inline int split_count(int split, int64_t tiles, int64_t K, int bk, int64_t *kPer) {
+    int64_t S = kSplitFactor[split];
+    if (S == 0) {
+        S = tiles >= kFillTarget ? 1 : (kFillTarget + tiles - 1) / tiles;
+        const int64_t maxS = K / (2 * (int64_t)bk);
+        if (S > maxS) S = maxS;
+        if (S > kMaxSplits) S = kMaxSplits;
+    }
+    if (S < 1) S = 1;
+    int64_t per = (K + S - 1) / S;
+    per = (per + bk - 1) / bk * bk;
+    S = (K + per - 1) / per;
+    if (kPer) *kPer = per;
+    return (int)S;
+}
 constexpr int kTablePad = 256;      // M/N tables padded to a multiple of this
 
 struct TileShape { int bm, bn, bk; };

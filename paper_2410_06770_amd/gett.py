@@ -24,7 +24,7 @@ GETT_HEURISTIC, GETT_PREDICT, GETT_AUTOTUNE = 0, 1, 2
 NUM_FEATURES = 64
 NUM_ORDERS = 4
 NUM_SPLITS = 4
-SPLIT_FACTORS = (1, 2, 4, 8)
+SPLIT_FACTORS = (1, 2, 4, 0)   # 0: enough K slices to fill the chip
 
 _lib = None
 i64 = ct.c_int64
@@ -73,6 +73,8 @@ def lib():
     L.gett_autotune.restype = i64
     a11 = [i64, I64P, I64P, i64, I64P, I64P, i64, I64P, I64P, I64P, I64P]
     L.gett_features.argtypes = [ct.c_int] + a11 + [ct.POINTER(ct.c_float)]
+    L.gett_heuristic_schedule.argtypes = [ct.c_int] + a11
+    L.gett_heuristic_schedule.restype = i64
     L.gett_plan_describe.argtypes = [ct.c_int, i64, i64] + a11 + [I64P, i64]
     L.gett_plan_describe.restype = i64
     L.gett_plan_tables.argtypes = [ct.c_int, i64, i64] + a11 + [I64P, i64]
@@ -255,6 +257,13 @@ def gett_features(prec, ranka, exta, inca, rankb, extb, incb, conts, conta, cont
     if rc:
         raise GettError(rc, "gett_features")
     return np.array(out[:], dtype=np.float32)
+
+
+def gett_heuristic_schedule(prec, ranka, exta, inca, rankb, extb, incb, conts, conta, contb,
+                            perm, incc) -> int:
+    return int(lib().gett_heuristic_schedule(int(prec), int(ranka), _arr(exta), _arr(inca),
+                                             int(rankb), _arr(extb), _arr(incb), int(conts),
+                                             _arr(conta), _arr(contb), _arr(perm), _arr(incc)))
 
 
 def _describe(fn, prec, order, tile, args):

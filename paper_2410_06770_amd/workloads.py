@@ -69,8 +69,16 @@ def _draw(rng, n, dist):
     raise ValueError(dist)
 
 
+def view_layout(ext, rng, layout="packed"):
+    """(parent element count, base, increments) of a view of extents ``ext``
+    with the given layout (see make_view); draws only layout randomness."""
+    v = make_view(ext, rng, np.float32, layout=layout, values=np.zeros(
+        int(np.prod(ext)) if len(ext) else 1), fill=0.0, _layout_only=True)
+    return v
+
+
 def make_view(ext, rng, dtype=np.float64, layout="packed", dist="uniform",
-              fill=np.nan, values=None) -> View:
+              fill=np.nan, values=None, _layout_only=False) -> View:
     """A view of extents ``ext`` holding fresh draws.
 
     layouts: ``packed``; ``sub`` (random place in a same-rank parent whose
@@ -110,6 +118,13 @@ def make_view(ext, rng, dtype=np.float64, layout="packed", dist="uniform",
         raise ValueError(layout)
     pinc = packed_incs(pext)
     total = int(np.prod(pext)) if pext else 1
+    if _layout_only:
+        base = sum(p * s for p, s in zip(pos, pinc))
+        inc = [pinc[m] * st for m, st in zip(modes, step)]
+        if layout in ("neg", "subneg"):
+            base += sum((e - 1) * s for e, s in zip(ext, inc) if e > 0)
+            inc = [-s for s in inc]
+        return max(total, 1), int(base), inc
     buf = np.full(max(total, 1), fill, dtype=dtype)
     base = sum(p * s for p, s in zip(pos, pinc))
     inc = [pinc[m] * st for m, st in zip(modes, step)]

@@ -1,0 +1,175 @@
+"""Batched xGETT (one persistent kernel in a captured HIP graph) on the GPU.
+
+Bars: every problem of the batch against the FP64 oracle on sampled outputs
+within the element-wise bound of its precision (FP32: (K+2) u32; BF16x3:
+3 * 2^-16 + (K+2) u32, times |C_in| + sum |a||b|); the batch equals single
+calls forced onto the same tile bit for bit (same code, same summation
+order); a replay of the captured graph with new pointers computes the new
+problem.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2410_06770_amd import gett, workloads as W
+from tests.helpers import call14, e_cw, e_nrm, outside_mask, to_device
+
+pytestmark = pytest.mark.gpu
+U32 = 2.0 ** -24
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    gett.lib()
+    gett.use_torch_stream()
+    yield
+
+
+def upload(problems):
+    dev = []
+    for pr in problems:
+        At, a = to_device(pr.A)
+        Bt, b = to_device(pr.B)
+        Ct, c = to_device(pr.C)
+        dev.append((At, Bt, Ct, a, b, c))
+    return dev
+
+
+def run_batch(problems, dev, prec, fn=None):
+    import torch
+    fn = fn or (gett.dgett_batch if prec == gett.GETT_FP64 else gett.sgett_batch)
+    info = [0] * len(problems)
+    print(f"\n[gpu] batch of {len(problems)} prec={prec}", flush=True)
+    rc = fn(len(problems), prec, [p.ranka for p in problems], [p.exta for p in problems],
+            [p.inca for p in problems], [d[3] for d in dev], [p.rankb for p in problems],
+            [p.extb for p in problems], [p.incb for p in problems], [d[4] for d in dev],
+            [p.conts for p in problems], [p.conta for p in problems],
+            [p.contb for p in problems], [p.perm for p in problems],
+            [p.incc for p in problems], [d[5] for d in dev], info)
+    torch.cuda.synchronize()
+    return rc, info
+
+
+def bound(prec, K):
+    return (K + 2) * U32 + (3 * 2.0 ** -16 if prec == gett.GETT_BF16X3 else 0.0)
+
+
+def check_problem(pr, got, prec, sample=96):
+    total = int(np.prod(pr.extc())) if pr.extc() else 1
+    K = pr.mnk()[2]
+    worst = 0.0
+    for first in sorted({0, max(total // 2 - sample // 2, 0), max(total - sample, 0)}):
+        ref, cabs = oracle.exact(pr, pr.A, pr.B, pr.C, first, min(first + sample, total))
+        sel = ~np.isnan(ref)
+        ec = e_cw(got[sel], ref[sel], cabs[sel])
+        assert ec <= bound(prec, K), (pr.name, ec, bound(prec, K))
+        worst = max(worst, ec)
+    m = outside_mask(pr.C)
+    assert np.array_equal(got[m], pr.C.buf[m])
+    return worst
+
+
+@pytest.mark.parametrize("prec", [gett.GETT_BF16X3, gett.GETT_FP32])
+def test_uneven_batch_of_512(prec):
+    """The uneven batch workload: 512 problems, ranks 2-5, 1-3 contracted
+    modes, extents log-uniform in [4,128], a quarter strided."""
+    problems = W.config_batch(512)
+    dev = upload(problems)
+    rc, info = run_batch(problems, dev, prec)
+    assert rc == 0 and all(i == 0 for i in info)
+    for pr, d in zip(problems, dev):
+        check_problem(pr, d[2].cpu().numpy(), prec)
+
+
+def test_dgett_batch_paper_cases():
+    rng = np.random.default_rng(41)
+    problems = [W.paper_case(c, rng) for c in W.PAPER_CASES for _ in range(2)]
+    dev = upload(problems)
+    rc, info = run_batch(problems, dev, gett.GETT_FP64)
+    assert rc == 0
+    for pr, d in zip(problems, dev):
+        got = d[2].cpu().numpy()
+        ref, cabs = oracle.exact(pr, pr.A, pr.B, pr.C)
+        sel = ~np.isnan(ref)
+        K = pr.mnk()[2]
+        assert e_cw(got[sel], ref[sel], cabs[sel]) <= (K + 2) * 2.0 ** -53
+        m = outside_mask(pr.C)
+        assert np.array_equal(got[m], pr.C.buf[m])
+
+
+def test_batch_equals_single_calls_bitwise():
+    """Single calls forced onto the batch tile (64x64, order 0, no split)
+    run the same code in the same order."""
+    import torch
+    problems = W.config_batch(48, seed=7)
+    dev = upload(problems)
+    rc, _ = run_batch(problems, dev, gett.GETT_BF16X3)
+    assert rc == 0
+    batch_out = [d[2].cpu().numpy() for d in dev]
+    gett.gett_set_schedule(gett.schedule_id(0, 0, 0))
+    try:
+        for pr, d in zip(problems, dev):
+            d[2].copy_(torch.from_numpy(pr.C.buf).cuda())
+            assert call14(gett.sgett_bf16x3, pr, d[3], d[4], d[5]) == 0
+        torch.cuda.synchronize()
+    finally:
+        gett.gett_set_schedule(-1)
+    for d, bo in zip(dev, batch_out):
+        assert np.array_equal(d[2].cpu().numpy(), bo)
+
+
+def test_graph_replay_with_new_pointers():
+    """Same signatures, new buffers and values: the captured graph is replayed
+    with rewritten descriptors and computes the new problems."""
+    problems = W.config_batch(40, seed=8)
+    dev = upload(problems)
+    assert run_batch(problems, dev, gett.GETT_FP32)[0] == 0
+    # fresh data of the same signatures
+    rng = np.random.default_rng(99)
+    fresh = []
+    for pr in problems:
+        A = W.View(pr.A.buf.copy(), pr.A.base, pr.A.ext, pr.A.inc)
+        idx = A.element_index()
+        A.buf[idx] = rng.standard_normal(idx.size).astype(np.float32)
+        fresh.append(pr.with_views(A, pr.B, pr.C.copy()))
+    dev2 = upload(fresh)
+    for _ in range(2):          # replay twice; the second must see zeroed C again
+        for pr, d in zip(fresh, dev2):
+            import torch
+            d[2].copy_(torch.from_numpy(pr.C.buf).cuda())
+        assert run_batch(fresh, dev2, gett.GETT_FP32)[0] == 0
+        for pr, d in zip(fresh, dev2):
+            check_problem(pr, d[2].cpu().numpy(), gett.GETT_FP32, sample=32)
+
+
+def test_batch_rejects_invalid_problem_and_skips_empty():
+    rng = np.random.default_rng(5)
+    problems = [W.paper_case("basic", rng, dtype=np.float32) for _ in range(4)]
+    dev = upload(problems)
+    bad = list(problems)
+    bad_perm = [list(p.perm) for p in problems]
+    if len(bad_perm[2]) >= 2:
+        bad_perm[2][0] = bad_perm[2][1]
+    else:
+        bad_perm[2] = [5]
+    info = [0] * 4
+    rc = gett.sgett_batch(4, gett.GETT_FP32, [p.ranka for p in bad], [p.exta for p in bad],
+                          [p.inca for p in bad], [d[3] for d in dev], [p.rankb for p in bad],
+                          [p.extb for p in bad], [p.incb for p in bad], [d[4] for d in dev],
+                          [p.conts for p in bad], [p.conta for p in bad], [p.contb for p in bad],
+                          bad_perm, [p.incc for p in bad], [d[5] for d in dev], info)
+    assert rc == -3000 - 12 and info[2] == -12
+    for pr, d in zip(problems, dev):           # nothing was queued
+        assert np.array_equal(d[2].cpu().numpy(), pr.C.buf)
+    # a zero-extent problem inside a batch is a no-op
+    z = W.Problem(2, [3, 0], [1, 3], 2, [0, 4], [1, 1], 1, [1], [0], [0, 1], [1, 3],
+                  problems[0].A, problems[0].B, W.make_c([3, 4], rng, np.float32))
+    mixed = [problems[0], z, problems[1]]
+    dev3 = upload(mixed)
+    rc, info = run_batch(mixed, dev3, gett.GETT_FP32)
+    assert rc == 0
+    check_problem(problems[0], dev3[0][2].cpu().numpy(), gett.GETT_FP32)
+    assert np.array_equal(dev3[1][2].cpu().numpy(), z.C.buf)

@@ -191,7 +191,8 @@ def test_every_schedule_matches(capsys):
         for sid in range(gett.num_schedules()):
             tile, order, split = gett.schedule_of(sid)
             bk = gett.gett_tile_shape(prec, tile)[2]
-            if gett.SPLIT_FACTORS[split] > 1 and K < gett.SPLIT_FACTORS[split] * bk:
+            S = gett.SPLIT_FACTORS[split]
+            if (S > 1 and K < S * bk) or (S == 0 and K < 4 * bk):
                 continue
             assert gett.gett_set_schedule(sid) == 0
             try:
