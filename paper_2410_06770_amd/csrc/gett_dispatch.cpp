@@ -3,6 +3,19 @@
 
 namespace gett {
 
+static thread_local hipError_t t_last_hip_error = hipSuccess;
+
+int launch_status() {
+    const hipError_t e = hipGetLastError();
+    if (e == hipSuccess) return 0;
+    t_last_hip_error = e;
+    return GETT_ERR_HIP;
+}
+
+const char *last_hip_error_name() {
+    return t_last_hip_error == hipSuccess ? "" : hipGetErrorName(t_last_hip_error);
+}
+
 #define GETT_DECLARE_PRECISION(SUFFIX)                                                             \
     int launch_tile_##SUFFIX(int tile, bool afk, bool bfk, const TileParams &p, hipStream_t s);    \
     int launch_splitk_reduce_##SUFFIX(const TileParams &p, hipStream_t s);                        \

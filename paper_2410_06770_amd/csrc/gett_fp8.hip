@@ -168,9 +168,10 @@ int launch_fp8_quant(const float *X, const int64_t *offR, int64_t rows, int64_t 
     const int64_t tasks = rowsPad * nb;
     const int64_t blocks = (tasks + 3) / 4;
     if (blocks > INT32_MAX) return GETT_ERR_INTERNAL;
+    (void)hipGetLastError();   // clear a stale error left by other HIP users
     hipLaunchKernelGGL(fp8_quant_kernel, dim3((unsigned)blocks), dim3(256), 0, s, X, offR, rows,
                        rowsPad, offK, K, Q, E);
-    return hipGetLastError() == hipSuccess ? 0 : GETT_ERR_HIP;
+    return launch_status();
 }
 
 int launch_fp8_gemm(int tile, const uint8_t *QA, const int32_t *EA, const uint8_t *QB,
@@ -178,15 +179,17 @@ int launch_fp8_gemm(int tile, const uint8_t *QA, const int32_t *EA, const uint8_
                     int64_t M, int64_t N, int64_t K, hipStream_t s) {
     if (tile == 3) {
         const int tilesM = (int)((M + 127) / 128), tilesN = (int)((N + 127) / 128);
+        (void)hipGetLastError();   // clear a stale error left by other HIP users
         hipLaunchKernelGGL((fp8_gemm_kernel<128, 128>), dim3(tilesM * tilesN), dim3(256), 0, s, QA,
                            EA, QB, EB, C, offCM, offCN, M, N, K, tilesM, tilesN);
     } else {
         // operands are padded to multiples of 128 rows, so 64-row tiles stay inside
         const int tilesM = (int)((M + 63) / 64), tilesN = (int)((N + 63) / 64);
+        (void)hipGetLastError();   // clear a stale error left by other HIP users
         hipLaunchKernelGGL((fp8_gemm_kernel<64, 64>), dim3(tilesM * tilesN), dim3(256), 0, s, QA,
                            EA, QB, EB, C, offCM, offCN, M, N, K, tilesM, tilesN);
     }
-    return hipGetLastError() == hipSuccess ? 0 : GETT_ERR_HIP;
+    return launch_status();
 }
 
 }  // namespace gett

@@ -1080,7 +1080,12 @@ const char *gett_strerror(int code) {
         return "invalid argument";
     }
     switch (code) {
-    case GETT_ERR_HIP: return "HIP runtime error";
+    case GETT_ERR_HIP: {
+        static thread_local char buf[128];
+        snprintf(buf, sizeof buf, "HIP runtime error (last launch error: %s)",
+                 last_hip_error_name());
+        return buf;
+    }
     case GETT_ERR_ALLOC: return "device allocation failed";
     case GETT_ERR_DEVICE: return "device is not gfx950 (MI355X)";
     case GETT_ERR_INTERNAL: return "internal planner limit";

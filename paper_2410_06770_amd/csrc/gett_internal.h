@@ -84,6 +84,11 @@ struct BatchProblem {
     int32_t pad_;
 };
 
+// Status of the launch just made: 0, or GETT_ERR_HIP with the HIP error kept
+// for gett_strerror (callers clear any stale error before launching).
+int launch_status();
+const char *last_hip_error_name();
+
 // Kernel launchers (defined in the .hip files).
 int launch_tile(int prec, int tile, bool aFastK, bool bFastK, const TileParams &p,
                 hipStream_t s);

@@ -123,20 +123,24 @@ static int blocks_for(int64_t n) { return (int)((n + 255) / 256); }
 
 int launch_mlp_linear_fwd(const float *X, const float *W, const float *b, float *Y, int64_t batch,
                           int64_t din, int64_t dout, int relu, hipStream_t s) {
+    (void)hipGetLastError();   // clear a stale error left by other HIP users
     hipLaunchKernelGGL(mlp_fwd_kernel, dim3(blocks_for(batch * dout)), dim3(256), 0, s, X, W, b, Y,
                        batch, din, dout, relu);
-    return hipGetLastError() == hipSuccess ? 0 : GETT_ERR_HIP;
+    return launch_status();
 }
 
 int launch_mlp_linear_bwd(const float *X, const float *W, const float *Y, const float *dY,
                           float *dX, float *dW, float *db, int64_t batch, int64_t din,
                           int64_t dout, int relu, hipStream_t s) {
+    (void)hipGetLastError();   // clear a stale error left by other HIP users
     hipLaunchKernelGGL(mlp_bwd_w_kernel, dim3(blocks_for(dout * din + dout)), dim3(256), 0, s, X, Y,
                        dY, dW, db, batch, din, dout, relu);
-    if (dX)
+    if (launch_status()) return GETT_ERR_HIP;
+    if (dX) {
         hipLaunchKernelGGL(mlp_bwd_x_kernel, dim3(blocks_for(batch * din)), dim3(256), 0, s, W, Y,
                            dY, dX, batch, din, dout, relu);
-    return hipGetLastError() == hipSuccess ? 0 : GETT_ERR_HIP;
+    }
+    return launch_status();
 }
 
 int launch_mlp_xent(const float *Z, const float *T, float *dZ, float *loss, int64_t batch,
@@ -144,17 +148,19 @@ int launch_mlp_xent(const float *Z, const float *T, float *dZ, float *loss, int6
     Heads h;
     h.n = (int32_t)nheads;
     for (int i = 0; i < 8; ++i) h.size[i] = i < nheads ? (int32_t)head_sizes[i] : 0;
+    (void)hipGetLastError();   // clear a stale error left by other HIP users
     hipLaunchKernelGGL(mlp_xent_kernel, dim3(1), dim3(256), 0, s, Z, T, dZ, loss, batch, total, h);
-    return hipGetLastError() == hipSuccess ? 0 : GETT_ERR_HIP;
+    return launch_status();
 }
 
 int launch_mlp_adam(float *P, const float *G, float *m, float *v, int64_t n, float lr, float b1,
                     float b2, float eps, int64_t t, hipStream_t s) {
     const float c1 = 1.f - powf(b1, (float)t);
     const float c2 = 1.f - powf(b2, (float)t);
+    (void)hipGetLastError();   // clear a stale error left by other HIP users
     hipLaunchKernelGGL(mlp_adam_kernel, dim3(blocks_for(n)), dim3(256), 0, s, P, G, m, v, n, lr, b1,
                        b2, eps, c1, c2);
-    return hipGetLastError() == hipSuccess ? 0 : GETT_ERR_HIP;
+    return launch_status();
 }
 
 }  // namespace gett

@@ -432,8 +432,9 @@ static int launch_one(const TileParams &p, hipStream_t s) {
         attr_set = true;
     }
     const int total = p.tilesM * p.tilesN * p.splits;
+    (void)hipGetLastError();   // clear a stale error left by other HIP users
     hipLaunchKernelGGL(kern, dim3(total), dim3(kThreads), Cfg::kLdsBytes, s, p);
-    return hipGetLastError() == hipSuccess ? 0 : GETT_ERR_HIP;
+    return launch_status();
 }
 
 template <int PREC, int BM, int BN, int BK>
@@ -469,8 +470,9 @@ template <int PREC> static int launch_splitk_reduce_prec(const TileParams &p, hi
     int64_t blocks = (MN + 255) / 256;
     if (blocks > 65536) blocks = 65536;
     if (blocks < 1) blocks = 1;
+    (void)hipGetLastError();   // clear a stale error left by other HIP users
     hipLaunchKernelGGL(splitk_reduce_kernel<PREC>, dim3(blocks), dim3(256), 0, s, p);
-    return hipGetLastError() == hipSuccess ? 0 : GETT_ERR_HIP;
+    return launch_status();
 }
 
 template <int PREC> static int batch_grid_size_prec() {
@@ -487,9 +489,10 @@ template <int PREC>
 static int launch_batch_prec(const BatchProblem *d_probs, const int32_t *d_items, int32_t nitems,
                              int32_t grid, hipStream_t s) {
     if (grid < 1 || nitems < 1) return 0;
+    (void)hipGetLastError();   // clear a stale error left by other HIP users
     hipLaunchKernelGGL(gett_batch_kernel<PREC>, dim3(grid), dim3(kThreads), batch_lds<PREC>(), s,
                        d_probs, d_items, nitems);
-    return hipGetLastError() == hipSuccess ? 0 : GETT_ERR_HIP;
+    return launch_status();
 }
 
 // Defines the four per-precision entry points used by the host dispatcher.

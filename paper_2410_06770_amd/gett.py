@@ -46,6 +46,15 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                            "`python -m paper_2410_06770_amd.build` (there is no fallback)")
+    # PyTorch-ROCm ships its own libamdhip64.so.7 with the same soname as the
+    # system one this library links against.  Whichever is loaded first serves
+    # the whole process; load torch's first so that torch and the library
+    # share one HIP runtime (device memory, streams and events are then the
+    # same objects on both sides).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ct.CDLL(LIB_PATH)
     a14 = [i64, I64P, I64P, vp, i64, I64P, I64P, vp, i64, I64P, I64P, I64P, I64P, vp]
     for name in ("dgett", "sgett", "sgett_bf16x3", "sgett_fp8"):

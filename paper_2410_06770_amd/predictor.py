@@ -137,7 +137,8 @@ class MLP:
                                                 (y2, W3, b3, z, H2, DOUT, 0)):
             rc = gett.gett_mlp_linear_fwd(xin.data_ptr(), W.data_ptr(), b.data_ptr(),
                                           y.data_ptr(), B, din, dout, relu)
-            assert rc == 0, rc
+            if rc:
+                raise gett.GettError(rc, "gett_mlp_linear_fwd")
         return y1, y2, z
 
     def loss_and_grads(self, X, T):
