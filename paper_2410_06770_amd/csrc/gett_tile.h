@@ -26,6 +26,8 @@
 // tile at once; only the summation order differs.
 #pragma once
 
+#include <type_traits>
+
 #include "gett_internal.h"
 
 namespace gett {
@@ -98,7 +100,6 @@ template <int PREC, int ROWS, int BK, bool FASTK> struct Gather {
     static_assert(BK <= 64, "one wave holds a step's contracted offsets");
 
     const T *base[NF];  // X + free offset of each row this thread reads
-    bool okF[NF];
     int row[NF];        // tile row of each free offset
     int j0;             // first contracted index of this thread (wave-uniform when !FASTK)
     int64_t koff;       // contracted offset held by this lane for the current step
@@ -111,7 +112,6 @@ template <int PREC, int ROWS, int BK, bool FASTK> struct Gather {
             const int r = y + (ROWS / boxX) * x;     // tile row (C-fast side first)
             const int64_t g = r0 + r;
             row[0] = r;
-            okF[0] = g < nrows;
             base[0] = X + offFree[g];
             j0 = __builtin_amdgcn_readfirstlane(t / ROWS);
         } else {
@@ -121,7 +121,6 @@ template <int PREC, int ROWS, int BK, bool FASTK> struct Gather {
                 const int r = t / BK + i * (kThreads / BK);
                 const int64_t g = r0 + r;
                 row[i] = r;
-                okF[i] = g < nrows;
                 base[i] = X + offFree[g];
             }
         }
@@ -134,6 +133,11 @@ template <int PREC, int ROWS, int BK, bool FASTK> struct Gather {
         else koff = offK[k0 + j0];
     }
 
+    // Values of the step starting at k0.  Rows past the operand's extent read
+    // the element of row 0 (their padded offset is 0) and are never stored,
+    // so only contracted positions need masking, and only while a step may
+    // reach past kend (MASKED): those read the zero buffer instead.
+    template <bool MASKED>
     __device__ __forceinline__ void load(int64_t k0, int64_t kend, T (&v)[PER]) const {
         const T *zero = reinterpret_cast<const T *>(g_gett_zero);
         if constexpr (!FASTK) {
@@ -141,14 +145,16 @@ template <int PREC, int ROWS, int BK, bool FASTK> struct Gather {
             for (int i = 0; i < PER; ++i) {
                 const int j = j0 + i * (kThreads / ROWS);   // uniform
                 const int64_t ko = readlane64(koff, j % BK);
-                const T *ptr = (okF[0] && k0 + j < kend) ? base[0] + ko : zero;
+                const T *ptr = base[0] + ko;
+                if constexpr (MASKED) ptr = (k0 + j < kend) ? ptr : zero;
                 v[i] = *ptr;
             }
         } else {
             const bool kk = k0 + j0 < kend;
 #pragma unroll
             for (int i = 0; i < PER; ++i) {
-                const T *ptr = (okF[i] && kk) ? base[i] + koff : zero;
+                const T *ptr = base[i] + koff;
+                if constexpr (MASKED) ptr = kk ? ptr : zero;
                 v[i] = *ptr;
             }
         }
@@ -236,22 +242,29 @@ __device__ __forceinline__ void gett_tile(const TileParams &p, int64_t m0, int64
     // the extra loads of the last steps stay in bounds.  A loop without
     // branches lets the accumulators live in the MFMA registers throughout.
     const int64_t nsteps = (kend - kbeg + BK - 1) / BK;
+    const int64_t nfull = (kend - kbeg) / BK;    // steps lying wholly below kend
     ga.load_koffs(p.offAK, kbeg);
     gb.load_koffs(p.offBK, kbeg);
-    ga.load(kbeg, kend, va);
-    gb.load(kbeg, kend, vb);
+    ga.template load<true>(kbeg, kend, va);
+    gb.template load<true>(kbeg, kend, vb);
     ga.load_koffs(p.offAK, kbeg + BK);
     gb.load_koffs(p.offBK, kbeg + BK);
     ga.store(stageA(0), va);
     gb.store(stageB(0), vb);
     __syncthreads();
 
-    for (int64_t s = 0; s < nsteps; ++s) {
+    // One K step: issue the next step's loads first (they land while the
+    // MFMAs run), compute on the current LDS stage, then stage the loaded
+    // values and synchronise.  The loop body has no branches, so the
+    // accumulators stay in place; the step count only selects which of two
+    // copies of the body runs (unmasked loads while the next step lies
+    // wholly below kend).
+    auto step = [&](int64_t s, auto masked) {
+        constexpr bool MASKED = decltype(masked)::value;
         const int cur = static_cast<int>(s & 1);
         const int64_t k1 = kbeg + (s + 1) * BK;
-        // issue the next step's loads first; they land while the MFMAs run
-        ga.load(k1, kend, va);
-        gb.load(k1, kend, vb);
+        ga.template load<MASKED>(k1, kend, va);
+        gb.template load<MASKED>(k1, kend, vb);
         ga.load_koffs(p.offAK, k1 + BK);
         gb.load_koffs(p.offBK, k1 + BK);
         __builtin_amdgcn_sched_barrier(0);
@@ -313,7 +326,10 @@ __device__ __forceinline__ void gett_tile(const TileParams &p, int64_t m0, int64
         ga.store(stageA(cur ^ 1), va);
         gb.store(stageB(cur ^ 1), vb);
         __syncthreads();
-    }
+    };
+    int64_t s = 0;
+    for (; s + 1 < nfull; ++s) step(s, std::false_type{});
+    for (; s < nsteps; ++s) step(s, std::true_type{});
 
     // Epilogue.  Fragment (i, j), register v of lane l holds D[row][l%16]
     // (row = M position, column = N position) with row = 4*(l/16) + v for
