@@ -26,8 +26,6 @@
 // tile at once; only the summation order differs.
 #pragma once
 
-#include <type_traits>
-
 #include "gett_internal.h"
 
 namespace gett {
@@ -133,12 +131,21 @@ template <int PREC, int ROWS, int BK, bool FASTK> struct Gather {
         else koff = offK[k0 + j0];
     }
 
+    // The same for a step that may start below klo (the first step of a
+    // range): positions below klo take klo's offset (their values are masked).
+    __device__ __forceinline__ void load_koffs_from(const int64_t *__restrict__ offK, int64_t k0,
+                                                    int64_t klo) {
+        const int64_t k = k0 + (FASTK ? j0 : (threadIdx.x & 63) % BK);
+        koff = offK[k < klo ? klo : k];
+    }
+
     // Values of the step starting at k0.  Rows past the operand's extent read
     // the element of row 0 (their padded offset is 0) and are never stored,
-    // so only contracted positions need masking, and only while a step may
-    // reach past kend (MASKED): those read the zero buffer instead.
+    // so only contracted positions need masking, and only in the first step
+    // of a range (MASKED), which may start below klo: those positions read
+    // the zero buffer instead.
     template <bool MASKED>
-    __device__ __forceinline__ void load(int64_t k0, int64_t kend, T (&v)[PER]) const {
+    __device__ __forceinline__ void load(int64_t k0, int64_t klo, T (&v)[PER]) const {
         const T *zero = reinterpret_cast<const T *>(g_gett_zero);
         if constexpr (!FASTK) {
 #pragma unroll
@@ -146,11 +153,11 @@ template <int PREC, int ROWS, int BK, bool FASTK> struct Gather {
                 const int j = j0 + i * (kThreads / ROWS);   // uniform
                 const int64_t ko = readlane64(koff, j % BK);
                 const T *ptr = base[0] + ko;
-                if constexpr (MASKED) ptr = (k0 + j < kend) ? ptr : zero;
+                if constexpr (MASKED) ptr = (k0 + j >= klo) ? ptr : zero;
                 v[i] = *ptr;
             }
         } else {
-            const bool kk = k0 + j0 < kend;
+            const bool kk = k0 + j0 >= klo;
 #pragma unroll
             for (int i = 0; i < PER; ++i) {
                 const T *ptr = base[i] + koff;
@@ -236,35 +243,35 @@ __device__ __forceinline__ void gett_tile(const TileParams &p, int64_t m0, int64
     auto stageA = [&](int buf) { return smem + buf * Cfg::kStageBytes; };
     auto stageB = [&](int buf) { return smem + buf * Cfg::kStageBytes + Cfg::LA::kBytes; };
 
-    // The K loop is branch-free: every step loads the next step's values
-    // (masked to zero past kend) and the offsets of the step after that.
-    // The contracted tables carry enough zero padding past K for both, so
-    // the extra loads of the last steps stay in bounds.  A loop without
-    // branches lets the accumulators live in the MFMA registers throughout.
+    // The K loop is branch-free.  Steps are aligned to end at kend, so only
+    // the first one can be partial (its positions below kbeg read zeros) and
+    // every step inside the loop is whole.  Each step loads the next step's
+    // values and the offsets of the step after that; the last step's loads
+    // read past kend, which is in bounds: the contracted tables carry zero
+    // padding past K (offset 0, i.e. a valid element) and a split slice that
+    // ends below K reads real positions of the next slice.  The values are
+    // never used.  A loop without branches lets the accumulators live in the
+    // MFMA registers throughout.
     const int64_t nsteps = (kend - kbeg + BK - 1) / BK;
-    const int64_t nfull = (kend - kbeg) / BK;    // steps lying wholly below kend
-    ga.load_koffs(p.offAK, kbeg);
-    gb.load_koffs(p.offBK, kbeg);
-    ga.template load<true>(kbeg, kend, va);
-    gb.template load<true>(kbeg, kend, vb);
-    ga.load_koffs(p.offAK, kbeg + BK);
-    gb.load_koffs(p.offBK, kbeg + BK);
+    const int64_t kfirst = kend - nsteps * BK;   // may lie below kbeg (and below 0)
+    ga.load_koffs_from(p.offAK, kfirst, kbeg);
+    gb.load_koffs_from(p.offBK, kfirst, kbeg);
+    ga.template load<true>(kfirst, kbeg, va);
+    gb.template load<true>(kfirst, kbeg, vb);
+    ga.load_koffs(p.offAK, kfirst + BK);          // kfirst + BK > kbeg
+    gb.load_koffs(p.offBK, kfirst + BK);
     ga.store(stageA(0), va);
     gb.store(stageB(0), vb);
     __syncthreads();
 
     // One K step: issue the next step's loads first (they land while the
     // MFMAs run), compute on the current LDS stage, then stage the loaded
-    // values and synchronise.  The loop body has no branches, so the
-    // accumulators stay in place; the step count only selects which of two
-    // copies of the body runs (unmasked loads while the next step lies
-    // wholly below kend).
-    auto step = [&](int64_t s, auto masked) {
-        constexpr bool MASKED = decltype(masked)::value;
+    // values and synchronise.
+    for (int64_t s = 0; s < nsteps; ++s) {
         const int cur = static_cast<int>(s & 1);
-        const int64_t k1 = kbeg + (s + 1) * BK;
-        ga.template load<MASKED>(k1, kend, va);
-        gb.template load<MASKED>(k1, kend, vb);
+        const int64_t k1 = kfirst + (s + 1) * BK;
+        ga.template load<false>(k1, kbeg, va);
+        gb.template load<false>(k1, kbeg, vb);
         ga.load_koffs(p.offAK, k1 + BK);
         gb.load_koffs(p.offBK, k1 + BK);
         __builtin_amdgcn_sched_barrier(0);
@@ -326,10 +333,7 @@ __device__ __forceinline__ void gett_tile(const TileParams &p, int64_t m0, int64
         ga.store(stageA(cur ^ 1), va);
         gb.store(stageB(cur ^ 1), vb);
         __syncthreads();
-    };
-    int64_t s = 0;
-    for (; s + 1 < nfull; ++s) step(s, std::false_type{});
-    for (; s < nsteps; ++s) step(s, std::true_type{});
+    }
 
     // Epilogue.  Fragment (i, j), register v of lane l holds D[row][l%16]
     // (row = M position, column = N position) with row = 4*(l/16) + v for
