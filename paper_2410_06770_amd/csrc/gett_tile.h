@@ -88,19 +88,50 @@ __device__ __forceinline__ int64_t readlane64(int64_t v, int lane) {
     return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
 }
 
+// Split two FP32 values into packed bfloat16 pairs: hi = bf16(x) (round to
+// nearest even), lo = bf16(x - hi) (the subtraction is exact).  Element 0
+// goes to the low half of each word.
+__device__ __forceinline__ void bf16x3_split_pair(float x0, float x1, uint32_t &hi, uint32_t &lo) {
+    typedef float f2_t __attribute__((ext_vector_type(2)));
+    typedef __bf16 b2_t __attribute__((ext_vector_type(2)));
+    hi = __builtin_bit_cast(uint32_t, __builtin_convertvector(f2_t{x0, x1}, b2_t));
+    const float h0 = __uint_as_float(hi << 16), h1 = __uint_as_float(hi & 0xffff0000u);
+    lo = __builtin_bit_cast(uint32_t, __builtin_convertvector(f2_t{x0 - h0, x1 - h1}, b2_t));
+}
+
 // Gather of one operand's ROWS x BK sub-tile into registers.
+//
+// Within a step, the LDS column c of both operands holds contracted position
+// kpos(c) of the step; any permutation works as long as A and B share it.
+// FP64/FP32 use the identity.  BF16x3 uses c = 2q + e <-> q + e * BK/2, so
+// that a thread that runs along K with lanes q = 0 .. BK/2 - 1 (neighbouring
+// lanes read neighbouring positions) holds two values that are neighbours in
+// LDS and writes each plane as one 4-byte word, and a thread that runs along
+// the free axis holds a contiguous run of columns and writes 16-byte chunks.
 template <int PREC, int ROWS, int BK, bool FASTK> struct Gather {
     using T = typename PrecT<PREC>::T;
+    static constexpr bool kSplit = PREC == kBF3;
     static constexpr int PER = ROWS * BK / kThreads;   // values per thread
-    static constexpr int NF = FASTK ? PER : 1;
+    static constexpr int KP = (kSplit && FASTK) ? 2 : 1;   // positions per row (FASTK)
+    static constexpr int KL = BK / KP;                 // lanes along K per row (FASTK)
+    static constexpr int NF = FASTK ? PER / KP : 1;     // rows per thread
     static_assert(ROWS * BK % kThreads == 0, "tile too small for the workgroup");
-    static_assert(FASTK ? (kThreads % BK == 0) : (kThreads % ROWS == 0), "loader shape");
+    static_assert(FASTK ? (kThreads % KL == 0) : (kThreads % ROWS == 0), "loader shape");
     static_assert(BK <= 64, "one wave holds a step's contracted offsets");
+    static_assert(!kSplit || FASTK || PER % 8 == 0, "16-byte LDS chunks");
 
     const T *base[NF];  // X + free offset of each row this thread reads
     int row[NF];        // tile row of each free offset
-    int j0;             // first contracted index of this thread (wave-uniform when !FASTK)
-    int64_t koff;       // contracted offset held by this lane for the current step
+    int j0;             // !FASTK: wave-uniform column group; FASTK: lane position q
+    int64_t koff[KP];   // contracted offsets held by this lane for the current step
+
+    static __device__ __forceinline__ constexpr int kpos(int c) {
+        return kSplit ? (c >> 1) + (c & 1) * (BK / 2) : c;
+    }
+    // !FASTK: LDS column of the thread's i-th value.
+    __device__ __forceinline__ int col(int i) const {
+        return kSplit ? j0 * PER + i : j0 + i * (kThreads / ROWS);
+    }
 
     __device__ void init(const T *X, int t, int64_t r0, int64_t nrows,
                          const int64_t *__restrict__ offFree, int boxX) {
@@ -113,10 +144,10 @@ template <int PREC, int ROWS, int BK, bool FASTK> struct Gather {
             base[0] = X + offFree[g];
             j0 = __builtin_amdgcn_readfirstlane(t / ROWS);
         } else {
-            j0 = t % BK;
+            j0 = t % KL;
 #pragma unroll
-            for (int i = 0; i < PER; ++i) {
-                const int r = t / BK + i * (kThreads / BK);
+            for (int i = 0; i < NF; ++i) {
+                const int r = t / KL + i * (kThreads / KL);
                 const int64_t g = r0 + r;
                 row[i] = r;
                 base[i] = X + offFree[g];
@@ -124,19 +155,32 @@ template <int PREC, int ROWS, int BK, bool FASTK> struct Gather {
         }
     }
 
-    // One vector load per step: lane l holds offK[k0 + (l % BK)] (or
-    // offK[k0 + j0] when threads run along K).
+    // Contracted offsets of the step starting at k0: lane l holds
+    // offK[k0 + (l % BK)] (threads along the free axis pick theirs with
+    // readlane), or offK[k0 + q + e * KL] when threads run along K.
     __device__ __forceinline__ void load_koffs(const int64_t *__restrict__ offK, int64_t k0) {
-        if constexpr (!FASTK) koff = offK[k0 + (threadIdx.x & 63) % BK];
-        else koff = offK[k0 + j0];
+        if constexpr (!FASTK) {
+            koff[0] = offK[k0 + (threadIdx.x & 63) % BK];
+        } else {
+#pragma unroll
+            for (int e = 0; e < KP; ++e) koff[e] = offK[k0 + j0 + e * KL];
+        }
     }
 
     // The same for a step that may start below klo (the first step of a
     // range): positions below klo take klo's offset (their values are masked).
     __device__ __forceinline__ void load_koffs_from(const int64_t *__restrict__ offK, int64_t k0,
                                                     int64_t klo) {
-        const int64_t k = k0 + (FASTK ? j0 : (threadIdx.x & 63) % BK);
-        koff = offK[k < klo ? klo : k];
+        if constexpr (!FASTK) {
+            const int64_t k = k0 + (threadIdx.x & 63) % BK;
+            koff[0] = offK[k < klo ? klo : k];
+        } else {
+#pragma unroll
+            for (int e = 0; e < KP; ++e) {
+                const int64_t k = k0 + j0 + e * KL;
+                koff[e] = offK[k < klo ? klo : k];
+            }
+        }
     }
 
     // Values of the step starting at k0.  Rows past the operand's extent read
@@ -150,19 +194,22 @@ template <int PREC, int ROWS, int BK, bool FASTK> struct Gather {
         if constexpr (!FASTK) {
 #pragma unroll
             for (int i = 0; i < PER; ++i) {
-                const int j = j0 + i * (kThreads / ROWS);   // uniform
-                const int64_t ko = readlane64(koff, j % BK);
+                const int k = kpos(col(i));                  // uniform
+                const int64_t ko = readlane64(koff[0], k);
                 const T *ptr = base[0] + ko;
-                if constexpr (MASKED) ptr = (k0 + j >= klo) ? ptr : zero;
+                if constexpr (MASKED) ptr = (k0 + k >= klo) ? ptr : zero;
                 v[i] = *ptr;
             }
         } else {
-            const bool kk = k0 + j0 >= klo;
 #pragma unroll
-            for (int i = 0; i < PER; ++i) {
-                const T *ptr = base[i] + koff;
-                if constexpr (MASKED) ptr = kk ? ptr : zero;
-                v[i] = *ptr;
+            for (int e = 0; e < KP; ++e) {
+                const bool kk = k0 + j0 + e * KL >= klo;
+#pragma unroll
+                for (int i = 0; i < NF; ++i) {
+                    const T *ptr = base[i] + koff[e];
+                    if constexpr (MASKED) ptr = kk ? ptr : zero;
+                    v[i * KP + e] = *ptr;
+                }
             }
         }
     }
@@ -170,25 +217,37 @@ template <int PREC, int ROWS, int BK, bool FASTK> struct Gather {
     // Write the registers into the LDS tile.
     __device__ __forceinline__ void store(void *lds, const T (&v)[PER]) const {
         using L = OpLds<PREC, ROWS, BK>;
-        if constexpr (PREC == kBF3) {
-            __bf16 *hi = reinterpret_cast<__bf16 *>(lds);
-            __bf16 *lo = hi + ROWS * L::kLd;
+        if constexpr (kSplit) {
+            uint32_t *hi = reinterpret_cast<uint32_t *>(lds);       // bfloat16 pairs
+            uint32_t *lo = hi + ROWS * L::kLd / 2;
+            if constexpr (FASTK) {
 #pragma unroll
-            for (int i = 0; i < PER; ++i) {
-                const int r = FASTK ? row[i] : row[0];
-                const int j = FASTK ? j0 : j0 + i * (kThreads / ROWS);
-                const float x = v[i];
-                const __bf16 h = (__bf16)x;                 // round to nearest even
-                const float rest = x - (float)h;            // exact
-                hi[r * L::kLd + j] = h;
-                lo[r * L::kLd + j] = (__bf16)rest;
+                for (int i = 0; i < NF; ++i) {
+                    uint32_t h, l;
+                    bf16x3_split_pair(v[2 * i], v[2 * i + 1], h, l);
+                    const int w = (row[i] * L::kLd + 2 * j0) / 2;
+                    hi[w] = h;
+                    lo[w] = l;
+                }
+            } else {
+                const int w0 = (row[0] * L::kLd + j0 * PER) / 2;
+#pragma unroll
+                for (int c = 0; c < PER / 8; ++c) {
+                    uint4 h, l;
+                    bf16x3_split_pair(v[8 * c + 0], v[8 * c + 1], h.x, l.x);
+                    bf16x3_split_pair(v[8 * c + 2], v[8 * c + 3], h.y, l.y);
+                    bf16x3_split_pair(v[8 * c + 4], v[8 * c + 5], h.z, l.z);
+                    bf16x3_split_pair(v[8 * c + 6], v[8 * c + 7], h.w, l.w);
+                    *reinterpret_cast<uint4 *>(hi + w0 + 4 * c) = h;
+                    *reinterpret_cast<uint4 *>(lo + w0 + 4 * c) = l;
+                }
             }
         } else {
             T *s = reinterpret_cast<T *>(lds);
 #pragma unroll
             for (int i = 0; i < PER; ++i) {
                 const int r = FASTK ? row[i] : row[0];
-                const int j = FASTK ? j0 : j0 + i * (kThreads / ROWS);
+                const int j = FASTK ? j0 : col(i);
                 s[j * L::kLd + r] = v[i];
             }
         }
