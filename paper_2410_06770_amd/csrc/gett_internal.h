@@ -49,17 +49,33 @@ inline int split_count(int split, int64_t tiles, int64_t K, int bk, int64_t *kPe
 }
 constexpr int kTablePad = 256;      // M/N tables padded to a multiple of this
 
-struct TileShape { int bm, bn, bk; };
+// load_fence: the compiler keeps the next step's global loads ahead of the
+// step's MFMA block (a scheduling barrier between them).  Without it the
+// loads may move into the MFMA block; which is faster depends on the tile
+// (measured on gfx950 per precision and tile).
+struct TileShape { int bm, bn, bk; bool load_fence; };
 
 // Tile menus.  FP64/FP32 run 16x16x4 MFMA steps (BK multiple of 4), the BF16x3
 // path 16x16x32 BF16 MFMA steps (BK multiple of 32).  Each workgroup is a 2x2
 // grid of waves, so BM and BN are multiples of 32.
 constexpr TileShape kTiles[4][kNumTiles] = {
-    /* FP64   */ {{64, 64, 16}, {64, 128, 16}, {128, 64, 16}, {128, 128, 16}, {128, 128, 8}},
-    /* FP32   */ {{64, 64, 16}, {64, 128, 16}, {128, 64, 16}, {128, 128, 16}, {128, 128, 32}},
-    /* BF16x3 */ {{64, 64, 32}, {64, 128, 32}, {128, 64, 32}, {128, 128, 32}, {128, 128, 64}},
-    /* FP8    */ {{64, 64, 128}, {64, 128, 128}, {128, 64, 128}, {128, 128, 128}, {128, 128, 128}},
+    /* FP64   */ {{64, 64, 16, true}, {64, 128, 16, false}, {128, 64, 16, false},
+                  {128, 128, 16, true}, {128, 64, 8, false}},
+    /* FP32   */ {{64, 64, 16, true}, {64, 128, 16, true}, {128, 64, 16, true},
+                  {128, 128, 16, true}, {128, 128, 32, true}},
+    /* BF16x3 */ {{64, 64, 32, true}, {64, 128, 32, true}, {128, 64, 32, true},
+                  {128, 128, 32, true}, {128, 128, 64, true}},
+    /* FP8    */ {{64, 64, 128, true}, {64, 128, 128, true}, {128, 64, 128, true},
+                  {128, 128, 128, true}, {128, 128, 128, true}},
 };
+
+// Flag of the menu entry with this shape (first match).
+constexpr bool tile_load_fence(int prec, int bm, int bn, int bk) {
+    for (int t = 0; t < kNumTiles; ++t)
+        if (kTiles[prec][t].bm == bm && kTiles[prec][t].bn == bn && kTiles[prec][t].bk == bk)
+            return kTiles[prec][t].load_fence;
+    return true;
+}
 
 // Arguments of one tile kernel launch (passed by value in the kernarg segment).
 struct TileParams {

@@ -333,7 +333,7 @@ __device__ __forceinline__ void gett_tile(const TileParams &p, int64_t m0, int64
         gb.template load<false>(k1, kbeg, vb);
         ga.load_koffs(p.offAK, k1 + BK);
         gb.load_koffs(p.offBK, k1 + BK);
-        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (tile_load_fence(PREC, BM, BN, BK)) __builtin_amdgcn_sched_barrier(0);
         if constexpr (!kSplit) {
             const T *sa = reinterpret_cast<const T *>(stageA(cur));
             const T *sb = reinterpret_cast<const T *>(stageB(cur));
@@ -388,7 +388,6 @@ __device__ __forceinline__ void gett_tile(const TileParams &p, int64_t m0, int64
                     }
             }
         }
-        __builtin_amdgcn_sched_barrier(0);
         ga.store(stageA(cur ^ 1), va);
         gb.store(stageB(cur ^ 1), vb);
         __syncthreads();
