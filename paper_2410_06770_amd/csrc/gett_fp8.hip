@@ -1,23 +1,32 @@
 // gett_fp8.hip -- the FP8 (OCP E4M3) path of SGETT.
 //
-// quant:  one wave per (row, 128-block): the wave gathers the block's 128
-//         values through the row and contracted offset tables, finds the
-//         largest magnitude, picks the power-of-two scale 2^e (smallest e >=
-//         -127 with amax / 2^e <= 448; exact integer logic on the binary
-//         exponent), and writes the E4M3 codes (round to nearest even) into a
-//         dense K-contiguous row, with e beside it.
+// quant:  each (row, 128-block) of an operand gets its largest magnitude
+//         amax, the power-of-two scale 2^e (smallest e >= -127 with
+//         amax / 2^e <= 448; exact integer logic on the binary exponent), and
+//         E4M3 codes (round to nearest even) written into a dense
+//         K-contiguous row, with e beside it.  Two loader shapes, as in the
+//         tile kernels: when the contracted positions are the operand's
+//         cheapest direction in memory, one wave takes one (row, block) with
+//         lanes along K; when the rows are, one wave takes 64 neighbouring
+//         rows of one block with a lane per row, so every load of the wave
+//         reads 64 neighbours.
 // gemm:   both operands are then dense [rows][Kp] byte matrices, the shape the
 //         16x16x128 FP8 MFMA reads directly: each lane takes 32 consecutive
 //         codes of one row.  The block scales go in as the MFMA's E8M0 scale
 //         operands (bias 127), so the matrix core applies 2^(eA + eB) to each
-//         128-block product exactly and accumulates in FP32.  The epilogue
-//         scatters through the C offset tables (PERM and INCC) and adds C_in.
+//         128-block product exactly and accumulates in FP32.  The next
+//         block's codes are loaded into registers while the current block
+//         runs on the matrix cores (double-buffered LDS, one barrier per
+//         block).  The epilogue scatters through the C offset tables (PERM
+//         and INCC) and adds C_in.
+#include "gett_grid.h"
 #include "gett_internal.h"
 
 namespace gett {
 
 typedef float f4_t __attribute__((ext_vector_type(4)));
 typedef int i8_t __attribute__((ext_vector_type(8)));
+typedef unsigned u4_t __attribute__((ext_vector_type(4)));
 
 // Scale exponent from the block maximum (see file comment).
 __device__ __forceinline__ int fp8_scale_exp(float amax) {
@@ -43,6 +52,14 @@ __device__ __forceinline__ unsigned e4m3_code(float v) {
     return (unsigned)packed & 0xFFu;
 }
 
+// Four codes in one word, first value in the low byte.
+__device__ __forceinline__ unsigned e4m3_word(float a, float b, float c, float d) {
+    int w = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
+    w = __builtin_amdgcn_cvt_pk_fp8_f32(c, d, w, true);
+    return (unsigned)w;
+}
+
+// Lanes along K: one wave per (row, 128-block), two positions per lane.
 __global__ __launch_bounds__(256) void fp8_quant_kernel(const float *__restrict__ X,
                                                         const int64_t *__restrict__ offR,
                                                         int64_t rows, int64_t rowsPad,
@@ -77,6 +94,99 @@ __global__ __launch_bounds__(256) void fp8_quant_kernel(const float *__restrict_
     if (lane == 0) E[r * nb + blk] = e;
 }
 
+// Lanes along the rows: one wave per (64 rows, 128-block); each lane keeps its
+// row's 128 values in registers, so X is read once.
+__global__ __launch_bounds__(256) void fp8_quant_rows_kernel(const float *__restrict__ X,
+                                                             const int64_t *__restrict__ offR,
+                                                             int64_t rows, int64_t rowsPad,
+                                                             const int64_t *__restrict__ offK,
+                                                             int64_t K, uint8_t *__restrict__ Q,
+                                                             int32_t *__restrict__ E) {
+    const int64_t nb = (K + 127) / 128;
+    const int64_t Kp = nb * 128;
+    const int lane = threadIdx.x & 63;
+    const int64_t groups = (rowsPad + 63) / 64;
+    const int64_t task = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (task >= groups * nb) return;
+    const int64_t blk = task / groups, g = task - blk * groups;   // neighbouring waves: neighbouring rows
+    const int64_t r = g * 64 + lane;
+    const bool live = r < rows;
+    const float *x = X + (live ? offR[r] : 0);
+    const int64_t k0 = blk * 128;
+    const int kn = (int)(K - k0 < 128 ? K - k0 : 128);   // wave-uniform
+    float v[128];
+    float amax = 0.f;
+#pragma unroll
+    for (int i = 0; i < 128; ++i) {
+        v[i] = (i < kn && live) ? x[offK[k0 + i]] : 0.f;
+        amax = fmaxf(amax, fabsf(v[i]));
+    }
+    const int e = fp8_scale_exp(amax);
+    const float inv = ldexpf(1.f, -e);
+    if (r >= rowsPad) return;
+    uint4 *q = reinterpret_cast<uint4 *>(Q + r * Kp + k0);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const float *w = v + 16 * c;
+        uint4 out;
+        out.x = e4m3_word(w[0] * inv, w[1] * inv, w[2] * inv, w[3] * inv);
+        out.y = e4m3_word(w[4] * inv, w[5] * inv, w[6] * inv, w[7] * inv);
+        out.z = e4m3_word(w[8] * inv, w[9] * inv, w[10] * inv, w[11] * inv);
+        out.w = e4m3_word(w[12] * inv, w[13] * inv, w[14] * inv, w[15] * inv);
+        q[c] = out;
+    }
+    E[r * nb + blk] = e;
+}
+
+// Load one 128-block of a ROWS x 128 code tile into registers: 16-byte
+// chunks, eight per row.
+template <int CH>
+__device__ __forceinline__ void fp8_load_block(const uint8_t *__restrict__ base, int64_t Kp,
+                                               int64_t blk, int t, u4_t (&r)[CH]) {
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+        const int idx = t + c * 256, row = idx >> 3, part = idx & 7;
+        r[c] = *reinterpret_cast<const u4_t *>(base + row * Kp + blk * 128 + part * 16);
+    }
+}
+
+template <int CH, int LDK>
+__device__ __forceinline__ void fp8_store_block(uint8_t *s, int t, const u4_t (&r)[CH]) {
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+        const int idx = t + c * 256, row = idx >> 3, part = idx & 7;
+        *reinterpret_cast<u4_t *>(s + row * LDK + part * 16) = r[c];
+    }
+}
+
+// One 128-block on the matrix cores: each wave's FM x FN fragments.  sE holds
+// the biased block exponents of the tile's A rows, then of its B rows.
+template <int FM, int FN, int WTM, int WTN, int LDK, int BM>
+__device__ __forceinline__ void fp8_mma_block(const uint8_t *sA, const uint8_t *sB,
+                                              const int32_t *sE, int wm, int wn, int lane,
+                                              int kc, f4_t (&acc)[FM][FN]) {
+    i8_t a[FM], b[FN];
+    int sa[FM], sb[FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i) {
+        const int r = wm * WTM + i * 16 + (lane & 15);
+        a[i] = *reinterpret_cast<const i8_t *>(sA + r * LDK + kc);
+        sa[i] = sE[r];
+    }
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+        const int r = wn * WTN + j * 16 + (lane & 15);
+        b[j] = *reinterpret_cast<const i8_t *>(sB + r * LDK + kc);
+        sb[j] = sE[BM + r];
+    }
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a[i], b[j], acc[i][j], 0,
+                                                                         0, 0, sa[i], 0, sb[j]);
+}
+
 // C tile BM x BN, 4 waves as 2 x 2, each wave (BM/2) x (BN/2) in 16x16 fragments.
 template <int BM, int BN>
 __global__ __launch_bounds__(256) void fp8_gemm_kernel(const uint8_t *__restrict__ QA,
@@ -90,61 +200,76 @@ __global__ __launch_bounds__(256) void fp8_gemm_kernel(const uint8_t *__restrict
                                                        int tilesM, int tilesN) {
     constexpr int WTM = BM / 2, WTN = BN / 2, FM = WTM / 16, FN = WTN / 16;
     constexpr int LDK = 128 + 16;            // bytes per LDS row (16-byte pad)
-    __shared__ __align__(16) uint8_t sA[BM * LDK];
-    __shared__ __align__(16) uint8_t sB[BN * LDK];
-    __shared__ int32_t sEA[BM], sEB[BN];
+    constexpr int CA = BM * 8 / 256, CB = BN * 8 / 256;   // 16-byte chunks per thread
+    __shared__ __align__(16) uint8_t sA[2][BM * LDK];
+    __shared__ __align__(16) uint8_t sB[2][BN * LDK];
+    __shared__ int32_t sE[2][BM + BN];
+    static_assert(BM + BN <= 256 && 256 % (BM + BN) == 0, "one scale per thread");
 
     const int64_t nb = (K + 127) / 128;
     const int64_t Kp = nb * 128;
-    const int bid = blockIdx.x;
-    const int tm = bid % tilesM, tn = bid / tilesM;
+    int tm, tn;
+    tile_coords(xcd_remap(blockIdx.x, gridDim.x), tilesM, tilesN, tm, tn);
     const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6, wm = w >> 1, wn = w & 1;
 
+    // Rows are padded to a multiple of 128 in both operands, so every tile
+    // row exists in the quantised buffers.
+    const uint8_t *pa = QA + m0 * Kp, *pb = QB + n0 * Kp;
     f4_t acc[FM][FN];
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int j = 0; j < FN; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
 
-    for (int64_t blk = 0; blk < nb; ++blk) {
-        // stage the 128-wide block of both operands (rows are padded to 128)
-        for (int c = t; c < BM * 8; c += 256) {
-            const int r = c >> 3, part = c & 7;
-            const uint4 v = *reinterpret_cast<const uint4 *>(QA + (m0 + r) * Kp + blk * 128 + part * 16);
-            *reinterpret_cast<uint4 *>(sA + r * LDK + part * 16) = v;
-        }
-        for (int c = t; c < BN * 8; c += 256) {
-            const int r = c >> 3, part = c & 7;
-            const uint4 v = *reinterpret_cast<const uint4 *>(QB + (n0 + r) * Kp + blk * 128 + part * 16);
-            *reinterpret_cast<uint4 *>(sB + r * LDK + part * 16) = v;
-        }
-        for (int r = t; r < BM; r += 256) sEA[r] = EA[(m0 + r) * nb + blk];
-        for (int r = t; r < BN; r += 256) sEB[r] = EB[(n0 + r) * nb + blk];
-        __syncthreads();
-        i8_t a[FM], b[FN];
-        int sa[FM], sb[FN];
-        const int kc = 32 * (lane >> 4);
+    // C_in of this lane's outputs, loaded now so that its latency hides
+    // behind the K loop (each output belongs to one tile only).  Positions
+    // past M or N are neither read nor written.
+    float cin[FN][FM][4];
 #pragma unroll
-        for (int i = 0; i < FM; ++i) {
-            const int r = wm * WTM + i * 16 + (lane & 15);
-            a[i] = *reinterpret_cast<const i8_t *>(sA + r * LDK + kc);
-            sa[i] = sEA[r] + 127;
-        }
-#pragma unroll
-        for (int j = 0; j < FN; ++j) {
-            const int r = wn * WTN + j * 16 + (lane & 15);
-            b[j] = *reinterpret_cast<const i8_t *>(sB + r * LDK + kc);
-            sb[j] = sEB[r] + 127;
-        }
+    for (int j = 0; j < FN; ++j) {
+        const int64_t n = n0 + wn * WTN + j * 16 + (lane & 15);
+        const int64_t ocn = n < N ? offCN[n] : 0;
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
-            for (int j = 0; j < FN; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
-                    a[i], b[j], acc[i][j], 0, 0, 0, sa[i], 0, sb[j]);
+            for (int v = 0; v < 4; ++v) {
+                const int64_t m = m0 + wm * WTM + i * 16 + 4 * (lane >> 4) + v;
+                cin[j][i][v] = (n < N && m < M) ? C[offCM[m] + ocn] : 0.f;
+            }
+    }
+    // Thread t carries the scale of tile row t mod (BM + BN) (A rows, then B
+    // rows; with fewer rows than threads, two threads carry the same one).
+    const int sidx = t % (BM + BN);
+    const int32_t *ex = sidx < BM ? EA + (m0 + sidx) * nb : EB + (n0 + sidx - BM) * nb;
+    // The next block's codes load into registers while the current block
+    // runs on the matrix cores; the last block reloads itself (a valid
+    // address, never stored).
+    u4_t ra[CA], rb[CB];
+    fp8_load_block<CA>(pa, Kp, 0, t, ra);
+    fp8_load_block<CB>(pb, Kp, 0, t, rb);
+    int32_t xs = ex[0];
+    fp8_store_block<CA, LDK>(sA[0], t, ra);
+    fp8_store_block<CB, LDK>(sB[0], t, rb);
+    sE[0][sidx] = xs + 127;      // E8M0 bias
+    __syncthreads();
+    const int kc = 32 * (lane >> 4);
+    for (int64_t blk = 0; blk < nb; ++blk) {
+        const int cur = static_cast<int>(blk & 1);
+        const int64_t nxt = blk + 1 < nb ? blk + 1 : blk;
+        fp8_load_block<CA>(pa, Kp, nxt, t, ra);
+        fp8_load_block<CB>(pb, Kp, nxt, t, rb);
+        xs = ex[nxt];
+        fp8_mma_block<FM, FN, WTM, WTN, LDK, BM>(sA[cur], sB[cur], sE[cur], wm, wn, lane, kc, acc);
+        // Keep the stores (which wait for the loads just issued) after the
+        // MFMAs, so the loads land while the matrix cores run.
+        __builtin_amdgcn_sched_barrier(0);
+        fp8_store_block<CA, LDK>(sA[cur ^ 1], t, ra);
+        fp8_store_block<CB, LDK>(sB[cur ^ 1], t, rb);
+        sE[cur ^ 1][sidx] = xs + 127;
         __syncthreads();
     }
+    // C_in was loaded before the K loop: add and store.
 #pragma unroll
     for (int j = 0; j < FN; ++j) {
         const int64_t n = n0 + wn * WTN + j * 16 + (lane & 15);
@@ -155,22 +280,25 @@ __global__ __launch_bounds__(256) void fp8_gemm_kernel(const uint8_t *__restrict
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int64_t m = m0 + wm * WTM + i * 16 + 4 * (lane >> 4) + v;
-                if (m >= M) continue;
-                const int64_t off = offCM[m] + ocn;
-                C[off] = C[off] + acc[i][j][v];
+                if (m < M) C[offCM[m] + ocn] = cin[j][i][v] + acc[i][j][v];
             }
     }
 }
 
 int launch_fp8_quant(const float *X, const int64_t *offR, int64_t rows, int64_t rowsPad,
-                     const int64_t *offK, int64_t K, uint8_t *Q, int32_t *E, hipStream_t s) {
+                     const int64_t *offK, int64_t K, bool rowsFast, uint8_t *Q, int32_t *E,
+                     hipStream_t s) {
     const int64_t nb = (K + 127) / 128;
-    const int64_t tasks = rowsPad * nb;
+    const int64_t tasks = rowsFast ? (rowsPad + 63) / 64 * nb : rowsPad * nb;
     const int64_t blocks = (tasks + 3) / 4;
     if (blocks > INT32_MAX) return GETT_ERR_INTERNAL;
     (void)hipGetLastError();   // clear a stale error left by other HIP users
-    hipLaunchKernelGGL(fp8_quant_kernel, dim3((unsigned)blocks), dim3(256), 0, s, X, offR, rows,
-                       rowsPad, offK, K, Q, E);
+    if (rowsFast)
+        hipLaunchKernelGGL(fp8_quant_rows_kernel, dim3((unsigned)blocks), dim3(256), 0, s, X, offR,
+                           rows, rowsPad, offK, K, Q, E);
+    else
+        hipLaunchKernelGGL(fp8_quant_kernel, dim3((unsigned)blocks), dim3(256), 0, s, X, offR, rows,
+                           rowsPad, offK, K, Q, E);
     return launch_status();
 }
 

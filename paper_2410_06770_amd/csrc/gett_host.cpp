@@ -294,11 +294,25 @@ struct Fp8Plan {
     int64_t M = 0, N = 0, K = 0, nb = 0, Kp = 0;
     int64_t *d_tab = nullptr;  // rowsA [M], kA [K], rowsB [N], kB [K], offCM [M], offCN [N]
     int tile = 3;
+    bool aRowsFast = false, bRowsFast = false;   // quantisation loader per operand
+    bool swapped = false;      // the GEMM's first operand is B
     ~Fp8Plan() {
         if (d_tab) (void)hipFree(d_tab);
     }
 };
 static std::unordered_map<std::string, std::unique_ptr<Fp8Plan>> g_fp8;
+
+// Whether an operand's rows are cheaper to walk in memory than its
+// contracted positions: smallest |increment| among row modes below that among
+// contracted modes (slot = the operand's increment slot in the K groups).
+static bool rows_fast(const std::vector<GMode> &rows, const std::vector<GMode> &k, int slot) {
+    int64_t r = INT64_MAX, c = INT64_MAX;
+    for (auto &x : rows)
+        if (x.ext > 1) r = std::min<int64_t>(r, std::llabs(x.i0));
+    for (auto &x : k)
+        if (x.ext > 1) c = std::min<int64_t>(c, std::llabs(slot ? x.i1 : x.i0));
+    return r < c;
+}
 
 static int get_fp8_plan(const Args &a, int dev, Fp8Plan **out) {
     const std::string key = signature_key(a, kFP8, dev, -7);
@@ -313,6 +327,25 @@ static int get_fp8_plan(const Args &a, int dev, Fp8Plan **out) {
     std::vector<GMode> ra, rb, k;
     canonical_groups(a, ra, rb, k);
     auto pl = std::make_unique<Fp8Plan>();
+    // The GEMM's lanes run along N in the epilogue: when C's cheapest mode is
+    // one of A's free modes, exchange the operands (the block scales are per
+    // row of each operand either way, so the quantised model is unchanged).
+    auto min_inc = [](const std::vector<GMode> &g, int slot) {
+        int64_t m = INT64_MAX;
+        for (auto &x : g)
+            if (x.ext > 1) m = std::min<int64_t>(m, std::llabs(slot ? x.i1 : x.i0));
+        return m;
+    };
+    if (min_inc(ra, 1) < min_inc(rb, 1)) {
+        std::swap(ra, rb);
+        for (auto &x : k) std::swap(x.i0, x.i1);
+        pl->swapped = true;
+    }
+    // N positions in order of increasing C increment, so that the lanes of
+    // the epilogue (neighbouring N positions) write neighbouring outputs.
+    std::stable_sort(rb.begin(), rb.end(), [](const GMode &x, const GMode &y) {
+        return std::llabs(x.i1) < std::llabs(y.i1);
+    });
     auto size = [](const std::vector<GMode> &g) {
         int64_t s = 1;
         for (auto &x : g) s *= x.ext;
@@ -338,6 +371,8 @@ static int get_fp8_plan(const Args &a, int dev, Fp8Plan **out) {
         return GETT_ERR_HIP;
     const int64_t tilesBig = ((pl->M + 127) / 128) * ((pl->N + 127) / 128);
     pl->tile = tilesBig >= 256 ? 3 : 0;
+    pl->aRowsFast = rows_fast(ra, k, 0);
+    pl->bRowsFast = rows_fast(rb, k, 1);
     std::lock_guard<std::mutex> lk(g_mu);
     auto &slot = g_fp8[key];
     if (!slot) slot = std::move(pl);
@@ -360,8 +395,9 @@ static int run_fp8(const Args &a, const float *A, const float *B, float *C, hipS
     uint8_t *QB = QA + (size_t)Mq * Kp;
     int32_t *EA = reinterpret_cast<int32_t *>(QB + (size_t)Nq * Kp);
     int32_t *EB = EA + (size_t)Mq * nb;
-    rc = launch_fp8_quant(A, rowsA, M, Mq, kA, K, QA, EA, s);
-    if (!rc) rc = launch_fp8_quant(B, rowsB, N, Nq, kB, K, QB, EB, s);
+    const float *X0 = pl->swapped ? B : A, *X1 = pl->swapped ? A : B;
+    rc = launch_fp8_quant(X0, rowsA, M, Mq, kA, K, pl->aRowsFast, QA, EA, s);
+    if (!rc) rc = launch_fp8_quant(X1, rowsB, N, Nq, kB, K, pl->bRowsFast, QB, EB, s);
     if (!rc) rc = launch_fp8_gemm(pl->tile, QA, EA, QB, EB, C, offCM, offCN, M, N, K, s);
     if (hipFreeAsync(ws, s) != hipSuccess && !rc) rc = GETT_ERR_HIP;
     return rc;
@@ -905,7 +941,7 @@ int sgett_fp8_quantize(int64_t rankx, const int64_t *extx, const int64_t *incx, 
         return GETT_ERR_ALLOC;
     if (hipMemcpyAsync(d, h.data(), h.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess)
         return GETT_ERR_HIP;
-    rc = launch_fp8_quant(X, d, R, R, d + R, K, QX, EX, s);
+    rc = launch_fp8_quant(X, d, R, R, d + R, K, rows_fast(rows, kk, 0), QX, EX, s);
     (void)hipFreeAsync(d, s);
     // h must outlive the copy: wait for it
     if (hipStreamSynchronize(s) != hipSuccess && !rc) rc = GETT_ERR_HIP;
