@@ -83,7 +83,10 @@ extern "C" {
 #define GETT_BF16X3 2
 #define GETT_FP8    3
 
-/* Schedule policies (gett_set_policy). */
+/* Schedule policies (gett_set_policy).  Environment: GETT_POLICY =
+   heuristic | predict | autotune sets the initial policy; GETT_MODEL names a
+   predictor weights file loaded on the first prediction when none was loaded
+   with gett_load_predictor; GETT_LOG=1 prints each new plan to stderr. */
 #define GETT_HEURISTIC 0   /* built-in rules (default) */
 #define GETT_PREDICT   1   /* MLP schedule predictor (gett_load_predictor) */
 #define GETT_AUTOTUNE  2   /* time the whole schedule menu on a plan-cache miss */

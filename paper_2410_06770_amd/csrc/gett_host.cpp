@@ -26,7 +26,16 @@ namespace gett {
 // ---------------------------------------------------------------------------
 static thread_local hipStream_t t_stream = nullptr;
 static thread_local int64_t t_last_schedule = -1;
-static std::atomic<int> g_policy{GETT_HEURISTIC};
+// Initial policy from GETT_POLICY (heuristic | predict | autotune); the
+// C-ABI setter overrides it.
+static int policy_from_env() {
+    const char *e = getenv("GETT_POLICY");
+    if (!e) return GETT_HEURISTIC;
+    if (strcmp(e, "predict") == 0) return GETT_PREDICT;
+    if (strcmp(e, "autotune") == 0) return GETT_AUTOTUNE;
+    return GETT_HEURISTIC;
+}
+static std::atomic<int> g_policy{policy_from_env()};
 static std::atomic<int64_t> g_forced{-1};
 static std::mutex g_mu;   // guards the caches below
 
@@ -480,6 +489,19 @@ static int load_predictor(const char *path) {
 // Run the network on one feature vector with the library's own kernels and
 // return the best valid joint schedule under the summed log-probabilities.
 static bool predict(int prec, const Args &a, int64_t K, Sched *out) {
+    // Without a loaded network, GETT_MODEL names the weights file to load
+    // (once, on the first prediction).
+    static std::once_flag env_model;
+    std::call_once(env_model, [] {
+        const char *m = getenv("GETT_MODEL");
+        bool have;
+        {
+            std::lock_guard<std::mutex> lk(g_pred_mu);
+            have = g_pred != nullptr;
+        }
+        if (m && !have && load_predictor(m) != 0 && g_log)
+            fprintf(stderr, "[gett] GETT_MODEL=%s could not be loaded\n", m);
+    });
     std::lock_guard<std::mutex> lk(g_pred_mu);
     Predictor *pr = g_pred.get();
     if (!pr) return false;

@@ -114,3 +114,17 @@ def test_batch_validation():
     assert rc == -1000 - 10
     assert gett.sgett_batch(1, 7, [2], [[1]], [[1]], [8], [2], [[1]], [[1]], [8], [1], [[0]],
                             [[0]], [[0, 1]], [[1, 1]], [8]) == -2
+
+
+@pytest.mark.parametrize("value,want", [("predict", 1), ("autotune", 2), ("heuristic", 0),
+                                        ("unknown", 0)])
+def test_policy_from_environment(value, want):
+    """GETT_POLICY sets the initial schedule policy (fresh process, no GPU)."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = "from paper_2410_06770_amd import gett; print(gett.gett_get_policy())"
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True,
+                       env=dict(os.environ, GETT_POLICY=value), timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert int(r.stdout.strip().splitlines()[-1]) == want
