@@ -11,7 +11,9 @@ Inputs are resident in HBM before the timed region starts.
 One step = one xGETT call of the primary path (DGETT, FP64).  The same
 workload also runs through SGETT (FP32 MFMA), split BF16x3 SGETT and FP8
 SGETT; their rates and errors against the FP64 oracle (on a sample of
-outputs) are reported under "paths".  Kernel durations come from HIP events
+outputs) are reported under "paths".  A last leg runs the uneven batch of 512
+problems through split BF16x3 as one replay of the captured batch graph and
+as 512 separate calls ("batch").  Kernel durations come from HIP events
 recorded on the library's stream around every call.
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3]
@@ -44,6 +46,8 @@ def parse():
                     help="schedule choice on the first call (autotune times the whole menu "
                          "before the timed region)")
     ap.add_argument("--schedule", type=int, default=-1, help="force one schedule id")
+    ap.add_argument("--batch", type=int, default=512,
+                    help="problems in the batched leg (graph replay vs separate calls); 0 skips")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--traffic-json", default="profiles/traffic.json",
@@ -158,6 +162,8 @@ def main():
     if "f32" in results and "bf16x3" in results:
         results["bf16x3"]["speedup_vs_f32"] = round(results["f32"]["ms"] / results["bf16x3"]["ms"], 3)
 
+    batch = batch_leg(args.batch, gett, W, torch, stream) if args.batch > 0 else None
+
     path, ms, tflops, peak, wall = primary
     out = {
         "metric": METRIC,
@@ -182,23 +188,89 @@ def main():
                      "traffic": load_traffic(args.traffic_json, path, results[path]["schedule"])},
         "paths": results,
     }
+    if batch is not None:
+        out["batch"] = batch
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pr64, args.cpu_seconds, flops)
     print(json.dumps(out))
 
 
+def batch_leg(count, gett, W, torch, stream, reps=10):
+    """The uneven batch workload through split BF16x3: one replay of the
+    captured batch graph against the same problems as separate sgett_bf16x3
+    calls (both with the heuristic schedule; the batch always runs the 64x64
+    tile).  Inputs resident; HIP events on the library's stream."""
+    problems = W.config_batch(count)
+    keep, args = [], []
+    for pr in problems:
+        ts = []
+        ptr = []
+        for v in (pr.A, pr.B, pr.C):
+            t = torch.from_numpy(v.buf).to("cuda")
+            ts.append(t)
+            ptr.append(t.data_ptr() + v.base * t.element_size())
+        keep.append(ts)
+        args.append(ptr)
+    flops = float(sum(2.0 * np.prod(pr.mnk()) for pr in problems))
+    gett.gett_set_schedule(-1)
+    gett.gett_set_policy(gett.GETT_HEURISTIC)
+    info = [0] * count
+
+    def run_batch():
+        rc = gett.sgett_batch(count, gett.GETT_BF16X3, [p.ranka for p in problems],
+                              [p.exta for p in problems], [p.inca for p in problems],
+                              [a[0] for a in args], [p.rankb for p in problems],
+                              [p.extb for p in problems], [p.incb for p in problems],
+                              [a[1] for a in args], [p.conts for p in problems],
+                              [p.conta for p in problems], [p.contb for p in problems],
+                              [p.perm for p in problems], [p.incc for p in problems],
+                              [a[2] for a in args], info)
+        if rc:
+            raise RuntimeError(f"sgett_batch: {rc}")
+
+    def run_separate():
+        for pr, (a, b, c) in zip(problems, args):
+            rc = gett.sgett_bf16x3(pr.ranka, pr.exta, pr.inca, a, pr.rankb, pr.extb, pr.incb, b,
+                                   pr.conts, pr.conta, pr.contb, pr.perm, pr.incc, c)
+            if rc:
+                raise RuntimeError(f"sgett_bf16x3: {gett.strerror(rc)}")
+
+    def timed(fn, n):
+        fn()                       # plans, tables and the graph are built here
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(n + 1)]
+        ev[0].record(stream)
+        for i in range(n):
+            fn()
+            ev[i + 1].record(stream)
+        torch.cuda.synchronize()
+        return float(np.mean([ev[i].elapsed_time(ev[i + 1]) for i in range(n)]))
+
+    print(f"[bench] batch of {count}: graph replays", file=sys.stderr, flush=True)
+    g_ms = timed(run_batch, reps)
+    print(f"[bench] batch of {count}: separate calls", file=sys.stderr, flush=True)
+    s_ms = timed(run_separate, max(2, reps // 3))
+    del keep
+    torch.cuda.empty_cache()
+    return {"problems": count, "path": "bf16x3", "flops": flops,
+            "graph_ms": round(g_ms, 4), "graph_tflops": round(flops / (g_ms * 1e-3) / 1e12, 3),
+            "separate_ms": round(s_ms, 4),
+            "separate_tflops": round(flops / (s_ms * 1e-3) / 1e12, 3),
+            "speedup": round(s_ms / g_ms, 3)}
+
+
 def load_traffic(path, prec_path, schedule):
     """HBM bytes per launch of the timed kernel, from the rocprofv3 counter
     runs summarised in profiles/ (FETCH_SIZE and WRITE_SIZE scaled by the
-    same counters on a plain copy of known size); None when they were taken
-    for another schedule or are missing."""
+    same counters on a plain copy of known size), kept per schedule; None
+    when this schedule was not measured or the kernel sources changed since."""
     try:
         with open(path) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    e = t.get(prec_path)
-    if not e or e.get("schedule") != schedule or e.get("kernel_source_hash") != kernel_hash():
+    e = (t.get(prec_path) or {}).get("by_schedule", {}).get(str(schedule))
+    if not e or e.get("kernel_source_hash") != kernel_hash():
         return None
     return {"read_bytes": e["read_bytes"], "write_bytes": e["write_bytes"],
             "algorithmic_bytes": e["algorithmic_bytes"], "unit": "bytes/launch"}
@@ -209,7 +281,7 @@ def kernel_hash():
     h = hashlib.sha256()
     src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2410_06770_amd", "csrc")
     for name in sorted(os.listdir(src)):
-        if name.startswith("gett_tile"):
+        if name.startswith(("gett_tile", "gett_grid")) or name == "gett_internal.h":
             with open(os.path.join(src, name), "rb") as f:
                 h.update(f.read())
     return h.hexdigest()[:16]

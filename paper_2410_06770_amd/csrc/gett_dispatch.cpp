@@ -21,7 +21,9 @@ const char *last_hip_error_name() {
     int launch_splitk_reduce_##SUFFIX(const TileParams &p, hipStream_t s);                        \
     int batch_grid_size_##SUFFIX();                                                                \
     int launch_batch_##SUFFIX(const BatchProblem *d, const int32_t *it, int32_t n, int32_t g,      \
-                              hipStream_t s);
+                              hipStream_t s);                                                      \
+    int launch_batch_reduce_##SUFFIX(const BatchProblem *d, const int32_t *l, int32_t n,           \
+                                     hipStream_t s);
 GETT_DECLARE_PRECISION(f64)
 GETT_DECLARE_PRECISION(f32)
 GETT_DECLARE_PRECISION(bf3)
@@ -60,6 +62,16 @@ int launch_batch(int prec, const BatchProblem *d_probs, int32_t nprobs, const in
     case kF64: return launch_batch_f64(d_probs, d_items, nitems, grid, s);
     case kF32: return launch_batch_f32(d_probs, d_items, nitems, grid, s);
     case kBF3: return launch_batch_bf3(d_probs, d_items, nitems, grid, s);
+    default: return GETT_ERR_INTERNAL;
+    }
+}
+
+int launch_batch_reduce(int prec, const BatchProblem *d_probs, const int32_t *d_list, int32_t n,
+                        hipStream_t s) {
+    switch (prec) {
+    case kF64: return launch_batch_reduce_f64(d_probs, d_list, n, s);
+    case kF32: return launch_batch_reduce_f32(d_probs, d_list, n, s);
+    case kBF3: return launch_batch_reduce_bf3(d_probs, d_list, n, s);
     default: return GETT_ERR_INTERNAL;
     }
 }

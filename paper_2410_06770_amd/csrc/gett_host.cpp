@@ -732,29 +732,45 @@ static int run(int prec, const Args &a, const void *A, const void *B, void *C) {
 // Batches
 // ---------------------------------------------------------------------------
 struct BatchGraph {
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    BatchProblem *h_desc = nullptr;   // pinned host descriptors (copied by the graph)
+    // Two instances of the graph, each copying its own pinned descriptor
+    // buffer: the host fills one while the GPU may still be running the
+    // replay that copied the other.
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    BatchProblem *h_desc[2] = {nullptr, nullptr};   // pinned host descriptors
+    hipEvent_t done[2] = {nullptr, nullptr};         // replay of instance b finished
+    int next = 0;                                    // instance of the next replay
     BatchProblem *d_desc = nullptr;
     int32_t *d_items = nullptr;
     int32_t nprobs = 0, nitems = 0;
-    hipEvent_t done = nullptr;
     std::vector<Plan *> plans;
+    // Problems cut along K: slice count, slice length and workspace offset
+    // (doubles) per problem (splits 1: not cut), the list of cut problems on
+    // the device and their FP64 partial-sum workspace.
+    std::vector<int32_t> splits;
+    std::vector<int64_t> kper, ws_off;
+    int32_t *d_split = nullptr;
+    double *d_ws = nullptr;
+    std::mutex mu;             // one caller at a time rewrites and launches
     ~BatchGraph() {
-        if (exec) (void)hipGraphExecDestroy(exec);
-        if (graph) (void)hipGraphDestroy(graph);
-        if (h_desc) (void)hipHostFree(h_desc);
+        for (int b = 0; b < 2; ++b) {
+            if (exec[b]) (void)hipGraphExecDestroy(exec[b]);
+            if (graph[b]) (void)hipGraphDestroy(graph[b]);
+            if (h_desc[b]) (void)hipHostFree(h_desc[b]);
+            if (done[b]) (void)hipEventDestroy(done[b]);
+        }
         if (d_desc) (void)hipFree(d_desc);
         if (d_items) (void)hipFree(d_items);
-        if (done) (void)hipEventDestroy(done);
+        if (d_split) (void)hipFree(d_split);
+        if (d_ws) (void)hipFree(d_ws);
     }
 };
 static std::unordered_map<std::string, std::unique_ptr<BatchGraph>> g_graphs;
 
-// Run a batch: per-problem plans with the batch tile (64x64 of the precision,
-// no split), one work list ordered longest contraction first, and a graph of
-// {descriptor copy, persistent kernel} captured once per batch signature and
-// replayed.  Pointers may change between calls: the descriptors are rewritten
+// Run a batch: per-problem plans with the batch tile (64x64 of the precision),
+// problems with long contractions cut along K, one work list ordered longest
+// item first, and a graph of {descriptor copy, persistent kernel, reduction
+// of the cut problems} captured once per batch signature and replayed.  Pointers may change between calls: the descriptors are rewritten
 // in pinned memory (after the previous replay has finished) before each
 // replay, and the graph's copy node moves them to the device.
 static int run_batch(int prec, int64_t count, const Args *args, const void *const *A,
@@ -766,8 +782,11 @@ static int run_batch(int prec, int64_t count, const Args *args, const void *cons
     key.append(reinterpret_cast<const char *>(&dev), sizeof dev);
     std::vector<char> live(count, 0);
     for (int64_t i = 0; i < count; ++i) {
-        Canon c = canonicalise(args[i], 0, 64);
-        live[i] = !(c.empty || c.M == 0 || c.N == 0 || c.K == 0);
+        // a problem with a zero extent anywhere has nothing to compute
+        bool nz = true;
+        for (int64_t j = 0; j < args[i].ranka; ++j) nz = nz && args[i].exta[j] != 0;
+        for (int64_t j = 0; j < args[i].rankb; ++j) nz = nz && args[i].extb[j] != 0;
+        live[i] = nz;
         key += signature_key(args[i], prec, live[i], 0);
     }
     BatchGraph *bg = nullptr;
@@ -779,8 +798,17 @@ static int run_batch(int prec, int64_t count, const Args *args, const void *cons
     if (!bg) {
         auto nb = std::make_unique<BatchGraph>();
         nb->plans.assign(count, nullptr);
-        struct Work { int64_t K; int32_t prob, ntiles; };
-        std::vector<Work> work;
+        nb->splits.assign(count, 1);
+        nb->kper.assign(count, 0);
+        nb->ws_off.assign(count, 0);
+        const int bk = kTiles[prec][0].bk;
+        const int grid_max = std::max(batch_grid_size(prec), 1);
+        // Work in K steps per problem; a problem whose tiles would each take
+        // more steps than the average workgroup's share (at least 64) is cut
+        // along K into slices of about that length, so no single item holds
+        // up the whole launch.  Slices write FP64 partials that a reduction
+        // kernel in the same graph adds to C_in in slice order.
+        int64_t total = 0;
         for (int64_t i = 0; i < count; ++i) {
             if (!live[i]) continue;
             Plan *pl = nullptr;
@@ -788,66 +816,120 @@ static int run_batch(int prec, int64_t count, const Args *args, const void *cons
             if (rc) return rc;
             nb->plans[i] = pl;
             TileParams p = make_params(*pl, nullptr, nullptr, nullptr);
-            work.push_back({p.K, (int32_t)i, p.tilesM * p.tilesN});
+            total += (int64_t)p.tilesM * p.tilesN * ((p.K + bk - 1) / bk);
+        }
+        const int64_t cap = std::max<int64_t>(64, (total + grid_max - 1) / grid_max);
+        struct Work { int64_t len; int32_t prob, nitems; };
+        std::vector<Work> work;
+        std::vector<int32_t> cut;
+        int64_t ws_total = 0;
+        for (int64_t i = 0; i < count; ++i) {
+            if (!nb->plans[i]) continue;
+            TileParams p = make_params(*nb->plans[i], nullptr, nullptr, nullptr);
+            const int64_t steps = (p.K + bk - 1) / bk;
+            int64_t S = 1, per = steps * bk;
+            if (steps > cap) {
+                S = (steps + cap - 1) / cap;
+                per = (steps + S - 1) / S * bk;
+                S = (p.K + per - 1) / per;      // every slice starts below K
+            }
+            const int64_t items = (int64_t)p.tilesM * p.tilesN * S;
+            if (items > INT32_MAX / 2) return GETT_ERR_INTERNAL;
+            if (S > 1) {
+                nb->splits[i] = (int32_t)S;
+                nb->kper[i] = per;
+                nb->ws_off[i] = ws_total;
+                ws_total += S * p.M * p.N;
+                cut.push_back((int32_t)i);
+            }
+            work.push_back({S > 1 ? per : p.K, (int32_t)i, (int32_t)items});
         }
         std::stable_sort(work.begin(), work.end(),
-                         [](const Work &a, const Work &b) { return a.K > b.K; });
+                         [](const Work &a, const Work &b) { return a.len > b.len; });
         std::vector<int32_t> items;
         for (auto &w : work)
-            for (int32_t t = 0; t < w.ntiles; ++t) {
+            for (int32_t t = 0; t < w.nitems; ++t) {
                 items.push_back(w.prob);
                 items.push_back(t);
             }
+        if (ws_total > 0 &&
+            (hipMalloc(reinterpret_cast<void **>(&nb->d_ws), ws_total * sizeof(double)) !=
+                 hipSuccess ||
+             hipMalloc(reinterpret_cast<void **>(&nb->d_split), cut.size() * sizeof(int32_t)) !=
+                 hipSuccess))
+            return GETT_ERR_ALLOC;
+        if (!cut.empty() && hipMemcpy(nb->d_split, cut.data(), cut.size() * sizeof(int32_t),
+                                      hipMemcpyHostToDevice) != hipSuccess)
+            return GETT_ERR_HIP;
         nb->nprobs = (int32_t)count;
         nb->nitems = (int32_t)(items.size() / 2);
         const size_t dbytes = sizeof(BatchProblem) * std::max<int64_t>(count, 1);
-        if (hipHostMalloc(reinterpret_cast<void **>(&nb->h_desc), dbytes, hipHostMallocDefault) !=
-                hipSuccess ||
-            hipMalloc(reinterpret_cast<void **>(&nb->d_desc), dbytes) != hipSuccess ||
+        if (hipMalloc(reinterpret_cast<void **>(&nb->d_desc), dbytes) != hipSuccess ||
             hipMalloc(reinterpret_cast<void **>(&nb->d_items),
                       std::max<size_t>(items.size(), 2) * sizeof(int32_t)) != hipSuccess)
             return GETT_ERR_ALLOC;
-        memset(nb->h_desc, 0, dbytes);
         if (!items.empty() &&
             hipMemcpy(nb->d_items, items.data(), items.size() * sizeof(int32_t),
                       hipMemcpyHostToDevice) != hipSuccess)
             return GETT_ERR_HIP;
-        if (hipEventCreateWithFlags(&nb->done, hipEventDisableTiming) != hipSuccess)
-            return GETT_ERR_HIP;
-        const int grid = std::min<int64_t>(std::max(batch_grid_size(prec), 1),
-                                           std::max<int32_t>(nb->nitems, 1));
-        hipStream_t cs;
-        if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return GETT_ERR_HIP;
-        int rc = 0;
-        if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) rc = GETT_ERR_HIP;
-        if (!rc && hipMemcpyAsync(nb->d_desc, nb->h_desc, dbytes, hipMemcpyHostToDevice, cs) !=
-                       hipSuccess)
-            rc = GETT_ERR_HIP;
-        if (!rc && nb->nitems > 0)
-            rc = launch_batch(prec, nb->d_desc, nb->nprobs, nb->d_items, nb->nitems, grid, cs);
-        hipGraph_t g = nullptr;
-        if (hipStreamEndCapture(cs, &g) != hipSuccess && !rc) rc = GETT_ERR_HIP;
-        nb->graph = g;
-        if (!rc && hipGraphInstantiate(&nb->exec, g, nullptr, nullptr, 0) != hipSuccess)
-            rc = GETT_ERR_HIP;
-        (void)hipStreamDestroy(cs);
-        if (rc) return rc;
+        const int grid = std::min<int64_t>(grid_max, std::max<int32_t>(nb->nitems, 1));
+        for (int b = 0; b < 2; ++b) {
+            if (hipHostMalloc(reinterpret_cast<void **>(&nb->h_desc[b]), dbytes,
+                              hipHostMallocDefault) != hipSuccess)
+                return GETT_ERR_ALLOC;
+            memset(nb->h_desc[b], 0, dbytes);
+            if (hipEventCreateWithFlags(&nb->done[b], hipEventDisableTiming) != hipSuccess)
+                return GETT_ERR_HIP;
+            hipStream_t cs;
+            if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
+                return GETT_ERR_HIP;
+            int rc = 0;
+            if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess)
+                rc = GETT_ERR_HIP;
+            if (!rc && hipMemcpyAsync(nb->d_desc, nb->h_desc[b], dbytes, hipMemcpyHostToDevice,
+                                      cs) != hipSuccess)
+                rc = GETT_ERR_HIP;
+            if (!rc && nb->nitems > 0)
+                rc = launch_batch(prec, nb->d_desc, nb->nprobs, nb->d_items, nb->nitems, grid, cs);
+            if (!rc && !cut.empty())
+                rc = launch_batch_reduce(prec, nb->d_desc, nb->d_split, (int32_t)cut.size(), cs);
+            hipGraph_t g = nullptr;
+            if (hipStreamEndCapture(cs, &g) != hipSuccess && !rc) rc = GETT_ERR_HIP;
+            nb->graph[b] = g;
+            if (!rc && hipGraphInstantiate(&nb->exec[b], g, nullptr, nullptr, 0) != hipSuccess)
+                rc = GETT_ERR_HIP;
+            (void)hipStreamDestroy(cs);
+            if (rc) return rc;
+        }
         std::lock_guard<std::mutex> lk(g_mu);
         auto &slot = g_graphs[key];
         if (!slot) slot = std::move(nb);
         bg = slot.get();
     }
-    // previous replay must have consumed the pinned descriptors
-    if (hipEventSynchronize(bg->done) != hipSuccess) return GETT_ERR_HIP;
+    // The replay that last used this instance's pinned descriptors (two
+    // replays ago) must have finished before they are rewritten.
+    std::lock_guard<std::mutex> lk(bg->mu);
+    const int b = bg->next;
+    bg->next ^= 1;
+    if (hipEventSynchronize(bg->done[b]) != hipSuccess) return GETT_ERR_HIP;
+    BatchProblem *h = bg->h_desc[b];
     for (int64_t i = 0; i < count; ++i) {
         if (!bg->plans[i]) continue;
         const Plan &pl = *bg->plans[i];
-        bg->h_desc[i].p = make_params(pl, A[i], B[i], C[i]);
-        bg->h_desc[i].aFastK = pl.tab->cn.aFastK;
-        bg->h_desc[i].bFastK = pl.tab->cn.bFastK;
+        h[i].p = make_params(pl, A[i], B[i], C[i]);
+        if (bg->splits[i] > 1) {
+            h[i].p.splits = bg->splits[i];
+            h[i].p.kPerSplit = bg->kper[i];
+            h[i].p.ws = bg->d_ws + bg->ws_off[i];
+        }
+        h[i].aFastK = pl.tab->cn.aFastK;
+        h[i].bFastK = pl.tab->cn.bFastK;
     }
-    if (hipGraphLaunch(bg->exec, s) != hipSuccess) return GETT_ERR_HIP;
-    if (hipEventRecord(bg->done, s) != hipSuccess) return GETT_ERR_HIP;
+    // Replays share the device descriptors and workspace: order this one
+    // after the previous replay even when the caller switched streams.
+    if (hipStreamWaitEvent(s, bg->done[b ^ 1], 0) != hipSuccess) return GETT_ERR_HIP;
+    if (hipGraphLaunch(bg->exec[b], s) != hipSuccess) return GETT_ERR_HIP;
+    if (hipEventRecord(bg->done[b], s) != hipSuccess) return GETT_ERR_HIP;
     return 0;
 }
 

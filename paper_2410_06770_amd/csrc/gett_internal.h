@@ -112,6 +112,10 @@ int launch_splitk_reduce(int prec, const TileParams &p, hipStream_t s);
 int launch_batch(int prec, const BatchProblem *d_probs, int32_t nprobs, const int32_t *d_items,
                  int32_t nitems, int32_t grid, hipStream_t s);
 int batch_grid_size(int prec);
+// C = C_in + sum of the FP64 slice partials for the listed batch problems
+// (those cut along K), reading their descriptors on the device.
+int launch_batch_reduce(int prec, const BatchProblem *d_probs, const int32_t *d_list, int32_t n,
+                        hipStream_t s);
 
 // FP8 path: quantisation into canonical K-contiguous rows and the GEMM on them.
 // rowsFast selects the loader whose lanes run along the rows (for operands

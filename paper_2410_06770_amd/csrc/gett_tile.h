@@ -443,8 +443,8 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(TileParams p) {
 }
 
 // ---------------------------------------------------------------------------
-// Batched launch: one persistent grid walks a work list of (problem, tile)
-// items, longest contraction first; every item runs the same tile code as a
+// Batched launch: one persistent grid walks a work list of (problem, tile,
+// K slice) items, longest first; every item runs the same tile code as a
 // single call with the 64x64 tile of the precision.  Each problem's
 // descriptor says which operands read along K, and a uniform switch picks the
 // matching compiled loader variant.
@@ -460,19 +460,48 @@ __global__ __launch_bounds__(kThreads) void gett_batch_kernel(const BatchProblem
         const int32_t tile = items[2 * it + 1];
         const BatchProblem &bp = probs[pi];
         const TileParams p = bp.p;
+        // A problem cut along K numbers its items slice-major: slice z covers
+        // [z kPerSplit, min(K, (z+1) kPerSplit)) and writes FP64 partials.
+        const int32_t tilesMN = p.tilesM * p.tilesN;
+        const int32_t split = tile / tilesMN;
         int tm, tn;
-        tile_coords(tile, p.tilesM, p.tilesN, tm, tn);
+        tile_coords(tile - split * tilesMN, p.tilesM, p.tilesN, tm, tn);
         const int64_t m0 = (int64_t)tm * ts.bm, n0 = (int64_t)tn * ts.bn;
+        const int64_t kbeg = (int64_t)split * p.kPerSplit;
+        const int64_t kend = min(p.K, kbeg + p.kPerSplit);
         const int variant = bp.aFastK * 2 + bp.bFastK;
         if (variant == 0)
-            gett_tile<PREC, ts.bm, ts.bn, ts.bk, false, false>(p, m0, n0, 0, p.K, 0, smem);
+            gett_tile<PREC, ts.bm, ts.bn, ts.bk, false, false>(p, m0, n0, kbeg, kend, split, smem);
         else if (variant == 1)
-            gett_tile<PREC, ts.bm, ts.bn, ts.bk, false, true>(p, m0, n0, 0, p.K, 0, smem);
+            gett_tile<PREC, ts.bm, ts.bn, ts.bk, false, true>(p, m0, n0, kbeg, kend, split, smem);
         else if (variant == 2)
-            gett_tile<PREC, ts.bm, ts.bn, ts.bk, true, false>(p, m0, n0, 0, p.K, 0, smem);
+            gett_tile<PREC, ts.bm, ts.bn, ts.bk, true, false>(p, m0, n0, kbeg, kend, split, smem);
         else
-            gett_tile<PREC, ts.bm, ts.bn, ts.bk, true, true>(p, m0, n0, 0, p.K, 0, smem);
+            gett_tile<PREC, ts.bm, ts.bn, ts.bk, true, true>(p, m0, n0, kbeg, kend, split, smem);
         __syncthreads();   // the next item reuses the LDS stages
+    }
+}
+
+// The batch's problems cut along K: C = C_in + sum of the slices' partials in
+// slice order, in FP64 (the descriptors are read on the device, so a graph
+// replay with new pointers reduces into the new C).
+template <int PREC>
+__global__ __launch_bounds__(256) void batch_reduce_kernel(const BatchProblem *__restrict__ probs,
+                                                           const int32_t *__restrict__ list,
+                                                           int32_t n) {
+    using T = typename PrecT<PREC>::T;
+    for (int32_t li = blockIdx.y; li < n; li += gridDim.y) {
+        const TileParams &p = probs[list[li]].p;
+        const int64_t MN = p.M * p.N;
+        T *Cp = static_cast<T *>(p.C);
+        for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < MN;
+             idx += (int64_t)gridDim.x * blockDim.x) {
+            const int64_t m = idx / p.N, nn = idx - m * p.N;
+            const int64_t off = p.offCM[m] + p.offCN[nn];
+            double s = (double)Cp[off];
+            for (int z = 0; z < p.splits; ++z) s += p.ws[(int64_t)z * MN + idx];
+            Cp[off] = (T)s;
+        }
     }
 }
 
@@ -553,7 +582,17 @@ static int launch_batch_prec(const BatchProblem *d_probs, const int32_t *d_items
     return launch_status();
 }
 
-// Defines the four per-precision entry points used by the host dispatcher.
+template <int PREC>
+static int launch_batch_reduce_prec(const BatchProblem *d_probs, const int32_t *d_list, int32_t n,
+                                    hipStream_t s) {
+    if (n < 1) return 0;
+    (void)hipGetLastError();   // clear a stale error left by other HIP users
+    hipLaunchKernelGGL(batch_reduce_kernel<PREC>, dim3(64, (unsigned)min(n, 65535)), dim3(256), 0,
+                       s, d_probs, d_list, n);
+    return launch_status();
+}
+
+// Defines the five per-precision entry points used by the host dispatcher.
 #define GETT_DEFINE_PRECISION(PREC, SUFFIX)                                                        \
     int launch_tile_##SUFFIX(int tile, bool afk, bool bfk, const TileParams &p, hipStream_t s) {   \
         return launch_prec<PREC>(tile, afk, bfk, p, s);                                            \
@@ -565,6 +604,10 @@ static int launch_batch_prec(const BatchProblem *d_probs, const int32_t *d_items
     int launch_batch_##SUFFIX(const BatchProblem *d, const int32_t *it, int32_t n, int32_t g,      \
                               hipStream_t s) {                                                     \
         return launch_batch_prec<PREC>(d, it, n, g, s);                                            \
+    }                                                                                              \
+    int launch_batch_reduce_##SUFFIX(const BatchProblem *d, const int32_t *l, int32_t n,           \
+                                     hipStream_t s) {                                              \
+        return launch_batch_reduce_prec<PREC>(d, l, n, s);                                         \
     }
 
 }  // namespace gett
