@@ -17,6 +17,7 @@ from __future__ import annotations
 import argparse
 import json
 import math
+import os
 import struct
 import sys
 
@@ -215,19 +216,47 @@ def split_heldout(n, n_heldout, seed=55):
     return np.sort(perm[n_heldout:]), np.sort(perm[:n_heldout])
 
 
-def train(F, T, epochs=300, batch=256, lr=2e-3, seed=0, log=None):
+def save_checkpoint(m, path, epoch, losses):
+    """Trainer state after `epoch` epochs: parameters, Adam moments and step,
+    input normalisation, loss history (numpy .npz, no pickles)."""
+    tmp = path + ".tmp.npz"
+    np.savez(tmp, P=m.P.cpu().numpy(), m=m.m.cpu().numpy(), v=m.v.cpu().numpy(),
+             t=np.int64(m.t), mean=m.mean, std=m.std, epoch=np.int64(epoch),
+             losses=np.asarray(losses, dtype=np.float64))
+    os.replace(tmp, path)
+
+
+def load_checkpoint(m, path):
+    with np.load(path, allow_pickle=False) as z:
+        m.P.copy_(m.torch.from_numpy(z["P"]))
+        m.m.copy_(m.torch.from_numpy(z["m"]))
+        m.v.copy_(m.torch.from_numpy(z["v"]))
+        m.t = int(z["t"])
+        m.mean = z["mean"].astype(np.float32)
+        m.std = z["std"].astype(np.float32)
+        return int(z["epoch"]), list(z["losses"])
+
+
+def train(F, T, epochs=300, batch=256, lr=2e-3, seed=0, log=None, checkpoint=None, every=25):
+    """Adam on the soft-target cross-entropy, every step on the GPU.  Epoch e
+    shuffles with its own seed (seed, e), so a run resumed from a checkpoint
+    (written every `every` epochs when `checkpoint` names a file, and read
+    back when that file exists) repeats the uninterrupted run exactly."""
     import torch
     m = MLP(seed=seed)
     m.mean = F.mean(axis=0).astype(np.float32)
     m.std = F.std(axis=0).astype(np.float32)
     m.std[m.std < 1e-6] = 1.0
+    start, losses = 0, []
+    if checkpoint and os.path.exists(checkpoint):
+        start, losses = load_checkpoint(m, checkpoint)
+        if log:
+            print(f"[predictor] resumed at epoch {start}", file=log, flush=True)
     Xall = torch.from_numpy(m.normalise(F)).cuda()
     Tall = torch.from_numpy(T).cuda()
-    rng = np.random.default_rng(seed)
     n = F.shape[0]
-    losses = []
-    for ep in range(epochs):
-        order = rng.permutation(n)
+    for ep in range(start, epochs):
+        order = np.random.default_rng([seed, ep]).permutation(n)
         tot = 0.0
         for s in range(0, n, batch):
             idx = torch.from_numpy(order[s:s + batch]).cuda()
@@ -239,6 +268,8 @@ def train(F, T, epochs=300, batch=256, lr=2e-3, seed=0, log=None):
         losses.append(tot / n)
         if log and (ep % 50 == 0 or ep == epochs - 1):
             print(f"[predictor] epoch {ep} loss {losses[-1]:.4f}", file=log, flush=True)
+        if checkpoint and ((ep + 1) % every == 0 or ep == epochs - 1):
+            save_checkpoint(m, checkpoint, ep + 1, losses)
     return m, losses
 
 
@@ -267,6 +298,8 @@ def main():
     ap.add_argument("--heldout", type=int, default=1000)
     ap.add_argument("--epochs", type=int, default=300)
     ap.add_argument("--report", default=None)
+    ap.add_argument("--checkpoint", default=None,
+                    help="trainer state file: written every 25 epochs, resumed from if present")
     args = ap.parse_args()
     gett.lib()
     gett.use_torch_stream()
@@ -274,7 +307,7 @@ def main():
     F, T, times = dataset(rows)
     n_held = min(args.heldout, len(rows) // 4)
     tr, te = split_heldout(len(rows), n_held)
-    m, losses = train(F[tr], T[tr], epochs=args.epochs, log=sys.stderr)
+    m, losses = train(F[tr], T[tr], epochs=args.epochs, log=sys.stderr, checkpoint=args.checkpoint)
     m.save(args.out)
     mlp_r, heur_r, _ = evaluate(m, [rows[i] for i in te], F[te], times[te])
     rep = {"signatures": len(rows), "train": len(tr), "heldout": len(te),

@@ -137,6 +137,19 @@ def test_training_lowers_the_loss():
     assert losses[-1] < 0.8 * losses[0]
 
 
+def test_training_resumes_from_checkpoint_exactly(tmp_path):
+    """5 epochs, checkpoint, 5 more from the file == 10 epochs in one go, bit
+    for bit (fixed-order kernels, per-epoch shuffle seeds)."""
+    rng = np.random.default_rng(9)
+    F, T = _synthetic(rng, 384)
+    ref, lref = P.train(F, T, epochs=10, batch=128, lr=3e-3)
+    path = str(tmp_path / "trainer.npz")
+    P.train(F, T, epochs=5, batch=128, lr=3e-3, checkpoint=path, every=5)
+    got, lgot = P.train(F, T, epochs=10, batch=128, lr=3e-3, checkpoint=path, every=5)
+    assert np.array_equal(ref.P.cpu().numpy(), got.P.cpu().numpy())
+    assert np.array_equal(np.asarray(lref), np.asarray(lgot))
+
+
 def test_library_predict_policy_follows_the_network(tmp_path):
     import torch
     rng = np.random.default_rng(6)
@@ -172,6 +185,46 @@ def test_library_predict_policy_follows_the_network(tmp_path):
             assert e_cw(got[sel], ref_[sel], cabs[sel]) <= 3 * 2.0 ** -16 + (K + 2) * 2.0 ** -24
     finally:
         gett.gett_set_policy(gett.GETT_HEURISTIC)
+
+
+def test_predict_policy_from_environment(tmp_path):
+    """GETT_POLICY=predict with GETT_MODEL=<weights> in a fresh process picks
+    the schedule the network picks here (the library loads the weights on its
+    first prediction)."""
+    import subprocess
+    import sys
+    rng = np.random.default_rng(8)
+    F, T = _synthetic(rng)
+    m, _ = P.train(F, T, epochs=5, batch=128)
+    path = str(tmp_path / "model.bin")
+    m.save(path)
+    pr = W.paper_case("cube_2", np.random.default_rng(12), dtype=np.float32, dist="normal")
+    f = gett.gett_features(gett.GETT_BF16X3, *pr.args())
+    K = pr.mnk()[2]
+    valid = []
+    for sid in range(gett.num_schedules()):
+        t_, o_, sp = gett.schedule_of(sid)
+        bk = gett.gett_tile_shape(gett.GETT_BF16X3, t_)[2]
+        S = gett.SPLIT_FACTORS[sp]
+        valid.append(not ((S > 1 and K < S * bk) or (S == 0 and K < 4 * bk)))
+    want = P.choose(m.logits(f[None, :])[0], np.array(valid))
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = (
+        "import numpy as np, torch\n"
+        "from paper_2410_06770_amd import gett, workloads as W\n"
+        "from tests.helpers import call14, to_device\n"
+        "gett.use_torch_stream()\n"
+        "pr = W.paper_case('cube_2', np.random.default_rng(12), dtype=np.float32, dist='normal')\n"
+        "At, a = to_device(pr.A); Bt, b = to_device(pr.B); Ct, c = to_device(pr.C)\n"
+        "assert call14(gett.sgett_bf16x3, pr, a, b, c) == 0\n"
+        "torch.cuda.synchronize()\n"
+        "print('SCHED', gett.gett_last_schedule())\n")
+    print("\n[gpu] subprocess with GETT_POLICY=predict", flush=True)
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True,
+                       env=dict(os.environ, GETT_POLICY="predict", GETT_MODEL=path), timeout=300)
+    assert r.returncode == 0, r.stderr[-3000:]
+    got = int([l for l in r.stdout.splitlines() if l.startswith("SCHED")][-1].split()[1])
+    assert got == want
 
 
 def test_network_beats_heuristic_on_heldout_signatures():
