@@ -304,3 +304,40 @@ def test_fp8_cc_error_is_reported():
     en = e_nrm(got[sel], ref[sel])
     print(f"\n[fp8] cc e_nrm={en:.3e} e_cw={e_cw(got[sel], ref[sel], cabs[sel]):.3e}")
     assert en < 0.1
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_offsets_beyond_int32(prec):
+    """Element offsets past 2^31: A[a, k] of extents (7, 33) with increments
+    (-1, 2^26), the pointer six elements into a parent of 2^31 + 7 elements
+    (8 GiB FP32, 16 GiB FP64) that holds NaN except at the viewed elements;
+    C[a, d] += sum_k A[a, k] B[k, d].  The result must equal the oracle's on a
+    packed copy of the same values, within the path's bound."""
+    import torch
+    dtype = np.float64 if prec == gett.GETT_FP64 else np.float32
+    tdt = torch.float64 if prec == gett.GETT_FP64 else torch.float32
+    rng = np.random.default_rng(2 ** 31 % 1000)
+    step = 2 ** 26
+    base = 6
+    # packed copy for the oracle: A ext (7, 33), inc (1, 7)
+    pr = W.build_problem(rng, (2, [7, 33], 2, [33, 9], 1, [1], [0], [0, 1]), dtype,
+                         dist="normal", name="int64offsets")
+    a_vals = pr.A.buf[pr.A.element_index()]          # column-major order over (a, k)
+    aa, kk = np.meshgrid(np.arange(7), np.arange(33), indexing="ij")
+    off = (base - aa + kk * step).reshape(-1, order="F")
+    assert off.max() >= 2 ** 31 and off.min() == 0
+    print(f"\n[gpu] int64 offsets prec={prec}: parent of {2 ** 31 + 7} elements", flush=True)
+    parent = torch.full((2 ** 31 + 7,), float("nan"), dtype=tdt, device="cuda")
+    parent[torch.from_numpy(off).cuda()] = torch.from_numpy(np.ascontiguousarray(a_vals)).cuda()
+    Bt, b = to_device(pr.B)
+    Ct, c = to_device(pr.C)
+    a = parent.data_ptr() + base * parent.element_size()
+    rc = gett.ENTRY[prec](2, [7, 33], [-1, step], a, pr.rankb, pr.extb, pr.incb, b, pr.conts,
+                          pr.conta, pr.contb, pr.perm, pr.incc, c)
+    assert rc == 0, gett.strerror(rc)
+    torch.cuda.synchronize()
+    got = Ct.cpu().numpy()
+    del parent
+    torch.cuda.empty_cache()
+    check_against_oracle(pr, prec, got)
+    check_outside(pr, got)
