@@ -9,8 +9,9 @@
 //            memory is the free axis or the contracted axis; consecutive
 //            threads run along that axis so that a wave's loads share cache
 //            lines.  The free offsets a thread needs are fixed for the whole
-//            tile and held in registers; the contracted offsets of a step are
-//            either wave-uniform (scalar loads) or one vector load.
+//            tile and held in registers; the contracted offsets of a step
+//            come from one vector load (broadcast with readlane where they
+//            are wave-uniform).
 //   stage:   values go to LDS (double-buffered; the next step's global loads
 //            are in flight while the current step runs on the matrix cores).
 //            The BF16x3 path splits each FP32 value into hi/lo bfloat16 planes
@@ -57,9 +58,9 @@ template <int PREC, int ROWS, int BK> struct OpLds {
     static constexpr int kBytes = kSplit ? kElems * 2 : kElems * (PREC == kF64 ? 8 : 4);
 };
 
-// Zeros read in place of masked-off elements (rows past the tile's extent,
-// contracted positions past the range): a load from here needs no select
-// afterwards, so the loaded value can go straight to LDS.
+// Zeros read in place of masked-off elements (contracted positions of a
+// range's first step that lie below the range): a load from here needs no
+// select afterwards, so the loaded value can go straight to LDS.
 static __device__ __align__(16) double g_gett_zero[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 
 __device__ __forceinline__ int64_t readlane64(int64_t v, int lane) {
