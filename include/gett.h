@@ -151,13 +151,22 @@ int sgett_fp8_quantize(int64_t rankx, const int64_t *extx, const int64_t *incx, 
 
 /* Batched xGETT: COUNT independent problems run as one persistent kernel
    launch captured in a HIP graph (replayed when the same batch signature
-   comes again).  Every per-problem argument becomes an array over problems;
-   array arguments become arrays of pointers (primitive types only).  PREC is
-   GETT_FP32 or GETT_BF16X3 for sgett_batch (dgett_batch ignores it).
-   INFO (host array, may be NULL) receives each problem's INFO.  Returns 0;
-   -1 for COUNT < 0; -2 for a bad PREC; -1000*(p+1) + INFO_p for the first
-   problem p whose INFO_p is non-zero (nothing is queued then); or a runtime
-   error code > 0.  Outputs of different problems must not overlap. */
+   comes again).  Problems whose contraction is long compared with the
+   batch's average work per workgroup are cut along K; their FP64 partial
+   sums go to a library-owned workspace and a reduction kernel in the same
+   graph adds them to C_in in slice order (results differ from a single call
+   only in summation order).  Every per-problem argument becomes an array
+   over problems; array arguments become arrays of pointers (primitive types
+   only).  PREC is GETT_FP32 or GETT_BF16X3 for sgett_batch (dgett_batch
+   ignores it).  INFO (host array, may be NULL) receives each problem's INFO.
+   Returns 0; -1 for COUNT < 0; -2 for a bad PREC; -1000*(p+1) + INFO_p for
+   the first problem p whose INFO_p is non-zero (nothing is queued then); or
+   a runtime error code > 0.  Asynchronous on the calling thread's stream;
+   a call may block the host until the replay before the previous one has
+   finished (the library keeps two descriptor buffers per batch signature),
+   and replays of one batch signature are ordered on the GPU even across
+   streams.  Outputs of different problems must not overlap, and a batch's
+   buffers must stay valid until its replay has run. */
 int sgett_batch(int64_t count, int64_t prec,
                 const int64_t *ranka, const int64_t *const *exta, const int64_t *const *inca,
                 const float *const *A,
