@@ -183,8 +183,20 @@ __device__ __forceinline__ void fp8_mma_block(const uint8_t *sA, const uint8_t *
     for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int j = 0; j < FN; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a[i], b[j], acc[i][j], 0,
-                                                                         0, 0, sa[i], 0, sb[j]);
+            // B first: the result holds 16 N positions by 16 M positions, so
+            // each lane ends with four neighbouring N positions of one M row
+            // (C's cheapest direction), stored as one 16-byte word.
+            acc[i][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(b[j], a[i], acc[i][j], 0,
+                                                                         0, 0, sb[j], 0, sa[i]);
+}
+
+// Whether the four N positions n .. n+3 of an M row are neighbours in C,
+// all inside N, and start on a 16-byte boundary (one vector access).
+__device__ __forceinline__ bool fp8_c_word(const float *C, const int64_t *__restrict__ offCN,
+                                           int64_t ocm, int64_t o0, int64_t n, int64_t N) {
+    if (n + 3 >= N) return false;
+    if (offCN[n + 1] != o0 + 1 || offCN[n + 2] != o0 + 2 || offCN[n + 3] != o0 + 3) return false;
+    return (reinterpret_cast<uintptr_t>(C + ocm + o0) & 15) == 0;
 }
 
 // C tile BM x BN, 4 waves as 2 x 2, each wave (BM/2) x (BN/2) in 16x16 fragments.
@@ -223,20 +235,33 @@ __global__ __launch_bounds__(256) void fp8_gemm_kernel(const uint8_t *__restrict
         for (int j = 0; j < FN; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
 
     // C_in of this lane's outputs, loaded now so that its latency hides
-    // behind the K loop (each output belongs to one tile only).  Positions
-    // past M or N are neither read nor written.
-    float cin[FN][FM][4];
+    // behind the K loop (each output belongs to one tile only).  Lane l holds
+    // M row (l % 16) and the four N positions 4 (l / 16) .. + 3 of each
+    // fragment; where those four are neighbours in C (and 16-byte aligned)
+    // they move as one word.  Positions past M or N are neither read nor
+    // written.
+    f4_t cin[FM][FN];
+    const int lm = lane & 15, ln = 4 * (lane >> 4);
 #pragma unroll
-    for (int j = 0; j < FN; ++j) {
-        const int64_t n = n0 + wn * WTN + j * 16 + (lane & 15);
-        const int64_t ocn = n < N ? offCN[n] : 0;
+    for (int i = 0; i < FM; ++i) {
+        const int64_t m = m0 + wm * WTM + i * 16 + lm;
+        const int64_t ocm = m < M ? offCM[m] : 0;
 #pragma unroll
-        for (int i = 0; i < FM; ++i)
+        for (int j = 0; j < FN; ++j) {
+            const int64_t n = n0 + wn * WTN + j * 16 + ln;
+            f4_t x = f4_t{0.f, 0.f, 0.f, 0.f};
+            if (m < M) {
+                const int64_t o0 = n < N ? offCN[n] : 0;
+                if (fp8_c_word(C, offCN, ocm, o0, n, N)) {
+                    x = *reinterpret_cast<const f4_t *>(C + ocm + o0);
+                } else {
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int64_t m = m0 + wm * WTM + i * 16 + 4 * (lane >> 4) + v;
-                cin[j][i][v] = (n < N && m < M) ? C[offCM[m] + ocn] : 0.f;
+                    for (int v = 0; v < 4; ++v)
+                        if (n + v < N) x[v] = C[ocm + offCN[n + v]];
+                }
             }
+            cin[i][j] = x;
+        }
     }
     // Thread t carries the scale of tile row t mod (BM + BN) (A rows, then B
     // rows; with fewer rows than threads, two threads carry the same one).
@@ -271,17 +296,24 @@ __global__ __launch_bounds__(256) void fp8_gemm_kernel(const uint8_t *__restrict
     }
     // C_in was loaded before the K loop: add and store.
 #pragma unroll
-    for (int j = 0; j < FN; ++j) {
-        const int64_t n = n0 + wn * WTN + j * 16 + (lane & 15);
-        if (n >= N) continue;
-        const int64_t ocn = offCN[n];
+    for (int i = 0; i < FM; ++i) {
+        const int64_t m = m0 + wm * WTM + i * 16 + lm;
+        if (m >= M) continue;
+        const int64_t ocm = offCM[m];
 #pragma unroll
-        for (int i = 0; i < FM; ++i)
+        for (int j = 0; j < FN; ++j) {
+            const int64_t n = n0 + wn * WTN + j * 16 + ln;
+            if (n >= N) continue;
+            const int64_t o0 = offCN[n];
+            const f4_t y = cin[i][j] + acc[i][j];
+            if (fp8_c_word(C, offCN, ocm, o0, n, N)) {
+                *reinterpret_cast<f4_t *>(C + ocm + o0) = y;
+            } else {
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int64_t m = m0 + wm * WTM + i * 16 + 4 * (lane >> 4) + v;
-                if (m < M) C[offCM[m] + ocn] = cin[j][i][v] + acc[i][j][v];
+                for (int v = 0; v < 4; ++v)
+                    if (n + v < N) C[ocm + offCN[n + v]] = y[v];
             }
+        }
     }
 }
 
