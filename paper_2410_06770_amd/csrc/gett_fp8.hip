@@ -7,9 +7,9 @@
 //         K-contiguous row, with e beside it.  Two loader shapes, as in the
 //         tile kernels: when the contracted positions are the operand's
 //         cheapest direction in memory, one wave takes one (row, block) with
-//         lanes along K; when the rows are, one wave takes 64 neighbouring
-//         rows of one block with a lane per row, so every load of the wave
-//         reads 64 neighbours.
+//         lanes along K; when the rows are, one wave takes 16 neighbouring
+//         rows of one block with four lanes per row, so every load of the
+//         wave reads 16 neighbours at four positions.
 // gemm:   both operands are then dense [rows][Kp] byte matrices, the shape the
 //         16x16x128 FP8 MFMA reads directly: each lane takes 32 consecutive
 //         codes of one row.  The block scales go in as the MFMA's E8M0 scale
@@ -94,39 +94,49 @@ __global__ __launch_bounds__(256) void fp8_quant_kernel(const float *__restrict_
     if (lane == 0) E[r * nb + blk] = e;
 }
 
-// Lanes along the rows: one wave per (64 rows, 128-block); each lane keeps its
-// row's 128 values in registers, so X is read once.
+// Lanes along the rows: one wave per (16 rows, 128-block); four lanes share a
+// row, each keeping a quarter of the block (32 values) in registers, so X is
+// read once and every load of the wave reads 16 neighbouring rows at four
+// contracted positions.
 __global__ __launch_bounds__(256) void fp8_quant_rows_kernel(const float *__restrict__ X,
                                                              const int64_t *__restrict__ offR,
+                                                             const int32_t *__restrict__ rowMap,
                                                              int64_t rows, int64_t rowsPad,
                                                              const int64_t *__restrict__ offK,
                                                              int64_t K, uint8_t *__restrict__ Q,
                                                              int32_t *__restrict__ E) {
+    constexpr int RPW = 16, PART = 128 / (64 / RPW);   // rows per wave, values per lane
     const int64_t nb = (K + 127) / 128;
     const int64_t Kp = nb * 128;
     const int lane = threadIdx.x & 63;
-    const int64_t groups = (rowsPad + 63) / 64;
+    const int64_t groups = (rowsPad + RPW - 1) / RPW;
     const int64_t task = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (task >= groups * nb) return;
     const int64_t blk = task / groups, g = task - blk * groups;   // neighbouring waves: neighbouring rows
-    const int64_t r = g * 64 + lane;
-    const bool live = r < rows;
-    const float *x = X + (live ? offR[r] : 0);
-    const int64_t k0 = blk * 128;
-    const int kn = (int)(K - k0 < 128 ? K - k0 : 128);   // wave-uniform
-    float v[128];
+    const int64_t p = g * RPW + (lane % RPW);                      // walk position
+    const int part = lane / RPW;                                   // quarter of the block
+    const bool live = p < rows;
+    const float *x = X + (live ? offR[p] : 0);
+    // output row: rows are walked in the operand's order, padding rows in place
+    const int64_t r = (rowMap && live) ? (int64_t)rowMap[p] : p;
+    const int64_t k0 = blk * 128 + part * PART;
+    const int64_t kn = K - k0;                                     // positions left from k0
+    float v[PART];
     float amax = 0.f;
 #pragma unroll
-    for (int i = 0; i < 128; ++i) {
+    for (int i = 0; i < PART; ++i) {
         v[i] = (i < kn && live) ? x[offK[k0 + i]] : 0.f;
         amax = fmaxf(amax, fabsf(v[i]));
     }
+    // the four lanes of a row are RPW apart
+    amax = fmaxf(amax, __shfl_xor(amax, RPW, 64));
+    amax = fmaxf(amax, __shfl_xor(amax, 2 * RPW, 64));
     const int e = fp8_scale_exp(amax);
     const float inv = ldexpf(1.f, -e);
-    if (r >= rowsPad) return;
+    if (p >= rowsPad) return;
     uint4 *q = reinterpret_cast<uint4 *>(Q + r * Kp + k0);
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
+    for (int c = 0; c < PART / 16; ++c) {
         const float *w = v + 16 * c;
         uint4 out;
         out.x = e4m3_word(w[0] * inv, w[1] * inv, w[2] * inv, w[3] * inv);
@@ -135,7 +145,7 @@ __global__ __launch_bounds__(256) void fp8_quant_rows_kernel(const float *__rest
         out.w = e4m3_word(w[12] * inv, w[13] * inv, w[14] * inv, w[15] * inv);
         q[c] = out;
     }
-    E[r * nb + blk] = e;
+    if (part == 0) E[r * nb + blk] = e;
 }
 
 // Load one 128-block of a ROWS x 128 code tile into registers: 16-byte
@@ -317,17 +327,17 @@ __global__ __launch_bounds__(256) void fp8_gemm_kernel(const uint8_t *__restrict
     }
 }
 
-int launch_fp8_quant(const float *X, const int64_t *offR, int64_t rows, int64_t rowsPad,
-                     const int64_t *offK, int64_t K, bool rowsFast, uint8_t *Q, int32_t *E,
-                     hipStream_t s) {
+int launch_fp8_quant(const float *X, const int64_t *offR, const int32_t *rowMap, int64_t rows,
+                     int64_t rowsPad, const int64_t *offK, int64_t K, bool rowsFast, uint8_t *Q,
+                     int32_t *E, hipStream_t s) {
     const int64_t nb = (K + 127) / 128;
-    const int64_t tasks = rowsFast ? (rowsPad + 63) / 64 * nb : rowsPad * nb;
+    const int64_t tasks = rowsFast ? (rowsPad + 15) / 16 * nb : rowsPad * nb;
     const int64_t blocks = (tasks + 3) / 4;
     if (blocks > INT32_MAX) return GETT_ERR_INTERNAL;
     (void)hipGetLastError();   // clear a stale error left by other HIP users
     if (rowsFast)
         hipLaunchKernelGGL(fp8_quant_rows_kernel, dim3((unsigned)blocks), dim3(256), 0, s, X, offR,
-                           rows, rowsPad, offK, K, Q, E);
+                           rowMap, rows, rowsPad, offK, K, Q, E);
     else
         hipLaunchKernelGGL(fp8_quant_kernel, dim3((unsigned)blocks), dim3(256), 0, s, X, offR, rows,
                            rowsPad, offK, K, Q, E);

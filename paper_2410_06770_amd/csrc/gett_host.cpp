@@ -305,8 +305,16 @@ struct Fp8Plan {
     int tile = 3;
     bool aRowsFast = false, bRowsFast = false;   // quantisation loader per operand
     bool swapped = false;      // the GEMM's first operand is B
+    // For an operand quantised with lanes along its rows: its row offsets in
+    // the operand's own cheapest order and, for each, the GEMM row it fills.
+    int64_t *d_rowsOp[2] = {nullptr, nullptr};
+    int32_t *d_rowMap[2] = {nullptr, nullptr};
     ~Fp8Plan() {
         if (d_tab) (void)hipFree(d_tab);
+        for (int i = 0; i < 2; ++i) {
+            if (d_rowsOp[i]) (void)hipFree(d_rowsOp[i]);
+            if (d_rowMap[i]) (void)hipFree(d_rowMap[i]);
+        }
     }
 };
 static std::unordered_map<std::string, std::unique_ptr<Fp8Plan>> g_fp8;
@@ -321,6 +329,42 @@ static bool rows_fast(const std::vector<GMode> &rows, const std::vector<GMode> &
     for (auto &x : k)
         if (x.ext > 1) c = std::min<int64_t>(c, std::llabs(slot ? x.i1 : x.i0));
     return r < c;
+}
+
+// The rows of a group walked in the operand's own order (modes by increasing
+// |operand increment|): their operand offsets, and for each the row's index
+// in the group's given (GEMM) order.
+static void operand_order(const std::vector<GMode> &g, int64_t R, std::vector<int64_t> &off,
+                          std::vector<int32_t> &map) {
+    std::vector<size_t> ord(g.size());
+    for (size_t i = 0; i < g.size(); ++i) ord[i] = i;
+    std::stable_sort(ord.begin(), ord.end(), [&](size_t x, size_t y) {
+        return std::llabs(g[x].i0) < std::llabs(g[y].i0);
+    });
+    std::vector<int64_t> radix(g.size());
+    int64_t r = 1;
+    for (size_t i = 0; i < g.size(); ++i) {
+        radix[i] = r;
+        r *= g[i].ext;
+    }
+    std::vector<GMode> og;
+    for (size_t i : ord) og.push_back(g[i]);
+    off.assign(R, 0);
+    group_offsets(og, 0, R, off.data());
+    map.assign(R, 0);
+    std::vector<int64_t> coord(og.size(), 0);
+    int64_t idx = 0;   // GEMM-order index of the current operand-order row
+    for (int64_t p = 0; p < R; ++p) {
+        map[p] = (int32_t)idx;
+        for (size_t k = 0; k < og.size(); ++k) {   // odometer, first operand-order mode fastest
+            if (++coord[k] < og[k].ext) {
+                idx += radix[ord[k]];
+                break;
+            }
+            idx -= radix[ord[k]] * (og[k].ext - 1);
+            coord[k] = 0;
+        }
+    }
 }
 
 static int get_fp8_plan(const Args &a, int dev, Fp8Plan **out) {
@@ -382,6 +426,24 @@ static int get_fp8_plan(const Args &a, int dev, Fp8Plan **out) {
     pl->tile = tilesBig >= 256 ? 3 : 0;
     pl->aRowsFast = rows_fast(ra, k, 0);
     pl->bRowsFast = rows_fast(rb, k, 1);
+    for (int side = 0; side < 2; ++side) {
+        const bool rf = side ? pl->bRowsFast : pl->aRowsFast;
+        const std::vector<GMode> &g = side ? rb : ra;
+        const int64_t R = side ? pl->N : pl->M;
+        if (!rf || R == 0) continue;
+        if (R > INT32_MAX) return GETT_ERR_INTERNAL;
+        std::vector<int64_t> off;
+        std::vector<int32_t> map;
+        operand_order(g, R, off, map);
+        if (hipMalloc(&pl->d_rowsOp[side], R * sizeof(int64_t)) != hipSuccess ||
+            hipMalloc(&pl->d_rowMap[side], R * sizeof(int32_t)) != hipSuccess)
+            return GETT_ERR_ALLOC;
+        if (hipMemcpy(pl->d_rowsOp[side], off.data(), R * sizeof(int64_t),
+                      hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(pl->d_rowMap[side], map.data(), R * sizeof(int32_t),
+                      hipMemcpyHostToDevice) != hipSuccess)
+            return GETT_ERR_HIP;
+    }
     std::lock_guard<std::mutex> lk(g_mu);
     auto &slot = g_fp8[key];
     if (!slot) slot = std::move(pl);
@@ -405,8 +467,11 @@ static int run_fp8(const Args &a, const float *A, const float *B, float *C, hipS
     int32_t *EA = reinterpret_cast<int32_t *>(QB + (size_t)Nq * Kp);
     int32_t *EB = EA + (size_t)Mq * nb;
     const float *X0 = pl->swapped ? B : A, *X1 = pl->swapped ? A : B;
-    rc = launch_fp8_quant(X0, rowsA, M, Mq, kA, K, pl->aRowsFast, QA, EA, s);
-    if (!rc) rc = launch_fp8_quant(X1, rowsB, N, Nq, kB, K, pl->bRowsFast, QB, EB, s);
+    rc = launch_fp8_quant(X0, pl->aRowsFast ? pl->d_rowsOp[0] : rowsA, pl->d_rowMap[0], M, Mq,
+                          kA, K, pl->aRowsFast, QA, EA, s);
+    if (!rc)
+        rc = launch_fp8_quant(X1, pl->bRowsFast ? pl->d_rowsOp[1] : rowsB, pl->d_rowMap[1], N, Nq,
+                              kB, K, pl->bRowsFast, QB, EB, s);
     if (!rc) rc = launch_fp8_gemm(pl->tile, QA, EA, QB, EB, C, offCM, offCN, M, N, K, s);
     if (hipFreeAsync(ws, s) != hipSuccess && !rc) rc = GETT_ERR_HIP;
     return rc;
@@ -1045,7 +1110,7 @@ int sgett_fp8_quantize(int64_t rankx, const int64_t *extx, const int64_t *incx, 
         return GETT_ERR_ALLOC;
     if (hipMemcpyAsync(d, h.data(), h.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess)
         return GETT_ERR_HIP;
-    rc = launch_fp8_quant(X, d, R, R, d + R, K, rows_fast(rows, kk, 0), QX, EX, s);
+    rc = launch_fp8_quant(X, d, nullptr, R, R, d + R, K, rows_fast(rows, kk, 0), QX, EX, s);
     (void)hipFreeAsync(d, s);
     // h must outlive the copy: wait for it
     if (hipStreamSynchronize(s) != hipSuccess && !rc) rc = GETT_ERR_HIP;

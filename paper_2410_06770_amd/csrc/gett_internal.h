@@ -119,10 +119,12 @@ int launch_batch_reduce(int prec, const BatchProblem *d_probs, const int32_t *d_
 
 // FP8 path: quantisation into canonical K-contiguous rows and the GEMM on them.
 // rowsFast selects the loader whose lanes run along the rows (for operands
-// whose rows, not their contracted positions, are the cheap direction).
-int launch_fp8_quant(const float *X, const int64_t *offR, int64_t rows, int64_t rowsPad,
-                     const int64_t *offK, int64_t K, bool rowsFast, uint8_t *Q, int32_t *E,
-                     hipStream_t s);
+// whose rows, not their contracted positions, are the cheap direction); it
+// walks the rows in the order of offR, and rowMap (NULL: identity) gives the
+// output row of each.
+int launch_fp8_quant(const float *X, const int64_t *offR, const int32_t *rowMap, int64_t rows,
+                     int64_t rowsPad, const int64_t *offK, int64_t K, bool rowsFast, uint8_t *Q,
+                     int32_t *E, hipStream_t s);
 int launch_fp8_gemm(int tile, const uint8_t *QA, const int32_t *EA, const uint8_t *QB,
                     const int32_t *EB, float *C, const int64_t *offCM, const int64_t *offCN,
                     int64_t M, int64_t N, int64_t K, hipStream_t s);
