@@ -281,7 +281,7 @@ def kernel_hash():
     h = hashlib.sha256()
     src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2410_06770_amd", "csrc")
     for name in sorted(os.listdir(src)):
-        if name.startswith(("gett_tile", "gett_grid")) or name == "gett_internal.h":
+        if name.startswith(("gett_tile", "gett_grid", "gett_config")):
             with open(os.path.join(src, name), "rb") as f:
                 h.update(f.read())
     return h.hexdigest()[:16]

@@ -1,104 +1,15 @@
-// gett_internal.h -- types shared by the host planner and the gfx950 kernels.
-//
-// A planned contraction is a GEMM over three linearised index spaces:
-//   M = free modes of the (possibly swapped) A operand,
-//   N = free modes of the B operand,
-//   K = contracted pairs,
-// and every element address comes from per-group offset tables:
-//   C[offCM[m] + offCN[n]] += sum_k A[offAM[m] + offAK[k]] * B[offBK[k] + offBN[n]].
-// Section 6 of the paper computes the same sums by walking the free and the
-// contracted coordinates with odometers (Algorithms 1 and 2); the tables hold
-// exactly the increment-times-coordinate sums those walks produce, once per
-// group instead of once per term.
+// gett_internal.h -- launcher and status declarations shared by the host
+// runtime and the gfx950 kernel files; the tile menus and launch descriptors
+// are in gett_config.h.
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include "gett.h"
+#include "gett_config.h"
 
 namespace gett {
-
-enum Prec : int { kF64 = 0, kF32 = 1, kBF3 = 2, kFP8 = 3 };
-
-constexpr int kThreads = 256;       // 4 waves of 64 per workgroup
-constexpr int kNumTiles = 5;        // tile menu size per precision
-constexpr int kNumOrders = 4;
-constexpr int kNumSplits = 4;       // split-K options: 1, 2, 4 slices, or "fill"
-constexpr int kSplitFactor[kNumSplits] = {1, 2, 4, 0};   // 0 = enough slices to fill the chip
-constexpr int kFillTarget = 2048;   // workgroups the "fill" option aims at
-constexpr int kMaxSplits = 4096;
-
-// Number of K slices actually launched for split option `split`: every slice
-// starts below K (so the kernel's look-ahead loads stay inside the padded
-// contracted tables) and gets at least two K steps.
-inline int split_count(int split, int64_t tiles, int64_t K, int bk, int64_t *kPer) {
-    int64_t S = kSplitFactor[split];
-    if (S == 0) {
-        S = tiles >= kFillTarget ? 1 : (kFillTarget + tiles - 1) / tiles;
-        const int64_t maxS = K / (2 * (int64_t)bk);
-        if (S > maxS) S = maxS;
-        if (S > kMaxSplits) S = kMaxSplits;
-    }
-    if (S < 1) S = 1;
-    int64_t per = (K + S - 1) / S;
-    per = (per + bk - 1) / bk * bk;
-    S = (K + per - 1) / per;
-    if (kPer) *kPer = per;
-    return (int)S;
-}
-constexpr int kTablePad = 256;      // M/N tables padded to a multiple of this
-
-// load_fence: the compiler keeps the next step's global loads ahead of the
-// step's MFMA block (a scheduling barrier between them).  Without it the
-// loads may move into the MFMA block; which is faster depends on the tile
-// (measured on gfx950 per precision and tile).
-struct TileShape { int bm, bn, bk; bool load_fence; };
-
-// Tile menus.  FP64/FP32 run 16x16x4 MFMA steps (BK multiple of 4), the BF16x3
-// path 16x16x32 BF16 MFMA steps (BK multiple of 32).  Each workgroup is a 2x2
-// grid of waves, so BM and BN are multiples of 32.
-constexpr TileShape kTiles[4][kNumTiles] = {
-    /* FP64   */ {{64, 64, 16, true}, {64, 128, 16, false}, {128, 64, 16, false},
-                  {128, 128, 16, true}, {128, 64, 8, false}},
-    /* FP32   */ {{64, 64, 16, true}, {64, 128, 16, true}, {128, 64, 16, true},
-                  {128, 128, 16, true}, {128, 128, 32, true}},
-    /* BF16x3 */ {{64, 64, 32, true}, {64, 128, 32, true}, {128, 64, 32, true},
-                  {128, 128, 32, true}, {128, 128, 64, true}},
-    /* FP8    */ {{64, 64, 128, true}, {64, 128, 128, true}, {128, 64, 128, true},
-                  {128, 128, 128, true}, {128, 128, 128, true}},
-};
-
-// Flag of the menu entry with this shape (first match).
-constexpr bool tile_load_fence(int prec, int bm, int bn, int bk) {
-    for (int t = 0; t < kNumTiles; ++t)
-        if (kTiles[prec][t].bm == bm && kTiles[prec][t].bn == bn && kTiles[prec][t].bk == bk)
-            return kTiles[prec][t].load_fence;
-    return true;
-}
-
-// Arguments of one tile kernel launch (passed by value in the kernarg segment).
-struct TileParams {
-    const void *A;
-    const void *B;
-    void *C;
-    const int64_t *offAM, *offCM;   // M tables (padded)
-    const int64_t *offBN, *offCN;   // N tables (padded)
-    const int64_t *offAK, *offBK;   // K tables (padded to a multiple of BK)
-    int64_t M, N, K;
-    int64_t kPerSplit;              // contracted positions per split (multiple of BK)
-    int32_t tilesM, tilesN, splits;
-    int32_t bBoxX;                  // B loader sub-box width along its fast free mode
-    double *ws;                     // split-K partials [split][M][N], n fastest; null = direct
-};
-
-// One problem of a batched launch (device-resident descriptor).
-struct BatchProblem {
-    TileParams p;
-    int32_t aFastK, bFastK;
-    int32_t tileBase;               // first work item of this problem
-    int32_t pad_;
-};
 
 // Status of the launch just made: 0, or GETT_ERR_HIP with the HIP error kept
 // for gett_strerror (callers clear any stale error before launching).
