@@ -253,6 +253,43 @@ def test_fp8_quantizer_codes_bitwise():
         assert np.array_equal(Qt.cpu().numpy(), Q)
 
 
+def _check_fp8_model(pr, got, tag):
+    """GPU FP8 result against the exact value of the quantised operands
+    (the oracle's canonical quantisation), placed into C's layout."""
+    QA, EA, QB, EB, K = _fp8_reference(pr)
+    model = oracle.fp8_gemm(QA, EA, QB, EB, K)          # [rowsA, rowsB] in canonical orders
+    # place the model into C's layout: canonical rows are the free lists in order
+    ref, cabs = oracle.exact(pr, pr.A, pr.B, pr.C)
+    fa, fb = pr.free_modes()
+    extc = pr.extc()
+    idx = pr.C.element_index()                         # C positions, column-major over C modes
+    cvals = got[idx].astype(np.float64).reshape(extc, order="F") if extc else got[idx]
+    # output coordinates -> (row of A, row of B)
+    grid = np.indices(extc) if extc else np.zeros((0,), dtype=np.int64)
+    pos = {q: p for p, q in enumerate(pr.perm)}
+    ra = np.zeros(extc, dtype=np.int64) if extc else np.int64(0)
+    rb = np.zeros(extc, dtype=np.int64) if extc else np.int64(0)
+    s = 1
+    for p, i in enumerate(fa):
+        ra = ra + grid[pr.perm[p]] * s
+        s *= pr.exta[i]
+    s = 1
+    for p, j in enumerate(fb):
+        rb = rb + grid[pr.perm[len(fa) + p]] * s
+        s *= pr.extb[j]
+    mval = model[ra, rb]
+    cin = pr.C.buf[idx].astype(np.float64).reshape(extc, order="F") if extc else pr.C.buf[idx]
+    exp = mval + cin
+    # The FP8 matrix core does not round its 128-term sums correctly:
+    # measured on random full-range E4M3 codes its error reaches 2^-12
+    # of the largest product of a block (sums of moderate-range codes
+    # come out exact).  Bound: 2^-10 of sum |a||b| per element, plus
+    # FP32 accumulation across blocks; 1.3 covers quantised magnitudes.
+    bnd = view_values(pr.C, cabs) * 1.3 * (2.0 ** -10 + (K + 2) * U32) + 1e-30
+    assert np.all(np.abs(cvals - exp) <= bnd), tag
+    check_outside(pr, got)
+
+
 @pytest.mark.parametrize("case", ["basic", "subtensor", "negative", "cube_2", "hypercube_3",
                                   "scalar", "nothing", "lowerrank"])
 def test_fp8_against_quantised_model(case):
@@ -260,38 +297,21 @@ def test_fp8_against_quantised_model(case):
     for rep in range(3):
         pr = W.paper_case(case, rng, dtype=np.float32, dist="normal")
         got = run_gpu(pr, gett.GETT_FP8, f"fp8 rep{rep}")
-        QA, EA, QB, EB, K = _fp8_reference(pr)
-        model = oracle.fp8_gemm(QA, EA, QB, EB, K)          # [rowsA, rowsB] in canonical orders
-        # place the model into C's layout: canonical rows are the free lists in order
-        ref, cabs = oracle.exact(pr, pr.A, pr.B, pr.C)
-        fa, fb = pr.free_modes()
-        extc = pr.extc()
-        idx = pr.C.element_index()                         # C positions, column-major over C modes
-        cvals = got[idx].astype(np.float64).reshape(extc, order="F") if extc else got[idx]
-        # output coordinates -> (row of A, row of B)
-        grid = np.indices(extc) if extc else np.zeros((0,), dtype=np.int64)
-        pos = {q: p for p, q in enumerate(pr.perm)}
-        ra = np.zeros(extc, dtype=np.int64) if extc else np.int64(0)
-        rb = np.zeros(extc, dtype=np.int64) if extc else np.int64(0)
-        s = 1
-        for p, i in enumerate(fa):
-            ra = ra + grid[pr.perm[p]] * s
-            s *= pr.exta[i]
-        s = 1
-        for p, j in enumerate(fb):
-            rb = rb + grid[pr.perm[len(fa) + p]] * s
-            s *= pr.extb[j]
-        mval = model[ra, rb]
-        cin = pr.C.buf[idx].astype(np.float64).reshape(extc, order="F") if extc else pr.C.buf[idx]
-        exp = mval + cin
-        # The FP8 matrix core does not round its 128-term sums correctly:
-        # measured on random full-range E4M3 codes its error reaches 2^-12
-        # of the largest product of a block (sums of moderate-range codes
-        # come out exact).  Bound: 2^-10 of sum |a||b| per element, plus
-        # FP32 accumulation across blocks; 1.3 covers quantised magnitudes.
-        bnd = view_values(pr.C, cabs) * 1.3 * (2.0 ** -10 + (K + 2) * U32) + 1e-30
-        assert np.all(np.abs(cvals - exp) <= bnd), case
-        check_outside(pr, got)
+        _check_fp8_model(pr, got, case)
+
+
+@pytest.mark.parametrize("layout", ["step2", "packed", "sub"])
+def test_fp8_strided_permuted_shape(layout):
+    """The strided workload's structure at a small size, C[b,e,a,d] =
+    sum_{c,f} A[a,b,c,f] B[f,d,c,e]: the plan swaps the operands and orders
+    N by C's increments (b first) while A's own cheapest mode is a, so the
+    row-direction quantiser walks A through its row map."""
+    rng = np.random.default_rng(zlib.crc32(layout.encode()) + 21)
+    sig = (4, [12, 16, 24, 10], 4, [10, 14, 24, 18], 2, [2, 3], [2, 0], [2, 0, 3, 1])
+    pr = W.build_problem(rng, sig, np.float32, layout_a=layout, dist="normal",
+                         name=f"fp8_strided_{layout}")
+    got = run_gpu(pr, gett.GETT_FP8, "fp8 strided")
+    _check_fp8_model(pr, got, layout)
 
 
 def test_fp8_cc_error_is_reported():
