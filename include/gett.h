@@ -267,7 +267,10 @@ int64_t gett_plan_tables(int prec, int64_t order, int64_t tile, int64_t ranka,
 
 const char *gett_strerror(int code);
 
-/* Release the plan cache, device tables, graphs and predictor. */
+/* Wait for the current device to finish its queued work, then release the
+   plan cache, device tables, graphs, workspaces and predictor.  Returns 0 or
+   GETT_ERR_HIP when the wait failed (the caches are released either way).
+   Must not race with other calls into the library. */
 int gett_finalize(void);
 
 /* ---------------------------------------------------------------------- */

@@ -1300,6 +1300,10 @@ const char *gett_strerror(int code) {
 }
 
 int gett_finalize(void) {
+    // Queued work may still read the tables, graphs and workspaces: wait for
+    // the device before releasing them.
+    int rc = 0;
+    if (hipDeviceSynchronize() != hipSuccess) rc = GETT_ERR_HIP;
     {
         std::lock_guard<std::mutex> lk(g_mu);
         g_graphs.clear();
@@ -1310,7 +1314,7 @@ int gett_finalize(void) {
     }
     std::lock_guard<std::mutex> lk(g_pred_mu);
     g_pred.reset();
-    return 0;
+    return rc;
 }
 
 int gett_mlp_linear_fwd(const float *X, const float *W, const float *b, float *Y, int64_t batch,
