@@ -765,11 +765,17 @@ static int run(int prec, const Args &a, const void *A, const void *B, void *C) {
     const int64_t forced = g_forced.load();
     Plan *pl = nullptr;
     // Under the AUTOTUNE policy a plan-cache miss times the menu; the timing
-    // runs accumulate into C, so C's footprint is saved and restored around it.
+    // runs accumulate into C, so C's footprint is saved and restored around it
+    // (only then: a cached plan needs no timing).
     void *saved = nullptr;
     int64_t lo = 0, span = 0;
     const size_t esz = prec == kF64 ? 8 : 4;
-    if (g_policy.load() == GETT_AUTOTUNE && forced < 0) {
+    bool cached = false;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        cached = g_plans.count(signature_key(a, prec, dev, forced)) != 0;
+    }
+    if (g_policy.load() == GETT_AUTOTUNE && forced < 0 && !cached) {
         span = c_span_elems(a, &lo);
         char *cbase = static_cast<char *>(C) + lo * (int64_t)esz;
         if (hipMallocAsync(&saved, span * esz, s) != hipSuccess) return GETT_ERR_ALLOC;
