@@ -1,12 +1,17 @@
 #!/usr/bin/env python3
 """Benchmark of the xGETT hot path on one MI355X.
 
-Workload: the strided + permuted contraction
+Workload (default): the strided + permuted contraction
     C[b,e,a,d] = sum_{c,f} A[a,b,c,f] B[f,d,c,e]
 with A of extents (48,64,96,40) read with step 2 on every mode of a packed
 (96,128,192,80) parent, B (40,56,96,72) dense, C dense (M, N, K = 3072,
 4032, 3840; 2MNK = 9.513e10 flops), values normal(0,1) from a fixed seed.
-Inputs are resident in HBM before the timed region starts.
+Inputs are resident in HBM before the timed region starts.  `--workload cc`
+runs the coupled-cluster-shaped precision study instead,
+    C[a,b,c,d] = sum_{i,j} A[a,b,i,j] B[i,j,c,d]
+with virtual extent 96 and occupied extent 32 (M, N, K = 9216, 9216, 1024;
+2MNK = 1.739e11), FP32 values normal(0,1) scaled by 10^U(-3,3) per slice
+(the FP64 path gets the same values widened).
 
 One step = one xGETT call of the primary path (DGETT, FP64).  The same
 workload also runs through SGETT (FP32 MFMA), split BF16x3 SGETT and FP8
@@ -14,9 +19,13 @@ SGETT; their rates and errors against the FP64 oracle (on a sample of
 outputs) are reported under "paths".  A last leg runs the uneven batch of 512
 problems through split BF16x3 as one replay of the captured batch graph and
 as 512 separate calls ("batch").  Kernel durations come from HIP events
-recorded on the library's stream around every call.
+recorded on the library's stream around every call.  For context only, the
+same contraction through PyTorch (rocBLAS / hipBLASLt behind it) is timed
+twice under "context": torch.einsum on the strided views (it materialises
+transposes) and a plain matmul of packed M x K and K x N matrices of the
+same sizes (a library GEMM that does none of the contraction's addressing).
 
-    python bench.py [--gpus 1] [--steps 20] [--warmup 3]
+    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--workload strided_perm|cc]
 """
 from __future__ import annotations
 
@@ -30,11 +39,24 @@ import numpy as np
 
 METRIC = "xGETT TFLOP/s & % MFMA peak: plain FP64/FP32 vs split-BF16 at stated rel err"
 PEAK = {"f64": 78.6, "f32": 157.3, "bf16": 2516.6, "fp8": 5033.2}   # dense MFMA TFLOP/s
+WORKLOADS = {
+    "strided_perm": ("config_strided_perm",
+                     "strided_perm: C[b,e,a,d] = sum_{c,f} A[a,b,c,f] B[f,d,c,e]; "
+                     "A (48,64,96,40) step 2 in a (96,128,192,80) parent, "
+                     "B (40,56,96,72) dense, C dense",
+                     "synthetic (seeded normal(0,1))"),
+    "cc": ("config_cc",
+           "cc: C[a,b,c,d] = sum_{i,j} A[a,b,i,j] B[i,j,c,d]; virtual 96, occupied 32, dense",
+           "synthetic (seeded normal(0,1) x 10^U(-3,3) per slice, FP32 values)"),
+}
 
 
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="strided_perm")
+    ap.add_argument("--no-context", action="store_true",
+                    help="skip the PyTorch einsum / matmul context timings")
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--paths", default="f64,f32,bf16x3,fp8")
@@ -92,12 +114,15 @@ def main():
     entry = {"f64": gett.dgett, "f32": gett.sgett, "bf16x3": gett.sgett_bf16x3,
              "fp8": gett.sgett_fp8}
     results = {}
+    context = {}
     problems = {}
+    builder, wdesc, wdata = WORKLOADS[args.workload]
+    make = getattr(W, builder)
     for path in paths:
         dtype = np.float64 if path == "f64" else np.float32
         if dtype not in problems:
-            problems[dtype] = W.config_strided_perm(dtype=dtype)
-    pr64 = problems.get(np.float64) or W.config_strided_perm(dtype=np.float64)
+            problems[dtype] = make(dtype=dtype)
+    pr64 = problems.get(np.float64) or make(dtype=np.float64)
     M, N, K = pr64.mnk()
     flops = 2.0 * M * N * K
     print(f"[bench] workload M={M} N={N} K={K} flops={flops:.4e}", file=sys.stderr, flush=True)
@@ -156,6 +181,9 @@ def main():
         print(f"[bench] {path}: {json.dumps(res)}", file=sys.stderr, flush=True)
         if primary is None:
             primary = (path, ms, tflops, peak, wall)
+        if not args.no_context and path in ("f64", "f32"):
+            context.update(torch_context(pr, path, At, Bt, Ct, flops, args.steps, args.warmup,
+                                         torch, stream))
         del At, Bt, Ct
         torch.cuda.empty_cache()
 
@@ -178,16 +206,17 @@ def main():
         "vs_baseline": None,
         "dtype": {"f64": "f64", "f32": "f32", "bf16x3": "bf16x3(f32 acc, f64 sum)",
                   "fp8": "e4m3(f32 acc)"}[path],
-        "data": "synthetic (seeded normal(0,1))",
-        "config": {"workload": "strided_perm: C[b,e,a,d] = sum_{c,f} A[a,b,c,f] B[f,d,c,e]; "
-                               "A (48,64,96,40) step 2 in a (96,128,192,80) parent, "
-                               "B (40,56,96,72) dense, C dense",
+        "data": wdata,
+        "config": {"workload": wdesc,
                    "M": M, "N": N, "K": K, "flops_per_step": flops, "path": path},
         "roofline": {"bound": "mfma", "achieved": round(tflops, 3), "peak": peak,
                      "unit": "TFLOP/s", "frac": round(tflops / peak, 4),
-                     "traffic": load_traffic(args.traffic_json, path, results[path]["schedule"])},
+                     "traffic": load_traffic(args.traffic_json, args.workload, path,
+                                             results[path]["schedule"])},
         "paths": results,
     }
+    if context:
+        out["context"] = context
     if batch is not None:
         out["batch"] = batch
     if not args.no_cpu_baseline:
@@ -259,17 +288,70 @@ def batch_leg(count, gett, W, torch, stream, reps=10):
             "speedup": round(s_ms / g_ms, 3)}
 
 
-def load_traffic(path, prec_path, schedule):
+def torch_context(pr, path, At, Bt, Ct, flops, steps, warmup, torch, stream):
+    """PyTorch on the same contraction, for context: einsum over the strided
+    views of the resident operands (accumulated into C's view), and a plain
+    matmul of packed M x K and K x N matrices of the same sizes."""
+    def view(t, v):
+        return torch.as_strided(t, v.ext, v.inc, v.base)
+
+    letters = "abcdefghijklmnopqrstuvwxyz"
+    la = list(letters[:pr.ranka])
+    lb = [None] * pr.rankb
+    nxt = pr.ranka
+    for ka, kb in zip(pr.conta, pr.contb):
+        lb[kb] = la[ka]
+    for j in range(pr.rankb):
+        if lb[j] is None:
+            lb[j] = letters[nxt]
+            nxt += 1
+    fa, fb = pr.free_modes()
+    free = [la[i] for i in fa] + [lb[j] for j in fb]
+    out = [None] * len(free)
+    for p, q in enumerate(pr.perm):
+        out[q] = free[p]
+    spec = f"{''.join(la)},{''.join(lb)}->{''.join(out)}"
+    Av, Bv, Cv = view(At, pr.A), view(Bt, pr.B), view(Ct, pr.C)
+    M, N, K = pr.mnk()
+    Am = torch.randn(M, K, dtype=At.dtype, device="cuda")
+    Bm = torch.randn(K, N, dtype=At.dtype, device="cuda")
+    Cm = torch.zeros(M, N, dtype=At.dtype, device="cuda")
+
+    def timed(fn):
+        for _ in range(warmup + 1):
+            fn()
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        ev[0].record(stream)
+        for i in range(steps):
+            fn()
+            ev[i + 1].record(stream)
+        torch.cuda.synchronize()
+        ms = float(np.mean([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]))
+        return {"ms": round(ms, 4), "tflops": round(flops / (ms * 1e-3) / 1e12, 3)}
+
+    print(f"[bench] context {path}: torch.einsum {spec} and torch.matmul", file=sys.stderr,
+          flush=True)
+    res = {f"torch_einsum_{path}": dict(timed(lambda: Cv.add_(torch.einsum(spec, Av, Bv))),
+                                        spec=spec),
+           f"torch_matmul_{path}": dict(timed(lambda: torch.matmul(Am, Bm, out=Cm)),
+                                        shape=[M, N, K])}
+    del Am, Bm, Cm
+    return res
+
+
+def load_traffic(path, workload, prec_path, schedule):
     """HBM bytes per launch of the timed kernel, from the rocprofv3 counter
     runs summarised in profiles/ (FETCH_SIZE and WRITE_SIZE scaled by the
-    same counters on a plain copy of known size), kept per schedule; None
-    when this schedule was not measured or the kernel sources changed since."""
+    same counters on a plain copy of known size), kept per workload and
+    schedule; None when this schedule was not measured or the kernel sources
+    changed since."""
     try:
         with open(path) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    e = (t.get(prec_path) or {}).get("by_schedule", {}).get(str(schedule))
+    e = ((t.get(workload) or {}).get(prec_path) or {}).get("by_schedule", {}).get(str(schedule))
     if not e or e.get("kernel_source_hash") != kernel_hash():
         return None
     return {"read_bytes": e["read_bytes"], "write_bytes": e["write_bytes"],

@@ -51,20 +51,23 @@ constexpr int kTablePad = 256;      // M/N tables padded to a multiple of this
 // step's MFMA block (a scheduling barrier between them).  Without it the
 // loads may move into the MFMA block; which is faster depends on the tile
 // (measured on gfx950 per precision and tile).
-struct TileShape { int bm, bn, bk; bool load_fence; };
+// depth: how many K steps ahead of the MFMAs the global loads run (1 or 2).
+// Depth 2 keeps two register sets of staged values, so a load has two steps
+// of MFMA work to land in instead of one.
+struct TileShape { int bm, bn, bk; bool load_fence; int depth; };
 
 // Tile menus.  FP64/FP32 run 16x16x4 MFMA steps (BK multiple of 4), the BF16x3
 // path 16x16x32 BF16 MFMA steps (BK multiple of 32).  Each workgroup is a 2x2
 // grid of waves, so BM and BN are multiples of 32.
 constexpr TileShape kTiles[4][kNumTiles] = {
-    /* FP64   */ {{64, 64, 16, true}, {64, 128, 16, false}, {128, 64, 16, false},
-                  {128, 128, 16, true}, {128, 64, 8, false}},
-    /* FP32   */ {{64, 64, 16, true}, {64, 128, 16, true}, {128, 64, 16, true},
-                  {128, 128, 16, true}, {128, 128, 32, true}},
-    /* BF16x3 */ {{64, 64, 32, true}, {64, 128, 32, true}, {128, 64, 32, true},
-                  {128, 128, 32, true}, {128, 128, 64, true}},
-    /* FP8    */ {{64, 64, 128, true}, {64, 128, 128, true}, {128, 64, 128, true},
-                  {128, 128, 128, true}, {128, 128, 128, true}},
+    /* FP64   */ {{64, 64, 16, true, 1}, {64, 128, 16, false, 1}, {128, 64, 16, false, 1},
+                  {128, 128, 16, true, 1}, {128, 64, 8, false, 1}},
+    /* FP32   */ {{64, 64, 16, true, 2}, {64, 128, 16, true, 2}, {128, 64, 16, true, 2},
+                  {128, 128, 16, true, 2}, {128, 128, 32, true, 2}},
+    /* BF16x3 */ {{64, 64, 32, true, 1}, {64, 128, 32, true, 1}, {128, 64, 32, true, 1},
+                  {128, 128, 32, true, 1}, {128, 128, 64, true, 1}},
+    /* FP8    */ {{64, 64, 128, true, 1}, {64, 128, 128, true, 1}, {128, 64, 128, true, 1},
+                  {128, 128, 128, true, 1}, {128, 128, 128, true, 1}},
 };
 
 // Flag of the menu entry with this shape (first match).
@@ -73,6 +76,13 @@ constexpr bool tile_load_fence(int prec, int bm, int bn, int bk) {
         if (kTiles[prec][t].bm == bm && kTiles[prec][t].bn == bn && kTiles[prec][t].bk == bk)
             return kTiles[prec][t].load_fence;
     return true;
+}
+
+constexpr int tile_depth(int prec, int bm, int bn, int bk) {
+    for (int t = 0; t < kNumTiles; ++t)
+        if (kTiles[prec][t].bm == bm && kTiles[prec][t].bn == bn && kTiles[prec][t].bk == bk)
+            return kTiles[prec][t].depth;
+    return 1;
 }
 
 // Arguments of one tile kernel launch (passed by value in the kernarg segment).

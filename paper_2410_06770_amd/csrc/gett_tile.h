@@ -171,12 +171,20 @@ template <int PREC, int ROWS, int BK, bool FASTK> struct Gather {
     // the zero buffer instead.
     template <bool MASKED>
     __device__ __forceinline__ void load(int64_t k0, int64_t klo, T (&v)[PER]) const {
+        load_with<MASKED>(koff, k0, klo, v);
+    }
+
+    // The same with contracted offsets held elsewhere (a copy taken before
+    // the next step's offsets were requested into koff).
+    template <bool MASKED>
+    __device__ __forceinline__ void load_with(const int64_t (&ko_)[KP], int64_t k0, int64_t klo,
+                                              T (&v)[PER]) const {
         const T *zero = reinterpret_cast<const T *>(g_gett_zero);
         if constexpr (!FASTK) {
 #pragma unroll
             for (int i = 0; i < PER; ++i) {
                 const int k = kpos(col(i));                  // uniform
-                const int64_t ko = readlane64(koff[0], k);
+                const int64_t ko = readlane64(ko_[0], k);
                 const T *ptr = base[0] + ko;
                 if constexpr (MASKED) ptr = (k0 + k >= klo) ? ptr : zero;
                 v[i] = *ptr;
@@ -187,7 +195,7 @@ template <int PREC, int ROWS, int BK, bool FASTK> struct Gather {
                 const bool kk = k0 + j0 + e * KL >= klo;
 #pragma unroll
                 for (int i = 0; i < NF; ++i) {
-                    const T *ptr = base[i] + koff[e];
+                    const T *ptr = base[i] + ko_[e];
                     if constexpr (MASKED) ptr = kk ? ptr : zero;
                     v[i * KP + e] = *ptr;
                 }
@@ -245,6 +253,41 @@ template <int PREC, int BM, int BN, int BK> struct TileCfg {
     static_assert(BK % (PREC == kBF3 ? 32 : 4) == 0, "BK");
 };
 
+// MFMA work of one staged K step for the FP64/FP32 tiles that load two
+// steps ahead: the wave's FM x FN fragments over the stage's BK contracted
+// positions.
+template <int PREC, int BM, int BN, int BK>
+__device__ __forceinline__ void mma_stage(typename PrecT<PREC>::Acc (&acc)[BM / 32][BN / 32],
+                                          const unsigned char *stA, const unsigned char *stB,
+                                          int lane, int wm, int wn) {
+    static_assert(PREC == kF64 || PREC == kF32, "plain MFMA tiles only");
+    using Cfg = TileCfg<PREC, BM, BN, BK>;
+    using T = typename PrecT<PREC>::T;
+    constexpr int FM = Cfg::FM, FN = Cfg::FN;
+    const T *sa = reinterpret_cast<const T *>(stA);
+    const T *sb = reinterpret_cast<const T *>(stB);
+#pragma unroll
+    for (int ks = 0; ks < BK / 4; ++ks) {
+        const int kr = ks * 4 + (lane >> 4);
+        T a[FM], b[FN];
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+            a[i] = sa[kr * Cfg::LA::kLd + wm * Cfg::WTM + i * 16 + (lane & 15)];
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+            b[j] = sb[kr * Cfg::LB::kLd + wn * Cfg::WTN + j * 16 + (lane & 15)];
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j) {
+                if constexpr (PREC == kF64)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+                else
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+            }
+    }
+}
+
 // One BM x BN tile over contracted range [kbeg, kend).
 template <int PREC, int BM, int BN, int BK, bool AFK, bool BFK>
 __device__ __forceinline__ void gett_tile(const TileParams &p, int64_t m0, int64_t n0, int64_t kbeg,
@@ -284,94 +327,166 @@ __device__ __forceinline__ void gett_tile(const TileParams &p, int64_t m0, int64
     auto stageB = [&](int buf) { return smem + buf * Cfg::kStageBytes + Cfg::LA::kBytes; };
 
     // The K loop is branch-free.  Steps are aligned to end at kend, so only
-    // the first one can be partial (its positions below kbeg read zeros) and
-    // every step inside the loop is whole.  Each step loads the next step's
-    // values and the offsets of the step after that; the last step's loads
-    // read past kend, which is in bounds: the contracted tables carry zero
-    // padding past K (offset 0, i.e. a valid element) and a split slice that
-    // ends below K reads real positions of the next slice.  The values are
-    // never used.  A loop without branches lets the accumulators live in the
-    // MFMA registers throughout.
-    const int64_t nsteps = (kend - kbeg + BK - 1) / BK;
-    const int64_t kfirst = kend - nsteps * BK;   // may lie below kbeg (and below 0)
-    ga.load_koffs_from(p.offAK, kfirst, kbeg);
-    gb.load_koffs_from(p.offBK, kfirst, kbeg);
-    ga.template load<true>(kfirst, kbeg, va);
-    gb.template load<true>(kfirst, kbeg, vb);
-    ga.load_koffs(p.offAK, kfirst + BK);          // kfirst + BK > kbeg
-    gb.load_koffs(p.offBK, kfirst + BK);
-    ga.store(stageA(0), va);
-    gb.store(stageB(0), vb);
-    __syncthreads();
+    // the leading steps can be partial (their positions below kbeg read
+    // zeros) and every step inside the loop is whole.  Each step loads the
+    // values DEPTH steps ahead and the offsets of the step after those; the
+    // last steps' loads read past kend, which is in bounds: the contracted
+    // tables carry zero padding past K (offset 0, i.e. a valid element) and
+    // a split slice that ends below K reads real positions of the next
+    // slice.  The values are never used.  A loop without branches lets the
+    // accumulators live in the MFMA registers throughout.
+    constexpr int DEPTH = tile_depth(PREC, BM, BN, BK);
+    static_assert(DEPTH == 1 || (DEPTH == 2 && !kSplit), "load depth (BF16x3 tiles use 1)");
+    int64_t nsteps = (kend - kbeg + BK - 1) / BK;
+    if constexpr (DEPTH == 2) nsteps += nsteps & 1;   // pairs of steps (one may be all zeros)
+    const int64_t kfirst = kend - nsteps * BK;       // may lie below kbeg (and below 0)
 
-    // One K step: issue the next step's loads first (they land while the
-    // MFMAs run), compute on the current LDS stage, then stage the loaded
-    // values and synchronise.
-    for (int64_t s = 0; s < nsteps; ++s) {
-        const int cur = static_cast<int>(s & 1);
-        const int64_t k1 = kfirst + (s + 1) * BK;
-        ga.template load<false>(k1, kbeg, va);
-        gb.template load<false>(k1, kbeg, vb);
-        ga.load_koffs(p.offAK, k1 + BK);
-        gb.load_koffs(p.offBK, k1 + BK);
-        if constexpr (tile_load_fence(PREC, BM, BN, BK)) __builtin_amdgcn_sched_barrier(0);
-        if constexpr (!kSplit) {
-            const T *sa = reinterpret_cast<const T *>(stageA(cur));
-            const T *sb = reinterpret_cast<const T *>(stageB(cur));
-#pragma unroll
-            for (int ks = 0; ks < BK / 4; ++ks) {
-                const int kr = ks * 4 + (lane >> 4);
-                T a[FM], b[FN];
-#pragma unroll
-                for (int i = 0; i < FM; ++i)
-                    a[i] = sa[kr * Cfg::LA::kLd + wm * Cfg::WTM + i * 16 + (lane & 15)];
-#pragma unroll
-                for (int j = 0; j < FN; ++j)
-                    b[j] = sb[kr * Cfg::LB::kLd + wn * Cfg::WTN + j * 16 + (lane & 15)];
-#pragma unroll
-                for (int i = 0; i < FM; ++i)
-#pragma unroll
-                    for (int j = 0; j < FN; ++j) {
-                        if constexpr (PREC == kF64)
-                            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
-                        else
-                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
-                    }
-            }
-        } else {
-            const __bf16 *ahi = reinterpret_cast<const __bf16 *>(stageA(cur));
-            const __bf16 *alo = ahi + BM * Cfg::LA::kLd;
-            const __bf16 *bhi = reinterpret_cast<const __bf16 *>(stageB(cur));
-            const __bf16 *blo = bhi + BN * Cfg::LB::kLd;
-#pragma unroll
-            for (int ks = 0; ks < BK / 32; ++ks) {
-                const int kc = ks * 32 + 8 * (lane >> 4);
-                bf8_t ah[FM], al[FM], bh[FN], bl[FN];
-#pragma unroll
-                for (int i = 0; i < FM; ++i) {
-                    const int r = wm * Cfg::WTM + i * 16 + (lane & 15);
-                    ah[i] = *reinterpret_cast<const bf8_t *>(ahi + r * Cfg::LA::kLd + kc);
-                    al[i] = *reinterpret_cast<const bf8_t *>(alo + r * Cfg::LA::kLd + kc);
-                }
-#pragma unroll
-                for (int j = 0; j < FN; ++j) {
-                    const int r = wn * Cfg::WTN + j * 16 + (lane & 15);
-                    bh[j] = *reinterpret_cast<const bf8_t *>(bhi + r * Cfg::LB::kLd + kc);
-                    bl[j] = *reinterpret_cast<const bf8_t *>(blo + r * Cfg::LB::kLd + kc);
-                }
-#pragma unroll
-                for (int i = 0; i < FM; ++i)
-#pragma unroll
-                    for (int j = 0; j < FN; ++j) {
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
-                        acx[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acx[i][j], 0, 0, 0);
-                        acx[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acx[i][j], 0, 0, 0);
-                    }
-            }
-        }
-        ga.store(stageA(cur ^ 1), va);
-        gb.store(stageB(cur ^ 1), vb);
+    if constexpr (DEPTH == 1) {
+        ga.load_koffs_from(p.offAK, kfirst, kbeg);
+        gb.load_koffs_from(p.offBK, kfirst, kbeg);
+        ga.template load<true>(kfirst, kbeg, va);
+        gb.template load<true>(kfirst, kbeg, vb);
+        ga.load_koffs(p.offAK, kfirst + BK);          // kfirst + BK > kbeg
+        gb.load_koffs(p.offBK, kfirst + BK);
+        ga.store(stageA(0), va);
+        gb.store(stageB(0), vb);
         __syncthreads();
+
+        // One K step: issue the next step's loads first (they land while the
+        // MFMAs run), compute on the current LDS stage, then stage the loaded
+        // values and synchronise.
+        for (int64_t s = 0; s < nsteps; ++s) {
+            const int cur = static_cast<int>(s & 1);
+            const int64_t k1 = kfirst + (s + 1) * BK;
+            ga.template load<false>(k1, kbeg, va);
+            gb.template load<false>(k1, kbeg, vb);
+            ga.load_koffs(p.offAK, k1 + BK);
+            gb.load_koffs(p.offBK, k1 + BK);
+            if constexpr (tile_load_fence(PREC, BM, BN, BK)) __builtin_amdgcn_sched_barrier(0);
+            if constexpr (!kSplit) {
+                const T *sa = reinterpret_cast<const T *>(stageA(cur));
+                const T *sb = reinterpret_cast<const T *>(stageB(cur));
+#pragma unroll
+                for (int ks = 0; ks < BK / 4; ++ks) {
+                    const int kr = ks * 4 + (lane >> 4);
+                    T a[FM], b[FN];
+#pragma unroll
+                    for (int i = 0; i < FM; ++i)
+                        a[i] = sa[kr * Cfg::LA::kLd + wm * Cfg::WTM + i * 16 + (lane & 15)];
+#pragma unroll
+                    for (int j = 0; j < FN; ++j)
+                        b[j] = sb[kr * Cfg::LB::kLd + wn * Cfg::WTN + j * 16 + (lane & 15)];
+#pragma unroll
+                    for (int i = 0; i < FM; ++i)
+#pragma unroll
+                        for (int j = 0; j < FN; ++j) {
+                            if constexpr (PREC == kF64)
+                                acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+                            else
+                                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+                        }
+                }
+            } else {
+                const __bf16 *ahi = reinterpret_cast<const __bf16 *>(stageA(cur));
+                const __bf16 *alo = ahi + BM * Cfg::LA::kLd;
+                const __bf16 *bhi = reinterpret_cast<const __bf16 *>(stageB(cur));
+                const __bf16 *blo = bhi + BN * Cfg::LB::kLd;
+#pragma unroll
+                for (int ks = 0; ks < BK / 32; ++ks) {
+                    const int kc = ks * 32 + 8 * (lane >> 4);
+                    bf8_t ah[FM], al[FM], bh[FN], bl[FN];
+#pragma unroll
+                    for (int i = 0; i < FM; ++i) {
+                        const int r = wm * Cfg::WTM + i * 16 + (lane & 15);
+                        ah[i] = *reinterpret_cast<const bf8_t *>(ahi + r * Cfg::LA::kLd + kc);
+                        al[i] = *reinterpret_cast<const bf8_t *>(alo + r * Cfg::LA::kLd + kc);
+                    }
+#pragma unroll
+                    for (int j = 0; j < FN; ++j) {
+                        const int r = wn * Cfg::WTN + j * 16 + (lane & 15);
+                        bh[j] = *reinterpret_cast<const bf8_t *>(bhi + r * Cfg::LB::kLd + kc);
+                        bl[j] = *reinterpret_cast<const bf8_t *>(blo + r * Cfg::LB::kLd + kc);
+                    }
+#pragma unroll
+                    for (int i = 0; i < FM; ++i)
+#pragma unroll
+                        for (int j = 0; j < FN; ++j) {
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+                            acx[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acx[i][j], 0, 0, 0);
+                            acx[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acx[i][j], 0, 0, 0);
+                        }
+                }
+            }
+            ga.store(stageA(cur ^ 1), va);
+            gb.store(stageB(cur ^ 1), vb);
+            __syncthreads();
+        }
+    } else {
+        // Two register sets: set h holds the values of the steps s with
+        // s % 2 == h.  Step s loads step s + 2 into set s % 2 (staged into
+        // LDS one step earlier), computes on its LDS stage, then stages set
+        // (s + 1) % 2, loaded a whole step before, into the other LDS stage.
+        // Loads complete in issue order, so each step requests the offsets
+        // of step s + 3 before the values of step s + 2 (those use a copy of
+        // the offsets already held): the next step then waits for its
+        // offsets without waiting for values it needs only a step later.
+        using GA = Gather<PREC, BM, BK, AFK>;
+        using GB = Gather<PREC, BN, BK, BFK>;
+        T va2[GA::PER];
+        T vb2[GB::PER];
+        int64_t koa[GA::KP], kob[GB::KP];
+        ga.load_koffs_from(p.offAK, kfirst, kbeg);
+        gb.load_koffs_from(p.offBK, kfirst, kbeg);
+        ga.template load<true>(kfirst, kbeg, va);
+        gb.template load<true>(kfirst, kbeg, vb);
+        ga.load_koffs_from(p.offAK, kfirst + BK, kbeg);
+        gb.load_koffs_from(p.offBK, kfirst + BK, kbeg);
+#pragma unroll
+        for (int e = 0; e < GA::KP; ++e) koa[e] = ga.koff[e];
+#pragma unroll
+        for (int e = 0; e < GB::KP; ++e) kob[e] = gb.koff[e];
+        ga.load_koffs(p.offAK, kfirst + 2 * BK);      // kfirst + 2 BK > kbeg
+        gb.load_koffs(p.offBK, kfirst + 2 * BK);
+        ga.template load_with<true>(koa, kfirst + BK, kbeg, va2);
+        gb.template load_with<true>(kob, kfirst + BK, kbeg, vb2);
+        ga.store(stageA(0), va);
+        gb.store(stageB(0), vb);
+        __syncthreads();
+
+        for (int64_t s = 0; s < nsteps; s += 2) {
+            // even step: LDS stage 0 computed, set 1 staged into stage 1
+            const int64_t k2 = kfirst + (s + 2) * BK;
+#pragma unroll
+            for (int e = 0; e < GA::KP; ++e) koa[e] = ga.koff[e];
+#pragma unroll
+            for (int e = 0; e < GB::KP; ++e) kob[e] = gb.koff[e];
+            ga.load_koffs(p.offAK, k2 + BK);
+            gb.load_koffs(p.offBK, k2 + BK);
+            __builtin_amdgcn_sched_barrier(0);
+            ga.template load_with<false>(koa, k2, kbeg, va);
+            gb.template load_with<false>(kob, k2, kbeg, vb);
+            if constexpr (tile_load_fence(PREC, BM, BN, BK)) __builtin_amdgcn_sched_barrier(0);
+            mma_stage<PREC, BM, BN, BK>(acc, stageA(0), stageB(0), lane, wm, wn);
+            ga.store(stageA(1), va2);
+            gb.store(stageB(1), vb2);
+            __syncthreads();
+            // odd step: LDS stage 1 computed, set 0 staged into stage 0
+            const int64_t k3 = k2 + BK;
+#pragma unroll
+            for (int e = 0; e < GA::KP; ++e) koa[e] = ga.koff[e];
+#pragma unroll
+            for (int e = 0; e < GB::KP; ++e) kob[e] = gb.koff[e];
+            ga.load_koffs(p.offAK, k3 + BK);
+            gb.load_koffs(p.offBK, k3 + BK);
+            __builtin_amdgcn_sched_barrier(0);
+            ga.template load_with<false>(koa, k3, kbeg, va2);
+            gb.template load_with<false>(kob, k3, kbeg, vb2);
+            if constexpr (tile_load_fence(PREC, BM, BN, BK)) __builtin_amdgcn_sched_barrier(0);
+            mma_stage<PREC, BM, BN, BK>(acc, stageA(1), stageB(1), lane, wm, wn);
+            ga.store(stageA(0), va);
+            gb.store(stageB(0), vb);
+            __syncthreads();
+        }
     }
 
     // Epilogue.  Fragment (i, j), register v of lane l holds D[row][l%16]

@@ -359,7 +359,9 @@ def config_cc(dtype=np.float32, seed=3, with_data=True, v=96, o=32) -> Problem:
     """C[a,b,c,d] = sum_{i,j} A[a,b,i,j] B[i,j,c,d], virtual extent 96,
     occupied extent 32, dense.  Values normal(0,1) times 10^u per slice, where
     a slice fixes the operand's last mode and u ~ U(-3,3): 32 draws for A
-    (its last mode j is contracted), 96 for B (its last mode d is free)."""
+    (its last mode j is contracted), 96 for B (its last mode d is free).
+    The values are FP32 numbers; an FP64 problem holds the same values
+    widened."""
     rng = np.random.default_rng(seed)
     exta, extb = [v, v, o, o], [o, o, v, v]
     pr = Problem(4, exta, packed_incs(exta), 4, extb, packed_incs(extb), 2, [2, 3], [0, 1],
@@ -373,8 +375,8 @@ def config_cc(dtype=np.float32, seed=3, with_data=True, v=96, o=32) -> Problem:
     ub = rng.uniform(-3.0, 3.0, extb[-1])
     a = a * np.repeat(10.0 ** ua, na // exta[-1])
     b = b * np.repeat(10.0 ** ub, nb // extb[-1])
-    A = View(a.astype(dtype), 0, exta, packed_incs(exta))
-    B = View(b.astype(dtype), 0, extb, packed_incs(extb))
+    A = View(a.astype(np.float32).astype(dtype), 0, exta, packed_incs(exta))
+    B = View(b.astype(np.float32).astype(dtype), 0, extb, packed_incs(extb))
     C = make_c([v, v, v, v], rng, dtype)
     return pr.with_views(A, B, C)
 

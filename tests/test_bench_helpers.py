@@ -25,11 +25,13 @@ def test_traffic_lookup_by_schedule_and_source_hash(tmp_path):
     rec = {"read_bytes": 2.0e9, "write_bytes": 1.0e8, "algorithmic_bytes": 4.0e8,
            "kernel_source_hash": h}
     path = tmp_path / "traffic.json"
-    path.write_text(json.dumps({"f64": {"by_schedule": {"12": rec, "33": dict(rec, kernel_source_hash="0" * 16)}}}))
-    got = bench.load_traffic(str(path), "f64", 12)
+    path.write_text(json.dumps({"strided_perm": {"f64": {"by_schedule": {
+        "12": rec, "33": dict(rec, kernel_source_hash="0" * 16)}}}}))
+    got = bench.load_traffic(str(path), "strided_perm", "f64", 12)
     assert got == {"read_bytes": 2.0e9, "write_bytes": 1.0e8, "algorithmic_bytes": 4.0e8,
                    "unit": "bytes/launch"}
-    assert bench.load_traffic(str(path), "f64", 14) is None      # not profiled
-    assert bench.load_traffic(str(path), "f64", 33) is None      # kernel changed since
-    assert bench.load_traffic(str(path), "f32", 12) is None
-    assert bench.load_traffic(str(tmp_path / "missing.json"), "f64", 12) is None
+    assert bench.load_traffic(str(path), "strided_perm", "f64", 14) is None   # not profiled
+    assert bench.load_traffic(str(path), "strided_perm", "f64", 33) is None   # kernel changed
+    assert bench.load_traffic(str(path), "strided_perm", "f32", 12) is None
+    assert bench.load_traffic(str(path), "cc", "f64", 12) is None             # other workload
+    assert bench.load_traffic(str(tmp_path / "missing.json"), "strided_perm", "f64", 12) is None

@@ -170,9 +170,11 @@ def test_strided_permuted_other_readings(reading):
             check_against_oracle(pr, prec, got, first, last)
 
 
-@pytest.mark.parametrize("prec", [gett.GETT_FP32, gett.GETT_BF16X3])
+@pytest.mark.parametrize("prec", PRECS)
 def test_cc_full_size(prec):
-    pr = W.config_cc()
+    """The coupled-cluster-shaped workload at full size (FP64: the same
+    FP32 values widened), outputs checked on sampled ranges."""
+    pr = W.config_cc(dtype=np.float64 if prec == gett.GETT_FP64 else np.float32)
     got = run_gpu(pr, prec, "cc")
     total = int(np.prod(pr.extc()))
     for first, last in _samples(total):
