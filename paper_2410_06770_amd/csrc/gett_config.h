@@ -60,8 +60,8 @@ struct TileShape { int bm, bn, bk; bool load_fence; int depth; };
 // path 16x16x32 BF16 MFMA steps (BK multiple of 32).  Each workgroup is a 2x2
 // grid of waves, so BM and BN are multiples of 32.
 constexpr TileShape kTiles[4][kNumTiles] = {
-    /* FP64   */ {{64, 64, 16, true, 1}, {64, 128, 16, false, 1}, {128, 64, 16, false, 1},
-                  {128, 128, 16, true, 1}, {128, 64, 8, false, 1}},
+    /* FP64   */ {{64, 64, 16, true, 1}, {64, 128, 16, true, 1}, {128, 64, 16, false, 1},
+                  {128, 128, 16, true, 1}, {128, 64, 8, true, 1}},
     /* FP32   */ {{64, 64, 16, true, 2}, {64, 128, 16, true, 2}, {128, 64, 16, true, 2},
                   {128, 128, 16, true, 2}, {128, 128, 32, true, 2}},
     /* BF16x3 */ {{64, 64, 32, true, 1}, {64, 128, 32, true, 1}, {128, 64, 32, true, 1},

@@ -100,7 +100,7 @@ static Sched heuristic(int prec, int64_t M, int64_t N, int64_t K) {
     // Relative per-CU throughput of each tile once the chip is full, from
     // timings of the menu on large strided and dense contractions.
     static const double kSpeed[4][kNumTiles] = {
-        {0.85, 0.97, 1.0, 0.93, 0.98},  // FP64: the 128x64 tiles run 3-4 workgroups per CU
+        {0.88, 0.92, 1.0, 0.80, 0.96},  // FP64: the 128x64 tiles run 3-4 workgroups per CU
         {0.8, 0.9, 0.9, 1.0, 0.95},     // FP32
         {0.95, 0.9, 1.0, 0.85, 0.8},    // BF16x3
         {0.8, 0.9, 0.9, 1.0, 1.0}};     // FP8 (its own kernel)

@@ -101,10 +101,17 @@ template <int PREC, int ROWS, int BK, bool FASTK> struct Gather {
     static_assert(BK <= 64, "one wave holds a step's contracted offsets");
     static_assert(!kSplit || FASTK || PER % 8 == 0, "16-byte LDS chunks");
 
+    // !FASTK with plain values: every value a thread loads sits in a
+    // wave-uniform LDS column, so its contracted offset is the same for the
+    // whole wave and is read with a scalar load (one per value, no lane
+    // shuffles).  The BF16x3 loader keeps one offset per lane.
+    static constexpr bool kScalarK = !FASTK && !kSplit;
+    static constexpr int NK = kScalarK ? PER : KP;     // offsets held per step
+
     const T *base[NF];  // X + free offset of each row this thread reads
     int row[NF];        // tile row of each free offset
     int j0;             // !FASTK: wave-uniform column group; FASTK: lane position q
-    int64_t koff[KP];   // contracted offsets held by this lane for the current step
+    int64_t koff[NK];   // contracted offsets for the current step
 
     static __device__ __forceinline__ constexpr int kpos(int c) {
         return kSplit ? (c >> 1) + (c & 1) * (BK / 2) : c;
@@ -140,7 +147,10 @@ template <int PREC, int ROWS, int BK, bool FASTK> struct Gather {
     // offK[k0 + (l % BK)] (threads along the free axis pick theirs with
     // readlane), or offK[k0 + q + e * KL] when threads run along K.
     __device__ __forceinline__ void load_koffs(const int64_t *__restrict__ offK, int64_t k0) {
-        if constexpr (!FASTK) {
+        if constexpr (kScalarK) {
+#pragma unroll
+            for (int i = 0; i < PER; ++i) koff[i] = offK[k0 + col(i)];
+        } else if constexpr (!FASTK) {
             koff[0] = offK[k0 + (threadIdx.x & 63) % BK];
         } else {
 #pragma unroll
@@ -152,7 +162,13 @@ template <int PREC, int ROWS, int BK, bool FASTK> struct Gather {
     // range): positions below klo take klo's offset (their values are masked).
     __device__ __forceinline__ void load_koffs_from(const int64_t *__restrict__ offK, int64_t k0,
                                                     int64_t klo) {
-        if constexpr (!FASTK) {
+        if constexpr (kScalarK) {
+#pragma unroll
+            for (int i = 0; i < PER; ++i) {
+                const int64_t k = k0 + col(i);
+                koff[i] = offK[k < klo ? klo : k];
+            }
+        } else if constexpr (!FASTK) {
             const int64_t k = k0 + (threadIdx.x & 63) % BK;
             koff[0] = offK[k < klo ? klo : k];
         } else {
@@ -177,10 +193,17 @@ template <int PREC, int ROWS, int BK, bool FASTK> struct Gather {
     // The same with contracted offsets held elsewhere (a copy taken before
     // the next step's offsets were requested into koff).
     template <bool MASKED>
-    __device__ __forceinline__ void load_with(const int64_t (&ko_)[KP], int64_t k0, int64_t klo,
+    __device__ __forceinline__ void load_with(const int64_t (&ko_)[NK], int64_t k0, int64_t klo,
                                               T (&v)[PER]) const {
         const T *zero = reinterpret_cast<const T *>(g_gett_zero);
-        if constexpr (!FASTK) {
+        if constexpr (kScalarK) {
+#pragma unroll
+            for (int i = 0; i < PER; ++i) {
+                const T *ptr = base[0] + ko_[i];
+                if constexpr (MASKED) ptr = (k0 + col(i) >= klo) ? ptr : zero;
+                v[i] = *ptr;
+            }
+        } else if constexpr (!FASTK) {
 #pragma unroll
             for (int i = 0; i < PER; ++i) {
                 const int k = kpos(col(i));                  // uniform
@@ -434,7 +457,7 @@ __device__ __forceinline__ void gett_tile(const TileParams &p, int64_t m0, int64
         using GB = Gather<PREC, BN, BK, BFK>;
         T va2[GA::PER];
         T vb2[GB::PER];
-        int64_t koa[GA::KP], kob[GB::KP];
+        int64_t koa[GA::NK], kob[GB::NK];
         ga.load_koffs_from(p.offAK, kfirst, kbeg);
         gb.load_koffs_from(p.offBK, kfirst, kbeg);
         ga.template load<true>(kfirst, kbeg, va);
@@ -442,9 +465,9 @@ __device__ __forceinline__ void gett_tile(const TileParams &p, int64_t m0, int64
         ga.load_koffs_from(p.offAK, kfirst + BK, kbeg);
         gb.load_koffs_from(p.offBK, kfirst + BK, kbeg);
 #pragma unroll
-        for (int e = 0; e < GA::KP; ++e) koa[e] = ga.koff[e];
+        for (int e = 0; e < GA::NK; ++e) koa[e] = ga.koff[e];
 #pragma unroll
-        for (int e = 0; e < GB::KP; ++e) kob[e] = gb.koff[e];
+        for (int e = 0; e < GB::NK; ++e) kob[e] = gb.koff[e];
         ga.load_koffs(p.offAK, kfirst + 2 * BK);      // kfirst + 2 BK > kbeg
         gb.load_koffs(p.offBK, kfirst + 2 * BK);
         ga.template load_with<true>(koa, kfirst + BK, kbeg, va2);
@@ -457,9 +480,9 @@ __device__ __forceinline__ void gett_tile(const TileParams &p, int64_t m0, int64
             // even step: LDS stage 0 computed, set 1 staged into stage 1
             const int64_t k2 = kfirst + (s + 2) * BK;
 #pragma unroll
-            for (int e = 0; e < GA::KP; ++e) koa[e] = ga.koff[e];
+            for (int e = 0; e < GA::NK; ++e) koa[e] = ga.koff[e];
 #pragma unroll
-            for (int e = 0; e < GB::KP; ++e) kob[e] = gb.koff[e];
+            for (int e = 0; e < GB::NK; ++e) kob[e] = gb.koff[e];
             ga.load_koffs(p.offAK, k2 + BK);
             gb.load_koffs(p.offBK, k2 + BK);
             __builtin_amdgcn_sched_barrier(0);
@@ -473,9 +496,9 @@ __device__ __forceinline__ void gett_tile(const TileParams &p, int64_t m0, int64
             // odd step: LDS stage 1 computed, set 0 staged into stage 0
             const int64_t k3 = k2 + BK;
 #pragma unroll
-            for (int e = 0; e < GA::KP; ++e) koa[e] = ga.koff[e];
+            for (int e = 0; e < GA::NK; ++e) koa[e] = ga.koff[e];
 #pragma unroll
-            for (int e = 0; e < GB::KP; ++e) kob[e] = gb.koff[e];
+            for (int e = 0; e < GB::NK; ++e) kob[e] = gb.koff[e];
             ga.load_koffs(p.offAK, k3 + BK);
             gb.load_koffs(p.offBK, k3 + BK);
             __builtin_amdgcn_sched_barrier(0);
