@@ -22,8 +22,9 @@ as 512 separate calls ("batch").  Kernel durations come from HIP events
 recorded on the library's stream around every call.  For context only, the
 same contraction through PyTorch (rocBLAS / hipBLASLt behind it) is timed
 twice under "context": torch.einsum on the strided views (it materialises
-transposes) and a plain matmul of packed M x K and K x N matrices of the
-same sizes (a library GEMM that does none of the contraction's addressing).
+transposes) and C += A B with packed M x K and K x N matrices of the same
+sizes (torch addmm: a library GEMM that does none of the contraction's
+addressing).
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--workload strided_perm|cc]
 """
@@ -56,7 +57,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="strided_perm")
     ap.add_argument("--no-context", action="store_true",
-                    help="skip the PyTorch einsum / matmul context timings")
+                    help="skip the PyTorch einsum / addmm context timings")
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--paths", default="f64,f32,bf16x3,fp8")
@@ -290,8 +291,8 @@ def batch_leg(count, gett, W, torch, stream, reps=10):
 
 def torch_context(pr, path, At, Bt, Ct, flops, steps, warmup, torch, stream):
     """PyTorch on the same contraction, for context: einsum over the strided
-    views of the resident operands (accumulated into C's view), and a plain
-    matmul of packed M x K and K x N matrices of the same sizes."""
+    views of the resident operands (accumulated into C's view), and C += A B
+    on packed M x K and K x N matrices of the same sizes (addmm)."""
     def view(t, v):
         return torch.as_strided(t, v.ext, v.inc, v.base)
 
@@ -330,12 +331,11 @@ def torch_context(pr, path, At, Bt, Ct, flops, steps, warmup, torch, stream):
         ms = float(np.mean([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]))
         return {"ms": round(ms, 4), "tflops": round(flops / (ms * 1e-3) / 1e12, 3)}
 
-    print(f"[bench] context {path}: torch.einsum {spec} and torch.matmul", file=sys.stderr,
+    print(f"[bench] context {path}: torch.einsum {spec} and addmm", file=sys.stderr,
           flush=True)
     res = {f"torch_einsum_{path}": dict(timed(lambda: Cv.add_(torch.einsum(spec, Av, Bv))),
                                         spec=spec),
-           f"torch_matmul_{path}": dict(timed(lambda: torch.matmul(Am, Bm, out=Cm)),
-                                        shape=[M, N, K])}
+           f"torch_addmm_{path}": dict(timed(lambda: Cm.addmm_(Am, Bm)), shape=[M, N, K])}
     del Am, Bm, Cm
     return res
 
