@@ -54,20 +54,27 @@ constexpr int kTablePad = 256;      // M/N tables padded to a multiple of this
 // depth: how many K steps ahead of the MFMAs the global loads run (1 or 2).
 // Depth 2 keeps two register sets of staged values, so a load has two steps
 // of MFMA work to land in instead of one.
-struct TileShape { int bm, bn, bk; bool load_fence; int depth; };
+// addr32: when both operands' addressed spans fit 4 GB, the tile loads
+// through a uniform 64-bit base plus 32-bit lane offsets (fewer VALU
+// instructions per value; FP64/FP32 only, measured per tile).
+struct TileShape { int bm, bn, bk; bool load_fence; int depth; bool addr32; };
 
 // Tile menus.  FP64/FP32 run 16x16x4 MFMA steps (BK multiple of 4), the BF16x3
 // path 16x16x32 BF16 MFMA steps (BK multiple of 32).  Each workgroup is a 2x2
 // grid of waves, so BM and BN are multiples of 32.
 constexpr TileShape kTiles[4][kNumTiles] = {
-    /* FP64   */ {{64, 64, 16, true, 1}, {64, 128, 16, true, 1}, {128, 64, 16, false, 1},
-                  {128, 128, 16, true, 1}, {128, 64, 8, true, 1}},
-    /* FP32   */ {{64, 64, 16, true, 2}, {64, 128, 16, true, 2}, {128, 64, 16, true, 2},
-                  {128, 128, 16, true, 2}, {128, 128, 32, true, 2}},
-    /* BF16x3 */ {{64, 64, 32, true, 1}, {64, 128, 32, true, 1}, {128, 64, 32, true, 1},
-                  {128, 128, 32, true, 1}, {128, 128, 64, true, 1}},
-    /* FP8    */ {{64, 64, 128, true, 1}, {64, 128, 128, true, 1}, {128, 64, 128, true, 1},
-                  {128, 128, 128, true, 1}, {128, 128, 128, true, 1}},
+    /* FP64   */ {{64, 64, 16, true, 1, true}, {64, 128, 16, true, 1, true},
+                  {128, 64, 16, false, 1, false}, {128, 128, 16, true, 1, true},
+                  {128, 64, 8, true, 1, false}},
+    /* FP32   */ {{64, 64, 16, true, 2, true}, {64, 128, 16, true, 2, true},
+                  {128, 64, 16, true, 2, true}, {128, 128, 16, true, 2, true},
+                  {128, 128, 32, true, 2, true}},
+    /* BF16x3 */ {{64, 64, 32, true, 1, false}, {64, 128, 32, true, 1, false},
+                  {128, 64, 32, true, 1, false}, {128, 128, 32, true, 1, false},
+                  {128, 128, 64, true, 1, false}},
+    /* FP8    */ {{64, 64, 128, true, 1, false}, {64, 128, 128, true, 1, false},
+                  {128, 64, 128, true, 1, false}, {128, 128, 128, true, 1, false},
+                  {128, 128, 128, true, 1, false}},
 };
 
 // Flag of the menu entry with this shape (first match).
@@ -76,6 +83,13 @@ constexpr bool tile_load_fence(int prec, int bm, int bn, int bk) {
         if (kTiles[prec][t].bm == bm && kTiles[prec][t].bn == bn && kTiles[prec][t].bk == bk)
             return kTiles[prec][t].load_fence;
     return true;
+}
+
+constexpr bool tile_addr32(int prec, int bm, int bn, int bk) {
+    for (int t = 0; t < kNumTiles; ++t)
+        if (kTiles[prec][t].bm == bm && kTiles[prec][t].bn == bn && kTiles[prec][t].bk == bk)
+            return kTiles[prec][t].addr32;
+    return false;
 }
 
 constexpr int tile_depth(int prec, int bm, int bn, int bk) {
@@ -98,6 +112,13 @@ struct TileParams {
     int32_t tilesM, tilesN, splits;
     int32_t bBoxX;                  // B loader sub-box width along its fast free mode
     double *ws;                     // split-K partials [split][M][N], n fastest; null = direct
+    // Lowest element offset either operand addresses (free plus contracted
+    // table minima, padding included), and whether each operand's whole
+    // addressed span fits 32-bit byte offsets from there: then the FP64/FP32
+    // tiles address it as a uniform 64-bit base plus a 32-bit lane offset.
+    int64_t aLo, bLo;
+    int32_t off32;
+    int32_t pad_;
 };
 
 // One problem of a batched launch (device-resident descriptor).

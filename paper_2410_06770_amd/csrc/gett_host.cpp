@@ -143,6 +143,7 @@ struct TableSet {
     Canon cn;
     int64_t Mp = 0, Np = 0, Kp = 0;
     int64_t *d_tab = nullptr;   // offAM, offCM [Mp]; offBN, offCN [Np]; offAK, offBK [Kp]
+    int64_t aLo = 0, aSpan = 0, bLo = 0, bSpan = 0;   // addressed element range of A and B
     ~TableSet() {
         if (d_tab) (void)hipFree(d_tab);
     }
@@ -177,6 +178,24 @@ static int upload_tables(TableSet &t) {
     p += 2 * t.Np;
     group_offsets(c.k, 0, t.Kp, p);
     group_offsets(c.k, 1, t.Kp, p + t.Kp);
+    // Range of element offsets each operand's loads can reach: free table
+    // plus contracted table, padding (offset 0) included.
+    auto range = [](const int64_t *v, int64_t n, int64_t &lo, int64_t &hi) {
+        lo = hi = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            lo = std::min(lo, v[i]);
+            hi = std::max(hi, v[i]);
+        }
+    };
+    int64_t fl, fh, kl, kh;
+    range(h.data(), t.Mp, fl, fh);
+    range(p, t.Kp, kl, kh);
+    t.aLo = fl + kl;
+    t.aSpan = (fh - fl) + (kh - kl);
+    range(h.data() + 2 * t.Mp, t.Np, fl, fh);
+    range(p + t.Kp, t.Kp, kl, kh);
+    t.bLo = fl + kl;
+    t.bSpan = (fh - fl) + (kh - kl);
     const size_t bytes = h.size() * sizeof(int64_t);
     if (hipMalloc(&t.d_tab, bytes) != hipSuccess) return GETT_ERR_ALLOC;
     if (hipMemcpy(t.d_tab, h.data(), bytes, hipMemcpyHostToDevice) != hipSuccess)
@@ -278,6 +297,12 @@ static TileParams make_params(const Plan &pl, const void *A, const void *B, void
     p.kPerSplit = per;
     p.bBoxX = c.boxX > 0 ? c.boxX : ts.bn;
     p.ws = nullptr;
+    p.aLo = t.aLo;
+    p.bLo = t.bLo;
+    const int64_t esz = pl.prec == kF64 ? 8 : 4;
+    const int64_t lim = (int64_t)1 << 32;
+    p.off32 = (t.aSpan < lim / esz && t.bSpan < lim / esz) ? 1 : 0;
+    p.pad_ = 0;
     return p;
 }
 

@@ -89,7 +89,7 @@ __device__ __forceinline__ void bf16x3_split_pair(float x0, float x1, uint32_t &
 // lanes read neighbouring positions) holds two values that are neighbours in
 // LDS and writes each plane as one 4-byte word, and a thread that runs along
 // the free axis holds a contiguous run of columns and writes 16-byte chunks.
-template <int PREC, int ROWS, int BK, bool FASTK> struct Gather {
+template <int PREC, int ROWS, int BK, bool FASTK, bool O32 = false> struct Gather {
     using T = typename PrecT<PREC>::T;
     static constexpr bool kSplit = PREC == kBF3;
     static constexpr int PER = ROWS * BK / kThreads;   // values per thread
@@ -107,11 +107,18 @@ template <int PREC, int ROWS, int BK, bool FASTK> struct Gather {
     // shuffles).  The BF16x3 loader keeps one offset per lane.
     static constexpr bool kScalarK = !FASTK && !kSplit;
     static constexpr int NK = kScalarK ? PER : KP;     // offsets held per step
+    // O32 (plain values, operand span below 4 GB): the whole-step loads take
+    // a wave-uniform 64-bit base and a 32-bit byte offset per lane, so a
+    // value costs one 32-bit add (lanes along K) or none (lanes along the
+    // free axis, whose contracted offset joins the uniform base).
+    static_assert(!O32 || !kSplit, "32-bit addressing is for plain values");
 
     const T *base[NF];  // X + free offset of each row this thread reads
     int row[NF];        // tile row of each free offset
     int j0;             // !FASTK: wave-uniform column group; FASTK: lane position q
     int64_t koff[NK];   // contracted offsets for the current step
+    const T *lo;        // O32: X + the lowest element offset the operand addresses
+    uint32_t vrow[NF];  // O32: byte offset of each row's free offset from lo
 
     static __device__ __forceinline__ constexpr int kpos(int c) {
         return kSplit ? (c >> 1) + (c & 1) * (BK / 2) : c;
@@ -122,7 +129,8 @@ template <int PREC, int ROWS, int BK, bool FASTK> struct Gather {
     }
 
     __device__ void init(const T *X, int t, int64_t r0, int64_t nrows,
-                         const int64_t *__restrict__ offFree, int boxX) {
+                         const int64_t *__restrict__ offFree, int boxX, int64_t xlo = 0) {
+        if constexpr (O32) lo = X + xlo;
         if constexpr (!FASTK) {
             const int il = t % ROWS;                 // consecutive threads: consecutive il
             const int x = il % boxX, y = il / boxX;  // loader walks the box's x side
@@ -130,6 +138,7 @@ template <int PREC, int ROWS, int BK, bool FASTK> struct Gather {
             const int64_t g = r0 + r;
             row[0] = r;
             base[0] = X + offFree[g];
+            if constexpr (O32) vrow[0] = (uint32_t)(offFree[g] - xlo) * (uint32_t)sizeof(T);
             j0 = __builtin_amdgcn_readfirstlane(t / ROWS);
         } else {
             j0 = t % KL;
@@ -139,6 +148,7 @@ template <int PREC, int ROWS, int BK, bool FASTK> struct Gather {
                 const int64_t g = r0 + r;
                 row[i] = r;
                 base[i] = X + offFree[g];
+                if constexpr (O32) vrow[i] = (uint32_t)(offFree[g] - xlo) * (uint32_t)sizeof(T);
             }
         }
     }
@@ -152,6 +162,11 @@ template <int PREC, int ROWS, int BK, bool FASTK> struct Gather {
             for (int i = 0; i < PER; ++i) koff[i] = offK[k0 + col(i)];
         } else if constexpr (!FASTK) {
             koff[0] = offK[k0 + (threadIdx.x & 63) % BK];
+        } else if constexpr (O32) {
+            // only the low word takes part in 32-bit addressing: load just it
+            const uint32_t *lo32 = reinterpret_cast<const uint32_t *>(offK);
+#pragma unroll
+            for (int e = 0; e < KP; ++e) koff[e] = lo32[2 * (k0 + j0 + e * KL)];
         } else {
 #pragma unroll
             for (int e = 0; e < KP; ++e) koff[e] = offK[k0 + j0 + e * KL];
@@ -196,7 +211,34 @@ template <int PREC, int ROWS, int BK, bool FASTK> struct Gather {
     __device__ __forceinline__ void load_with(const int64_t (&ko_)[NK], int64_t k0, int64_t klo,
                                               T (&v)[PER]) const {
         const T *zero = reinterpret_cast<const T *>(g_gett_zero);
-        if constexpr (kScalarK) {
+        if constexpr (O32 && !MASKED) {
+            // lo + vrow + (contracted offset) * size, all within 4 GB of lo:
+            // the 32-bit sum wraps to the exact byte offset.
+            const char *b = reinterpret_cast<const char *>(lo);
+            if constexpr (kScalarK) {
+                // The empty asm statements keep the uniform base in SGPRs and
+                // the lane offset a 32-bit value inside the loop, so the load
+                // is selected as base + zero-extended offset (no 64-bit add).
+                uint32_t vr = vrow[0];
+                asm("" : "+v"(vr));
+#pragma unroll
+                for (int i = 0; i < PER; ++i) {
+                    uint64_t bk = reinterpret_cast<uint64_t>(lo + ko_[i]);
+                    asm("" : "+s"(bk));
+                    using GT = const __attribute__((address_space(1))) char;
+                    v[i] = *reinterpret_cast<const __attribute__((address_space(1))) T *>(
+                        reinterpret_cast<GT *>(bk) + vr);
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < KP; ++e) {
+                    const uint32_t kb = (uint32_t)ko_[e] * (uint32_t)sizeof(T);
+#pragma unroll
+                    for (int i = 0; i < NF; ++i)
+                        v[i * KP + e] = *reinterpret_cast<const T *>(b + (uint32_t)(vrow[i] + kb));
+                }
+            }
+        } else if constexpr (kScalarK) {
 #pragma unroll
             for (int i = 0; i < PER; ++i) {
                 const T *ptr = base[0] + ko_[i];
@@ -312,7 +354,7 @@ __device__ __forceinline__ void mma_stage(typename PrecT<PREC>::Acc (&acc)[BM / 
 }
 
 // One BM x BN tile over contracted range [kbeg, kend).
-template <int PREC, int BM, int BN, int BK, bool AFK, bool BFK>
+template <int PREC, int BM, int BN, int BK, bool AFK, bool BFK, bool O32 = false>
 __device__ __forceinline__ void gett_tile(const TileParams &p, int64_t m0, int64_t n0, int64_t kbeg,
                                           int64_t kend, int split, unsigned char *smem) {
     using Cfg = TileCfg<PREC, BM, BN, BK>;
@@ -326,12 +368,12 @@ __device__ __forceinline__ void gett_tile(const TileParams &p, int64_t m0, int64
     const int w = wave_id();
     const int wm = w >> 1, wn = w & 1;
 
-    Gather<PREC, BM, BK, AFK> ga;
-    Gather<PREC, BN, BK, BFK> gb;
+    Gather<PREC, BM, BK, AFK, O32> ga;
+    Gather<PREC, BN, BK, BFK, O32> gb;
     const T *__restrict__ A = static_cast<const T *>(p.A);
     const T *__restrict__ B = static_cast<const T *>(p.B);
-    ga.init(A, t, m0, p.M, p.offAM, BM);
-    gb.init(B, t, n0, p.N, p.offBN, p.bBoxX);
+    ga.init(A, t, m0, p.M, p.offAM, BM, p.aLo);
+    gb.init(B, t, n0, p.N, p.offBN, p.bBoxX, p.bLo);
 
     Acc acc[FM][FN];
     Acc acx[kSplit ? FM : 1][kSplit ? FN : 1];
@@ -343,8 +385,8 @@ __device__ __forceinline__ void gett_tile(const TileParams &p, int64_t m0, int64
             if constexpr (kSplit) acx[i][j] = Acc{};
         }
 
-    T va[Gather<PREC, BM, BK, AFK>::PER];
-    T vb[Gather<PREC, BN, BK, BFK>::PER];
+    T va[Gather<PREC, BM, BK, AFK, O32>::PER];
+    T vb[Gather<PREC, BN, BK, BFK, O32>::PER];
 
     auto stageA = [&](int buf) { return smem + buf * Cfg::kStageBytes; };
     auto stageB = [&](int buf) { return smem + buf * Cfg::kStageBytes + Cfg::LA::kBytes; };
@@ -385,7 +427,7 @@ __device__ __forceinline__ void gett_tile(const TileParams &p, int64_t m0, int64
             gb.template load<false>(k1, kbeg, vb);
             ga.load_koffs(p.offAK, k1 + BK);
             gb.load_koffs(p.offBK, k1 + BK);
-            if constexpr (tile_load_fence(PREC, BM, BN, BK)) __builtin_amdgcn_sched_barrier(0);
+            if constexpr (O32 || tile_load_fence(PREC, BM, BN, BK)) __builtin_amdgcn_sched_barrier(0);
             if constexpr (!kSplit) {
                 const T *sa = reinterpret_cast<const T *>(stageA(cur));
                 const T *sb = reinterpret_cast<const T *>(stageB(cur));
@@ -453,8 +495,8 @@ __device__ __forceinline__ void gett_tile(const TileParams &p, int64_t m0, int64
         // of step s + 3 before the values of step s + 2 (those use a copy of
         // the offsets already held): the next step then waits for its
         // offsets without waiting for values it needs only a step later.
-        using GA = Gather<PREC, BM, BK, AFK>;
-        using GB = Gather<PREC, BN, BK, BFK>;
+        using GA = Gather<PREC, BM, BK, AFK, O32>;
+        using GB = Gather<PREC, BN, BK, BFK, O32>;
         T va2[GA::PER];
         T vb2[GB::PER];
         int64_t koa[GA::NK], kob[GB::NK];
@@ -488,7 +530,7 @@ __device__ __forceinline__ void gett_tile(const TileParams &p, int64_t m0, int64
             __builtin_amdgcn_sched_barrier(0);
             ga.template load_with<false>(koa, k2, kbeg, va);
             gb.template load_with<false>(kob, k2, kbeg, vb);
-            if constexpr (tile_load_fence(PREC, BM, BN, BK)) __builtin_amdgcn_sched_barrier(0);
+            if constexpr (O32 || tile_load_fence(PREC, BM, BN, BK)) __builtin_amdgcn_sched_barrier(0);
             mma_stage<PREC, BM, BN, BK>(acc, stageA(0), stageB(0), lane, wm, wn);
             ga.store(stageA(1), va2);
             gb.store(stageB(1), vb2);
@@ -504,7 +546,7 @@ __device__ __forceinline__ void gett_tile(const TileParams &p, int64_t m0, int64
             __builtin_amdgcn_sched_barrier(0);
             ga.template load_with<false>(koa, k3, kbeg, va2);
             gb.template load_with<false>(kob, k3, kbeg, vb2);
-            if constexpr (tile_load_fence(PREC, BM, BN, BK)) __builtin_amdgcn_sched_barrier(0);
+            if constexpr (O32 || tile_load_fence(PREC, BM, BN, BK)) __builtin_amdgcn_sched_barrier(0);
             mma_stage<PREC, BM, BN, BK>(acc, stageA(1), stageB(1), lane, wm, wn);
             ga.store(stageA(0), va);
             gb.store(stageB(0), vb);
@@ -549,7 +591,7 @@ __device__ __forceinline__ void gett_tile(const TileParams &p, int64_t m0, int64
     }
 }
 
-template <int PREC, int BM, int BN, int BK, bool AFK, bool BFK>
+template <int PREC, int BM, int BN, int BK, bool AFK, bool BFK, bool O32>
 __global__ __launch_bounds__(kThreads) void gett_tile_kernel(TileParams p) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int tiles = p.tilesM * p.tilesN;
@@ -561,8 +603,8 @@ __global__ __launch_bounds__(kThreads) void gett_tile_kernel(TileParams p) {
     const int64_t kbeg = (int64_t)split * p.kPerSplit;
     int64_t kend = kbeg + p.kPerSplit;
     if (kend > p.K) kend = p.K;
-    gett_tile<PREC, BM, BN, BK, AFK, BFK>(p, (int64_t)tm * BM, (int64_t)tn * BN, kbeg, kend, split,
-                                          smem);
+    gett_tile<PREC, BM, BN, BK, AFK, BFK, O32>(p, (int64_t)tm * BM, (int64_t)tn * BN, kbeg, kend,
+                                               split, smem);
 }
 
 // C[off(m,n)] = C_in + sum_s ws[s][m][n], in FP64, s in order.
@@ -645,10 +687,10 @@ __global__ __launch_bounds__(256) void batch_reduce_kernel(const BatchProblem *_
 }
 
 // Host-side launch helpers (instantiated per precision in its own file).
-template <int PREC, int BM, int BN, int BK, bool AFK, bool BFK>
+template <int PREC, int BM, int BN, int BK, bool AFK, bool BFK, bool O32>
 static int launch_one(const TileParams &p, hipStream_t s) {
     using Cfg = TileCfg<PREC, BM, BN, BK>;
-    auto kern = gett_tile_kernel<PREC, BM, BN, BK, AFK, BFK>;
+    auto kern = gett_tile_kernel<PREC, BM, BN, BK, AFK, BFK, O32>;
     static bool attr_set = false;   // per instantiation; LDS above 64 KB needs opting in
     if (!attr_set) {
         if (hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
@@ -663,14 +705,24 @@ static int launch_one(const TileParams &p, hipStream_t s) {
     return launch_status();
 }
 
+template <int PREC, int BM, int BN, int BK, bool O32>
+static int launch_fast_o(bool afk, bool bfk, const TileParams &p, hipStream_t s) {
+    if (afk) {
+        if (bfk) return launch_one<PREC, BM, BN, BK, true, true, O32>(p, s);
+        return launch_one<PREC, BM, BN, BK, true, false, O32>(p, s);
+    }
+    if (bfk) return launch_one<PREC, BM, BN, BK, false, true, O32>(p, s);
+    return launch_one<PREC, BM, BN, BK, false, false, O32>(p, s);
+}
+
+// Tiles marked addr32 in the menu take the 32-bit addressing variant when
+// both operands' spans allow it (FP64/FP32 only).
 template <int PREC, int BM, int BN, int BK>
 static int launch_fast(bool afk, bool bfk, const TileParams &p, hipStream_t s) {
-    if (afk) {
-        if (bfk) return launch_one<PREC, BM, BN, BK, true, true>(p, s);
-        return launch_one<PREC, BM, BN, BK, true, false>(p, s);
+    if constexpr (PREC != kBF3 && tile_addr32(PREC, BM, BN, BK)) {
+        if (p.off32) return launch_fast_o<PREC, BM, BN, BK, true>(afk, bfk, p, s);
     }
-    if (bfk) return launch_one<PREC, BM, BN, BK, false, true>(p, s);
-    return launch_one<PREC, BM, BN, BK, false, false>(p, s);
+    return launch_fast_o<PREC, BM, BN, BK, false>(afk, bfk, p, s);
 }
 
 template <int PREC>
