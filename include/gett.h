@@ -249,7 +249,11 @@ int gett_features(int prec, int64_t ranka, const int64_t *exta, const int64_t *i
 /* Planner introspection (host only, no HIP call): canonical groups for the
    heuristic schedule with order ORDER and tile T.  out receives
    [swapped, M, N, K, nM, nN, nK, aFastK, bFastK, bBoxX, then per group mode
-   (ext, inc_1, inc_2) for M (incA, incC), N (incB, incC), K (incA, incB)];
+   (ext, inc_1, inc_2) for M (incA, incC), N (incB, incC), K (incA, incB),
+   then aLo, aSpan, bLo, bSpan: the lowest element offset each (canonical)
+   operand can address and the span above it, padding included; the FP64
+   and FP32 tiles use 32-bit lane offsets when both spans times the element
+   size are below 2^32];
    returns the number of values written or a negative INFO. */
 int64_t gett_plan_describe(int prec, int64_t order, int64_t tile, int64_t ranka,
                            const int64_t *exta, const int64_t *inca, int64_t rankb,

@@ -178,24 +178,7 @@ static int upload_tables(TableSet &t) {
     p += 2 * t.Np;
     group_offsets(c.k, 0, t.Kp, p);
     group_offsets(c.k, 1, t.Kp, p + t.Kp);
-    // Range of element offsets each operand's loads can reach: free table
-    // plus contracted table, padding (offset 0) included.
-    auto range = [](const int64_t *v, int64_t n, int64_t &lo, int64_t &hi) {
-        lo = hi = 0;
-        for (int64_t i = 0; i < n; ++i) {
-            lo = std::min(lo, v[i]);
-            hi = std::max(hi, v[i]);
-        }
-    };
-    int64_t fl, fh, kl, kh;
-    range(h.data(), t.Mp, fl, fh);
-    range(p, t.Kp, kl, kh);
-    t.aLo = fl + kl;
-    t.aSpan = (fh - fl) + (kh - kl);
-    range(h.data() + 2 * t.Mp, t.Np, fl, fh);
-    range(p + t.Kp, t.Kp, kl, kh);
-    t.bLo = fl + kl;
-    t.bSpan = (fh - fl) + (kh - kl);
+    operand_ranges(c, t.aLo, t.aSpan, t.bLo, t.bSpan);
     const size_t bytes = h.size() * sizeof(int64_t);
     if (hipMalloc(&t.d_tab, bytes) != hipSuccess) return GETT_ERR_ALLOC;
     if (hipMemcpy(t.d_tab, h.data(), bytes, hipMemcpyHostToDevice) != hipSuccess)
@@ -1275,6 +1258,9 @@ static int64_t describe(int prec, int64_t order, int64_t tile, const Args &a, in
                 v.push_back(x.i0);
                 v.push_back(x.i1);
             }
+        int64_t r[4];
+        operand_ranges(c, r[0], r[1], r[2], r[3]);
+        v.insert(v.end(), r, r + 4);
     } else {
         if (c.empty) return 0;
         v.resize(2 * (c.M + c.N + c.K));

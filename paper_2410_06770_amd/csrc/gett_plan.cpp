@@ -276,6 +276,27 @@ void group_offsets(const std::vector<GMode> &g, int slot, int64_t padded, int64_
     for (int64_t idx = total; idx < padded; ++idx) out[idx] = 0;
 }
 
+void group_range(const std::vector<GMode> &g, int slot, int64_t &lo, int64_t &hi) {
+    lo = hi = 0;
+    for (const GMode &m : g) {
+        const int64_t span = (slot ? m.i1 : m.i0) * (m.ext - 1);
+        if (span < 0) lo += span;
+        else hi += span;
+    }
+}
+
+void operand_ranges(const Canon &c, int64_t &aLo, int64_t &aSpan, int64_t &bLo, int64_t &bSpan) {
+    int64_t fl, fh, kl, kh;
+    group_range(c.m, 0, fl, fh);
+    group_range(c.k, 0, kl, kh);
+    aLo = fl + kl;
+    aSpan = (fh - fl) + (kh - kl);
+    group_range(c.n, 0, fl, fh);
+    group_range(c.k, 1, kl, kh);
+    bLo = fl + kl;
+    bSpan = (fh - fl) + (kh - kl);
+}
+
 void canonical_groups(const Args &a, std::vector<GMode> &rowsA, std::vector<GMode> &rowsB,
                       std::vector<GMode> &kAB) {
     raw_groups(a, rowsA, rowsB, kAB);

@@ -53,6 +53,16 @@ Canon canonicalise(const Args &a, int order, int bn);
 // `padded` entries; first mode fastest.
 void group_offsets(const std::vector<GMode> &g, int slot, int64_t padded, int64_t *out);
 
+// Smallest and largest entry of a group's offset table for slot s (padding
+// zeros included): every coordinate combination occurs, so each mode
+// contributes min(0, inc (ext - 1)) and max(0, inc (ext - 1)).
+void group_range(const std::vector<GMode> &g, int slot, int64_t &lo, int64_t &hi);
+
+// Element range each operand of a canonical form can address (free table
+// plus contracted table): lowest offset and span, for A (M, K slot 0) and
+// B (N, K slot 1).
+void operand_ranges(const Canon &c, int64_t &aLo, int64_t &aSpan, int64_t &bLo, int64_t &bSpan);
+
 // Canonical (schedule-independent) orders used by the FP8 path: rows of A are
 // A's free modes in ascending order, rows of B likewise, contracted positions
 // follow the pairs in CONTA order; first fastest.  Extent-1 and zero extents

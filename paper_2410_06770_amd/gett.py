@@ -311,15 +311,18 @@ def _describe(fn, prec, order, tile, args):
 
 
 def gett_plan_describe(prec, order, tile, *args):
-    """Canonical groups: dict(swapped, M, N, K, m, n, k, aFastK, bFastK, boxX)
-    with each group a list of (ext, inc0, inc1); or a negative INFO."""
+    """Canonical groups: dict(swapped, M, N, K, m, n, k, aFastK, bFastK, boxX,
+    aLo, aSpan, bLo, bSpan) with each group a list of (ext, inc0, inc1); or a
+    negative INFO."""
     v = _describe(lib().gett_plan_describe, prec, order, tile, args)
     if isinstance(v, int):
         return v
     nm, nn, nk = v[4], v[5], v[6]
     modes = [tuple(v[10 + 3 * i: 13 + 3 * i]) for i in range(nm + nn + nk)]
+    r = v[10 + 3 * (nm + nn + nk):]
     return dict(swapped=bool(v[0]), M=v[1], N=v[2], K=v[3], m=modes[:nm], n=modes[nm:nm + nn],
-                k=modes[nm + nn:], aFastK=bool(v[7]), bFastK=bool(v[8]), boxX=v[9])
+                k=modes[nm + nn:], aFastK=bool(v[7]), bFastK=bool(v[8]), boxX=v[9],
+                aLo=r[0], aSpan=r[1], bLo=r[2], bSpan=r[3])
 
 
 def gett_plan_tables(prec, order, tile, *args):

@@ -363,3 +363,52 @@ def test_offsets_beyond_int32(prec):
     torch.cuda.empty_cache()
     check_against_oracle(pr, prec, got)
     check_outside(pr, got)
+
+
+@pytest.mark.parametrize("prec", [gett.GETT_FP64, gett.GETT_FP32])
+@pytest.mark.parametrize("side", ["below", "above"])
+def test_addressing_at_the_4gb_boundary(prec, side):
+    """A[a, k] of extents (7, 33) with increments (-1, step), the pointer six
+    elements into its parent, so the operand spans 6 + 32 step elements: just
+    under 4 GB (the tile's 32-bit lane offsets, whose sums wrap to the exact
+    byte offset) or just over (64-bit lane pointers).  Run on a tile that
+    takes 32-bit offsets when it can; the result must equal the oracle's on a
+    packed copy of the same values."""
+    import torch
+    dtype = np.float64 if prec == gett.GETT_FP64 else np.float32
+    tdt = torch.float64 if prec == gett.GETT_FP64 else torch.float32
+    esz = np.dtype(dtype).itemsize
+    limit = 2 ** 32 // esz                         # span bound of 32-bit addressing
+    step = (limit - 7) // 32 if side == "below" else limit // 32
+    base = 6
+    rng = np.random.default_rng(4 * esz + (side == "above"))
+    pr = W.build_problem(rng, (2, [7, 33], 2, [33, 9], 1, [1], [0], [0, 1]), dtype,
+                         dist="normal", name="addr32")
+    a_vals = pr.A.buf[pr.A.element_index()]
+    aa, kk = np.meshgrid(np.arange(7), np.arange(33), indexing="ij")
+    off = (base - aa + kk * step).reshape(-1, order="F")
+    args = (2, [7, 33], [-1, step], pr.rankb, pr.extb, pr.incb, pr.conts, pr.conta, pr.contb,
+            pr.perm, pr.incc)
+    tile = 0                                      # takes 32-bit offsets when the spans allow
+    d = gett.gett_plan_describe(prec, 0, tile, *args)
+    span = max(d["aSpan"], d["bSpan"])
+    assert span == 6 + 32 * step
+    assert (span < limit) == (side == "below")
+    print(f"\n[gpu] 4 GB boundary prec={prec} side={side} span={span} elements", flush=True)
+    parent = torch.full((int(off.max()) + 1,), float("nan"), dtype=tdt, device="cuda")
+    parent[torch.from_numpy(off).cuda()] = torch.from_numpy(np.ascontiguousarray(a_vals)).cuda()
+    Bt, b = to_device(pr.B)
+    Ct, c = to_device(pr.C)
+    a = parent.data_ptr() + base * parent.element_size()
+    assert gett.gett_set_schedule(gett.schedule_id(tile, 0, 0)) == 0
+    try:
+        rc = gett.ENTRY[prec](*args[:3], a, *args[3:6], b, *args[6:], c)
+    finally:
+        gett.gett_set_schedule(-1)
+    assert rc == 0, gett.strerror(rc)
+    torch.cuda.synchronize()
+    got = Ct.cpu().numpy()
+    del parent
+    torch.cuda.empty_cache()
+    check_against_oracle(pr, prec, got)
+    check_outside(pr, got)

@@ -106,3 +106,29 @@ def test_features_shape_and_determinism():
     assert f1.shape == (64,) and np.all(np.isfinite(f1))
     assert np.array_equal(f1, f2)
     assert f1[36] == pytest.approx(np.log2(2.0 * 3072 * 4032 * 3840), rel=1e-6)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_operand_ranges_match_the_tables(seed):
+    """The addressed range the planner reports per operand (lowest offset and
+    span, used to choose 32-bit lane offsets) is the min/max of its free
+    table plus its contracted table, negative increments included."""
+    rng = np.random.default_rng(seed + 400)
+    for rep in range(8):
+        sig = W.random_signature(rng)
+        layouts = [("packed", "packed"), ("sub", "step2"), ("step2", "sub")][rep % 3]
+        pr = W.build_problem(rng, sig, np.float64, layouts[0], layouts[1])
+        args = list(problem_args(pr))
+        if rep % 2:   # flip some increments negative
+            args[2] = [-x if i % 2 else x for i, x in enumerate(args[2])]
+            args[5] = [-x for x in args[5]]
+        for order in range(4):
+            got = gett.gett_plan_tables(0, order, 0, *args)
+            if isinstance(got, int) or got[1]["M"] * got[1]["N"] * got[1]["K"] == 0:
+                continue
+            (am, cm, bn, cn, ak, bk), d = got
+            span = lambda *t: sum(int(x.max()) - int(x.min()) for x in t)
+            assert d["aLo"] == int(am.min()) + int(ak.min()), (sig, order)
+            assert d["aSpan"] == span(am, ak), (sig, order)
+            assert d["bLo"] == int(bn.min()) + int(bk.min()), (sig, order)
+            assert d["bSpan"] == span(bn, bk), (sig, order)
