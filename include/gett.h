@@ -86,7 +86,14 @@ extern "C" {
 /* Schedule policies (gett_set_policy).  Environment: GETT_POLICY =
    heuristic | predict | autotune sets the initial policy; GETT_MODEL names a
    predictor weights file loaded on the first prediction when none was loaded
-   with gett_load_predictor; GETT_LOG=1 prints each new plan to stderr. */
+   with gett_load_predictor; GETT_LOG=1 prints each new plan to stderr (with
+   the source of its schedule: forced, heuristic, predictor, autotuned, tuned
+   in this process, or tune-db).  GETT_TUNE_DB names a text file that keeps
+   the AUTOTUNE policy's choices across processes: read on the first tuning
+   decision (a missing file is an empty one), one line appended per newly
+   tuned signature (its integers, " = ", schedule id, median microseconds);
+   a signature found there is not timed again.  Concurrent processes may
+   append to one file; a later line for a signature wins. */
 #define GETT_HEURISTIC 0   /* built-in rules (default) */
 #define GETT_PREDICT   1   /* MLP schedule predictor (gett_load_predictor) */
 #define GETT_AUTOTUNE  2   /* time the whole schedule menu on a plan-cache miss */
@@ -215,8 +222,18 @@ int64_t gett_num_tiles(int prec);
 int gett_tile_shape(int prec, int64_t t, int64_t *out);
 /* Force one schedule for every following call on any thread (id < 0 clears). */
 int gett_set_schedule(int64_t id);
-/* Schedule chosen for the last plan built by the calling thread (or -1). */
+/* Schedule the calling thread's last call ran (or -1); a split schedule that
+   ran unsplit because of the workspace cap reports split option 0. */
 int64_t gett_last_schedule(void);
+
+/* Cap, in bytes, on the FP64 partial-sum workspace of split-K schedules
+   (initial value from GETT_MAX_WORKSPACE, default unlimited).  A call whose
+   schedule would need more, or whose workspace cannot be allocated, runs the
+   same tile and mode order without splitting K (same arithmetic apart from
+   the summation order); a batch whose graph is built under the cap cuts no
+   further problems along K once their partials would exceed it.  Returns 0,
+   or GETT_ERR_STATE for a negative size. */
+int gett_set_max_workspace(int64_t bytes);
 
 /* Autotuner: time every valid schedule of the menu for one problem of
    precision PREC (the 14 xGETT arguments, device data; C is overwritten by

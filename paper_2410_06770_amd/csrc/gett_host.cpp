@@ -36,6 +36,17 @@ static int policy_from_env() {
     return GETT_HEURISTIC;
 }
 static std::atomic<int> g_policy{policy_from_env()};
+// Cap on split-K workspace bytes (GETT_MAX_WORKSPACE, gett_set_max_workspace):
+// a split schedule whose FP64 partials would exceed it, or whose workspace
+// cannot be allocated, runs unsplit; batches stop cutting problems along K.
+static int64_t max_ws_from_env() {
+    const char *e = getenv("GETT_MAX_WORKSPACE");
+    if (!e || !*e) return INT64_MAX;
+    char *end = nullptr;
+    const long long v = strtoll(e, &end, 10);
+    return (end && *end == 0 && v >= 0) ? (int64_t)v : INT64_MAX;
+}
+static std::atomic<int64_t> g_max_ws{max_ws_from_env()};
 static std::atomic<int64_t> g_forced{-1};
 static std::mutex g_mu;   // guards the caches below
 
@@ -208,7 +219,8 @@ static int get_tables(const Args &a, int order, int bn, int dev, TableSet **out)
     return 0;
 }
 
-static Sched choose_schedule(int prec, const Args &a, int64_t M, int64_t N, int64_t K);
+static Sched choose_schedule(int prec, const Args &a, int64_t M, int64_t N, int64_t K,
+                             const char **source);
 
 static int get_plan(int prec, const Args &a, int dev, int64_t forced, Plan **out) {
     const std::string key = signature_key(a, prec, dev, forced);
@@ -224,11 +236,12 @@ static int get_plan(int prec, const Args &a, int dev, int64_t forced, Plan **out
     // Plan outside the lock (the predictor/autotuner may launch kernels).
     Canon c0 = canonicalise(a, 0, 128);
     Sched s;
+    const char *source = "forced";
     if (forced >= 0) {
         s = sched_of(forced);
         if (!sched_valid(prec, s, c0.K)) return GETT_ERR_STATE;
     } else {
-        s = choose_schedule(prec, a, c0.M, c0.N, c0.K);
+        s = choose_schedule(prec, a, c0.M, c0.N, c0.K, &source);
     }
     auto pl = std::make_unique<Plan>();
     pl->prec = prec;
@@ -243,9 +256,9 @@ static int get_plan(int prec, const Args &a, int dev, int64_t forced, Plan **out
         return GETT_ERR_INTERNAL;
     if (g_log)
         fprintf(stderr, "[gett] plan prec=%d M=%lld N=%lld K=%lld tile=%d order=%d split=%d "
-                        "swapped=%d aFastK=%d bFastK=%d boxX=%d\n",
+                        "swapped=%d aFastK=%d bFastK=%d boxX=%d source=%s\n",
                 prec, (long long)cn.M, (long long)cn.N, (long long)cn.K, s.tile, s.order, s.split,
-                (int)cn.swapped, (int)cn.aFastK, (int)cn.bFastK, cn.boxX);
+                (int)cn.swapped, (int)cn.aFastK, (int)cn.bFastK, cn.boxX, source);
     std::lock_guard<std::mutex> lk(g_mu);
     auto &slot = g_plans[key];
     if (!slot) slot = std::move(pl);   // another thread may have won the race
@@ -255,10 +268,12 @@ static int get_plan(int prec, const Args &a, int dev, int64_t forced, Plan **out
 }
 
 // Fill the launch parameters of a plan for concrete pointers.
-static TileParams make_params(const Plan &pl, const void *A, const void *B, void *C) {
+static TileParams make_params(const Plan &pl, const void *A, const void *B, void *C,
+                              int split = -1) {
     const TableSet &t = *pl.tab;
     const Canon &c = t.cn;
     const TileShape ts = kTiles[pl.prec][pl.sched.tile];
+    if (split < 0) split = pl.sched.split;
     TileParams p;
     p.A = c.swapped ? B : A;
     p.B = c.swapped ? A : B;
@@ -275,8 +290,8 @@ static TileParams make_params(const Plan &pl, const void *A, const void *B, void
     p.tilesM = (int32_t)((c.M + ts.bm - 1) / ts.bm);
     p.tilesN = (int32_t)((c.N + ts.bn - 1) / ts.bn);
     int64_t per = 0;
-    p.splits = split_count(pl.sched.split, (int64_t)p.tilesM * p.tilesN,
-                           std::max<int64_t>(c.K, 1), ts.bk, &per);
+    p.splits = split_count(split, (int64_t)p.tilesM * p.tilesN, std::max<int64_t>(c.K, 1), ts.bk,
+                           &per);
     p.kPerSplit = per;
     p.bBoxX = c.boxX > 0 ? c.boxX : ts.bn;
     p.ws = nullptr;
@@ -292,14 +307,19 @@ static TileParams make_params(const Plan &pl, const void *A, const void *B, void
 static int run_plan(const Plan &pl, const void *A, const void *B, void *C, hipStream_t s) {
     TileParams p = make_params(pl, A, B, C);
     if (p.splits > 1) {
-        const size_t bytes = (size_t)p.splits * p.M * p.N * sizeof(double);
+        const int64_t bytes = (int64_t)p.splits * p.M * p.N * (int64_t)sizeof(double);
         void *ws = nullptr;
-        if (hipMallocAsync(&ws, bytes, s) != hipSuccess) return GETT_ERR_ALLOC;
-        p.ws = static_cast<double *>(ws);
-        int rc = launch_tile(pl.prec, pl.sched.tile, pl.tab->cn.aFastK, pl.tab->cn.bFastK, p, s);
-        if (!rc) rc = launch_splitk_reduce(pl.prec, p, s);
-        if (hipFreeAsync(ws, s) != hipSuccess && !rc) rc = GETT_ERR_HIP;
-        return rc;
+        if (bytes <= g_max_ws.load() && hipMallocAsync(&ws, (size_t)bytes, s) == hipSuccess) {
+            p.ws = static_cast<double *>(ws);
+            int rc = launch_tile(pl.prec, pl.sched.tile, pl.tab->cn.aFastK, pl.tab->cn.bFastK, p, s);
+            if (!rc) rc = launch_splitk_reduce(pl.prec, p, s);
+            if (hipFreeAsync(ws, s) != hipSuccess && !rc) rc = GETT_ERR_HIP;
+            return rc;
+        }
+        // over the cap or out of memory: the same tile and order, unsplit
+        (void)hipGetLastError();
+        p = make_params(pl, A, B, C, 0);
+        t_last_schedule = sched_id(Sched{pl.sched.tile, pl.sched.order, 0});
     }
     return launch_tile(pl.prec, pl.sched.tile, pl.tab->cn.aFastK, pl.tab->cn.bFastK, p, s);
 }
@@ -700,32 +720,104 @@ static int64_t autotune(int prec, const Args &a, const void *A, const void *B, v
 // Tuned choices found by the AUTOTUNE policy (signature -> schedule).
 static std::unordered_map<std::string, Sched> g_tuned;
 
+// The same choices persisted across processes when GETT_TUNE_DB names a
+// file: one text line per signature, its integers (precision, then the
+// xGETT arguments), " = ", the schedule id and its median time in
+// microseconds.  The file is read on the first tuning decision and a line is
+// appended after each new tuning; a later line for the same signature wins,
+// and lines that do not parse or name an invalid schedule are ignored.
+static std::unordered_map<std::string, Sched> g_tuned_db;
+static bool g_tuned_db_read = false;
+
+static const char *tune_db_path() {
+    const char *p = getenv("GETT_TUNE_DB");
+    return (p && *p) ? p : nullptr;
+}
+
+static std::string tune_db_key(const Args &a, int prec) {
+    const std::string bin = signature_key(a, prec, -1, -3);
+    std::string s;
+    for (size_t i = 0; i < bin.size() / sizeof(int64_t); ++i) {
+        int64_t v;
+        memcpy(&v, bin.data() + i * sizeof(int64_t), sizeof v);
+        if (i) s += ' ';
+        s += std::to_string(v);
+    }
+    return s;
+}
+
+static void read_tune_db_locked() {
+    if (g_tuned_db_read) return;
+    g_tuned_db_read = true;
+    const char *path = tune_db_path();
+    FILE *f = path ? fopen(path, "r") : nullptr;
+    if (!f) return;   // no file yet
+    char *line = nullptr;
+    size_t cap = 0;
+    while (getline(&line, &cap, f) > 0) {
+        const char *eq = strstr(line, " = ");
+        long long id = -1;
+        if (!eq || sscanf(eq + 3, "%lld", &id) != 1 || id < 0 || id >= kNumSched) continue;
+        g_tuned_db[std::string(line, eq - line)] = sched_of(id);
+    }
+    free(line);
+    fclose(f);
+}
+
+static void append_tune_db_locked(const std::string &key, int64_t id, double us) {
+    const char *path = tune_db_path();
+    FILE *f = path ? fopen(path, "a") : nullptr;
+    if (!f) return;
+    fprintf(f, "%s = %lld %.3f\n", key.c_str(), (long long)id, us);
+    fclose(f);
+}
+
 static thread_local const void *t_tune_ptrs[3] = {nullptr, nullptr, nullptr};
 static thread_local int t_tune_dev = 0;
 
-static Sched choose_schedule(int prec, const Args &a, int64_t M, int64_t N, int64_t K) {
+static Sched choose_schedule(int prec, const Args &a, int64_t M, int64_t N, int64_t K,
+                             const char **source) {
     const int pol = g_policy.load();
     Sched s = heuristic(prec, M, N, K);
+    *source = "heuristic";
     if (pol == GETT_PREDICT) {
         Sched p;
-        if (predict(prec, a, K, &p)) s = p;
+        if (predict(prec, a, K, &p)) {
+            s = p;
+            *source = "predictor";
+        }
     } else if (pol == GETT_AUTOTUNE && t_tune_ptrs[0]) {
         const std::string key = signature_key(a, prec, t_tune_dev, -3);
+        const std::string dkey = tune_db_key(a, prec);
         {
             std::lock_guard<std::mutex> lk(g_mu);
             auto it = g_tuned.find(key);
-            if (it != g_tuned.end()) return it->second;
+            if (it != g_tuned.end()) {
+                *source = "tuned";
+                return it->second;
+            }
+            read_tune_db_locked();
+            auto jt = g_tuned_db.find(dkey);
+            if (jt != g_tuned_db.end() && sched_valid(prec, jt->second, K)) {
+                g_tuned[key] = jt->second;
+                *source = "tune-db";
+                return jt->second;
+            }
         }
         int st = 0;
-        // The tuning runs overwrite C; the caller's C is restored by the final run
-        // only if C started at zero, so the policy saves and restores C itself.
+        // The tuning runs accumulate into C; run() saves and restores C's
+        // footprint around a plan-cache miss under this policy.
+        std::vector<double> us(kNumSched, -1.0);
         const int64_t id = autotune(prec, a, t_tune_ptrs[0], t_tune_ptrs[1],
-                                    const_cast<void *>(t_tune_ptrs[2]), t_tune_dev, 1, 3, nullptr,
-                                    0, &st);
+                                    const_cast<void *>(t_tune_ptrs[2]), t_tune_dev, 1, 3,
+                                    us.data(), kNumSched, &st);
         if (!st && id >= 0) {
             s = sched_of(id);
+            *source = "autotuned";
             std::lock_guard<std::mutex> lk(g_mu);
             g_tuned[key] = s;
+            g_tuned_db[dkey] = s;
+            append_tune_db_locked(dkey, id, us[id]);
         }
     }
     return s;
@@ -911,6 +1003,10 @@ static int run_batch(int prec, int64_t count, const Args *args, const void *cons
                 S = (steps + cap - 1) / cap;
                 per = (steps + S - 1) / S * bk;
                 S = (p.K + per - 1) / per;      // every slice starts below K
+                if ((ws_total + S * p.M * p.N) * (int64_t)sizeof(double) > g_max_ws.load()) {
+                    S = 1;                       // over the workspace cap: not cut
+                    per = steps * bk;
+                }
             }
             const int64_t items = (int64_t)p.tilesM * p.tilesN * S;
             if (items > INT32_MAX / 2) return GETT_ERR_INTERNAL;
@@ -1189,6 +1285,12 @@ int gett_set_schedule(int64_t id) {
 }
 int64_t gett_last_schedule(void) { return t_last_schedule; }
 
+int gett_set_max_workspace(int64_t bytes) {
+    if (bytes < 0) return GETT_ERR_STATE;
+    g_max_ws.store(bytes);
+    return 0;
+}
+
 int64_t gett_autotune(int prec, int64_t ranka, const int64_t *exta, const int64_t *inca,
                       const void *A, int64_t rankb, const int64_t *extb, const int64_t *incb,
                       const void *B, int64_t conts, const int64_t *conta, const int64_t *contb,
@@ -1328,6 +1430,8 @@ int gett_finalize(void) {
         g_tables.clear();
         g_fp8.clear();
         g_tuned.clear();
+        g_tuned_db.clear();
+        g_tuned_db_read = false;   // a later tuning reads GETT_TUNE_DB again
     }
     std::lock_guard<std::mutex> lk(g_pred_mu);
     g_pred.reset();

@@ -21,6 +21,8 @@ LIB_PATH = os.environ.get("GETT_LIB") or os.path.join(_HERE, "libgett.so")
 
 GETT_FP64, GETT_FP32, GETT_BF16X3, GETT_FP8 = 0, 1, 2, 3
 GETT_HEURISTIC, GETT_PREDICT, GETT_AUTOTUNE = 0, 1, 2
+# positive runtime codes (negative codes are INFO = -i for argument i)
+GETT_ERR_HIP, GETT_ERR_ALLOC, GETT_ERR_DEVICE, GETT_ERR_INTERNAL, GETT_ERR_STATE = 1, 2, 3, 4, 5
 NUM_FEATURES = 64
 NUM_ORDERS = 4
 NUM_SPLITS = 4
@@ -75,6 +77,8 @@ def lib():
     L.gett_tile_shape.argtypes = [ct.c_int, i64, I64P]
     L.gett_set_schedule.argtypes = [i64]
     L.gett_last_schedule.restype = i64
+    L.gett_set_max_workspace.argtypes = [i64]
+    L.gett_set_max_workspace.restype = ct.c_int
     L.gett_autotune.argtypes = [ct.c_int, i64, I64P, I64P, vp, i64, I64P, I64P, vp, i64, I64P,
                                 I64P, I64P, I64P, vp, i64, i64, ct.POINTER(ct.c_double), i64,
                                 ct.POINTER(ct.c_int)]
@@ -249,6 +253,10 @@ def gett_set_schedule(sched_id: int) -> int:
 
 def gett_last_schedule() -> int:
     return int(lib().gett_last_schedule())
+
+
+def gett_set_max_workspace(nbytes: int) -> int:
+    return int(lib().gett_set_max_workspace(int(nbytes)))
 
 
 def num_schedules() -> int:

@@ -128,3 +128,11 @@ def test_policy_from_environment(value, want):
                        env=dict(os.environ, GETT_POLICY=value), timeout=300)
     assert r.returncode == 0, r.stderr[-2000:]
     assert int(r.stdout.strip().splitlines()[-1]) == want
+
+
+def test_workspace_cap_setter_checks_its_argument():
+    """The split-K workspace cap takes a byte count; negative sizes are an
+    error and nothing touches the GPU."""
+    assert gett.gett_set_max_workspace(-1) == gett.GETT_ERR_STATE
+    assert gett.gett_set_max_workspace(0) == 0
+    assert gett.gett_set_max_workspace(2 ** 63 - 1) == 0

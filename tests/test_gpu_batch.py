@@ -215,3 +215,36 @@ def test_batch_rejects_invalid_problem_and_skips_empty():
     assert rc == 0
     check_problem(problems[0], dev3[0][2].cpu().numpy(), gett.GETT_FP32)
     assert np.array_equal(dev3[1][2].cpu().numpy(), z.C.buf)
+
+
+@pytest.mark.parametrize("prec", [gett.GETT_FP64, gett.GETT_BF16X3])
+def test_batch_built_under_a_workspace_cap_is_not_cut(prec):
+    """The same kind of batch built while the split-K workspace cap is zero:
+    no problem is cut along K (the long ones run whole in the persistent
+    kernel) and every result still meets its bound."""
+    import torch
+    rng = np.random.default_rng(78)
+    dtype = np.float64 if prec == gett.GETT_FP64 else np.float32
+    problems = []
+    for i, k in enumerate([50001, 12345]):
+        sig = (2, [k, 24], 2, [40, k], 1, [0], [1], [0, 1])
+        problems.append(W.build_problem(rng, sig, dtype, dist="normal", name=f"capk{i}"))
+    problems += W.config_batch(48, seed=10, dtype=dtype)
+    dev = upload(problems)
+    try:
+        assert gett.gett_set_max_workspace(0) == 0
+        rc, info = run_batch(problems, dev, prec)
+    finally:
+        gett.gett_set_max_workspace(2 ** 63 - 1)
+    assert rc == 0 and all(i == 0 for i in info)
+    torch.cuda.synchronize()
+    for pr, d in zip(problems, dev):
+        got = d[2].cpu().numpy()
+        if prec == gett.GETT_FP64:
+            ref, cabs = oracle.exact(pr, pr.A, pr.B, pr.C)
+            sel = ~np.isnan(ref)
+            assert e_cw(got[sel], ref[sel], cabs[sel]) <= (pr.mnk()[2] + 2) * 2.0 ** -53
+            m = outside_mask(pr.C)
+            assert np.array_equal(got[m], pr.C.buf[m])
+        else:
+            check_problem(pr, got, prec)

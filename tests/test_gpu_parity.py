@@ -412,3 +412,29 @@ def test_addressing_at_the_4gb_boundary(prec, side):
     torch.cuda.empty_cache()
     check_against_oracle(pr, prec, got)
     check_outside(pr, got)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_workspace_cap_runs_split_schedules_unsplit(prec):
+    """A forced split-K schedule under a zero workspace cap runs its tile and
+    order unsplit (the last-schedule query says so); with the cap lifted the
+    same call splits K again.  Both results match the oracle."""
+    dtype = np.float64 if prec == gett.GETT_FP64 else np.float32
+    pr = W.config_small_dgett()
+    if dtype != np.float64:
+        pr = pr.with_views(*[W.View(v.buf.astype(dtype), v.base, v.ext, v.inc)
+                             for v in (pr.A, pr.B, pr.C)])
+    split_id = gett.schedule_id(0, 0, 1)
+    try:
+        assert gett.gett_set_schedule(split_id) == 0
+        assert gett.gett_set_max_workspace(0) == 0
+        got = run_gpu(pr, prec, "cap 0")
+        assert gett.gett_last_schedule() == gett.schedule_id(0, 0, 0)
+        check_against_oracle(pr, prec, got)
+        assert gett.gett_set_max_workspace(2 ** 63 - 1) == 0
+        got = run_gpu(pr, prec, "no cap")
+        assert gett.gett_last_schedule() == split_id
+        check_against_oracle(pr, prec, got)
+    finally:
+        gett.gett_set_max_workspace(2 ** 63 - 1)
+        gett.gett_set_schedule(-1)

@@ -227,6 +227,56 @@ def test_predict_policy_from_environment(tmp_path):
     assert got == want
 
 
+def test_autotune_choices_persist_in_tune_db(tmp_path):
+    """GETT_POLICY=autotune with GETT_TUNE_DB: a first process times the menu
+    for a signature and appends its choice to the file (lines that do not
+    parse are skipped); a second process takes the schedule from the file
+    without timing (its plan log names the source), gives the bitwise-same
+    result, and leaves the file as it was.  Both match the oracle."""
+    import subprocess
+    import sys
+    db = tmp_path / "tuned.txt"
+    db.write_text("not a record\n1 2 3 = x\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = [str(tmp_path / "c1.npy"), str(tmp_path / "c2.npy")]
+    code = (
+        "import sys, numpy as np, torch\n"
+        "from paper_2410_06770_amd import gett, workloads as W\n"
+        "from tests.helpers import call14, to_device\n"
+        "gett.use_torch_stream()\n"
+        "pr = W.paper_case('cube_2', np.random.default_rng(12), dtype=np.float32, dist='normal')\n"
+        "At, a = to_device(pr.A); Bt, b = to_device(pr.B); Ct, c = to_device(pr.C)\n"
+        "assert call14(gett.sgett, pr, a, b, c) == 0\n"
+        "torch.cuda.synchronize()\n"
+        "np.save(sys.argv[1], Ct.cpu().numpy())\n"
+        "print('SCHED', gett.gett_last_schedule())\n")
+    env = dict(os.environ, GETT_POLICY="autotune", GETT_TUNE_DB=str(db), GETT_LOG="1")
+    runs = []
+    for i in range(2):
+        print(f"\n[gpu] subprocess {i} with GETT_TUNE_DB", flush=True)
+        r = subprocess.run([sys.executable, "-c", code, out[i]], cwd=root, capture_output=True,
+                           text=True, env=env, timeout=300)
+        assert r.returncode == 0, r.stderr[-3000:]
+        runs.append(r)
+        if i == 0:
+            after_first = db.read_text()
+    assert "source=autotuned" in runs[0].stderr, runs[0].stderr[-2000:]
+    assert "source=tune-db" in runs[1].stderr, runs[1].stderr[-2000:]
+    records = [l for l in after_first.splitlines() if " = " in l and l.split(" = ")[1][0].isdigit()]
+    assert len(records) == 1
+    assert db.read_text() == after_first
+    sched = [int([l for l in r.stdout.splitlines() if l.startswith("SCHED")][-1].split()[1])
+             for r in runs]
+    assert sched[0] == sched[1] == int(records[0].split(" = ")[1].split()[0])
+    pr = W.paper_case("cube_2", np.random.default_rng(12), dtype=np.float32, dist="normal")
+    c1, c2 = np.load(out[0]), np.load(out[1])
+    assert np.array_equal(c1, c2)
+    ref, cabs = oracle.exact(pr, pr.A, pr.B, pr.C)
+    sel = ~np.isnan(ref)
+    d = c1[sel].astype(np.float64) - ref[sel]
+    assert np.linalg.norm(d) <= 1e-5 * np.linalg.norm(ref[sel])
+
+
 def test_network_beats_heuristic_on_heldout_signatures():
     """Trained on the autotuner's timing database, evaluated on held-out
     signatures against exhaustive search (the database's optimum)."""
