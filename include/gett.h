@@ -235,6 +235,16 @@ int64_t gett_last_schedule(void);
    or GETT_ERR_STATE for a negative size. */
 int gett_set_max_workspace(int64_t bytes);
 
+/* Accesses outside their tensor's addressed range counted by the FP64, FP32
+   and BF16x3 kernels on the current device since the last reset (waits for
+   the device first; RESET != 0 clears the count).  Only the checked build,
+   libgett_check.so (compiled with GETT_ADDR_CHECK), tests every gathered
+   element of A and B and every C element against the range that the
+   extents and increments give; there an out-of-range access is counted and
+   redirected to a zero or dropped instead of being made.  Returns -1 in the
+   normal build, GETT_ERR_HIP if the device query failed. */
+int64_t gett_addr_violations(int reset);
+
 /* Autotuner: time every valid schedule of the menu for one problem of
    precision PREC (the 14 xGETT arguments, device data; C is overwritten by
    the timing runs) with HIP events on the current stream: each valid

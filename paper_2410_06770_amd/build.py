@@ -17,6 +17,10 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.environ.get("GETT_LIB_OUT") or os.path.join(HERE, "libgett.so")
+# The checked build: every gathered and every C element is tested against its
+# tensor's addressed range (GETT_ADDR_CHECK); for tests, not for speed.
+CHECK_OBJ = os.path.join(HERE, "_build_check")
+CHECK_LIB = os.path.join(HERE, "libgett_check.so")
 
 SOURCES = ["gett_tile_f64.hip", "gett_tile_f32.hip", "gett_tile_bf3.hip", "gett_fp8.hip",
            "gett_mlp.hip", "gett_dispatch.cpp", "gett_plan.cpp", "gett_host.cpp"]
@@ -36,28 +40,36 @@ DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-p
 EXTRA = os.environ.get("GETT_EXTRA_FLAGS", "").split()
 
 
-def _compile(src: str) -> str:
+def _compile(src: str, objdir: str, defs: list) -> str:
     path = os.path.join(CSRC, src)
-    obj = os.path.join(OBJ, src + ".o")
+    obj = os.path.join(objdir, src + ".o")
     if src.endswith(".hip"):
-        cmd = ["hipcc", "-x", "hip", *DEVICE, *COMMON, *FILE_FLAGS.get(src, []), *EXTRA, "-c",
-               path, "-o", obj]
+        cmd = ["hipcc", "-x", "hip", *DEVICE, *COMMON, *defs, *FILE_FLAGS.get(src, []), *EXTRA,
+               "-c", path, "-o", obj]
     else:
-        cmd = ["hipcc", *COMMON, "-c", path, "-o", obj]
+        cmd = ["hipcc", *COMMON, *defs, "-c", path, "-o", obj]
     subprocess.check_call(cmd)
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(OBJ, exist_ok=True)
+def _build(objdir: str, lib: str, defs: list, verbose: bool) -> str:
+    os.makedirs(objdir, exist_ok=True)
     jobs = min(len(SOURCES), max(1, min(8, os.cpu_count() or 1)))
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = LIB + ".tmp"
+        objs = list(ex.map(lambda src: _compile(src, objdir, defs), SOURCES))
+    tmp = lib + ".tmp"
     subprocess.check_call(["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs])
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
     if verbose:
-        print(f"built {LIB}")
+        print(f"built {lib}")
+    return lib
+
+
+def build(verbose: bool = False, check: bool = True) -> str:
+    """Build libgett.so, and the checked libgett_check.so unless check=False."""
+    _build(OBJ, LIB, [], verbose)
+    if check:
+        _build(CHECK_OBJ, CHECK_LIB, ["-DGETT_ADDR_CHECK"], verbose)
     return LIB
 
 

@@ -119,6 +119,11 @@ struct TileParams {
     int64_t aLo, bLo;
     int32_t off32;
     int32_t pad_;
+#ifdef GETT_ADDR_CHECK
+    // Checked build only: the addressed element ranges [lo, lo + span] of A,
+    // B and C (C from its own increments) that every access is tested against.
+    int64_t aSpan, bSpan, cLo, cSpan;
+#endif
 };
 
 // One problem of a batched launch (device-resident descriptor).

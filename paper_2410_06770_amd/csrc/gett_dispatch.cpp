@@ -23,7 +23,8 @@ const char *last_hip_error_name() {
     int launch_batch_##SUFFIX(const BatchProblem *d, const int32_t *it, int32_t n, int32_t g,      \
                               hipStream_t s);                                                      \
     int launch_batch_reduce_##SUFFIX(const BatchProblem *d, const int32_t *l, int32_t n,           \
-                                     hipStream_t s);
+                                     hipStream_t s);                                               \
+    int64_t addr_violations_##SUFFIX(bool reset);
 GETT_DECLARE_PRECISION(f64)
 GETT_DECLARE_PRECISION(f32)
 GETT_DECLARE_PRECISION(bf3)
@@ -75,5 +76,16 @@ int launch_batch_reduce(int prec, const BatchProblem *d_probs, const int32_t *d_
     default: return GETT_ERR_INTERNAL;
     }
 }
+
+#ifdef GETT_ADDR_CHECK
+int64_t addr_violations(int prec, bool reset) {
+    switch (prec) {
+    case kF64: return addr_violations_f64(reset);
+    case kF32: return addr_violations_f32(reset);
+    case kBF3: return addr_violations_bf3(reset);
+    default: return -1;
+    }
+}
+#endif
 
 }  // namespace gett

@@ -155,6 +155,7 @@ struct TableSet {
     int64_t Mp = 0, Np = 0, Kp = 0;
     int64_t *d_tab = nullptr;   // offAM, offCM [Mp]; offBN, offCN [Np]; offAK, offBK [Kp]
     int64_t aLo = 0, aSpan = 0, bLo = 0, bSpan = 0;   // addressed element range of A and B
+    int64_t cLo = 0, cSpan = 0;                        // and of C
     ~TableSet() {
         if (d_tab) (void)hipFree(d_tab);
     }
@@ -190,6 +191,13 @@ static int upload_tables(TableSet &t) {
     group_offsets(c.k, 0, t.Kp, p);
     group_offsets(c.k, 1, t.Kp, p + t.Kp);
     operand_ranges(c, t.aLo, t.aSpan, t.bLo, t.bSpan);
+    {
+        int64_t ml, mh, nl, nh;
+        group_range(c.m, 1, ml, mh);
+        group_range(c.n, 1, nl, nh);
+        t.cLo = ml + nl;
+        t.cSpan = (mh - ml) + (nh - nl);
+    }
     const size_t bytes = h.size() * sizeof(int64_t);
     if (hipMalloc(&t.d_tab, bytes) != hipSuccess) return GETT_ERR_ALLOC;
     if (hipMemcpy(t.d_tab, h.data(), bytes, hipMemcpyHostToDevice) != hipSuccess)
@@ -301,6 +309,19 @@ static TileParams make_params(const Plan &pl, const void *A, const void *B, void
     const int64_t lim = (int64_t)1 << 32;
     p.off32 = (t.aSpan < lim / esz && t.bSpan < lim / esz) ? 1 : 0;
     p.pad_ = 0;
+#ifdef GETT_ADDR_CHECK
+    // GETT_CHECK_SHRINK=1 narrows the checked ranges of A and B by one
+    // element at the top (the accesses themselves are unchanged), so a test
+    // can see the checker report the tensors' last elements.
+    static const bool shrink = [] {
+        const char *e = getenv("GETT_CHECK_SHRINK");
+        return e && e[0] == '1';
+    }();
+    p.aSpan = t.aSpan - (shrink ? 1 : 0);
+    p.bSpan = t.bSpan - (shrink ? 1 : 0);
+    p.cLo = t.cLo;
+    p.cSpan = t.cSpan;
+#endif
     return p;
 }
 
@@ -1284,6 +1305,21 @@ int gett_set_schedule(int64_t id) {
     return 0;
 }
 int64_t gett_last_schedule(void) { return t_last_schedule; }
+
+int64_t gett_addr_violations(int reset) {
+#ifdef GETT_ADDR_CHECK
+    int64_t total = 0;
+    for (int prec : {kF64, kF32, kBF3}) {
+        const int64_t v = addr_violations(prec, reset != 0);
+        if (v < 0) return GETT_ERR_HIP;
+        total += v;
+    }
+    return total;
+#else
+    (void)reset;
+    return -1;
+#endif
+}
 
 int gett_set_max_workspace(int64_t bytes) {
     if (bytes < 0) return GETT_ERR_STATE;

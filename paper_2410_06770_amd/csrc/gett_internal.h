@@ -27,6 +27,11 @@ int batch_grid_size(int prec);
 // (those cut along K), reading their descriptors on the device.
 int launch_batch_reduce(int prec, const BatchProblem *d_probs, const int32_t *d_list, int32_t n,
                         hipStream_t s);
+#ifdef GETT_ADDR_CHECK
+// Checked build: out-of-range accesses counted by the kernels of one
+// precision on the current device (optionally reset); negative on a HIP error.
+int64_t addr_violations(int prec, bool reset);
+#endif
 
 // FP8 path: quantisation into canonical K-contiguous rows and the GEMM on them.
 // rowsFast selects the loader whose lanes run along the rows (for operands

@@ -63,6 +63,37 @@ template <int PREC, int ROWS, int BK> struct OpLds {
 // select afterwards, so the loaded value can go straight to LDS.
 static __device__ __align__(16) double g_gett_zero[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 
+#ifdef GETT_ADDR_CHECK
+// Checked build: every gathered element and every C element is tested
+// against its tensor's addressed range [lo, lo + span] (element offsets from
+// the tensor's pointer); an access outside is counted here and redirected to
+// the zero buffer (loads) or dropped (stores), so it cannot fault.
+static __device__ unsigned long long g_gett_viol = 0;
+
+template <class T>
+__device__ __forceinline__ const T *gett_checked(const T *X, const T *ptr, int64_t lo, int64_t span) {
+    const T *zero = reinterpret_cast<const T *>(g_gett_zero);
+    if (ptr == zero) return ptr;   // masked positions read the zero buffer on purpose
+    const int64_t d = ptr - X;
+    if (d < lo || d > lo + span) {
+        atomicAdd(&g_gett_viol, 1ull);
+        return zero;
+    }
+    return ptr;
+}
+
+__device__ __forceinline__ bool gett_check_c(int64_t off, int64_t lo, int64_t span) {
+    if (off < lo || off > lo + span) {
+        atomicAdd(&g_gett_viol, 1ull);
+        return false;
+    }
+    return true;
+}
+#define GETT_CHECK_C(off, p) if (!gett_check_c((off), (p).cLo, (p).cSpan)) continue
+#else
+#define GETT_CHECK_C(off, p) (void)0
+#endif
+
 __device__ __forceinline__ int64_t readlane64(int64_t v, int lane) {
     const int lo = __builtin_amdgcn_readlane((int)(v & 0xffffffff), lane);
     const int hi = __builtin_amdgcn_readlane((int)(v >> 32), lane);
@@ -119,6 +150,15 @@ template <int PREC, int ROWS, int BK, bool FASTK, bool O32 = false> struct Gathe
     int64_t koff[NK];   // contracted offsets for the current step
     const T *lo;        // O32: X + the lowest element offset the operand addresses
     uint32_t vrow[NF];  // O32: byte offset of each row's free offset from lo
+#ifdef GETT_ADDR_CHECK
+    const T *cX;        // the operand's pointer and addressed range
+    int64_t cLo, cSpan;
+    __device__ __forceinline__ const T *chk(const T *ptr) const {
+        return gett_checked(cX, ptr, cLo, cSpan);
+    }
+#else
+    __device__ __forceinline__ const T *chk(const T *ptr) const { return ptr; }
+#endif
 
     static __device__ __forceinline__ constexpr int kpos(int c) {
         return kSplit ? (c >> 1) + (c & 1) * (BK / 2) : c;
@@ -129,8 +169,16 @@ template <int PREC, int ROWS, int BK, bool FASTK, bool O32 = false> struct Gathe
     }
 
     __device__ void init(const T *X, int t, int64_t r0, int64_t nrows,
-                         const int64_t *__restrict__ offFree, int boxX, int64_t xlo = 0) {
+                         const int64_t *__restrict__ offFree, int boxX, int64_t xlo = 0,
+                         int64_t xspan = 0) {
         if constexpr (O32) lo = X + xlo;
+#ifdef GETT_ADDR_CHECK
+        cX = X;
+        cLo = xlo;
+        cSpan = xspan;
+#else
+        (void)xspan;
+#endif
         if constexpr (!FASTK) {
             const int il = t % ROWS;                 // consecutive threads: consecutive il
             const int x = il % boxX, y = il / boxX;  // loader walks the box's x side
@@ -220,14 +268,22 @@ template <int PREC, int ROWS, int BK, bool FASTK, bool O32 = false> struct Gathe
                 // the lane offset a 32-bit value inside the loop, so the load
                 // is selected as base + zero-extended offset (no 64-bit add).
                 uint32_t vr = vrow[0];
+#ifndef GETT_ADDR_CHECK
                 asm("" : "+v"(vr));
+#endif
 #pragma unroll
                 for (int i = 0; i < PER; ++i) {
                     uint64_t bk = reinterpret_cast<uint64_t>(lo + ko_[i]);
+#ifndef GETT_ADDR_CHECK
                     asm("" : "+s"(bk));
+#endif
                     using GT = const __attribute__((address_space(1))) char;
+#ifdef GETT_ADDR_CHECK
+                    v[i] = *chk(reinterpret_cast<const T *>(reinterpret_cast<const char *>(bk) + vr));
+#else
                     v[i] = *reinterpret_cast<const __attribute__((address_space(1))) T *>(
                         reinterpret_cast<GT *>(bk) + vr);
+#endif
                 }
             } else {
 #pragma unroll
@@ -235,7 +291,7 @@ template <int PREC, int ROWS, int BK, bool FASTK, bool O32 = false> struct Gathe
                     const uint32_t kb = (uint32_t)ko_[e] * (uint32_t)sizeof(T);
 #pragma unroll
                     for (int i = 0; i < NF; ++i)
-                        v[i * KP + e] = *reinterpret_cast<const T *>(b + (uint32_t)(vrow[i] + kb));
+                        v[i * KP + e] = *chk(reinterpret_cast<const T *>(b + (uint32_t)(vrow[i] + kb)));
                 }
             }
         } else if constexpr (kScalarK) {
@@ -243,7 +299,7 @@ template <int PREC, int ROWS, int BK, bool FASTK, bool O32 = false> struct Gathe
             for (int i = 0; i < PER; ++i) {
                 const T *ptr = base[0] + ko_[i];
                 if constexpr (MASKED) ptr = (k0 + col(i) >= klo) ? ptr : zero;
-                v[i] = *ptr;
+                v[i] = *chk(ptr);
             }
         } else if constexpr (!FASTK) {
 #pragma unroll
@@ -252,7 +308,7 @@ template <int PREC, int ROWS, int BK, bool FASTK, bool O32 = false> struct Gathe
                 const int64_t ko = readlane64(ko_[0], k);
                 const T *ptr = base[0] + ko;
                 if constexpr (MASKED) ptr = (k0 + k >= klo) ? ptr : zero;
-                v[i] = *ptr;
+                v[i] = *chk(ptr);
             }
         } else {
 #pragma unroll
@@ -262,7 +318,7 @@ template <int PREC, int ROWS, int BK, bool FASTK, bool O32 = false> struct Gathe
                 for (int i = 0; i < NF; ++i) {
                     const T *ptr = base[i] + ko_[e];
                     if constexpr (MASKED) ptr = kk ? ptr : zero;
-                    v[i * KP + e] = *ptr;
+                    v[i * KP + e] = *chk(ptr);
                 }
             }
         }
@@ -372,8 +428,13 @@ __device__ __forceinline__ void gett_tile(const TileParams &p, int64_t m0, int64
     Gather<PREC, BN, BK, BFK, O32> gb;
     const T *__restrict__ A = static_cast<const T *>(p.A);
     const T *__restrict__ B = static_cast<const T *>(p.B);
+#ifdef GETT_ADDR_CHECK
+    ga.init(A, t, m0, p.M, p.offAM, BM, p.aLo, p.aSpan);
+    gb.init(B, t, n0, p.N, p.offBN, p.bBoxX, p.bLo, p.bSpan);
+#else
     ga.init(A, t, m0, p.M, p.offAM, BM, p.aLo);
     gb.init(B, t, n0, p.N, p.offBN, p.bBoxX, p.bLo);
+#endif
 
     Acc acc[FM][FN];
     Acc acx[kSplit ? FM : 1][kSplit ? FN : 1];
@@ -577,6 +638,7 @@ __device__ __forceinline__ void gett_tile(const TileParams &p, int64_t m0, int64
                     p.ws[((int64_t)split * p.M + m) * p.N + n] = part;
                 } else {
                     const int64_t off = p.offCM[m] + ocn;
+                    GETT_CHECK_C(off, p);
                     if constexpr (PREC == kF64) {
                         Cp[off] = Cp[off] + acc[i][j][v];
                     } else if constexpr (PREC == kF32) {
@@ -617,6 +679,7 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(TileParams p) {
          idx += (int64_t)gridDim.x * blockDim.x) {
         const int64_t m = idx / p.N, n = idx - m * p.N;
         const int64_t off = p.offCM[m] + p.offCN[n];
+        GETT_CHECK_C(off, p);
         double s = (double)Cp[off];
         for (int z = 0; z < p.splits; ++z) s += p.ws[(int64_t)z * MN + idx];
         Cp[off] = (T)s;
@@ -679,6 +742,7 @@ __global__ __launch_bounds__(256) void batch_reduce_kernel(const BatchProblem *_
              idx += (int64_t)gridDim.x * blockDim.x) {
             const int64_t m = idx / p.N, nn = idx - m * p.N;
             const int64_t off = p.offCM[m] + p.offCN[nn];
+            GETT_CHECK_C(off, p);
             double s = (double)Cp[off];
             for (int z = 0; z < p.splits; ++z) s += p.ws[(int64_t)z * MN + idx];
             Cp[off] = (T)s;
@@ -783,7 +847,26 @@ static int launch_batch_reduce_prec(const BatchProblem *d_probs, const int32_t *
     return launch_status();
 }
 
-// Defines the five per-precision entry points used by the host dispatcher.
+// Out-of-range accesses counted by this file's kernels on the current device
+// (checked build; -1 otherwise).
+static int64_t addr_violations_here(bool reset) {
+#ifdef GETT_ADDR_CHECK
+    unsigned long long v = 0;
+    if (hipDeviceSynchronize() != hipSuccess ||
+        hipMemcpyFromSymbol(&v, HIP_SYMBOL(g_gett_viol), sizeof v) != hipSuccess)
+        return -1;
+    if (reset) {
+        const unsigned long long z = 0;
+        if (hipMemcpyToSymbol(HIP_SYMBOL(g_gett_viol), &z, sizeof z) != hipSuccess) return -1;
+    }
+    return (int64_t)v;
+#else
+    (void)reset;
+    return -1;
+#endif
+}
+
+// Defines the per-precision entry points used by the host dispatcher.
 #define GETT_DEFINE_PRECISION(PREC, SUFFIX)                                                        \
     int launch_tile_##SUFFIX(int tile, bool afk, bool bfk, const TileParams &p, hipStream_t s) {   \
         return launch_prec<PREC>(tile, afk, bfk, p, s);                                            \
@@ -799,6 +882,7 @@ static int launch_batch_reduce_prec(const BatchProblem *d_probs, const int32_t *
     int launch_batch_reduce_##SUFFIX(const BatchProblem *d, const int32_t *l, int32_t n,           \
                                      hipStream_t s) {                                              \
         return launch_batch_reduce_prec<PREC>(d, l, n, s);                                         \
-    }
+    }                                                                                              \
+    int64_t addr_violations_##SUFFIX(bool reset) { return addr_violations_here(reset); }
 
 }  // namespace gett

@@ -79,6 +79,8 @@ def lib():
     L.gett_last_schedule.restype = i64
     L.gett_set_max_workspace.argtypes = [i64]
     L.gett_set_max_workspace.restype = ct.c_int
+    L.gett_addr_violations.argtypes = [ct.c_int]
+    L.gett_addr_violations.restype = i64
     L.gett_autotune.argtypes = [ct.c_int, i64, I64P, I64P, vp, i64, I64P, I64P, vp, i64, I64P,
                                 I64P, I64P, I64P, vp, i64, i64, ct.POINTER(ct.c_double), i64,
                                 ct.POINTER(ct.c_int)]
@@ -257,6 +259,10 @@ def gett_last_schedule() -> int:
 
 def gett_set_max_workspace(nbytes: int) -> int:
     return int(lib().gett_set_max_workspace(int(nbytes)))
+
+
+def gett_addr_violations(reset: bool = False) -> int:
+    return int(lib().gett_addr_violations(1 if reset else 0))
 
 
 def num_schedules() -> int:
