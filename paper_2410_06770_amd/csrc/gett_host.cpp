@@ -168,7 +168,9 @@ struct Plan {
 };
 
 static std::unordered_map<std::string, std::unique_ptr<TableSet>> g_tables;
-static std::unordered_map<std::string, std::unique_ptr<Plan>> g_plans;
+// Plans are shared: a call or a captured batch graph keeps the plans it uses
+// alive while a policy change empties the cache.
+static std::unordered_map<std::string, std::shared_ptr<Plan>> g_plans;
 
 static int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
@@ -230,13 +232,13 @@ static int get_tables(const Args &a, int order, int bn, int dev, TableSet **out)
 static Sched choose_schedule(int prec, const Args &a, int64_t M, int64_t N, int64_t K,
                              const char **source);
 
-static int get_plan(int prec, const Args &a, int dev, int64_t forced, Plan **out) {
+static int get_plan(int prec, const Args &a, int dev, int64_t forced, std::shared_ptr<Plan> *out) {
     const std::string key = signature_key(a, prec, dev, forced);
     {
         std::lock_guard<std::mutex> lk(g_mu);
         auto it = g_plans.find(key);
         if (it != g_plans.end()) {
-            *out = it->second.get();
+            *out = it->second;
             t_last_schedule = sched_id(it->second->sched);
             return 0;
         }
@@ -251,7 +253,7 @@ static int get_plan(int prec, const Args &a, int dev, int64_t forced, Plan **out
     } else {
         s = choose_schedule(prec, a, c0.M, c0.N, c0.K, &source);
     }
-    auto pl = std::make_unique<Plan>();
+    auto pl = std::make_shared<Plan>();
     pl->prec = prec;
     pl->sched = s;
     const TileShape ts = kTiles[prec][s.tile];
@@ -270,7 +272,7 @@ static int get_plan(int prec, const Args &a, int dev, int64_t forced, Plan **out
     std::lock_guard<std::mutex> lk(g_mu);
     auto &slot = g_plans[key];
     if (!slot) slot = std::move(pl);   // another thread may have won the race
-    *out = slot.get();
+    *out = slot;
     t_last_schedule = sched_id(slot->sched);
     return 0;
 }
@@ -669,7 +671,7 @@ static bool predict(int prec, const Args &a, int64_t K, Sched *out) {
 // ---------------------------------------------------------------------------
 static int time_schedule(int prec, const Args &a, const void *A, const void *B, void *C, int dev,
                          int64_t id, int warmup, int reps, double *us) {
-    Plan *pl = nullptr;
+    std::shared_ptr<Plan> pl;
     int rc = get_plan(prec, a, dev, id, &pl);
     if (rc) return rc;
     hipStream_t s = t_stream;
@@ -884,7 +886,7 @@ static int run(int prec, const Args &a, const void *A, const void *B, void *C) {
         return run_fp8(a, static_cast<const float *>(A), static_cast<const float *>(B),
                        static_cast<float *>(C), s, dev);
     const int64_t forced = g_forced.load();
-    Plan *pl = nullptr;
+    std::shared_ptr<Plan> pl;
     // Under the AUTOTUNE policy a plan-cache miss times the menu; the timing
     // runs accumulate into C, so C's footprint is saved and restored around it
     // (only then: a cached plan needs no timing).
@@ -935,7 +937,7 @@ struct BatchGraph {
     BatchProblem *d_desc = nullptr;
     int32_t *d_items = nullptr;
     int32_t nprobs = 0, nitems = 0;
-    std::vector<Plan *> plans;
+    std::vector<std::shared_ptr<Plan>> plans;
     // Problems cut along K: slice count, slice length and workspace offset
     // (doubles) per problem (splits 1: not cut), the list of cut problems on
     // the device and their FP64 partial-sum workspace.
@@ -1003,7 +1005,7 @@ static int run_batch(int prec, int64_t count, const Args *args, const void *cons
         int64_t total = 0;
         for (int64_t i = 0; i < count; ++i) {
             if (!live[i]) continue;
-            Plan *pl = nullptr;
+            std::shared_ptr<Plan> pl;
             int rc = get_plan(prec, args[i], dev, forced, &pl);
             if (rc) return rc;
             nb->plans[i] = pl;

@@ -225,6 +225,11 @@ def gett_set_stream(stream_handle: int) -> int:
     return lib().gett_set_stream(vp(stream_handle) if stream_handle else None)
 
 
+def gett_get_stream() -> int:
+    """The calling thread's stream handle (0: the null stream)."""
+    return int(lib().gett_get_stream() or 0)
+
+
 def gett_set_policy(policy: int) -> int:
     return lib().gett_set_policy(int(policy))
 

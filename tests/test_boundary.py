@@ -136,3 +136,26 @@ def test_workspace_cap_setter_checks_its_argument():
     assert gett.gett_set_max_workspace(-1) == gett.GETT_ERR_STATE
     assert gett.gett_set_max_workspace(0) == 0
     assert gett.gett_set_max_workspace(2 ** 63 - 1) == 0
+
+
+def test_stream_setting_is_per_thread():
+    """gett_set_stream sets the calling thread's stream only (no HIP call)."""
+    import threading
+    fake = 0x1230
+    assert gett.gett_set_stream(fake) == 0
+    seen = {}
+
+    def other():
+        seen["before"] = gett.gett_get_stream()
+        gett.gett_set_stream(0x4560)
+        seen["after"] = gett.gett_get_stream()
+
+    th = threading.Thread(target=other)
+    th.start()
+    th.join()
+    try:
+        assert not seen["before"]
+        assert seen["after"] == 0x4560
+        assert gett.gett_get_stream() == fake
+    finally:
+        gett.gett_set_stream(0)
