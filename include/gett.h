@@ -248,8 +248,11 @@ int64_t gett_addr_violations(int reset);
 /* Autotuner: time every valid schedule of the menu for one problem of
    precision PREC (the 14 xGETT arguments, device data; C is overwritten by
    the timing runs) with HIP events on the current stream: each valid
-   schedule once after WARMUP untimed runs, then the six fastest again, REPS
-   timed runs each.  times_us[id] receives the median of the re-timed ones,
+   schedule once after WARMUP untimed runs, then the six fastest again after
+   one untimed run each, REPS timed runs each, in rounds that time every one
+   of the six once (so a clock drift during the pass affects all six alike).
+   The AUTOTUNE policy uses WARMUP 1, REPS 5.  times_us[id] receives the
+   median of the re-timed ones,
    the single time of the others and -1 for invalid schedules; returns the
    best id (>= 0), or -1 with *status set to a negative INFO or a positive
    runtime error. */

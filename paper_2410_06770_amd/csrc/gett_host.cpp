@@ -699,9 +699,12 @@ static int time_schedule(int prec, const Args &a, const void *A, const void *B, 
 }
 
 // Two passes: every valid schedule once (after `warmup` untimed runs), then
-// the fastest few again with `reps` timed runs each; their medians decide.
-// times[] receives the median for re-timed schedules, the single time for
-// the others, and -1 for invalid ones.
+// the fastest few again, `reps` timed runs each after one untimed run; their
+// medians decide.  The second pass runs in rounds that time every candidate
+// once, so a drift of the clock or power state over the pass shifts all
+// candidates alike instead of favouring the ones timed first.  times[]
+// receives the median for re-timed schedules, the single time for the
+// others, and -1 for invalid ones.
 static int64_t autotune(int prec, const Args &a, const void *A, const void *B, void *C, int dev,
                         int warmup, int reps, double *times, int64_t ntimes, int *status) {
     Canon c0 = canonicalise(a, 0, 128);
@@ -720,15 +723,53 @@ static int64_t autotune(int prec, const Args &a, const void *A, const void *B, v
         if (t1[id] > 0) order.push_back(id);
     std::sort(order.begin(), order.end(), [&](int64_t x, int64_t y) { return t1[x] < t1[y]; });
     const size_t top = std::min<size_t>(order.size(), 6);
+    if (top == 0) return -1;
+    std::vector<std::shared_ptr<Plan>> plans(top);
+    hipStream_t s = t_stream;
+    int rc = 0;
+    for (size_t i = 0; i < top && !rc; ++i)
+        if (!(rc = get_plan(prec, a, dev, order[i], &plans[i]))) rc = run_plan(*plans[i], A, B, C, s);
+    if (rc) {
+        *status = rc;
+        return -1;
+    }
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) {
+        *status = GETT_ERR_HIP;
+        return -1;
+    }
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        *status = GETT_ERR_HIP;
+        return -1;
+    }
+    const int nr = std::max(reps, 1);
+    std::vector<std::vector<double>> tt(top, std::vector<double>(nr));
+    for (int r = 0; r < nr && !rc; ++r)
+        for (size_t i = 0; i < top && !rc; ++i) {
+            (void)hipEventRecord(e0, s);
+            rc = run_plan(*plans[i], A, B, C, s);
+            (void)hipEventRecord(e1, s);
+            if (rc) break;
+            if (hipEventSynchronize(e1) != hipSuccess) {
+                rc = GETT_ERR_HIP;
+                break;
+            }
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            tt[i][r] = ms * 1e3;
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) {
+        *status = rc;
+        return -1;
+    }
     double best = 1e300;
     int64_t best_id = -1;
     for (size_t i = 0; i < top; ++i) {
-        double us = 0;
-        int rc = time_schedule(prec, a, A, B, C, dev, order[i], 0, reps, &us);
-        if (rc) {
-            *status = rc;
-            return -1;
-        }
+        std::sort(tt[i].begin(), tt[i].end());
+        const double us = tt[i][nr / 2];
         t1[order[i]] = us;
         if (us < best) {
             best = us;
@@ -832,7 +873,7 @@ static Sched choose_schedule(int prec, const Args &a, int64_t M, int64_t N, int6
         // footprint around a plan-cache miss under this policy.
         std::vector<double> us(kNumSched, -1.0);
         const int64_t id = autotune(prec, a, t_tune_ptrs[0], t_tune_ptrs[1],
-                                    const_cast<void *>(t_tune_ptrs[2]), t_tune_dev, 1, 3,
+                                    const_cast<void *>(t_tune_ptrs[2]), t_tune_dev, 1, 5,
                                     us.data(), kNumSched, &st);
         if (!st && id >= 0) {
             s = sched_of(id);
