@@ -6,8 +6,8 @@
 //         E4M3 codes (round to nearest even) written into a dense
 //         K-contiguous row, with e beside it.  Two loader shapes, as in the
 //         tile kernels: when the contracted positions are the operand's
-//         cheapest direction in memory, one wave takes one (row, block) with
-//         lanes along K; when the rows are, one wave takes 16 neighbouring
+//         cheapest direction in memory, one wave takes a run of blocks of
+//         one row with lanes along K; when the rows are, one wave takes 16 neighbouring
 //         rows of one block with four lanes per row, so every load of the
 //         wave reads 16 neighbours at four positions.
 // gemm:   both operands are then dense [rows][Kp] byte matrices, the shape the
@@ -59,7 +59,19 @@ __device__ __forceinline__ unsigned e4m3_word(float a, float b, float c, float d
     return (unsigned)w;
 }
 
-// Lanes along K: one wave per (row, 128-block), two positions per lane.
+// Lanes along K: one wave per (row, run of up to kQuantRun consecutive
+// 128-blocks); lane l takes positions l and l + 64 of each block, so each
+// load instruction reads 64 neighbouring table entries and, where K runs
+// contiguously, 64 neighbouring values.  All of a wave's loads are issued
+// before its first block is reduced, so a run's blocks are in flight
+// together (one block per wave left the loads latency-bound).  The waves of
+// a workgroup take consecutive runs of one row (giving them neighbouring
+// rows of one run instead measured slower).  Loads past the run's last block repeat
+// that block, and positions past K read position K - 1 again (the
+// contracted table holds exactly K offsets); both are discarded, so every
+// load stays inside the table and the operand.
+constexpr int kQuantRun = 8;
+
 __global__ __launch_bounds__(256) void fp8_quant_kernel(const float *__restrict__ X,
                                                         const int64_t *__restrict__ offR,
                                                         int64_t rows, int64_t rowsPad,
@@ -68,30 +80,45 @@ __global__ __launch_bounds__(256) void fp8_quant_kernel(const float *__restrict_
                                                         int32_t *__restrict__ E) {
     const int64_t nb = (K + 127) / 128;
     const int64_t Kp = nb * 128;
+    const int64_t runs = (nb + kQuantRun - 1) / kQuantRun;
     const int lane = threadIdx.x & 63;
     const int64_t task = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);   // one wave per task
-    if (task >= rowsPad * nb) return;
-    const int64_t r = task / nb, blk = task - r * nb;
-    uint8_t *q = Q + r * Kp + blk * 128;
-    if (r >= rows) {     // padding rows of the operand: zero codes, zero exponent
-        q[2 * lane] = 0;
-        q[2 * lane + 1] = 0;
-        if (lane == 0) E[r * nb + blk] = 0;
+    if (task >= rowsPad * runs) return;
+    const int64_t r = task / runs, run = task - r * runs, b0 = run * kQuantRun;
+    const int nbl = (int)(nb - b0 < kQuantRun ? nb - b0 : kQuantRun);    // blocks in this run
+    uint8_t *q = Q + r * Kp;
+    if (r >= rows) {     // padding rows of the operand: zero codes, zero exponents
+        for (int j = 0; j < nbl; ++j) {
+            q[(b0 + j) * 128 + lane] = 0;
+            q[(b0 + j) * 128 + 64 + lane] = 0;
+            if (lane == 0) E[r * nb + b0 + j] = 0;
+        }
         return;
     }
     const int64_t base = offR[r];
-    const int64_t k0 = blk * 128 + 2 * lane;
-    const float v0 = k0 < K ? X[base + offK[k0]] : 0.f;
-    const float v1 = k0 + 1 < K ? X[base + offK[k0 + 1]] : 0.f;
-    float amax = fmaxf(fabsf(v0), fabsf(v1));
+    float v0[kQuantRun], v1[kQuantRun];
 #pragma unroll
-    for (int s = 32; s > 0; s >>= 1) amax = fmaxf(amax, __shfl_xor(amax, s, 64));
-    const int e = fp8_scale_exp(amax);
-    const float inv = ldexpf(1.f, -e);    // exact power of two (e >= -127: 2^127 fits)
-    const unsigned c0 = k0 < K ? e4m3_code(v0 * inv) : 0u;
-    const unsigned c1 = k0 + 1 < K ? e4m3_code(v1 * inv) : 0u;
-    *reinterpret_cast<uint16_t *>(q + 2 * lane) = (uint16_t)(c0 | (c1 << 8));
-    if (lane == 0) E[r * nb + blk] = e;
+    for (int j = 0; j < kQuantRun; ++j) {
+        const int64_t blk = j < nbl ? b0 + j : nb - 1;
+        const int64_t k0 = blk * 128 + lane, k1 = k0 + 64;
+        const float x0 = X[base + offK[k0 < K ? k0 : K - 1]];
+        const float x1 = X[base + offK[k1 < K ? k1 : K - 1]];
+        v0[j] = k0 < K ? x0 : 0.f;
+        v1[j] = k1 < K ? x1 : 0.f;
+    }
+#pragma unroll
+    for (int j = 0; j < kQuantRun; ++j) {
+        if (j >= nbl) break;                            // uniform across the wave
+        float amax = fmaxf(fabsf(v0[j]), fabsf(v1[j]));
+#pragma unroll
+        for (int s = 32; s > 0; s >>= 1) amax = fmaxf(amax, __shfl_xor(amax, s, 64));
+        const int e = fp8_scale_exp(amax);
+        const float inv = ldexpf(1.f, -e);    // exact power of two (e >= -127: 2^127 fits)
+        const int64_t k0 = (b0 + j) * 128 + lane, k1 = k0 + 64;
+        q[k0] = (uint8_t)(k0 < K ? e4m3_code(v0[j] * inv) : 0u);
+        q[k1] = (uint8_t)(k1 < K ? e4m3_code(v1[j] * inv) : 0u);
+        if (lane == 0) E[r * nb + b0 + j] = e;
+    }
 }
 
 // Lanes along the rows: one wave per (16 rows, 128-block); four lanes share a
@@ -345,7 +372,8 @@ int launch_fp8_quant(const float *X, const int64_t *offR, const int32_t *rowMap,
                      int64_t rowsPad, const int64_t *offK, int64_t K, bool rowsFast, uint8_t *Q,
                      int32_t *E, hipStream_t s) {
     const int64_t nb = (K + 127) / 128;
-    const int64_t tasks = rowsFast ? (rowsPad + 15) / 16 * nb : rowsPad * nb;
+    const int64_t tasks = rowsFast ? (rowsPad + 15) / 16 * nb
+                                   : rowsPad * ((nb + kQuantRun - 1) / kQuantRun);
     const int64_t blocks = (tasks + 3) / 4;
     if (blocks > INT32_MAX) return GETT_ERR_INTERNAL;
     (void)hipGetLastError();   // clear a stale error left by other HIP users

@@ -232,9 +232,12 @@ def test_fp8_quantizer_codes_bitwise():
     import torch
     rng = np.random.default_rng(31)
     # rows the cheap direction (lanes along rows, ragged row groups and blocks)
-    # and contracted positions the cheap direction (lanes along K)
+    # and contracted positions the cheap direction (lanes along K; the last
+    # two cases span several runs of blocks per wave, the last run and its
+    # last block ragged)
     for shape, cont in (([40, 300], [1]), ([150, 3, 200], [2]), ([7, 5, 33, 6], [2, 0]),
-                        ([130, 129], [0])):
+                        ([130, 129], [0]), ([2500, 9], [0]), ([1030, 3, 5], [0]),
+                        ([9, 2500], [1])):
         X = W.make_view(shape, rng, np.float32, layout="sub", dist="normal")
         X.buf[X.element_index()] *= (10.0 ** rng.uniform(-3, 3, X.element_index().size)).astype(np.float32)
         free = [i for i in range(len(shape)) if i not in cont]
