@@ -223,7 +223,9 @@ int gett_tile_shape(int prec, int64_t t, int64_t *out);
 /* Force one schedule for every following call on any thread (id < 0 clears). */
 int gett_set_schedule(int64_t id);
 /* Schedule the calling thread's last call ran (or -1); a split schedule that
-   ran unsplit because of the workspace cap reports split option 0. */
+   ran unsplit because of the workspace cap reports split option 0.  An FP8
+   call reports its GEMM tile (0: 64x64, 3: 128x128, chosen by tile count)
+   with order and split 0. */
 int64_t gett_last_schedule(void);
 
 /* Cap, in bytes, on the FP64 partial-sum workspace of split-K schedules

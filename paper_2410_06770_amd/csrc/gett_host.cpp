@@ -506,6 +506,9 @@ static int run_fp8(const Args &a, const float *A, const float *B, float *C, hipS
     Fp8Plan *pl = nullptr;
     int rc = get_fp8_plan(a, dev, &pl);
     if (rc) return rc;
+    // The FP8 path has no schedule menu: its GEMM tile (64x64 or 128x128) is
+    // chosen by tile count; reported as that tile with order and split 0.
+    t_last_schedule = sched_id(Sched{pl->tile, 0, 0});
     const int64_t M = pl->M, N = pl->N, K = pl->K, nb = pl->nb, Kp = pl->Kp;
     const int64_t *rowsA = pl->d_tab, *kA = rowsA + M, *rowsB = kA + K, *kB = rowsB + N;
     const int64_t *offCM = kB + K, *offCN = offCM + M;

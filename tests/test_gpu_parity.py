@@ -324,6 +324,7 @@ def test_fp8_cc_error_is_reported():
     exact result is reported (not gated); codes follow the model."""
     pr = W.config_cc()
     got = run_gpu(pr, gett.GETT_FP8, "cc fp8")
+    assert gett.gett_last_schedule() == 3       # 128x128 GEMM tiles (5184 of them)
     ref, cabs = oracle.exact(pr, pr.A, pr.B, pr.C, 0, 3000)
     sel = ~np.isnan(ref)
     en = e_nrm(got[sel], ref[sel])
