@@ -73,7 +73,9 @@ def parse():
                     help="problems in the batched leg (graph replay vs separate calls); 0 skips")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
-    ap.add_argument("--traffic-json", default="profiles/traffic.json",
+    ap.add_argument("--traffic-json",
+                    default=os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                                         "traffic.json"),
                     help="HBM traffic per launch measured with rocprofv3 counters")
     return ap.parse_args()
 
