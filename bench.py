@@ -84,8 +84,8 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this benchmark runs on exactly one GPU; the contraction is "
-                                   "not sharded across GPUs in this build (see DESIGN.md)",
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; the library does "
+                                   "not shard a contraction across GPUs",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 

@@ -19,7 +19,7 @@
  *     Coordinates).  C is updated as C <- C + A*B (Algorithm 1's update), so
  *     the oracle accumulates into C; it never clears it.
  *
- * Readings of the paper that this file relies on (each is listed in the design doc):
+ * Readings of the paper that this file relies on:
  *   - The two IncCoords calls of Algorithm 1 pass the extent arrays the wrong
  *     way round; the contracted odometer wraps at the contracted extents and the
  *     free odometer at the free extents.
