@@ -20,8 +20,8 @@ const char *last_hip_error_name() {
     int launch_tile_##SUFFIX(int tile, bool afk, bool bfk, const TileParams &p, hipStream_t s);    \
     int launch_splitk_reduce_##SUFFIX(const TileParams &p, hipStream_t s);                        \
     int batch_grid_size_##SUFFIX();                                                                \
-    int launch_batch_##SUFFIX(const BatchProblem *d, const int32_t *it, int32_t n, int32_t g,      \
-                              hipStream_t s);                                                      \
+    int launch_batch_##SUFFIX(const BatchProblem *d, const int32_t *it, int32_t n, int32_t *nx,    \
+                              int32_t g, hipStream_t s);                                                      \
     int launch_batch_reduce_##SUFFIX(const BatchProblem *d, const int32_t *l, int32_t n,           \
                                      hipStream_t s);                                               \
     int64_t addr_violations_##SUFFIX(bool reset);
@@ -57,12 +57,12 @@ int batch_grid_size(int prec) {
 }
 
 int launch_batch(int prec, const BatchProblem *d_probs, int32_t nprobs, const int32_t *d_items,
-                 int32_t nitems, int32_t grid, hipStream_t s) {
+                 int32_t nitems, int32_t *d_next, int32_t grid, hipStream_t s) {
     (void)nprobs;
     switch (prec) {
-    case kF64: return launch_batch_f64(d_probs, d_items, nitems, grid, s);
-    case kF32: return launch_batch_f32(d_probs, d_items, nitems, grid, s);
-    case kBF3: return launch_batch_bf3(d_probs, d_items, nitems, grid, s);
+    case kF64: return launch_batch_f64(d_probs, d_items, nitems, d_next, grid, s);
+    case kF32: return launch_batch_f32(d_probs, d_items, nitems, d_next, grid, s);
+    case kBF3: return launch_batch_bf3(d_probs, d_items, nitems, d_next, grid, s);
     default: return GETT_ERR_INTERNAL;
     }
 }

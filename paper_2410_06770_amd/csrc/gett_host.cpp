@@ -1105,7 +1105,10 @@ static int run_batch(int prec, int64_t count, const Args *args, const void *cons
             return GETT_ERR_HIP;
         nb->nprobs = (int32_t)count;
         nb->nitems = (int32_t)(items.size() / 2);
-        const size_t dbytes = sizeof(BatchProblem) * std::max<int64_t>(count, 1);
+        // The descriptors, then the batch kernel's item counter: each replay's
+        // copy of the pinned buffer (whose counter word stays 0) clears it.
+        const size_t desc_bytes = sizeof(BatchProblem) * std::max<int64_t>(count, 1);
+        const size_t dbytes = desc_bytes + 256;
         if (hipMalloc(reinterpret_cast<void **>(&nb->d_desc), dbytes) != hipSuccess ||
             hipMalloc(reinterpret_cast<void **>(&nb->d_items),
                       std::max<size_t>(items.size(), 2) * sizeof(int32_t)) != hipSuccess)
@@ -1132,7 +1135,10 @@ static int run_batch(int prec, int64_t count, const Args *args, const void *cons
                                       cs) != hipSuccess)
                 rc = GETT_ERR_HIP;
             if (!rc && nb->nitems > 0)
-                rc = launch_batch(prec, nb->d_desc, nb->nprobs, nb->d_items, nb->nitems, grid, cs);
+                rc = launch_batch(prec, nb->d_desc, nb->nprobs, nb->d_items, nb->nitems,
+                                  reinterpret_cast<int32_t *>(
+                                      reinterpret_cast<char *>(nb->d_desc) + desc_bytes),
+                                  grid, cs);
             if (!rc && !cut.empty())
                 rc = launch_batch_reduce(prec, nb->d_desc, nb->d_split, (int32_t)cut.size(), cs);
             hipGraph_t g = nullptr;

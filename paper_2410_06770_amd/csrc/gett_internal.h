@@ -20,8 +20,10 @@ const char *last_hip_error_name();
 int launch_tile(int prec, int tile, bool aFastK, bool bFastK, const TileParams &p,
                 hipStream_t s);
 int launch_splitk_reduce(int prec, const TileParams &p, hipStream_t s);
+// Persistent batch kernel: its workgroups claim items through *d_next, which
+// must be 0 when the kernel starts.
 int launch_batch(int prec, const BatchProblem *d_probs, int32_t nprobs, const int32_t *d_items,
-                 int32_t nitems, int32_t grid, hipStream_t s);
+                 int32_t nitems, int32_t *d_next, int32_t grid, hipStream_t s);
 int batch_grid_size(int prec);
 // C = C_in + sum of the FP64 slice partials for the listed batch problems
 // (those cut along K), reading their descriptors on the device.

@@ -688,18 +688,27 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(TileParams p) {
 
 // ---------------------------------------------------------------------------
 // Batched launch: one persistent grid walks a work list of (problem, tile,
-// K slice) items, longest first; every item runs the same tile code as a
-// single call with the 64x64 tile of the precision.  Each problem's
+// K slice) items, longest first, each workgroup taking the next unclaimed
+// item from a counter (so one that drew long items takes fewer); every item
+// runs the same tile code as a single call with the 64x64 tile of the
+// precision.  Each problem's
 // descriptor says which operands read along K, and a uniform switch picks the
 // matching compiled loader variant.
 // ---------------------------------------------------------------------------
 template <int PREC>
 __global__ __launch_bounds__(kThreads) void gett_batch_kernel(const BatchProblem *__restrict__ probs,
                                                               const int32_t *__restrict__ items,
-                                                              int32_t nitems) {
+                                                              int32_t nitems, int32_t *next) {
     extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int32_t s_item;
     constexpr TileShape ts = kTiles[PREC][0];
-    for (int32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+    // *next starts at 0 (the launch's descriptor copy clears it); every
+    // workgroup leaves once the count has passed the last item.
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(next, 1);
+        __syncthreads();
+        const int32_t it = s_item;
+        if (it >= nitems) break;
         const int32_t pi = items[2 * it];
         const int32_t tile = items[2 * it + 1];
         const BatchProblem &bp = probs[pi];
@@ -722,7 +731,7 @@ __global__ __launch_bounds__(kThreads) void gett_batch_kernel(const BatchProblem
             gett_tile<PREC, ts.bm, ts.bn, ts.bk, true, false>(p, m0, n0, kbeg, kend, split, smem);
         else
             gett_tile<PREC, ts.bm, ts.bn, ts.bk, true, true>(p, m0, n0, kbeg, kend, split, smem);
-        __syncthreads();   // the next item reuses the LDS stages
+        __syncthreads();   // the next item reuses the LDS stages and s_item
     }
 }
 
@@ -829,11 +838,11 @@ template <int PREC> static int batch_grid_size_prec() {
 
 template <int PREC>
 static int launch_batch_prec(const BatchProblem *d_probs, const int32_t *d_items, int32_t nitems,
-                             int32_t grid, hipStream_t s) {
+                             int32_t *d_next, int32_t grid, hipStream_t s) {
     if (grid < 1 || nitems < 1) return 0;
     (void)hipGetLastError();   // clear a stale error left by other HIP users
     hipLaunchKernelGGL(gett_batch_kernel<PREC>, dim3(grid), dim3(kThreads), batch_lds<PREC>(), s,
-                       d_probs, d_items, nitems);
+                       d_probs, d_items, nitems, d_next);
     return launch_status();
 }
 
@@ -875,9 +884,9 @@ static int64_t addr_violations_here(bool reset) {
         return launch_splitk_reduce_prec<PREC>(p, s);                                              \
     }                                                                                              \
     int batch_grid_size_##SUFFIX() { return batch_grid_size_prec<PREC>(); }                        \
-    int launch_batch_##SUFFIX(const BatchProblem *d, const int32_t *it, int32_t n, int32_t g,      \
-                              hipStream_t s) {                                                     \
-        return launch_batch_prec<PREC>(d, it, n, g, s);                                            \
+    int launch_batch_##SUFFIX(const BatchProblem *d, const int32_t *it, int32_t n, int32_t *nx,    \
+                              int32_t g, hipStream_t s) {                                          \
+        return launch_batch_prec<PREC>(d, it, n, nx, g, s);                                        \
     }                                                                                              \
     int launch_batch_reduce_##SUFFIX(const BatchProblem *d, const int32_t *l, int32_t n,           \
                                      hipStream_t s) {                                              \
