@@ -187,6 +187,33 @@ def test_graph_replay_with_new_pointers():
             check_problem(pr, d[2].cpu().numpy(), gett.GETT_FP32, sample=32)
 
 
+def test_replays_claim_every_item_each_time():
+    """The persistent kernel's workgroups claim items from a counter that each
+    replay's descriptor copy clears.  Six replays in a row on one signature
+    set, with the program's own GPU work and synchronisations between them,
+    C reset before each: every replay must give the first replay's result
+    bit for bit (a counter left over from the previous replay would skip
+    items and leave C_in in place)."""
+    import torch
+    problems = W.config_batch(48, seed=12)
+    dev = upload(problems)
+    first = None
+    for rep in range(6):
+        for pr, d in zip(problems, dev):
+            d[2].copy_(torch.from_numpy(pr.C.buf).cuda())
+        scratch = torch.randn(1 << 20, device="cuda")
+        (scratch * 2.0).sum().item()               # eager work between replays
+        assert run_batch(problems, dev, gett.GETT_BF16X3)[0] == 0
+        got = [d[2].cpu().numpy() for d in dev]
+        if first is None:
+            first = got
+            for pr, g in zip(problems[:8], got[:8]):
+                check_problem(pr, g, gett.GETT_BF16X3, sample=32)
+        else:
+            for a, b in zip(first, got):
+                assert np.array_equal(a, b), rep
+
+
 def test_batch_rejects_invalid_problem_and_skips_empty():
     rng = np.random.default_rng(5)
     problems = [W.paper_case("basic", rng, dtype=np.float32) for _ in range(4)]
