@@ -39,6 +39,10 @@ def build(force: bool = True) -> str:
     return _LIB
 
 
+KINDS = {np.dtype(np.float64): 0, np.dtype(np.float32): 1, np.dtype(np.complex128): 2,
+         np.dtype(np.complex64): 3}
+
+
 def lib():
     global _lib
     if _lib is None:
@@ -47,19 +51,35 @@ def lib():
         L = ct.CDLL(_LIB)
         vp = ct.c_void_p
         i64 = ct.c_int64
+        dp = ct.POINTER(ct.c_double)
         args14 = [i64, I64P, I64P, vp, i64, I64P, I64P, vp, i64, I64P, I64P, I64P, I64P, vp]
         L.gett_ref_check.argtypes = args14
         L.gett_ref_check.restype = ct.c_int
         L.gett_ref_dgett.argtypes = args14
         L.gett_ref_dgett.restype = ct.c_int
+        L.gett_ref_zgett.argtypes = args14
+        L.gett_ref_zgett.restype = ct.c_int
         L.gett_ref_sgett_f64.argtypes = args14 + [vp, vp, i64, i64]
         L.gett_ref_sgett_f64.restype = ct.c_int
         L.gett_ref_dgett_range.argtypes = args14 + [vp, vp, i64, i64]
         L.gett_ref_dgett_range.restype = ct.c_int
+        L.gett_ref_exact.argtypes = [ct.c_int] + args14 + [vp, vp, i64, i64]
+        L.gett_ref_exact.restype = ct.c_int
+        L.gett_ref_exact_at.argtypes = [ct.c_int] + args14 + [i64, vp, vp, vp]
+        L.gett_ref_exact_at.restype = ct.c_int
+        L.gett_ref_exact_ex.argtypes = [ct.c_int, dp, i64, I64P, I64P, vp, i64, I64P, I64P, vp,
+                                        i64, I64P, I64P, i64, I64P, I64P, I64P, I64P, dp, vp,
+                                        vp, vp, i64, i64, i64, vp, vp, vp]
+        L.gett_ref_exact_ex.restype = ct.c_int
+        L.gett_ref_unary.argtypes = [ct.c_int, dp, i64, I64P, I64P, vp, i64, I64P, i64, I64P,
+                                     I64P, I64P, I64P, dp, vp, vp, vp, i64, i64, i64, vp, vp,
+                                     vp]
+        L.gett_ref_unary.restype = ct.c_int
         L.gett_ref_num_threads.restype = ct.c_int
         L.gett_ref_set_num_threads.argtypes = [ct.c_int]
         L.gett_ref_output_offsets.argtypes = [i64, I64P, I64P, i64, I64P, I64P, i64, I64P, I64P,
                                               I64P, I64P, i64, I64P, I64P]
+        L.gett_ref_output_offsets.restype = ct.c_int
         L.gett_ref_bf16_split.argtypes = [i64, vp, vp, vp]
         L.gett_ref_e4m3_decode.argtypes = [ct.c_uint8]
         L.gett_ref_e4m3_decode.restype = ct.c_double
@@ -86,6 +106,17 @@ def _ptr(buf: np.ndarray | None, base: int):
     return ct.c_void_p(buf.ctypes.data + int(base) * buf.itemsize)
 
 
+def _kind(*bufs) -> int:
+    kinds = {KINDS[np.dtype(b.dtype)] for b in bufs if b is not None}
+    assert len(kinds) == 1, "A, B and C must hold the same element type"
+    return kinds.pop()
+
+
+def _scalar(x):
+    z = complex(x)
+    return (ct.c_double * 2)(z.real, z.imag)
+
+
 def check(ranka, exta, inca, rankb, extb, incb, conts, conta, contb, perm, incc,
           A=1, B=1, C=1) -> int:
     """INFO code of the oracle's own argument checks (0 = valid).  A, B, C are
@@ -96,36 +127,128 @@ def check(ranka, exta, inca, rankb, extb, incb, conts, conta, contb, perm, incc,
                                 _arr(incc), p(C))
 
 
+def _args14(pr, A, B, C):
+    return (pr.ranka, _arr(pr.exta), _arr(pr.inca), _ptr(A.buf, A.base),
+            pr.rankb, _arr(pr.extb), _arr(pr.incb), _ptr(B.buf, B.base),
+            pr.conts, _arr(pr.conta), _arr(pr.contb), _arr(pr.perm),
+            _arr(pr.incc), _ptr(C.buf, C.base))
+
+
 def dgett(pr, A, B, C) -> int:
     """FP64 xGETT in place on the oracle: C <- C + sum A*B (Algorithm 1).
     ``pr`` carries the integer arguments; A, B, C are views over float64."""
-    return lib().gett_ref_dgett(pr.ranka, _arr(pr.exta), _arr(pr.inca), _ptr(A.buf, A.base),
-                                pr.rankb, _arr(pr.extb), _arr(pr.incb), _ptr(B.buf, B.base),
-                                pr.conts, _arr(pr.conta), _arr(pr.contb), _arr(pr.perm),
-                                _arr(pr.incc), _ptr(C.buf, C.base))
+    return lib().gett_ref_dgett(*_args14(pr, A, B, C))
+
+
+def zgett(pr, A, B, C) -> int:
+    """Complex FP64 xGETT in place (views over complex128)."""
+    return lib().gett_ref_zgett(*_args14(pr, A, B, C))
+
+
+def _out_buffers(C):
+    cx = np.iscomplexobj(C.buf)
+    cout = np.full(C.buf.shape, np.nan, dtype=np.complex128 if cx else np.float64)
+    if cx:
+        cout[:] = complex(np.nan, np.nan)
+    cabs = np.full(C.buf.shape, np.nan, dtype=np.float64)
+    return cout, cabs
 
 
 def exact(pr, A, B, C, first: int = 0, last: int = -1):
-    """Exact-in-double contraction of the views' values (float32 or float64):
-    returns (Cout, Cabs) as float64 parent buffers shaped like C's parent,
-    Cout = C_in + sum a*b and Cabs = |C_in| + sum |a||b| at every output
-    position of [first, last) of the free odometer; other entries are NaN."""
-    cout = np.full(C.buf.shape, np.nan, dtype=np.float64)
-    cabs = np.full(C.buf.shape, np.nan, dtype=np.float64)
-    args = (pr.ranka, _arr(pr.exta), _arr(pr.inca), _ptr(A.buf, A.base),
-            pr.rankb, _arr(pr.extb), _arr(pr.incb), _ptr(B.buf, B.base),
-            pr.conts, _arr(pr.conta), _arr(pr.contb), _arr(pr.perm),
-            _arr(pr.incc), _ptr(C.buf, C.base), _ptr(cout, C.base), _ptr(cabs, C.base),
-            int(first), int(last))
-    if A.buf.dtype == np.float32:
-        assert B.buf.dtype == np.float32 and C.buf.dtype == np.float32
-        info = lib().gett_ref_sgett_f64(*args)
-    else:
-        assert A.buf.dtype == np.float64 and B.buf.dtype == np.float64 and C.buf.dtype == np.float64
-        info = lib().gett_ref_dgett_range(*args)
+    """Exact-in-double contraction of the views' values (float32, float64,
+    complex64 or complex128): returns (Cout, Cabs) as parent buffers shaped
+    like C's parent, Cout = C_in + sum a*b (complex128 for complex data) and
+    Cabs = |C_in| + sum |a||b| (complex |x| = |Re x| + |Im x|) at every
+    output position of [first, last) (first output mode fastest); other
+    entries are NaN."""
+    cout, cabs = _out_buffers(C)
+    info = lib().gett_ref_exact(_kind(A.buf, B.buf, C.buf), *_args14(pr, A, B, C),
+                                _ptr(cout, C.base), _ptr(cabs, C.base), int(first), int(last))
     if info:
         raise ValueError(f"oracle rejected the arguments: INFO={info}")
     return cout, cabs
+
+
+def exact_at(pr, A, B, C, positions):
+    """The same as :func:`exact` for a list of output positions: returns
+    (values, bounds) in list order (values complex128 for complex data)."""
+    pos = np.ascontiguousarray(positions, dtype=np.int64)
+    cx = np.iscomplexobj(C.buf)
+    val = np.empty(pos.size, dtype=np.complex128 if cx else np.float64)
+    bnd = np.empty(pos.size, dtype=np.float64)
+    info = lib().gett_ref_exact_at(_kind(A.buf, B.buf, C.buf), *_args14(pr, A, B, C), pos.size,
+                                   pos.ctypes.data, val.ctypes.data, bnd.ctypes.data)
+    if info:
+        raise ValueError(f"oracle rejected the arguments: INFO={info}")
+    return val, bnd
+
+
+def output_offsets(pr, positions):
+    """Element offsets in C (relative to coordinate 0) of output positions."""
+    pos = np.ascontiguousarray(positions, dtype=np.int64)
+    off = np.empty(pos.size, dtype=np.int64)
+    info = lib().gett_ref_output_offsets(pr.ranka, _arr(pr.exta), _arr(pr.inca), pr.rankb,
+                                         _arr(pr.extb), _arr(pr.incb), pr.conts, _arr(pr.conta),
+                                         _arr(pr.contb), _arr(pr.perm), _arr(pr.incc), pos.size,
+                                         pos.ctypes.data_as(I64P), off.ctypes.data_as(I64P))
+    assert info == 0
+    return off
+
+
+def exact_ex(pr, A, B, C, alpha=1.0, beta=1.0, hada=(), hadb=(), first=0, last=-1,
+             positions=None):
+    """Scaled contraction with Hadamard pairs: alpha * sum + beta * C_in.
+    ``pr.perm``/``pr.incc`` cover A's free modes, B's free modes, then the
+    pairs (hada[h], hadb[h]).  Returns (Cout, Cabs) parent buffers, or
+    (values, bounds) for a list of positions."""
+    kind = _kind(A.buf, B.buf, C.buf)
+    hads = len(hada)
+    common = (kind, _scalar(alpha), pr.ranka, _arr(pr.exta), _arr(pr.inca), _ptr(A.buf, A.base),
+              pr.rankb, _arr(pr.extb), _arr(pr.incb), _ptr(B.buf, B.base), pr.conts,
+              _arr(pr.conta), _arr(pr.contb), hads, _arr(hada), _arr(hadb), _arr(pr.perm),
+              _arr(pr.incc), _scalar(beta), _ptr(C.buf, C.base))
+    if positions is None:
+        cout, cabs = _out_buffers(C)
+        info = lib().gett_ref_exact_ex(*common, _ptr(cout, C.base), _ptr(cabs, C.base),
+                                       int(first), int(last), -1, None, None, None)
+        if info:
+            raise ValueError(f"oracle rejected the arguments: INFO={info}")
+        return cout, cabs
+    pos = np.ascontiguousarray(positions, dtype=np.int64)
+    val = np.empty(pos.size, dtype=np.complex128 if kind >= 2 else np.float64)
+    bnd = np.empty(pos.size, dtype=np.float64)
+    info = lib().gett_ref_exact_ex(*common, None, None, 0, 0, pos.size, pos.ctypes.data,
+                                   val.ctypes.data, bnd.ctypes.data)
+    if info:
+        raise ValueError(f"oracle rejected the arguments: INFO={info}")
+    return val, bnd
+
+
+def unary(A, suma, tra, trb, perm, incc, C, alpha=1.0, beta=1.0, first=0, last=-1,
+          positions=None):
+    """Unary operation on the view A: alpha * (sum over the modes ``suma``
+    and the trace pairs (tra[t], trb[t])) + beta * C_in, output modes = A's
+    remaining modes in ascending order placed by ``perm`` with increments
+    ``incc``.  Returns (Cout, Cabs) or (values, bounds) like exact_ex."""
+    kind = _kind(A.buf, C.buf)
+    common = (kind, _scalar(alpha), len(A.ext), _arr(A.ext), _arr(A.inc), _ptr(A.buf, A.base),
+              len(suma), _arr(suma), len(tra), _arr(tra), _arr(trb), _arr(perm), _arr(incc),
+              _scalar(beta), _ptr(C.buf, C.base))
+    if positions is None:
+        cout, cabs = _out_buffers(C)
+        info = lib().gett_ref_unary(*common, _ptr(cout, C.base), _ptr(cabs, C.base), int(first),
+                                    int(last), -1, None, None, None)
+        if info:
+            raise ValueError(f"oracle rejected the arguments: INFO={info}")
+        return cout, cabs
+    pos = np.ascontiguousarray(positions, dtype=np.int64)
+    val = np.empty(pos.size, dtype=np.complex128 if kind >= 2 else np.float64)
+    bnd = np.empty(pos.size, dtype=np.float64)
+    info = lib().gett_ref_unary(*common, None, None, 0, 0, pos.size, pos.ctypes.data,
+                                val.ctypes.data, bnd.ctypes.data)
+    if info:
+        raise ValueError(f"oracle rejected the arguments: INFO={info}")
+    return val, bnd
 
 
 def num_threads() -> int:

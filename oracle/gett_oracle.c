@@ -1,47 +1,71 @@
 /*
- * gett_oracle.c -- plain, slow CPU oracle for the xGETT binary tensor contraction.
+ * gett_oracle.c -- plain, slow CPU oracle of the binary tensor contraction.
  *
  * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the CPU
  * baseline leg of the benchmark load this file's library.  It shares no code,
- * header, table or helper with the GPU library; it is written straight from the
- * paper ("BLAS-like Interface for Binary Tensor Contractions", arXiv 2410.06770):
+ * header, table or helper with the GPU library.  What it computes comes from
+ * "BLAS-like Interface for Binary Tensor Contractions" (arXiv 2410.06770):
  *
- *   - Section 2.2 (Binary Tensor Contraction): the definition.  Every output
- *     value is the sum, over all coordinates of the contracted indices, of the
- *     product of the matching values of A and B; contracted extents must agree;
- *     the free indices may appear in C in any order.
+ *   - Section 2.2 (Binary Tensor Contraction): each output value is the sum,
+ *     over every coordinate combination of the contracted indices, of the
+ *     product of the matching values of A and B; paired contracted indices have
+ *     equal extents; the free indices may be placed in C in any order.
  *   - Section 5.6 (Selecting permutation), fourth option: PERM has one entry per
- *     free index, A's free indices first then B's, and the entry is the position
- *     of that index in C.
+ *     free index, A's free indices first then B's, and each entry is the
+ *     position of that index in C.
  *   - Section 5.7 (Parameter order): the final argument list.
- *   - Section 6 (Implementation): the preprocessing into "manageable format"
- *     and Algorithm 1 (Binary Tensor Contraction) with Algorithm 2 (Increment
- *     Coordinates).  C is updated as C <- C + A*B (Algorithm 1's update), so
- *     the oracle accumulates into C; it never clears it.
+ *   - Section 6 (Implementation), Algorithm 1: C <- C + A*B for every term,
+ *     the contracted coordinates walked with the first index changing fastest
+ *     (Algorithm 2), so this oracle accumulates into C and never clears it.
  *
- * Readings of the paper that this file relies on:
- *   - The two IncCoords calls of Algorithm 1 pass the extent arrays the wrong
- *     way round; the contracted odometer wraps at the contracted extents and the
- *     free odometer at the free extents.
+ * How it is organised (its own form, not the printed listing): the arguments
+ * are first turned into two lists of modes, the OUTPUT modes of C in output
+ * order (extent and the increment of each of A, B and C along the mode) and
+ * the SUMMED modes (extent and the increments of A and B).  Every output is
+ * then formed on its own: its linear position s (first output mode fastest)
+ * is decoded into coordinates by division and remainder, and the summed
+ * modes are walked by a recursive loop nest whose innermost loop runs over the
+ * first summed mode, which visits the terms in the order of Algorithm 1.
+ * There is no rank limit: every per-mode array is allocated to the rank.
+ *
+ * Extensions beyond the paper's xGETT, each reduced to the same two lists:
+ *   - complex data (the c and z prefixes of Section 2.3): a product is the
+ *     complex product, formed as (ar br - ai bi) + i (ar bi + ai br);
+ *   - scaling C <- alpha * sum + beta * C (the ALPHA/BETA of xGEMM, Section
+ *     2.3.1) and Hadamard modes (Section 9, future work): a mode carried by A,
+ *     B and C alike is an output mode with increments in all three;
+ *   - unary operations (Section 9: reduction, transpose, trace): there is no
+ *     B; summed modes are single modes of A or trace pairs of modes of A (a
+ *     pair walks one coordinate along both, so its increment is their sum).
+ *
+ * Readings of the paper this file relies on:
+ *   - The two odometer calls of Algorithm 1 pass the extent arrays the wrong
+ *     way round; the contracted walk wraps at the contracted extents and the
+ *     free walk at the free extents.
  *   - INCC is indexed by output position (the "increments of C" of Section 6),
  *     not the two leading dimensions of the matrix stage.
  *   - Increments are element counts of any sign; each pointer addresses the
- *     element whose coordinates are all zero.
+ *     element whose coordinates are all zero.  Complex increments count
+ *     complex elements.
  *   - Indices in CONTA, CONTB and PERM are 0-based.
  *
- * Floating point: every product and every sum is one IEEE double operation in
- * the serial order of Algorithm 1 (compile with -ffp-contract=off).  OpenMP
- * splits only the outer loop over output elements, so each element's sum is
- * formed in the same order whatever the thread count.
+ * Floating point: every product and every sum is one IEEE double operation
+ * (compile with -ffp-contract=off).  Each output's sum starts from C_in and
+ * takes its terms in Algorithm 1's order, so the result does not depend on
+ * how the outputs are split over threads.  Alongside each value the oracle
+ * forms the bound |C_in| + sum |a||b| (complex: |x| = |Re x| + |Im x|), the
+ * denominator of the component-wise error measure.
  *
  * Pins (tests/test_oracle.py, run without a GPU): brute force from the
- * definition over full index tuples, numpy.einsum, numpy.matmul for the matrix
- * special cases, closed forms (all-ones operands, outer product, scalar
- * operand), commutativity and cyclic output shifts, sub-tensor extraction and
- * negative increments.  The FP8 and BF16x3 models below are pinned by the
- * format definitions (exhaustive decode/encode round trips), by exact
- * reproduction on values that the formats represent exactly, and by their
- * error bounds against the exact contraction.
+ * definition over full index tuples (values and the absolute-value bound),
+ * numpy.einsum, numpy.matmul for the matrix special cases, closed forms
+ * (all-ones operands, outer product, scalar operand), commutativity and
+ * cyclic output shifts, sub-tensor extraction, negative increments, a
+ * rank-70 contraction, the four real contractions that make up a complex one,
+ * and planted mistakes that the pins must reject.  The FP8 and BF16x3 models
+ * at the end are pinned by the format definitions (exhaustive decode/encode
+ * round trips), by exact reproduction on values that the formats represent
+ * exactly, and by their error bounds against the exact contraction.
  */
 #include <math.h>
 #include <stdint.h>
@@ -51,7 +75,8 @@
 #include <omp.h>
 #endif
 
-#define REF_MAXRANK 64
+/* Element kinds of the data pointers. */
+enum { REF_F64 = 0, REF_F32 = 1, REF_Z128 = 2, REF_C64 = 3 };
 
 /* ------------------------------------------------------------------------- */
 /* Argument checks: LAPACK-style INFO, -i names the i-th argument in the      */
@@ -81,7 +106,7 @@ static int ref_span_ok(int64_t rank, const int64_t *ext, const int64_t *inc) {
     return 1;
 }
 
-static int ref_nelem(int64_t rank, const int64_t *ext, int64_t *n) {
+static int ref_count_ok(int64_t rank, const int64_t *ext, int64_t *n) {
     int64_t p = 1;
     for (int64_t i = 0; i < rank; ++i)
         if (!ref_mul_ok(p, ext[i], &p)) return 0;
@@ -89,283 +114,546 @@ static int ref_nelem(int64_t rank, const int64_t *ext, int64_t *n) {
     return 1;
 }
 
-int gett_ref_check(int64_t ranka, const int64_t *exta, const int64_t *inca, const void *A,
-                   int64_t rankb, const int64_t *extb, const int64_t *incb, const void *B,
-                   int64_t conts, const int64_t *conta, const int64_t *contb,
-                   const int64_t *perm, const int64_t *incc, const void *C) {
+/* Whether the list idx[0..n) holds distinct modes in [0, rank) that are not
+   yet marked in used[]; marks them. */
+static int ref_mark_modes(int64_t n, const int64_t *idx, int64_t rank, char *used) {
+    for (int64_t k = 0; k < n; ++k) {
+        if (idx[k] < 0 || idx[k] >= rank || used[idx[k]]) return 0;
+        used[idx[k]] = 1;
+    }
+    return 1;
+}
+
+/* Checks of the binary call with optional Hadamard pairs (hads = 0 is the
+   paper's xGETT).  INFO numbers the paper's 14 arguments; a bad Hadamard list
+   is reported as -15 (count) or -16 (modes). */
+static int ref_check_binary(int64_t ranka, const int64_t *exta, const int64_t *inca, const void *A,
+                            int64_t rankb, const int64_t *extb, const int64_t *incb, const void *B,
+                            int64_t conts, const int64_t *conta, const int64_t *contb,
+                            int64_t hads, const int64_t *hada, const int64_t *hadb,
+                            const int64_t *perm, const int64_t *incc, const void *C) {
     int64_t na = 0, nb = 0;
-    if (ranka < 0 || ranka > REF_MAXRANK) return -1;
+    if (ranka < 0) return -1;
     if (ranka > 0 && exta == NULL) return -2;
     for (int64_t i = 0; i < ranka; ++i) if (exta[i] < 0) return -2;
     if (ranka > 0 && inca == NULL) return -3;
     if (ranka > 0 && !ref_span_ok(ranka, exta, inca)) return -3;
-    if (!ref_nelem(ranka, exta, &na)) return -2;
+    if (!ref_count_ok(ranka, exta, &na)) return -2;
     if (na > 0 && A == NULL) return -4;
 
-    if (rankb < 0 || rankb > REF_MAXRANK) return -5;
+    if (rankb < 0) return -5;
     if (rankb > 0 && extb == NULL) return -6;
     for (int64_t i = 0; i < rankb; ++i) if (extb[i] < 0) return -6;
     if (rankb > 0 && incb == NULL) return -7;
     if (rankb > 0 && !ref_span_ok(rankb, extb, incb)) return -7;
-    if (!ref_nelem(rankb, extb, &nb)) return -6;
+    if (!ref_count_ok(rankb, extb, &nb)) return -6;
     if (nb > 0 && B == NULL) return -8;
 
     if (conts < 0 || conts > ranka || conts > rankb) return -9;
-    if (conts > 0 && conta == NULL) return -10;
-    for (int64_t k = 0; k < conts; ++k) {
-        if (conta[k] < 0 || conta[k] >= ranka) return -10;
-        for (int64_t l = 0; l < k; ++l) if (conta[l] == conta[k]) return -10;
+    if (hads < 0 || conts + hads > ranka || conts + hads > rankb) return -15;
+    char *useda = calloc((size_t)ranka + 1, 1), *usedb = calloc((size_t)rankb + 1, 1);
+    int64_t rc = ranka + rankb - 2 * conts - hads;
+    int64_t *extc = malloc(sizeof(int64_t) * (size_t)(rc + 1));
+    char *seen = calloc((size_t)rc + 1, 1);
+    int info = 0;
+    if (!useda || !usedb || !extc || !seen) { info = -1; goto done; }
+    if (conts > 0 && conta == NULL) { info = -10; goto done; }
+    if (!ref_mark_modes(conts, conta, ranka, useda)) { info = -10; goto done; }
+    if (conts > 0 && contb == NULL) { info = -11; goto done; }
+    if (!ref_mark_modes(conts, contb, rankb, usedb)) { info = -11; goto done; }
+    /* Section 2.2: paired contracted indices have equal extents. */
+    for (int64_t k = 0; k < conts; ++k)
+        if (exta[conta[k]] != extb[contb[k]]) { info = -11; goto done; }
+    if (hads > 0 && (hada == NULL || hadb == NULL)) { info = -16; goto done; }
+    if (!ref_mark_modes(hads, hada, ranka, useda) || !ref_mark_modes(hads, hadb, rankb, usedb)) {
+        info = -16;
+        goto done;
     }
-    if (conts > 0 && contb == NULL) return -11;
-    for (int64_t k = 0; k < conts; ++k) {
-        if (contb[k] < 0 || contb[k] >= rankb) return -11;
-        for (int64_t l = 0; l < k; ++l) if (contb[l] == contb[k]) return -11;
-        /* Section 2.2: paired contracted indices must have equal extents. */
-        if (exta[conta[k]] != extb[contb[k]]) return -11;
+    for (int64_t h = 0; h < hads; ++h)
+        if (exta[hada[h]] != extb[hadb[h]]) { info = -16; goto done; }
+    if (rc > 0 && perm == NULL) { info = -12; goto done; }
+    for (int64_t p = 0; p < rc; ++p) {
+        if (perm[p] < 0 || perm[p] >= rc || seen[perm[p]]) { info = -12; goto done; }
+        seen[perm[p]] = 1;
     }
-    int64_t rc = ranka + rankb - 2 * conts;
-    if (rc > 0 && perm == NULL) return -12;
-    {
-        char seen[2 * REF_MAXRANK];
-        memset(seen, 0, sizeof seen);
-        for (int64_t p = 0; p < rc; ++p) {
-            if (perm[p] < 0 || perm[p] >= rc || seen[perm[p]]) return -12;
-            seen[perm[p]] = 1;
-        }
-    }
-    /* Output extents follow from the free indices placed by PERM. */
-    int64_t extc[2 * REF_MAXRANK];
+    /* Output extents: A's free modes, B's free modes, then Hadamard pairs,
+       each placed by PERM. */
     {
         int64_t p = 0;
-        for (int64_t i = 0; i < ranka; ++i) {
-            int c = 0;
-            for (int64_t k = 0; k < conts; ++k) if (conta[k] == i) c = 1;
-            if (!c) extc[perm[p++]] = exta[i];
-        }
-        for (int64_t j = 0; j < rankb; ++j) {
-            int c = 0;
-            for (int64_t k = 0; k < conts; ++k) if (contb[k] == j) c = 1;
-            if (!c) extc[perm[p++]] = extb[j];
-        }
+        for (int64_t i = 0; i < ranka; ++i) if (!useda[i]) extc[perm[p++]] = exta[i];
+        for (int64_t j = 0; j < rankb; ++j) if (!usedb[j]) extc[perm[p++]] = extb[j];
+        for (int64_t h = 0; h < hads; ++h) extc[perm[p++]] = exta[hada[h]];
     }
-    if (rc > 0 && incc == NULL) return -13;
+    if (rc > 0 && incc == NULL) { info = -13; goto done; }
     for (int64_t q = 0; q < rc; ++q)
-        if (incc[q] == 0 && extc[q] > 1) return -13;
-    if (rc > 0 && !ref_span_ok(rc, extc, incc)) return -13;
-    int64_t nc = 0;
-    if (!ref_nelem(rc, extc, &nc)) return -13;
-    if (nc > 0 && C == NULL) return -14;
-    return 0;
+        if (incc[q] == 0 && extc[q] > 1) { info = -13; goto done; }
+    if (rc > 0 && !ref_span_ok(rc, extc, incc)) { info = -13; goto done; }
+    {
+        int64_t nc = 0;
+        if (!ref_count_ok(rc, extc, &nc)) { info = -13; goto done; }
+        if (nc > 0 && C == NULL) { info = -14; goto done; }
+    }
+done:
+    free(useda);
+    free(usedb);
+    free(extc);
+    free(seen);
+    return info;
+}
+
+int gett_ref_check(int64_t ranka, const int64_t *exta, const int64_t *inca, const void *A,
+                   int64_t rankb, const int64_t *extb, const int64_t *incb, const void *B,
+                   int64_t conts, const int64_t *conta, const int64_t *contb,
+                   const int64_t *perm, const int64_t *incc, const void *C) {
+    return ref_check_binary(ranka, exta, inca, A, rankb, extb, incb, B, conts, conta, contb, 0,
+                            NULL, NULL, perm, incc, C);
 }
 
 /* ------------------------------------------------------------------------- */
-/* Section 6 preprocessing: the "manageable format".                          */
+/* The two mode lists.                                                        */
 /* ------------------------------------------------------------------------- */
 typedef struct {
-    int64_t NumFreeInd, NumContInd;
-    int64_t SizeFreeInd, SizeContInd;
-    int64_t ExtFreeInd[2 * REF_MAXRANK];
-    int64_t IncFreeInd[2 * REF_MAXRANK];
-    int     TenFreeInd[2 * REF_MAXRANK]; /* 0 = A, 1 = B */
-    int64_t IncC[2 * REF_MAXRANK];
-    int64_t ExtContInd[REF_MAXRANK];
-    int64_t IncContA[REF_MAXRANK];       /* Algorithm 1's IncA: contracted increments of A */
-    int64_t IncContB[REF_MAXRANK];       /* Algorithm 1's IncB: contracted increments of B */
-} ref_prep_t;
+    int64_t nq;                        /* output modes, output order */
+    int64_t *q_ext, *q_a, *q_b, *q_c;  /* extent; increment in A, B, C */
+    int64_t nk;                        /* summed modes, first walked fastest */
+    int64_t *k_ext, *k_a, *k_b;        /* extent; increment in A, B */
+    int64_t outputs;                   /* product of the output extents */
+} ref_modes;
 
-static void ref_prepare(int64_t ranka, const int64_t *exta, const int64_t *inca,
-                        int64_t rankb, const int64_t *extb, const int64_t *incb,
-                        int64_t conts, const int64_t *conta, const int64_t *contb,
-                        const int64_t *perm, const int64_t *incc, ref_prep_t *P) {
-    P->NumFreeInd = ranka + rankb - 2 * conts;
-    P->NumContInd = conts;
-    /* Free indices of A in ascending mode order, then those of B (Section 5.6);
-       entry p of PERM is the output position of the p-th free index. */
+static void ref_modes_free(ref_modes *L) {
+    free(L->q_ext); free(L->q_a); free(L->q_b); free(L->q_c);
+    free(L->k_ext); free(L->k_a); free(L->k_b);
+    memset(L, 0, sizeof *L);
+}
+
+static int ref_modes_alloc(ref_modes *L, int64_t nq, int64_t nk) {
+    memset(L, 0, sizeof *L);
+    L->nq = nq;
+    L->nk = nk;
+    size_t qb = sizeof(int64_t) * (size_t)(nq + 1), kb = sizeof(int64_t) * (size_t)(nk + 1);
+    L->q_ext = calloc(1, qb); L->q_a = calloc(1, qb); L->q_b = calloc(1, qb); L->q_c = calloc(1, qb);
+    L->k_ext = calloc(1, kb); L->k_a = calloc(1, kb); L->k_b = calloc(1, kb);
+    if (!L->q_ext || !L->q_a || !L->q_b || !L->q_c || !L->k_ext || !L->k_a || !L->k_b) {
+        ref_modes_free(L);
+        return 0;
+    }
+    return 1;
+}
+
+/* Binary call (Section 6 preprocessing): free index p (A's free modes in
+   ascending order, then B's, then Hadamard pairs in list order) becomes
+   output mode PERM[p]; contracted pair k becomes summed mode k.  Arguments
+   must have passed the checks. */
+static int ref_modes_binary(ref_modes *L, int64_t ranka, const int64_t *exta, const int64_t *inca,
+                            int64_t rankb, const int64_t *extb, const int64_t *incb,
+                            int64_t conts, const int64_t *conta, const int64_t *contb,
+                            int64_t hads, const int64_t *hada, const int64_t *hadb,
+                            const int64_t *perm, const int64_t *incc) {
+    const int64_t nq = ranka + rankb - 2 * conts - hads;
+    if (!ref_modes_alloc(L, nq, conts)) return 0;
+    char *in_a = calloc((size_t)ranka + 1, 1), *in_b = calloc((size_t)rankb + 1, 1);
+    if (!in_a || !in_b) { free(in_a); free(in_b); ref_modes_free(L); return 0; }
+    for (int64_t k = 0; k < conts; ++k) { in_a[conta[k]] = 1; in_b[contb[k]] = 1; }
+    for (int64_t h = 0; h < hads; ++h) { in_a[hada[h]] = 1; in_b[hadb[h]] = 1; }
     int64_t p = 0;
-    for (int t = 0; t < 2; ++t) {
-        int64_t rank = t == 0 ? ranka : rankb;
-        const int64_t *ext = t == 0 ? exta : extb;
-        const int64_t *inc = t == 0 ? inca : incb;
-        const int64_t *cont = t == 0 ? conta : contb;
-        for (int64_t i = 0; i < rank; ++i) {
-            int contracted = 0;
-            for (int64_t k = 0; k < conts; ++k) if (cont[k] == i) contracted = 1;
-            if (contracted) continue;
-            int64_t q = perm[p++];
-            P->ExtFreeInd[q] = ext[i];
-            P->IncFreeInd[q] = inc[i];
-            P->TenFreeInd[q] = t;
-        }
+    for (int64_t i = 0; i < ranka; ++i) {
+        if (in_a[i]) continue;
+        const int64_t q = perm[p++];
+        L->q_ext[q] = exta[i]; L->q_a[q] = inca[i]; L->q_b[q] = 0;
     }
-    for (int64_t q = 0; q < P->NumFreeInd; ++q) P->IncC[q] = incc[q];
+    for (int64_t j = 0; j < rankb; ++j) {
+        if (in_b[j]) continue;
+        const int64_t q = perm[p++];
+        L->q_ext[q] = extb[j]; L->q_a[q] = 0; L->q_b[q] = incb[j];
+    }
+    for (int64_t h = 0; h < hads; ++h) {
+        const int64_t q = perm[p++];
+        L->q_ext[q] = exta[hada[h]]; L->q_a[q] = inca[hada[h]]; L->q_b[q] = incb[hadb[h]];
+    }
+    for (int64_t q = 0; q < nq; ++q) L->q_c[q] = incc[q];
     for (int64_t k = 0; k < conts; ++k) {
-        P->ExtContInd[k] = exta[conta[k]];
-        P->IncContA[k] = inca[conta[k]];
-        P->IncContB[k] = incb[contb[k]];
+        L->k_ext[k] = exta[conta[k]];
+        L->k_a[k] = inca[conta[k]];
+        L->k_b[k] = incb[contb[k]];
     }
-    P->SizeFreeInd = 1;
-    for (int64_t q = 0; q < P->NumFreeInd; ++q) P->SizeFreeInd *= P->ExtFreeInd[q];
-    P->SizeContInd = 1;
-    for (int64_t k = 0; k < conts; ++k) P->SizeContInd *= P->ExtContInd[k];
+    L->outputs = 1;
+    for (int64_t q = 0; q < nq; ++q) L->outputs *= L->q_ext[q];
+    free(in_a);
+    free(in_b);
+    return 1;
 }
 
-/* Algorithm 2 (Increment Coordinates): mixed-radix odometer, first index
-   fastest; it returns at once when there are no indices. */
-static void IncCoords(int64_t NumOfInd, int64_t *Coords, const int64_t *Exts) {
-    if (NumOfInd <= 0) return;
-    int64_t i = 0;
-    do {
-        Coords[i] = (Coords[i] + 1) % Exts[i];
-        i = i + 1;
-    } while (Coords[i - 1] == 0 && i < NumOfInd);
-}
+/* ------------------------------------------------------------------------- */
+/* One output.                                                                */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    int kind;
+    const void *A, *B;     /* B == NULL: unary, every product is a * 1 */
+    double re, im, mag;    /* running sum (real part, imaginary part), sum |a||b| */
+} ref_acc;
 
-/* Coordinates of linear output position s in the free odometer's order (used
-   only to start a chunk of the outer loop; the loop itself uses IncCoords). */
-static void decode_coords(int64_t s, int64_t n, const int64_t *ext, int64_t *coord) {
-    for (int64_t i = 0; i < n; ++i) {
-        coord[i] = s % ext[i];
-        s /= ext[i];
-    }
-}
-
-/* Element loaders: the oracle computes in double whatever the storage type. */
-typedef double (*ref_load_t)(const void *base, int64_t idx);
-static double ld_f64(const void *b, int64_t i) { return ((const double *)b)[i]; }
-static double ld_f32(const void *b, int64_t i) { return (double)((const float *)b)[i]; }
-
-/* Algorithm 1 over output positions [s0, s1).  For each output element the
-   contracted odometer walks every contracted coordinate; acc starts from the
-   current C value and takes one product and one sum per term.  The absolute
-   sum |C_in| + sum |a||b| is formed beside it when cabs != NULL. */
-static void ref_alg1_range(const ref_prep_t *P, int64_t s0, int64_t s1,
-                           const void *A, ref_load_t ldA, const void *B, ref_load_t ldB,
-                           const void *Cin, ref_load_t ldC,
-                           double *Cout, double *Cabs) {
-    int64_t CoordFreeInd[2 * REF_MAXRANK];
-    int64_t CoordContInd[REF_MAXRANK];
-    decode_coords(s0, P->NumFreeInd, P->ExtFreeInd, CoordFreeInd);
-    for (int64_t k = 0; k < P->NumContInd; ++k) CoordContInd[k] = 0;
-    for (int64_t i = s0; i < s1; ++i) {
-        int64_t IdxC = 0, FreeIdxA = 0, FreeIdxB = 0;
-        for (int64_t j = 0; j < P->NumFreeInd; ++j) {
-            IdxC += P->IncC[j] * CoordFreeInd[j];
-            if (P->TenFreeInd[j] == 0)
-                FreeIdxA += P->IncFreeInd[j] * CoordFreeInd[j];
-            else
-                FreeIdxB += P->IncFreeInd[j] * CoordFreeInd[j];
-        }
-        double c0 = ldC(Cin, IdxC);
-        double acc = c0;
-        double abs_acc = fabs(c0);
-        for (int64_t j = 0; j < P->SizeContInd; ++j) {
-            int64_t IdxA = FreeIdxA, IdxB = FreeIdxB;
-            for (int64_t k = 0; k < P->NumContInd; ++k) {
-                IdxA += P->IncContA[k] * CoordContInd[k];
-                IdxB += P->IncContB[k] * CoordContInd[k];
-            }
-            double a = ldA(A, IdxA), b = ldB(B, IdxB);
-            double prod = a * b;
-            acc = acc + prod;
-            if (Cabs) abs_acc = abs_acc + fabs(a) * fabs(b);
-            IncCoords(P->NumContInd, CoordContInd, P->ExtContInd);
-        }
-        Cout[IdxC] = acc;
-        if (Cabs) Cabs[IdxC] = abs_acc;
-        IncCoords(P->NumFreeInd, CoordFreeInd, P->ExtFreeInd);
+static inline void ref_load(int kind, const void *X, int64_t i, double *re, double *im) {
+    switch (kind) {
+    case REF_F64: *re = ((const double *)X)[i]; *im = 0.0; break;
+    case REF_F32: *re = (double)((const float *)X)[i]; *im = 0.0; break;
+    case REF_Z128: *re = ((const double *)X)[2 * i]; *im = ((const double *)X)[2 * i + 1]; break;
+    default: *re = (double)((const float *)X)[2 * i]; *im = (double)((const float *)X)[2 * i + 1];
     }
 }
 
-/* Outer loop of Algorithm 1 split over threads in contiguous chunks, at most
-   [first, last) of the output positions (last < 0 means all of them). */
-static void ref_alg1(const ref_prep_t *P, int64_t first, int64_t last,
-                     const void *A, ref_load_t ldA, const void *B, ref_load_t ldB,
-                     const void *Cin, ref_load_t ldC, double *Cout, double *Cabs) {
-    int64_t n = P->SizeFreeInd;
-    if (last < 0 || last > n) last = n;
+static inline int ref_is_complex(int kind) { return kind == REF_Z128 || kind == REF_C64; }
+
+/* One term of the sum: the product of A at offset oa and B at offset ob. */
+static inline void ref_term(ref_acc *s, int64_t oa, int64_t ob) {
+    double ar, ai, br = 1.0, bi = 0.0;
+    ref_load(s->kind, s->A, oa, &ar, &ai);
+    if (s->B) ref_load(s->kind, s->B, ob, &br, &bi);
+    if (ref_is_complex(s->kind)) {
+        const double pr = ar * br - ai * bi;
+        const double pi = ar * bi + ai * br;
+        s->re = s->re + pr;
+        s->im = s->im + pi;
+        s->mag = s->mag + (fabs(ar) + fabs(ai)) * (fabs(br) + fabs(bi));
+    } else {
+        s->re = s->re + ar * br;
+        s->mag = s->mag + fabs(ar) * fabs(br);
+    }
+}
+
+/* Every coordinate combination of summed modes 0..level: a loop over mode
+   `level` around the walk of the modes below it, so mode 0 is innermost and
+   changes fastest. */
+static void ref_walk(const ref_modes *L, int64_t level, int64_t oa, int64_t ob, ref_acc *s) {
+    if (level < 0) {
+        ref_term(s, oa, ob);
+        return;
+    }
+    const int64_t e = L->k_ext[level], da = L->k_a[level], db = L->k_b[level];
+    if (level == 0) {
+        for (int64_t i = 0; i < e; ++i) ref_term(s, oa + i * da, ob + i * db);
+        return;
+    }
+    for (int64_t i = 0; i < e; ++i) ref_walk(L, level - 1, oa + i * da, ob + i * db, s);
+}
+
+/* Offsets in A, B and C of output position s (first output mode fastest). */
+static void ref_place(const ref_modes *L, int64_t s, int64_t *oa, int64_t *ob, int64_t *oc) {
+    int64_t a = 0, b = 0, c = 0, rest = s;
+    for (int64_t q = 0; q < L->nq; ++q) {
+        const int64_t x = rest % L->q_ext[q];
+        rest /= L->q_ext[q];
+        a += x * L->q_a[q];
+        b += x * L->q_b[q];
+        c += x * L->q_c[q];
+    }
+    *oa = a;
+    *ob = b;
+    *oc = c;
+}
+
+/* How the result combines with C_in. */
+typedef struct {
+    int scaled;                  /* 0: C_in + sum (Algorithm 1); 1: alpha sum + beta C_in */
+    double alr, ali, ber, bei;   /* alpha and beta (imaginary parts 0 for real data) */
+} ref_mix;
+
+/* Value (re, im) and bound of output position s.  Cin may be NULL only for a
+   scaled call with beta == 0 (C_in is not read then, as in BLAS). */
+static void ref_output(const ref_modes *L, int kind, const void *A, const void *B, const void *Cin,
+                       const ref_mix *mx, int64_t s, int64_t *oc_out, double *vre, double *vim,
+                       double *vmag) {
+    int64_t oa, ob, oc;
+    ref_place(L, s, &oa, &ob, &oc);
+    *oc_out = oc;
+    double cr = 0.0, ci = 0.0;
+    const int read_c = !mx->scaled || mx->ber != 0.0 || mx->bei != 0.0;
+    if (read_c) ref_load(kind, Cin, oc, &cr, &ci);
+    ref_acc acc = {kind, A, B, 0.0, 0.0, 0.0};
+    if (!mx->scaled) {
+        acc.re = cr;
+        acc.im = ci;
+        acc.mag = fabs(cr) + fabs(ci);
+    }
+    ref_walk(L, L->nk - 1, oa, ob, &acc);
+    if (!mx->scaled) {
+        *vre = acc.re;
+        *vim = acc.im;
+        *vmag = acc.mag;
+        return;
+    }
+    /* alpha * sum + beta * C_in, complex products written out */
+    const double sr = mx->alr * acc.re - mx->ali * acc.im;
+    const double si = mx->alr * acc.im + mx->ali * acc.re;
+    const double tr = mx->ber * cr - mx->bei * ci;
+    const double ti = mx->ber * ci + mx->bei * cr;
+    *vre = sr + tr;
+    *vim = si + ti;
+    *vmag = (fabs(mx->alr) + fabs(mx->ali)) * acc.mag +
+            (fabs(mx->ber) + fabs(mx->bei)) * (fabs(cr) + fabs(ci));
+}
+
+/* Outputs [first, last) (last < 0: all), written to Cout and Cbound at C's
+   own element offsets (Cout: one double per real element, two per complex
+   one; Cbound: one double per element; either may be NULL). */
+static void ref_range(const ref_modes *L, int kind, const void *A, const void *B, const void *Cin,
+                      const ref_mix *mx, int64_t first, int64_t last, double *Cout,
+                      double *Cbound) {
+    if (last < 0 || last > L->outputs) last = L->outputs;
     if (first < 0) first = 0;
-    if (first >= last) return;
-    int64_t total = last - first;
-    int64_t chunk = 256;
-    int64_t nchunks = (total + chunk - 1) / chunk;
-#pragma omp parallel for schedule(dynamic, 1)
-    for (int64_t c = 0; c < nchunks; ++c) {
-        int64_t s0 = first + c * chunk;
-        int64_t s1 = s0 + chunk < last ? s0 + chunk : last;
-        ref_alg1_range(P, s0, s1, A, ldA, B, ldB, Cin, ldC, Cout, Cabs);
+    const int cx = ref_is_complex(kind);
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t s = first; s < last; ++s) {
+        int64_t oc;
+        double vr, vi, vm;
+        ref_output(L, kind, A, B, Cin, mx, s, &oc, &vr, &vi, &vm);
+        if (Cout) {
+            if (cx) { Cout[2 * oc] = vr; Cout[2 * oc + 1] = vi; }
+            else Cout[oc] = vr;
+        }
+        if (Cbound) Cbound[oc] = vm;
     }
 }
+
+/* Listed output positions: val[i] (two doubles per complex value) and
+   bound[i] for position pos[i]; positions outside [0, outputs) give NaN. */
+static void ref_points(const ref_modes *L, int kind, const void *A, const void *B,
+                       const void *Cin, const ref_mix *mx, int64_t n, const int64_t *pos,
+                       double *val, double *bound) {
+    const int cx = ref_is_complex(kind);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; ++i) {
+        double vr = NAN, vi = NAN, vm = NAN;
+        if (pos[i] >= 0 && pos[i] < L->outputs) {
+            int64_t oc;
+            ref_output(L, kind, A, B, Cin, mx, pos[i], &oc, &vr, &vi, &vm);
+        }
+        if (cx) { val[2 * i] = vr; val[2 * i + 1] = vi; }
+        else val[i] = vr;
+        bound[i] = vm;
+    }
+}
+
+static const ref_mix REF_PLAIN = {0, 1.0, 0.0, 1.0, 0.0};
 
 /* ------------------------------------------------------------------------- */
 /* Public oracle entry points (host pointers; each addresses coordinate 0).   */
 /* ------------------------------------------------------------------------- */
 
-/* FP64 xGETT: C <- C + contraction, in place (Algorithm 1). */
+/* The paper's call on any element kind: C_in + sum into Cout/Cbound for the
+   outputs [first, last). */
+int gett_ref_exact(int kind, int64_t ranka, const int64_t *exta, const int64_t *inca,
+                   const void *A, int64_t rankb, const int64_t *extb, const int64_t *incb,
+                   const void *B, int64_t conts, const int64_t *conta, const int64_t *contb,
+                   const int64_t *perm, const int64_t *incc, const void *Cin, double *Cout,
+                   double *Cbound, int64_t first, int64_t last) {
+    if (kind < REF_F64 || kind > REF_C64) return -100;
+    int info = gett_ref_check(ranka, exta, inca, A, rankb, extb, incb, B, conts, conta, contb,
+                              perm, incc, Cin);
+    if (info) return info;
+    ref_modes L;
+    if (!ref_modes_binary(&L, ranka, exta, inca, rankb, extb, incb, conts, conta, contb, 0, NULL,
+                          NULL, perm, incc))
+        return -101;
+    ref_range(&L, kind, A, B, Cin, &REF_PLAIN, first, last, Cout, Cbound);
+    ref_modes_free(&L);
+    return 0;
+}
+
+/* The same for a list of output positions (first output mode fastest). */
+int gett_ref_exact_at(int kind, int64_t ranka, const int64_t *exta, const int64_t *inca,
+                      const void *A, int64_t rankb, const int64_t *extb, const int64_t *incb,
+                      const void *B, int64_t conts, const int64_t *conta, const int64_t *contb,
+                      const int64_t *perm, const int64_t *incc, const void *Cin, int64_t n,
+                      const int64_t *pos, double *val, double *bound) {
+    if (kind < REF_F64 || kind > REF_C64) return -100;
+    int info = gett_ref_check(ranka, exta, inca, A, rankb, extb, incb, B, conts, conta, contb,
+                              perm, incc, Cin);
+    if (info) return info;
+    ref_modes L;
+    if (!ref_modes_binary(&L, ranka, exta, inca, rankb, extb, incb, conts, conta, contb, 0, NULL,
+                          NULL, perm, incc))
+        return -101;
+    ref_points(&L, kind, A, B, Cin, &REF_PLAIN, n, pos, val, bound);
+    ref_modes_free(&L);
+    return 0;
+}
+
+/* Scaled call with Hadamard pairs: C <- alpha * sum + beta * C_in, where the
+   output modes are A's free modes, B's free modes, then the HADS pairs
+   (HADA[h] of A with HADB[h] of B, equal extents), placed by PERM.  alpha and
+   beta point to (re, im) pairs (im ignored for real kinds).  Either Cout or
+   val/pos is used: with n < 0 the outputs [first, last) go to Cout/Cbound,
+   otherwise the n listed positions go to val/bound. */
+int gett_ref_exact_ex(int kind, const double *alpha, int64_t ranka, const int64_t *exta,
+                      const int64_t *inca, const void *A, int64_t rankb, const int64_t *extb,
+                      const int64_t *incb, const void *B, int64_t conts, const int64_t *conta,
+                      const int64_t *contb, int64_t hads, const int64_t *hada,
+                      const int64_t *hadb, const int64_t *perm, const int64_t *incc,
+                      const double *beta, const void *Cin, double *Cout, double *Cbound,
+                      int64_t first, int64_t last, int64_t n, const int64_t *pos, double *val,
+                      double *bound) {
+    if (kind < REF_F64 || kind > REF_C64 || !alpha || !beta) return -100;
+    ref_mix mx = {1, alpha[0], ref_is_complex(kind) ? alpha[1] : 0.0, beta[0],
+                  ref_is_complex(kind) ? beta[1] : 0.0};
+    const int need_c = mx.ber != 0.0 || mx.bei != 0.0;
+    int info = ref_check_binary(ranka, exta, inca, A, rankb, extb, incb, B, conts, conta, contb,
+                                hads, hada, hadb, perm, incc, need_c ? Cin : (const void *)1);
+    if (info) return info;
+    ref_modes L;
+    if (!ref_modes_binary(&L, ranka, exta, inca, rankb, extb, incb, conts, conta, contb, hads,
+                          hada, hadb, perm, incc))
+        return -101;
+    if (n < 0) ref_range(&L, kind, A, B, Cin, &mx, first, last, Cout, Cbound);
+    else ref_points(&L, kind, A, B, Cin, &mx, n, pos, val, bound);
+    ref_modes_free(&L);
+    return 0;
+}
+
+/* Unary operation on A (Section 9: transpose, reduction, trace):
+   C <- alpha * sum + beta * C_in.  Output modes: A's modes that are neither
+   summed nor in a trace pair, in ascending order, placed by PERM.  Summed:
+   the NSUM modes SUMA (in list order), then the NTR trace pairs (TRA[t] with
+   TRB[t], equal extents; one coordinate walks both).  Transpose is NSUM =
+   NTR = 0.  INFO: -1..-4 as for A, -5 NSUM/NTR, -6 SUMA, -7 TRA/TRB, -8 PERM,
+   -9 INCC, -10 C.  Output like gett_ref_exact_ex. */
+int gett_ref_unary(int kind, const double *alpha, int64_t ranka, const int64_t *exta,
+                   const int64_t *inca, const void *A, int64_t nsum, const int64_t *suma,
+                   int64_t ntr, const int64_t *tra, const int64_t *trb, const int64_t *perm,
+                   const int64_t *incc, const double *beta, const void *Cin, double *Cout,
+                   double *Cbound, int64_t first, int64_t last, int64_t n, const int64_t *pos,
+                   double *val, double *bound) {
+    if (kind < REF_F64 || kind > REF_C64 || !alpha || !beta) return -100;
+    ref_mix mx = {1, alpha[0], ref_is_complex(kind) ? alpha[1] : 0.0, beta[0],
+                  ref_is_complex(kind) ? beta[1] : 0.0};
+    int64_t na = 0;
+    if (ranka < 0) return -1;
+    if (ranka > 0 && exta == NULL) return -2;
+    for (int64_t i = 0; i < ranka; ++i) if (exta[i] < 0) return -2;
+    if (ranka > 0 && inca == NULL) return -3;
+    if (ranka > 0 && !ref_span_ok(ranka, exta, inca)) return -3;
+    if (!ref_count_ok(ranka, exta, &na)) return -2;
+    if (na > 0 && A == NULL) return -4;
+    if (nsum < 0 || ntr < 0 || nsum + 2 * ntr > ranka) return -5;
+    const int64_t nq = ranka - nsum - 2 * ntr;
+    char *used = calloc((size_t)ranka + 1, 1);
+    char *seen = calloc((size_t)nq + 1, 1);
+    int64_t *extc = malloc(sizeof(int64_t) * (size_t)(nq + 1));
+    ref_modes L;
+    memset(&L, 0, sizeof L);
+    int info = 0;
+    if (!used || !seen || !extc) { info = -101; goto out; }
+    if (nsum > 0 && suma == NULL) { info = -6; goto out; }
+    if (!ref_mark_modes(nsum, suma, ranka, used)) { info = -6; goto out; }
+    if (ntr > 0 && (tra == NULL || trb == NULL)) { info = -7; goto out; }
+    if (!ref_mark_modes(ntr, tra, ranka, used) || !ref_mark_modes(ntr, trb, ranka, used)) {
+        info = -7;
+        goto out;
+    }
+    for (int64_t t = 0; t < ntr; ++t)
+        if (exta[tra[t]] != exta[trb[t]]) { info = -7; goto out; }
+    if (nq > 0 && perm == NULL) { info = -8; goto out; }
+    for (int64_t p = 0; p < nq; ++p) {
+        if (perm[p] < 0 || perm[p] >= nq || seen[perm[p]]) { info = -8; goto out; }
+        seen[perm[p]] = 1;
+    }
+    {
+        int64_t p = 0;
+        for (int64_t i = 0; i < ranka; ++i) if (!used[i]) extc[perm[p++]] = exta[i];
+    }
+    if (nq > 0 && incc == NULL) { info = -9; goto out; }
+    for (int64_t q = 0; q < nq; ++q)
+        if (incc[q] == 0 && extc[q] > 1) { info = -9; goto out; }
+    if (nq > 0 && !ref_span_ok(nq, extc, incc)) { info = -9; goto out; }
+    {
+        int64_t nc = 0;
+        if (!ref_count_ok(nq, extc, &nc)) { info = -9; goto out; }
+        const int need_c = mx.ber != 0.0 || mx.bei != 0.0;
+        if (nc > 0 && need_c && Cin == NULL) { info = -10; goto out; }
+    }
+    if (!ref_modes_alloc(&L, nq, nsum + ntr)) { info = -101; goto out; }
+    {
+        int64_t p = 0;
+        for (int64_t i = 0; i < ranka; ++i) {
+            if (used[i]) continue;
+            const int64_t q = perm[p++];
+            L.q_ext[q] = exta[i]; L.q_a[q] = inca[i]; L.q_b[q] = 0; L.q_c[q] = incc[q];
+        }
+        for (int64_t k = 0; k < nsum; ++k) {
+            L.k_ext[k] = exta[suma[k]]; L.k_a[k] = inca[suma[k]]; L.k_b[k] = 0;
+        }
+        for (int64_t t = 0; t < ntr; ++t) {
+            L.k_ext[nsum + t] = exta[tra[t]];
+            L.k_a[nsum + t] = inca[tra[t]] + inca[trb[t]];
+            L.k_b[nsum + t] = 0;
+        }
+        L.outputs = 1;
+        for (int64_t q = 0; q < nq; ++q) L.outputs *= L.q_ext[q];
+    }
+    if (n < 0) ref_range(&L, kind, A, NULL, Cin, &mx, first, last, Cout, Cbound);
+    else ref_points(&L, kind, A, NULL, Cin, &mx, n, pos, val, bound);
+out:
+    ref_modes_free(&L);
+    free(used);
+    free(seen);
+    free(extc);
+    return info;
+}
+
+/* FP64 xGETT in place: C <- C + sum A*B (Algorithm 1's update). */
 int gett_ref_dgett(int64_t ranka, const int64_t *exta, const int64_t *inca, const double *A,
                    int64_t rankb, const int64_t *extb, const int64_t *incb, const double *B,
                    int64_t conts, const int64_t *conta, const int64_t *contb,
                    const int64_t *perm, const int64_t *incc, double *C) {
-    int info = gett_ref_check(ranka, exta, inca, A, rankb, extb, incb, B, conts, conta, contb,
-                              perm, incc, C);
-    if (info) return info;
-    ref_prep_t P;
-    ref_prepare(ranka, exta, inca, rankb, extb, incb, conts, conta, contb, perm, incc, &P);
-    ref_alg1(&P, 0, -1, A, ld_f64, B, ld_f64, C, ld_f64, C, NULL);
-    return 0;
+    return gett_ref_exact(REF_F64, ranka, exta, inca, A, rankb, extb, incb, B, conts, conta,
+                          contb, perm, incc, C, C, NULL, 0, -1);
 }
 
-/* Exact-in-double contraction of FP32 data: Cout <- Cin + sum a*b and
-   Cabs <- |Cin| + sum |a||b|, both in double with the INCC layout (Cout and
-   Cabs are double arrays indexed like C).  Only output positions
-   [first, last) of the free odometer are formed (last < 0: all of them), so a
-   bounded sample of a large contraction can be timed. */
+/* Complex FP64 xGETT in place (interleaved re, im pairs). */
+int gett_ref_zgett(int64_t ranka, const int64_t *exta, const int64_t *inca, const double *A,
+                   int64_t rankb, const int64_t *extb, const int64_t *incb, const double *B,
+                   int64_t conts, const int64_t *conta, const int64_t *contb,
+                   const int64_t *perm, const int64_t *incc, double *C) {
+    return gett_ref_exact(REF_Z128, ranka, exta, inca, A, rankb, extb, incb, B, conts, conta,
+                          contb, perm, incc, C, C, NULL, 0, -1);
+}
+
+/* FP32 data, out of place in double: Cout <- Cin + sum a*b and
+   Cabs <- |Cin| + sum |a||b| for the outputs [first, last). */
 int gett_ref_sgett_f64(int64_t ranka, const int64_t *exta, const int64_t *inca, const float *A,
                        int64_t rankb, const int64_t *extb, const int64_t *incb, const float *B,
                        int64_t conts, const int64_t *conta, const int64_t *contb,
                        const int64_t *perm, const int64_t *incc, const float *Cin,
                        double *Cout, double *Cabs, int64_t first, int64_t last) {
-    int info = gett_ref_check(ranka, exta, inca, A, rankb, extb, incb, B, conts, conta, contb,
-                              perm, incc, Cin);
-    if (info) return info;
-    ref_prep_t P;
-    ref_prepare(ranka, exta, inca, rankb, extb, incb, conts, conta, contb, perm, incc, &P);
-    ref_alg1(&P, first, last, A, ld_f32, B, ld_f32, Cin, ld_f32, Cout, Cabs);
-    return 0;
+    return gett_ref_exact(REF_F32, ranka, exta, inca, A, rankb, extb, incb, B, conts, conta,
+                          contb, perm, incc, Cin, Cout, Cabs, first, last);
 }
 
-/* Same as gett_ref_dgett but out of place with the absolute sum beside it and
-   an output range, for bounded samples and component-wise error bounds. */
+/* FP64 data, out of place with the bound beside it. */
 int gett_ref_dgett_range(int64_t ranka, const int64_t *exta, const int64_t *inca, const double *A,
                          int64_t rankb, const int64_t *extb, const int64_t *incb, const double *B,
                          int64_t conts, const int64_t *conta, const int64_t *contb,
                          const int64_t *perm, const int64_t *incc, const double *Cin,
                          double *Cout, double *Cabs, int64_t first, int64_t last) {
-    int info = gett_ref_check(ranka, exta, inca, A, rankb, extb, incb, B, conts, conta, contb,
-                              perm, incc, Cin);
-    if (info) return info;
-    ref_prep_t P;
-    ref_prepare(ranka, exta, inca, rankb, extb, incb, conts, conta, contb, perm, incc, &P);
-    ref_alg1(&P, first, last, A, ld_f64, B, ld_f64, Cin, ld_f64, Cout, Cabs);
-    return 0;
+    return gett_ref_exact(REF_F64, ranka, exta, inca, A, rankb, extb, incb, B, conts, conta,
+                          contb, perm, incc, Cin, Cout, Cabs, first, last);
 }
 
-/* Offsets (element units, relative to each pointer) of output position s of
-   the free odometer in C, and of the matching free parts of A and B; used by
-   tests that sample single outputs of large contractions. */
+/* Element offsets in C of output positions s[0..n) (first output mode
+   fastest); used by tests that place single outputs of large contractions. */
 int gett_ref_output_offsets(int64_t ranka, const int64_t *exta, const int64_t *inca,
                             int64_t rankb, const int64_t *extb, const int64_t *incb,
                             int64_t conts, const int64_t *conta, const int64_t *contb,
                             const int64_t *perm, const int64_t *incc,
                             int64_t n, const int64_t *s, int64_t *offc) {
-    ref_prep_t P;
-    ref_prepare(ranka, exta, inca, rankb, extb, incb, conts, conta, contb, perm, incc, &P);
-    int64_t coord[2 * REF_MAXRANK];
+    ref_modes L;
+    if (!ref_modes_binary(&L, ranka, exta, inca, rankb, extb, incb, conts, conta, contb, 0, NULL,
+                          NULL, perm, incc))
+        return -101;
     for (int64_t i = 0; i < n; ++i) {
-        decode_coords(s[i], P.NumFreeInd, P.ExtFreeInd, coord);
-        int64_t o = 0;
-        for (int64_t j = 0; j < P.NumFreeInd; ++j) o += P.IncC[j] * coord[j];
-        offc[i] = o;
+        int64_t oa, ob;
+        ref_place(&L, s[i], &oa, &ob, &offc[i]);
     }
+    ref_modes_free(&L);
     return 0;
 }
 
@@ -374,6 +662,16 @@ int gett_ref_num_threads(void) {
     return omp_get_max_threads();
 #else
     return 1;
+#endif
+}
+
+/* Thread count of the loop over outputs (tests check that it does not
+   change any result). */
+void gett_ref_set_num_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
 #endif
 }
 
@@ -399,9 +697,7 @@ static double ref_bf16_rne(float x) {
 }
 
 /* BF16x3 model: x = hi + lo + rest with hi = bf16(x), lo = bf16(x - hi);
-   the product a*b is taken as hi_a*hi_b + hi_a*lo_b + lo_a*hi_b.  Each split
-   part and each product is exact in double, so this returns the value the
-   split method aims at with all accumulation done exactly enough (in double). */
+   the product a*b is taken as hi_a*hi_b + hi_a*lo_b + lo_a*hi_b. */
 void gett_ref_bf16_split(int64_t n, const float *x, float *hi, float *lo) {
     for (int64_t i = 0; i < n; ++i) {
         double h = ref_bf16_rne(x[i]);
@@ -509,14 +805,4 @@ void gett_ref_fp8_gemm(int64_t M, int64_t N, int64_t K, const uint8_t *QA, const
             out[m + M * n] = acc;
         }
     }
-}
-
-/* Thread count of the oracle's outer loop (tests check that it does not
-   change any result). */
-void gett_ref_set_num_threads(int n) {
-#ifdef _OPENMP
-    if (n > 0) omp_set_num_threads(n);
-#else
-    (void)n;
-#endif
 }

@@ -133,10 +133,15 @@ def make_view(ext, rng, dtype=np.float64, layout="packed", dist="uniform",
         base += sum((e - 1) * s for e, s in zip(ext, inc) if e > 0)
         inc = [-s for s in inc]
     v = View(buf, int(base), ext, inc)
+    cplx = np.issubdtype(np.dtype(dtype), np.complexfloating)
     if values is None:
         values = _draw(rng, n, dist)
+        if cplx:     # real parts, then imaginary parts, from the same stream
+            values = values + 1j * _draw(rng, n, dist)
     if n > 0:
-        buf[v.element_index()] = np.asarray(values, dtype=np.float64).astype(dtype)
+        vals = np.asarray(values)
+        vals = vals.astype(np.complex128 if cplx else np.float64)
+        buf[v.element_index()] = vals.astype(dtype)
     return v
 
 

@@ -62,6 +62,8 @@ BAD = [(-1, dict(ranka=-1)), (-1, dict(ranka=65)), (-2, dict(exta=[3, -1])),
 @pytest.mark.parametrize("fn", ["dgett", "sgett", "sgett_bf16x3", "sgett_fp8"])
 def test_info_codes(fn, code, kw):
     assert call(getattr(gett, fn), **kw) == code
+    if kw.get("ranka", 0) > 64:
+        return   # the library's documented rank limit; the oracle has none
     # the oracle's independent checks agree
     d = dict(OK)
     d.update(kw)

@@ -15,7 +15,8 @@ import pytest
 
 import oracle
 from paper_2410_06770_amd import workloads as W
-from tests.helpers import brute_force, einsum_ref, e_nrm, outside_mask, view_values
+from tests.helpers import (brute_force, brute_force_abs, brute_force_unary, einsum_ref,
+                           e_nrm, outside_mask, view_values)
 
 
 def run_oracle(pr):
@@ -424,28 +425,314 @@ def test_bf16_split_matches_torch_and_bounds():
     assert np.all(oracle.bf16_split(th)[1] == 0)
 
 
+# ------------------------------------------- the bound |C_in| + sum |a||b|
+BOUND_CASES = ["basic", "nothing", "scalar", "rank0", "subtensor", "negative", "subneg",
+               "lowerrank", "cube_2", "hypercube_3"]
+
+
+@pytest.mark.parametrize("case", BOUND_CASES)
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_bound_matches_brute_force(case, dtype):
+    """The second output of the oracle, |C_in| + sum |a||b|, against the same
+    sum over every pair of index tuples; bitwise on integers (every partial sum
+    is an integer), within a few ulps of the summed terms otherwise (all terms
+    are non-negative, so only the order of the additions differs).  The values
+    themselves, for FP32 as for FP64 data, against the brute force too."""
+    rng = np.random.default_rng(zlib.crc32(case.encode()) + (7 if dtype == np.float32 else 3))
+    for rep in range(3):
+        for dist in ("int", "uniform"):
+            pr = W.paper_case(case, rng, dtype=dtype, dist=dist)
+            if np.prod(pr.exta) * np.prod(pr.extb) > 200000:
+                continue
+            idx = pr.C.element_index()
+            pr.C.buf[idx] = W._draw(rng, idx.size, "int").astype(dtype)
+            val, bnd = oracle.exact(pr, pr.A, pr.B, pr.C)
+            ref_v = brute_force(pr)
+            ref_b = brute_force_abs(pr)
+            got_v, got_b = view_values(pr.C, val), view_values(pr.C, bnd)
+            if dist == "int":
+                assert np.array_equal(got_v, ref_v), (case, rep)
+                assert np.array_equal(got_b, ref_b), (case, rep)
+            else:
+                K = pr.mnk()[2]
+                assert np.all(np.abs(got_b - ref_b) <= (K + 2) * 2.0 ** -52 * ref_b)
+                assert np.all(np.abs(got_v - ref_v) <= (K + 2) * 2.0 ** -52 * ref_b)
+
+
+def test_exact_at_equals_exact():
+    """The list-of-positions entry forms exactly the values of the range entry."""
+    rng = np.random.default_rng(41)
+    for dtype in (np.float64, np.float32, np.complex128):
+        for _ in range(6):
+            sig = W.random_signature(rng, (1, 4), (1, 4), (1, 5), (0, 3))
+            pr = W.build_problem(rng, sig, dtype, "sub", "neg", "sub")
+            full, fb = oracle.exact(pr, pr.A, pr.B, pr.C)
+            total = int(np.prod(pr.extc()))
+            pos = rng.integers(0, total, 50)
+            off = oracle.output_offsets(pr, pos) + pr.C.base
+            val, bnd = oracle.exact_at(pr, pr.A, pr.B, pr.C, pos)
+            assert np.array_equal(val, full[off]) and np.array_equal(bnd, fb[off])
+            # out-of-range positions give NaN
+            v2, b2 = oracle.exact_at(pr, pr.A, pr.B, pr.C, [-1, total])
+            assert np.all(np.isnan(b2))
+
+
+def test_rank_70_of_mostly_extent_one_modes():
+    """The paper allows arbitrary ranks: A and B of rank 70 (68 extent-1 modes
+    scattered among two real ones each) give the contraction of the squeezed
+    operands."""
+    rng = np.random.default_rng(70)
+    ra = rb = 70
+    exta, extb = [1] * ra, [1] * rb
+    exta[3], exta[61] = 5, 7          # A[.., i, .., k, ..]
+    extb[10], extb[69] = 7, 4         # B[.., k, .., j]
+    A = W.make_view(exta, rng, np.float64, dist="int")
+    B = W.make_view(extb, rng, np.float64, dist="int")
+    # contract A's mode 61 with B's mode 10 and 20 extent-1 pairs besides
+    conta = [61] + list(range(20, 40))
+    contb = [10] + list(range(30, 50))
+    rc = ra + rb - 2 * len(conta)
+    perm = rng.permutation(rc).tolist()
+    pr = W.Problem(ra, exta, A.inc, rb, extb, B.inc, len(conta), conta, contb, perm, [])
+    C = W.make_c(pr.extc(), rng, np.float64)
+    pr.incc = C.inc
+    pr = pr.with_views(A, B, C)
+    val = oracle.exact(pr, A, B, C)[0]
+    flat = val[C.element_index()]        # column-major over C's 98 modes, 96 of extent 1
+    a2 = A.buf[A.element_index()].reshape(5, 7, order="F")
+    b2 = B.buf[B.element_index()].reshape(7, 4, order="F")
+    ref = a2 @ b2                      # [i, j]
+    # output positions of A's mode 3 (i) and B's mode 69 (j)
+    fa, fb = pr.free_modes()
+    qi = perm[fa.index(3)]
+    qj = perm[len(fa) + fb.index(69)]
+    got = flat.reshape(5, 4, order="F") if qi < qj else flat.reshape(4, 5, order="F").T
+    assert np.array_equal(got, ref)
+    assert oracle.check(*pr.args()) == 0
+
+
+# ------------------------------------------------------------------- complex
+@pytest.mark.parametrize("seed", range(10))
+def test_complex_matches_brute_force(seed):
+    """Complex contraction (the c and z prefixes): the oracle's value and
+    bound against the definition with complex products; bitwise on Gaussian
+    integers."""
+    rng = np.random.default_rng(500 + seed)
+    sig = W.random_signature(rng, (0, 3), (0, 3), (1, 3), (0, 3))
+    for dtype in (np.complex128, np.complex64):
+        for dist in ("int", "uniform"):
+            pr = W.build_problem(rng, sig, dtype, "sub", "neg", "sub", dist=dist)
+            idx = pr.C.element_index()
+            pr.C.buf[idx] = (W._draw(rng, idx.size, "int") + 1j * W._draw(rng, idx.size, "int"))
+            val, bnd = oracle.exact(pr, pr.A, pr.B, pr.C)
+            ref = brute_force(pr)
+            refb = brute_force_abs(pr)
+            got, gotb = view_values(pr.C, val), view_values(pr.C, bnd)
+            if dist == "int":
+                assert np.array_equal(got, ref) and np.array_equal(gotb, refb)
+            else:
+                assert e_nrm(got, ref) <= 1e-15
+                assert np.allclose(gotb, refb, rtol=1e-14, atol=0)
+
+
+def test_complex_is_four_real_contractions():
+    """Re C = Re A Re B - Im A Im B and Im C = Re A Im B + Im A Re B, each a
+    real contraction of the same signature (integers: exact)."""
+    rng = np.random.default_rng(61)
+    for _ in range(8):
+        sig = W.random_signature(rng, (1, 4), (1, 4), (1, 4), (0, 3))
+        pr = W.build_problem(rng, sig, np.complex128, "sub", "packed", "packed", dist="int")
+        z = np.zeros_like(pr.C.buf)
+        pr = pr.with_views(pr.A, pr.B, W.View(z, pr.C.base, pr.C.ext, pr.C.inc))
+        zc = pr.C.copy()
+        assert oracle.zgett(pr, pr.A, pr.B, zc) == 0
+        part = {}
+        for a_name, fa in (("r", np.real), ("i", np.imag)):
+            for b_name, fb in (("r", np.real), ("i", np.imag)):
+                Ar = W.View(np.ascontiguousarray(fa(pr.A.buf)), pr.A.base, pr.A.ext, pr.A.inc)
+                Br = W.View(np.ascontiguousarray(fb(pr.B.buf)), pr.B.base, pr.B.ext, pr.B.inc)
+                Cr = W.View(np.zeros(pr.C.buf.shape), pr.C.base, pr.C.ext, pr.C.inc)
+                assert oracle.dgett(pr, Ar, Br, Cr) == 0
+                part[a_name + b_name] = view_values(Cr)
+        got = view_values(zc)
+        assert np.array_equal(got.real, part["rr"] - part["ii"])
+        assert np.array_equal(got.imag, part["ri"] + part["ir"])
+
+
+def test_complex_vs_einsum():
+    rng = np.random.default_rng(62)
+    for case in ("basic", "subtensor", "negative", "hypercube_2"):
+        pr = W.paper_case(case, rng, dtype=np.complex128)
+        C = pr.C.copy()
+        assert oracle.zgett(pr, pr.A, pr.B, C) == 0
+        assert e_nrm(view_values(C), einsum_ref(pr)) <= 1e-14
+
+
+# ------------------------------------------------ scaling and Hadamard modes
+def _hadamard_problem(rng, dtype, hads, dist="int"):
+    """A random contraction with ``hads`` Hadamard pairs; PERM and C cover
+    A's free modes, B's free modes, then the pairs."""
+    while True:
+        sig = W.random_signature(rng, (1, 4), (1, 4), (1, 4), (0, 3))
+        ra, exta, rb, extb, cs, conta, contb, _ = sig
+        fa = [i for i in range(ra) if i not in conta]
+        fb = [j for j in range(rb) if j not in contb]
+        if len(fa) >= hads and len(fb) >= hads:
+            break
+    hada = [int(x) for x in rng.choice(fa, size=hads, replace=False)]
+    hadb = [int(x) for x in rng.choice(fb, size=hads, replace=False)]
+    for a, b in zip(hada, hadb):
+        extb[b] = exta[a]
+    A = W.make_view(exta, rng, dtype, "sub", dist=dist)
+    B = W.make_view(extb, rng, dtype, "neg", dist=dist)
+    rc = ra + rb - 2 * cs - hads
+    perm = rng.permutation(rc).tolist()
+    free = [exta[i] for i in fa if i not in hada] + [extb[j] for j in fb if j not in hadb] + \
+        [exta[i] for i in hada]
+    extc = [0] * rc
+    for p, q in enumerate(perm):
+        extc[q] = free[p]
+    C = W.make_view(extc, rng, dtype, "sub", dist=dist, fill=W.SENTINEL)
+    pr = W.Problem(ra, exta, A.inc, rb, extb, B.inc, cs, conta, contb, perm, C.inc, A, B, C)
+    return pr, hada, hadb
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_scaled_and_hadamard_match_brute_force(seed):
+    rng = np.random.default_rng(800 + seed)
+    for dtype in (np.float64, np.complex128):
+        hads = int(rng.integers(0, 3))
+        pr, hada, hadb = _hadamard_problem(rng, dtype, hads)
+        cx = dtype == np.complex128
+        alpha = complex(int(rng.integers(-3, 4)), int(rng.integers(-3, 4)) if cx else 0)
+        beta = complex(int(rng.integers(-3, 4)), int(rng.integers(-3, 4)) if cx else 0)
+        if not cx:
+            alpha, beta = alpha.real, beta.real
+        val, bnd = oracle.exact_ex(pr, pr.A, pr.B, pr.C, alpha, beta, hada, hadb)
+        ref = brute_force(pr, alpha, beta, hada, hadb)
+        refb = brute_force_abs(pr, alpha, beta, hada, hadb)
+        assert np.array_equal(view_values(pr.C, val), ref)
+        assert np.array_equal(view_values(pr.C, bnd), refb)
+        total = int(np.prod(pr.C.ext))
+        pos = rng.integers(0, max(total, 1), 20) if total else np.zeros(0, dtype=np.int64)
+        v2, b2 = oracle.exact_ex(pr, pr.A, pr.B, pr.C, alpha, beta, hada, hadb, positions=pos)
+        assert np.array_equal(v2, ref.reshape(-1, order="F")[pos])
+        assert np.array_equal(b2, refb.reshape(-1, order="F")[pos])
+
+
+def test_hadamard_vs_einsum():
+    """A Hadamard mode is an index shared by A, B and C: numpy.einsum with the
+    same letter in all three operands."""
+    rng = np.random.default_rng(90)
+    A = W.make_view([4, 5, 6], rng)          # A[i, k, h]
+    B = W.make_view([6, 5, 3], rng)          # B[h, k, j]
+    pr = W.Problem(3, [4, 5, 6], A.inc, 3, [6, 5, 3], B.inc, 1, [1], [1], [2, 0, 1], [])
+    C = W.make_c([3, 6, 4], rng, np.float64)  # C[j, h, i]: free i -> 2, j -> 0, pair h -> 1
+    pr.incc = C.inc
+    pr = pr.with_views(A, B, C)
+    val, _ = oracle.exact_ex(pr, A, B, C, 2.0, 0.0, [2], [0])
+    ref = 2.0 * np.einsum("ikh,hkj->jhi", A.gather(), B.gather())
+    assert e_nrm(view_values(C, val), ref) <= 1e-15
+
+
+def test_beta_zero_does_not_read_c():
+    """With beta = 0 C_in is not read (BLAS convention): NaN there is ignored."""
+    rng = np.random.default_rng(91)
+    pr = W.paper_case("basic", rng)
+    pr.C.buf[pr.C.element_index()] = np.nan
+    val, _ = oracle.exact_ex(pr, pr.A, pr.B, pr.C, 1.5, 0.0)
+    ref = 1.5 * np.einsum(__import__("tests.helpers", fromlist=["x"]).einsum_subscripts(pr),
+                          pr.A.gather(), pr.B.gather())
+    assert e_nrm(view_values(pr.C, val), ref) <= 1e-15
+
+
+# ---------------------------------------------------------- unary operations
+def _unary_case(rng, dtype, nsum, ntr, dist="int"):
+    r = nsum + 2 * ntr + int(rng.integers(0, 3))
+    ext = [int(rng.integers(1, 5)) for _ in range(r)]
+    modes = rng.permutation(r).tolist()
+    suma = modes[:nsum]
+    tra = modes[nsum:nsum + ntr]
+    trb = modes[nsum + ntr:nsum + 2 * ntr]
+    for x, y in zip(tra, trb):
+        ext[y] = ext[x]
+    A = W.make_view(ext, rng, dtype, "sub", dist=dist)
+    rest = [i for i in range(r) if i not in suma + tra + trb]
+    perm = rng.permutation(len(rest)).tolist()
+    extc = [0] * len(rest)
+    for p, q in enumerate(perm):
+        extc[q] = ext[rest[p]]
+    C = W.make_view(extc, rng, dtype, "sub", dist=dist, fill=W.SENTINEL)
+    return A, suma, tra, trb, perm, C
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_unary_matches_brute_force(seed):
+    """Transpose (nothing summed), reduction (summed modes) and trace (pairs
+    walked together), alone and combined, with alpha and beta."""
+    rng = np.random.default_rng(1200 + seed)
+    for dtype in (np.float64, np.complex128):
+        nsum, ntr = [(0, 0), (1, 0), (2, 0), (0, 1), (1, 1), (0, 2)][seed % 6]
+        A, suma, tra, trb, perm, C = _unary_case(rng, dtype, nsum, ntr)
+        alpha, beta = float(rng.integers(-3, 4)), float(rng.integers(-3, 4))
+        val, bnd = oracle.unary(A, suma, tra, trb, perm, C.inc, C, alpha, beta)
+        rv, rb = brute_force_unary(A, suma, tra, trb, perm, C.ext, C.gather(), alpha, beta)
+        assert np.array_equal(view_values(C, val), rv)
+        assert np.array_equal(view_values(C, bnd), rb)
+
+
+def test_unary_special_cases_vs_numpy():
+    rng = np.random.default_rng(77)
+    A = W.make_view([3, 4, 5], rng)
+    a = A.gather()
+    # transpose: C[k, i, j] = A[i, j, k]
+    C = W.make_c([5, 3, 4], rng, np.float64)
+    val, _ = oracle.unary(A, [], [], [], [1, 2, 0], C.inc, C, 1.0, 0.0)
+    assert np.array_equal(view_values(C, val), np.transpose(a, (2, 0, 1)))
+    # reduction over j: C[i, k] = sum_j A[i, j, k]
+    C = W.make_c([3, 5], rng, np.float64)
+    val, _ = oracle.unary(A, [1], [], [], [0, 1], C.inc, C, 1.0, 0.0)
+    assert e_nrm(view_values(C, val), a.sum(axis=1)) <= 1e-15
+    # trace of a square slice: C[j] = sum_i A2[i, j, i]
+    A2 = W.make_view([4, 3, 4], rng)
+    C = W.make_c([3], rng, np.float64)
+    val, _ = oracle.unary(A2, [], [0], [2], [0], C.inc, C, 1.0, 0.0)
+    assert e_nrm(view_values(C, val), np.trace(A2.gather(), axis1=0, axis2=2)) <= 1e-15
+
+
 # ----------------------------------------------- planted mistakes are caught
 MUTANTS = {
     # contracted increments of B replaced by those of A
-    "wrong_increment": ("P->IncContB[k] = incb[contb[k]];", "P->IncContB[k] = inca[conta[k]];"),
+    "wrong_increment": ("L->k_b[k] = incb[contb[k]];", "L->k_b[k] = inca[conta[k]];"),
     # PERM read as a gather (entry q names the free index placed at q)
-    "perm_gather": ("int64_t q = perm[p++];", "int64_t q = p++;"),
-    # Algorithm 1's odometer calls taken literally (extent arrays swapped)
-    "literal_extents": ("IncCoords(P->NumContInd, CoordContInd, P->ExtContInd);",
-                        "IncCoords(P->NumContInd, CoordContInd, P->ExtFreeInd);"),
+    "perm_gather": ("const int64_t q = perm[p++];", "const int64_t q = p++;"),
+    # every summed mode wrapping at the first one's extent
+    "walk_extent": ("const int64_t e = L->k_ext[level], da", "const int64_t e = L->k_ext[0], da"),
+    # output coordinates not divided down (every mode reads s mod its extent)
+    "decode": ("        rest /= L->q_ext[q];\n", ""),
     # product sign dropped
-    "sign": ("double prod = a * b;", "double prod = -(a * b);"),
+    "sign": ("s->re = s->re + ar * br;", "s->re = s->re - ar * br;"),
     # overwrite instead of accumulate
-    "overwrite": ("double acc = c0;", "double acc = 0.0;"),
+    "overwrite": ("        acc.re = cr;\n", "        acc.re = 0.0;\n"),
+    # the bound without |C_in|
+    "bound_no_cin": ("acc.mag = fabs(cr) + fabs(ci);", "acc.mag = 0.0;"),
+    # the bound with a quarter of each term
+    "bound_quarter": ("s->mag = s->mag + fabs(ar) * fabs(br);",
+                      "s->mag = s->mag + fabs(ar) * fabs(br) / 4;"),
+    # the bound taken as |sum a b| instead of sum |a||b|
+    "bound_of_sum": ("*vmag = acc.mag;", "*vmag = fabs(acc.re);"),
+    # complex product with the wrong sign on Im A Im B
+    "complex_sign": ("const double pr = ar * br - ai * bi;", "const double pr = ar * br + ai * bi;"),
 }
 
 
 @pytest.mark.parametrize("mutant", sorted(MUTANTS))
 def test_pins_catch_planted_mistakes(mutant, tmp_path):
-    """A copy of the oracle with one planted mistake fails the pins."""
+    """A copy of the oracle with one planted mistake fails the pins: values
+    and bounds of real and complex contractions against the brute force."""
     src = open(os.path.join(os.path.dirname(oracle.__file__), "gett_oracle.c")).read()
     old, new = MUTANTS[mutant]
-    assert old in src
+    assert src.count(old) >= 1, mutant
     mdir = tmp_path / "oracle"
     mdir.mkdir()
     (mdir / "gett_oracle.c").write_text(src.replace(old, new))
@@ -456,16 +743,19 @@ sys.path.insert(0, {str(tmp_path)!r}); sys.path.insert(1, {os.path.dirname(os.pa
 import oracle
 assert oracle.__file__.startswith({str(tmp_path)!r})
 from paper_2410_06770_amd import workloads as W
-from tests.helpers import brute_force, einsum_ref, view_values
+from tests.helpers import brute_force, brute_force_abs, view_values
 rng = np.random.default_rng(3)
 fails = 0
 for i in range(30):
     sig = W.random_signature(rng, (1, 3), (1, 3), (2, 3), (0, 2))
-    pr = W.build_problem(rng, sig, dist="int")
-    pr.C.buf[pr.C.element_index()] = 1.0
-    C = pr.C.copy(); oracle.dgett(pr, pr.A, pr.B, C)
-    if not np.array_equal(view_values(C), brute_force(pr)):
-        fails += 1
+    for dtype in (np.float64, np.complex128):
+        pr = W.build_problem(rng, sig, dtype, dist="int")
+        pr.C.buf[pr.C.element_index()] = 1.0 - 2.0j if dtype == np.complex128 else 1.0
+        val, bnd = oracle.exact(pr, pr.A, pr.B, pr.C)
+        if not np.array_equal(view_values(pr.C, val), brute_force(pr)):
+            fails += 1
+        if not np.array_equal(view_values(pr.C, bnd), brute_force_abs(pr)):
+            fails += 1
 print("FAILS", fails)
 """
     out = subprocess.run(["python", "-c", script], capture_output=True, text=True, timeout=300)
