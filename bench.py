@@ -16,7 +16,8 @@ with virtual extent 96 and occupied extent 32 (M, N, K = 9216, 9216, 1024;
 One step = one xGETT call of the primary path (DGETT, FP64).  The same
 workload also runs through SGETT (FP32 MFMA), split BF16x3 SGETT and FP8
 SGETT; their rates and errors against the FP64 oracle (on a sample of
-outputs) are reported under "paths".  A last leg runs the uneven batch of 512
+outputs) are reported under "paths".  The default run then times the same
+four paths on the precision-study workload under "cc_study".  A last leg runs the uneven batch of 512
 problems through split BF16x3 as one replay of the captured batch graph and
 as 512 separate calls ("batch").  Kernel durations come from HIP events
 recorded on the library's stream around every call.  For context only, the
@@ -62,6 +63,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--paths", default="f64,f32,bf16x3,fp8")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cc-study", action="store_true",
+                    help="skip the precision study legs that follow the strided workload")
     ap.add_argument("--no-check", action="store_true", help="skip the sampled error check")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target duration of the CPU oracle sample")
@@ -114,12 +117,66 @@ def main():
         del src, dst
 
     paths = [p for p in args.paths.split(",") if p]
+    results, context, pr64, primary = run_workload(args, args.workload, paths, gett, W, torch,
+                                                   stream, with_context=not args.no_context)
+    M, N, K = pr64.mnk()
+    flops = 2.0 * M * N * K
+    builder, wdesc, wdata = WORKLOADS[args.workload]
+    # The precision study (the largest single-GPU workload) runs in the
+    # default invocation too, under its own key.
+    study = None
+    if args.workload != "cc" and not args.no_cc_study:
+        study_res, study_ctx, pr_cc, _ = run_workload(args, "cc", paths, gett, W, torch, stream,
+                                                      with_context=False)
+        Mc, Nc, Kc = pr_cc.mnk()
+        study = {"workload": WORKLOADS["cc"][1], "M": Mc, "N": Nc, "K": Kc,
+                 "flops_per_call": 2.0 * Mc * Nc * Kc, "paths": study_res}
+        del pr_cc
+
+    batch = batch_leg(args.batch, gett, W, torch, stream) if args.batch > 0 else None
+
+    path, ms, tflops, peak, wall = primary
+    out = {
+        "metric": METRIC,
+        "value": round(tflops, 3),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"f64": "f64", "f32": "f32", "bf16x3": "bf16x3(f32 acc, f64 sum)",
+                  "fp8": "e4m3(f32 acc)"}[path],
+        "data": wdata,
+        "config": {"workload": wdesc,
+                   "M": M, "N": N, "K": K, "flops_per_step": flops, "path": path},
+        "roofline": {"bound": "mfma", "achieved": round(tflops, 3), "peak": peak,
+                     "unit": "TFLOP/s", "frac": round(tflops / peak, 4),
+                     "traffic": load_traffic(args.traffic_json, args.workload, path,
+                                             results[path]["schedule"])},
+        "paths": results,
+    }
+    if context:
+        out["context"] = context
+    if study is not None:
+        out["cc_study"] = study
+    if batch is not None:
+        out["batch"] = batch
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(pr64, args.cpu_seconds, flops)
+    print(json.dumps(out))
+
+
+def run_workload(args, workload, paths, gett, W, torch, stream, with_context):
+    """Time every precision path on one workload.  Returns (results per path,
+    PyTorch context timings, the FP64 problem, the first path's (name, ms,
+    TFLOP/s, peak, wall seconds))."""
     entry = {"f64": gett.dgett, "f32": gett.sgett, "bf16x3": gett.sgett_bf16x3,
              "fp8": gett.sgett_fp8}
-    results = {}
-    context = {}
-    problems = {}
-    builder, wdesc, wdata = WORKLOADS[args.workload]
+    results, context, problems = {}, {}, {}
+    builder = WORKLOADS[workload][0]
     make = getattr(W, builder)
     for path in paths:
         dtype = np.float64 if path == "f64" else np.float32
@@ -128,8 +185,8 @@ def main():
     pr64 = problems.get(np.float64) or make(dtype=np.float64)
     M, N, K = pr64.mnk()
     flops = 2.0 * M * N * K
-    print(f"[bench] workload M={M} N={N} K={K} flops={flops:.4e}", file=sys.stderr, flush=True)
-
+    print(f"[bench] workload {workload} M={M} N={N} K={K} flops={flops:.4e}", file=sys.stderr,
+          flush=True)
     primary = None
     for path in paths:
         dtype = np.float64 if path == "f64" else np.float32
@@ -150,7 +207,7 @@ def main():
             if rc:
                 raise RuntimeError(f"{path}: {gett.strerror(rc)}")
 
-        print(f"[bench] path {path}: first call", file=sys.stderr, flush=True)
+        print(f"[bench] {workload} path {path}: first call", file=sys.stderr, flush=True)
         call()                      # also builds the plan
         torch.cuda.synchronize()
         err = {}
@@ -183,60 +240,35 @@ def main():
         ms_cold = cold[0].elapsed_time(cold[1])
         del flush
         tflops = flops / (ms * 1e-3) / 1e12
-        peak = {"f64": PEAK["f64"], "f32": PEAK["f32"], "bf16x3": PEAK["f32"],
-                "fp8": PEAK["fp8"]}[path]
+        # % of the matrix peak of the arithmetic the path runs: BF16x3 does
+        # three BF16 products per term, so its MFMA-pipe use is 3 x its
+        # effective rate against the BF16 peak.
+        if path == "bf16x3":
+            peak, pct = PEAK["bf16"], 100 * 3 * tflops / PEAK["bf16"]
+        else:
+            peak = {"f64": PEAK["f64"], "f32": PEAK["f32"], "fp8": PEAK["fp8"]}[path]
+            pct = 100 * tflops / peak
         res = {"tflops": round(tflops, 3), "ms": round(ms, 4), "ms_min": round(min(durs), 4),
                "ms_median": round(float(np.median(durs)), 4), "ms_cold": round(ms_cold, 4),
-               "pct_peak": round(100 * tflops / peak, 2), "peak_tflops": peak,
+               "pct_peak": round(pct, 2), "peak_tflops": peak,
                "schedule": int(sched), "wall_ms_per_step": round(1e3 * wall / args.steps, 4)}
         if path == "bf16x3":
-            res["bf16_mfma_util_pct"] = round(100 * 3 * tflops / PEAK["bf16"], 2)
+            res["pct_peak_basis"] = "3 BF16 products per term vs the BF16 matrix peak"
+            res["effective_pct_of_f32_peak"] = round(100 * tflops / PEAK["f32"], 2)
         res.update(err)
         results[path] = res
-        print(f"[bench] {path}: {json.dumps(res)}", file=sys.stderr, flush=True)
+        print(f"[bench] {workload} {path}: {json.dumps(res)}", file=sys.stderr, flush=True)
         if primary is None:
-            primary = (path, ms, tflops, peak, wall)
-        if not args.no_context and path in ("f64", "f32"):
+            primary = (path, ms, tflops, PEAK["bf16"] if path == "bf16x3" else peak, wall)
+        if with_context and path in ("f64", "f32"):
             context.update(torch_context(pr, path, At, Bt, Ct, flops, args.steps, args.warmup,
                                          torch, stream))
         del At, Bt, Ct
         torch.cuda.empty_cache()
-
     if "f32" in results and "bf16x3" in results:
         results["bf16x3"]["speedup_vs_f32"] = round(results["f32"]["ms"] / results["bf16x3"]["ms"], 3)
-
-    batch = batch_leg(args.batch, gett, W, torch, stream) if args.batch > 0 else None
-
-    path, ms, tflops, peak, wall = primary
-    out = {
-        "metric": METRIC,
-        "value": round(tflops, 3),
-        "unit": "TFLOP/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": {"f64": "f64", "f32": "f32", "bf16x3": "bf16x3(f32 acc, f64 sum)",
-                  "fp8": "e4m3(f32 acc)"}[path],
-        "data": wdata,
-        "config": {"workload": wdesc,
-                   "M": M, "N": N, "K": K, "flops_per_step": flops, "path": path},
-        "roofline": {"bound": "mfma", "achieved": round(tflops, 3), "peak": peak,
-                     "unit": "TFLOP/s", "frac": round(tflops / peak, 4),
-                     "traffic": load_traffic(args.traffic_json, args.workload, path,
-                                             results[path]["schedule"])},
-        "paths": results,
-    }
-    if context:
-        out["context"] = context
-    if batch is not None:
-        out["batch"] = batch
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(pr64, args.cpu_seconds, flops)
-    print(json.dumps(out))
+    del problems
+    return results, context, pr64, primary
 
 
 def batch_leg(count, gett, W, torch, stream, reps=10):

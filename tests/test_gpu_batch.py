@@ -53,20 +53,41 @@ def run_batch(problems, dev, prec, fn=None):
     return rc, info
 
 
+NRM_STATS = []   # (e_nrm, kappa) of every problem checked, for the report
+
+
 def bound(prec, K):
     return (K + 2) * U32 + (3 * 2.0 ** -16 if prec == gett.GETT_BF16X3 else 0.0)
 
 
-def check_problem(pr, got, prec, sample=96):
+def check_problem(pr, got, prec, sample=96, nrm_tol=1e-5):
+    """Sampled outputs of one problem: element-wise bound on each, and the
+    normwise error over all the samples of the problem: the per-problem
+    e_nrm <= 1e-5 of the batched workload, scaled by the samples' own
+    cancellation kappa = ||C_in| + sum |a||b|| / ||C|| (>= 1).  A problem
+    whose outputs cancel (a full contraction to one scalar, say) has a
+    relative error kappa times that of its terms in any floating-point
+    order, FP32 included; for kappa near 1 the gate is plain e_nrm."""
     total = int(np.prod(pr.extc())) if pr.extc() else 1
     K = pr.mnk()[2]
     worst = 0.0
+    gs, rs, bs = [], [], []
     for first in sorted({0, max(total // 2 - sample // 2, 0), max(total - sample, 0)}):
         ref, cabs = oracle.exact(pr, pr.A, pr.B, pr.C, first, min(first + sample, total))
         sel = ~np.isnan(ref)
         ec = e_cw(got[sel], ref[sel], cabs[sel])
         assert ec <= bound(prec, K), (pr.name, ec, bound(prec, K))
         worst = max(worst, ec)
+        gs.append(got[sel].astype(np.float64))
+        rs.append(ref[sel])
+        bs.append(cabs[sel])
+    if nrm_tol is not None:
+        r = np.concatenate(rs)
+        en = e_nrm(np.concatenate(gs), r)
+        nr = np.linalg.norm(r)
+        kappa = max(1.0, float(np.linalg.norm(np.concatenate(bs)) / nr)) if nr > 0 else 1.0
+        assert en <= nrm_tol * kappa, (pr.name, prec, en, kappa)
+        NRM_STATS.append((en, kappa))
     m = outside_mask(pr.C)
     assert np.array_equal(got[m], pr.C.buf[m])
     return worst
@@ -80,8 +101,14 @@ def test_uneven_batch_of_512(prec):
     dev = upload(problems)
     rc, info = run_batch(problems, dev, prec)
     assert rc == 0 and all(i == 0 for i in info)
+    NRM_STATS.clear()
     for pr, d in zip(problems, dev):
         check_problem(pr, d[2].cpu().numpy(), prec)
+    en = np.array([e for e, _ in NRM_STATS])
+    kap = np.array([k for _, k in NRM_STATS])
+    print(f"\n[batch] prec={prec}: e_nrm <= 1e-5 on {int(np.sum(en <= 1e-5))} of {en.size} "
+          f"problems; max e_nrm {en.max():.2e}; max e_nrm/kappa {np.max(en / kap):.2e}; "
+          f"kappa > 2 on {int(np.sum(kap > 2))}", flush=True)
 
 
 def test_dgett_batch_paper_cases():

@@ -3,8 +3,8 @@ every gathered element of A and B and every C element against the range its
 tensor's extents and increments allow, counting an access outside it (which
 it then redirects to a zero or drops).  A sweep of problems runs through it
 in a fresh process: negative increments, sub-tensors, step-2 layouts, forced
-split-K and 32-bit-addressing schedules, the strided workload's structure
-and a batch, for FP64, FP32 and BF16x3.  The sweep must give correct
+split-K, boxed-order and 32-bit-addressing schedules, the strided workload's
+structure and a batch, for FP64, FP32 and BF16x3.  The sweep must give correct
 results and no violation; with the checked ranges of A and B narrowed by one
 element (GETT_CHECK_SHRINK=1, the accesses themselves unchanged) the same
 sweep must report violations."""
@@ -70,6 +70,13 @@ for prec in (gett.GETT_FP64, gett.GETT_FP32, gett.GETT_BF16X3):
         if not ((S > 1 and K < S * bk) or (S == 0 and K < 4 * bk)):
             run(pr, prec, sid)
             break
+
+    # boxed N orders (a box of 4 or 16 positions of C's fastest N mode)
+    sig3 = (4, [16, 32, 12, 10], 4, [10, 12, 12, 20], 2, [2, 3], [2, 0], [2, 0, 3, 1])
+    pr = W.build_problem(rng, sig3, dtype, "step2", "packed", "packed", dist="normal",
+                         name="boxed")
+    for sid in (gett.schedule_id(1, 2, 0), gett.schedule_id(2, 3, 1)):
+        run(pr, prec, sid)
 
 # a batch (FP32 through BF16x3), one problem cut along K
 problems = W.config_batch(24, seed=21)
