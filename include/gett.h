@@ -51,7 +51,9 @@
  *   >0   runtime error: GETT_ERR_HIP (HIP runtime failure), GETT_ERR_ALLOC
  *        (device allocation failed), GETT_ERR_DEVICE (current device is not
  *        gfx950), GETT_ERR_INTERNAL (planner limit, e.g. a group's offset
- *        table would exceed 2^31 entries), GETT_ERR_STATE (bad control call).
+ *        table would exceed 2^31 entries), GETT_ERR_STATE (bad control call),
+ *        GETT_ERR_SCRATCH (dgett_noalloc only: problem too large for its
+ *        scratch array).
  *        gett_strerror() names every code.
  *
  * Aliasing: A and B may overlap each other and themselves (they are only
@@ -104,6 +106,7 @@ extern "C" {
 #define GETT_ERR_DEVICE   3
 #define GETT_ERR_INTERNAL 4
 #define GETT_ERR_STATE    5
+#define GETT_ERR_SCRATCH  6   /* problem too large for dgett_noalloc's scratch */
 
 /* ---------------------------------------------------------------------- */
 /* xGETT entry points (Section 5.7 argument list; semantics above).         */
@@ -190,6 +193,27 @@ int dgett_batch(int64_t count, int64_t prec,
                 const int64_t *conts, const int64_t *const *conta, const int64_t *const *contb,
                 const int64_t *const *perm, const int64_t *const *incc, double *const *C,
                 int64_t *info);
+
+/* DGETT that allocates nothing, for callers that cannot allocate device
+   memory (code under HIP graph capture, tight serving loops, harnesses that
+   forbid hipMalloc).  Same 14 arguments, semantics and INFO codes as dgett,
+   and the same tile and split-K kernels.  Its offset tables and split-K
+   partial sums live in a device array of GETT_NOALLOC_SCRATCH_BYTES that the
+   library holds on each GPU it runs on until the process ends; the tables are
+   written into it by a kernel on the caller's stream on every call (no plan
+   cache, no host-to-device copy).  The schedule is the one forced with
+   gett_set_schedule, else the built-in heuristic (the PREDICT and AUTOTUNE
+   policies are not used here).  Returns GETT_ERR_SCRATCH, before any HIP
+   call, when the six offset tables (2 * (Mp + Np + Kp) int64 entries, each
+   group's length padded as in dgett) exceed the array; a split-K schedule
+   whose FP64 partials do not fit beside the tables runs unsplit.  Every call
+   on one GPU shares that GPU's array: calls that overlap on one GPU (other
+   streams or threads) race; calls queued on one stream are ordered. */
+#define GETT_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int dgett_noalloc(int64_t ranka, const int64_t *exta, const int64_t *inca, const double *A,
+                  int64_t rankb, const int64_t *extb, const int64_t *incb, const double *B,
+                  int64_t conts, const int64_t *conta, const int64_t *contb,
+                  const int64_t *perm, const int64_t *incc, double *C);
 
 /* ---------------------------------------------------------------------- */
 /* Control plane (not part of xGETT's argument list).                       */

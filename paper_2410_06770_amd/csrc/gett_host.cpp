@@ -17,6 +17,7 @@
 
 #include "gett.h"
 #include "gett_internal.h"
+#include "gett_noalloc.h"
 #include "gett_plan.h"
 
 namespace gett {
@@ -967,6 +968,95 @@ static int run(int prec, const Args &a, const void *A, const void *B, void *C) {
 }
 
 // ---------------------------------------------------------------------------
+// Allocation-free DGETT: tables and split-K partials in the device scratch
+// array (gett_noalloc.hip); no plan cache, no allocation of any kind on the
+// device.
+// ---------------------------------------------------------------------------
+static void fill_group(const std::vector<GMode> &g, int idx, int64_t size, int64_t pad,
+                       FillGroups &f) {
+    f.nmodes[idx] = (int32_t)g.size();
+    for (size_t j = 0; j < g.size(); ++j) f.modes[idx][j] = FillMode{g[j].ext, g[j].i0, g[j].i1};
+    f.size[idx] = size;
+    f.pad[idx] = pad;
+}
+
+static int run_noalloc(const Args &a, const double *A, const double *B, double *C) {
+    int info = validate(a, A, B, C);
+    if (info) return info;
+    Canon probe = canonicalise(a, 0, 128);
+    if (probe.empty || probe.M == 0 || probe.N == 0 || probe.K == 0) return 0;
+    const int64_t forced = g_forced.load();
+    Sched s = forced >= 0 ? sched_of(forced) : heuristic(kF64, probe.M, probe.N, probe.K);
+    if (!sched_valid(kF64, s, probe.K)) return GETT_ERR_STATE;
+    const TileShape ts = kTiles[kF64][s.tile];
+    // The plan, built on the stack: canonical form, padded table lengths and
+    // address ranges as in a cached plan, tables in the scratch array.
+    TableSet t;
+    t.cn = canonicalise(a, s.order, ts.bn);
+    const Canon &c = t.cn;
+    if (c.M > INT32_MAX || c.N > INT32_MAX) return GETT_ERR_INTERNAL;
+    if ((int)c.m.size() > kFillModes || (int)c.n.size() > kFillModes ||
+        (int)c.k.size() > kFillModes)
+        return GETT_ERR_SCRATCH;
+    t.Mp = round_up(std::max<int64_t>(c.M, 1), kTablePad);
+    t.Np = round_up(std::max<int64_t>(c.N, 1), kTablePad);
+    t.Kp = round_up(std::max<int64_t>(c.K, 1), 128) + 256;
+    const int64_t tab_bytes = round_up(2 * (t.Mp + t.Np + t.Kp) * (int64_t)sizeof(int64_t), 256);
+    if (tab_bytes > (int64_t)GETT_NOALLOC_SCRATCH_BYTES) return GETT_ERR_SCRATCH;
+    operand_ranges(c, t.aLo, t.aSpan, t.bLo, t.bSpan);
+    {
+        int64_t ml, mh, nl, nh;
+        group_range(c.m, 1, ml, mh);
+        group_range(c.n, 1, nl, nh);
+        t.cLo = ml + nl;
+        t.cSpan = (mh - ml) + (nh - nl);
+    }
+    const int64_t tiles = ((c.M + ts.bm - 1) / ts.bm) * ((c.N + ts.bn - 1) / ts.bn);
+    if (tiles * split_count(s.split, tiles, std::max<int64_t>(c.K, 1), ts.bk, nullptr) >
+        INT32_MAX)
+        return GETT_ERR_INTERNAL;
+    int dev = 0;
+    int rc = check_device(&dev);
+    if (rc) return rc;
+    void *scr = nullptr;
+    int64_t scr_bytes = 0;
+    rc = noalloc_scratch(dev, &scr, &scr_bytes);
+    if (rc) return rc;
+    hipStream_t st = t_stream;
+    FillGroups f{};
+    fill_group(c.m, 0, c.M, t.Mp, f);
+    fill_group(c.n, 1, c.N, t.Np, f);
+    fill_group(c.k, 2, c.K, t.Kp, f);
+    int64_t *tab = static_cast<int64_t *>(scr);
+    rc = launch_table_fill(f, tab, st);
+    if (rc) return rc;
+    t.d_tab = tab;
+    Plan pl;
+    pl.prec = kF64;
+    pl.sched = s;
+    pl.tab = &t;
+    TileParams p = make_params(pl, A, B, C);
+    t_last_schedule = sched_id(s);
+    if (p.splits > 1) {
+        const int64_t ws_bytes = (int64_t)p.splits * p.M * p.N * (int64_t)sizeof(double);
+        if (tab_bytes + ws_bytes <= scr_bytes) {
+            // every (slice, m, n) partial is written by its tile: no clearing
+            p.ws = reinterpret_cast<double *>(static_cast<char *>(scr) + tab_bytes);
+            rc = launch_tile(kF64, s.tile, c.aFastK, c.bFastK, p, st);
+            if (!rc) rc = launch_splitk_reduce(kF64, p, st);
+        } else {
+            p = make_params(pl, A, B, C, 0);
+            t_last_schedule = sched_id(Sched{s.tile, s.order, 0});
+            rc = launch_tile(kF64, s.tile, c.aFastK, c.bFastK, p, st);
+        }
+    } else {
+        rc = launch_tile(kF64, s.tile, c.aFastK, c.bFastK, p, st);
+    }
+    t.d_tab = nullptr;   // the scratch array is not the table set's to free
+    return rc;
+}
+
+// ---------------------------------------------------------------------------
 // Batches
 // ---------------------------------------------------------------------------
 struct BatchGraph {
@@ -1324,6 +1414,13 @@ int dgett_batch(int64_t count, int64_t prec, const int64_t *ranka, const int64_t
                        contb, perm, incc, reinterpret_cast<void *const *>(C), info);
 }
 
+int dgett_noalloc(int64_t ranka, const int64_t *exta, const int64_t *inca, const double *A,
+                  int64_t rankb, const int64_t *extb, const int64_t *incb, const double *B,
+                  int64_t conts, const int64_t *conta, const int64_t *contb, const int64_t *perm,
+                  const int64_t *incc, double *C) {
+    return run_noalloc(GETT_ARGS_MAKE, A, B, C);
+}
+
 int gett_set_stream(void *hip_stream) {
     t_stream = static_cast<hipStream_t>(hip_stream);
     return 0;
@@ -1502,6 +1599,8 @@ const char *gett_strerror(int code) {
     case GETT_ERR_DEVICE: return "device is not gfx950 (MI355X)";
     case GETT_ERR_INTERNAL: return "internal planner limit";
     case GETT_ERR_STATE: return "invalid control call or state";
+    case GETT_ERR_SCRATCH:
+        return "problem too large for the allocation-free entry's scratch array";
     default: return "unknown error";
     }
 }

@@ -23,6 +23,8 @@ GETT_FP64, GETT_FP32, GETT_BF16X3, GETT_FP8 = 0, 1, 2, 3
 GETT_HEURISTIC, GETT_PREDICT, GETT_AUTOTUNE = 0, 1, 2
 # positive runtime codes (negative codes are INFO = -i for argument i)
 GETT_ERR_HIP, GETT_ERR_ALLOC, GETT_ERR_DEVICE, GETT_ERR_INTERNAL, GETT_ERR_STATE = 1, 2, 3, 4, 5
+GETT_ERR_SCRATCH = 6
+NOALLOC_SCRATCH_BYTES = 64 << 20   # GETT_NOALLOC_SCRATCH_BYTES
 NUM_FEATURES = 64
 NUM_ORDERS = 4
 NUM_SPLITS = 4
@@ -59,7 +61,7 @@ def lib():
         pass
     L = ct.CDLL(LIB_PATH)
     a14 = [i64, I64P, I64P, vp, i64, I64P, I64P, vp, i64, I64P, I64P, I64P, I64P, vp]
-    for name in ("dgett", "sgett", "sgett_bf16x3", "sgett_fp8"):
+    for name in ("dgett", "sgett", "sgett_bf16x3", "sgett_fp8", "dgett_noalloc"):
         getattr(L, name).argtypes = a14
         getattr(L, name).restype = ct.c_int
     L.sgett_fp8_quantize.argtypes = [i64, I64P, I64P, vp, i64, I64P, vp, vp]
@@ -146,6 +148,12 @@ def sgett_bf16x3(ranka, exta, inca, A, rankb, extb, incb, B, conts, conta, contb
 def sgett_fp8(ranka, exta, inca, A, rankb, extb, incb, B, conts, conta, contb, perm, incc,
               C) -> int:
     return _call14("sgett_fp8", ranka, exta, inca, A, rankb, extb, incb, B, conts, conta,
+                   contb, perm, incc, C)
+
+
+def dgett_noalloc(ranka, exta, inca, A, rankb, extb, incb, B, conts, conta, contb, perm, incc,
+                  C) -> int:
+    return _call14("dgett_noalloc", ranka, exta, inca, A, rankb, extb, incb, B, conts, conta,
                    contb, perm, incc, C)
 
 

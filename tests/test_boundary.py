@@ -59,7 +59,7 @@ BAD = [(-1, dict(ranka=-1)), (-1, dict(ranka=65)), (-2, dict(exta=[3, -1])),
 
 
 @pytest.mark.parametrize("code,kw", BAD)
-@pytest.mark.parametrize("fn", ["dgett", "sgett", "sgett_bf16x3", "sgett_fp8"])
+@pytest.mark.parametrize("fn", ["dgett", "sgett", "sgett_bf16x3", "sgett_fp8", "dgett_noalloc"])
 def test_info_codes(fn, code, kw):
     assert call(getattr(gett, fn), **kw) == code
     if kw.get("ranka", 0) > 64:
@@ -161,3 +161,13 @@ def test_stream_setting_is_per_thread():
         assert gett.gett_get_stream() == fake
     finally:
         gett.gett_set_stream(0)
+
+
+def test_noalloc_rejects_oversized_tables_before_any_hip_call():
+    """dgett_noalloc's offset tables must fit its scratch array: an outer
+    product with 5e6 x 5 outputs (80 MB of tables) is refused with
+    GETT_ERR_SCRATCH before the library touches a device (none here)."""
+    rc = gett.dgett_noalloc(1, [5_000_000], [1], 8, 1, [5], [1], 8, 0, [], [], [0, 1],
+                            [1, 5_000_000], 8)
+    assert rc == gett.GETT_ERR_SCRATCH
+    assert "scratch" in gett.strerror(rc)
