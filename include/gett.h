@@ -79,11 +79,13 @@
 extern "C" {
 #endif
 
-/* Precision codes (batch calls, schedules, features). */
+/* Precision codes (batch calls, schedules, features, tile menus). */
 #define GETT_FP64   0
 #define GETT_FP32   1
 #define GETT_BF16X3 2
 #define GETT_FP8    3
+#define GETT_Z64    4   /* complex FP64 (zgett) */
+#define GETT_C32    5   /* complex FP32 (cgett) */
 
 /* Schedule policies (gett_set_policy).  Environment: GETT_POLICY =
    heuristic | predict | autotune sets the initial policy; GETT_MODEL names a
@@ -193,6 +195,68 @@ int dgett_batch(int64_t count, int64_t prec,
                 const int64_t *conts, const int64_t *const *conta, const int64_t *const *contb,
                 const int64_t *const *perm, const int64_t *const *incc, double *const *C,
                 int64_t *info);
+
+/* ZGETT / CGETT: complex data (the c and z prefixes of the BLAS naming the
+   paper follows, Section 2.3).  A, B and C hold interleaved (real,
+   imaginary) pairs, double for zgett and float for cgett (the layout of C99
+   complex types); increments count complex elements.  Each complex product
+   is formed from four real MFMA products, re += ar br - ai bi and
+   im += ar bi + ai br, accumulated in FP64 (zgett) or FP32 (cgett).  Same
+   arguments, INFO codes and accumulate semantics as dgett. */
+int zgett(int64_t ranka, const int64_t *exta, const int64_t *inca, const void *A,
+          int64_t rankb, const int64_t *extb, const int64_t *incb, const void *B,
+          int64_t conts, const int64_t *conta, const int64_t *contb, const int64_t *perm,
+          const int64_t *incc, void *C);
+int cgett(int64_t ranka, const int64_t *exta, const int64_t *inca, const void *A,
+          int64_t rankb, const int64_t *extb, const int64_t *incb, const void *B,
+          int64_t conts, const int64_t *conta, const int64_t *contb, const int64_t *perm,
+          const int64_t *incc, void *C);
+
+/* Scaled contraction with Hadamard modes: C <- ALPHA * sum + BETA * C_in.
+   xGEMM carries ALPHA and BETA (Section 2.3.1) while xGETT does not; a mode
+   shared by A, B and C (a batch or Hadamard mode) is listed among the
+   paper's future work (Section 9).  HADS pairs: mode HADA[h] of A and mode
+   HADB[h] of B (equal extents, neither contracted) are one index that A, B
+   and C carry alike; it is neither summed nor free.  C's modes are A's free
+   modes (ascending), B's free modes, then the HADS pairs in list order,
+   RC = RANKA + RANKB - 2*CONTS - HADS of them, placed by PERM with
+   increments INCC as in dgett.  BETA == 0 does not read C (C_in may hold
+   anything, NaN included); with ALPHA = BETA = 1 and HADS = 0 the call is
+   the plain xGETT.  An empty contracted sum (a contracted extent of zero)
+   leaves C = BETA * C_in.  INFO = -i for the i-th argument in the order
+   below: -1 ALPHA (NULL, complex calls), -2..-12 as -1..-11 of dgett,
+   -13 HADS < 0 or CONTS + HADS > min(RANKA, RANKB), -14 HADA NULL, out of
+   range, repeated or contracted, -15 the same for HADB or an extent
+   mismatch, -16 PERM, -17 INCC, -18 BETA (NULL, complex calls), -19 C.
+   Complex ALPHA and BETA point to (re, im) pairs.  The precision of each
+   call is that of its unscaled counterpart; the scaling is done in the
+   epilogue (FP64 for dgett_ex and sgett_bf16x3_ex, FP32 for sgett_ex,
+   the element type for the complex calls). */
+int dgett_ex(double alpha, int64_t ranka, const int64_t *exta, const int64_t *inca,
+             const double *A, int64_t rankb, const int64_t *extb, const int64_t *incb,
+             const double *B, int64_t conts, const int64_t *conta, const int64_t *contb,
+             int64_t hads, const int64_t *hada, const int64_t *hadb, const int64_t *perm,
+             const int64_t *incc, double beta, double *C);
+int sgett_ex(float alpha, int64_t ranka, const int64_t *exta, const int64_t *inca,
+             const float *A, int64_t rankb, const int64_t *extb, const int64_t *incb,
+             const float *B, int64_t conts, const int64_t *conta, const int64_t *contb,
+             int64_t hads, const int64_t *hada, const int64_t *hadb, const int64_t *perm,
+             const int64_t *incc, float beta, float *C);
+int sgett_bf16x3_ex(float alpha, int64_t ranka, const int64_t *exta, const int64_t *inca,
+                    const float *A, int64_t rankb, const int64_t *extb, const int64_t *incb,
+                    const float *B, int64_t conts, const int64_t *conta, const int64_t *contb,
+                    int64_t hads, const int64_t *hada, const int64_t *hadb,
+                    const int64_t *perm, const int64_t *incc, float beta, float *C);
+int zgett_ex(const double *alpha, int64_t ranka, const int64_t *exta, const int64_t *inca,
+             const void *A, int64_t rankb, const int64_t *extb, const int64_t *incb,
+             const void *B, int64_t conts, const int64_t *conta, const int64_t *contb,
+             int64_t hads, const int64_t *hada, const int64_t *hadb, const int64_t *perm,
+             const int64_t *incc, const double *beta, void *C);
+int cgett_ex(const float *alpha, int64_t ranka, const int64_t *exta, const int64_t *inca,
+             const void *A, int64_t rankb, const int64_t *extb, const int64_t *incb,
+             const void *B, int64_t conts, const int64_t *conta, const int64_t *contb,
+             int64_t hads, const int64_t *hada, const int64_t *hadb, const int64_t *perm,
+             const int64_t *incc, const float *beta, void *C);
 
 /* DGETT that allocates nothing, for callers that cannot allocate device
    memory (code under HIP graph capture, tight serving loops, harnesses that

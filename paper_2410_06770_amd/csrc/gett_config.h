@@ -17,7 +17,16 @@
 
 namespace gett {
 
-enum Prec : int { kF64 = 0, kF32 = 1, kBF3 = 2, kFP8 = 3 };
+// Real precisions 0-3; complex data (interleaved real and imaginary parts,
+// Section 2.3's c and z prefixes): kZ64 = complex FP64 on FP64 MFMA, kC32 =
+// complex FP32 on FP32 MFMA, four real products per complex term.
+enum Prec : int { kF64 = 0, kF32 = 1, kBF3 = 2, kFP8 = 3, kZ64 = 4, kC32 = 5 };
+constexpr int kNumPrec = 6;
+constexpr bool prec_complex(int prec) { return prec == kZ64 || prec == kC32; }
+// Bytes of one element of the precision's data.
+constexpr int prec_bytes(int prec) {
+    return prec == kF64 ? 8 : prec == kZ64 ? 16 : prec == kC32 ? 8 : 4;
+}
 
 constexpr int kThreads = 256;       // 4 waves of 64 per workgroup
 constexpr int kNumTiles = 5;        // tile menu size per precision
@@ -62,7 +71,7 @@ struct TileShape { int bm, bn, bk; bool load_fence; int depth; bool addr32; };
 // Tile menus.  FP64/FP32 run 16x16x4 MFMA steps (BK multiple of 4), the BF16x3
 // path 16x16x32 BF16 MFMA steps (BK multiple of 32).  Each workgroup is a 2x2
 // grid of waves, so BM and BN are multiples of 32.
-constexpr TileShape kTiles[4][kNumTiles] = {
+constexpr TileShape kTiles[kNumPrec][kNumTiles] = {
     /* FP64   */ {{64, 64, 16, true, 1, true}, {64, 128, 16, true, 1, true},
                   {128, 64, 16, false, 1, false}, {128, 128, 16, true, 1, true},
                   {128, 64, 8, true, 1, false}},
@@ -75,6 +84,12 @@ constexpr TileShape kTiles[4][kNumTiles] = {
     /* FP8    */ {{64, 64, 128, true, 1, false}, {64, 128, 128, true, 1, false},
                   {128, 64, 128, true, 1, false}, {128, 128, 128, true, 1, false},
                   {128, 128, 128, true, 1, false}},
+    /* Z64    */ {{64, 64, 8, true, 1, false}, {64, 128, 8, true, 1, false},
+                  {128, 64, 8, true, 1, false}, {128, 128, 8, true, 1, false},
+                  {64, 64, 16, true, 1, false}},
+    /* C32    */ {{64, 64, 16, true, 1, false}, {64, 128, 16, true, 1, false},
+                  {128, 64, 16, true, 1, false}, {128, 128, 16, true, 1, false},
+                  {128, 128, 8, true, 1, false}},
 };
 
 // Flag of the menu entry with this shape (first match).
@@ -111,14 +126,23 @@ struct TileParams {
     int64_t kPerSplit;              // contracted positions per split (multiple of BK)
     int32_t tilesM, tilesN, splits;
     int32_t bBoxX;                  // B loader sub-box width along its fast free mode
-    double *ws;                     // split-K partials [split][M][N], n fastest; null = direct
+    double *ws;                     // split-K partials [h][split][M][N] (complex: re, im
+                                    // pairs), n fastest; null = direct
     // Lowest element offset either operand addresses (free plus contracted
     // table minima, padding included), and whether each operand's whole
     // addressed span fits 32-bit byte offsets from there: then the FP64/FP32
     // tiles address it as a uniform 64-bit base plus a 32-bit lane offset.
     int64_t aLo, bLo;
     int32_t off32;
-    int32_t pad_;
+    // Hadamard modes (shared by A, B and C): H positions, each with its own
+    // base offsets into A, B and C; the grid runs every tile once per
+    // position.  H = 1 and null tables without Hadamard modes.
+    int32_t H;
+    const int64_t *offAH, *offBH, *offCH;
+    // C <- alpha * sum + beta * C_in ((re, im) pairs; im is 0 for real
+    // data); beta == 0 does not read C.  alpha = beta = 1 is the paper's
+    // accumulate.
+    double alpha[2], beta[2];
 #ifdef GETT_ADDR_CHECK
     // Checked build only: the addressed element ranges [lo, lo + span] of A,
     // B and C (C from its own increments) that every access is tested against.

@@ -28,12 +28,20 @@ const char *last_hip_error_name() {
 GETT_DECLARE_PRECISION(f64)
 GETT_DECLARE_PRECISION(f32)
 GETT_DECLARE_PRECISION(bf3)
+#define GETT_DECLARE_TILE_PRECISION(SUFFIX)                                                        \
+    int launch_tile_##SUFFIX(int tile, bool afk, bool bfk, const TileParams &p, hipStream_t s);    \
+    int launch_splitk_reduce_##SUFFIX(const TileParams &p, hipStream_t s);                        \
+    int64_t addr_violations_##SUFFIX(bool reset);
+GETT_DECLARE_TILE_PRECISION(z64)
+GETT_DECLARE_TILE_PRECISION(c32)
 
 int launch_tile(int prec, int tile, bool aFastK, bool bFastK, const TileParams &p, hipStream_t s) {
     switch (prec) {
     case kF64: return launch_tile_f64(tile, aFastK, bFastK, p, s);
     case kF32: return launch_tile_f32(tile, aFastK, bFastK, p, s);
     case kBF3: return launch_tile_bf3(tile, aFastK, bFastK, p, s);
+    case kZ64: return launch_tile_z64(tile, aFastK, bFastK, p, s);
+    case kC32: return launch_tile_c32(tile, aFastK, bFastK, p, s);
     default: return GETT_ERR_INTERNAL;
     }
 }
@@ -43,6 +51,8 @@ int launch_splitk_reduce(int prec, const TileParams &p, hipStream_t s) {
     case kF64: return launch_splitk_reduce_f64(p, s);
     case kF32: return launch_splitk_reduce_f32(p, s);
     case kBF3: return launch_splitk_reduce_bf3(p, s);
+    case kZ64: return launch_splitk_reduce_z64(p, s);
+    case kC32: return launch_splitk_reduce_c32(p, s);
     default: return GETT_ERR_INTERNAL;
     }
 }
@@ -83,6 +93,8 @@ int64_t addr_violations(int prec, bool reset) {
     case kF64: return addr_violations_f64(reset);
     case kF32: return addr_violations_f32(reset);
     case kBF3: return addr_violations_bf3(reset);
+    case kZ64: return addr_violations_z64(reset);
+    case kC32: return addr_violations_c32(reset);
     default: return -1;
     }
 }

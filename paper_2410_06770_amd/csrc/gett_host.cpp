@@ -108,21 +108,23 @@ static bool sched_valid(int prec, const Sched &s, int64_t K) {
 // Built-in rules (the default policy, and the baseline of the predictor):
 // fill the 256 CUs with whole waves of tiles, prefer larger tiles, and split
 // K only when there are too few tiles to occupy the chip.
-static Sched heuristic(int prec, int64_t M, int64_t N, int64_t K) {
+static Sched heuristic(int prec, int64_t M, int64_t N, int64_t K, int64_t H = 1) {
     // Relative per-CU throughput of each tile once the chip is full, from
     // timings of the menu on large strided and dense contractions.
-    static const double kSpeed[4][kNumTiles] = {
+    static const double kSpeed[kNumPrec][kNumTiles] = {
         {0.88, 0.92, 1.0, 0.80, 0.96},  // FP64: the 128x64 tiles run 3-4 workgroups per CU
         {0.8, 0.9, 0.9, 1.0, 0.95},     // FP32
         {0.95, 0.9, 1.0, 0.85, 0.8},    // BF16x3
-        {0.8, 0.9, 0.9, 1.0, 1.0}};     // FP8 (its own kernel)
+        {0.8, 0.9, 0.9, 1.0, 1.0},      // FP8 (its own kernel)
+        {0.95, 1.0, 1.0, 0.9, 0.9},     // complex FP64
+        {0.9, 0.95, 0.95, 1.0, 0.9}};   // complex FP32
     const double *kTileSpeed = kSpeed[prec];
     double best = -1;
     Sched bs{3, 0, 0};
     for (int t = 0; t < kNumTiles; ++t) {
         const TileShape ts = kTiles[prec][t];
         const double tm = std::ceil((double)M / ts.bm), tn = std::ceil((double)N / ts.bn);
-        const double tiles = tm * tn;
+        const double tiles = tm * tn * (double)std::max<int64_t>(H, 1);
         const double slots = 256.0 * ((ts.bm * ts.bn >= 128 * 128) ? 1.0 : 2.0);
         const double waves = std::ceil(tiles / slots);
         const double util = tiles / (waves * slots);
@@ -134,7 +136,8 @@ static Sched heuristic(int prec, int64_t M, int64_t N, int64_t K) {
         }
     }
     const TileShape ts = kTiles[prec][bs.tile];
-    const double tiles = std::ceil((double)M / ts.bm) * std::ceil((double)N / ts.bn);
+    const double tiles = std::ceil((double)M / ts.bm) * std::ceil((double)N / ts.bn) *
+                         (double)std::max<int64_t>(H, 1);
     bs.split = 0;
     if (prec != kFP8 && tiles < 192) {
         // too few tiles for 256 CUs: split K, as far as the contraction allows
@@ -153,8 +156,10 @@ static Sched heuristic(int prec, int64_t M, int64_t N, int64_t K) {
 // K step or split share them.
 struct TableSet {
     Canon cn;
-    int64_t Mp = 0, Np = 0, Kp = 0;
-    int64_t *d_tab = nullptr;   // offAM, offCM [Mp]; offBN, offCN [Np]; offAK, offBK [Kp]
+    int64_t Mp = 0, Np = 0, Kp = 0, Hp = 0;
+    // offAM, offCM [Mp]; offBN, offCN [Np]; offAK, offBK [Kp]; then, with
+    // Hadamard modes, offAH, offBH, offCH [Hp]
+    int64_t *d_tab = nullptr;
     int64_t aLo = 0, aSpan = 0, bLo = 0, bSpan = 0;   // addressed element range of A and B
     int64_t cLo = 0, cSpan = 0;                        // and of C
     ~TableSet() {
@@ -183,7 +188,8 @@ static int upload_tables(TableSet &t) {
     // K tables: zero padding past K covers the kernel's look-ahead loads (two
     // steps of at most 64 positions past the last slice start, which is < K).
     t.Kp = round_up(std::max<int64_t>(c.K, 1), 128) + 256;
-    std::vector<int64_t> h(2 * (t.Mp + t.Np + t.Kp));
+    t.Hp = c.H > 1 ? c.H : 0;
+    std::vector<int64_t> h(2 * (t.Mp + t.Np + t.Kp) + 3 * t.Hp);
     int64_t *p = h.data();
     group_offsets(c.m, 0, t.Mp, p);
     group_offsets(c.m, 1, t.Mp, p + t.Mp);
@@ -193,6 +199,8 @@ static int upload_tables(TableSet &t) {
     p += 2 * t.Np;
     group_offsets(c.k, 0, t.Kp, p);
     group_offsets(c.k, 1, t.Kp, p + t.Kp);
+    p += 2 * t.Kp;
+    if (t.Hp) hadamard_offsets(c.h, p, p + t.Hp, p + 2 * t.Hp);
     operand_ranges(c, t.aLo, t.aSpan, t.bLo, t.bSpan);
     {
         int64_t ml, mh, nl, nh;
@@ -220,7 +228,7 @@ static int get_tables(const Args &a, int order, int bn, int dev, TableSet **out)
     }
     auto t = std::make_unique<TableSet>();
     t->cn = canonicalise(a, order, bn);
-    if (t->cn.M > INT32_MAX || t->cn.N > INT32_MAX) return GETT_ERR_INTERNAL;
+    if (t->cn.M > INT32_MAX || t->cn.N > INT32_MAX || t->cn.H > INT32_MAX) return GETT_ERR_INTERNAL;
     int rc = upload_tables(*t);
     if (rc) return rc;
     std::lock_guard<std::mutex> lk(g_mu);
@@ -230,7 +238,7 @@ static int get_tables(const Args &a, int order, int bn, int dev, TableSet **out)
     return 0;
 }
 
-static Sched choose_schedule(int prec, const Args &a, int64_t M, int64_t N, int64_t K,
+static Sched choose_schedule(int prec, const Args &a, int64_t M, int64_t N, int64_t K, int64_t H,
                              const char **source);
 
 static int get_plan(int prec, const Args &a, int dev, int64_t forced, std::shared_ptr<Plan> *out) {
@@ -252,7 +260,7 @@ static int get_plan(int prec, const Args &a, int dev, int64_t forced, std::share
         s = sched_of(forced);
         if (!sched_valid(prec, s, c0.K)) return GETT_ERR_STATE;
     } else {
-        s = choose_schedule(prec, a, c0.M, c0.N, c0.K, &source);
+        s = choose_schedule(prec, a, c0.M, c0.N, c0.K, c0.H, &source);
     }
     auto pl = std::make_shared<Plan>();
     pl->prec = prec;
@@ -262,7 +270,8 @@ static int get_plan(int prec, const Args &a, int dev, int64_t forced, std::share
     if (rc) return rc;
     const Canon &cn = pl->tab->cn;
     const int64_t tiles = ((cn.M + ts.bm - 1) / ts.bm) * ((cn.N + ts.bn - 1) / ts.bn);
-    if (tiles * split_count(s.split, tiles, std::max<int64_t>(cn.K, 1), ts.bk, nullptr) >
+    if (tiles * split_count(s.split, tiles, std::max<int64_t>(cn.K, 1), ts.bk, nullptr) *
+            std::max<int64_t>(cn.H, 1) >
         INT32_MAX)
         return GETT_ERR_INTERNAL;
     if (g_log)
@@ -308,10 +317,19 @@ static TileParams make_params(const Plan &pl, const void *A, const void *B, void
     p.ws = nullptr;
     p.aLo = t.aLo;
     p.bLo = t.bLo;
-    const int64_t esz = pl.prec == kF64 ? 8 : 4;
+    const int64_t esz = prec_bytes(pl.prec);
     const int64_t lim = (int64_t)1 << 32;
     p.off32 = (t.aSpan < lim / esz && t.bSpan < lim / esz) ? 1 : 0;
-    p.pad_ = 0;
+    p.H = (int32_t)std::max<int64_t>(c.H, 1);
+    const int64_t *th = t.d_tab + 2 * (t.Mp + t.Np + t.Kp);
+    // (the canonical form's Hadamard increments already follow a swap of A and B)
+    p.offAH = t.Hp ? th : nullptr;
+    p.offBH = t.Hp ? th + t.Hp : nullptr;
+    p.offCH = t.Hp ? th + 2 * t.Hp : nullptr;
+    p.alpha[0] = 1.0;
+    p.alpha[1] = 0.0;
+    p.beta[0] = 1.0;
+    p.beta[1] = 0.0;
 #ifdef GETT_ADDR_CHECK
     // GETT_CHECK_SHRINK=1 narrows the checked ranges of A and B by one
     // element at the top (the accesses themselves are unchanged), so a test
@@ -328,10 +346,22 @@ static TileParams make_params(const Plan &pl, const void *A, const void *B, void
     return p;
 }
 
-static int run_plan(const Plan &pl, const void *A, const void *B, void *C, hipStream_t s) {
+static const double kOne[2] = {1.0, 0.0};
+
+// alpha, beta: (re, im) pairs of C <- alpha * sum + beta * C_in.
+static int run_plan(const Plan &pl, const void *A, const void *B, void *C, hipStream_t s,
+                    const double *alpha = kOne, const double *beta = kOne) {
     TileParams p = make_params(pl, A, B, C);
+    auto scale = [&](TileParams &q) {
+        q.alpha[0] = alpha[0];
+        q.alpha[1] = alpha[1];
+        q.beta[0] = beta[0];
+        q.beta[1] = beta[1];
+    };
+    scale(p);
     if (p.splits > 1) {
-        const int64_t bytes = (int64_t)p.splits * p.M * p.N * (int64_t)sizeof(double);
+        const int64_t bytes = (int64_t)p.splits * p.M * p.N * (int64_t)p.H *
+                              (prec_complex(pl.prec) ? 2 : 1) * (int64_t)sizeof(double);
         void *ws = nullptr;
         if (bytes <= g_max_ws.load() && hipMallocAsync(&ws, (size_t)bytes, s) == hipSuccess) {
             p.ws = static_cast<double *>(ws);
@@ -343,6 +373,7 @@ static int run_plan(const Plan &pl, const void *A, const void *B, void *C, hipSt
         // over the cap or out of memory: the same tile and order, unsplit
         (void)hipGetLastError();
         p = make_params(pl, A, B, C, 0);
+        scale(p);
         t_last_schedule = sched_id(Sched{pl.sched.tile, pl.sched.order, 0});
     }
     return launch_tile(pl.prec, pl.sched.tile, pl.tab->cn.aFastK, pl.tab->cn.bFastK, p, s);
@@ -843,12 +874,13 @@ static void append_tune_db_locked(const std::string &key, int64_t id, double us)
 static thread_local const void *t_tune_ptrs[3] = {nullptr, nullptr, nullptr};
 static thread_local int t_tune_dev = 0;
 
-static Sched choose_schedule(int prec, const Args &a, int64_t M, int64_t N, int64_t K,
+static Sched choose_schedule(int prec, const Args &a, int64_t M, int64_t N, int64_t K, int64_t H,
                              const char **source) {
     const int pol = g_policy.load();
-    Sched s = heuristic(prec, M, N, K);
+    Sched s = heuristic(prec, M, N, K, H);
     *source = "heuristic";
-    if (pol == GETT_PREDICT) {
+    // The predictor knows the real precisions of single contractions only.
+    if (pol == GETT_PREDICT && prec <= kFP8 && a.hads == 0) {
         Sched p;
         if (predict(prec, a, K, &p)) {
             s = p;
@@ -896,21 +928,12 @@ static Sched choose_schedule(int prec, const Args &a, int64_t M, int64_t N, int6
 // ---------------------------------------------------------------------------
 static int64_t c_span_elems(const Args &a, int64_t *lo_out) {
     // extent of C's footprint in elements: [lo, hi]
-    bool contA[64] = {false}, contB[64] = {false};
-    for (int64_t x = 0; x < a.conts; ++x) {
-        contA[a.conta[x]] = true;
-        contB[a.contb[x]] = true;
-    }
-    std::vector<int64_t> extc(a.ranka + a.rankb - 2 * a.conts);
-    int64_t p = 0;
-    for (int64_t i = 0; i < a.ranka; ++i)
-        if (!contA[i]) extc[a.perm[p++]] = a.exta[i];
-    for (int64_t j = 0; j < a.rankb; ++j)
-        if (!contB[j]) extc[a.perm[p++]] = a.extb[j];
+    std::vector<int64_t> extc, incc;
+    output_modes(a, extc, incc);
     int64_t lo = 0, hi = 0;
     for (size_t q = 0; q < extc.size(); ++q) {
         if (extc[q] <= 1) continue;
-        const int64_t d = a.incc[q] * (extc[q] - 1);
+        const int64_t d = incc[q] * (extc[q] - 1);
         if (d < 0) lo += d;
         else hi += d;
     }
@@ -918,11 +941,43 @@ static int64_t c_span_elems(const Args &a, int64_t *lo_out) {
     return hi - lo + 1;
 }
 
-static int run(int prec, const Args &a, const void *A, const void *B, void *C) {
+// C <- beta * C_in on every output (the scaled calls whose contracted sum is
+// empty: a contracted extent of zero).
+static int scale_outputs(int prec, const Args &a, void *C, const double *beta, hipStream_t s) {
+    std::vector<int64_t> extc, incc;
+    output_modes(a, extc, incc);
+    ScaleModes sm{};
+    sm.total = 1;
+    for (size_t q = 0; q < extc.size(); ++q) {
+        sm.total *= extc[q];
+        if (extc[q] == 1) continue;
+        if (sm.n >= kScaleModes) return GETT_ERR_INTERNAL;
+        sm.ext[sm.n] = extc[q];
+        sm.inc[sm.n] = incc[q];
+        ++sm.n;
+    }
+    if (sm.total == 0) return 0;
+    return launch_scale_c(prec, C, sm, beta, s);
+}
+
+static bool is_one(const double *x) { return x[0] == 1.0 && x[1] == 0.0; }
+
+// alpha, beta: (re, im) pairs of C <- alpha * sum + beta * C_in (kOne for
+// the paper's accumulate).
+static int run(int prec, const Args &a, const void *A, const void *B, void *C,
+               const double *alpha = kOne, const double *beta = kOne) {
     int info = validate(a, A, B, C);
     if (info) return info;
     Canon probe = canonicalise(a, 0, 128);
-    if (probe.empty || probe.M == 0 || probe.N == 0 || probe.K == 0) return 0;
+    if (probe.empty || probe.M == 0 || probe.N == 0 || probe.K == 0 || probe.H == 0) {
+        // No term at all.  The paper's accumulate leaves C as it is; a scaled
+        // call still scales C_in (by beta) wherever C has outputs.
+        if (is_one(beta)) return 0;
+        int dev = 0;
+        int rc = check_device(&dev);
+        if (rc) return rc;
+        return scale_outputs(prec, a, C, beta, t_stream);
+    }
     int dev = 0;
     int rc = check_device(&dev);
     if (rc) return rc;
@@ -937,7 +992,7 @@ static int run(int prec, const Args &a, const void *A, const void *B, void *C) {
     // (only then: a cached plan needs no timing).
     void *saved = nullptr;
     int64_t lo = 0, span = 0;
-    const size_t esz = prec == kF64 ? 8 : 4;
+    const size_t esz = (size_t)prec_bytes(prec);
     bool cached = false;
     {
         std::lock_guard<std::mutex> lk(g_mu);
@@ -964,7 +1019,7 @@ static int run(int prec, const Args &a, const void *A, const void *B, void *C) {
         (void)hipFreeAsync(saved, s);
     }
     if (rc) return rc;
-    return run_plan(*pl, A, B, C, s);
+    return run_plan(*pl, A, B, C, s, alpha, beta);
 }
 
 // ---------------------------------------------------------------------------
@@ -1302,6 +1357,30 @@ static int batch_entry(int prec, int64_t count, const int64_t *ranka, const int6
 
 }  // namespace gett
 
+namespace gett {
+// INFO of the scaled calls, numbered in their argument order
+// (ALPHA, RANKA, EXTA, INCA, A, RANKB, EXTB, INCB, B, CONTS, CONTA, CONTB,
+// HADS, HADA, HADB, PERM, INCC, BETA, C): codes of the 14-argument checks
+// move to their new positions.
+static int ex_info(int v) {
+    if (v == 0) return 0;
+    if (v == kInfoHads) return -13;
+    if (v == kInfoHada) return -14;
+    if (v == kInfoHadb) return -15;
+    if (v >= -11) return v - 1;       // RANKA .. CONTB
+    if (v == -12) return -16;         // PERM
+    if (v == -13) return -17;         // INCC
+    return -19;                       // C
+}
+
+static int run_ex(int prec, const double *alpha, const Args &a, const void *A, const void *B,
+                  void *C, const double *beta) {
+    const int info = ex_info(validate(a, A, B, C));
+    if (info) return info;
+    return run(prec, a, A, B, C, alpha, beta);
+}
+}  // namespace gett
+
 using namespace gett;
 
 // ---------------------------------------------------------------------------
@@ -1414,11 +1493,76 @@ int dgett_batch(int64_t count, int64_t prec, const int64_t *ranka, const int64_t
                        contb, perm, incc, reinterpret_cast<void *const *>(C), info);
 }
 
+int zgett(int64_t ranka, const int64_t *exta, const int64_t *inca, const void *A, int64_t rankb,
+          const int64_t *extb, const int64_t *incb, const void *B, int64_t conts,
+          const int64_t *conta, const int64_t *contb, const int64_t *perm, const int64_t *incc,
+          void *C) {
+    return run(kZ64, GETT_ARGS_MAKE, A, B, C);
+}
+
+int cgett(int64_t ranka, const int64_t *exta, const int64_t *inca, const void *A, int64_t rankb,
+          const int64_t *extb, const int64_t *incb, const void *B, int64_t conts,
+          const int64_t *conta, const int64_t *contb, const int64_t *perm, const int64_t *incc,
+          void *C) {
+    return run(kC32, GETT_ARGS_MAKE, A, B, C);
+}
+
 int dgett_noalloc(int64_t ranka, const int64_t *exta, const int64_t *inca, const double *A,
                   int64_t rankb, const int64_t *extb, const int64_t *incb, const double *B,
                   int64_t conts, const int64_t *conta, const int64_t *contb, const int64_t *perm,
                   const int64_t *incc, double *C) {
     return run_noalloc(GETT_ARGS_MAKE, A, B, C);
+}
+
+#define GETT_EX_ARGS_MAKE                                                                        \
+    Args{ranka, exta, inca, rankb, extb, incb, conts, conta, contb, perm, incc, hads, hada, hadb}
+
+int dgett_ex(double alpha, int64_t ranka, const int64_t *exta, const int64_t *inca,
+             const double *A, int64_t rankb, const int64_t *extb, const int64_t *incb,
+             const double *B, int64_t conts, const int64_t *conta, const int64_t *contb,
+             int64_t hads, const int64_t *hada, const int64_t *hadb, const int64_t *perm,
+             const int64_t *incc, double beta, double *C) {
+    const double al[2] = {alpha, 0.0}, be[2] = {beta, 0.0};
+    return run_ex(kF64, al, GETT_EX_ARGS_MAKE, A, B, C, be);
+}
+
+int sgett_ex(float alpha, int64_t ranka, const int64_t *exta, const int64_t *inca,
+             const float *A, int64_t rankb, const int64_t *extb, const int64_t *incb,
+             const float *B, int64_t conts, const int64_t *conta, const int64_t *contb,
+             int64_t hads, const int64_t *hada, const int64_t *hadb, const int64_t *perm,
+             const int64_t *incc, float beta, float *C) {
+    const double al[2] = {alpha, 0.0}, be[2] = {beta, 0.0};
+    return run_ex(kF32, al, GETT_EX_ARGS_MAKE, A, B, C, be);
+}
+
+int sgett_bf16x3_ex(float alpha, int64_t ranka, const int64_t *exta, const int64_t *inca,
+                    const float *A, int64_t rankb, const int64_t *extb, const int64_t *incb,
+                    const float *B, int64_t conts, const int64_t *conta, const int64_t *contb,
+                    int64_t hads, const int64_t *hada, const int64_t *hadb,
+                    const int64_t *perm, const int64_t *incc, float beta, float *C) {
+    const double al[2] = {alpha, 0.0}, be[2] = {beta, 0.0};
+    return run_ex(kBF3, al, GETT_EX_ARGS_MAKE, A, B, C, be);
+}
+
+int zgett_ex(const double *alpha, int64_t ranka, const int64_t *exta, const int64_t *inca,
+             const void *A, int64_t rankb, const int64_t *extb, const int64_t *incb,
+             const void *B, int64_t conts, const int64_t *conta, const int64_t *contb,
+             int64_t hads, const int64_t *hada, const int64_t *hadb, const int64_t *perm,
+             const int64_t *incc, const double *beta, void *C) {
+    if (!alpha) return -1;
+    if (!beta) return -18;
+    return run_ex(kZ64, alpha, GETT_EX_ARGS_MAKE, A, B, C, beta);
+}
+
+int cgett_ex(const float *alpha, int64_t ranka, const int64_t *exta, const int64_t *inca,
+             const void *A, int64_t rankb, const int64_t *extb, const int64_t *incb,
+             const void *B, int64_t conts, const int64_t *conta, const int64_t *contb,
+             int64_t hads, const int64_t *hada, const int64_t *hadb, const int64_t *perm,
+             const int64_t *incc, const float *beta, void *C) {
+    if (!alpha) return -1;
+    if (!beta) return -18;
+    const double al[2] = {alpha[0], alpha[1]}, be[2] = {beta[0], beta[1]};
+    return run_ex(kC32, al, GETT_EX_ARGS_MAKE, A, B, C, be);
 }
 
 int gett_set_stream(void *hip_stream) {
@@ -1438,10 +1582,10 @@ int gett_get_policy(void) { return g_policy.load(); }
 
 int gett_load_predictor(const char *path) { return path ? load_predictor(path) : GETT_ERR_STATE; }
 
-int64_t gett_num_tiles(int prec) { return (prec >= 0 && prec <= 3) ? kNumTiles : 0; }
+int64_t gett_num_tiles(int prec) { return (prec >= 0 && prec < kNumPrec) ? kNumTiles : 0; }
 
 int gett_tile_shape(int prec, int64_t t, int64_t *out) {
-    if (prec < 0 || prec > 3 || t < 0 || t >= kNumTiles || !out) return GETT_ERR_STATE;
+    if (prec < 0 || prec >= kNumPrec || t < 0 || t >= kNumTiles || !out) return GETT_ERR_STATE;
     out[0] = kTiles[prec][t].bm;
     out[1] = kTiles[prec][t].bn;
     out[2] = kTiles[prec][t].bk;
@@ -1458,7 +1602,7 @@ int64_t gett_last_schedule(void) { return t_last_schedule; }
 int64_t gett_addr_violations(int reset) {
 #ifdef GETT_ADDR_CHECK
     int64_t total = 0;
-    for (int prec : {kF64, kF32, kBF3}) {
+    for (int prec : {kF64, kF32, kBF3, kZ64, kC32}) {
         const int64_t v = addr_violations(prec, reset != 0);
         if (v < 0) return GETT_ERR_HIP;
         total += v;
@@ -1532,7 +1676,8 @@ static int64_t describe(int prec, int64_t order, int64_t tile, const Args &a, in
     const int info = validate(a, reinterpret_cast<void *>(1), reinterpret_cast<void *>(1),
                               reinterpret_cast<void *>(1));
     if (info) return info;
-    if (prec < 0 || prec > 2 || order < 0 || order >= kNumOrders || tile < 0 || tile >= kNumTiles)
+    if (prec < 0 || prec >= kNumPrec || prec == kFP8 || order < 0 || order >= kNumOrders ||
+        tile < 0 || tile >= kNumTiles)
         return GETT_ERR_STATE;
     Canon c = canonicalise(a, (int)order, kTiles[prec][tile].bn);
     std::vector<int64_t> v;

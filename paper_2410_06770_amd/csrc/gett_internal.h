@@ -16,6 +16,19 @@ namespace gett {
 int launch_status();
 const char *last_hip_error_name();
 
+// Output modes of C (extent > 1) for the scaling pass of calls whose
+// contracted sum is empty; rank of C is at most 128, and at most 63 of its
+// modes can have extent > 1 in an addressable tensor.
+constexpr int kScaleModes = 64;
+struct ScaleModes {
+    int64_t ext[kScaleModes], inc[kScaleModes];
+    int32_t n;
+    int32_t pad_;
+    int64_t total;
+};
+// C <- beta * C (beta = (re, im); zero writes zeros without reading C).
+int launch_scale_c(int prec, void *C, const ScaleModes &m, const double *beta, hipStream_t s);
+
 // Kernel launchers (defined in the .hip files).
 int launch_tile(int prec, int tile, bool aFastK, bool bFastK, const TileParams &p,
                 hipStream_t s);

@@ -90,7 +90,24 @@ int validate(const Args &a, const void *A, const void *B, const void *C) {
         usedB[y] = true;
         if (a.exta[a.conta[k]] != a.extb[y]) return -11;   // Section 2.2: equal extents
     }
-    const int64_t rc = a.ranka + a.rankb - 2 * a.conts;
+    // Hadamard pairs: modes of A and B not contracted, each used once, equal
+    // extents.
+    if (a.hads < 0 || a.conts + a.hads > a.ranka || a.conts + a.hads > a.rankb) return kInfoHads;
+    if (a.hads > 0 && !a.hada) return kInfoHada;
+    bool hadA[kMaxRank] = {false}, hadB[kMaxRank] = {false};
+    for (int64_t h = 0; h < a.hads; ++h) {
+        const int64_t x = a.hada[h];
+        if (x < 0 || x >= a.ranka || usedA[x] || hadA[x]) return kInfoHada;
+        hadA[x] = true;
+    }
+    if (a.hads > 0 && !a.hadb) return kInfoHadb;
+    for (int64_t h = 0; h < a.hads; ++h) {
+        const int64_t y = a.hadb[h];
+        if (y < 0 || y >= a.rankb || usedB[y] || hadB[y]) return kInfoHadb;
+        hadB[y] = true;
+        if (a.exta[a.hada[h]] != a.extb[y]) return kInfoHadb;
+    }
+    const int64_t rc = out_rank(a);
     if (rc > 0 && !a.perm) return -12;
     bool seen[2 * kMaxRank] = {false};
     for (int64_t p = 0; p < rc; ++p) {
@@ -101,9 +118,10 @@ int validate(const Args &a, const void *A, const void *B, const void *C) {
     int64_t extc[2 * kMaxRank];
     int64_t p = 0;
     for (int64_t i = 0; i < a.ranka; ++i)
-        if (!usedA[i]) extc[a.perm[p++]] = a.exta[i];
+        if (!usedA[i] && !hadA[i]) extc[a.perm[p++]] = a.exta[i];
     for (int64_t j = 0; j < a.rankb; ++j)
-        if (!usedB[j]) extc[a.perm[p++]] = a.extb[j];
+        if (!usedB[j] && !hadB[j]) extc[a.perm[p++]] = a.extb[j];
+    for (int64_t h = 0; h < a.hads; ++h) extc[a.perm[p++]] = a.exta[a.hada[h]];
     if (rc > 0 && !a.incc) return -13;
     for (int64_t q = 0; q < rc; ++q)
         if (a.incc[q] == 0 && extc[q] > 1) return -13;
@@ -116,11 +134,15 @@ int validate(const Args &a, const void *A, const void *B, const void *C) {
 
 // Raw groups straight from the arguments (Section 6 preprocessing, regrouped).
 static void raw_groups(const Args &a, std::vector<GMode> &m, std::vector<GMode> &n,
-                       std::vector<GMode> &k) {
+                       std::vector<GMode> &k, std::vector<HMode> *hg = nullptr) {
     bool contA[kMaxRank] = {false}, contB[kMaxRank] = {false};
     for (int64_t x = 0; x < a.conts; ++x) {
         contA[a.conta[x]] = true;
         contB[a.contb[x]] = true;
+    }
+    for (int64_t h = 0; h < a.hads; ++h) {   // Hadamard modes are neither free nor summed
+        contA[a.hada[h]] = true;
+        contB[a.hadb[h]] = true;
     }
     int64_t p = 0;
     for (int64_t i = 0; i < a.ranka; ++i)
@@ -135,6 +157,12 @@ static void raw_groups(const Args &a, std::vector<GMode> &m, std::vector<GMode> 
         }
     for (int64_t x = 0; x < a.conts; ++x)
         k.push_back({a.exta[a.conta[x]], a.inca[a.conta[x]], a.incb[a.contb[x]]});
+    if (hg)
+        for (int64_t h = 0; h < a.hads; ++h) {
+            hg->push_back({a.exta[a.hada[h]], a.inca[a.hada[h]], a.incb[a.hadb[h]],
+                           a.incc[a.perm[p]]});
+            ++p;
+        }
 }
 
 static int64_t group_size(const std::vector<GMode> &g) {
@@ -179,10 +207,15 @@ static int64_t min_abs(const std::vector<GMode> &g, int slot) {
 Canon canonicalise(const Args &a, int order, int bn) {
     Canon c;
     std::vector<GMode> m, n, k;
-    raw_groups(a, m, n, k);
+    std::vector<HMode> h;
+    raw_groups(a, m, n, k, &h);
     for (auto *g : {&m, &n, &k})
         for (const auto &x : *g)
             if (x.ext == 0) c.empty = true;
+    for (const auto &x : h)
+        if (x.ext == 0) c.empty = true;
+    h.erase(std::remove_if(h.begin(), h.end(), [](const HMode &x) { return x.ext == 1; }),
+            h.end());
     auto drop1 = [](std::vector<GMode> &g) {
         g.erase(std::remove_if(g.begin(), g.end(), [](const GMode &x) { return x.ext == 1; }),
                 g.end());
@@ -197,6 +230,7 @@ Canon canonicalise(const Args &a, int order, int bn) {
         c.swapped = true;
         std::swap(m, n);
         for (auto &x : k) std::swap(x.i0, x.i1);
+        for (auto &x : h) std::swap(x.ia, x.ib);
     }
     merge_group(m);
     merge_group(n);
@@ -252,8 +286,50 @@ Canon canonicalise(const Args &a, int order, int bn) {
     c.M = group_size(m);
     c.N = group_size(n);
     c.K = group_size(k);
-    if (c.empty) c.M = c.N = c.K = 0;
+    c.h = h;
+    c.H = 1;
+    for (const auto &x : h) c.H *= x.ext;
+    if (c.empty) c.M = c.N = c.K = c.H = 0;
     return c;
+}
+
+void output_modes(const Args &a, std::vector<int64_t> &ext, std::vector<int64_t> &inc) {
+    bool skipA[kMaxRank] = {false}, skipB[kMaxRank] = {false};
+    for (int64_t x = 0; x < a.conts; ++x) {
+        skipA[a.conta[x]] = true;
+        skipB[a.contb[x]] = true;
+    }
+    for (int64_t h = 0; h < a.hads; ++h) {
+        skipA[a.hada[h]] = true;
+        skipB[a.hadb[h]] = true;
+    }
+    const int64_t rc = out_rank(a);
+    ext.assign(rc, 1);
+    inc.assign(a.incc, a.incc + rc);
+    int64_t p = 0;
+    for (int64_t i = 0; i < a.ranka; ++i)
+        if (!skipA[i]) ext[a.perm[p++]] = a.exta[i];
+    for (int64_t j = 0; j < a.rankb; ++j)
+        if (!skipB[j]) ext[a.perm[p++]] = a.extb[j];
+    for (int64_t h = 0; h < a.hads; ++h) ext[a.perm[p++]] = a.exta[a.hada[h]];
+}
+
+void hadamard_offsets(const std::vector<HMode> &h, int64_t *outA, int64_t *outB, int64_t *outC) {
+    int64_t total = 1;
+    for (const auto &x : h) total *= x.ext;
+    for (int64_t g = 0; g < total; ++g) {
+        int64_t r = g, oa = 0, ob = 0, oc = 0;
+        for (const auto &x : h) {
+            const int64_t c = r % x.ext;
+            r /= x.ext;
+            oa += c * x.ia;
+            ob += c * x.ib;
+            oc += c * x.ic;
+        }
+        outA[g] = oa;
+        outB[g] = ob;
+        outC[g] = oc;
+    }
 }
 
 void group_offsets(const std::vector<GMode> &g, int slot, int64_t padded, int64_t *out) {
@@ -385,7 +461,11 @@ std::string signature_key(const Args &a, int prec, int64_t extra0, int64_t extra
     for (int64_t i = 0; i < a.rankb; ++i) { v.push_back(a.extb[i]); v.push_back(a.incb[i]); }
     v.push_back(a.conts);
     for (int64_t i = 0; i < a.conts; ++i) { v.push_back(a.conta[i]); v.push_back(a.contb[i]); }
-    const int64_t rc = a.ranka + a.rankb - 2 * a.conts;
+    if (a.hads > 0) {
+        v.push_back(-1 - a.hads);
+        for (int64_t i = 0; i < a.hads; ++i) { v.push_back(a.hada[i]); v.push_back(a.hadb[i]); }
+    }
+    const int64_t rc = out_rank(a);
     for (int64_t i = 0; i < rc; ++i) { v.push_back(a.perm[i]); v.push_back(a.incc[i]); }
     return std::string(reinterpret_cast<const char *>(v.data()), v.size() * sizeof(int64_t));
 }

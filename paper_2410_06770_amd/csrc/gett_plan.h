@@ -8,7 +8,11 @@
 
 namespace gett {
 
-// The 14 xGETT arguments (Section 5.7), pointers excluded.
+// The 14 xGETT arguments (Section 5.7), pointers excluded, and the Hadamard
+// pairs of the extended calls: mode hada[h] of A and mode hadb[h] of B are
+// one index carried by A, B and C alike (neither summed nor free; Section 9
+// lists such batch modes as future work).  Output modes: A's free modes,
+// B's free modes, then the Hadamard pairs, placed by PERM.
 struct Args {
     int64_t ranka;
     const int64_t *exta, *inca;
@@ -16,10 +20,22 @@ struct Args {
     const int64_t *extb, *incb;
     int64_t conts;
     const int64_t *conta, *contb, *perm, *incc;
+    int64_t hads = 0;
+    const int64_t *hada = nullptr, *hadb = nullptr;
 };
 
-// LAPACK-style INFO (0 or -i).  Pointers are only tested against NULL.
+// INFO codes of validate beyond the 14 of the paper's argument list.
+constexpr int kInfoHads = -101, kInfoHada = -102, kInfoHadb = -103;
+
+// LAPACK-style INFO (0 or -i, i in the 14-argument order; kInfoHad* for the
+// Hadamard lists).  Pointers are only tested against NULL.
 int validate(const Args &a, const void *A, const void *B, const void *C);
+
+// Number of output modes: RANKA + RANKB - 2 CONTS - HADS.
+inline int64_t out_rank(const Args &a) { return a.ranka + a.rankb - 2 * a.conts - a.hads; }
+
+// Extents and increments of C by output position (valid arguments only).
+void output_modes(const Args &a, std::vector<int64_t> &ext, std::vector<int64_t> &inc);
 
 // One mode of a group: extent and the increments of the two tensors that
 // carry the group (M: A and C; N: B and C; K: A and B).
@@ -28,12 +44,19 @@ struct GMode {
     int64_t i0, i1;
 };
 
-// The contraction as a GEMM over three mode groups.
+// A Hadamard mode: extent and the increments in A, B and C.
+struct HMode {
+    int64_t ext, ia, ib, ic;
+};
+
+// The contraction as a GEMM over three mode groups, repeated over the
+// positions of the Hadamard group.
 struct Canon {
     bool empty = false;          // a zero extent: nothing to do
     bool swapped = false;        // A and B exchanged (so that C's fastest mode is in N)
     std::vector<GMode> m, n, k;  // ordered, first mode fastest
-    int64_t M = 1, N = 1, K = 1;
+    std::vector<HMode> h;        // Hadamard modes (increments follow any swap)
+    int64_t M = 1, N = 1, K = 1, H = 1;
     bool aFastK = false, bFastK = false;
     int boxX = 0;                // B loader box width (0: none)
 };
@@ -52,6 +75,10 @@ Canon canonicalise(const Args &a, int order, int bn);
 // Offsets of a group for tensor slot s (0: i0, 1: i1), padded with zeros to
 // `padded` entries; first mode fastest.
 void group_offsets(const std::vector<GMode> &g, int slot, int64_t padded, int64_t *out);
+
+// Offsets of the Hadamard group in A, B and C (H entries each, first mode
+// fastest) into outA/outB/outC.
+void hadamard_offsets(const std::vector<HMode> &h, int64_t *outA, int64_t *outB, int64_t *outC);
 
 // Smallest and largest entry of a group's offset table for slot s (padding
 // zeros included): every coordinate combination occurs, so each mode

@@ -35,27 +35,37 @@ namespace gett {
 typedef double d4_t __attribute__((ext_vector_type(4)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+typedef double d2_t __attribute__((ext_vector_type(2)));
+typedef float f2_t __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 __device__ __forceinline__ int wave_id() {
     return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 }
 
+// T: an element of the data; R: its real type (the MFMA operand type);
+// complex elements are (re, im) pairs.
 template <int PREC> struct PrecT;
-template <> struct PrecT<kF64> { using T = double; using Acc = d4_t; };
-template <> struct PrecT<kF32> { using T = float; using Acc = f4_t; };
-template <> struct PrecT<kBF3> { using T = float; using Acc = f4_t; };
+template <> struct PrecT<kF64> { using T = double; using R = double; using Acc = d4_t; };
+template <> struct PrecT<kF32> { using T = float; using R = float; using Acc = f4_t; };
+template <> struct PrecT<kBF3> { using T = float; using R = float; using Acc = f4_t; };
+template <> struct PrecT<kZ64> { using T = d2_t; using R = double; using Acc = d4_t; };
+template <> struct PrecT<kC32> { using T = f2_t; using R = float; using Acc = f4_t; };
 
 // Shared-memory layout of one operand tile (ROWS free positions x BK).
 //   FP64/FP32: [BK][ROWS + 1]  (k-major; a 16x4 MFMA operand is 16 neighbours
 //              in one k row; the +1 keeps column writes off one bank)
+//   complex:   real and imaginary planes, each [BK][ROWS + 1]
 //   BF16x3:    hi and lo planes, each [ROWS][BK + 8] bfloat16 (k contiguous;
 //              one 16-byte read gives a lane its 8 k values)
 template <int PREC, int ROWS, int BK> struct OpLds {
     static constexpr bool kSplit = PREC == kBF3;
+    static constexpr bool kCplx = prec_complex(PREC);
     static constexpr int kLd = kSplit ? BK + 8 : ROWS + 1;
-    static constexpr int kElems = kSplit ? 2 * ROWS * kLd : BK * kLd;
-    static constexpr int kBytes = kSplit ? kElems * 2 : kElems * (PREC == kF64 ? 8 : 4);
+    static constexpr int kPlane = BK * kLd;            // elements of one plane (plain values)
+    static constexpr int kElems = kSplit ? 2 * ROWS * kLd : (kCplx ? 2 : 1) * kPlane;
+    static constexpr int kBytes =
+        kSplit ? kElems * 2 : kElems * ((PREC == kF64 || PREC == kZ64) ? 8 : 4);
 };
 
 // Zeros read in place of masked-off elements (contracted positions of a
@@ -122,7 +132,9 @@ __device__ __forceinline__ void bf16x3_split_pair(float x0, float x1, uint32_t &
 // the free axis holds a contiguous run of columns and writes 16-byte chunks.
 template <int PREC, int ROWS, int BK, bool FASTK, bool O32 = false> struct Gather {
     using T = typename PrecT<PREC>::T;
+    using R = typename PrecT<PREC>::R;
     static constexpr bool kSplit = PREC == kBF3;
+    static constexpr bool kCplx = prec_complex(PREC);
     static constexpr int PER = ROWS * BK / kThreads;   // values per thread
     static constexpr int KP = (kSplit && FASTK) ? 2 : 1;   // positions per row (FASTK)
     static constexpr int KL = BK / KP;                 // lanes along K per row (FASTK)
@@ -142,7 +154,7 @@ template <int PREC, int ROWS, int BK, bool FASTK, bool O32 = false> struct Gathe
     // a wave-uniform 64-bit base and a 32-bit byte offset per lane, so a
     // value costs one 32-bit add (lanes along K) or none (lanes along the
     // free axis, whose contracted offset joins the uniform base).
-    static_assert(!O32 || !kSplit, "32-bit addressing is for plain values");
+    static_assert(!O32 || (!kSplit && !kCplx), "32-bit addressing is for plain real values");
 
     const T *base[NF];  // X + free offset of each row this thread reads
     int row[NF];        // tile row of each free offset
@@ -352,6 +364,15 @@ template <int PREC, int ROWS, int BK, bool FASTK, bool O32 = false> struct Gathe
                     *reinterpret_cast<uint4 *>(lo + w0 + 4 * c) = l;
                 }
             }
+        } else if constexpr (kCplx) {
+            R *s = reinterpret_cast<R *>(lds);
+#pragma unroll
+            for (int i = 0; i < PER; ++i) {
+                const int r = FASTK ? row[i] : row[0];
+                const int j = FASTK ? j0 : col(i);
+                s[j * L::kLd + r] = v[i].x;
+                s[L::kPlane + j * L::kLd + r] = v[i].y;
+            }
         } else {
             T *s = reinterpret_cast<T *>(lds);
 #pragma unroll
@@ -409,15 +430,22 @@ __device__ __forceinline__ void mma_stage(typename PrecT<PREC>::Acc (&acc)[BM / 
     }
 }
 
-// One BM x BN tile over contracted range [kbeg, kend).
+// One BM x BN tile over contracted range [kbeg, kend), reading A and B from
+// pA and pB and updating C at pC (the call's pointers, moved to a Hadamard
+// position when there is one); `slice` numbers the tile's FP64 partial-sum
+// slab when K is split.
 template <int PREC, int BM, int BN, int BK, bool AFK, bool BFK, bool O32 = false>
-__device__ __forceinline__ void gett_tile(const TileParams &p, int64_t m0, int64_t n0, int64_t kbeg,
+__device__ __forceinline__ void gett_tile(const TileParams &p, const void *pA, const void *pB,
+                                          void *pC, int64_t m0, int64_t n0, int64_t kbeg,
                                           int64_t kend, int split, unsigned char *smem) {
     using Cfg = TileCfg<PREC, BM, BN, BK>;
     using T = typename PrecT<PREC>::T;
+    using R = typename PrecT<PREC>::R;
     using Acc = typename PrecT<PREC>::Acc;
     constexpr int FM = Cfg::FM, FN = Cfg::FN;
     constexpr bool kSplit = PREC == kBF3;
+    constexpr bool kCplx = prec_complex(PREC);
+    constexpr bool kTwoAcc = kSplit || kCplx;   // BF16x3: hi*hi | cross terms; complex: re | im
 
     const int t = threadIdx.x;
     const int lane = lane_id();
@@ -426,8 +454,8 @@ __device__ __forceinline__ void gett_tile(const TileParams &p, int64_t m0, int64
 
     Gather<PREC, BM, BK, AFK, O32> ga;
     Gather<PREC, BN, BK, BFK, O32> gb;
-    const T *__restrict__ A = static_cast<const T *>(p.A);
-    const T *__restrict__ B = static_cast<const T *>(p.B);
+    const T *__restrict__ A = static_cast<const T *>(pA);
+    const T *__restrict__ B = static_cast<const T *>(pB);
 #ifdef GETT_ADDR_CHECK
     ga.init(A, t, m0, p.M, p.offAM, BM, p.aLo, p.aSpan);
     gb.init(B, t, n0, p.N, p.offBN, p.bBoxX, p.bLo, p.bSpan);
@@ -437,13 +465,13 @@ __device__ __forceinline__ void gett_tile(const TileParams &p, int64_t m0, int64
 #endif
 
     Acc acc[FM][FN];
-    Acc acx[kSplit ? FM : 1][kSplit ? FN : 1];
+    Acc acx[kTwoAcc ? FM : 1][kTwoAcc ? FN : 1];
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int j = 0; j < FN; ++j) {
             acc[i][j] = Acc{};
-            if constexpr (kSplit) acx[i][j] = Acc{};
+            if constexpr (kTwoAcc) acx[i][j] = Acc{};
         }
 
     T va[Gather<PREC, BM, BK, AFK, O32>::PER];
@@ -462,7 +490,8 @@ __device__ __forceinline__ void gett_tile(const TileParams &p, int64_t m0, int64
     // slice.  The values are never used.  A loop without branches lets the
     // accumulators live in the MFMA registers throughout.
     constexpr int DEPTH = tile_depth(PREC, BM, BN, BK);
-    static_assert(DEPTH == 1 || (DEPTH == 2 && !kSplit), "load depth (BF16x3 tiles use 1)");
+    static_assert(DEPTH == 1 || (DEPTH == 2 && !kTwoAcc),
+                  "load depth (BF16x3 and complex tiles use 1)");
     int64_t nsteps = (kend - kbeg + BK - 1) / BK;
     if constexpr (DEPTH == 2) nsteps += nsteps & 1;   // pairs of steps (one may be all zeros)
     const int64_t kfirst = kend - nsteps * BK;       // may lie below kbeg (and below 0)
@@ -489,7 +518,47 @@ __device__ __forceinline__ void gett_tile(const TileParams &p, int64_t m0, int64
             ga.load_koffs(p.offAK, k1 + BK);
             gb.load_koffs(p.offBK, k1 + BK);
             if constexpr (O32 || tile_load_fence(PREC, BM, BN, BK)) __builtin_amdgcn_sched_barrier(0);
-            if constexpr (!kSplit) {
+            if constexpr (kCplx) {
+                // (ar + i ai)(br + i bi): re += ar br - ai bi, im += ar bi + ai br,
+                // four real MFMAs per fragment and k step.
+                const R *sa = reinterpret_cast<const R *>(stageA(cur));
+                const R *sb = reinterpret_cast<const R *>(stageB(cur));
+#pragma unroll
+                for (int ks = 0; ks < BK / 4; ++ks) {
+                    const int kr = ks * 4 + (lane >> 4);
+                    R ar[FM], ai[FM], br[FN], bi[FN];
+#pragma unroll
+                    for (int i = 0; i < FM; ++i) {
+                        const int o = kr * Cfg::LA::kLd + wm * Cfg::WTM + i * 16 + (lane & 15);
+                        ar[i] = sa[o];
+                        ai[i] = sa[Cfg::LA::kPlane + o];
+                    }
+#pragma unroll
+                    for (int j = 0; j < FN; ++j) {
+                        const int o = kr * Cfg::LB::kLd + wn * Cfg::WTN + j * 16 + (lane & 15);
+                        br[j] = sb[o];
+                        bi[j] = sb[Cfg::LB::kPlane + o];
+                    }
+#pragma unroll
+                    for (int i = 0; i < FM; ++i) {
+                        const R nai = -ai[i];
+#pragma unroll
+                        for (int j = 0; j < FN; ++j) {
+                            if constexpr (PREC == kZ64) {
+                                acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], acc[i][j], 0, 0, 0);
+                                acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(nai, bi[j], acc[i][j], 0, 0, 0);
+                                acx[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bi[j], acx[i][j], 0, 0, 0);
+                                acx[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br[j], acx[i][j], 0, 0, 0);
+                            } else {
+                                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[i], br[j], acc[i][j], 0, 0, 0);
+                                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(nai, bi[j], acc[i][j], 0, 0, 0);
+                                acx[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[i], bi[j], acx[i][j], 0, 0, 0);
+                                acx[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[i], br[j], acx[i][j], 0, 0, 0);
+                            }
+                        }
+                    }
+                }
+            } else if constexpr (!kSplit) {
                 const T *sa = reinterpret_cast<const T *>(stageA(cur));
                 const T *sb = reinterpret_cast<const T *>(stageB(cur));
 #pragma unroll
@@ -618,7 +687,9 @@ __device__ __forceinline__ void gett_tile(const TileParams &p, int64_t m0, int64
     // Epilogue.  Fragment (i, j), register v of lane l holds D[row][l%16]
     // (row = M position, column = N position) with row = 4*(l/16) + v for
     // the FP32 and BF16 MFMA but row = l/16 + 4*v for the FP64 MFMA.
-    T *__restrict__ Cp = static_cast<T *>(p.C);
+    // C <- alpha * sum + beta * C_in; C_in is not read when beta is zero.
+    T *__restrict__ Cp = static_cast<T *>(pC);
+    const bool rdC = p.beta[0] != 0.0 || p.beta[1] != 0.0;
 #pragma unroll
     for (int j = 0; j < FN; ++j) {
         const int64_t n = n0 + wn * Cfg::WTN + j * 16 + (lane & 15);
@@ -628,24 +699,45 @@ __device__ __forceinline__ void gett_tile(const TileParams &p, int64_t m0, int64
         for (int i = 0; i < FM; ++i) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int rr = PREC == kF64 ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v;
+                constexpr bool kF64Layout = PREC == kF64 || PREC == kZ64;
+                const int rr = kF64Layout ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v;
                 const int64_t m = m0 + wm * Cfg::WTM + i * 16 + rr;
                 if (!(nok && m < p.M)) continue;
                 if (p.ws) {
-                    double part;
-                    if constexpr (kSplit) part = (double)acc[i][j][v] + (double)acx[i][j][v];
-                    else part = (double)acc[i][j][v];
-                    p.ws[((int64_t)split * p.M + m) * p.N + n] = part;
+                    const int64_t w = ((int64_t)split * p.M + m) * p.N + n;
+                    if constexpr (kCplx) {
+                        p.ws[2 * w] = (double)acc[i][j][v];
+                        p.ws[2 * w + 1] = (double)acx[i][j][v];
+                    } else if constexpr (kSplit) {
+                        p.ws[w] = (double)acc[i][j][v] + (double)acx[i][j][v];
+                    } else {
+                        p.ws[w] = (double)acc[i][j][v];
+                    }
                 } else {
                     const int64_t off = p.offCM[m] + ocn;
                     GETT_CHECK_C(off, p);
                     if constexpr (PREC == kF64) {
-                        Cp[off] = Cp[off] + acc[i][j][v];
+                        const double r = acc[i][j][v];
+                        Cp[off] = rdC ? p.beta[0] * Cp[off] + p.alpha[0] * r : p.alpha[0] * r;
                     } else if constexpr (PREC == kF32) {
-                        Cp[off] = Cp[off] + acc[i][j][v];
+                        const float r = acc[i][j][v];
+                        const float al = (float)p.alpha[0], be = (float)p.beta[0];
+                        Cp[off] = rdC ? be * Cp[off] + al * r : al * r;
+                    } else if constexpr (PREC == kBF3) {
+                        const double sum = (double)acc[i][j][v] + (double)acx[i][j][v];
+                        Cp[off] = (float)(rdC ? p.alpha[0] * sum + p.beta[0] * (double)Cp[off]
+                                              : p.alpha[0] * sum);
                     } else {
-                        const double sum = (double)acc[i][j][v] + (double)acx[i][j][v] + (double)Cp[off];
-                        Cp[off] = (float)sum;
+                        const R xr = acc[i][j][v], xi = acx[i][j][v];
+                        const R ar = (R)p.alpha[0], ai = (R)p.alpha[1];
+                        R outr = ar * xr - ai * xi, outi = ar * xi + ai * xr;
+                        if (rdC) {
+                            const T c = Cp[off];
+                            const R br = (R)p.beta[0], bi = (R)p.beta[1];
+                            outr += br * c.x - bi * c.y;
+                            outi += br * c.y + bi * c.x;
+                        }
+                        Cp[off] = T{outr, outi};
                     }
                 }
             }
@@ -656,33 +748,83 @@ __device__ __forceinline__ void gett_tile(const TileParams &p, int64_t m0, int64
 template <int PREC, int BM, int BN, int BK, bool AFK, bool BFK, bool O32>
 __global__ __launch_bounds__(kThreads) void gett_tile_kernel(TileParams p) {
     extern __shared__ __align__(16) unsigned char smem[];
+    using T = typename PrecT<PREC>::T;
     const int tiles = p.tilesM * p.tilesN;
-    const int total = tiles * p.splits;
+    const int perH = tiles * p.splits;
+    const int total = perH * p.H;
     const int logical = xcd_remap(blockIdx.x, total);
-    const int split = logical / tiles;
+    // Hadamard position h (every tile and K slice runs once per position):
+    // A, B and C move to that position's base offsets.
+    const int h = logical / perH;
+    const int rest = logical - h * perH;
+    const int split = rest / tiles;
     int tm, tn;
-    tile_coords(logical - split * tiles, p.tilesM, p.tilesN, tm, tn);
+    tile_coords(rest - split * tiles, p.tilesM, p.tilesN, tm, tn);
     const int64_t kbeg = (int64_t)split * p.kPerSplit;
     int64_t kend = kbeg + p.kPerSplit;
     if (kend > p.K) kend = p.K;
-    gett_tile<PREC, BM, BN, BK, AFK, BFK, O32>(p, (int64_t)tm * BM, (int64_t)tn * BN, kbeg, kend,
-                                               split, smem);
+    const T *A = static_cast<const T *>(p.A);
+    const T *B = static_cast<const T *>(p.B);
+    T *C = static_cast<T *>(p.C);
+    if (p.H > 1) {
+        A += p.offAH[h];
+        B += p.offBH[h];
+        C += p.offCH[h];
+    }
+    gett_tile<PREC, BM, BN, BK, AFK, BFK, O32>(p, A, B, C, (int64_t)tm * BM, (int64_t)tn * BN,
+                                               kbeg, kend, h * p.splits + split, smem);
 }
 
-// C[off(m,n)] = C_in + sum_s ws[s][m][n], in FP64, s in order.
+// C[off(m,n)] from the FP64 partials ws[h][s][m][n] of the K slices s, in
+// slice order: C_in + p_0 + p_1 + ... (the paper's accumulate) when alpha =
+// beta = 1, otherwise alpha * (p_0 + p_1 + ...) + beta * C_in (C_in not read
+// when beta = 0); complex partials are (re, im) pairs.
 template <int PREC>
 __global__ __launch_bounds__(256) void splitk_reduce_kernel(TileParams p) {
     using T = typename PrecT<PREC>::T;
+    using R = typename PrecT<PREC>::R;
     const int64_t MN = p.M * p.N;
+    const int64_t total = MN * p.H;
     T *Cp = static_cast<T *>(p.C);
-    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < MN;
+    const bool plain = p.alpha[0] == 1.0 && p.alpha[1] == 0.0 && p.beta[0] == 1.0 &&
+                       p.beta[1] == 0.0;
+    const bool rdC = p.beta[0] != 0.0 || p.beta[1] != 0.0;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
          idx += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t m = idx / p.N, n = idx - m * p.N;
+        const int64_t h = idx / MN, r = idx - h * MN;
+        const int64_t m = r / p.N, n = r - m * p.N;
         const int64_t off = p.offCM[m] + p.offCN[n];
         GETT_CHECK_C(off, p);
-        double s = (double)Cp[off];
-        for (int z = 0; z < p.splits; ++z) s += p.ws[(int64_t)z * MN + idx];
-        Cp[off] = (T)s;
+        const int64_t hoff = p.H > 1 ? p.offCH[h] : 0;
+        const double *ws = p.ws + (prec_complex(PREC) ? 2 : 1) * (h * p.splits * MN + r);
+        if constexpr (prec_complex(PREC)) {
+            double sr = 0.0, si = 0.0;
+            if (plain) {
+                sr = (double)Cp[hoff + off].x;
+                si = (double)Cp[hoff + off].y;
+            }
+            for (int z = 0; z < p.splits; ++z) {
+                sr += ws[2 * (int64_t)z * MN];
+                si += ws[2 * (int64_t)z * MN + 1];
+            }
+            if (!plain) {
+                double outr = p.alpha[0] * sr - p.alpha[1] * si;
+                double outi = p.alpha[0] * si + p.alpha[1] * sr;
+                if (rdC) {
+                    const double cr = (double)Cp[hoff + off].x, ci = (double)Cp[hoff + off].y;
+                    outr += p.beta[0] * cr - p.beta[1] * ci;
+                    outi += p.beta[0] * ci + p.beta[1] * cr;
+                }
+                sr = outr;
+                si = outi;
+            }
+            Cp[hoff + off] = T{(R)sr, (R)si};
+        } else {
+            double s = plain ? (double)Cp[hoff + off] : 0.0;
+            for (int z = 0; z < p.splits; ++z) s += ws[(int64_t)z * MN];
+            if (!plain) s = rdC ? p.alpha[0] * s + p.beta[0] * (double)Cp[hoff + off] : p.alpha[0] * s;
+            Cp[hoff + off] = (T)s;
+        }
     }
 }
 
@@ -724,13 +866,13 @@ __global__ __launch_bounds__(kThreads) void gett_batch_kernel(const BatchProblem
         const int64_t kend = min(p.K, kbeg + p.kPerSplit);
         const int variant = bp.aFastK * 2 + bp.bFastK;
         if (variant == 0)
-            gett_tile<PREC, ts.bm, ts.bn, ts.bk, false, false>(p, m0, n0, kbeg, kend, split, smem);
+            gett_tile<PREC, ts.bm, ts.bn, ts.bk, false, false>(p, p.A, p.B, p.C, m0, n0, kbeg, kend, split, smem);
         else if (variant == 1)
-            gett_tile<PREC, ts.bm, ts.bn, ts.bk, false, true>(p, m0, n0, kbeg, kend, split, smem);
+            gett_tile<PREC, ts.bm, ts.bn, ts.bk, false, true>(p, p.A, p.B, p.C, m0, n0, kbeg, kend, split, smem);
         else if (variant == 2)
-            gett_tile<PREC, ts.bm, ts.bn, ts.bk, true, false>(p, m0, n0, kbeg, kend, split, smem);
+            gett_tile<PREC, ts.bm, ts.bn, ts.bk, true, false>(p, p.A, p.B, p.C, m0, n0, kbeg, kend, split, smem);
         else
-            gett_tile<PREC, ts.bm, ts.bn, ts.bk, true, true>(p, m0, n0, kbeg, kend, split, smem);
+            gett_tile<PREC, ts.bm, ts.bn, ts.bk, true, true>(p, p.A, p.B, p.C, m0, n0, kbeg, kend, split, smem);
         __syncthreads();   // the next item reuses the LDS stages and s_item
     }
 }
@@ -772,7 +914,7 @@ static int launch_one(const TileParams &p, hipStream_t s) {
             return GETT_ERR_HIP;
         attr_set = true;
     }
-    const int total = p.tilesM * p.tilesN * p.splits;
+    const int total = p.tilesM * p.tilesN * p.splits * p.H;
     (void)hipGetLastError();   // clear a stale error left by other HIP users
     hipLaunchKernelGGL(kern, dim3(total), dim3(kThreads), Cfg::kLdsBytes, s, p);
     return launch_status();
@@ -817,7 +959,7 @@ template <int PREC> static int batch_lds() {
 }
 
 template <int PREC> static int launch_splitk_reduce_prec(const TileParams &p, hipStream_t s) {
-    const int64_t MN = p.M * p.N;
+    const int64_t MN = p.M * p.N * p.H;
     int64_t blocks = (MN + 255) / 256;
     if (blocks > 65536) blocks = 65536;
     if (blocks < 1) blocks = 1;
@@ -891,6 +1033,16 @@ static int64_t addr_violations_here(bool reset) {
     int launch_batch_reduce_##SUFFIX(const BatchProblem *d, const int32_t *l, int32_t n,           \
                                      hipStream_t s) {                                              \
         return launch_batch_reduce_prec<PREC>(d, l, n, s);                                         \
+    }                                                                                              \
+    int64_t addr_violations_##SUFFIX(bool reset) { return addr_violations_here(reset); }
+
+// The same for precisions without a batched entry point (complex data).
+#define GETT_DEFINE_TILE_PRECISION(PREC, SUFFIX)                                                   \
+    int launch_tile_##SUFFIX(int tile, bool afk, bool bfk, const TileParams &p, hipStream_t s) {   \
+        return launch_prec<PREC>(tile, afk, bfk, p, s);                                            \
+    }                                                                                              \
+    int launch_splitk_reduce_##SUFFIX(const TileParams &p, hipStream_t s) {                       \
+        return launch_splitk_reduce_prec<PREC>(p, s);                                              \
     }                                                                                              \
     int64_t addr_violations_##SUFFIX(bool reset) { return addr_violations_here(reset); }
 

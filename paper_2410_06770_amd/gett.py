@@ -19,7 +19,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("GETT_LIB") or os.path.join(_HERE, "libgett.so")
 
-GETT_FP64, GETT_FP32, GETT_BF16X3, GETT_FP8 = 0, 1, 2, 3
+GETT_FP64, GETT_FP32, GETT_BF16X3, GETT_FP8, GETT_Z64, GETT_C32 = 0, 1, 2, 3, 4, 5
 GETT_HEURISTIC, GETT_PREDICT, GETT_AUTOTUNE = 0, 1, 2
 # positive runtime codes (negative codes are INFO = -i for argument i)
 GETT_ERR_HIP, GETT_ERR_ALLOC, GETT_ERR_DEVICE, GETT_ERR_INTERNAL, GETT_ERR_STATE = 1, 2, 3, 4, 5
@@ -61,8 +61,18 @@ def lib():
         pass
     L = ct.CDLL(LIB_PATH)
     a14 = [i64, I64P, I64P, vp, i64, I64P, I64P, vp, i64, I64P, I64P, I64P, I64P, vp]
-    for name in ("dgett", "sgett", "sgett_bf16x3", "sgett_fp8", "dgett_noalloc"):
+    for name in ("dgett", "sgett", "sgett_bf16x3", "sgett_fp8", "dgett_noalloc", "zgett",
+                 "cgett"):
         getattr(L, name).argtypes = a14
+        getattr(L, name).restype = ct.c_int
+    ex17 = [i64, I64P, I64P, vp, i64, I64P, I64P, vp, i64, I64P, I64P, i64, I64P, I64P, I64P,
+            I64P]
+    L.dgett_ex.argtypes = [ct.c_double] + ex17 + [ct.c_double, vp]
+    L.sgett_ex.argtypes = [ct.c_float] + ex17 + [ct.c_float, vp]
+    L.sgett_bf16x3_ex.argtypes = [ct.c_float] + ex17 + [ct.c_float, vp]
+    L.zgett_ex.argtypes = [vp] + ex17 + [vp, vp]
+    L.cgett_ex.argtypes = [vp] + ex17 + [vp, vp]
+    for name in ("dgett_ex", "sgett_ex", "sgett_bf16x3_ex", "zgett_ex", "cgett_ex"):
         getattr(L, name).restype = ct.c_int
     L.sgett_fp8_quantize.argtypes = [i64, I64P, I64P, vp, i64, I64P, vp, vp]
     L.sgett_fp8_quantize.restype = ct.c_int
@@ -157,7 +167,74 @@ def dgett_noalloc(ranka, exta, inca, A, rankb, extb, incb, B, conts, conta, cont
                    contb, perm, incc, C)
 
 
-ENTRY = {GETT_FP64: dgett, GETT_FP32: sgett, GETT_BF16X3: sgett_bf16x3, GETT_FP8: sgett_fp8}
+def zgett(ranka, exta, inca, A, rankb, extb, incb, B, conts, conta, contb, perm, incc, C) -> int:
+    """Complex FP64: A, B, C address interleaved (re, im) doubles."""
+    return _call14("zgett", ranka, exta, inca, A, rankb, extb, incb, B, conts, conta, contb,
+                   perm, incc, C)
+
+
+def cgett(ranka, exta, inca, A, rankb, extb, incb, B, conts, conta, contb, perm, incc, C) -> int:
+    """Complex FP32: A, B, C address interleaved (re, im) floats."""
+    return _call14("cgett", ranka, exta, inca, A, rankb, extb, incb, B, conts, conta, contb,
+                   perm, incc, C)
+
+
+def _ex_args(ranka, exta, inca, A, rankb, extb, incb, B, conts, conta, contb, hads, hada, hadb,
+             perm, incc):
+    return (int(ranka), _arr(exta), _arr(inca), vp(A) if A else None, int(rankb), _arr(extb),
+            _arr(incb), vp(B) if B else None, int(conts), _arr(conta), _arr(contb), int(hads),
+            _arr(hada), _arr(hadb), _arr(perm), _arr(incc))
+
+
+def dgett_ex(alpha, ranka, exta, inca, A, rankb, extb, incb, B, conts, conta, contb, hads, hada,
+             hadb, perm, incc, beta, C) -> int:
+    return lib().dgett_ex(float(alpha), *_ex_args(ranka, exta, inca, A, rankb, extb, incb, B,
+                                                  conts, conta, contb, hads, hada, hadb, perm,
+                                                  incc), float(beta), vp(C) if C else None)
+
+
+def sgett_ex(alpha, ranka, exta, inca, A, rankb, extb, incb, B, conts, conta, contb, hads, hada,
+             hadb, perm, incc, beta, C) -> int:
+    return lib().sgett_ex(float(alpha), *_ex_args(ranka, exta, inca, A, rankb, extb, incb, B,
+                                                  conts, conta, contb, hads, hada, hadb, perm,
+                                                  incc), float(beta), vp(C) if C else None)
+
+
+def sgett_bf16x3_ex(alpha, ranka, exta, inca, A, rankb, extb, incb, B, conts, conta, contb, hads,
+                    hada, hadb, perm, incc, beta, C) -> int:
+    return lib().sgett_bf16x3_ex(float(alpha), *_ex_args(ranka, exta, inca, A, rankb, extb, incb,
+                                                         B, conts, conta, contb, hads, hada,
+                                                         hadb, perm, incc), float(beta),
+                                 vp(C) if C else None)
+
+
+def _cpair(x, ctype):
+    if x is None:
+        return None
+    z = complex(x)
+    return ct.cast((ctype * 2)(z.real, z.imag), vp)
+
+
+def zgett_ex(alpha, ranka, exta, inca, A, rankb, extb, incb, B, conts, conta, contb, hads, hada,
+             hadb, perm, incc, beta, C) -> int:
+    """alpha, beta: Python complex numbers (None passes a NULL pointer)."""
+    return lib().zgett_ex(_cpair(alpha, ct.c_double), *_ex_args(
+        ranka, exta, inca, A, rankb, extb, incb, B, conts, conta, contb, hads, hada, hadb, perm,
+        incc), _cpair(beta, ct.c_double), vp(C) if C else None)
+
+
+def cgett_ex(alpha, ranka, exta, inca, A, rankb, extb, incb, B, conts, conta, contb, hads, hada,
+             hadb, perm, incc, beta, C) -> int:
+    return lib().cgett_ex(_cpair(alpha, ct.c_float), *_ex_args(
+        ranka, exta, inca, A, rankb, extb, incb, B, conts, conta, contb, hads, hada, hadb, perm,
+        incc), _cpair(beta, ct.c_float), vp(C) if C else None)
+
+
+EX_ENTRY = {GETT_FP64: dgett_ex, GETT_FP32: sgett_ex, GETT_BF16X3: sgett_bf16x3_ex,
+            GETT_Z64: zgett_ex, GETT_C32: cgett_ex}
+
+ENTRY = {GETT_FP64: dgett, GETT_FP32: sgett, GETT_BF16X3: sgett_bf16x3, GETT_FP8: sgett_fp8,
+         GETT_Z64: zgett, GETT_C32: cgett}
 
 
 def sgett_fp8_quantize(rankx, extx, incx, X, conts, contx, QX, EX) -> int:

@@ -247,6 +247,37 @@ def build_problem(rng, sig, dtype=np.float64, layout_a="packed", layout_b="packe
     return pr.with_views(A, B, C)
 
 
+def hadamard_problem(rng, dtype, hads, dist="int", ranks=(1, 4), ext=(1, 4), conts=(0, 3),
+                     layouts=("sub", "neg", "sub")):
+    """A random contraction with ``hads`` Hadamard pairs (a mode of A and a
+    mode of B, neither contracted, that C carries too).  PERM and C cover
+    A's free modes, B's free modes, then the pairs.  Returns (Problem, hada,
+    hadb)."""
+    while True:
+        sig = random_signature(rng, ranks, ranks, ext, conts)
+        ra, exta, rb, extb, cs, conta, contb, _ = sig
+        fa = [i for i in range(ra) if i not in conta]
+        fb = [j for j in range(rb) if j not in contb]
+        if len(fa) >= hads and len(fb) >= hads:
+            break
+    hada = [int(x) for x in rng.choice(fa, size=hads, replace=False)]
+    hadb = [int(x) for x in rng.choice(fb, size=hads, replace=False)]
+    for a, b in zip(hada, hadb):
+        extb[b] = exta[a]
+    A = make_view(exta, rng, dtype, layouts[0], dist=dist)
+    B = make_view(extb, rng, dtype, layouts[1], dist=dist)
+    rc = ra + rb - 2 * cs - hads
+    perm = rng.permutation(rc).tolist()
+    free = [exta[i] for i in fa if i not in hada] + [extb[j] for j in fb if j not in hadb] + \
+        [exta[i] for i in hada]
+    extc = [0] * rc
+    for p, q in enumerate(perm):
+        extc[q] = free[p]
+    C = make_view(extc, rng, dtype, layouts[2], dist=dist, fill=SENTINEL)
+    pr = Problem(ra, exta, A.inc, rb, extb, B.inc, cs, conta, contb, perm, C.inc, A, B, C)
+    return pr, hada, hadb
+
+
 # The paper's test families (Section 7).  Each returns a Problem.
 def paper_case(name: str, rng, dtype=np.float64, dist="uniform") -> Problem:
     R15 = (1, 5)

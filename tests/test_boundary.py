@@ -171,3 +171,46 @@ def test_noalloc_rejects_oversized_tables_before_any_hip_call():
                             [1, 5_000_000], 8)
     assert rc == gett.GETT_ERR_SCRATCH
     assert "scratch" in gett.strerror(rc)
+
+
+EX_OK = dict(alpha=1.0, ranka=3, exta=[3, 4, 5], inca=[1, 3, 12], rankb=3, extb=[4, 5, 6],
+             incb=[1, 4, 20], conts=1, conta=[1], contb=[0], hads=1, hada=[2], hadb=[1],
+             perm=[2, 0, 1], incc=[1, 3, 18], beta=0.5)
+
+
+def call_ex(fn, A=8, B=8, C=8, **kw):
+    d = dict(EX_OK)
+    d.update(kw)
+    return fn(d["alpha"], d["ranka"], d["exta"], d["inca"], A, d["rankb"], d["extb"], d["incb"],
+              B, d["conts"], d["conta"], d["contb"], d["hads"], d["hada"], d["hadb"], d["perm"],
+              d["incc"], d["beta"], C)
+
+
+# INFO of the scaled calls is numbered in their own argument order:
+# ALPHA, RANKA .. CONTB (-2..-12), HADS -13, HADA -14, HADB -15, PERM -16,
+# INCC -17, BETA -18, C -19.
+EX_BAD = [(-2, dict(ranka=-1)), (-3, dict(exta=[3, -1, 5])), (-5, dict(A=0)),
+          (-9, dict(B=0)), (-10, dict(conts=4)), (-11, dict(conta=[7])),
+          (-12, dict(contb=[3])), (-13, dict(hads=-1)), (-13, dict(hads=3)),
+          (-14, dict(hada=[1])), (-14, dict(hada=[9])), (-15, dict(hadb=[0])),
+          (-15, dict(hadb=[2])), (-16, dict(perm=[0, 0, 1])), (-17, dict(incc=[0, 3, 18])),
+          (-19, dict(C=0))]
+
+
+@pytest.mark.parametrize("code,kw", EX_BAD)
+@pytest.mark.parametrize("fn", ["dgett_ex", "sgett_ex", "sgett_bf16x3_ex", "zgett_ex",
+                                "cgett_ex"])
+def test_scaled_call_info_codes(fn, code, kw):
+    assert call_ex(getattr(gett, fn), **kw) == code
+
+
+def test_complex_scaled_calls_need_alpha_and_beta():
+    assert call_ex(gett.zgett_ex, alpha=None) == -1
+    assert call_ex(gett.cgett_ex, beta=None) == -18
+
+
+def test_valid_scaled_calls_pass_the_checks():
+    """Valid arguments get past every check: without a GPU the first HIP
+    call fails with a runtime code (> 0), never an INFO."""
+    for fn in ("dgett_ex", "sgett_ex", "sgett_bf16x3_ex", "zgett_ex", "cgett_ex"):
+        assert call_ex(getattr(gett, fn)) > 0

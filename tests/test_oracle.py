@@ -572,29 +572,7 @@ def test_complex_vs_einsum():
 def _hadamard_problem(rng, dtype, hads, dist="int"):
     """A random contraction with ``hads`` Hadamard pairs; PERM and C cover
     A's free modes, B's free modes, then the pairs."""
-    while True:
-        sig = W.random_signature(rng, (1, 4), (1, 4), (1, 4), (0, 3))
-        ra, exta, rb, extb, cs, conta, contb, _ = sig
-        fa = [i for i in range(ra) if i not in conta]
-        fb = [j for j in range(rb) if j not in contb]
-        if len(fa) >= hads and len(fb) >= hads:
-            break
-    hada = [int(x) for x in rng.choice(fa, size=hads, replace=False)]
-    hadb = [int(x) for x in rng.choice(fb, size=hads, replace=False)]
-    for a, b in zip(hada, hadb):
-        extb[b] = exta[a]
-    A = W.make_view(exta, rng, dtype, "sub", dist=dist)
-    B = W.make_view(extb, rng, dtype, "neg", dist=dist)
-    rc = ra + rb - 2 * cs - hads
-    perm = rng.permutation(rc).tolist()
-    free = [exta[i] for i in fa if i not in hada] + [extb[j] for j in fb if j not in hadb] + \
-        [exta[i] for i in hada]
-    extc = [0] * rc
-    for p, q in enumerate(perm):
-        extc[q] = free[p]
-    C = W.make_view(extc, rng, dtype, "sub", dist=dist, fill=W.SENTINEL)
-    pr = W.Problem(ra, exta, A.inc, rb, extb, B.inc, cs, conta, contb, perm, C.inc, A, B, C)
-    return pr, hada, hadb
+    return W.hadamard_problem(rng, dtype, hads, dist)
 
 
 @pytest.mark.parametrize("seed", range(8))
