@@ -89,6 +89,8 @@ def lib():
         L.gett_ref_fp8_scale_exp.restype = ct.c_int
         L.gett_ref_fp8_quantize.argtypes = [vp, i64, vp, i64, vp, vp, vp]
         L.gett_ref_fp8_gemm.argtypes = [i64, i64, i64, vp, vp, vp, vp, vp]
+        L.gett_ref_fp8_quantize_bs.argtypes = [vp, i64, vp, i64, vp, i64, vp, vp]
+        L.gett_ref_fp8_gemm_bs.argtypes = [i64, i64, i64, i64, vp, vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -281,30 +283,39 @@ def canonical_offsets(pr):
     return rowsA, rowsB, kA, kB
 
 
-def fp8_quantize(X, rows_off, k_off):
+def fp8_quantize(X, rows_off, k_off, block=128):
     """Quantise a float32 view (buffer + base) into E4M3 codes with one
-    power-of-two scale per row per 128 contracted positions.  Returns
-    (codes uint8 [rows, Kp], exponents int32 [rows, blocks])."""
+    power-of-two scale per row per ``block`` contracted positions (128, or
+    32 for the MX-style variant).  Returns (codes uint8 [rows, Kp],
+    exponents int32 [rows, Kp / block]) with Kp = 128 * ceil(K / 128)."""
+    assert 128 % block == 0
     rows = len(rows_off)
     K = len(k_off)
-    nb = (K + 127) // 128
-    Q = np.zeros((rows, nb * 128), dtype=np.uint8)
-    E = np.zeros((rows, nb), dtype=np.int32)
+    Kp = (K + 127) // 128 * 128
+    Q = np.zeros((rows, Kp), dtype=np.uint8)
+    E = np.zeros((rows, Kp // block), dtype=np.int32)
     ro = np.ascontiguousarray(rows_off, dtype=np.int64)
     ko = np.ascontiguousarray(k_off, dtype=np.int64)
-    lib().gett_ref_fp8_quantize(_ptr(X.buf, X.base), rows, ro.ctypes.data, K, ko.ctypes.data,
-                                Q.ctypes.data, E.ctypes.data)
+    if block == 128:
+        lib().gett_ref_fp8_quantize(_ptr(X.buf, X.base), rows, ro.ctypes.data, K, ko.ctypes.data,
+                                    Q.ctypes.data, E.ctypes.data)
+    else:
+        lib().gett_ref_fp8_quantize_bs(_ptr(X.buf, X.base), rows, ro.ctypes.data, K,
+                                       ko.ctypes.data, block, Q.ctypes.data, E.ctypes.data)
     return Q, E
 
 
-def fp8_gemm(QA, EA, QB, EB, K):
+def fp8_gemm(QA, EA, QB, EB, K, block=128):
     """Exact double value of the quantised product, out[m, n]."""
     M, N = QA.shape[0], QB.shape[0]
     out = np.zeros((N, M), dtype=np.float64)
-    lib().gett_ref_fp8_gemm(M, N, K, np.ascontiguousarray(QA).ctypes.data,
-                            np.ascontiguousarray(EA).ctypes.data,
-                            np.ascontiguousarray(QB).ctypes.data,
-                            np.ascontiguousarray(EB).ctypes.data, out.ctypes.data)
+    args = (np.ascontiguousarray(QA).ctypes.data, np.ascontiguousarray(EA).ctypes.data,
+            np.ascontiguousarray(QB).ctypes.data, np.ascontiguousarray(EB).ctypes.data,
+            out.ctypes.data)
+    if block == 128:
+        lib().gett_ref_fp8_gemm(M, N, K, *args)
+    else:
+        lib().gett_ref_fp8_gemm_bs(M, N, K, block, *args)
     return out.T
 
 

@@ -761,23 +761,25 @@ int gett_ref_fp8_scale_exp(double amax) {
 
 /* Quantise rows of a (rows x K) operand given as element offsets: row r,
    canonical contracted position k, value X[offR[r] + offK[k]].  Blocks are
-   128 consecutive k; codes go to Q (rows x Kp, row-major, Kp = 128 * blocks,
-   zero codes in the padding) and exponents to E (rows x blocks). */
-void gett_ref_fp8_quantize(const float *X, int64_t rows, const int64_t *offR,
-                           int64_t K, const int64_t *offK, uint8_t *Q, int32_t *E) {
-    int64_t nb = (K + 127) / 128;
-    int64_t Kp = nb * 128;
+   BS consecutive k (BS = 128, or 32 for the MX-style variant; 128 is a
+   multiple of BS); codes go to Q (rows x Kp, row-major, Kp = 128 *
+   ceil(K / 128), zero codes in the padding) and exponents to E (rows x
+   Kp / BS; a block wholly in the padding gets exponent 0). */
+void gett_ref_fp8_quantize_bs(const float *X, int64_t rows, const int64_t *offR, int64_t K,
+                              const int64_t *offK, int64_t bs, uint8_t *Q, int32_t *E) {
+    int64_t Kp = (K + 127) / 128 * 128;
+    int64_t nb = Kp / bs;
 #pragma omp parallel for
     for (int64_t r = 0; r < rows; ++r) {
         for (int64_t b = 0; b < nb; ++b) {
             double amax = 0.0;
-            for (int64_t k = b * 128; k < K && k < b * 128 + 128; ++k) {
+            for (int64_t k = b * bs; k < K && k < b * bs + bs; ++k) {
                 double v = fabs((double)X[offR[r] + offK[k]]);
                 if (v > amax) amax = v;
             }
             int e = gett_ref_fp8_scale_exp(amax);
             E[r * nb + b] = e;
-            for (int64_t k = b * 128; k < b * 128 + 128; ++k) {
+            for (int64_t k = b * bs; k < b * bs + bs; ++k) {
                 uint8_t q = 0;
                 if (k < K) q = gett_ref_e4m3_encode(ldexp((double)X[offR[r] + offK[k]], -e));
                 Q[r * Kp + k] = q;
@@ -786,23 +788,35 @@ void gett_ref_fp8_quantize(const float *X, int64_t rows, const int64_t *offR,
     }
 }
 
+void gett_ref_fp8_quantize(const float *X, int64_t rows, const int64_t *offR,
+                           int64_t K, const int64_t *offK, uint8_t *Q, int32_t *E) {
+    gett_ref_fp8_quantize_bs(X, rows, offR, K, offK, 128, Q, E);
+}
+
 /* Exact value of the quantised product: out[m + M*n] = sum over blocks of
-   2^(EA+EB) * sum_k decode(QA) * decode(QB), all in double. */
-void gett_ref_fp8_gemm(int64_t M, int64_t N, int64_t K, const uint8_t *QA, const int32_t *EA,
-                       const uint8_t *QB, const int32_t *EB, double *out) {
-    int64_t nb = (K + 127) / 128;
-    int64_t Kp = nb * 128;
+   2^(EA+EB) * sum_k decode(QA) * decode(QB) over the block's BS positions,
+   all in double (one block's sum is exact; the sum over blocks rounds only
+   when their exponents lie far apart). */
+void gett_ref_fp8_gemm_bs(int64_t M, int64_t N, int64_t K, int64_t bs, const uint8_t *QA,
+                          const int32_t *EA, const uint8_t *QB, const int32_t *EB, double *out) {
+    int64_t Kp = (K + 127) / 128 * 128;
+    int64_t nb = Kp / bs;
 #pragma omp parallel for
     for (int64_t n = 0; n < N; ++n) {
         for (int64_t m = 0; m < M; ++m) {
             double acc = 0.0;
             for (int64_t b = 0; b < nb; ++b) {
                 double part = 0.0;
-                for (int64_t k = b * 128; k < b * 128 + 128; ++k)
+                for (int64_t k = b * bs; k < b * bs + bs; ++k)
                     part += gett_ref_e4m3_decode(QA[m * Kp + k]) * gett_ref_e4m3_decode(QB[n * Kp + k]);
                 acc += ldexp(part, EA[m * nb + b] + EB[n * nb + b]);
             }
             out[m + M * n] = acc;
         }
     }
+}
+
+void gett_ref_fp8_gemm(int64_t M, int64_t N, int64_t K, const uint8_t *QA, const int32_t *EA,
+                       const uint8_t *QB, const int32_t *EB, double *out) {
+    gett_ref_fp8_gemm_bs(M, N, K, 128, QA, EA, QB, EB, out);
 }

@@ -409,6 +409,59 @@ def test_fp8_model_error_bound():
     assert np.max(np.abs(got - ex) / ab) > 1e-4      # quantisation really happened
 
 
+def test_fp8_per32_blocks_match_torch_casts():
+    """MX-style blocks of 32: each block's exponent follows the scale rule on
+    the block's own largest magnitude, and its codes are torch's
+    float8_e4m3fn cast of the values divided by 2^e (an independent encoder);
+    padding past K holds zero codes and exponent 0."""
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(26)
+    X = W.make_view([7, 200], rng, np.float32, "sub", dist="normal")
+    vals = X.gather().astype(np.float64)
+    vals *= 2.0 ** rng.integers(-20, 20, size=(7, 200))       # every block its own range
+    X.buf[X.element_index()] = vals.reshape(-1, order="F").astype(np.float32)
+    vals = X.gather().astype(np.float64)
+    rows_off = np.arange(7) * X.inc[0]
+    k_off = np.arange(200) * X.inc[1]
+    Q, E = oracle.fp8_quantize(X, rows_off, k_off, block=32)
+    assert Q.shape == (7, 256) and E.shape == (7, 8)
+    for r in range(7):
+        for b in range(8):
+            blk = vals[r, 32 * b: min(200, 32 * b + 32)]
+            amax = float(np.max(np.abs(blk))) if blk.size else 0.0
+            e = oracle.fp8_scale_exp(amax)
+            assert E[r, b] == e
+            if blk.size:
+                t = torch.tensor(blk / 2.0 ** e, dtype=torch.float64).to(torch.float8_e4m3fn)
+                assert np.array_equal(Q[r, 32 * b: 32 * b + blk.size], t.view(torch.uint8).numpy())
+    assert not Q[:, 200:].any() and not E[:, 7:].any()
+
+
+def test_fp8_per32_model_exact_on_scaled_integers():
+    """Integers in [-4, 4] times a power of two per block of 32 (a different
+    range in every block, so every block has its own scale): the per-32
+    quantisation is exact and the model equals the exact contraction bit for
+    bit; the per-128 one loses the small blocks."""
+    rng = np.random.default_rng(27)
+    A = W.make_view([24, 256], rng, np.float32, dist="int")
+    B = W.make_view([256, 20], rng, np.float32, dist="int")
+    sa = 2.0 ** rng.integers(-12, 13, size=(1, 8)).repeat(32, axis=1)   # per 32 positions of K
+    sb = 2.0 ** rng.integers(-12, 13, size=(8, 1)).repeat(32, axis=0)
+    A.buf[A.element_index()] = (A.gather() * sa).reshape(-1, order="F").astype(np.float32)
+    B.buf[B.element_index()] = (B.gather() * sb).reshape(-1, order="F").astype(np.float32)
+    pr = _problem(A, B, 2, 2, [1], [0], [0, 1])
+    rA, rB, kA, kB = oracle.canonical_offsets(pr)
+    QA, EA = oracle.fp8_quantize(A, rA, kA, block=32)
+    QB, EB = oracle.fp8_quantize(B, rB, kB, block=32)
+    got = oracle.fp8_gemm(QA, EA, QB, EB, 256, block=32)
+    ex, _ = oracle.exact(pr, A, B, pr.C)
+    assert np.array_equal(got, view_values(pr.C, ex))
+    QA, EA = oracle.fp8_quantize(A, rA, kA)
+    QB, EB = oracle.fp8_quantize(B, rB, kB)
+    got128 = oracle.fp8_gemm(QA, EA, QB, EB, 256)
+    assert not np.array_equal(got128, view_values(pr.C, ex))
+
+
 def test_bf16_split_matches_torch_and_bounds():
     torch = pytest.importorskip("torch")
     rng = np.random.default_rng(25)
