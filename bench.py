@@ -63,6 +63,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--paths", default="f64,f32,bf16x3,fp8")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-unary", action="store_true",
+                    help="skip the unary (transpose, reduction) legs")
+    ap.add_argument("--no-complex", action="store_true",
+                    help="skip the complex (ZGETT, CGETT) legs")
     ap.add_argument("--no-cc-study", action="store_true",
                     help="skip the precision study legs that follow the strided workload")
     ap.add_argument("--no-check", action="store_true", help="skip the sampled error check")
@@ -133,6 +137,9 @@ def main():
                  "flops_per_call": 2.0 * Mc * Nc * Kc, "paths": study_res}
         del pr_cc
 
+    complex_res = complex_leg(args, gett, W, torch, stream) if not args.no_complex else None
+    unary_res = unary_leg(args, gett, torch, stream) if not args.no_unary else None
+
     batch = batch_leg(args.batch, gett, W, torch, stream) if args.batch > 0 else None
 
     path, ms, tflops, peak, wall = primary
@@ -162,6 +169,10 @@ def main():
         out["context"] = context
     if study is not None:
         out["cc_study"] = study
+    if complex_res is not None:
+        out["complex"] = complex_res
+    if unary_res is not None:
+        out["unary"] = unary_res
     if batch is not None:
         out["batch"] = batch
     if not args.no_cpu_baseline:
@@ -271,11 +282,129 @@ def run_workload(args, workload, paths, gett, W, torch, stream, with_context):
     return results, context, pr64, primary
 
 
+def complex_leg(args, gett, W, torch, stream):
+    """ZGETT and CGETT on the strided + permuted shape with complex data (A
+    read with step 2 from a 2x packed parent; M, N, K = 3072, 4032, 3840).
+    A complex term is four real products and four real additions, so the
+    rate is 8 MNK real flops per call against the FP64 / FP32 matrix peak."""
+    rng = np.random.default_rng(2)
+    out = {}
+    for name, prec, dt, tdt, peak in (("z64", gett.GETT_Z64, np.complex128, torch.complex128,
+                                       PEAK["f64"]),
+                                      ("c32", gett.GETT_C32, np.complex64, torch.complex64,
+                                       PEAK["f32"])):
+        pr = W.config_strided_perm(dtype=dt, reading="ii", with_data=False)
+        A = W.View(np.full(2 * int(np.prod(pr.exta)), np.nan, dtype=dt), 0, pr.exta, pr.inca)
+        idx = A.element_index()
+        A.buf[idx] = (rng.standard_normal(idx.size) + 1j * rng.standard_normal(idx.size)).astype(dt)
+        B = W.make_view(pr.extb, rng, dt, "packed", dist="normal")
+        C = W.make_c(pr.extc(), rng, dt)
+        pr = pr.with_views(A, B, C)
+        M, N, K = pr.mnk()
+        flops = 8.0 * M * N * K
+        At = torch.from_numpy(A.buf).to("cuda")
+        Bt = torch.from_numpy(B.buf).to("cuda")
+        Ct = torch.zeros(C.buf.shape, dtype=tdt, device="cuda")
+
+        def call():
+            rc = gett.ENTRY[prec](pr.ranka, pr.exta, pr.inca, At.data_ptr(), pr.rankb, pr.extb,
+                                  pr.incb, Bt.data_ptr(), pr.conts, pr.conta, pr.contb, pr.perm,
+                                  pr.incc, Ct.data_ptr())
+            if rc:
+                raise RuntimeError(f"{name}: {gett.strerror(rc)}")
+
+        print(f"[bench] complex {name}: first call", file=sys.stderr, flush=True)
+        call()
+        torch.cuda.synchronize()
+        err = {} if args.no_check else sampled_error(pr, Ct.cpu().numpy(), width=500)
+        sched = gett.gett_last_schedule()
+        for _ in range(args.warmup):
+            call()
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * args.steps)]
+        for i in range(args.steps):
+            ev[2 * i].record(stream)
+            call()
+            ev[2 * i + 1].record(stream)
+        torch.cuda.synchronize()
+        durs = [ev[2 * i].elapsed_time(ev[2 * i + 1]) for i in range(args.steps)]
+        ms = float(np.mean(durs))
+        tf = flops / (ms * 1e-3) / 1e12
+        out[name] = {"tflops_real": round(tf, 3), "ms": round(ms, 4),
+                     "ms_median": round(float(np.median(durs)), 4),
+                     "pct_peak": round(100 * tf / peak, 2), "peak_tflops": peak,
+                     "flops_per_call": flops, "schedule": int(sched), **err}
+        print(f"[bench] complex {name}: {json.dumps(out[name])}", file=sys.stderr, flush=True)
+        del At, Bt, Ct
+        torch.cuda.empty_cache()
+    out["workload"] = ("strided_perm shape, complex data: A (48,64,96,40) step 2 in a "
+                       "2x packed parent, B (40,56,96,72), C[b,e,a,d] dense")
+    return out
+
+
+def unary_leg(args, gett, torch, stream):
+    """The unary operations at HBM-bound sizes (FP64, beta = 0, so C is only
+    written): a 3-D transpose C[k,i,j] = A[i,j,k] of 512 MiB, and sums of an
+    (8192 x 8192) matrix over its fast and over its slow mode.  Algorithmic
+    bytes = |A| read + |C| written; achieved GB/s = those bytes / the mean
+    call time, against the 8 TB/s HBM peak."""
+    out = {}
+    cases = {
+        "transpose_kij_from_ijk": dict(ext=[1024, 1024, 64], suma=[], perm=[1, 2, 0]),
+        "sum_fast_mode": dict(ext=[8192, 8192], suma=[0], perm=[0]),
+        "sum_slow_mode": dict(ext=[8192, 8192], suma=[1], perm=[0]),
+    }
+    for name, cfg in cases.items():
+        ext, suma, perm = cfg["ext"], cfg["suma"], cfg["perm"]
+        inca, s_ = [], 1
+        for e in ext:
+            inca.append(s_)
+            s_ *= e
+        rest = [i for i in range(len(ext)) if i not in suma]
+        extc = [0] * len(rest)
+        for p_, q in enumerate(perm):
+            extc[q] = ext[rest[p_]]
+        incc, s_ = [], 1
+        for e in extc:
+            incc.append(s_)
+            s_ *= e
+        A = torch.randn(int(np.prod(ext)), dtype=torch.float64, device="cuda")
+        C = torch.empty(int(np.prod(extc)) if extc else 1, dtype=torch.float64, device="cuda")
+
+        def call():
+            rc = gett.dgett_unary(1.0, len(ext), ext, inca, A.data_ptr(), len(suma), suma, 0, [],
+                                  [], perm, incc, 0.0, C.data_ptr())
+            if rc:
+                raise RuntimeError(f"unary {name}: {gett.strerror(rc)}")
+
+        print(f"[bench] unary {name}", file=sys.stderr, flush=True)
+        for _ in range(args.warmup + 1):
+            call()
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * args.steps)]
+        for i in range(args.steps):
+            ev[2 * i].record(stream)
+            call()
+            ev[2 * i + 1].record(stream)
+        torch.cuda.synchronize()
+        ms = float(np.mean([ev[2 * i].elapsed_time(ev[2 * i + 1]) for i in range(args.steps)]))
+        nbytes = 8.0 * (A.numel() + C.numel())
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        out[name] = {"ms": round(ms, 4), "bytes": nbytes, "gb_s": round(gbs, 1),
+                     "frac_hbm": round(gbs / 8000.0, 4), "extents": ext, "summed": suma,
+                     "perm": perm}
+        print(f"[bench] unary {name}: {json.dumps(out[name])}", file=sys.stderr, flush=True)
+        del A, C
+        torch.cuda.empty_cache()
+    return out
+
+
 def batch_leg(count, gett, W, torch, stream, reps=10):
     """The uneven batch workload through split BF16x3: one replay of the
     captured batch graph against the same problems as separate sgett_bf16x3
-    calls (both with the heuristic schedule; the batch always runs the 64x64
-    tile).  Inputs resident; HIP events on the library's stream."""
+    calls, each forced onto the schedule its problem runs in the batch (the
+    policy picks one per problem: a batch tile and an N order, K unsplit).
+    Inputs resident; HIP events on the library's stream."""
     problems = W.config_batch(count)
     keep, args = [], []
     for pr in problems:
@@ -304,12 +433,16 @@ def batch_leg(count, gett, W, torch, stream, reps=10):
         if rc:
             raise RuntimeError(f"sgett_batch: {rc}")
 
+    scheds = []
+
     def run_separate():
-        for pr, (a, b, c) in zip(problems, args):
+        for pr, (a, b, c), sid in zip(problems, args, scheds):
+            gett.gett_set_schedule(sid)
             rc = gett.sgett_bf16x3(pr.ranka, pr.exta, pr.inca, a, pr.rankb, pr.extb, pr.incb, b,
                                    pr.conts, pr.conta, pr.contb, pr.perm, pr.incc, c)
             if rc:
                 raise RuntimeError(f"sgett_bf16x3: {gett.strerror(rc)}")
+        gett.gett_set_schedule(-1)
 
     def timed(fn, n):
         fn()                       # plans, tables and the graph are built here
@@ -324,6 +457,11 @@ def batch_leg(count, gett, W, torch, stream, reps=10):
 
     print(f"[bench] batch of {count}: graph replays", file=sys.stderr, flush=True)
     g_ms = timed(run_batch, reps)
+    scheds.extend(gett.gett_batch_last_schedules(count))
+    tiles = {}
+    for sid in scheds:
+        t = gett.schedule_of(sid)[0]
+        tiles[t] = tiles.get(t, 0) + 1
     print(f"[bench] batch of {count}: separate calls", file=sys.stderr, flush=True)
     s_ms = timed(run_separate, max(2, reps // 3))
     del keep
@@ -332,7 +470,8 @@ def batch_leg(count, gett, W, torch, stream, reps=10):
             "graph_ms": round(g_ms, 4), "graph_tflops": round(flops / (g_ms * 1e-3) / 1e12, 3),
             "separate_ms": round(s_ms, 4),
             "separate_tflops": round(flops / (s_ms * 1e-3) / 1e12, 3),
-            "speedup": round(s_ms / g_ms, 3)}
+            "speedup": round(s_ms / g_ms, 3),
+            "tiles_used": {str(k): v for k, v in sorted(tiles.items())}}
 
 
 def torch_context(pr, path, At, Bt, Ct, flops, steps, warmup, torch, stream):
@@ -422,14 +561,16 @@ def sampled_error(pr, got, width=1500):
     total = int(np.prod(pr.extc()))
     num = den = 0.0
     ecw = 0.0
+    cx = np.iscomplexobj(got)
     for s in (0, total // 2, total - width):
         ref, cabs = oracle.exact(pr, pr.A, pr.B, pr.C, s, s + width)
-        sel = ~np.isnan(ref)
-        d = got[sel].astype(np.float64) - ref[sel]
-        num += float(np.sum(d * d))
-        den += float(np.sum(ref[sel] ** 2))
+        sel = ~np.isnan(np.real(ref))
+        d = got[sel].astype(np.complex128 if cx else np.float64) - ref[sel]
+        num += float(np.sum(np.abs(d) ** 2))
+        den += float(np.sum(np.abs(ref[sel]) ** 2))
+        dm = np.abs(d.real) + np.abs(d.imag) if cx else np.abs(d)
         with np.errstate(invalid="ignore", divide="ignore"):
-            q = np.where(d == 0, 0.0, np.abs(d) / cabs[sel])
+            q = np.where(dm == 0, 0.0, dm / cabs[sel])
         ecw = max(ecw, float(np.max(q)))
     return {"e_nrm": float(np.sqrt(num / den)), "e_cw": ecw, "err_sample": 3 * width}
 

@@ -150,6 +150,18 @@ int sgett_fp8(int64_t ranka, const int64_t *exta, const int64_t *inca, const flo
               int64_t conts, const int64_t *conta, const int64_t *contb, const int64_t *perm,
               const int64_t *incc, float *C);
 
+/* SGETT on FP8 with MX-style blocks: the same as sgett_fp8 with blocks of
+   32 contracted positions instead of 128, so each 32 values of a row share a
+   power-of-two scale (an E8M0 exponent, the block size of the OCP
+   microscaling formats).  The gfx950 scaled MFMA applies the four scales of
+   each 128 positions per lane group in the matrix core.  Smaller blocks
+   follow the data's local range more closely than per-128 scales (fewer
+   values flush towards zero).  Same arguments and INFO codes as sgett_fp8. */
+int sgett_mxfp8(int64_t ranka, const int64_t *exta, const int64_t *inca, const float *A,
+                int64_t rankb, const int64_t *extb, const int64_t *incb, const float *B,
+                int64_t conts, const int64_t *conta, const int64_t *contb, const int64_t *perm,
+                const int64_t *incc, float *C);
+
 /* The quantisation step of sgett_fp8 on its own, for one operand: X is a
    device tensor of rank RANKX with extents/increments EXTX/INCX, CONTS of
    whose modes (CONTX) are contracted.  Writes codes to QX (device,
@@ -160,6 +172,10 @@ int sgett_fp8(int64_t ranka, const int64_t *exta, const int64_t *inca, const flo
    -8 EX). */
 int sgett_fp8_quantize(int64_t rankx, const int64_t *extx, const int64_t *incx, const float *X,
                        int64_t conts, const int64_t *contx, uint8_t *QX, int32_t *EX);
+/* The same with blocks of 32 (sgett_mxfp8): EX holds rows x 4*ceil(K/128)
+   exponents, the codes are laid out as for sgett_fp8_quantize. */
+int sgett_mxfp8_quantize(int64_t rankx, const int64_t *extx, const int64_t *incx, const float *X,
+                         int64_t conts, const int64_t *contx, uint8_t *QX, int32_t *EX);
 
 /* Batched xGETT: COUNT independent problems run as one persistent kernel
    launch captured in a HIP graph (replayed when the same batch signature
@@ -258,6 +274,41 @@ int cgett_ex(const float *alpha, int64_t ranka, const int64_t *exta, const int64
              int64_t hads, const int64_t *hada, const int64_t *hadb, const int64_t *perm,
              const int64_t *incc, const float *beta, void *C);
 
+/* Unary operations on A (transpose, reduction and trace, which Section 9
+   lists as future work):
+     C[PERM(rest)] <- ALPHA * sum A + BETA * C_in,
+   where the sum runs over the NSUM modes SUMA of A and over the NTR trace
+   pairs (TRA[t], TRB[t]) of equal extents, one coordinate walking both modes
+   of a pair; `rest` are A's other modes in ascending order, and PERM, INCC
+   place them in C as in xGETT.  NSUM = NTR = 0 is a (scaled) transpose.
+   BETA == 0 does not read C; an empty sum leaves BETA * C_in.  The kernels
+   are bound by HBM bandwidth: every element of A that takes part is read
+   once, every output read (BETA != 0) and written once; sums are formed in
+   FP64 (real and imaginary parts apart for complex data) in a fixed order.
+   INFO = -i for the i-th argument: -1 ALPHA (NULL, complex), -2 RANKA < 0 or
+   > 64, -3 EXTA, -4 INCA (NULL or an overflowing offset), -5 A, -6 NSUM < 0
+   or > RANKA, -7 SUMA (NULL, out of range, repeated), -8 NTR < 0 or
+   NSUM + 2 NTR > RANKA, -9 TRA (NULL, out of range, repeated, summed),
+   -10 TRB (the same, or an extent that differs from its TRA mode), -11 PERM,
+   -12 INCC, -13 BETA (NULL, complex), -14 C.  Element types as for
+   dgett, sgett, zgett and cgett. */
+int dgett_unary(double alpha, int64_t ranka, const int64_t *exta, const int64_t *inca,
+                const double *A, int64_t nsum, const int64_t *suma, int64_t ntr,
+                const int64_t *tra, const int64_t *trb, const int64_t *perm, const int64_t *incc,
+                double beta, double *C);
+int sgett_unary(float alpha, int64_t ranka, const int64_t *exta, const int64_t *inca,
+                const float *A, int64_t nsum, const int64_t *suma, int64_t ntr,
+                const int64_t *tra, const int64_t *trb, const int64_t *perm, const int64_t *incc,
+                float beta, float *C);
+int zgett_unary(const double *alpha, int64_t ranka, const int64_t *exta, const int64_t *inca,
+                const void *A, int64_t nsum, const int64_t *suma, int64_t ntr,
+                const int64_t *tra, const int64_t *trb, const int64_t *perm, const int64_t *incc,
+                const double *beta, void *C);
+int cgett_unary(const float *alpha, int64_t ranka, const int64_t *exta, const int64_t *inca,
+                const void *A, int64_t nsum, const int64_t *suma, int64_t ntr,
+                const int64_t *tra, const int64_t *trb, const int64_t *perm, const int64_t *incc,
+                const float *beta, void *C);
+
 /* DGETT that allocates nothing, for callers that cannot allocate device
    memory (code under HIP graph capture, tight serving loops, harnesses that
    forbid hipMalloc).  Same 14 arguments, semantics and INFO codes as dgett,
@@ -315,6 +366,16 @@ int gett_set_schedule(int64_t id);
    call reports its GEMM tile (0: 64x64, 3: 128x128, chosen by tile count)
    with order and split 0. */
 int64_t gett_last_schedule(void);
+
+/* Schedules the problems of the calling thread's last batch ran, one id
+   per problem (-1: nothing to compute), into ids (up to n of them); returns
+   the batch's problem count.  Each problem of a batch runs its own schedule:
+   one of the tiles compiled into the persistent batch kernel (tiles 0 and 2
+   of the precision's menu), any N order, K unsplit (the batch cuts long
+   contractions itself), chosen under the current policy: a forced schedule
+   of that kind, else the heuristic (least padding), the predictor or the
+   autotuner restricted to those schedules. */
+int64_t gett_batch_last_schedules(int64_t *ids, int64_t n);
 
 /* Cap, in bytes, on the FP64 partial-sum workspace of split-K schedules
    (initial value from GETT_MAX_WORKSPACE, default unlimited).  A call whose

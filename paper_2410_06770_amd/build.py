@@ -24,7 +24,8 @@ CHECK_LIB = os.path.join(HERE, "libgett_check.so")
 
 SOURCES = ["gett_tile_f64.hip", "gett_tile_f32.hip", "gett_tile_bf3.hip", "gett_tile_z64.hip",
            "gett_tile_c32.hip", "gett_fp8.hip",
-           "gett_mlp.hip", "gett_noalloc.hip", "gett_scale.hip", "gett_dispatch.cpp", "gett_plan.cpp", "gett_host.cpp"]
+           "gett_mlp.hip", "gett_noalloc.hip", "gett_scale.hip", "gett_unary.hip",
+           "gett_unary.cpp", "gett_dispatch.cpp", "gett_plan.cpp", "gett_host.cpp"]
 # Per-file code generation: the FP64 and FP32 tiles keep their MFMA
 # accumulators in ordinary VGPRs (no per-step copies to the accumulation
 # registers, lower register totals and higher occupancy); the BF16x3 tile,

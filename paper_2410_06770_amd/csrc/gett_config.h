@@ -150,12 +150,18 @@ struct TileParams {
 #endif
 };
 
+// Tiles compiled into the persistent batch kernel (menu indices of each
+// precision): every problem of a batch runs one of them, chosen per problem
+// by the schedule policy, and a uniform switch in the kernel picks it.
+constexpr int kBatchTiles = 2;
+constexpr int kBatchTile[kNumPrec][kBatchTiles] = {{0, 2}, {0, 2}, {0, 2}, {0, 0}, {0, 0}, {0, 0}};
+
 // One problem of a batched launch (device-resident descriptor).
 struct BatchProblem {
     TileParams p;
     int32_t aFastK, bFastK;
     int32_t tileBase;               // first work item of this problem
-    int32_t pad_;
+    int32_t tsel;                   // which batch tile (index into kBatchTile) it runs
 };
 
 }  // namespace gett

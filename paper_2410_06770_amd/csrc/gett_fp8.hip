@@ -72,14 +72,19 @@ __device__ __forceinline__ unsigned e4m3_word(float a, float b, float c, float d
 // load stays inside the table and the operand.
 constexpr int kQuantRun = 8;
 
+// BS: positions per scale, 128, or 32 (the MX-style blocks: lane l's two
+// positions l and l + 64 fall in blocks l / 32 and 2 + l / 32 of the 128).
+template <int BS>
 __global__ __launch_bounds__(256) void fp8_quant_kernel(const float *__restrict__ X,
                                                         const int64_t *__restrict__ offR,
                                                         int64_t rows, int64_t rowsPad,
                                                         const int64_t *__restrict__ offK,
                                                         int64_t K, uint8_t *__restrict__ Q,
                                                         int32_t *__restrict__ E) {
+    constexpr int SUB = 128 / BS;                                        // scales per 128
     const int64_t nb = (K + 127) / 128;
     const int64_t Kp = nb * 128;
+    const int64_t nbs = nb * SUB;
     const int64_t runs = (nb + kQuantRun - 1) / kQuantRun;
     const int lane = threadIdx.x & 63;
     const int64_t task = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);   // one wave per task
@@ -91,7 +96,7 @@ __global__ __launch_bounds__(256) void fp8_quant_kernel(const float *__restrict_
         for (int j = 0; j < nbl; ++j) {
             q[(b0 + j) * 128 + lane] = 0;
             q[(b0 + j) * 128 + 64 + lane] = 0;
-            if (lane == 0) E[r * nb + b0 + j] = 0;
+            if (lane < SUB) E[r * nbs + (b0 + j) * SUB + lane] = 0;
         }
         return;
     }
@@ -109,22 +114,42 @@ __global__ __launch_bounds__(256) void fp8_quant_kernel(const float *__restrict_
 #pragma unroll
     for (int j = 0; j < kQuantRun; ++j) {
         if (j >= nbl) break;                            // uniform across the wave
-        float amax = fmaxf(fabsf(v0[j]), fabsf(v1[j]));
-#pragma unroll
-        for (int s = 32; s > 0; s >>= 1) amax = fmaxf(amax, __shfl_xor(amax, s, 64));
-        const int e = fp8_scale_exp(amax);
-        const float inv = ldexpf(1.f, -e);    // exact power of two (e >= -127: 2^127 fits)
         const int64_t k0 = (b0 + j) * 128 + lane, k1 = k0 + 64;
-        q[k0] = (uint8_t)(k0 < K ? e4m3_code(v0[j] * inv) : 0u);
-        q[k1] = (uint8_t)(k1 < K ? e4m3_code(v1[j] * inv) : 0u);
-        if (lane == 0) E[r * nb + b0 + j] = e;
+        if constexpr (BS == 128) {
+            float amax = fmaxf(fabsf(v0[j]), fabsf(v1[j]));
+#pragma unroll
+            for (int s = 32; s > 0; s >>= 1) amax = fmaxf(amax, __shfl_xor(amax, s, 64));
+            const int e = fp8_scale_exp(amax);
+            const float inv = ldexpf(1.f, -e);  // exact power of two (e >= -127: 2^127 fits)
+            q[k0] = (uint8_t)(k0 < K ? e4m3_code(v0[j] * inv) : 0u);
+            q[k1] = (uint8_t)(k1 < K ? e4m3_code(v1[j] * inv) : 0u);
+            if (lane == 0) E[r * nbs + b0 + j] = e;
+        } else {
+            // blocks of 32: lanes 0-31 and 32-63 each hold one block of the
+            // low half (positions l) and one of the high half (l + 64)
+            float a0 = fabsf(v0[j]), a1 = fabsf(v1[j]);
+#pragma unroll
+            for (int s = 16; s > 0; s >>= 1) {
+                a0 = fmaxf(a0, __shfl_xor(a0, s, 64));
+                a1 = fmaxf(a1, __shfl_xor(a1, s, 64));
+            }
+            const int e0 = fp8_scale_exp(a0), e1 = fp8_scale_exp(a1);
+            q[k0] = (uint8_t)(k0 < K ? e4m3_code(v0[j] * ldexpf(1.f, -e0)) : 0u);
+            q[k1] = (uint8_t)(k1 < K ? e4m3_code(v1[j] * ldexpf(1.f, -e1)) : 0u);
+            if ((lane & 31) == 0) {
+                const int64_t eb = r * nbs + (b0 + j) * 4 + (lane >> 5);
+                E[eb] = e0;
+                E[eb + 2] = e1;
+            }
+        }
     }
 }
 
 // Lanes along the rows: one wave per (16 rows, 128-block); four lanes share a
 // row, each keeping a quarter of the block (32 values) in registers, so X is
 // read once and every load of the wave reads 16 neighbouring rows at four
-// contracted positions.
+// contracted positions.  With blocks of 32 each lane's quarter is one block.
+template <int BS>
 __global__ __launch_bounds__(256) void fp8_quant_rows_kernel(const float *__restrict__ X,
                                                              const int64_t *__restrict__ offR,
                                                              const int32_t *__restrict__ rowMap,
@@ -155,9 +180,11 @@ __global__ __launch_bounds__(256) void fp8_quant_rows_kernel(const float *__rest
         v[i] = (i < kn && live) ? x[offK[k0 + i]] : 0.f;
         amax = fmaxf(amax, fabsf(v[i]));
     }
-    // the four lanes of a row are RPW apart
-    amax = fmaxf(amax, __shfl_xor(amax, RPW, 64));
-    amax = fmaxf(amax, __shfl_xor(amax, 2 * RPW, 64));
+    if constexpr (BS == 128) {
+        // the four lanes of a row are RPW apart
+        amax = fmaxf(amax, __shfl_xor(amax, RPW, 64));
+        amax = fmaxf(amax, __shfl_xor(amax, 2 * RPW, 64));
+    }
     const int e = fp8_scale_exp(amax);
     const float inv = ldexpf(1.f, -e);
     if (p >= rowsPad) return;
@@ -172,7 +199,11 @@ __global__ __launch_bounds__(256) void fp8_quant_rows_kernel(const float *__rest
         out.w = e4m3_word(w[12] * inv, w[13] * inv, w[14] * inv, w[15] * inv);
         q[c] = out;
     }
-    if (part == 0) E[r * nb + blk] = e;
+    if constexpr (BS == 128) {
+        if (part == 0) E[r * nb + blk] = e;
+    } else {
+        E[r * nb * 4 + blk * 4 + part] = e;
+    }
 }
 
 // Load one 128-block of a ROWS x 128 code tile into registers: 16-byte
@@ -196,25 +227,48 @@ __device__ __forceinline__ void fp8_store_block(uint8_t *s, int t, const u4_t (&
     }
 }
 
+// Operand registers of one lane: with one scale per 128 any split of the
+// block between lanes works as long as A and B share it, and each lane takes
+// 32 consecutive codes; with one scale per 32 the matrix core's block b (of
+// 32) must be the stored block b, so lane group g takes the stored
+// positions 16 g .. 16 g + 15 and 64 + 16 g .. 64 + 16 g + 15 (the halves the
+// core reads as k = 16 g .. and 64 + 16 g ..), and supplies the scale of
+// block g of its row.
+template <int BS>
+__device__ __forceinline__ i8_t fp8_operand(const uint8_t *row, int lane) {
+    const int g = lane >> 4;
+    if constexpr (BS == 128) {
+        return *reinterpret_cast<const i8_t *>(row + 32 * g);
+    } else {
+        const u4_t lo = *reinterpret_cast<const u4_t *>(row + 16 * g);
+        const u4_t hi = *reinterpret_cast<const u4_t *>(row + 64 + 16 * g);
+        return i8_t{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w,
+                    (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+    }
+}
+
 // One 128-block on the matrix cores: each wave's FM x FN fragments.  sE holds
-// the biased block exponents of the tile's A rows, then of its B rows.
-template <int FM, int FN, int WTM, int WTN, int LDK, int BM>
+// the biased exponents of the tile's A rows, then of its B rows (one per row,
+// or four per row with blocks of 32).
+template <int FM, int FN, int WTM, int WTN, int LDK, int BM, int BS>
 __device__ __forceinline__ void fp8_mma_block(const uint8_t *sA, const uint8_t *sB,
                                               const int32_t *sE, int wm, int wn, int lane,
-                                              int kc, f4_t (&acc)[FM][FN]) {
+                                              f4_t (&acc)[FM][FN]) {
+    constexpr int SUB = 128 / BS;
+    const int sub = BS == 128 ? 0 : (lane >> 4);
     i8_t a[FM], b[FN];
     int sa[FM], sb[FN];
 #pragma unroll
     for (int i = 0; i < FM; ++i) {
         const int r = wm * WTM + i * 16 + (lane & 15);
-        a[i] = *reinterpret_cast<const i8_t *>(sA + r * LDK + kc);
-        sa[i] = sE[r];
+        a[i] = fp8_operand<BS>(sA + r * LDK, lane);
+        sa[i] = sE[r * SUB + sub];
     }
 #pragma unroll
     for (int j = 0; j < FN; ++j) {
         const int r = wn * WTN + j * 16 + (lane & 15);
-        b[j] = *reinterpret_cast<const i8_t *>(sB + r * LDK + kc);
-        sb[j] = sE[BM + r];
+        b[j] = fp8_operand<BS>(sB + r * LDK, lane);
+        sb[j] = sE[(BM + r) * SUB + sub];
     }
 #pragma unroll
     for (int i = 0; i < FM; ++i)
@@ -237,7 +291,7 @@ __device__ __forceinline__ bool fp8_c_word(const float *C, const int64_t *__rest
 }
 
 // C tile BM x BN, 4 waves as 2 x 2, each wave (BM/2) x (BN/2) in 16x16 fragments.
-template <int BM, int BN>
+template <int BM, int BN, int BS>
 __global__ __launch_bounds__(256) void fp8_gemm_kernel(const uint8_t *__restrict__ QA,
                                                        const int32_t *__restrict__ EA,
                                                        const uint8_t *__restrict__ QB,
@@ -252,11 +306,13 @@ __global__ __launch_bounds__(256) void fp8_gemm_kernel(const uint8_t *__restrict
     constexpr int CA = BM * 8 / 256, CB = BN * 8 / 256;   // 16-byte chunks per thread
     __shared__ __align__(16) uint8_t sA[2][BM * LDK];
     __shared__ __align__(16) uint8_t sB[2][BN * LDK];
-    __shared__ int32_t sE[2][BM + BN];
-    static_assert(BM + BN <= 256 && 256 % (BM + BN) == 0, "one scale per thread");
+    constexpr int SUB = 128 / BS;            // scales per row and 128-block
+    __shared__ __align__(16) int32_t sE[2][(BM + BN) * SUB];
+    static_assert(BM + BN <= 256 && 256 % (BM + BN) == 0, "one row of scales per thread");
 
     const int64_t nb = (K + 127) / 128;
     const int64_t Kp = nb * 128;
+    const int64_t nbs = nb * SUB;            // scales per row
     int tm, tn;
     tile_coords(xcd_remap(blockIdx.x, gridDim.x), tilesM, tilesN, tm, tn);
     const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
@@ -271,10 +327,24 @@ __global__ __launch_bounds__(256) void fp8_gemm_kernel(const uint8_t *__restrict
 #pragma unroll
         for (int j = 0; j < FN; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
 
-    // Thread t carries the scale of tile row t mod (BM + BN) (A rows, then B
-    // rows; with fewer rows than threads, two threads carry the same one).
+    // Thread t carries the scales of tile row t mod (BM + BN) (A rows, then B
+    // rows; with fewer rows than threads, two threads carry the same ones).
     const int sidx = t % (BM + BN);
-    const int32_t *ex = sidx < BM ? EA + (m0 + sidx) * nb : EB + (n0 + sidx - BM) * nb;
+    const int32_t *ex = sidx < BM ? EA + (m0 + sidx) * nbs : EB + (n0 + sidx - BM) * nbs;
+    typedef int i4s_t __attribute__((ext_vector_type(4)));
+    // this row's exponents of block blk, biased for E8M0 (bias 127)
+    auto scales = [&](int64_t blk) {
+        if constexpr (SUB == 1) {
+            return i4s_t{ex[blk] + 127, 0, 0, 0};
+        } else {
+            const i4s_t v = *reinterpret_cast<const i4s_t *>(ex + blk * 4);
+            return v + 127;
+        }
+    };
+    auto put_scales = [&](int32_t *se, i4s_t v) {
+        if constexpr (SUB == 1) se[sidx] = v.x;
+        else *reinterpret_cast<i4s_t *>(se + sidx * 4) = v;
+    };
     // Two register sets: the codes of block b + 2 load while block b runs on
     // the matrix cores and block b + 1 waits in the other set; loads past the
     // last block reload it (a valid address).  Blocks run in pairs; when their
@@ -284,38 +354,37 @@ __global__ __launch_bounds__(256) void fp8_gemm_kernel(const uint8_t *__restrict
     u4_t ra[CA], rb[CB], ra2[CA], rb2[CB];
     fp8_load_block<CA>(pa, Kp, 0, t, ra);
     fp8_load_block<CB>(pb, Kp, 0, t, rb);
-    int32_t xs = ex[0];
+    i4s_t xs = scales(0);
     const int64_t b1 = nb > 1 ? 1 : 0;
     fp8_load_block<CA>(pa, Kp, b1, t, ra2);
     fp8_load_block<CB>(pb, Kp, b1, t, rb2);
-    int32_t xs2 = ex[b1];
+    i4s_t xs2 = scales(b1);
     fp8_store_block<CA, LDK>(sA[0], t, ra);
     fp8_store_block<CB, LDK>(sB[0], t, rb);
-    sE[0][sidx] = xs + 127;      // E8M0 bias
+    put_scales(sE[0], xs);
     __syncthreads();
-    const int kc = 32 * (lane >> 4);
     for (int64_t blk = 0; blk < nb; blk += 2) {
         // even block: LDS stage 0, the next block waits in set 2
         const int64_t n2 = blk + 2 < nb ? blk + 2 : nb - 1;
         fp8_load_block<CA>(pa, Kp, n2, t, ra);
         fp8_load_block<CB>(pb, Kp, n2, t, rb);
-        xs = ex[n2];
-        fp8_mma_block<FM, FN, WTM, WTN, LDK, BM>(sA[0], sB[0], sE[0], wm, wn, lane, kc, acc);
+        xs = scales(n2);
+        fp8_mma_block<FM, FN, WTM, WTN, LDK, BM, BS>(sA[0], sB[0], sE[0], wm, wn, lane, acc);
         __builtin_amdgcn_sched_barrier(0);
         fp8_store_block<CA, LDK>(sA[1], t, ra2);
         fp8_store_block<CB, LDK>(sB[1], t, rb2);
-        sE[1][sidx] = blk + 1 < nb ? xs2 + 127 : 0;
+        put_scales(sE[1], blk + 1 < nb ? xs2 : i4s_t{0, 0, 0, 0});
         __syncthreads();
         // odd block: LDS stage 1, the next block waits in set 1
         const int64_t n3 = blk + 3 < nb ? blk + 3 : nb - 1;
         fp8_load_block<CA>(pa, Kp, n3, t, ra2);
         fp8_load_block<CB>(pb, Kp, n3, t, rb2);
-        xs2 = ex[n3];
-        fp8_mma_block<FM, FN, WTM, WTN, LDK, BM>(sA[1], sB[1], sE[1], wm, wn, lane, kc, acc);
+        xs2 = scales(n3);
+        fp8_mma_block<FM, FN, WTM, WTN, LDK, BM, BS>(sA[1], sB[1], sE[1], wm, wn, lane, acc);
         __builtin_amdgcn_sched_barrier(0);
         fp8_store_block<CA, LDK>(sA[0], t, ra);
         fp8_store_block<CB, LDK>(sB[0], t, rb);
-        sE[0][sidx] = xs + 127;
+        put_scales(sE[0], xs);
         __syncthreads();
     }
     // C_in of this lane's outputs.  Lane l holds M row (l % 16) and the four
@@ -370,36 +439,42 @@ __global__ __launch_bounds__(256) void fp8_gemm_kernel(const uint8_t *__restrict
 
 int launch_fp8_quant(const float *X, const int64_t *offR, const int32_t *rowMap, int64_t rows,
                      int64_t rowsPad, const int64_t *offK, int64_t K, bool rowsFast, uint8_t *Q,
-                     int32_t *E, hipStream_t s) {
+                     int32_t *E, hipStream_t s, int bs) {
     const int64_t nb = (K + 127) / 128;
     const int64_t tasks = rowsFast ? (rowsPad + 15) / 16 * nb
                                    : rowsPad * ((nb + kQuantRun - 1) / kQuantRun);
     const int64_t blocks = (tasks + 3) / 4;
     if (blocks > INT32_MAX) return GETT_ERR_INTERNAL;
     (void)hipGetLastError();   // clear a stale error left by other HIP users
-    if (rowsFast)
-        hipLaunchKernelGGL(fp8_quant_rows_kernel, dim3((unsigned)blocks), dim3(256), 0, s, X, offR,
-                           rowMap, rows, rowsPad, offK, K, Q, E);
-    else
-        hipLaunchKernelGGL(fp8_quant_kernel, dim3((unsigned)blocks), dim3(256), 0, s, X, offR, rows,
+    if (bs != 128 && bs != 32) return GETT_ERR_INTERNAL;
+    if (rowsFast) {
+        auto k = bs == 128 ? fp8_quant_rows_kernel<128> : fp8_quant_rows_kernel<32>;
+        hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(256), 0, s, X, offR, rowMap, rows,
                            rowsPad, offK, K, Q, E);
+    } else {
+        auto k = bs == 128 ? fp8_quant_kernel<128> : fp8_quant_kernel<32>;
+        hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(256), 0, s, X, offR, rows, rowsPad,
+                           offK, K, Q, E);
+    }
     return launch_status();
 }
 
 int launch_fp8_gemm(int tile, const uint8_t *QA, const int32_t *EA, const uint8_t *QB,
                     const int32_t *EB, float *C, const int64_t *offCM, const int64_t *offCN,
-                    int64_t M, int64_t N, int64_t K, hipStream_t s) {
+                    int64_t M, int64_t N, int64_t K, hipStream_t s, int bs) {
+    if (bs != 128 && bs != 32) return GETT_ERR_INTERNAL;
+    (void)hipGetLastError();   // clear a stale error left by other HIP users
     if (tile == 3) {
         const int tilesM = (int)((M + 127) / 128), tilesN = (int)((N + 127) / 128);
-        (void)hipGetLastError();   // clear a stale error left by other HIP users
-        hipLaunchKernelGGL((fp8_gemm_kernel<128, 128>), dim3(tilesM * tilesN), dim3(256), 0, s, QA,
-                           EA, QB, EB, C, offCM, offCN, M, N, K, tilesM, tilesN);
+        auto k = bs == 128 ? fp8_gemm_kernel<128, 128, 128> : fp8_gemm_kernel<128, 128, 32>;
+        hipLaunchKernelGGL(k, dim3(tilesM * tilesN), dim3(256), 0, s, QA, EA, QB, EB, C, offCM,
+                           offCN, M, N, K, tilesM, tilesN);
     } else {
         // operands are padded to multiples of 128 rows, so 64-row tiles stay inside
         const int tilesM = (int)((M + 63) / 64), tilesN = (int)((N + 63) / 64);
-        (void)hipGetLastError();   // clear a stale error left by other HIP users
-        hipLaunchKernelGGL((fp8_gemm_kernel<64, 64>), dim3(tilesM * tilesN), dim3(256), 0, s, QA,
-                           EA, QB, EB, C, offCM, offCN, M, N, K, tilesM, tilesN);
+        auto k = bs == 128 ? fp8_gemm_kernel<64, 64, 128> : fp8_gemm_kernel<64, 64, 32>;
+        hipLaunchKernelGGL(k, dim3(tilesM * tilesN), dim3(256), 0, s, QA, EA, QB, EB, C, offCM,
+                           offCN, M, N, K, tilesM, tilesN);
     }
     return launch_status();
 }

@@ -73,6 +73,8 @@ static int check_device(int *dev_out) {
     return it->second ? 0 : GETT_ERR_DEVICE;
 }
 
+int current_device_checked(int *dev) { return check_device(dev); }
+
 // ---------------------------------------------------------------------------
 // Schedules
 // ---------------------------------------------------------------------------
@@ -534,7 +536,9 @@ static int get_fp8_plan(const Args &a, int dev, Fp8Plan **out) {
     return 0;
 }
 
-static int run_fp8(const Args &a, const float *A, const float *B, float *C, hipStream_t s, int dev) {
+// bs: contracted positions per scale (128, or 32 for the MX-style call).
+static int run_fp8(const Args &a, const float *A, const float *B, float *C, hipStream_t s, int dev,
+                   int bs) {
     Fp8Plan *pl = nullptr;
     int rc = get_fp8_plan(a, dev, &pl);
     if (rc) return rc;
@@ -545,20 +549,21 @@ static int run_fp8(const Args &a, const float *A, const float *B, float *C, hipS
     const int64_t *rowsA = pl->d_tab, *kA = rowsA + M, *rowsB = kA + K, *kB = rowsB + N;
     const int64_t *offCM = kB + K, *offCN = offCM + M;
     const int64_t Mq = round_up(M, 128), Nq = round_up(N, 128);
-    const size_t bytes = (size_t)(Mq + Nq) * Kp + (size_t)(Mq + Nq) * nb * sizeof(int32_t) + 256;
+    const int64_t nbs = nb * (128 / bs);   // exponents per row
+    const size_t bytes = (size_t)(Mq + Nq) * Kp + (size_t)(Mq + Nq) * nbs * sizeof(int32_t) + 256;
     void *ws = nullptr;
     if (hipMallocAsync(&ws, bytes, s) != hipSuccess) return GETT_ERR_ALLOC;
     uint8_t *QA = static_cast<uint8_t *>(ws);
     uint8_t *QB = QA + (size_t)Mq * Kp;
     int32_t *EA = reinterpret_cast<int32_t *>(QB + (size_t)Nq * Kp);
-    int32_t *EB = EA + (size_t)Mq * nb;
+    int32_t *EB = EA + (size_t)Mq * nbs;
     const float *X0 = pl->swapped ? B : A, *X1 = pl->swapped ? A : B;
     rc = launch_fp8_quant(X0, pl->aRowsFast ? pl->d_rowsOp[0] : rowsA, pl->d_rowMap[0], M, Mq,
-                          kA, K, pl->aRowsFast, QA, EA, s);
+                          kA, K, pl->aRowsFast, QA, EA, s, bs);
     if (!rc)
         rc = launch_fp8_quant(X1, pl->bRowsFast ? pl->d_rowsOp[1] : rowsB, pl->d_rowMap[1], N, Nq,
-                              kB, K, pl->bRowsFast, QB, EB, s);
-    if (!rc) rc = launch_fp8_gemm(pl->tile, QA, EA, QB, EB, C, offCM, offCN, M, N, K, s);
+                              kB, K, pl->bRowsFast, QB, EB, s, bs);
+    if (!rc) rc = launch_fp8_gemm(pl->tile, QA, EA, QB, EB, C, offCM, offCN, M, N, K, s, bs);
     if (hipFreeAsync(ws, s) != hipSuccess && !rc) rc = GETT_ERR_HIP;
     return rc;
 }
@@ -639,7 +644,10 @@ static int load_predictor(const char *path) {
 
 // Run the network on one feature vector with the library's own kernels and
 // return the best valid joint schedule under the summed log-probabilities.
-static bool predict(int prec, const Args &a, int64_t K, Sched *out) {
+// A schedule filter (nullptr: every valid schedule of the menu).
+typedef bool (*SchedFilter)(int prec, const Sched &s);
+
+static bool predict(int prec, const Args &a, int64_t K, Sched *out, SchedFilter allow = nullptr) {
     // Without a loaded network, GETT_MODEL names the weights file to load
     // (once, on the first prediction).
     static std::once_flag env_model;
@@ -690,7 +698,7 @@ static bool predict(int prec, const Args &a, int64_t K, Sched *out) {
     bool found = false;
     for (int64_t id = 0; id < kNumSched; ++id) {
         Sched sc = sched_of(id);
-        if (!sched_valid(prec, sc, K)) continue;
+        if (!sched_valid(prec, sc, K) || (allow && !allow(prec, sc))) continue;
         const double v = lp[sc.tile] + lp[kNumTiles + sc.order] + lp[kNumTiles + kNumOrders + sc.split];
         if (v > best) {
             best = v;
@@ -741,12 +749,14 @@ static int time_schedule(int prec, const Args &a, const void *A, const void *B, 
 // receives the median for re-timed schedules, the single time for the
 // others, and -1 for invalid ones.
 static int64_t autotune(int prec, const Args &a, const void *A, const void *B, void *C, int dev,
-                        int warmup, int reps, double *times, int64_t ntimes, int *status) {
+                        int warmup, int reps, double *times, int64_t ntimes, int *status,
+                        SchedFilter allow = nullptr) {
     Canon c0 = canonicalise(a, 0, 128);
     *status = 0;
     std::vector<double> t1(kNumSched, -1.0);
     for (int64_t id = 0; id < kNumSched; ++id) {
-        if (!sched_valid(prec, sched_of(id), c0.K)) continue;
+        if (!sched_valid(prec, sched_of(id), c0.K) || (allow && !allow(prec, sched_of(id))))
+            continue;
         int rc = time_schedule(prec, a, A, B, C, dev, id, warmup, 1, &t1[id]);
         if (rc) {
             *status = rc;
@@ -965,7 +975,7 @@ static bool is_one(const double *x) { return x[0] == 1.0 && x[1] == 0.0; }
 // alpha, beta: (re, im) pairs of C <- alpha * sum + beta * C_in (kOne for
 // the paper's accumulate).
 static int run(int prec, const Args &a, const void *A, const void *B, void *C,
-               const double *alpha = kOne, const double *beta = kOne) {
+               const double *alpha = kOne, const double *beta = kOne, int fp8_block = 128) {
     int info = validate(a, A, B, C);
     if (info) return info;
     Canon probe = canonicalise(a, 0, 128);
@@ -984,7 +994,7 @@ static int run(int prec, const Args &a, const void *A, const void *B, void *C,
     hipStream_t s = t_stream;
     if (prec == kFP8)
         return run_fp8(a, static_cast<const float *>(A), static_cast<const float *>(B),
-                       static_cast<float *>(C), s, dev);
+                       static_cast<float *>(C), s, dev, fp8_block);
     const int64_t forced = g_forced.load();
     std::shared_ptr<Plan> pl;
     // Under the AUTOTUNE policy a plan-cache miss times the menu; the timing
@@ -1127,6 +1137,7 @@ struct BatchGraph {
     int32_t *d_items = nullptr;
     int32_t nprobs = 0, nitems = 0;
     std::vector<std::shared_ptr<Plan>> plans;
+    std::vector<int64_t> sids;   // each problem's schedule (-1: nothing to compute)
     // Problems cut along K: slice count, slice length and workspace offset
     // (doubles) per problem (splits 1: not cut), the list of cut problems on
     // the device and their FP64 partial-sum workspace.
@@ -1150,6 +1161,90 @@ struct BatchGraph {
 };
 static std::unordered_map<std::string, std::unique_ptr<BatchGraph>> g_graphs;
 
+// Schedules of the problems of the calling thread's last batch (-1: empty).
+static thread_local std::vector<int64_t> t_batch_scheds;
+
+static int batch_tile_index(int prec, int tile) {
+    for (int b = 0; b < kBatchTiles; ++b)
+        if (kBatchTile[prec][b] == tile) return b;
+    return -1;
+}
+
+// Schedules a batch problem can run: a batch tile, any N order, K unsplit
+// (the batch cuts long contractions itself).
+static bool batch_allow(int prec, const Sched &s) {
+    return s.split == 0 && batch_tile_index(prec, s.tile) >= 0;
+}
+
+// Built-in choice for a batch problem: the batch tile whose tiles waste the
+// least padding, weighted by the tile's relative speed (the batch as a whole
+// fills the chip, so the tile need not), N order by C's strides (the
+// epilogue's stores coalesce: on the uneven 512-problem batch the order by
+// C measured 3 % faster than the order by B, and the tile choice within
+// 1 %, the replay being bound by the latency of its many short items).
+static Sched batch_heuristic(int prec, int64_t M, int64_t N) {
+    static const double kBatchSpeed[kNumPrec][kBatchTiles] = {
+        {0.9, 1.0}, {0.9, 1.0}, {0.95, 1.0}, {1, 1}, {1, 1}, {1, 1}};
+    Sched best{kBatchTile[prec][0], 1, 0};
+    double bs = -1;
+    for (int b = 0; b < kBatchTiles; ++b) {
+        const TileShape ts = kTiles[prec][kBatchTile[prec][b]];
+        const double pad = ((double)M / (std::ceil((double)M / ts.bm) * ts.bm)) *
+                           ((double)N / (std::ceil((double)N / ts.bn) * ts.bn));
+        const double score = pad * kBatchSpeed[prec][b];
+        if (score > bs + 1e-9) {
+            bs = score;
+            best.tile = kBatchTile[prec][b];
+        }
+    }
+    return best;
+}
+
+// The schedule one problem of a batch runs, under the current policy: a
+// forced schedule that a batch can run; else the heuristic, the predictor or
+// the autotuner restricted to the batch's schedules (the autotuner times the
+// problem alone, with C's footprint saved and restored around the timing).
+static int batch_schedule(int prec, const Args &a, const void *A, const void *B, void *C,
+                          int dev, hipStream_t st, int64_t *id_out) {
+    const Canon c0 = canonicalise(a, 0, 128);
+    const int64_t forced = g_forced.load();
+    if (forced >= 0 && batch_allow(prec, sched_of(forced)) &&
+        sched_valid(prec, sched_of(forced), c0.K)) {
+        *id_out = forced;
+        return 0;
+    }
+    Sched s = batch_heuristic(prec, c0.M, c0.N);
+    const int pol = g_policy.load();
+    if (pol == GETT_PREDICT && prec <= kFP8) {
+        Sched ps;
+        if (predict(prec, a, c0.K, &ps, batch_allow)) s = ps;
+    } else if (pol == GETT_AUTOTUNE) {
+        int64_t lo = 0;
+        const int64_t span = c_span_elems(a, &lo);
+        const size_t esz = (size_t)prec_bytes(prec);
+        char *cbase = static_cast<char *>(C) + lo * (int64_t)esz;
+        void *saved = nullptr;
+        if (hipMallocAsync(&saved, span * esz, st) != hipSuccess) return GETT_ERR_ALLOC;
+        int rc = hipMemcpyAsync(saved, cbase, span * esz, hipMemcpyDeviceToDevice, st) !=
+                         hipSuccess
+                     ? GETT_ERR_HIP
+                     : 0;
+        int status = 0;
+        int64_t id = -1;
+        if (!rc) id = autotune(prec, a, A, B, C, dev, 1, 5, nullptr, 0, &status, batch_allow);
+        if (hipMemcpyAsync(cbase, saved, span * esz, hipMemcpyDeviceToDevice, st) !=
+                hipSuccess &&
+            !rc)
+            rc = GETT_ERR_HIP;
+        (void)hipFreeAsync(saved, st);
+        if (rc) return rc;
+        if (status) return status;
+        if (id >= 0) s = sched_of(id);
+    }
+    *id_out = sched_id(s);
+    return 0;
+}
+
 // Run a batch: per-problem plans with the batch tile (64x64 of the precision),
 // problems with long contractions cut along K, one work list ordered longest
 // item first, and a graph of {descriptor copy, persistent kernel, reduction
@@ -1158,11 +1253,13 @@ static std::unordered_map<std::string, std::unique_ptr<BatchGraph>> g_graphs;
 // replay, and the graph's copy node moves them to the device.
 static int run_batch(int prec, int64_t count, const Args *args, const void *const *A,
                      const void *const *B, void *const *C, int dev, hipStream_t s) {
-    const int64_t forced = sched_id(Sched{0, 0, 0});
     std::string key;
     key.reserve(64 * count);
     key.append(reinterpret_cast<const char *>(&prec), sizeof prec);
     key.append(reinterpret_cast<const char *>(&dev), sizeof dev);
+    // the per-problem schedules depend on the policy and a forced schedule
+    const int64_t pol_key[2] = {(int64_t)g_policy.load(), g_forced.load()};
+    key.append(reinterpret_cast<const char *>(pol_key), sizeof pol_key);
     std::vector<char> live(count, 0);
     for (int64_t i = 0; i < count; ++i) {
         // a problem with a zero extent anywhere has nothing to compute
@@ -1184,24 +1281,33 @@ static int run_batch(int prec, int64_t count, const Args *args, const void *cons
         nb->splits.assign(count, 1);
         nb->kper.assign(count, 0);
         nb->ws_off.assign(count, 0);
-        const int bk = kTiles[prec][0].bk;
+        nb->sids.assign(count, -1);
         const int grid_max = std::max(batch_grid_size(prec), 1);
+        // Work of an item in steps of the 64 x 64 tile: a step of a larger
+        // tile counts its area over 64 x 64.
+        auto area = [&](const Plan &pl) {
+            const TileShape ts = kTiles[prec][pl.sched.tile];
+            return (double)(ts.bm * ts.bn) / (64.0 * 64.0);
+        };
         // Work in K steps per problem; a problem whose tiles would each take
         // more steps than the average workgroup's share (at least 64) is cut
         // along K into slices of about that length, so no single item holds
         // up the whole launch.  Slices write FP64 partials that a reduction
         // kernel in the same graph adds to C_in in slice order.
-        int64_t total = 0;
+        double total = 0;
         for (int64_t i = 0; i < count; ++i) {
             if (!live[i]) continue;
+            int rc = batch_schedule(prec, args[i], A[i], B[i], C[i], dev, s, &nb->sids[i]);
+            if (rc) return rc;
             std::shared_ptr<Plan> pl;
-            int rc = get_plan(prec, args[i], dev, forced, &pl);
+            rc = get_plan(prec, args[i], dev, nb->sids[i], &pl);
             if (rc) return rc;
             nb->plans[i] = pl;
             TileParams p = make_params(*pl, nullptr, nullptr, nullptr);
-            total += (int64_t)p.tilesM * p.tilesN * ((p.K + bk - 1) / bk);
+            const int bk = kTiles[prec][pl->sched.tile].bk;
+            total += (double)p.tilesM * p.tilesN * ((p.K + bk - 1) / bk) * area(*pl);
         }
-        const int64_t cap = std::max<int64_t>(64, (total + grid_max - 1) / grid_max);
+        const double cap = std::max(64.0, total / grid_max);
         struct Work { int64_t len; int32_t prob, nitems; };
         std::vector<Work> work;
         std::vector<int32_t> cut;
@@ -1209,10 +1315,12 @@ static int run_batch(int prec, int64_t count, const Args *args, const void *cons
         for (int64_t i = 0; i < count; ++i) {
             if (!nb->plans[i]) continue;
             TileParams p = make_params(*nb->plans[i], nullptr, nullptr, nullptr);
+            const int bk = kTiles[prec][nb->plans[i]->sched.tile].bk;
+            const double ar = area(*nb->plans[i]);
             const int64_t steps = (p.K + bk - 1) / bk;
             int64_t S = 1, per = steps * bk;
-            if (steps > cap) {
-                S = (steps + cap - 1) / cap;
+            if (steps * ar > cap) {
+                S = (int64_t)std::ceil(steps * ar / cap);
                 per = (steps + S - 1) / S * bk;
                 S = (p.K + per - 1) / per;      // every slice starts below K
                 if ((ws_total + S * p.M * p.N) * (int64_t)sizeof(double) > g_max_ws.load()) {
@@ -1229,7 +1337,7 @@ static int run_batch(int prec, int64_t count, const Args *args, const void *cons
                 ws_total += S * p.M * p.N;
                 cut.push_back((int32_t)i);
             }
-            work.push_back({S > 1 ? per : p.K, (int32_t)i, (int32_t)items});
+            work.push_back({(int64_t)((S > 1 ? per : p.K) * ar), (int32_t)i, (int32_t)items});
         }
         std::stable_sort(work.begin(), work.end(),
                          [](const Work &a, const Work &b) { return a.len > b.len; });
@@ -1317,7 +1425,9 @@ static int run_batch(int prec, int64_t count, const Args *args, const void *cons
         }
         h[i].aFastK = pl.tab->cn.aFastK;
         h[i].bFastK = pl.tab->cn.bFastK;
+        h[i].tsel = batch_tile_index(prec, pl.sched.tile);
     }
+    t_batch_scheds = bg->sids;
     // Replays share the device descriptors and workspace: order this one
     // after the previous replay even when the caller switched streams.
     if (hipStreamWaitEvent(s, bg->done[b ^ 1], 0) != hipSuccess) return GETT_ERR_HIP;
@@ -1422,8 +1532,9 @@ int sgett_fp8(int64_t ranka, const int64_t *exta, const int64_t *inca, const flo
     return run(kFP8, GETT_ARGS_MAKE, A, B, C);
 }
 
-int sgett_fp8_quantize(int64_t rankx, const int64_t *extx, const int64_t *incx, const float *X,
-                       int64_t conts, const int64_t *contx, uint8_t *QX, int32_t *EX) {
+static int fp8_quantize_entry(int64_t rankx, const int64_t *extx, const int64_t *incx,
+                              const float *X, int64_t conts, const int64_t *contx, uint8_t *QX,
+                              int32_t *EX, int bs) {
     if (rankx < 0 || rankx > 64) return -1;
     if (rankx > 0 && !extx) return -2;
     int64_t n = 1;
@@ -1462,11 +1573,28 @@ int sgett_fp8_quantize(int64_t rankx, const int64_t *extx, const int64_t *incx, 
         return GETT_ERR_ALLOC;
     if (hipMemcpyAsync(d, h.data(), h.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess)
         return GETT_ERR_HIP;
-    rc = launch_fp8_quant(X, d, nullptr, R, R, d + R, K, rows_fast(rows, kk, 0), QX, EX, s);
+    rc = launch_fp8_quant(X, d, nullptr, R, R, d + R, K, rows_fast(rows, kk, 0), QX, EX, s, bs);
     (void)hipFreeAsync(d, s);
     // h must outlive the copy: wait for it
     if (hipStreamSynchronize(s) != hipSuccess && !rc) rc = GETT_ERR_HIP;
     return rc;
+}
+
+int sgett_fp8_quantize(int64_t rankx, const int64_t *extx, const int64_t *incx, const float *X,
+                       int64_t conts, const int64_t *contx, uint8_t *QX, int32_t *EX) {
+    return fp8_quantize_entry(rankx, extx, incx, X, conts, contx, QX, EX, 128);
+}
+
+int sgett_mxfp8_quantize(int64_t rankx, const int64_t *extx, const int64_t *incx, const float *X,
+                         int64_t conts, const int64_t *contx, uint8_t *QX, int32_t *EX) {
+    return fp8_quantize_entry(rankx, extx, incx, X, conts, contx, QX, EX, 32);
+}
+
+int sgett_mxfp8(int64_t ranka, const int64_t *exta, const int64_t *inca, const float *A,
+                int64_t rankb, const int64_t *extb, const int64_t *incb, const float *B,
+                int64_t conts, const int64_t *conta, const int64_t *contb, const int64_t *perm,
+                const int64_t *incc, float *C) {
+    return run(kFP8, GETT_ARGS_MAKE, A, B, C, kOne, kOne, 32);
 }
 
 int sgett_batch(int64_t count, int64_t prec, const int64_t *ranka, const int64_t *const *exta,
@@ -1598,6 +1726,13 @@ int gett_set_schedule(int64_t id) {
     return 0;
 }
 int64_t gett_last_schedule(void) { return t_last_schedule; }
+
+int64_t gett_batch_last_schedules(int64_t *ids, int64_t n) {
+    const int64_t m = (int64_t)t_batch_scheds.size();
+    if (ids)
+        for (int64_t i = 0; i < n && i < m; ++i) ids[i] = t_batch_scheds[i];
+    return m;
+}
 
 int64_t gett_addr_violations(int reset) {
 #ifdef GETT_ADDR_CHECK
@@ -1765,6 +1900,7 @@ int gett_finalize(void) {
         g_tuned_db.clear();
         g_tuned_db_read = false;   // a later tuning reads GETT_TUNE_DB again
     }
+    unary_release();
     std::lock_guard<std::mutex> lk(g_pred_mu);
     g_pred.reset();
     return rc;

@@ -29,6 +29,12 @@ struct ScaleModes {
 // C <- beta * C (beta = (re, im); zero writes zeros without reading C).
 int launch_scale_c(int prec, void *C, const ScaleModes &m, const double *beta, hipStream_t s);
 
+// The current device, checked once per device to be gfx950 (0, or
+// GETT_ERR_HIP / GETT_ERR_DEVICE).
+int current_device_checked(int *dev);
+// Releases the unary operations' plan cache (gett_finalize).
+void unary_release();
+
 // Kernel launchers (defined in the .hip files).
 int launch_tile(int prec, int tile, bool aFastK, bool bFastK, const TileParams &p,
                 hipStream_t s);
@@ -53,12 +59,14 @@ int64_t addr_violations(int prec, bool reset);
 // whose rows, not their contracted positions, are the cheap direction); it
 // walks the rows in the order of offR, and rowMap (NULL: identity) gives the
 // output row of each.
+// bs: contracted positions per scale, 128 or 32 (MX-style); E holds
+// 128 / bs exponents per row and 128-block.
 int launch_fp8_quant(const float *X, const int64_t *offR, const int32_t *rowMap, int64_t rows,
                      int64_t rowsPad, const int64_t *offK, int64_t K, bool rowsFast, uint8_t *Q,
-                     int32_t *E, hipStream_t s);
+                     int32_t *E, hipStream_t s, int bs);
 int launch_fp8_gemm(int tile, const uint8_t *QA, const int32_t *EA, const uint8_t *QB,
                     const int32_t *EB, float *C, const int64_t *offCM, const int64_t *offCN,
-                    int64_t M, int64_t N, int64_t K, hipStream_t s);
+                    int64_t M, int64_t N, int64_t K, hipStream_t s, int bs);
 
 // MLP kernels.
 int launch_mlp_linear_fwd(const float *X, const float *W, const float *b, float *Y, int64_t batch,

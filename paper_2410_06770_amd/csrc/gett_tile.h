@@ -430,6 +430,46 @@ __device__ __forceinline__ void mma_stage(typename PrecT<PREC>::Acc (&acc)[BM / 
     }
 }
 
+// MFMA work of one staged K step of the BF16x3 tiles that load two steps
+// ahead: hi*hi into acc, hi*lo + lo*hi into acx.
+template <int BM, int BN, int BK>
+__device__ __forceinline__ void mma_stage_split(f4_t (&acc)[BM / 32][BN / 32],
+                                                f4_t (&acx)[BM / 32][BN / 32],
+                                                const unsigned char *stA, const unsigned char *stB,
+                                                int lane, int wm, int wn) {
+    using Cfg = TileCfg<kBF3, BM, BN, BK>;
+    constexpr int FM = Cfg::FM, FN = Cfg::FN;
+    const __bf16 *ahi = reinterpret_cast<const __bf16 *>(stA);
+    const __bf16 *alo = ahi + BM * Cfg::LA::kLd;
+    const __bf16 *bhi = reinterpret_cast<const __bf16 *>(stB);
+    const __bf16 *blo = bhi + BN * Cfg::LB::kLd;
+#pragma unroll
+    for (int ks = 0; ks < BK / 32; ++ks) {
+        const int kc = ks * 32 + 8 * (lane >> 4);
+        bf8_t ah[FM], al[FM], bh[FN], bl[FN];
+#pragma unroll
+        for (int i = 0; i < FM; ++i) {
+            const int r = wm * Cfg::WTM + i * 16 + (lane & 15);
+            ah[i] = *reinterpret_cast<const bf8_t *>(ahi + r * Cfg::LA::kLd + kc);
+            al[i] = *reinterpret_cast<const bf8_t *>(alo + r * Cfg::LA::kLd + kc);
+        }
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+            const int r = wn * Cfg::WTN + j * 16 + (lane & 15);
+            bh[j] = *reinterpret_cast<const bf8_t *>(bhi + r * Cfg::LB::kLd + kc);
+            bl[j] = *reinterpret_cast<const bf8_t *>(blo + r * Cfg::LB::kLd + kc);
+        }
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j) {
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+                acx[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acx[i][j], 0, 0, 0);
+                acx[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acx[i][j], 0, 0, 0);
+            }
+    }
+}
+
 // One BM x BN tile over contracted range [kbeg, kend), reading A and B from
 // pA and pB and updating C at pC (the call's pointers, moved to a Hadamard
 // position when there is one); `slice` numbers the tile's FP64 partial-sum
@@ -490,8 +530,7 @@ __device__ __forceinline__ void gett_tile(const TileParams &p, const void *pA, c
     // slice.  The values are never used.  A loop without branches lets the
     // accumulators live in the MFMA registers throughout.
     constexpr int DEPTH = tile_depth(PREC, BM, BN, BK);
-    static_assert(DEPTH == 1 || (DEPTH == 2 && !kTwoAcc),
-                  "load depth (BF16x3 and complex tiles use 1)");
+    static_assert(DEPTH == 1 || (DEPTH == 2 && !kCplx), "load depth (complex tiles use 1)");
     int64_t nsteps = (kend - kbeg + BK - 1) / BK;
     if constexpr (DEPTH == 2) nsteps += nsteps & 1;   // pairs of steps (one may be all zeros)
     const int64_t kfirst = kend - nsteps * BK;       // may lie below kbeg (and below 0)
@@ -661,7 +700,8 @@ __device__ __forceinline__ void gett_tile(const TileParams &p, const void *pA, c
             ga.template load_with<false>(koa, k2, kbeg, va);
             gb.template load_with<false>(kob, k2, kbeg, vb);
             if constexpr (O32 || tile_load_fence(PREC, BM, BN, BK)) __builtin_amdgcn_sched_barrier(0);
-            mma_stage<PREC, BM, BN, BK>(acc, stageA(0), stageB(0), lane, wm, wn);
+            if constexpr (kSplit) mma_stage_split<BM, BN, BK>(acc, acx, stageA(0), stageB(0), lane, wm, wn);
+            else mma_stage<PREC, BM, BN, BK>(acc, stageA(0), stageB(0), lane, wm, wn);
             ga.store(stageA(1), va2);
             gb.store(stageB(1), vb2);
             __syncthreads();
@@ -677,7 +717,8 @@ __device__ __forceinline__ void gett_tile(const TileParams &p, const void *pA, c
             ga.template load_with<false>(koa, k3, kbeg, va2);
             gb.template load_with<false>(kob, k3, kbeg, vb2);
             if constexpr (O32 || tile_load_fence(PREC, BM, BN, BK)) __builtin_amdgcn_sched_barrier(0);
-            mma_stage<PREC, BM, BN, BK>(acc, stageA(1), stageB(1), lane, wm, wn);
+            if constexpr (kSplit) mma_stage_split<BM, BN, BK>(acc, acx, stageA(1), stageB(1), lane, wm, wn);
+            else mma_stage<PREC, BM, BN, BK>(acc, stageA(1), stageB(1), lane, wm, wn);
             ga.store(stageA(0), va);
             gb.store(stageB(0), vb);
             __syncthreads();
@@ -832,18 +873,40 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(TileParams p) {
 // Batched launch: one persistent grid walks a work list of (problem, tile,
 // K slice) items, longest first, each workgroup taking the next unclaimed
 // item from a counter (so one that drew long items takes fewer); every item
-// runs the same tile code as a single call with the 64x64 tile of the
-// precision.  Each problem's
-// descriptor says which operands read along K, and a uniform switch picks the
-// matching compiled loader variant.
+// runs the same tile code as a single call.  Each problem's descriptor says
+// which of the batch tiles it runs (its own schedule) and which operands
+// read along K, and a uniform switch picks the matching compiled variant.
 // ---------------------------------------------------------------------------
+template <int PREC, int TS>
+__device__ __forceinline__ void batch_item(const TileParams &p, int aFastK, int bFastK, int tile,
+                                           unsigned char *smem) {
+    constexpr TileShape ts = kTiles[PREC][kBatchTile[PREC][TS]];
+    // A problem cut along K numbers its items slice-major: slice z covers
+    // [z kPerSplit, min(K, (z+1) kPerSplit)) and writes FP64 partials.
+    const int32_t tilesMN = p.tilesM * p.tilesN;
+    const int32_t split = tile / tilesMN;
+    int tm, tn;
+    tile_coords(tile - split * tilesMN, p.tilesM, p.tilesN, tm, tn);
+    const int64_t m0 = (int64_t)tm * ts.bm, n0 = (int64_t)tn * ts.bn;
+    const int64_t kbeg = (int64_t)split * p.kPerSplit;
+    const int64_t kend = min(p.K, kbeg + p.kPerSplit);
+    const int variant = aFastK * 2 + bFastK;
+    if (variant == 0)
+        gett_tile<PREC, ts.bm, ts.bn, ts.bk, false, false>(p, p.A, p.B, p.C, m0, n0, kbeg, kend, split, smem);
+    else if (variant == 1)
+        gett_tile<PREC, ts.bm, ts.bn, ts.bk, false, true>(p, p.A, p.B, p.C, m0, n0, kbeg, kend, split, smem);
+    else if (variant == 2)
+        gett_tile<PREC, ts.bm, ts.bn, ts.bk, true, false>(p, p.A, p.B, p.C, m0, n0, kbeg, kend, split, smem);
+    else
+        gett_tile<PREC, ts.bm, ts.bn, ts.bk, true, true>(p, p.A, p.B, p.C, m0, n0, kbeg, kend, split, smem);
+}
+
 template <int PREC>
 __global__ __launch_bounds__(kThreads) void gett_batch_kernel(const BatchProblem *__restrict__ probs,
                                                               const int32_t *__restrict__ items,
                                                               int32_t nitems, int32_t *next) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int32_t s_item;
-    constexpr TileShape ts = kTiles[PREC][0];
     // *next starts at 0 (the launch's descriptor copy clears it); every
     // workgroup leaves once the count has passed the last item.
     for (;;) {
@@ -855,24 +918,10 @@ __global__ __launch_bounds__(kThreads) void gett_batch_kernel(const BatchProblem
         const int32_t tile = items[2 * it + 1];
         const BatchProblem &bp = probs[pi];
         const TileParams p = bp.p;
-        // A problem cut along K numbers its items slice-major: slice z covers
-        // [z kPerSplit, min(K, (z+1) kPerSplit)) and writes FP64 partials.
-        const int32_t tilesMN = p.tilesM * p.tilesN;
-        const int32_t split = tile / tilesMN;
-        int tm, tn;
-        tile_coords(tile - split * tilesMN, p.tilesM, p.tilesN, tm, tn);
-        const int64_t m0 = (int64_t)tm * ts.bm, n0 = (int64_t)tn * ts.bn;
-        const int64_t kbeg = (int64_t)split * p.kPerSplit;
-        const int64_t kend = min(p.K, kbeg + p.kPerSplit);
-        const int variant = bp.aFastK * 2 + bp.bFastK;
-        if (variant == 0)
-            gett_tile<PREC, ts.bm, ts.bn, ts.bk, false, false>(p, p.A, p.B, p.C, m0, n0, kbeg, kend, split, smem);
-        else if (variant == 1)
-            gett_tile<PREC, ts.bm, ts.bn, ts.bk, false, true>(p, p.A, p.B, p.C, m0, n0, kbeg, kend, split, smem);
-        else if (variant == 2)
-            gett_tile<PREC, ts.bm, ts.bn, ts.bk, true, false>(p, p.A, p.B, p.C, m0, n0, kbeg, kend, split, smem);
+        if (bp.tsel == 0)
+            batch_item<PREC, 0>(p, bp.aFastK, bp.bFastK, tile, smem);
         else
-            gett_tile<PREC, ts.bm, ts.bn, ts.bk, true, true>(p, p.A, p.B, p.C, m0, n0, kbeg, kend, split, smem);
+            batch_item<PREC, 1>(p, bp.aFastK, bp.bFastK, tile, smem);
         __syncthreads();   // the next item reuses the LDS stages and s_item
     }
 }
@@ -955,7 +1004,11 @@ static int launch_prec(int tile, bool afk, bool bfk, const TileParams &p, hipStr
 }
 
 template <int PREC> static int batch_lds() {
-    return TileCfg<PREC, kTiles[PREC][0].bm, kTiles[PREC][0].bn, kTiles[PREC][0].bk>::kLdsBytes;
+    constexpr TileShape t0 = kTiles[PREC][kBatchTile[PREC][0]];
+    constexpr TileShape t1 = kTiles[PREC][kBatchTile[PREC][1]];
+    constexpr int l0 = TileCfg<PREC, t0.bm, t0.bn, t0.bk>::kLdsBytes;
+    constexpr int l1 = TileCfg<PREC, t1.bm, t1.bn, t1.bk>::kLdsBytes;
+    return l0 > l1 ? l0 : l1;
 }
 
 template <int PREC> static int launch_splitk_reduce_prec(const TileParams &p, hipStream_t s) {

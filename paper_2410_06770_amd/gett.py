@@ -62,7 +62,7 @@ def lib():
     L = ct.CDLL(LIB_PATH)
     a14 = [i64, I64P, I64P, vp, i64, I64P, I64P, vp, i64, I64P, I64P, I64P, I64P, vp]
     for name in ("dgett", "sgett", "sgett_bf16x3", "sgett_fp8", "dgett_noalloc", "zgett",
-                 "cgett"):
+                 "cgett", "sgett_mxfp8"):
         getattr(L, name).argtypes = a14
         getattr(L, name).restype = ct.c_int
     ex17 = [i64, I64P, I64P, vp, i64, I64P, I64P, vp, i64, I64P, I64P, i64, I64P, I64P, I64P,
@@ -74,8 +74,16 @@ def lib():
     L.cgett_ex.argtypes = [vp] + ex17 + [vp, vp]
     for name in ("dgett_ex", "sgett_ex", "sgett_bf16x3_ex", "zgett_ex", "cgett_ex"):
         getattr(L, name).restype = ct.c_int
-    L.sgett_fp8_quantize.argtypes = [i64, I64P, I64P, vp, i64, I64P, vp, vp]
-    L.sgett_fp8_quantize.restype = ct.c_int
+    un11 = [i64, I64P, I64P, vp, i64, I64P, i64, I64P, I64P, I64P, I64P]
+    L.dgett_unary.argtypes = [ct.c_double] + un11 + [ct.c_double, vp]
+    L.sgett_unary.argtypes = [ct.c_float] + un11 + [ct.c_float, vp]
+    L.zgett_unary.argtypes = [vp] + un11 + [vp, vp]
+    L.cgett_unary.argtypes = [vp] + un11 + [vp, vp]
+    for name in ("dgett_unary", "sgett_unary", "zgett_unary", "cgett_unary"):
+        getattr(L, name).restype = ct.c_int
+    for name in ("sgett_fp8_quantize", "sgett_mxfp8_quantize"):
+        getattr(L, name).argtypes = [i64, I64P, I64P, vp, i64, I64P, vp, vp]
+        getattr(L, name).restype = ct.c_int
     for name in ("sgett_batch", "dgett_batch"):
         # array arguments are passed as raw addresses of numpy buffers
         getattr(L, name).argtypes = [i64, i64] + [vp] * 15
@@ -89,6 +97,8 @@ def lib():
     L.gett_tile_shape.argtypes = [ct.c_int, i64, I64P]
     L.gett_set_schedule.argtypes = [i64]
     L.gett_last_schedule.restype = i64
+    L.gett_batch_last_schedules.argtypes = [I64P, i64]
+    L.gett_batch_last_schedules.restype = i64
     L.gett_set_max_workspace.argtypes = [i64]
     L.gett_set_max_workspace.restype = ct.c_int
     L.gett_addr_violations.argtypes = [ct.c_int]
@@ -230,11 +240,59 @@ def cgett_ex(alpha, ranka, exta, inca, A, rankb, extb, incb, B, conts, conta, co
         incc), _cpair(beta, ct.c_float), vp(C) if C else None)
 
 
+def _unary_args(ranka, exta, inca, A, nsum, suma, ntr, tra, trb, perm, incc):
+    return (int(ranka), _arr(exta), _arr(inca), vp(A) if A else None, int(nsum), _arr(suma),
+            int(ntr), _arr(tra), _arr(trb), _arr(perm), _arr(incc))
+
+
+def dgett_unary(alpha, ranka, exta, inca, A, nsum, suma, ntr, tra, trb, perm, incc, beta,
+                C) -> int:
+    return lib().dgett_unary(float(alpha), *_unary_args(ranka, exta, inca, A, nsum, suma, ntr,
+                                                        tra, trb, perm, incc), float(beta),
+                             vp(C) if C else None)
+
+
+def sgett_unary(alpha, ranka, exta, inca, A, nsum, suma, ntr, tra, trb, perm, incc, beta,
+                C) -> int:
+    return lib().sgett_unary(float(alpha), *_unary_args(ranka, exta, inca, A, nsum, suma, ntr,
+                                                        tra, trb, perm, incc), float(beta),
+                             vp(C) if C else None)
+
+
+def zgett_unary(alpha, ranka, exta, inca, A, nsum, suma, ntr, tra, trb, perm, incc, beta,
+                C) -> int:
+    return lib().zgett_unary(_cpair(alpha, ct.c_double), *_unary_args(
+        ranka, exta, inca, A, nsum, suma, ntr, tra, trb, perm, incc),
+        _cpair(beta, ct.c_double), vp(C) if C else None)
+
+
+def cgett_unary(alpha, ranka, exta, inca, A, nsum, suma, ntr, tra, trb, perm, incc, beta,
+                C) -> int:
+    return lib().cgett_unary(_cpair(alpha, ct.c_float), *_unary_args(
+        ranka, exta, inca, A, nsum, suma, ntr, tra, trb, perm, incc),
+        _cpair(beta, ct.c_float), vp(C) if C else None)
+
+
+UNARY_ENTRY = {GETT_FP64: dgett_unary, GETT_FP32: sgett_unary, GETT_Z64: zgett_unary,
+               GETT_C32: cgett_unary}
+
 EX_ENTRY = {GETT_FP64: dgett_ex, GETT_FP32: sgett_ex, GETT_BF16X3: sgett_bf16x3_ex,
             GETT_Z64: zgett_ex, GETT_C32: cgett_ex}
 
 ENTRY = {GETT_FP64: dgett, GETT_FP32: sgett, GETT_BF16X3: sgett_bf16x3, GETT_FP8: sgett_fp8,
          GETT_Z64: zgett, GETT_C32: cgett}
+
+
+def sgett_mxfp8(ranka, exta, inca, A, rankb, extb, incb, B, conts, conta, contb, perm, incc,
+                C) -> int:
+    return _call14("sgett_mxfp8", ranka, exta, inca, A, rankb, extb, incb, B, conts, conta,
+                   contb, perm, incc, C)
+
+
+def sgett_mxfp8_quantize(rankx, extx, incx, X, conts, contx, QX, EX) -> int:
+    return lib().sgett_mxfp8_quantize(int(rankx), _arr(extx), _arr(incx), vp(X) if X else None,
+                                      int(conts), _arr(contx), vp(QX) if QX else None,
+                                      vp(EX) if EX else None)
 
 
 def sgett_fp8_quantize(rankx, extx, incx, X, conts, contx, QX, EX) -> int:
@@ -345,6 +403,15 @@ def gett_set_schedule(sched_id: int) -> int:
 
 def gett_last_schedule() -> int:
     return int(lib().gett_last_schedule())
+
+
+def gett_batch_last_schedules(n: int):
+    """Schedule id each problem of the calling thread's last batch ran
+    (-1 for a problem with nothing to compute)."""
+    m = int(lib().gett_batch_last_schedules(None, 0))
+    buf = (ct.c_int64 * max(m, 1))()
+    lib().gett_batch_last_schedules(buf, m)
+    return [int(x) for x in buf[:min(m, n)]]
 
 
 def gett_set_max_workspace(nbytes: int) -> int:

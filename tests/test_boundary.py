@@ -214,3 +214,36 @@ def test_valid_scaled_calls_pass_the_checks():
     call fails with a runtime code (> 0), never an INFO."""
     for fn in ("dgett_ex", "sgett_ex", "sgett_bf16x3_ex", "zgett_ex", "cgett_ex"):
         assert call_ex(getattr(gett, fn)) > 0
+
+
+UN_OK = dict(alpha=1.0, ranka=4, exta=[3, 4, 3, 5], inca=[1, 3, 12, 36], nsum=1, suma=[1],
+             ntr=1, tra=[0], trb=[2], perm=[0], incc=[1], beta=0.0)
+
+
+def call_un(fn, A=8, C=8, **kw):
+    d = dict(UN_OK)
+    d.update(kw)
+    return fn(d["alpha"], d["ranka"], d["exta"], d["inca"], A, d["nsum"], d["suma"], d["ntr"],
+              d["tra"], d["trb"], d["perm"], d["incc"], d["beta"], C)
+
+
+# INFO of the unary calls, numbered in their argument order (ALPHA, RANKA,
+# EXTA, INCA, A, NSUM, SUMA, NTR, TRA, TRB, PERM, INCC, BETA, C).
+UN_BAD = [(-2, dict(ranka=-1)), (-2, dict(ranka=65)), (-3, dict(exta=[3, -4, 3, 5])),
+          (-4, dict(inca=[1, 3, 12, 2 ** 62])), (-5, dict(A=0)), (-6, dict(nsum=5)),
+          (-7, dict(suma=[4])), (-8, dict(ntr=2)), (-9, dict(tra=[1])), (-9, dict(tra=[7])),
+          (-10, dict(trb=[0])), (-10, dict(trb=[3])), (-11, dict(perm=[1])),
+          (-12, dict(incc=[0])), (-14, dict(C=0))]
+
+
+@pytest.mark.parametrize("code,kw", UN_BAD)
+@pytest.mark.parametrize("fn", ["dgett_unary", "sgett_unary", "zgett_unary", "cgett_unary"])
+def test_unary_info_codes(fn, code, kw):
+    assert call_un(getattr(gett, fn), **kw) == code
+
+
+def test_valid_unary_calls_pass_the_checks():
+    for fn in ("dgett_unary", "sgett_unary", "zgett_unary", "cgett_unary"):
+        assert call_un(getattr(gett, fn)) > 0
+    assert call_un(gett.zgett_unary, alpha=None) == -1
+    assert call_un(gett.cgett_unary, beta=None) == -13

@@ -128,33 +128,77 @@ def test_dgett_batch_paper_cases():
 
 
 def test_batch_equals_single_calls_bitwise():
-    """Single calls forced onto the batch tile (64x64, order 0, no split)
-    run the same code in the same order.  The batch cuts a problem along K
-    only when its tiles need more than 64 K steps (and more than the average
-    workgroup's share), so problems with at most 64 steps (K <= 64 * 32) are
-    compared bit for bit; the longer ones are checked against the oracle."""
+    """Each problem of a batch runs its own schedule (one of the batch tiles
+    and an N order, chosen by the policy); single calls forced onto the
+    problem's schedule run the same code in the same order.  The batch cuts
+    a problem along K only when its tiles need more than 64 steps of the
+    64 x 64 tile (and more than the average workgroup's share), so problems
+    within that are compared bit for bit; the longer ones are checked
+    against the oracle."""
     import torch
     problems = W.config_batch(48, seed=7)
     dev = upload(problems)
     rc, _ = run_batch(problems, dev, gett.GETT_BF16X3)
     assert rc == 0
+    scheds = gett.gett_batch_last_schedules(len(problems))
+    assert len(scheds) == len(problems)
+    tiles = {gett.schedule_of(sid)[0] for sid in scheds if sid >= 0}
+    print(f"\n[batch] tiles used: {sorted(tiles)}", flush=True)
+    assert len(tiles) >= 2            # both compiled batch tiles are in use
     batch_out = [d[2].cpu().numpy() for d in dev]
-    gett.gett_set_schedule(gett.schedule_id(0, 0, 0))
     try:
-        for pr, d in zip(problems, dev):
+        for pr, d, sid in zip(problems, dev, scheds):
+            assert gett.schedule_of(sid)[2] == 0
+            gett.gett_set_schedule(sid)
             d[2].copy_(torch.from_numpy(pr.C.buf).cuda())
             assert call14(gett.sgett_bf16x3, pr, d[3], d[4], d[5]) == 0
         torch.cuda.synchronize()
     finally:
         gett.gett_set_schedule(-1)
     short = 0
-    for pr, d, bo in zip(problems, dev, batch_out):
-        if pr.mnk()[2] <= 64 * 32:
+    for pr, d, bo, sid in zip(problems, dev, batch_out, scheds):
+        # a K step of a tile counts its area over 64 x 64 in the batch's
+        # balance, so a problem is never cut when steps * area <= 64
+        bm, bn, bk = gett.gett_tile_shape(gett.GETT_BF16X3, gett.schedule_of(sid)[0])
+        if -(-pr.mnk()[2] // bk) * (bm * bn) / 4096 <= 64:
             assert np.array_equal(d[2].cpu().numpy(), bo), pr.name
             short += 1
         else:
             check_problem(pr, bo, gett.GETT_BF16X3)
-    assert short >= 40
+    assert short >= 30
+
+
+@pytest.mark.parametrize("policy", [gett.GETT_HEURISTIC, gett.GETT_AUTOTUNE])
+def test_batch_schedules_follow_the_policy(policy):
+    """Under the heuristic and the autotuner every problem gets a batch
+    schedule (a batch tile, any N order, K unsplit); a forced batch schedule
+    applies to every problem; results meet their bounds either way."""
+    import torch
+    problems = W.config_batch(32, seed=12)
+    dev = upload(problems)
+    old = gett.gett_get_policy()
+    try:
+        gett.gett_set_policy(policy)
+        rc, info = run_batch(problems, dev, gett.GETT_BF16X3)
+        assert rc == 0 and all(i == 0 for i in info)
+        scheds = gett.gett_batch_last_schedules(len(problems))
+        for sid in scheds:
+            t, o, sp = gett.schedule_of(sid)
+            assert sp == 0 and t in (0, 2)
+        for pr, d in zip(problems, dev):
+            check_problem(pr, d[2].cpu().numpy(), gett.GETT_BF16X3)
+        forced = gett.schedule_id(2, 1, 0)
+        gett.gett_set_schedule(forced)
+        for pr, d in zip(problems, dev):
+            d[2].copy_(torch.from_numpy(pr.C.buf).cuda())
+        rc, _ = run_batch(problems, dev, gett.GETT_BF16X3)
+        assert rc == 0
+        assert set(gett.gett_batch_last_schedules(len(problems))) == {forced}
+        for pr, d in zip(problems, dev):
+            check_problem(pr, d[2].cpu().numpy(), gett.GETT_BF16X3)
+    finally:
+        gett.gett_set_schedule(-1)
+        gett.gett_set_policy(old)
 
 
 @pytest.mark.parametrize("prec", [gett.GETT_BF16X3, gett.GETT_FP64])
