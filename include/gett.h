@@ -128,9 +128,9 @@ int sgett(int64_t ranka, const int64_t *exta, const int64_t *inca, const float *
 
 /* SGETT with split BF16x3 products: every FP32 value x is split into
    hi = bf16(x) and lo = bf16(x - hi) (round to nearest even); the product
-   a*b is formed as hi_a*hi_b + hi_a*lo_b + lo_a*hi_b on BF16 MFMA with FP32
-   accumulation, the hi*hi and cross terms in separate accumulators, which are
-   summed with C_in in FP64 and rounded once to FP32.  Finite inputs only. */
+   a*b is formed as hi_a*hi_b + hi_a*lo_b + lo_a*hi_b on BF16 MFMA, all three
+   accumulated in one FP32 sum, which is added to C_in in FP64 and rounded
+   once to FP32.  Finite inputs only. */
 int sgett_bf16x3(int64_t ranka, const int64_t *exta, const int64_t *inca, const float *A,
                  int64_t rankb, const int64_t *extb, const int64_t *incb, const float *B,
                  int64_t conts, const int64_t *conta, const int64_t *contb, const int64_t *perm,

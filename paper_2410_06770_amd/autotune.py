@@ -7,7 +7,7 @@ schedule that is not valid for the signature), as measured by the library's
 own ``gett_autotune`` (HIP events on the current stream).  Values are drawn on
 the GPU (normal(0,1)); the timings do not depend on them.
 
-    python -m paper_2410_06770_amd.autotune --db timing.jsonl --count 4000
+    python -m paper_2410_06770_amd.autotune --db timing.jsonl --count 10000 --heldout-first 1000
 """
 from __future__ import annotations
 
@@ -97,8 +97,16 @@ def time_signature(sig, layout, prec, rng, warmup=0, reps=3):
     return row
 
 
+def collect_order(count, first=()):
+    """Signature indices in timing order: those in `first` (ascending), then
+    the rest ascending."""
+    head = sorted(set(int(i) for i in first if 0 <= i < count))
+    hs = set(head)
+    return head + [i for i in range(count) if i not in hs]
+
+
 def collect(db_path, count=4000, seed=5, prec=BF16X3, flop_range=(1e6, 1e11), max_seconds=None,
-            log=sys.stderr):
+            first=(), log=sys.stderr):
     import torch
     gett.lib()
     gett.use_torch_stream()
@@ -106,7 +114,8 @@ def collect(db_path, count=4000, seed=5, prec=BF16X3, flop_range=(1e6, 1e11), ma
     sigs = W.predictor_signatures(count, seed=seed, flop_range=flop_range)
     t0 = time.time()
     done = 0
-    for i, (sig, layout) in enumerate(sigs):
+    for i in collect_order(count, first):
+        sig, layout = sigs[i]
         key = signature_key(sig, layout, prec)
         if key in db:
             continue
@@ -132,8 +141,14 @@ def main():
     ap.add_argument("--count", type=int, default=4000)
     ap.add_argument("--seed", type=int, default=5)
     ap.add_argument("--max-seconds", type=float, default=None)
+    ap.add_argument("--heldout-first", type=int, default=0,
+                    help="time the predictor's first N held-out signatures before the rest")
     args = ap.parse_args()
-    db = collect(args.db, args.count, args.seed, max_seconds=args.max_seconds)
+    first = ()
+    if args.heldout_first:
+        from .predictor import heldout_indices
+        first = heldout_indices(args.heldout_first, universe=args.count)
+    db = collect(args.db, args.count, args.seed, max_seconds=args.max_seconds, first=first)
     print(f"[autotune] database holds {len(db.rows)} signatures", flush=True)
 
 

@@ -431,10 +431,9 @@ __device__ __forceinline__ void mma_stage(typename PrecT<PREC>::Acc (&acc)[BM / 
 }
 
 // MFMA work of one staged K step of the BF16x3 tiles that load two steps
-// ahead: hi*hi into acc, hi*lo + lo*hi into acx.
+// ahead: hi*hi, hi*lo and lo*hi, all into acc.
 template <int BM, int BN, int BK>
 __device__ __forceinline__ void mma_stage_split(f4_t (&acc)[BM / 32][BN / 32],
-                                                f4_t (&acx)[BM / 32][BN / 32],
                                                 const unsigned char *stA, const unsigned char *stB,
                                                 int lane, int wm, int wn) {
     using Cfg = TileCfg<kBF3, BM, BN, BK>;
@@ -464,8 +463,8 @@ __device__ __forceinline__ void mma_stage_split(f4_t (&acc)[BM / 32][BN / 32],
 #pragma unroll
             for (int j = 0; j < FN; ++j) {
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
-                acx[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acx[i][j], 0, 0, 0);
-                acx[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acx[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
             }
     }
 }
@@ -485,7 +484,11 @@ __device__ __forceinline__ void gett_tile(const TileParams &p, const void *pA, c
     constexpr int FM = Cfg::FM, FN = Cfg::FN;
     constexpr bool kSplit = PREC == kBF3;
     constexpr bool kCplx = prec_complex(PREC);
-    constexpr bool kTwoAcc = kSplit || kCplx;   // BF16x3: hi*hi | cross terms; complex: re | im
+    // Complex tiles keep the real and imaginary sums apart (acc | acx).  The
+    // BF16x3 tiles add all three products into one FP32 set: the cross
+    // terms are 2^-8 of hi*hi, so a second set would save little rounding
+    // and costs occupancy.
+    constexpr bool kTwoAcc = kCplx;
 
     const int t = threadIdx.x;
     const int lane = lane_id();
@@ -646,8 +649,8 @@ __device__ __forceinline__ void gett_tile(const TileParams &p, const void *pA, c
 #pragma unroll
                         for (int j = 0; j < FN; ++j) {
                             acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
-                            acx[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acx[i][j], 0, 0, 0);
-                            acx[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acx[i][j], 0, 0, 0);
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
                         }
                 }
             }
@@ -700,7 +703,7 @@ __device__ __forceinline__ void gett_tile(const TileParams &p, const void *pA, c
             ga.template load_with<false>(koa, k2, kbeg, va);
             gb.template load_with<false>(kob, k2, kbeg, vb);
             if constexpr (O32 || tile_load_fence(PREC, BM, BN, BK)) __builtin_amdgcn_sched_barrier(0);
-            if constexpr (kSplit) mma_stage_split<BM, BN, BK>(acc, acx, stageA(0), stageB(0), lane, wm, wn);
+            if constexpr (kSplit) mma_stage_split<BM, BN, BK>(acc, stageA(0), stageB(0), lane, wm, wn);
             else mma_stage<PREC, BM, BN, BK>(acc, stageA(0), stageB(0), lane, wm, wn);
             ga.store(stageA(1), va2);
             gb.store(stageB(1), vb2);
@@ -717,7 +720,7 @@ __device__ __forceinline__ void gett_tile(const TileParams &p, const void *pA, c
             ga.template load_with<false>(koa, k3, kbeg, va2);
             gb.template load_with<false>(kob, k3, kbeg, vb2);
             if constexpr (O32 || tile_load_fence(PREC, BM, BN, BK)) __builtin_amdgcn_sched_barrier(0);
-            if constexpr (kSplit) mma_stage_split<BM, BN, BK>(acc, acx, stageA(1), stageB(1), lane, wm, wn);
+            if constexpr (kSplit) mma_stage_split<BM, BN, BK>(acc, stageA(1), stageB(1), lane, wm, wn);
             else mma_stage<PREC, BM, BN, BK>(acc, stageA(1), stageB(1), lane, wm, wn);
             ga.store(stageA(0), va);
             gb.store(stageB(0), vb);
@@ -749,8 +752,6 @@ __device__ __forceinline__ void gett_tile(const TileParams &p, const void *pA, c
                     if constexpr (kCplx) {
                         p.ws[2 * w] = (double)acc[i][j][v];
                         p.ws[2 * w + 1] = (double)acx[i][j][v];
-                    } else if constexpr (kSplit) {
-                        p.ws[w] = (double)acc[i][j][v] + (double)acx[i][j][v];
                     } else {
                         p.ws[w] = (double)acc[i][j][v];
                     }
@@ -765,7 +766,7 @@ __device__ __forceinline__ void gett_tile(const TileParams &p, const void *pA, c
                         const float al = (float)p.alpha[0], be = (float)p.beta[0];
                         Cp[off] = rdC ? be * Cp[off] + al * r : al * r;
                     } else if constexpr (PREC == kBF3) {
-                        const double sum = (double)acc[i][j][v] + (double)acx[i][j][v];
+                        const double sum = (double)acc[i][j][v];
                         Cp[off] = (float)(rdC ? p.alpha[0] * sum + p.beta[0] * (double)Cp[off]
                                               : p.alpha[0] * sum);
                     } else {

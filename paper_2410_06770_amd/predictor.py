@@ -211,9 +211,23 @@ def dataset(rows, tau=0.05):
     return F, T, times
 
 
-def split_heldout(n, n_heldout, seed=55):
-    perm = np.random.default_rng(seed).permutation(n)
-    return np.sort(perm[n_heldout:]), np.sort(perm[:n_heldout])
+UNIVERSE = 10000     # signatures drawn for the timing database (seed 5)
+
+
+def heldout_indices(n_heldout, universe=UNIVERSE, seed=55):
+    """Signature indices held out of training: the first n_heldout of a
+    seeded permutation of the universe."""
+    return np.sort(np.random.default_rng(seed).permutation(universe)[:n_heldout])
+
+
+def split_rows(rows, n_heldout, universe=UNIVERSE, seed=55):
+    """Training and held-out row positions.  A row is held out when its
+    signature index is held out, so a database that holds only part of the
+    universe (timed held-out signatures first) splits the same way."""
+    held = set(heldout_indices(n_heldout, universe, seed).tolist())
+    te = np.array([i for i, r in enumerate(rows) if r["index"] in held], dtype=np.int64)
+    tr = np.array([i for i, r in enumerate(rows) if r["index"] not in held], dtype=np.int64)
+    return tr, te
 
 
 def save_checkpoint(m, path, epoch, losses):
@@ -305,8 +319,7 @@ def main():
     gett.use_torch_stream()
     rows = load_rows(args.db)
     F, T, times = dataset(rows)
-    n_held = min(args.heldout, len(rows) // 4)
-    tr, te = split_heldout(len(rows), n_held)
+    tr, te = split_rows(rows, args.heldout)
     m, losses = train(F[tr], T[tr], epochs=args.epochs, log=sys.stderr, checkpoint=args.checkpoint)
     m.save(args.out)
     mlp_r, heur_r, _ = evaluate(m, [rows[i] for i in te], F[te], times[te])

@@ -288,8 +288,8 @@ def test_network_beats_heuristic_on_heldout_signatures():
         pytest.skip("timing database not collected")
     rows = P.load_rows(DB)
     F, T, times = P.dataset(rows)
-    n_held = min(1000, len(rows) // 4)
-    tr, te = P.split_heldout(len(rows), n_held)
+    tr, te = P.split_rows(rows, 1000)
+    assert len(te) >= 500 and len(tr) >= 2000
     m, losses = P.train(F[tr], T[tr], epochs=150)
     mlp_r, heur_r, _ = P.evaluate(m, [rows[i] for i in te], F[te], times[te])
     print(f"\n[predictor] held-out {len(te)}: mlp {mlp_r} heuristic {heur_r}")
