@@ -1,0 +1,38 @@
+// gett_bf3pack.h -- launch descriptors of the packed BF16x3 path (pack pass
+// and GEMM on the packed rows).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gett {
+
+constexpr int kPackedBM = 128, kPackedBN = 128;   // GEMM tile of the packed path
+constexpr int kPackedBK = 32;                     // packed positions per step
+constexpr int64_t kPackedMaxKq = (int64_t)1 << 24;   // row length limit (32-bit lane offsets)
+
+// Arguments of one packed GEMM launch.  A and B hold the hi planes of the
+// packed operands ([rows][Kq] bfloat16, rows padded to the tile), the lo
+// planes follow at +planeA / +planeB elements.
+struct Bf3Packed {
+    const uint16_t *A, *B;
+    int64_t planeA, planeB;
+    int64_t Kq;          // packed row length (multiple of 32)
+    int64_t kPer;        // packed positions per K slice (multiple of 32)
+    int32_t tilesM, tilesN, splits, pad_;
+    float *C;
+    const int64_t *offCM, *offCN;
+    int64_t M, N;
+    double *ws;          // FP64 partials [split][M][N] when splits > 1, else null
+    double alpha, beta;  // C <- alpha * sum + beta * C_in (beta == 0: C_in not read)
+};
+
+// Pack one operand: rows R (table offR in GEMM order, or with rowsFast the
+// rows in the operand's memory order with rowMap giving each one's GEMM row)
+// into hi plane P and lo plane P + plane.
+int launch_bf3_pack(const float *X, const int64_t *offR, const int32_t *rowMap, int64_t R,
+                    const int64_t *offK, int64_t K, int64_t Kq, bool rowsFast, uint16_t *P,
+                    int64_t plane, hipStream_t s);
+int launch_bf3_packed_gemm(const Bf3Packed &g, hipStream_t s);
+
+}  // namespace gett

@@ -1,0 +1,334 @@
+// gett_bf3pack.hip -- the packed form of the BF16x3 path of SGETT.
+//
+// The direct BF16x3 tiles split every FP32 value into bfloat16 hi and lo
+// each time a tile loads it, so an element of A is split once per tile
+// column of C (and one of B once per tile row), and the split, with the
+// gather's address arithmetic, leaves the vector ALU with several times the
+// matrix-core instruction count.  The packed form splits each element once:
+//
+// pack:  every row of an operand (a free position, in the order of the
+//        schedule's offset tables) becomes two dense bfloat16 rows, hi and
+//        lo, of Kq = K rounded up to 32 positions (zeros past K), in two
+//        planes [rows][Kq].  The contracted positions are stored in a fixed
+//        permutation shared by both operands (the sum is over the same
+//        pairs): groups of 512 positions, group g holding S = min(512,
+//        Kq - 512 g) / 8 chunks of 8, and chunk c of a group holds the
+//        positions 512 g + c + S e, e = 0 .. 7.  So a wave whose lanes run
+//        along K reads 64 neighbouring positions per load and still writes
+//        one 16-byte chunk per lane and plane, and a wave whose lanes run
+//        along the rows reads 16 neighbouring rows per load (its rows are
+//        walked in the operand's memory order and written to their table
+//        position).
+// gemm:  a 128 x 128 tile (4 waves as 2 x 2) walks the packed rows in steps
+//        of 32 positions with 16-byte loads only (no offset tables, no
+//        conversion), stages them through LDS, and forms hi*hi + hi*lo +
+//        lo*hi on the BF16 MFMA with one FP32 accumulator per output, as the
+//        direct tiles do; the epilogue is theirs too (offset tables of C,
+//        alpha and beta in FP64, one rounding; or FP64 partials of a K slice).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gett_bf3pack.h"
+#include "gett_grid.h"
+#include "gett_internal.h"
+
+namespace gett {
+
+namespace {
+
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+typedef uint32_t u4_t __attribute__((ext_vector_type(4)));
+
+// hi = bf16(x) (round to nearest even), lo = bf16(x - hi) (the subtraction
+// is exact) for two values, packed with the first in the low half.
+__device__ __forceinline__ void split_pair(float x0, float x1, uint32_t &hi, uint32_t &lo) {
+    typedef float f2_t __attribute__((ext_vector_type(2)));
+    typedef __bf16 b2_t __attribute__((ext_vector_type(2)));
+    hi = __builtin_bit_cast(uint32_t, __builtin_convertvector(f2_t{x0, x1}, b2_t));
+    const float h0 = __uint_as_float(hi << 16), h1 = __uint_as_float(hi & 0xffff0000u);
+    lo = __builtin_bit_cast(uint32_t, __builtin_convertvector(f2_t{x0 - h0, x1 - h1}, b2_t));
+}
+
+__device__ __forceinline__ void split8(const float (&v)[8], u4_t &hi, u4_t &lo) {
+    uint32_t h[4], l[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) split_pair(v[2 * i], v[2 * i + 1], h[i], l[i]);
+    hi = u4_t{h[0], h[1], h[2], h[3]};
+    lo = u4_t{l[0], l[1], l[2], l[3]};
+}
+
+// Contracted position of element e of packed chunk c (see the file comment).
+__device__ __forceinline__ int64_t chunk_pos(int64_t c, int e, int64_t Kq) {
+    const int64_t g = c >> 6;
+    const int64_t S = min<int64_t>(512, Kq - 512 * g) >> 3;
+    return 512 * g + (c & 63) + S * e;
+}
+
+// Lanes along K: one wave per (row, group of 512 packed positions); lane l
+// fills chunk l of the group.
+__global__ __launch_bounds__(256) void bf3_pack_k_kernel(const float *__restrict__ X,
+                                                         const int64_t *__restrict__ offR,
+                                                         int64_t R, const int64_t *__restrict__ offK,
+                                                         int64_t K, int64_t Kq,
+                                                         uint16_t *__restrict__ P, int64_t plane) {
+    const int64_t ng = (Kq + 511) / 512;
+    const int64_t task = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (task >= R * ng) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t r = task / ng, g = task - r * ng;
+    const int64_t S = min<int64_t>(512, Kq - 512 * g) >> 3;
+    if (lane >= S) return;
+    const int64_t c = 64 * g + lane;
+    const float *xr = X + offR[r];
+    float v[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int64_t k = chunk_pos(c, e, Kq);
+        v[e] = k < K ? xr[offK[k]] : 0.0f;
+    }
+    u4_t hi, lo;
+    split8(v, hi, lo);
+    uint16_t *dst = P + r * Kq + 8 * c;
+    *reinterpret_cast<u4_t *>(dst) = hi;
+    *reinterpret_cast<u4_t *>(dst + plane) = lo;
+}
+
+// Lanes along the rows: one wave per (16 rows in the operand's memory order,
+// 4 chunks); lane l takes row p0 + l % 16 and chunk c0 + l / 16, so each load
+// reads 16 neighbouring rows and each row's four chunks are stored together.
+__global__ __launch_bounds__(256) void bf3_pack_rows_kernel(
+    const float *__restrict__ X, const int64_t *__restrict__ rowsOp,
+    const int32_t *__restrict__ rowMap, int64_t R, const int64_t *__restrict__ offK, int64_t K,
+    int64_t Kq, uint16_t *__restrict__ P, int64_t plane) {
+    const int64_t nc = Kq / 8;
+    const int64_t cq = (nc + 3) / 4;
+    const int64_t task = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int64_t rb = task / cq, q = task - rb * cq;
+    const int64_t p = rb * 16 + (lane & 15);
+    const int64_t c = q * 4 + (lane >> 4);
+    if (p >= R || c >= nc) return;
+    const float *xr = X + rowsOp[p];
+    float v[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int64_t k = chunk_pos(c, e, Kq);
+        v[e] = k < K ? xr[offK[k]] : 0.0f;
+    }
+    u4_t hi, lo;
+    split8(v, hi, lo);
+    uint16_t *dst = P + (int64_t)rowMap[p] * Kq + 8 * c;
+    *reinterpret_cast<u4_t *>(dst) = hi;
+    *reinterpret_cast<u4_t *>(dst + plane) = lo;
+}
+
+// LDS rows hold the 32 positions of a step, 64 bytes, unpadded; the four
+// 16-byte chunks of row r are stored in the order c ^ swz(r), which keeps
+// both the stores (four lanes per row, rows in lane order) and the MFMA
+// operand reads (16 rows per chunk) free of bank conflicts with 32 or 64
+// four-byte banks.  swz depends on bits 1-3 of r only.
+constexpr int kLd = 32;
+__device__ __forceinline__ int swz(int r) { return ((((r >> 1) ^ (r >> 3)) & 1) << 1) | ((r >> 2) & 1); }
+
+template <int BM, int BN> struct PkCfg {
+    static constexpr int WTM = BM / 2, WTN = BN / 2, FM = WTM / 16, FN = WTN / 16;
+    static constexpr int PA = BM * kLd, PB = BN * kLd;   // elements of one LDS plane
+    static constexpr int SA = 2 * PA, SB = 2 * PB;       // one stage: hi and lo planes
+    static constexpr int CA = BM * 8 / 256, CB = BN * 8 / 256;   // 16-byte chunks per thread
+    static constexpr int kLdsBytes = 2 * (SA + SB) * 2;
+};
+
+// Chunk i of thread t in a ROWS-row operand tile: four neighbouring threads
+// take the four 16-byte chunks of one row's 32 positions (a load reads 64
+// contiguous bytes of each of 16 rows); chunk i covers rows (64 i) % ROWS +
+// t / 4 of plane 64 i / ROWS (both fixed once unrolled).
+template <int ROWS> struct PkLoad {
+    static_assert(ROWS % 64 == 0, "64 rows per chunk index");
+    static constexpr int C = ROWS * 8 / 256;
+    uint32_t goff[C];   // element offset from the tile's base in the chunk's plane
+    uint32_t soff[C];   // element offset in an LDS stage
+    __device__ __forceinline__ void init(int t, int64_t Kq) {
+        const int c = t & 3, cs = c ^ swz(t >> 2);
+#pragma unroll
+        for (int i = 0; i < C; ++i) {
+            const int pl = 64 * i / ROWS, rr = (64 * i) % ROWS + (t >> 2);
+            goff[i] = (uint32_t)(rr * Kq + 8 * c);
+            soff[i] = (uint32_t)(pl * ROWS * kLd + rr * kLd + 8 * cs);
+        }
+    }
+    __device__ __forceinline__ void load(const uint16_t *hi, const uint16_t *lo,
+                                         u4_t (&v)[C]) const {
+#pragma unroll
+        for (int i = 0; i < C; ++i)
+            v[i] = *reinterpret_cast<const u4_t *>((64 * i / ROWS ? lo : hi) + goff[i]);
+    }
+    __device__ __forceinline__ void store(uint16_t *s, const u4_t (&v)[C]) const {
+#pragma unroll
+        for (int i = 0; i < C; ++i) *reinterpret_cast<u4_t *>(s + soff[i]) = v[i];
+    }
+};
+
+template <int BM, int BN>
+__device__ __forceinline__ void pk_mma(const uint16_t *sA, const uint16_t *sB, int lane, int wm,
+                                       int wn, f4_t (&acc)[BM / 32][BN / 32]) {
+    using Cfg = PkCfg<BM, BN>;
+    constexpr int FM = Cfg::FM, FN = Cfg::FN;
+    const __bf16 *ahi = reinterpret_cast<const __bf16 *>(sA);
+    const __bf16 *alo = ahi + Cfg::PA;
+    const __bf16 *bhi = reinterpret_cast<const __bf16 *>(sB);
+    const __bf16 *blo = bhi + Cfg::PB;
+    const int kc = 8 * ((lane >> 4) ^ swz(lane & 15));   // rows start at multiples of 16
+    bf8_t bh[FN], bl[FN];
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+        const int r = wn * Cfg::WTN + j * 16 + (lane & 15);
+        bh[j] = *reinterpret_cast<const bf8_t *>(bhi + r * kLd + kc);
+        bl[j] = *reinterpret_cast<const bf8_t *>(blo + r * kLd + kc);
+    }
+#pragma unroll
+    for (int i = 0; i < FM; ++i) {
+        const int r = wm * Cfg::WTM + i * 16 + (lane & 15);
+        const bf8_t ah = *reinterpret_cast<const bf8_t *>(ahi + r * kLd + kc);
+        const bf8_t al = *reinterpret_cast<const bf8_t *>(alo + r * kLd + kc);
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[j], acc[i][j], 0, 0, 0);
+        }
+    }
+}
+
+// One BM x BN output tile over the packed range of its K slice.  Two
+// register sets: the step s + 2 loads while step s runs on the matrix cores
+// and step s + 1 waits in the other set (loads past the last step repeat
+// it); two LDS stages, one barrier per step.
+template <int BM, int BN>
+__global__ __launch_bounds__(256) void bf3_packed_gemm_kernel(Bf3Packed g) {
+    using Cfg = PkCfg<BM, BN>;
+    constexpr int FM = Cfg::FM, FN = Cfg::FN;
+    extern __shared__ __align__(16) uint16_t lds[];
+    uint16_t *sA = lds, *sB = lds + 2 * Cfg::SA;   // [stage][plane][row][kLd]
+
+    const int tiles = g.tilesM * g.tilesN;
+    const int logical = xcd_remap(blockIdx.x, tiles * g.splits);
+    const int split = logical / tiles;
+    int tm, tn;
+    tile_coords(logical - split * tiles, g.tilesM, g.tilesN, tm, tn);
+    const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
+    const int64_t kbeg = (int64_t)split * g.kPer;
+    const int64_t kend = min(kbeg + g.kPer, g.Kq);
+    const int64_t nsteps = (kend - kbeg) / 32;
+
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6, wm = w >> 1, wn = w & 1;
+    PkLoad<BM> la;
+    PkLoad<BN> lb;
+    la.init(t, g.Kq);
+    lb.init(t, g.Kq);
+    const uint16_t *aH = g.A + m0 * g.Kq + kbeg, *aL = aH + g.planeA;
+    const uint16_t *bH = g.B + n0 * g.Kq + kbeg, *bL = bH + g.planeB;
+
+    f4_t acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
+
+    u4_t ra0[Cfg::CA], rb0[Cfg::CB], ra1[Cfg::CA], rb1[Cfg::CB];
+    auto step = [&](int64_t s) { return 32 * (s < nsteps ? s : nsteps - 1); };
+    la.load(aH, aL, ra0);
+    lb.load(bH, bL, rb0);
+    la.load(aH + step(1), aL + step(1), ra1);
+    lb.load(bH + step(1), bL + step(1), rb1);
+    la.store(sA, ra0);
+    lb.store(sB, rb0);
+    __syncthreads();
+    for (int64_t s = 0; s < nsteps; s += 2) {
+        // even step: LDS stage 0, set 1 waits for stage 1
+        const int64_t k2 = step(s + 2);
+        la.load(aH + k2, aL + k2, ra0);
+        lb.load(bH + k2, bL + k2, rb0);
+        pk_mma<BM, BN>(sA, sB, lane, wm, wn, acc);
+        __builtin_amdgcn_sched_barrier(0);
+        la.store(sA + Cfg::SA, ra1);
+        lb.store(sB + Cfg::SB, rb1);
+        __syncthreads();
+        // odd step: LDS stage 1, set 0 waits for stage 0 (with an odd step
+        // count the last one holds a repeat of the last step: not computed)
+        const int64_t k3 = step(s + 3);
+        la.load(aH + k3, aL + k3, ra1);
+        lb.load(bH + k3, bL + k3, rb1);
+        if (s + 1 < nsteps) pk_mma<BM, BN>(sA + Cfg::SA, sB + Cfg::SB, lane, wm, wn, acc);
+        __builtin_amdgcn_sched_barrier(0);
+        la.store(sA, ra0);
+        lb.store(sB, rb0);
+        __syncthreads();
+    }
+
+    // Epilogue: fragment (i, j), register v of lane l holds M row
+    // 4 (l / 16) + v and N column l % 16 of the fragment.
+    const bool rdC = g.beta != 0.0;
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+        const int64_t n = n0 + wn * Cfg::WTN + j * 16 + (lane & 15);
+        if (n >= g.N) continue;
+        const int64_t ocn = g.offCN[n];
+#pragma unroll
+        for (int i = 0; i < FM; ++i) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t m = m0 + wm * Cfg::WTM + i * 16 + 4 * (lane >> 4) + v;
+                if (m >= g.M) continue;
+                if (g.ws) {
+                    g.ws[((int64_t)split * g.M + m) * g.N + n] = (double)acc[i][j][v];
+                } else {
+                    const int64_t off = g.offCM[m] + ocn;
+                    const double sum = (double)acc[i][j][v];
+                    g.C[off] = (float)(rdC ? g.alpha * sum + g.beta * (double)g.C[off]
+                                           : g.alpha * sum);
+                }
+            }
+        }
+    }
+}
+
+}  // namespace
+
+int launch_bf3_pack(const float *X, const int64_t *offR, const int32_t *rowMap, int64_t R,
+                    const int64_t *offK, int64_t K, int64_t Kq, bool rowsFast, uint16_t *P,
+                    int64_t plane, hipStream_t s) {
+    if (R == 0) return 0;
+    const int64_t tasks = rowsFast ? (R + 15) / 16 * ((Kq / 8 + 3) / 4) : R * ((Kq + 511) / 512);
+    const int64_t blocks = (tasks + 3) / 4;
+    if (blocks > INT32_MAX) return GETT_ERR_INTERNAL;
+    (void)hipGetLastError();   // clear a stale error left by other HIP users
+    if (rowsFast)
+        hipLaunchKernelGGL(bf3_pack_rows_kernel, dim3((unsigned)blocks), dim3(256), 0, s, X, offR,
+                           rowMap, R, offK, K, Kq, P, plane);
+    else
+        hipLaunchKernelGGL(bf3_pack_k_kernel, dim3((unsigned)blocks), dim3(256), 0, s, X, offR, R,
+                           offK, K, Kq, P, plane);
+    return launch_status();
+}
+
+int launch_bf3_packed_gemm(const Bf3Packed &g, hipStream_t s) {
+    constexpr int BM = kPackedBM, BN = kPackedBN;
+    using Cfg = PkCfg<BM, BN>;
+    static bool attr_set = false;   // set once per process (every device takes the same value)
+    if (!attr_set) {
+        if (hipFuncSetAttribute(reinterpret_cast<const void *>(bf3_packed_gemm_kernel<BM, BN>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                Cfg::kLdsBytes) != hipSuccess)
+            return GETT_ERR_HIP;
+        attr_set = true;
+    }
+    const int64_t total = (int64_t)g.tilesM * g.tilesN * g.splits;
+    if (total > INT32_MAX) return GETT_ERR_INTERNAL;
+    (void)hipGetLastError();   // clear a stale error left by other HIP users
+    auto kern = bf3_packed_gemm_kernel<BM, BN>;
+    hipLaunchKernelGGL(kern, dim3((unsigned)total), dim3(256), Cfg::kLdsBytes, s, g);
+    return launch_status();
+}
+
+}  // namespace gett

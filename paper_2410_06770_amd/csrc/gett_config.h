@@ -65,12 +65,16 @@ constexpr int kTablePad = 256;      // M/N tables padded to a multiple of this
 // of MFMA work to land in instead of one.
 // addr32: when both operands' addressed spans fit 4 GB, the tile loads
 // through a uniform 64-bit base plus 32-bit lane offsets (fewer VALU
-// instructions per value; FP64/FP32 only, measured per tile).
-struct TileShape { int bm, bn, bk; bool load_fence; int depth; bool addr32; };
+// instructions per value; real precisions, measured per tile).
+// packed (BF16x3 only): the entry is the packed form -- a pass splits each
+// operand element once into dense bfloat16 hi/lo rows, then a GEMM kernel
+// runs on those rows (its own kernels; the other flags do not apply).
+struct TileShape { int bm, bn, bk; bool load_fence; int depth; bool addr32; bool packed; };
 
 // Tile menus.  FP64/FP32 run 16x16x4 MFMA steps (BK multiple of 4), the BF16x3
 // path 16x16x32 BF16 MFMA steps (BK multiple of 32).  Each workgroup is a 2x2
-// grid of waves, so BM and BN are multiples of 32.
+// grid of waves, so BM and BN are multiples of 32.  The last BF16x3 entry is
+// the packed form (128 x 128 tiles on packed rows, 32 positions a step).
 constexpr TileShape kTiles[kNumPrec][kNumTiles] = {
     /* FP64   */ {{64, 64, 16, true, 1, true}, {64, 128, 16, true, 1, true},
                   {128, 64, 16, false, 1, false}, {128, 128, 16, true, 1, true},
@@ -78,9 +82,9 @@ constexpr TileShape kTiles[kNumPrec][kNumTiles] = {
     /* FP32   */ {{64, 64, 16, true, 2, true}, {64, 128, 16, true, 2, true},
                   {128, 64, 16, true, 2, true}, {128, 128, 16, true, 2, true},
                   {128, 128, 32, true, 2, true}},
-    /* BF16x3 */ {{64, 64, 32, true, 1, false}, {64, 128, 32, true, 1, false},
-                  {128, 64, 32, true, 1, false}, {128, 128, 32, true, 1, false},
-                  {128, 128, 64, true, 1, false}},
+    /* BF16x3 */ {{64, 64, 32, true, 1, true}, {64, 128, 32, true, 1, true},
+                  {128, 64, 32, true, 1, true}, {128, 128, 32, true, 1, false},
+                  {128, 128, 32, true, 1, false, true}},
     /* FP8    */ {{64, 64, 128, true, 1, false}, {64, 128, 128, true, 1, false},
                   {128, 64, 128, true, 1, false}, {128, 128, 128, true, 1, false},
                   {128, 128, 128, true, 1, false}},
@@ -91,6 +95,10 @@ constexpr TileShape kTiles[kNumPrec][kNumTiles] = {
                   {128, 64, 16, true, 1, false}, {128, 128, 16, true, 1, false},
                   {128, 128, 8, true, 1, false}},
 };
+
+// The direct BF16x3 tile of the packed entry's shape: it runs in the packed
+// form's place when the packed rows would not fit the workspace cap.
+constexpr int kPackedFallbackTile = 3;
 
 // Flag of the menu entry with this shape (first match).
 constexpr bool tile_load_fence(int prec, int bm, int bn, int bk) {

@@ -15,6 +15,7 @@
 #include <unordered_map>
 #include <vector>
 
+#include "gett_bf3pack.h"
 #include "gett.h"
 #include "gett_internal.h"
 #include "gett_noalloc.h"
@@ -94,11 +95,13 @@ static Sched sched_of(int64_t id) {
 }
 static const int64_t kNumSched = (int64_t)kNumTiles * kNumOrders * kNumSplits;
 
-// A schedule is usable when every split gets at least one K step.
-static bool sched_valid(int prec, const Sched &s, int64_t K) {
+// A schedule is usable when every split gets at least one K step; the packed
+// BF16x3 form takes contractions without Hadamard modes.
+static bool sched_valid(int prec, const Sched &s, int64_t K, int64_t H = 1) {
     if (s.tile < 0 || s.tile >= kNumTiles || s.order < 0 || s.order >= kNumOrders || s.split < 0 ||
         s.split >= kNumSplits)
         return false;
+    if (kTiles[prec][s.tile].packed && H > 1) return false;
     const int S = kSplitFactor[s.split];
     const int bk = kTiles[prec][s.tile].bk;
     if (S > 1 && K < (int64_t)S * bk) return false;
@@ -164,8 +167,16 @@ struct TableSet {
     int64_t *d_tab = nullptr;
     int64_t aLo = 0, aSpan = 0, bLo = 0, bSpan = 0;   // addressed element range of A and B
     int64_t cLo = 0, cSpan = 0;                        // and of C
+    // Packed BF16x3 form: the rows of A, then of B, in increasing operand
+    // offset (the pass whose lanes run along the rows walks them so), and
+    // each one's position in the tables' order; built on first use.
+    std::mutex pk_mu;
+    int64_t *d_pkRows = nullptr;
+    int32_t *d_pkMap = nullptr;
     ~TableSet() {
         if (d_tab) (void)hipFree(d_tab);
+        if (d_pkRows) (void)hipFree(d_pkRows);
+        if (d_pkMap) (void)hipFree(d_pkMap);
     }
 };
 
@@ -260,7 +271,7 @@ static int get_plan(int prec, const Args &a, int dev, int64_t forced, std::share
     const char *source = "forced";
     if (forced >= 0) {
         s = sched_of(forced);
-        if (!sched_valid(prec, s, c0.K)) return GETT_ERR_STATE;
+        if (!sched_valid(prec, s, c0.K, c0.H)) return GETT_ERR_STATE;
     } else {
         s = choose_schedule(prec, a, c0.M, c0.N, c0.K, c0.H, &source);
     }
@@ -350,6 +361,119 @@ static TileParams make_params(const Plan &pl, const void *A, const void *B, void
 
 static const double kOne[2] = {1.0, 0.0};
 
+static int packed_rows(TableSet &t) {
+    std::lock_guard<std::mutex> lk(t.pk_mu);
+    if (t.d_pkRows) return 0;
+    const Canon &c = t.cn;
+    const int64_t R[2] = {c.M, c.N};
+    std::vector<int64_t> rows(c.M + c.N);
+    std::vector<int32_t> map(c.M + c.N);
+    for (int side = 0; side < 2; ++side) {
+        const int64_t base = side ? c.M : 0;
+        std::vector<int64_t> off(R[side]);
+        group_offsets(side ? c.n : c.m, 0, R[side], off.data());
+        std::vector<int32_t> ord(R[side]);
+        for (int64_t i = 0; i < R[side]; ++i) ord[i] = (int32_t)i;
+        std::stable_sort(ord.begin(), ord.end(),
+                         [&](int32_t x, int32_t y) { return off[x] < off[y]; });
+        for (int64_t i = 0; i < R[side]; ++i) {
+            rows[base + i] = off[ord[i]];
+            map[base + i] = ord[i];
+        }
+    }
+    const size_t n = std::max<size_t>(rows.size(), 1);
+    int64_t *dr = nullptr;
+    int32_t *dm = nullptr;
+    if (hipMalloc(&dr, n * sizeof(int64_t)) != hipSuccess) return GETT_ERR_ALLOC;
+    if (hipMalloc(&dm, n * sizeof(int32_t)) != hipSuccess) {
+        (void)hipFree(dr);
+        return GETT_ERR_ALLOC;
+    }
+    if (!rows.empty() &&
+        (hipMemcpy(dr, rows.data(), rows.size() * sizeof(int64_t), hipMemcpyHostToDevice) !=
+             hipSuccess ||
+         hipMemcpy(dm, map.data(), map.size() * sizeof(int32_t), hipMemcpyHostToDevice) !=
+             hipSuccess)) {
+        (void)hipFree(dr);
+        (void)hipFree(dm);
+        return GETT_ERR_HIP;
+    }
+    t.d_pkRows = dr;
+    t.d_pkMap = dm;
+    return 0;
+}
+
+// The packed BF16x3 form: pack A and B into hi/lo rows (one workspace with
+// the FP64 partials of a K split), the GEMM, then the slices' reduction.
+// *fallback is set, with nothing launched, when the rows are too long or
+// the workspace is over the cap or cannot be allocated: the caller then runs
+// the direct 128 x 128 tile with the same order and split.
+static int run_packed(const Plan &pl, const TileParams &p, hipStream_t s, bool *fallback) {
+    *fallback = false;
+    TableSet &t = *pl.tab;
+    const Canon &c = t.cn;
+    const int64_t M = c.M, N = c.N, K = c.K;
+    const int64_t Kq = round_up(std::max<int64_t>(K, 1), kPackedBK);
+    const int64_t Mq = round_up(std::max<int64_t>(M, 1), kPackedBM);
+    const int64_t Nq = round_up(std::max<int64_t>(N, 1), kPackedBN);
+    const int64_t tilesM = Mq / kPackedBM, tilesN = Nq / kPackedBN;
+    int64_t per = 0;
+    const int S = split_count(pl.sched.split, tilesM * tilesN, Kq, kPackedBK, &per);
+    const int64_t pk = 4 * (Mq + Nq) * Kq;
+    const int64_t wsb = S > 1 ? (int64_t)S * M * N * (int64_t)sizeof(double) : 0;
+    if (Kq > kPackedMaxKq || tilesM * tilesN * S > INT32_MAX || pk + wsb > g_max_ws.load()) {
+        *fallback = true;
+        return 0;
+    }
+    int rc = packed_rows(t);
+    if (rc) return rc;
+    void *buf = nullptr;
+    if (hipMallocAsync(&buf, (size_t)(pk + wsb), s) != hipSuccess) {
+        (void)hipGetLastError();
+        *fallback = true;
+        return 0;
+    }
+    uint16_t *PA = static_cast<uint16_t *>(buf);
+    uint16_t *PB = PA + 2 * Mq * Kq;
+    double *ws = wsb ? reinterpret_cast<double *>(static_cast<char *>(buf) + pk) : nullptr;
+    const float *XA = static_cast<const float *>(p.A), *XB = static_cast<const float *>(p.B);
+    rc = launch_bf3_pack(XA, c.aFastK ? p.offAM : t.d_pkRows, c.aFastK ? nullptr : t.d_pkMap, M,
+                         p.offAK, K, Kq, !c.aFastK, PA, Mq * Kq, s);
+    if (!rc)
+        rc = launch_bf3_pack(XB, c.bFastK ? p.offBN : t.d_pkRows + M,
+                             c.bFastK ? nullptr : t.d_pkMap + M, N, p.offBK, K, Kq, !c.bFastK,
+                             PB, Nq * Kq, s);
+    if (!rc) {
+        Bf3Packed g{};
+        g.A = PA;
+        g.B = PB;
+        g.planeA = Mq * Kq;
+        g.planeB = Nq * Kq;
+        g.Kq = Kq;
+        g.kPer = per;
+        g.tilesM = (int32_t)tilesM;
+        g.tilesN = (int32_t)tilesN;
+        g.splits = S;
+        g.C = static_cast<float *>(p.C);
+        g.offCM = p.offCM;
+        g.offCN = p.offCN;
+        g.M = M;
+        g.N = N;
+        g.ws = ws;
+        g.alpha = p.alpha[0];
+        g.beta = p.beta[0];
+        rc = launch_bf3_packed_gemm(g, s);
+    }
+    if (!rc && S > 1) {
+        TileParams q = p;
+        q.ws = ws;
+        q.splits = S;
+        rc = launch_splitk_reduce(kBF3, q, s);
+    }
+    if (hipFreeAsync(buf, s) != hipSuccess && !rc) rc = GETT_ERR_HIP;
+    return rc;
+}
+
 // alpha, beta: (re, im) pairs of C <- alpha * sum + beta * C_in.
 static int run_plan(const Plan &pl, const void *A, const void *B, void *C, hipStream_t s,
                     const double *alpha = kOne, const double *beta = kOne) {
@@ -361,13 +485,21 @@ static int run_plan(const Plan &pl, const void *A, const void *B, void *C, hipSt
         q.beta[1] = beta[1];
     };
     scale(p);
+    int tile = pl.sched.tile;
+    if (kTiles[pl.prec][tile].packed) {
+        bool fallback = false;
+        const int rc = run_packed(pl, p, s, &fallback);
+        if (!fallback) return rc;
+        tile = kPackedFallbackTile;
+        t_last_schedule = sched_id(Sched{tile, pl.sched.order, pl.sched.split});
+    }
     if (p.splits > 1) {
         const int64_t bytes = (int64_t)p.splits * p.M * p.N * (int64_t)p.H *
                               (prec_complex(pl.prec) ? 2 : 1) * (int64_t)sizeof(double);
         void *ws = nullptr;
         if (bytes <= g_max_ws.load() && hipMallocAsync(&ws, (size_t)bytes, s) == hipSuccess) {
             p.ws = static_cast<double *>(ws);
-            int rc = launch_tile(pl.prec, pl.sched.tile, pl.tab->cn.aFastK, pl.tab->cn.bFastK, p, s);
+            int rc = launch_tile(pl.prec, tile, pl.tab->cn.aFastK, pl.tab->cn.bFastK, p, s);
             if (!rc) rc = launch_splitk_reduce(pl.prec, p, s);
             if (hipFreeAsync(ws, s) != hipSuccess && !rc) rc = GETT_ERR_HIP;
             return rc;
@@ -376,9 +508,9 @@ static int run_plan(const Plan &pl, const void *A, const void *B, void *C, hipSt
         (void)hipGetLastError();
         p = make_params(pl, A, B, C, 0);
         scale(p);
-        t_last_schedule = sched_id(Sched{pl.sched.tile, pl.sched.order, 0});
+        t_last_schedule = sched_id(Sched{tile, pl.sched.order, 0});
     }
-    return launch_tile(pl.prec, pl.sched.tile, pl.tab->cn.aFastK, pl.tab->cn.bFastK, p, s);
+    return launch_tile(pl.prec, tile, pl.tab->cn.aFastK, pl.tab->cn.bFastK, p, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -755,7 +887,7 @@ static int64_t autotune(int prec, const Args &a, const void *A, const void *B, v
     *status = 0;
     std::vector<double> t1(kNumSched, -1.0);
     for (int64_t id = 0; id < kNumSched; ++id) {
-        if (!sched_valid(prec, sched_of(id), c0.K) || (allow && !allow(prec, sched_of(id))))
+        if (!sched_valid(prec, sched_of(id), c0.K, c0.H) || (allow && !allow(prec, sched_of(id))))
             continue;
         int rc = time_schedule(prec, a, A, B, C, dev, id, warmup, 1, &t1[id]);
         if (rc) {
@@ -908,7 +1040,7 @@ static Sched choose_schedule(int prec, const Args &a, int64_t M, int64_t N, int6
             }
             read_tune_db_locked();
             auto jt = g_tuned_db.find(dkey);
-            if (jt != g_tuned_db.end() && sched_valid(prec, jt->second, K)) {
+            if (jt != g_tuned_db.end() && sched_valid(prec, jt->second, K, H)) {
                 g_tuned[key] = jt->second;
                 *source = "tune-db";
                 return jt->second;

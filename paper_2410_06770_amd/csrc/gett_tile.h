@@ -104,12 +104,6 @@ __device__ __forceinline__ bool gett_check_c(int64_t off, int64_t lo, int64_t sp
 #define GETT_CHECK_C(off, p) (void)0
 #endif
 
-__device__ __forceinline__ int64_t readlane64(int64_t v, int lane) {
-    const int lo = __builtin_amdgcn_readlane((int)(v & 0xffffffff), lane);
-    const int hi = __builtin_amdgcn_readlane((int)(v >> 32), lane);
-    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
-}
-
 // Split two FP32 values into packed bfloat16 pairs: hi = bf16(x) (round to
 // nearest even), lo = bf16(x - hi) (the subtraction is exact).  Element 0
 // goes to the low half of each word.
@@ -144,17 +138,16 @@ template <int PREC, int ROWS, int BK, bool FASTK, bool O32 = false> struct Gathe
     static_assert(BK <= 64, "one wave holds a step's contracted offsets");
     static_assert(!kSplit || FASTK || PER % 8 == 0, "16-byte LDS chunks");
 
-    // !FASTK with plain values: every value a thread loads sits in a
-    // wave-uniform LDS column, so its contracted offset is the same for the
-    // whole wave and is read with a scalar load (one per value, no lane
-    // shuffles).  The BF16x3 loader keeps one offset per lane.
-    static constexpr bool kScalarK = !FASTK && !kSplit;
+    // !FASTK: every value a thread loads sits in a wave-uniform LDS column,
+    // so its contracted offset is the same for the whole wave and is read
+    // with a scalar load (one per value, no lane shuffles).
+    static constexpr bool kScalarK = !FASTK;
     static constexpr int NK = kScalarK ? PER : KP;     // offsets held per step
-    // O32 (plain values, operand span below 4 GB): the whole-step loads take
+    // O32 (real values, operand span below 4 GB): the whole-step loads take
     // a wave-uniform 64-bit base and a 32-bit byte offset per lane, so a
     // value costs one 32-bit add (lanes along K) or none (lanes along the
     // free axis, whose contracted offset joins the uniform base).
-    static_assert(!O32 || (!kSplit && !kCplx), "32-bit addressing is for plain real values");
+    static_assert(!O32 || !kCplx, "32-bit addressing is for real values");
 
     const T *base[NF];  // X + free offset of each row this thread reads
     int row[NF];        // tile row of each free offset
@@ -213,15 +206,13 @@ template <int PREC, int ROWS, int BK, bool FASTK, bool O32 = false> struct Gathe
         }
     }
 
-    // Contracted offsets of the step starting at k0: lane l holds
-    // offK[k0 + (l % BK)] (threads along the free axis pick theirs with
-    // readlane), or offK[k0 + q + e * KL] when threads run along K.
+    // Contracted offsets of the step starting at k0: offK[k0 + kpos(c)] for
+    // each (wave-uniform) column c a thread along the free axis loads, or
+    // offK[k0 + q + e * KL] when threads run along K.
     __device__ __forceinline__ void load_koffs(const int64_t *__restrict__ offK, int64_t k0) {
         if constexpr (kScalarK) {
 #pragma unroll
-            for (int i = 0; i < PER; ++i) koff[i] = offK[k0 + col(i)];
-        } else if constexpr (!FASTK) {
-            koff[0] = offK[k0 + (threadIdx.x & 63) % BK];
+            for (int i = 0; i < PER; ++i) koff[i] = offK[k0 + kpos(col(i))];
         } else if constexpr (O32) {
             // only the low word takes part in 32-bit addressing: load just it
             const uint32_t *lo32 = reinterpret_cast<const uint32_t *>(offK);
@@ -240,12 +231,9 @@ template <int PREC, int ROWS, int BK, bool FASTK, bool O32 = false> struct Gathe
         if constexpr (kScalarK) {
 #pragma unroll
             for (int i = 0; i < PER; ++i) {
-                const int64_t k = k0 + col(i);
+                const int64_t k = k0 + kpos(col(i));
                 koff[i] = offK[k < klo ? klo : k];
             }
-        } else if constexpr (!FASTK) {
-            const int64_t k = k0 + (threadIdx.x & 63) % BK;
-            koff[0] = offK[k < klo ? klo : k];
         } else {
 #pragma unroll
             for (int e = 0; e < KP; ++e) {
@@ -310,16 +298,7 @@ template <int PREC, int ROWS, int BK, bool FASTK, bool O32 = false> struct Gathe
 #pragma unroll
             for (int i = 0; i < PER; ++i) {
                 const T *ptr = base[0] + ko_[i];
-                if constexpr (MASKED) ptr = (k0 + col(i) >= klo) ? ptr : zero;
-                v[i] = *chk(ptr);
-            }
-        } else if constexpr (!FASTK) {
-#pragma unroll
-            for (int i = 0; i < PER; ++i) {
-                const int k = kpos(col(i));                  // uniform
-                const int64_t ko = readlane64(ko_[0], k);
-                const T *ptr = base[0] + ko;
-                if constexpr (MASKED) ptr = (k0 + k >= klo) ? ptr : zero;
+                if constexpr (MASKED) ptr = (k0 + kpos(col(i)) >= klo) ? ptr : zero;
                 v[i] = *chk(ptr);
             }
         } else {
@@ -981,10 +960,10 @@ static int launch_fast_o(bool afk, bool bfk, const TileParams &p, hipStream_t s)
 }
 
 // Tiles marked addr32 in the menu take the 32-bit addressing variant when
-// both operands' spans allow it (FP64/FP32 only).
+// both operands' spans allow it (real precisions).
 template <int PREC, int BM, int BN, int BK>
 static int launch_fast(bool afk, bool bfk, const TileParams &p, hipStream_t s) {
-    if constexpr (PREC != kBF3 && tile_addr32(PREC, BM, BN, BK)) {
+    if constexpr (tile_addr32(PREC, BM, BN, BK)) {
         if (p.off32) return launch_fast_o<PREC, BM, BN, BK, true>(afk, bfk, p, s);
     }
     return launch_fast_o<PREC, BM, BN, BK, false>(afk, bfk, p, s);

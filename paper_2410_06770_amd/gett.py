@@ -29,6 +29,9 @@ NUM_FEATURES = 64
 NUM_ORDERS = 4
 NUM_SPLITS = 4
 SPLIT_FACTORS = (1, 2, 4, 0)   # 0: enough K slices to fill the chip
+# The BF16x3 menu entry that is the packed form (hi/lo rows packed once, then
+# a GEMM on them); it takes no Hadamard modes.
+BF16X3_PACKED_TILE = 4
 
 _lib = None
 i64 = ct.c_int64

@@ -209,7 +209,8 @@ def test_boxed_orders_every_schedule(prec):
 
 
 # ------------------------------------------------- 64-bit variants over 4 GB
-ADDR32_TILES = {gett.GETT_FP64: [0, 1, 3], gett.GETT_FP32: [0, 1, 2, 3, 4]}
+ADDR32_TILES = {gett.GETT_FP64: [0, 1, 3], gett.GETT_FP32: [0, 1, 2, 3, 4],
+                gett.GETT_BF16X3: [0, 1, 2, 3, 4]}
 
 
 @pytest.mark.parametrize("prec,tile", [(p, t) for p, ts in ADDR32_TILES.items() for t in ts])

@@ -369,7 +369,7 @@ def test_offsets_beyond_int32(prec):
     check_outside(pr, got)
 
 
-@pytest.mark.parametrize("prec", [gett.GETT_FP64, gett.GETT_FP32])
+@pytest.mark.parametrize("prec", [gett.GETT_FP64, gett.GETT_FP32, gett.GETT_BF16X3])
 @pytest.mark.parametrize("side", ["below", "above"])
 def test_addressing_at_the_4gb_boundary(prec, side):
     """A[a, k] of extents (7, 33) with increments (-1, step), the pointer six
