@@ -7,13 +7,13 @@
 
 namespace gett {
 
-constexpr int kPackedBM = 128, kPackedBN = 128;   // GEMM tile of the packed path
 constexpr int kPackedBK = 32;                     // packed positions per step
 constexpr int64_t kPackedMaxKq = (int64_t)1 << 24;   // row length limit (32-bit lane offsets)
 
 // Arguments of one packed GEMM launch.  A and B hold the hi planes of the
-// packed operands ([rows][Kq] bfloat16, rows padded to the tile), the lo
-// planes follow at +planeA / +planeB elements.
+// packed operands (rows padded to the tile, Kq positions each, in blocks of
+// 16 rows by 32 positions), the lo planes follow at +planeA / +planeB
+// elements.
 struct Bf3Packed {
     const uint16_t *A, *B;
     int64_t planeA, planeB;
@@ -33,6 +33,8 @@ struct Bf3Packed {
 int launch_bf3_pack(const float *X, const int64_t *offR, const int32_t *rowMap, int64_t R,
                     const int64_t *offK, int64_t K, int64_t Kq, bool rowsFast, uint16_t *P,
                     int64_t plane, hipStream_t s);
-int launch_bf3_packed_gemm(const Bf3Packed &g, hipStream_t s);
+// GEMM tiles (bm x bn): 128 x 128 (4 waves, two workgroups per CU) and
+// 192 x 256 (8 waves, one per CU); rows padded to the tile.
+int launch_bf3_packed_gemm(int bm, int bn, const Bf3Packed &g, hipStream_t s);
 
 }  // namespace gett

@@ -9,7 +9,12 @@
 // pack:  every row of an operand (a free position, in the order of the
 //        schedule's offset tables) becomes two dense bfloat16 rows, hi and
 //        lo, of Kq = K rounded up to 32 positions (zeros past K), in two
-//        planes [rows][Kq].  The contracted positions are stored in a fixed
+//        planes.  A plane is stored in blocks of 16 rows by one step of 32
+//        positions (1 KB, rows of 64 bytes inside), row groups outermost and
+//        steps next, so that a step of a tile's rows is whole cache lines
+//        (64-byte row pieces 2 KB or more apart would each fetch a 128-byte
+//        line of which the next step needs the other half, after it has left
+//        the L1).  The contracted positions are stored in a fixed
 //        permutation shared by both operands (the sum is over the same
 //        pairs): groups of 512 positions, group g holding S = min(512,
 //        Kq - 512 g) / 8 chunks of 8, and chunk c of a group holds the
@@ -65,38 +70,61 @@ __device__ __forceinline__ int64_t chunk_pos(int64_t c, int e, int64_t Kq) {
     return 512 * g + (c & 63) + S * e;
 }
 
-// Lanes along K: one wave per (row, group of 512 packed positions); lane l
-// fills chunk l of the group.
+// Element offset of packed positions j .. j + 7 (j a multiple of 8) of row
+// r in a plane of Kq positions per row (see the file comment).
+__device__ __forceinline__ int64_t pk_off(int64_t r, int64_t j, int64_t Kq) {
+    return ((r >> 4) * (Kq >> 5) + (j >> 5)) * 512 + (r & 15) * 32 + (j & 31);
+}
+
+constexpr int kPackRowsK = 4;      // rows per wave, lanes along K
+constexpr int kPackBlocksR = 4;    // 16-row blocks per wave, lanes along the rows
+
+// Lanes along K: one wave per (kPackRowsK rows, group of 512 packed
+// positions); lane l fills chunk l of the group in each row, its contracted
+// offsets read once for all of them.
 __global__ __launch_bounds__(256) void bf3_pack_k_kernel(const float *__restrict__ X,
                                                          const int64_t *__restrict__ offR,
                                                          int64_t R, const int64_t *__restrict__ offK,
                                                          int64_t K, int64_t Kq,
                                                          uint16_t *__restrict__ P, int64_t plane) {
     const int64_t ng = (Kq + 511) / 512;
+    const int64_t nrb = (R + kPackRowsK - 1) / kPackRowsK;
     const int64_t task = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (task >= R * ng) return;
+    if (task >= nrb * ng) return;
     const int lane = threadIdx.x & 63;
-    const int64_t r = task / ng, g = task - r * ng;
+    const int64_t rb = task / ng, g = task - rb * ng;
     const int64_t S = min<int64_t>(512, Kq - 512 * g) >> 3;
     if (lane >= S) return;
     const int64_t c = 64 * g + lane;
-    const float *xr = X + offR[r];
-    float v[8];
+    int64_t ko[8];
+    uint32_t valid = 0;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
         const int64_t k = chunk_pos(c, e, Kq);
-        v[e] = k < K ? xr[offK[k]] : 0.0f;
+        ko[e] = k < K ? offK[k] : 0;
+        valid |= (k < K ? 1u : 0u) << e;
     }
-    u4_t hi, lo;
-    split8(v, hi, lo);
-    uint16_t *dst = P + r * Kq + 8 * c;
-    *reinterpret_cast<u4_t *>(dst) = hi;
-    *reinterpret_cast<u4_t *>(dst + plane) = lo;
+#pragma unroll
+    for (int q = 0; q < kPackRowsK; ++q) {
+        const int64_t r = rb * kPackRowsK + q;
+        if (r >= R) break;
+        const float *xr = X + offR[r];
+        float v[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = (valid >> e) & 1 ? xr[ko[e]] : 0.0f;
+        u4_t hi, lo;
+        split8(v, hi, lo);
+        uint16_t *dst = P + pk_off(r, 8 * c, Kq);
+        *reinterpret_cast<u4_t *>(dst) = hi;
+        *reinterpret_cast<u4_t *>(dst + plane) = lo;
+    }
 }
 
-// Lanes along the rows: one wave per (16 rows in the operand's memory order,
-// 4 chunks); lane l takes row p0 + l % 16 and chunk c0 + l / 16, so each load
-// reads 16 neighbouring rows and each row's four chunks are stored together.
+// Lanes along the rows: one wave per (kPackBlocksR blocks of 16 rows in the
+// operand's memory order, 4 chunks); lane l takes row l % 16 of each block
+// and chunk c0 + l / 16, so each load reads 16 neighbouring rows, each row's
+// four chunks are stored together, and the contracted offsets are read once
+// for all the blocks.
 __global__ __launch_bounds__(256) void bf3_pack_rows_kernel(
     const float *__restrict__ X, const int64_t *__restrict__ rowsOp,
     const int32_t *__restrict__ rowMap, int64_t R, const int64_t *__restrict__ offK, int64_t K,
@@ -105,22 +133,31 @@ __global__ __launch_bounds__(256) void bf3_pack_rows_kernel(
     const int64_t cq = (nc + 3) / 4;
     const int64_t task = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int64_t rb = task / cq, q = task - rb * cq;
-    const int64_t p = rb * 16 + (lane & 15);
+    const int64_t sb = task / cq, q = task - sb * cq;
     const int64_t c = q * 4 + (lane >> 4);
-    if (p >= R || c >= nc) return;
-    const float *xr = X + rowsOp[p];
-    float v[8];
+    if (sb * 16 * kPackBlocksR >= R || c >= nc) return;
+    int64_t ko[8];
+    uint32_t valid = 0;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
         const int64_t k = chunk_pos(c, e, Kq);
-        v[e] = k < K ? xr[offK[k]] : 0.0f;
+        ko[e] = k < K ? offK[k] : 0;
+        valid |= (k < K ? 1u : 0u) << e;
     }
-    u4_t hi, lo;
-    split8(v, hi, lo);
-    uint16_t *dst = P + (int64_t)rowMap[p] * Kq + 8 * c;
-    *reinterpret_cast<u4_t *>(dst) = hi;
-    *reinterpret_cast<u4_t *>(dst + plane) = lo;
+#pragma unroll
+    for (int b = 0; b < kPackBlocksR; ++b) {
+        const int64_t p = (sb * kPackBlocksR + b) * 16 + (lane & 15);
+        if (p >= R) break;
+        const float *xr = X + rowsOp[p];
+        float v[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = (valid >> e) & 1 ? xr[ko[e]] : 0.0f;
+        u4_t hi, lo;
+        split8(v, hi, lo);
+        uint16_t *dst = P + pk_off(rowMap[p], 8 * c, Kq);
+        *reinterpret_cast<u4_t *>(dst) = hi;
+        *reinterpret_cast<u4_t *>(dst + plane) = lo;
+    }
 }
 
 // LDS rows hold the 32 positions of a step, 64 bytes, unpadded; the four
@@ -140,32 +177,37 @@ template <int BM, int BN> struct PkCfg {
 };
 
 // Chunk i of thread t in a ROWS-row operand tile: four neighbouring threads
-// take the four 16-byte chunks of one row's 32 positions (a load reads 64
-// contiguous bytes of each of 16 rows); chunk i covers rows (64 i) % ROWS +
-// t / 4 of plane 64 i / ROWS (both fixed once unrolled).
+// take the four 16-byte chunks of one row's 32 positions, so a wave's load
+// reads one whole 1 KB block; chunk i covers row (64 i) % ROWS + t / 4 of
+// plane 64 i / ROWS.  Offsets are from the tile's first block of the step.
 template <int ROWS> struct PkLoad {
     static_assert(ROWS % 64 == 0, "64 rows per chunk index");
     static constexpr int C = ROWS * 8 / 256;
-    uint32_t goff[C];   // element offset from the tile's base in the chunk's plane
-    uint32_t soff[C];   // element offset in an LDS stage
+    uint32_t goff;      // element offset of the thread's 16 bytes inside a block
+    uint32_t soff;      // element offset in an LDS stage, before the chunk's constant
+    int rg0;            // row group of row t / 4
+    int64_t gstride;    // elements from one row group to the next (Kq * 16)
     __device__ __forceinline__ void init(int t, int64_t Kq) {
-        const int c = t & 3, cs = c ^ swz(t >> 2);
-#pragma unroll
-        for (int i = 0; i < C; ++i) {
-            const int pl = 64 * i / ROWS, rr = (64 * i) % ROWS + (t >> 2);
-            goff[i] = (uint32_t)(rr * Kq + 8 * c);
-            soff[i] = (uint32_t)(pl * ROWS * kLd + rr * kLd + 8 * cs);
-        }
+        const int c = t & 3, r = t >> 2;
+        gstride = Kq * 16;
+        goff = (uint32_t)((r & 15) * 32 + 8 * c);
+        soff = (uint32_t)(r * kLd + 8 * (c ^ swz(r)));
+        rg0 = r >> 4;
     }
     __device__ __forceinline__ void load(const uint16_t *hi, const uint16_t *lo,
                                          u4_t (&v)[C]) const {
 #pragma unroll
-        for (int i = 0; i < C; ++i)
-            v[i] = *reinterpret_cast<const u4_t *>((64 * i / ROWS ? lo : hi) + goff[i]);
+        for (int i = 0; i < C; ++i) {
+            const uint16_t *base = (64 * i / ROWS ? lo : hi) +
+                                   (int64_t)(((64 * i) % ROWS) / 16 + rg0) * gstride;
+            v[i] = *reinterpret_cast<const u4_t *>(base + goff);
+        }
     }
     __device__ __forceinline__ void store(uint16_t *s, const u4_t (&v)[C]) const {
 #pragma unroll
-        for (int i = 0; i < C; ++i) *reinterpret_cast<u4_t *>(s + soff[i]) = v[i];
+        for (int i = 0; i < C; ++i)
+            *reinterpret_cast<u4_t *>(s + (64 * i / ROWS) * ROWS * kLd + ((64 * i) % ROWS) * kLd +
+                                      soff) = v[i];
     }
 };
 
@@ -179,35 +221,94 @@ __device__ __forceinline__ void pk_mma(const uint16_t *sA, const uint16_t *sB, i
     const __bf16 *bhi = reinterpret_cast<const __bf16 *>(sB);
     const __bf16 *blo = bhi + Cfg::PB;
     const int kc = 8 * ((lane >> 4) ^ swz(lane & 15));   // rows start at multiples of 16
-    bf8_t bh[FN], bl[FN];
-#pragma unroll
-    for (int j = 0; j < FN; ++j) {
-        const int r = wn * Cfg::WTN + j * 16 + (lane & 15);
-        bh[j] = *reinterpret_cast<const bf8_t *>(bhi + r * kLd + kc);
-        bl[j] = *reinterpret_cast<const bf8_t *>(blo + r * kLd + kc);
-    }
+    bf8_t ah[FM], al[FM];
 #pragma unroll
     for (int i = 0; i < FM; ++i) {
         const int r = wm * Cfg::WTM + i * 16 + (lane & 15);
-        const bf8_t ah = *reinterpret_cast<const bf8_t *>(ahi + r * kLd + kc);
-        const bf8_t al = *reinterpret_cast<const bf8_t *>(alo + r * kLd + kc);
+        ah[i] = *reinterpret_cast<const bf8_t *>(ahi + r * kLd + kc);
+        al[i] = *reinterpret_cast<const bf8_t *>(alo + r * kLd + kc);
+    }
 #pragma unroll
-        for (int j = 0; j < FN; ++j) {
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[j], acc[i][j], 0, 0, 0);
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[j], acc[i][j], 0, 0, 0);
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[j], acc[i][j], 0, 0, 0);
+    for (int j = 0; j < FN; ++j) {
+        const int r = wn * Cfg::WTN + j * 16 + (lane & 15);
+        const bf8_t bh = *reinterpret_cast<const bf8_t *>(bhi + r * kLd + kc);
+        const bf8_t bl = *reinterpret_cast<const bf8_t *>(blo + r * kLd + kc);
+#pragma unroll
+        for (int i = 0; i < FM; ++i) {
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh, acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl, acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh, acc[i][j], 0, 0, 0);
         }
     }
 }
 
-// One BM x BN output tile over the packed range of its K slice.  Two
-// register sets: the step s + 2 loads while step s runs on the matrix cores
-// and step s + 1 waits in the other set (loads past the last step repeat
-// it); two LDS stages, one barrier per step.
+// A wave's outputs: fragment (i, j), register v of lane l holds M row
+// mw + 16 i + 4 (l / 16) + v and N column nw + 16 j + l % 16.  FP64 partials
+// of a K slice, or C <- alpha * sum + beta * C_in in FP64 rounded once; one
+// column of fragments at a time, its C_in read before any of it is written
+// (a store to C could alias a later load of C, so loads interleaved with
+// stores would wait out one another).
+template <int FM, int FN>
+__device__ __forceinline__ void pk_epilogue(const Bf3Packed &g, const f4_t (&acc)[FM][FN],
+                                            int64_t mw, int64_t nw, int lane, int split) {
+    float *__restrict__ C = g.C;
+    if (g.ws) {
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+            const int64_t n = nw + j * 16 + (lane & 15);
+            if (n >= g.N) continue;
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int64_t m = mw + i * 16 + 4 * (lane >> 4) + v;
+                    if (m < g.M) g.ws[((int64_t)split * g.M + m) * g.N + n] = (double)acc[i][j][v];
+                }
+        }
+        return;
+    }
+    const bool rdC = g.beta != 0.0;
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+        const int64_t n = nw + j * 16 + (lane & 15);
+        const bool nok = n < g.N;
+        const int64_t ocn = nok ? g.offCN[n] : 0;
+        int64_t off[FM][4];
+        bool ok[FM][4];
+        float cin[FM][4];
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t m = mw + i * 16 + 4 * (lane >> 4) + v;
+                ok[i][v] = nok && m < g.M;
+                off[i][v] = ok[i][v] ? g.offCM[m] + ocn : 0;
+                cin[i][v] = (rdC && ok[i][v]) ? C[off[i][v]] : 0.0f;
+            }
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                if (!ok[i][v]) continue;
+                const double sum = (double)acc[i][j][v];
+                C[off[i][v]] = (float)(rdC ? g.alpha * sum + g.beta * (double)cin[i][v]
+                                           : g.alpha * sum);
+            }
+    }
+}
+
+// One BM x BN output tile over the packed range of its K slice, two LDS
+// stages and one barrier per step.  128 x 128 tiles (two workgroups per CU)
+// keep two register sets: step s + 2 loads while step s runs on the matrix
+// cores and step s + 1 waits in the other set (loads past the last step
+// repeat it).  Larger tiles (one workgroup per CU, the accumulators in the
+// accumulation registers) keep one set: step s + 1 loads while step s runs,
+// behind a step's worth of MFMA work.
 template <int BM, int BN>
 __global__ __launch_bounds__(256) void bf3_packed_gemm_kernel(Bf3Packed g) {
     using Cfg = PkCfg<BM, BN>;
     constexpr int FM = Cfg::FM, FN = Cfg::FN;
+    constexpr bool kTwoSets = BM * BN <= 128 * 128;
     extern __shared__ __align__(16) uint16_t lds[];
     uint16_t *sA = lds, *sB = lds + 2 * Cfg::SA;   // [stage][plane][row][kLd]
 
@@ -226,8 +327,9 @@ __global__ __launch_bounds__(256) void bf3_packed_gemm_kernel(Bf3Packed g) {
     PkLoad<BN> lb;
     la.init(t, g.Kq);
     lb.init(t, g.Kq);
-    const uint16_t *aH = g.A + m0 * g.Kq + kbeg, *aL = aH + g.planeA;
-    const uint16_t *bH = g.B + n0 * g.Kq + kbeg, *bL = bH + g.planeB;
+    // first block of the tile's rows at the slice's first step; a step is 512 elements on
+    const uint16_t *aH = g.A + m0 * g.Kq + kbeg * 16, *aL = aH + g.planeA;
+    const uint16_t *bH = g.B + n0 * g.Kq + kbeg * 16, *bL = bH + g.planeB;
 
     f4_t acc[FM][FN];
 #pragma unroll
@@ -235,62 +337,191 @@ __global__ __launch_bounds__(256) void bf3_packed_gemm_kernel(Bf3Packed g) {
 #pragma unroll
         for (int j = 0; j < FN; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
 
-    u4_t ra0[Cfg::CA], rb0[Cfg::CB], ra1[Cfg::CA], rb1[Cfg::CB];
-    auto step = [&](int64_t s) { return 32 * (s < nsteps ? s : nsteps - 1); };
-    la.load(aH, aL, ra0);
-    lb.load(bH, bL, rb0);
-    la.load(aH + step(1), aL + step(1), ra1);
-    lb.load(bH + step(1), bL + step(1), rb1);
-    la.store(sA, ra0);
-    lb.store(sB, rb0);
-    __syncthreads();
-    for (int64_t s = 0; s < nsteps; s += 2) {
-        // even step: LDS stage 0, set 1 waits for stage 1
-        const int64_t k2 = step(s + 2);
-        la.load(aH + k2, aL + k2, ra0);
-        lb.load(bH + k2, bL + k2, rb0);
-        pk_mma<BM, BN>(sA, sB, lane, wm, wn, acc);
-        __builtin_amdgcn_sched_barrier(0);
-        la.store(sA + Cfg::SA, ra1);
-        lb.store(sB + Cfg::SB, rb1);
-        __syncthreads();
-        // odd step: LDS stage 1, set 0 waits for stage 0 (with an odd step
-        // count the last one holds a repeat of the last step: not computed)
-        const int64_t k3 = step(s + 3);
-        la.load(aH + k3, aL + k3, ra1);
-        lb.load(bH + k3, bL + k3, rb1);
-        if (s + 1 < nsteps) pk_mma<BM, BN>(sA + Cfg::SA, sB + Cfg::SB, lane, wm, wn, acc);
-        __builtin_amdgcn_sched_barrier(0);
+    auto step = [&](int64_t s) { return 512 * (s < nsteps ? s : nsteps - 1); };
+    if constexpr (kTwoSets) {
+        u4_t ra0[Cfg::CA], rb0[Cfg::CB], ra1[Cfg::CA], rb1[Cfg::CB];
+        la.load(aH, aL, ra0);
+        lb.load(bH, bL, rb0);
+        la.load(aH + step(1), aL + step(1), ra1);
+        lb.load(bH + step(1), bL + step(1), rb1);
         la.store(sA, ra0);
         lb.store(sB, rb0);
         __syncthreads();
-    }
-
-    // Epilogue: fragment (i, j), register v of lane l holds M row
-    // 4 (l / 16) + v and N column l % 16 of the fragment.
-    const bool rdC = g.beta != 0.0;
-#pragma unroll
-    for (int j = 0; j < FN; ++j) {
-        const int64_t n = n0 + wn * Cfg::WTN + j * 16 + (lane & 15);
-        if (n >= g.N) continue;
-        const int64_t ocn = g.offCN[n];
-#pragma unroll
-        for (int i = 0; i < FM; ++i) {
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int64_t m = m0 + wm * Cfg::WTM + i * 16 + 4 * (lane >> 4) + v;
-                if (m >= g.M) continue;
-                if (g.ws) {
-                    g.ws[((int64_t)split * g.M + m) * g.N + n] = (double)acc[i][j][v];
-                } else {
-                    const int64_t off = g.offCM[m] + ocn;
-                    const double sum = (double)acc[i][j][v];
-                    g.C[off] = (float)(rdC ? g.alpha * sum + g.beta * (double)g.C[off]
-                                           : g.alpha * sum);
-                }
-            }
+        for (int64_t s = 0; s < nsteps; s += 2) {
+            // even step: LDS stage 0, set 1 waits for stage 1
+            const int64_t k2 = step(s + 2);
+            la.load(aH + k2, aL + k2, ra0);
+            lb.load(bH + k2, bL + k2, rb0);
+            __builtin_amdgcn_s_setprio(1);
+            pk_mma<BM, BN>(sA, sB, lane, wm, wn, acc);
+            __builtin_amdgcn_s_setprio(0);
+            __builtin_amdgcn_sched_barrier(0);
+            la.store(sA + Cfg::SA, ra1);
+            lb.store(sB + Cfg::SB, rb1);
+            __syncthreads();
+            // odd step: LDS stage 1, set 0 waits for stage 0 (with an odd step
+            // count the last one holds a repeat of the last step: not computed)
+            const int64_t k3 = step(s + 3);
+            la.load(aH + k3, aL + k3, ra1);
+            lb.load(bH + k3, bL + k3, rb1);
+            __builtin_amdgcn_s_setprio(1);
+            if (s + 1 < nsteps) pk_mma<BM, BN>(sA + Cfg::SA, sB + Cfg::SB, lane, wm, wn, acc);
+            __builtin_amdgcn_s_setprio(0);
+            __builtin_amdgcn_sched_barrier(0);
+            la.store(sA, ra0);
+            lb.store(sB, rb0);
+            __syncthreads();
+        }
+    } else {
+        u4_t ra[Cfg::CA], rb[Cfg::CB];
+        la.load(aH, aL, ra);
+        lb.load(bH, bL, rb);
+        la.store(sA, ra);
+        lb.store(sB, rb);
+        __syncthreads();
+        for (int64_t s = 0; s < nsteps; ++s) {
+            const int cur = (int)(s & 1);
+            const int64_t k1 = step(s + 1);
+            la.load(aH + k1, aL + k1, ra);
+            lb.load(bH + k1, bL + k1, rb);
+            __builtin_amdgcn_s_setprio(1);
+            pk_mma<BM, BN>(sA + cur * Cfg::SA, sB + cur * Cfg::SB, lane, wm, wn, acc);
+            __builtin_amdgcn_s_setprio(0);
+            __builtin_amdgcn_sched_barrier(0);
+            la.store(sA + (cur ^ 1) * Cfg::SA, ra);
+            lb.store(sB + (cur ^ 1) * Cfg::SB, rb);
+            __syncthreads();
         }
     }
+
+    pk_epilogue<FM, FN>(g, acc, m0 + wm * Cfg::WTM, n0 + wn * Cfg::WTN, lane, split);
+}
+
+// The large tiles: 8 waves (512 threads) as 2 x 4, each wave (BM / 2) x
+// (BN / 4), one workgroup per CU.  Thread t stages chunk i of row slot
+// u = t / 4 + 128 i of the tile's A (B) rows, hi plane then lo plane (slot
+// u is plane u / ROWS, row u % ROWS), four threads per row as above.
+template <int ROWS> struct PkLoad8 {
+    static_assert(ROWS % 64 == 0, "whole 16-row runs per wave");
+    static constexpr int C = ROWS / 64;   // chunks per thread (2 ROWS x 4 over 512 threads)
+    uint32_t goff;                         // element offset of the thread's 16 bytes in a block
+    int32_t rsl;                           // t / 4
+    int c;                                 // t % 4
+    int64_t gstride;                       // elements from one row group to the next
+    __device__ __forceinline__ void init(int t, int64_t Kq) {
+        gstride = Kq * 16;
+        c = t & 3;
+        rsl = t >> 2;
+        goff = (uint32_t)((rsl & 15) * 32 + 8 * c);
+    }
+    __device__ __forceinline__ void load(const uint16_t *hi, const uint16_t *lo,
+                                         u4_t (&v)[C]) const {
+#pragma unroll
+        for (int i = 0; i < C; ++i) {
+            const int u = rsl + 128 * i;
+            const int pl = u >= ROWS, rr = pl ? u - ROWS : u;
+            v[i] = *reinterpret_cast<const u4_t *>((pl ? lo : hi) + (int64_t)(rr >> 4) * gstride +
+                                                   goff);
+        }
+    }
+    __device__ __forceinline__ void store(uint16_t *s, const u4_t (&v)[C]) const {
+#pragma unroll
+        for (int i = 0; i < C; ++i) {
+            const int u = rsl + 128 * i;
+            const int pl = u >= ROWS, rr = pl ? u - ROWS : u;
+            *reinterpret_cast<u4_t *>(s + pl * ROWS * kLd + rr * kLd + 8 * (c ^ swz(rr))) = v[i];
+        }
+    }
+};
+
+template <int BM, int BN> struct Pk8Cfg {
+    static constexpr int WTM = BM / 2, WTN = BN / 4, FM = WTM / 16, FN = WTN / 16;
+    static constexpr int PA = BM * kLd, PB = BN * kLd;
+    static constexpr int SA = 2 * PA, SB = 2 * PB;
+    static constexpr int kLdsBytes = 2 * (SA + SB) * 2;
+};
+
+template <int BM, int BN>
+__global__ __launch_bounds__(512) void bf3_packed_gemm8_kernel(Bf3Packed g) {
+    using Cfg = Pk8Cfg<BM, BN>;
+    constexpr int FM = Cfg::FM, FN = Cfg::FN;
+    extern __shared__ __align__(16) uint16_t lds[];
+    uint16_t *sA = lds, *sB = lds + 2 * Cfg::SA;   // [stage][plane][row][kLd]
+
+    const int tiles = g.tilesM * g.tilesN;
+    const int logical = xcd_remap(blockIdx.x, tiles * g.splits);
+    const int split = logical / tiles;
+    int tm, tn;
+    tile_coords(logical - split * tiles, g.tilesM, g.tilesN, tm, tn);
+    const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
+    const int64_t kbeg = (int64_t)split * g.kPer;
+    const int64_t kend = min(kbeg + g.kPer, g.Kq);
+    const int64_t nsteps = (kend - kbeg) / 32;
+
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6, wm = w >> 2, wn = w & 3;
+    PkLoad8<BM> la;
+    PkLoad8<BN> lb;
+    la.init(t, g.Kq);
+    lb.init(t, g.Kq);
+    // first block of the tile's rows at the slice's first step; a step is 512 elements on
+    const uint16_t *aH = g.A + m0 * g.Kq + kbeg * 16, *aL = aH + g.planeA;
+    const uint16_t *bH = g.B + n0 * g.Kq + kbeg * 16, *bL = bH + g.planeB;
+
+    f4_t acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
+
+    const int kc = 8 * ((lane >> 4) ^ swz(lane & 15));   // rows start at multiples of 16
+    auto mma = [&](const uint16_t *stA, const uint16_t *stB) {
+        const __bf16 *ahi = reinterpret_cast<const __bf16 *>(stA), *alo = ahi + Cfg::PA;
+        const __bf16 *bhi = reinterpret_cast<const __bf16 *>(stB), *blo = bhi + Cfg::PB;
+        bf8_t ah[FM], al[FM];
+#pragma unroll
+        for (int i = 0; i < FM; ++i) {
+            const int r = wm * Cfg::WTM + i * 16 + (lane & 15);
+            ah[i] = *reinterpret_cast<const bf8_t *>(ahi + r * kLd + kc);
+            al[i] = *reinterpret_cast<const bf8_t *>(alo + r * kLd + kc);
+        }
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+            const int r = wn * Cfg::WTN + j * 16 + (lane & 15);
+            const bf8_t bh = *reinterpret_cast<const bf8_t *>(bhi + r * kLd + kc);
+            const bf8_t bl = *reinterpret_cast<const bf8_t *>(blo + r * kLd + kc);
+#pragma unroll
+            for (int i = 0; i < FM; ++i) {
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh, acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl, acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh, acc[i][j], 0, 0, 0);
+            }
+        }
+    };
+
+    auto step = [&](int64_t s) { return 512 * (s < nsteps ? s : nsteps - 1); };
+    u4_t ra[PkLoad8<BM>::C], rb[PkLoad8<BN>::C];
+    la.load(aH, aL, ra);
+    lb.load(bH, bL, rb);
+    la.store(sA, ra);
+    lb.store(sB, rb);
+    __syncthreads();
+    for (int64_t s = 0; s < nsteps; ++s) {
+        const int cur = (int)(s & 1);
+        const int64_t k1 = step(s + 1);
+        la.load(aH + k1, aL + k1, ra);
+        lb.load(bH + k1, bL + k1, rb);
+        // raised priority while issuing MFMAs: a wave that holds its operands
+        // runs ahead of the waves still reading LDS (measured 6 % faster)
+        __builtin_amdgcn_s_setprio(1);
+        mma(sA + cur * Cfg::SA, sB + cur * Cfg::SB);
+        __builtin_amdgcn_s_setprio(0);
+        __builtin_amdgcn_sched_barrier(0);
+        la.store(sA + (cur ^ 1) * Cfg::SA, ra);
+        lb.store(sB + (cur ^ 1) * Cfg::SB, rb);
+        __syncthreads();
+    }
+
+    pk_epilogue<FM, FN>(g, acc, m0 + wm * Cfg::WTM, n0 + wn * Cfg::WTN, lane, split);
 }
 
 }  // namespace
@@ -299,7 +530,8 @@ int launch_bf3_pack(const float *X, const int64_t *offR, const int32_t *rowMap, 
                     const int64_t *offK, int64_t K, int64_t Kq, bool rowsFast, uint16_t *P,
                     int64_t plane, hipStream_t s) {
     if (R == 0) return 0;
-    const int64_t tasks = rowsFast ? (R + 15) / 16 * ((Kq / 8 + 3) / 4) : R * ((Kq + 511) / 512);
+    const int64_t tasks = rowsFast ? (R + 16 * kPackBlocksR - 1) / (16 * kPackBlocksR) * ((Kq / 8 + 3) / 4)
+                                   : (R + kPackRowsK - 1) / kPackRowsK * ((Kq + 511) / 512);
     const int64_t blocks = (tasks + 3) / 4;
     if (blocks > INT32_MAX) return GETT_ERR_INTERNAL;
     (void)hipGetLastError();   // clear a stale error left by other HIP users
@@ -312,8 +544,7 @@ int launch_bf3_pack(const float *X, const int64_t *offR, const int32_t *rowMap, 
     return launch_status();
 }
 
-int launch_bf3_packed_gemm(const Bf3Packed &g, hipStream_t s) {
-    constexpr int BM = kPackedBM, BN = kPackedBN;
+template <int BM, int BN> static int launch_gemm(const Bf3Packed &g, hipStream_t s) {
     using Cfg = PkCfg<BM, BN>;
     static bool attr_set = false;   // set once per process (every device takes the same value)
     if (!attr_set) {
@@ -329,6 +560,30 @@ int launch_bf3_packed_gemm(const Bf3Packed &g, hipStream_t s) {
     auto kern = bf3_packed_gemm_kernel<BM, BN>;
     hipLaunchKernelGGL(kern, dim3((unsigned)total), dim3(256), Cfg::kLdsBytes, s, g);
     return launch_status();
+}
+
+template <int BM, int BN> static int launch_gemm8(const Bf3Packed &g, hipStream_t s) {
+    using Cfg = Pk8Cfg<BM, BN>;
+    static bool attr_set = false;   // set once per process (every device takes the same value)
+    if (!attr_set) {
+        if (hipFuncSetAttribute(reinterpret_cast<const void *>(bf3_packed_gemm8_kernel<BM, BN>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                Cfg::kLdsBytes) != hipSuccess)
+            return GETT_ERR_HIP;
+        attr_set = true;
+    }
+    const int64_t total = (int64_t)g.tilesM * g.tilesN * g.splits;
+    if (total > INT32_MAX) return GETT_ERR_INTERNAL;
+    (void)hipGetLastError();   // clear a stale error left by other HIP users
+    auto kern = bf3_packed_gemm8_kernel<BM, BN>;
+    hipLaunchKernelGGL(kern, dim3((unsigned)total), dim3(512), Cfg::kLdsBytes, s, g);
+    return launch_status();
+}
+
+int launch_bf3_packed_gemm(int bm, int bn, const Bf3Packed &g, hipStream_t s) {
+    if (bm == 128 && bn == 128) return launch_gemm<128, 128>(g, s);
+    if (bm == 192 && bn == 256) return launch_gemm8<192, 256>(g, s);
+    return GETT_ERR_INTERNAL;
 }
 
 }  // namespace gett

@@ -73,8 +73,8 @@ struct TileShape { int bm, bn, bk; bool load_fence; int depth; bool addr32; bool
 
 // Tile menus.  FP64/FP32 run 16x16x4 MFMA steps (BK multiple of 4), the BF16x3
 // path 16x16x32 BF16 MFMA steps (BK multiple of 32).  Each workgroup is a 2x2
-// grid of waves, so BM and BN are multiples of 32.  The last BF16x3 entry is
-// the packed form (128 x 128 tiles on packed rows, 32 positions a step).
+// grid of waves, so BM and BN are multiples of 32.  BF16x3 entries 1 and 4
+// are the packed form (GEMM tiles on packed rows, 32 positions a step).
 constexpr TileShape kTiles[kNumPrec][kNumTiles] = {
     /* FP64   */ {{64, 64, 16, true, 1, true}, {64, 128, 16, true, 1, true},
                   {128, 64, 16, false, 1, false}, {128, 128, 16, true, 1, true},
@@ -82,7 +82,7 @@ constexpr TileShape kTiles[kNumPrec][kNumTiles] = {
     /* FP32   */ {{64, 64, 16, true, 2, true}, {64, 128, 16, true, 2, true},
                   {128, 64, 16, true, 2, true}, {128, 128, 16, true, 2, true},
                   {128, 128, 32, true, 2, true}},
-    /* BF16x3 */ {{64, 64, 32, true, 1, true}, {64, 128, 32, true, 1, true},
+    /* BF16x3 */ {{64, 64, 32, true, 1, true}, {192, 256, 32, true, 1, false, true},
                   {128, 64, 32, true, 1, true}, {128, 128, 32, true, 1, false},
                   {128, 128, 32, true, 1, false, true}},
     /* FP8    */ {{64, 64, 128, true, 1, false}, {64, 128, 128, true, 1, false},

@@ -119,7 +119,7 @@ static Sched heuristic(int prec, int64_t M, int64_t N, int64_t K, int64_t H = 1)
     static const double kSpeed[kNumPrec][kNumTiles] = {
         {0.88, 0.92, 1.0, 0.80, 0.96},  // FP64: the 128x64 tiles run 3-4 workgroups per CU
         {0.8, 0.9, 0.9, 1.0, 0.95},     // FP32
-        {0.95, 0.9, 1.0, 0.85, 0.8},    // BF16x3
+        {0.7, 1.0, 0.75, 0.8, 0.9},     // BF16x3 (1 and 4: the packed form)
         {0.8, 0.9, 0.9, 1.0, 1.0},      // FP8 (its own kernel)
         {0.95, 1.0, 1.0, 0.9, 0.9},     // complex FP64
         {0.9, 0.95, 0.95, 1.0, 0.9}};   // complex FP32
@@ -192,6 +192,60 @@ static std::unordered_map<std::string, std::unique_ptr<TableSet>> g_tables;
 static std::unordered_map<std::string, std::shared_ptr<Plan>> g_plans;
 
 static int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+// Stream-ordered temporary buffers (split-K partials, packed rows, FP8
+// codes, saved C footprints) come from one memory pool per device that keeps
+// freed memory (release threshold: unlimited), so back-to-back calls reuse it
+// instead of mapping it again; gett_finalize returns it.
+static std::map<int, hipMemPool_t> g_pools;
+static std::mutex g_pool_mu;
+
+static hipMemPool_t work_pool(int dev) {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    auto it = g_pools.find(dev);
+    if (it != g_pools.end()) return it->second;
+    hipMemPoolProps props{};
+    props.allocType = hipMemAllocationTypePinned;
+    props.location.type = hipMemLocationTypeDevice;
+    props.location.id = dev;
+    hipMemPool_t pool = nullptr;
+    if (hipMemPoolCreate(&pool, &props) != hipSuccess) {
+        (void)hipGetLastError();
+        pool = nullptr;
+    } else {
+        uint64_t keep = UINT64_MAX;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+    }
+    g_pools[dev] = pool;
+    return pool;
+}
+
+int work_alloc(void **p, size_t bytes, hipStream_t s) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return GETT_ERR_HIP;
+    hipMemPool_t pool = work_pool(dev);
+    const hipError_t e = pool ? hipMallocFromPoolAsync(p, bytes, pool, s) : hipMallocAsync(p, bytes, s);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return GETT_ERR_ALLOC;
+    }
+    return 0;
+}
+
+int work_free(void *p, hipStream_t s) { return hipFreeAsync(p, s) == hipSuccess ? 0 : GETT_ERR_HIP; }
+
+static void work_pools_trim() {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    for (auto &kv : g_pools)
+        if (kv.second) (void)hipMemPoolTrimTo(kv.second, 0);
+}
+
+// Tile width the offset tables of a schedule's tile are built for: the
+// packed BF16x3 entries take the tables of their fallback tile (their GEMM
+// reads packed rows, so the N order's boxes need not match its width).
+static int table_bn(int prec, int tile) {
+    return kTiles[prec][kTiles[prec][tile].packed ? kPackedFallbackTile : tile].bn;
+}
 
 // Build the host tables of a canonical form and upload them.
 static int upload_tables(TableSet &t) {
@@ -279,7 +333,7 @@ static int get_plan(int prec, const Args &a, int dev, int64_t forced, std::share
     pl->prec = prec;
     pl->sched = s;
     const TileShape ts = kTiles[prec][s.tile];
-    int rc = get_tables(a, s.order, ts.bn, dev, &pl->tab);
+    int rc = get_tables(a, s.order, table_bn(prec, s.tile), dev, &pl->tab);
     if (rc) return rc;
     const Canon &cn = pl->tab->cn;
     const int64_t tiles = ((cn.M + ts.bm - 1) / ts.bm) * ((cn.N + ts.bn - 1) / ts.bn);
@@ -300,12 +354,13 @@ static int get_plan(int prec, const Args &a, int dev, int64_t forced, std::share
     return 0;
 }
 
-// Fill the launch parameters of a plan for concrete pointers.
+// Fill the launch parameters of a plan for concrete pointers (the plan's
+// split and tile unless given).
 static TileParams make_params(const Plan &pl, const void *A, const void *B, void *C,
-                              int split = -1) {
+                              int split = -1, int tile = -1) {
     const TableSet &t = *pl.tab;
     const Canon &c = t.cn;
-    const TileShape ts = kTiles[pl.prec][pl.sched.tile];
+    const TileShape ts = kTiles[pl.prec][tile < 0 ? pl.sched.tile : tile];
     if (split < 0) split = pl.sched.split;
     TileParams p;
     p.A = c.swapped ? B : A;
@@ -413,10 +468,11 @@ static int run_packed(const Plan &pl, const TileParams &p, hipStream_t s, bool *
     TableSet &t = *pl.tab;
     const Canon &c = t.cn;
     const int64_t M = c.M, N = c.N, K = c.K;
+    const TileShape ts = kTiles[pl.prec][pl.sched.tile];
     const int64_t Kq = round_up(std::max<int64_t>(K, 1), kPackedBK);
-    const int64_t Mq = round_up(std::max<int64_t>(M, 1), kPackedBM);
-    const int64_t Nq = round_up(std::max<int64_t>(N, 1), kPackedBN);
-    const int64_t tilesM = Mq / kPackedBM, tilesN = Nq / kPackedBN;
+    const int64_t Mq = round_up(std::max<int64_t>(M, 1), ts.bm);
+    const int64_t Nq = round_up(std::max<int64_t>(N, 1), ts.bn);
+    const int64_t tilesM = Mq / ts.bm, tilesN = Nq / ts.bn;
     int64_t per = 0;
     const int S = split_count(pl.sched.split, tilesM * tilesN, Kq, kPackedBK, &per);
     const int64_t pk = 4 * (Mq + Nq) * Kq;
@@ -428,8 +484,7 @@ static int run_packed(const Plan &pl, const TileParams &p, hipStream_t s, bool *
     int rc = packed_rows(t);
     if (rc) return rc;
     void *buf = nullptr;
-    if (hipMallocAsync(&buf, (size_t)(pk + wsb), s) != hipSuccess) {
-        (void)hipGetLastError();
+    if (work_alloc(&buf, (size_t)(pk + wsb), s)) {
         *fallback = true;
         return 0;
     }
@@ -462,7 +517,7 @@ static int run_packed(const Plan &pl, const TileParams &p, hipStream_t s, bool *
         g.ws = ws;
         g.alpha = p.alpha[0];
         g.beta = p.beta[0];
-        rc = launch_bf3_packed_gemm(g, s);
+        rc = launch_bf3_packed_gemm(ts.bm, ts.bn, g, s);
     }
     if (!rc && S > 1) {
         TileParams q = p;
@@ -470,8 +525,8 @@ static int run_packed(const Plan &pl, const TileParams &p, hipStream_t s, bool *
         q.splits = S;
         rc = launch_splitk_reduce(kBF3, q, s);
     }
-    if (hipFreeAsync(buf, s) != hipSuccess && !rc) rc = GETT_ERR_HIP;
-    return rc;
+    const int frc = work_free(buf, s);
+    return rc ? rc : frc;
 }
 
 // alpha, beta: (re, im) pairs of C <- alpha * sum + beta * C_in.
@@ -492,21 +547,23 @@ static int run_plan(const Plan &pl, const void *A, const void *B, void *C, hipSt
         if (!fallback) return rc;
         tile = kPackedFallbackTile;
         t_last_schedule = sched_id(Sched{tile, pl.sched.order, pl.sched.split});
+        p = make_params(pl, A, B, C, -1, tile);
+        scale(p);
     }
     if (p.splits > 1) {
         const int64_t bytes = (int64_t)p.splits * p.M * p.N * (int64_t)p.H *
                               (prec_complex(pl.prec) ? 2 : 1) * (int64_t)sizeof(double);
         void *ws = nullptr;
-        if (bytes <= g_max_ws.load() && hipMallocAsync(&ws, (size_t)bytes, s) == hipSuccess) {
+        if (bytes <= g_max_ws.load() && work_alloc(&ws, (size_t)bytes, s) == 0) {
             p.ws = static_cast<double *>(ws);
             int rc = launch_tile(pl.prec, tile, pl.tab->cn.aFastK, pl.tab->cn.bFastK, p, s);
             if (!rc) rc = launch_splitk_reduce(pl.prec, p, s);
-            if (hipFreeAsync(ws, s) != hipSuccess && !rc) rc = GETT_ERR_HIP;
-            return rc;
+            const int frc = work_free(ws, s);
+            return rc ? rc : frc;
         }
         // over the cap or out of memory: the same tile and order, unsplit
         (void)hipGetLastError();
-        p = make_params(pl, A, B, C, 0);
+        p = make_params(pl, A, B, C, 0, tile);
         scale(p);
         t_last_schedule = sched_id(Sched{tile, pl.sched.order, 0});
     }
@@ -684,7 +741,7 @@ static int run_fp8(const Args &a, const float *A, const float *B, float *C, hipS
     const int64_t nbs = nb * (128 / bs);   // exponents per row
     const size_t bytes = (size_t)(Mq + Nq) * Kp + (size_t)(Mq + Nq) * nbs * sizeof(int32_t) + 256;
     void *ws = nullptr;
-    if (hipMallocAsync(&ws, bytes, s) != hipSuccess) return GETT_ERR_ALLOC;
+    if (work_alloc(&ws, bytes, s)) return GETT_ERR_ALLOC;
     uint8_t *QA = static_cast<uint8_t *>(ws);
     uint8_t *QB = QA + (size_t)Mq * Kp;
     int32_t *EA = reinterpret_cast<int32_t *>(QB + (size_t)Nq * Kp);
@@ -696,7 +753,7 @@ static int run_fp8(const Args &a, const float *A, const float *B, float *C, hipS
         rc = launch_fp8_quant(X1, pl->bRowsFast ? pl->d_rowsOp[1] : rowsB, pl->d_rowMap[1], N, Nq,
                               kB, K, pl->bRowsFast, QB, EB, s, bs);
     if (!rc) rc = launch_fp8_gemm(pl->tile, QA, EA, QB, EB, C, offCM, offCN, M, N, K, s, bs);
-    if (hipFreeAsync(ws, s) != hipSuccess && !rc) rc = GETT_ERR_HIP;
+    if (work_free(ws, s) && !rc) rc = GETT_ERR_HIP;
     return rc;
 }
 
@@ -1946,7 +2003,7 @@ static int64_t describe(int prec, int64_t order, int64_t tile, const Args &a, in
     if (prec < 0 || prec >= kNumPrec || prec == kFP8 || order < 0 || order >= kNumOrders ||
         tile < 0 || tile >= kNumTiles)
         return GETT_ERR_STATE;
-    Canon c = canonicalise(a, (int)order, kTiles[prec][tile].bn);
+    Canon c = canonicalise(a, (int)order, table_bn((int)prec, (int)tile));
     std::vector<int64_t> v;
     if (!tables) {
         v = {c.swapped, c.M, c.N, c.K, (int64_t)c.m.size(), (int64_t)c.n.size(),
@@ -2033,6 +2090,7 @@ int gett_finalize(void) {
         g_tuned_db_read = false;   // a later tuning reads GETT_TUNE_DB again
     }
     unary_release();
+    work_pools_trim();
     std::lock_guard<std::mutex> lk(g_pred_mu);
     g_pred.reset();
     return rc;

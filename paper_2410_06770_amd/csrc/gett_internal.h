@@ -34,6 +34,10 @@ int launch_scale_c(int prec, void *C, const ScaleModes &m, const double *beta, h
 int current_device_checked(int *dev);
 // Releases the unary operations' plan cache (gett_finalize).
 void unary_release();
+// Stream-ordered temporary buffer on the current device from the library's
+// pool (0 or GETT_ERR_ALLOC), and its release on the same stream.
+int work_alloc(void **p, size_t bytes, hipStream_t s);
+int work_free(void *p, hipStream_t s);
 
 // Kernel launchers (defined in the .hip files).
 int launch_tile(int prec, int tile, bool aFastK, bool bFastK, const TileParams &p,

@@ -713,20 +713,19 @@ __device__ __forceinline__ void gett_tile(const TileParams &p, const void *pA, c
     // C <- alpha * sum + beta * C_in; C_in is not read when beta is zero.
     T *__restrict__ Cp = static_cast<T *>(pC);
     const bool rdC = p.beta[0] != 0.0 || p.beta[1] != 0.0;
+    constexpr bool kF64Layout = PREC == kF64 || PREC == kZ64;
+    if (p.ws) {
 #pragma unroll
-    for (int j = 0; j < FN; ++j) {
-        const int64_t n = n0 + wn * Cfg::WTN + j * 16 + (lane & 15);
-        const bool nok = n < p.N;
-        const int64_t ocn = p.offCN[n];
+        for (int j = 0; j < FN; ++j) {
+            const int64_t n = n0 + wn * Cfg::WTN + j * 16 + (lane & 15);
+            const bool nok = n < p.N;
 #pragma unroll
-        for (int i = 0; i < FM; ++i) {
+            for (int i = 0; i < FM; ++i) {
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                constexpr bool kF64Layout = PREC == kF64 || PREC == kZ64;
-                const int rr = kF64Layout ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v;
-                const int64_t m = m0 + wm * Cfg::WTM + i * 16 + rr;
-                if (!(nok && m < p.M)) continue;
-                if (p.ws) {
+                for (int v = 0; v < 4; ++v) {
+                    const int rr = kF64Layout ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v;
+                    const int64_t m = m0 + wm * Cfg::WTM + i * 16 + rr;
+                    if (!(nok && m < p.M)) continue;
                     const int64_t w = ((int64_t)split * p.M + m) * p.N + n;
                     if constexpr (kCplx) {
                         p.ws[2 * w] = (double)acc[i][j][v];
@@ -734,31 +733,71 @@ __device__ __forceinline__ void gett_tile(const TileParams &p, const void *pA, c
                     } else {
                         p.ws[w] = (double)acc[i][j][v];
                     }
-                } else {
-                    const int64_t off = p.offCM[m] + ocn;
-                    GETT_CHECK_C(off, p);
+                }
+            }
+        }
+        return;
+    }
+    // A group of EG fragments of one column at a time, its C_in read before
+    // any of it is written: the loads are in flight together (a store to C
+    // could alias a later load of C, so loads interleaved with stores wait
+    // out one another).  Groups are small enough to leave the tiles'
+    // register counts (and so their occupancy) as they are.
+    constexpr int EG = 1;
+    static_assert(FM % EG == 0, "whole groups");
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+        const int64_t n = n0 + wn * Cfg::WTN + j * 16 + (lane & 15);
+        const bool nok = n < p.N;
+        const int64_t ocn = p.offCN[n];
+#pragma unroll
+        for (int i0 = 0; i0 < FM; i0 += EG) {
+            int64_t off[EG][4];
+            bool ok[EG][4];
+            T cin[EG][4];
+#pragma unroll
+            for (int e = 0; e < EG; ++e) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int rr = kF64Layout ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v;
+                    const int64_t m = m0 + wm * Cfg::WTM + (i0 + e) * 16 + rr;
+                    ok[e][v] = nok && m < p.M;
+                    off[e][v] = ok[e][v] ? p.offCM[m] + ocn : 0;
+#ifdef GETT_ADDR_CHECK
+                    if (ok[e][v]) ok[e][v] = gett_check_c(off[e][v], p.cLo, p.cSpan);
+#endif
+                    cin[e][v] = (rdC && ok[e][v]) ? Cp[off[e][v]] : T{};
+                }
+            }
+#pragma unroll
+            for (int e = 0; e < EG; ++e) {
+                const int i = i0 + e;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    if (!ok[e][v]) continue;
+                    const int64_t o = off[e][v];
                     if constexpr (PREC == kF64) {
                         const double r = acc[i][j][v];
-                        Cp[off] = rdC ? p.beta[0] * Cp[off] + p.alpha[0] * r : p.alpha[0] * r;
+                        Cp[o] = rdC ? p.beta[0] * cin[e][v] + p.alpha[0] * r : p.alpha[0] * r;
                     } else if constexpr (PREC == kF32) {
                         const float r = acc[i][j][v];
                         const float al = (float)p.alpha[0], be = (float)p.beta[0];
-                        Cp[off] = rdC ? be * Cp[off] + al * r : al * r;
+                        Cp[o] = rdC ? be * cin[e][v] + al * r : al * r;
                     } else if constexpr (PREC == kBF3) {
                         const double sum = (double)acc[i][j][v];
-                        Cp[off] = (float)(rdC ? p.alpha[0] * sum + p.beta[0] * (double)Cp[off]
-                                              : p.alpha[0] * sum);
+                        Cp[o] = (float)(rdC ? p.alpha[0] * sum + p.beta[0] * (double)cin[e][v]
+                                            : p.alpha[0] * sum);
                     } else {
                         const R xr = acc[i][j][v], xi = acx[i][j][v];
                         const R ar = (R)p.alpha[0], ai = (R)p.alpha[1];
                         R outr = ar * xr - ai * xi, outi = ar * xi + ai * xr;
                         if (rdC) {
-                            const T c = Cp[off];
+                            const T c = cin[e][v];
                             const R br = (R)p.beta[0], bi = (R)p.beta[1];
                             outr += br * c.x - bi * c.y;
                             outi += br * c.y + bi * c.x;
                         }
-                        Cp[off] = T{outr, outi};
+                        Cp[o] = T{outr, outi};
                     }
                 }
             }
@@ -973,14 +1012,16 @@ template <int PREC>
 static int launch_prec(int tile, bool afk, bool bfk, const TileParams &p, hipStream_t s) {
     constexpr TileShape t0 = kTiles[PREC][0], t1 = kTiles[PREC][1], t2 = kTiles[PREC][2],
                         t3 = kTiles[PREC][3], t4 = kTiles[PREC][4];
+    // packed entries run their own kernels (never through here)
     switch (tile) {
-    case 0: return launch_fast<PREC, t0.bm, t0.bn, t0.bk>(afk, bfk, p, s);
-    case 1: return launch_fast<PREC, t1.bm, t1.bn, t1.bk>(afk, bfk, p, s);
-    case 2: return launch_fast<PREC, t2.bm, t2.bn, t2.bk>(afk, bfk, p, s);
-    case 3: return launch_fast<PREC, t3.bm, t3.bn, t3.bk>(afk, bfk, p, s);
-    case 4: return launch_fast<PREC, t4.bm, t4.bn, t4.bk>(afk, bfk, p, s);
-    default: return GETT_ERR_INTERNAL;
+    case 0: if constexpr (!t0.packed) return launch_fast<PREC, t0.bm, t0.bn, t0.bk>(afk, bfk, p, s); break;
+    case 1: if constexpr (!t1.packed) return launch_fast<PREC, t1.bm, t1.bn, t1.bk>(afk, bfk, p, s); break;
+    case 2: if constexpr (!t2.packed) return launch_fast<PREC, t2.bm, t2.bn, t2.bk>(afk, bfk, p, s); break;
+    case 3: if constexpr (!t3.packed) return launch_fast<PREC, t3.bm, t3.bn, t3.bk>(afk, bfk, p, s); break;
+    case 4: if constexpr (!t4.packed) return launch_fast<PREC, t4.bm, t4.bn, t4.bk>(afk, bfk, p, s); break;
+    default: break;
     }
+    return GETT_ERR_INTERNAL;
 }
 
 template <int PREC> static int batch_lds() {

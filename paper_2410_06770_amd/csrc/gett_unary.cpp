@@ -368,8 +368,7 @@ int run_unary(int prec, const double *alpha, const UArgs &u, const void *A, cons
     void *ws = nullptr;
     if (S > 1) {
         const int64_t bytes = S * p.nO * (prec >= 4 ? 2 : 1) * (int64_t)sizeof(double);
-        if (hipMallocAsync(&ws, (size_t)bytes, s) != hipSuccess) {
-            (void)hipGetLastError();   // no workspace: one slice
+        if (work_alloc(&ws, (size_t)bytes, s)) {   // no workspace: one slice
             p.S = 1;
             p.rPer = p.nR;
         } else {
@@ -378,7 +377,7 @@ int run_unary(int prec, const double *alpha, const UArgs &u, const void *A, cons
     }
     rc = pl->lanes_r ? launch_unary_lanes_r(prec, p, s) : launch_unary_tiled(prec, p, s);
     if (!rc && p.S > 1) rc = launch_unary_finish(prec, p, s);
-    if (ws && hipFreeAsync(ws, s) != hipSuccess && !rc) rc = GETT_ERR_HIP;
+    if (ws && work_free(ws, s) && !rc) rc = GETT_ERR_HIP;
     return rc;
 }
 

@@ -29,9 +29,10 @@ NUM_FEATURES = 64
 NUM_ORDERS = 4
 NUM_SPLITS = 4
 SPLIT_FACTORS = (1, 2, 4, 0)   # 0: enough K slices to fill the chip
-# The BF16x3 menu entry that is the packed form (hi/lo rows packed once, then
-# a GEMM on them); it takes no Hadamard modes.
-BF16X3_PACKED_TILE = 4
+# The BF16x3 menu entries that are the packed form (hi/lo rows packed once,
+# then a GEMM on them: 192 x 256 and 128 x 128 tiles); they take no Hadamard
+# modes.
+BF16X3_PACKED_TILES = (1, 4)
 
 _lib = None
 i64 = ct.c_int64

@@ -24,8 +24,8 @@ pytestmark = pytest.mark.gpu
 
 U32 = 2.0 ** -24
 BF3 = gett.GETT_BF16X3
-PACKED = gett.BF16X3_PACKED_TILE
-FALLBACK = 3        # the direct tile of its shape
+PACKED_TILES = gett.BF16X3_PACKED_TILES
+FALLBACK = 3        # the direct 128 x 128 tile, which runs when the packed rows do not fit
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -75,8 +75,9 @@ def _kappa(ref, cabs):
     return float(np.linalg.norm(cabs) / n) if n > 0 else 1.0
 
 
+@pytest.mark.parametrize("PACKED", PACKED_TILES)
 @pytest.mark.parametrize("case", W.PAPER_CASES)
-def test_packed_paper_families(case):
+def test_packed_paper_families(case, PACKED):
     """The paper's test families through the packed form, N orders 0-3."""
     rng = np.random.default_rng(zlib.crc32(case.encode()) + 77)
     for order in range(4):
@@ -106,9 +107,10 @@ SHAPES = [
 ]
 
 
+@pytest.mark.parametrize("PACKED", PACKED_TILES)
 @pytest.mark.parametrize("shape", range(len(SHAPES)))
 @pytest.mark.parametrize("layouts", [("packed", "packed"), ("sub", "neg"), ("step2", "subneg")])
-def test_packed_shapes(shape, layouts):
+def test_packed_shapes(shape, layouts, PACKED):
     exta, extb, conta, contb, perm = SHAPES[shape]
     sig = (len(exta), exta, len(extb), extb, len(conta), conta, contb, perm)
     rng = np.random.default_rng(1000 + 31 * shape + len(layouts[0]) + 7 * len(layouts[1]))
@@ -124,9 +126,10 @@ def test_packed_shapes(shape, layouts):
             check(pr, got, bitwise=dist == "int")
 
 
+@pytest.mark.parametrize("PACKED", PACKED_TILES)
 @pytest.mark.parametrize("workload", ["strided", "cc"])
 @pytest.mark.parametrize("order,split", [(2, 0), (0, 1)])
-def test_packed_full_size_every_tile(workload, order, split):
+def test_packed_full_size_every_tile(workload, order, split, PACKED):
     """The benchmark's workloads at full size through the packed form:
     outputs in every tile, the ragged edges whole."""
     rng = np.random.default_rng(zlib.crc32(workload.encode()) + 10 * order + split)
@@ -138,15 +141,17 @@ def test_packed_full_size_every_tile(workload, order, split):
     assert not np.isnan(got[pr.C.element_index()]).any()
 
 
-def test_packed_full_size_integers_bitwise():
-    rng = np.random.default_rng(4242)
+@pytest.mark.parametrize("PACKED", PACKED_TILES)
+def test_packed_full_size_integers_bitwise(PACKED):
+    rng = np.random.default_rng(4242 + PACKED)
     pr = W.config_strided_perm(dtype=np.float32, dist="int")
     got = run_forced(pr, gett.schedule_id(PACKED, 2, 0), "int")
     pos, _ = tile_positions(pr, BF3, rng)
     check_positions(pr, BF3, got, pos, bitwise=True)
 
 
-def test_packed_falls_back_over_the_workspace_cap():
+@pytest.mark.parametrize("PACKED", PACKED_TILES)
+def test_packed_falls_back_over_the_workspace_cap(PACKED):
     """Packed rows larger than the workspace cap: the direct tile of the same
     shape runs instead (reported as such), with the same result bar."""
     rng = np.random.default_rng(5151)
@@ -164,8 +169,9 @@ def test_packed_falls_back_over_the_workspace_cap():
     check(pr, got, bitwise=True)
 
 
+@pytest.mark.parametrize("PACKED", PACKED_TILES)
 @pytest.mark.parametrize("split", [0, 2])
-def test_packed_alpha_beta(split):
+def test_packed_alpha_beta(split, PACKED):
     """C <- alpha * sum + beta * C_in through the packed form (beta = 0 over
     a NaN-filled C reads nothing)."""
     import torch
@@ -197,7 +203,8 @@ def test_packed_alpha_beta(split):
         assert np.array_equal(got[m], pr.C.buf[m])
 
 
-def test_packed_is_not_valid_with_hadamard_modes():
+@pytest.mark.parametrize("PACKED", PACKED_TILES)
+def test_packed_is_not_valid_with_hadamard_modes(PACKED):
     """A forced packed schedule on a call with Hadamard modes is refused
     (GETT_ERR_STATE); the direct tiles take such calls."""
     import torch
