@@ -91,6 +91,8 @@ def lib():
         L.gett_ref_fp8_gemm.argtypes = [i64, i64, i64, vp, vp, vp, vp, vp]
         L.gett_ref_fp8_quantize_bs.argtypes = [vp, i64, vp, i64, vp, i64, vp, vp]
         L.gett_ref_fp8_gemm_bs.argtypes = [i64, i64, i64, i64, vp, vp, vp, vp, vp]
+        L.gett_ref_ozaki_split.argtypes = [vp, i64, vp, i64, vp, i64, vp, vp]
+        L.gett_ref_ozaki_gemm.argtypes = [i64, i64, i64, i64, vp, vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -316,6 +318,32 @@ def fp8_gemm(QA, EA, QB, EB, K, block=128):
         lib().gett_ref_fp8_gemm(M, N, K, *args)
     else:
         lib().gett_ref_fp8_gemm_bs(M, N, K, block, *args)
+    return out.T
+
+
+def ozaki_split(X, rows_off, k_off, slices):
+    """Ozaki splitting of a float64 view's rows (see gett_oracle.c): returns
+    (Q int8 [slices, rows, Kq], E int32 [rows]) with Kq = 64 ceil(K / 64)."""
+    rows, K = len(rows_off), len(k_off)
+    Kq = (K + 63) // 64 * 64
+    Q = np.zeros((slices, rows, Kq), dtype=np.int8)
+    E = np.zeros(rows, dtype=np.int32)
+    ro = np.ascontiguousarray(rows_off, dtype=np.int64)
+    ko = np.ascontiguousarray(k_off, dtype=np.int64)
+    lib().gett_ref_ozaki_split(_ptr(X.buf, X.base), rows, ro.ctypes.data, K, ko.ctypes.data,
+                               slices, Q.ctypes.data, E.ctypes.data)
+    return Q, E
+
+
+def ozaki_gemm(QA, EA, QB, EB, K, slices):
+    """The scheme's product out[m, n] (no C_in), in the order gett_oracle.c
+    states."""
+    M, N = QA.shape[1], QB.shape[1]
+    out = np.zeros((N, M), dtype=np.float64)
+    lib().gett_ref_ozaki_gemm(M, N, K, slices, np.ascontiguousarray(QA).ctypes.data,
+                              np.ascontiguousarray(EA).ctypes.data,
+                              np.ascontiguousarray(QB).ctypes.data,
+                              np.ascontiguousarray(EB).ctypes.data, out.ctypes.data)
     return out.T
 
 

@@ -820,3 +820,70 @@ void gett_ref_fp8_gemm(int64_t M, int64_t N, int64_t K, const uint8_t *QA, const
                        const uint8_t *QB, const int32_t *EB, double *out) {
     gett_ref_fp8_gemm_bs(M, N, K, 128, QA, EA, QB, EB, out);
 }
+
+/* ------------------------------------------------------------------------
+ * Ozaki-scheme splitting and product (Ozaki, Ogita, Oishi and Rump, 2012;
+ * the INT8 form of Ootomo, Ozaki and Yokota, 2024), the emulated DGETT's
+ * model.  Not in the paper; its precision variants are.
+ *
+ * Split: each row r of an operand (rows x K, values X[offR[r] + offK[k]])
+ * gets the binary exponent e_r of its largest magnitude (frexp: max =
+ * f 2^e_r, f in [0.5, 1); 0 for an all-zero row), so every value scaled by
+ * 2^-e_r lies in (-1, 1).  S slices of 7 bits then follow by truncation:
+ * x <- x 2^-e_r; for s = 1 .. S: x <- 128 x, q_s = trunc(x), x <- x - q_s.
+ * Every step is exact in double, |q_s| <= 127, and the value equals
+ * 2^e_r (sum_s q_s 2^-7s + x_S 2^-7S) with |x_S| < 1.
+ * Q is [S][rows][Kq] (int8, zeros past K, Kq = 64 ceil(K / 64)), E [rows].
+ * ------------------------------------------------------------------------ */
+void gett_ref_ozaki_split(const double *X, int64_t rows, const int64_t *offR, int64_t K,
+                          const int64_t *offK, int64_t S, int8_t *Q, int32_t *E) {
+    const int64_t Kq = (K + 63) / 64 * 64;
+#pragma omp parallel for
+    for (int64_t r = 0; r < rows; ++r) {
+        double amax = 0.0;
+        for (int64_t k = 0; k < K; ++k) {
+            const double v = fabs(X[offR[r] + offK[k]]);
+            if (v > amax) amax = v;
+        }
+        int e = 0;
+        if (amax > 0.0) (void)frexp(amax, &e);
+        E[r] = e;
+        for (int64_t k = 0; k < Kq; ++k) {
+            double x = k < K ? ldexp(X[offR[r] + offK[k]], -e) : 0.0;
+            for (int64_t s = 0; s < S; ++s) {
+                x *= 128.0;
+                const double q = trunc(x);
+                x -= q;
+                Q[(s * rows + r) * Kq + k] = (int8_t)q;
+            }
+        }
+    }
+}
+
+/* The scheme's product, without C_in: out[m + M n] = sum over d = S+1 down
+ * to 2 of ldexp(P_d, EA[m] + EB[n] - 7 d), in that order in double, where
+ * P_d = sum over slice pairs (s, t), s + t = d, s, t >= 1, of
+ * sum_k QA[s][m][k] QB[t][n][k], exact in int64 (pairs with s + t > S + 1
+ * are left out: they are below the slicing's own truncation). */
+void gett_ref_ozaki_gemm(int64_t M, int64_t N, int64_t K, int64_t S, const int8_t *QA,
+                         const int32_t *EA, const int8_t *QB, const int32_t *EB, double *out) {
+    const int64_t Kq = (K + 63) / 64 * 64;
+#pragma omp parallel for
+    for (int64_t n = 0; n < N; ++n) {
+        for (int64_t m = 0; m < M; ++m) {
+            double acc = 0.0;
+            for (int64_t d = S + 1; d >= 2; --d) {
+                int64_t p = 0;
+                for (int64_t s = 1; s <= S; ++s) {
+                    const int64_t t = d - s;
+                    if (t < 1 || t > S) continue;
+                    const int8_t *qa = QA + ((s - 1) * M + m) * Kq;
+                    const int8_t *qb = QB + ((t - 1) * N + n) * Kq;
+                    for (int64_t k = 0; k < Kq; ++k) p += (int64_t)qa[k] * (int64_t)qb[k];
+                }
+                acc += ldexp((double)p, EA[m] + EB[n] - 7 * (int)d);
+            }
+            out[m + M * n] = acc;
+        }
+    }
+}
