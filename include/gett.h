@@ -318,7 +318,9 @@ int cgett_unary(const float *alpha, int64_t ranka, const int64_t *exta, const in
    written into it by a kernel on the caller's stream on every call (no plan
    cache, no host-to-device copy).  The schedule is the one forced with
    gett_set_schedule, else the built-in heuristic (the PREDICT and AUTOTUNE
-   policies are not used here).  Returns GETT_ERR_SCRATCH, before any HIP
+   policies are not used here); a packed menu entry (whose rows would need a
+   workspace) is replaced by the direct 128 x 128 tile (entry 3) with the same
+   order and split.  Returns GETT_ERR_SCRATCH, before any HIP
    call, when the six offset tables (2 * (Mp + Np + Kp) int64 entries, each
    group's length padded as in dgett) exceed the array; a split-K schedule
    whose FP64 partials do not fit beside the tables runs unsplit.  Every call

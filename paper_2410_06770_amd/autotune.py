@@ -2,10 +2,12 @@
 keep the results in an append-only, resumable timing database (JSON lines).
 
 Each row: the signature (xGETT integer arguments), its layout tag, the
-precision, and the median time in microseconds of every schedule id (-1 for a
+precision, and the time in microseconds of every schedule id (-1 for a
 schedule that is not valid for the signature), as measured by the library's
-own ``gett_autotune`` (HIP events on the current stream).  Values are drawn on
-the GPU (normal(0,1)); the timings do not depend on them.
+own ``gett_autotune`` (HIP events on the current stream): every valid
+schedule is timed once after one untimed run, then the six fastest are timed
+five times more each, in interleaved rounds, and keep their median.  Values
+are drawn on the GPU (normal(0,1)); the timings do not depend on them.
 
     python -m paper_2410_06770_amd.autotune --db timing.jsonl --count 10000 --heldout-first 1000
 """
@@ -79,7 +81,7 @@ def make_problem_on_device(sig, layout, rng, dtype):
     return pr, (At, Bt, Ct), (At.data_ptr() + basea * e, Bt.data_ptr() + baseb * e, Ct.data_ptr())
 
 
-def time_signature(sig, layout, prec, rng, warmup=0, reps=3):
+def time_signature(sig, layout, prec, rng, warmup=1, reps=5):
     import torch
     dtype = np.float64 if prec == gett.GETT_FP64 else np.float32
     pr, keep, (a, b, c) = make_problem_on_device(sig, layout, rng, dtype)

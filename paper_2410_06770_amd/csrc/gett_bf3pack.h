@@ -1,5 +1,5 @@
-// gett_bf3pack.h -- launch descriptors of the packed BF16x3 path (pack pass
-// and GEMM on the packed rows).
+// gett_bf3pack.h -- launch descriptors of the packed forms (BF16x3 and FP64):
+// the pack pass and the GEMMs on the packed rows.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -28,11 +28,29 @@ struct Bf3Packed {
 };
 
 // Pack one operand: rows R (table offR in GEMM order, or with rowsFast the
-// rows in the operand's memory order with rowMap giving each one's GEMM row)
-// into hi plane P and lo plane P + plane.
-int launch_bf3_pack(const float *X, const int64_t *offR, const int32_t *rowMap, int64_t R,
-                    const int64_t *offK, int64_t K, int64_t Kq, bool rowsFast, uint16_t *P,
-                    int64_t plane, hipStream_t s);
+// rows in the operand's memory order with rowMap giving each one's GEMM row).
+// BF16x3 (f64 false): float values split into hi plane P and lo plane
+// P + plane (bfloat16 elements); FP64: double values copied into plane P.
+int launch_pack(bool f64, const void *X, const int64_t *offR, const int32_t *rowMap, int64_t R,
+                const int64_t *offK, int64_t K, int64_t Kq, bool rowsFast, void *P, int64_t plane,
+                hipStream_t s);
+
+// The packed FP64 form: planes of doubles in 2 KB blocks of 16 rows by 16
+// positions; GEMM tile 128 x 128 (4 waves, two workgroups per CU).
+constexpr int kPacked64BK = 16;   // packed positions per step
+struct F64Packed {
+    const double *A, *B;
+    int64_t Kq;          // packed row length (multiple of 16)
+    int64_t kPer;        // packed positions per K slice (multiple of 16)
+    int32_t tilesM, tilesN, splits, pad_;
+    double *C;
+    const int64_t *offCM, *offCN;
+    int64_t M, N;
+    double *ws;          // FP64 partials [split][M][N] when splits > 1, else null
+    double alpha, beta;  // C <- beta * C_in + alpha * sum (beta == 0: C_in not read)
+};
+int launch_f64_packed_gemm(const F64Packed &g, hipStream_t s);
+
 // GEMM tiles (bm x bn): 128 x 128 (4 waves, two workgroups per CU) and
 // 192 x 256 (8 waves, one per CU); rows padded to the tile.
 int launch_bf3_packed_gemm(int bm, int bn, const Bf3Packed &g, hipStream_t s);

@@ -76,17 +76,51 @@ __device__ __forceinline__ int64_t pk_off(int64_t r, int64_t j, int64_t Kq) {
     return ((r >> 4) * (Kq >> 5) + (j >> 5)) * 512 + (r & 15) * 32 + (j & 31);
 }
 
+// FP64 planes (the packed FP64 form): blocks of 16 rows by 16 positions
+// (2 KB, rows of 128 bytes), row groups outermost; element offset of packed
+// positions j .. j + 7 (j a multiple of 8) of row r.
+__device__ __forceinline__ int64_t pk64_off(int64_t r, int64_t j, int64_t Kq) {
+    return ((r >> 4) * (Kq >> 4) + (j >> 4)) * 256 + (r & 15) * 16 + (j & 15);
+}
+
+// Where a pass puts one chunk (8 packed positions of one row): BF16x3 splits
+// the values into the hi and lo planes, FP64 copies them.
+template <bool F64> struct PackOut;
+template <> struct PackOut<false> {
+    using T = float;
+    static __device__ __forceinline__ void put(void *P, int64_t plane, int64_t r, int64_t c,
+                                               int64_t Kq, const float (&v)[8]) {
+        u4_t hi, lo;
+        split8(v, hi, lo);
+        uint16_t *dst = static_cast<uint16_t *>(P) + pk_off(r, 8 * c, Kq);
+        *reinterpret_cast<u4_t *>(dst) = hi;
+        *reinterpret_cast<u4_t *>(dst + plane) = lo;
+    }
+};
+template <> struct PackOut<true> {
+    using T = double;
+    static __device__ __forceinline__ void put(void *P, int64_t, int64_t r, int64_t c, int64_t Kq,
+                                               const double (&v)[8]) {
+        typedef double d2v_t __attribute__((ext_vector_type(2)));
+        d2v_t *dst = reinterpret_cast<d2v_t *>(static_cast<double *>(P) + pk64_off(r, 8 * c, Kq));
+#pragma unroll
+        for (int i = 0; i < 4; ++i) dst[i] = d2v_t{v[2 * i], v[2 * i + 1]};
+    }
+};
+
 constexpr int kPackRowsK = 4;      // rows per wave, lanes along K
 constexpr int kPackBlocksR = 4;    // 16-row blocks per wave, lanes along the rows
 
 // Lanes along K: one wave per (kPackRowsK rows, group of 512 packed
 // positions); lane l fills chunk l of the group in each row, its contracted
 // offsets read once for all of them.
-__global__ __launch_bounds__(256) void bf3_pack_k_kernel(const float *__restrict__ X,
-                                                         const int64_t *__restrict__ offR,
-                                                         int64_t R, const int64_t *__restrict__ offK,
-                                                         int64_t K, int64_t Kq,
-                                                         uint16_t *__restrict__ P, int64_t plane) {
+template <bool F64>
+__global__ __launch_bounds__(256) void pack_k_kernel(const typename PackOut<F64>::T *__restrict__ X,
+                                                     const int64_t *__restrict__ offR, int64_t R,
+                                                     const int64_t *__restrict__ offK, int64_t K,
+                                                     int64_t Kq, void *__restrict__ P,
+                                                     int64_t plane) {
+    using T = typename PackOut<F64>::T;
     const int64_t ng = (Kq + 511) / 512;
     const int64_t nrb = (R + kPackRowsK - 1) / kPackRowsK;
     const int64_t task = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -108,15 +142,11 @@ __global__ __launch_bounds__(256) void bf3_pack_k_kernel(const float *__restrict
     for (int q = 0; q < kPackRowsK; ++q) {
         const int64_t r = rb * kPackRowsK + q;
         if (r >= R) break;
-        const float *xr = X + offR[r];
-        float v[8];
+        const T *xr = X + offR[r];
+        T v[8];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) v[e] = (valid >> e) & 1 ? xr[ko[e]] : 0.0f;
-        u4_t hi, lo;
-        split8(v, hi, lo);
-        uint16_t *dst = P + pk_off(r, 8 * c, Kq);
-        *reinterpret_cast<u4_t *>(dst) = hi;
-        *reinterpret_cast<u4_t *>(dst + plane) = lo;
+        for (int e = 0; e < 8; ++e) v[e] = (valid >> e) & 1 ? xr[ko[e]] : T(0);
+        PackOut<F64>::put(P, plane, r, c, Kq, v);
     }
 }
 
@@ -125,10 +155,12 @@ __global__ __launch_bounds__(256) void bf3_pack_k_kernel(const float *__restrict
 // and chunk c0 + l / 16, so each load reads 16 neighbouring rows, each row's
 // four chunks are stored together, and the contracted offsets are read once
 // for all the blocks.
-__global__ __launch_bounds__(256) void bf3_pack_rows_kernel(
-    const float *__restrict__ X, const int64_t *__restrict__ rowsOp,
+template <bool F64>
+__global__ __launch_bounds__(256) void pack_rows_kernel(
+    const typename PackOut<F64>::T *__restrict__ X, const int64_t *__restrict__ rowsOp,
     const int32_t *__restrict__ rowMap, int64_t R, const int64_t *__restrict__ offK, int64_t K,
-    int64_t Kq, uint16_t *__restrict__ P, int64_t plane) {
+    int64_t Kq, void *__restrict__ P, int64_t plane) {
+    using T = typename PackOut<F64>::T;
     const int64_t nc = Kq / 8;
     const int64_t cq = (nc + 3) / 4;
     const int64_t task = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -148,15 +180,11 @@ __global__ __launch_bounds__(256) void bf3_pack_rows_kernel(
     for (int b = 0; b < kPackBlocksR; ++b) {
         const int64_t p = (sb * kPackBlocksR + b) * 16 + (lane & 15);
         if (p >= R) break;
-        const float *xr = X + rowsOp[p];
-        float v[8];
+        const T *xr = X + rowsOp[p];
+        T v[8];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) v[e] = (valid >> e) & 1 ? xr[ko[e]] : 0.0f;
-        u4_t hi, lo;
-        split8(v, hi, lo);
-        uint16_t *dst = P + pk_off(rowMap[p], 8 * c, Kq);
-        *reinterpret_cast<u4_t *>(dst) = hi;
-        *reinterpret_cast<u4_t *>(dst + plane) = lo;
+        for (int e = 0; e < 8; ++e) v[e] = (valid >> e) & 1 ? xr[ko[e]] : T(0);
+        PackOut<F64>::put(P, plane, rowMap[p], c, Kq, v);
     }
 }
 
@@ -524,23 +552,181 @@ __global__ __launch_bounds__(512) void bf3_packed_gemm8_kernel(Bf3Packed g) {
     pk_epilogue<FM, FN>(g, acc, m0 + wm * Cfg::WTM, n0 + wn * Cfg::WTN, lane, split);
 }
 
+// ---------------------------------------------------------------------------
+// The packed FP64 form: the same pass (values copied, not split) into 2 KB
+// blocks of 16 rows by 16 positions, and a GEMM on the 16x16x4 FP64 MFMA.
+// ---------------------------------------------------------------------------
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef double d2v_t __attribute__((ext_vector_type(2)));
+
+// LDS rows hold one step's 16 positions (128 bytes, unpadded); position k of
+// row r sits at k ^ (r % 16), so the MFMA operand reads (16 rows, one
+// position) and the 16-byte stores (eight threads per row) are free of bank
+// conflicts.  A 16-byte chunk (positions 2c, 2c + 1) lands on the aligned
+// pair c ^ ((r % 16) / 2), its two values swapped when r is odd.
+template <int ROWS> struct Pk64Load {
+    static_assert(ROWS % 32 == 0, "32 rows per chunk index");
+    static constexpr int C = ROWS / 32;   // 16-byte chunks per thread (ROWS x 8 over 256)
+    uint32_t goff;      // element offset of the thread's chunk inside a block
+    int rg0, row0, c;
+    int64_t gstride;    // elements from one row group to the next (Kq * 16)
+    __device__ __forceinline__ void init(int t, int64_t Kq) {
+        c = t & 7;
+        row0 = t >> 3;   // 0 .. 31
+        rg0 = row0 >> 4;
+        gstride = Kq * 16;
+        goff = (uint32_t)((row0 & 15) * 16 + 2 * c);
+    }
+    __device__ __forceinline__ void load(const double *base, d2v_t (&v)[C]) const {
+#pragma unroll
+        for (int i = 0; i < C; ++i)
+            v[i] = *reinterpret_cast<const d2v_t *>(base + (int64_t)(2 * i + rg0) * gstride + goff);
+    }
+    __device__ __forceinline__ void store(double *sm, const d2v_t (&v)[C]) const {
+        const int m = row0 & 15;   // the same for every chunk (rows 32 i apart)
+        const int q = c ^ (m >> 1);
+#pragma unroll
+        for (int i = 0; i < C; ++i) {
+            const int row = 32 * i + row0;
+            const d2v_t x = (m & 1) ? d2v_t{v[i].y, v[i].x} : v[i];
+            *reinterpret_cast<d2v_t *>(sm + row * 16 + 2 * q) = x;
+        }
+    }
+};
+
+template <int BM, int BN>
+__global__ __launch_bounds__(256) void f64_packed_gemm_kernel(F64Packed g) {
+    constexpr int WTM = BM / 2, WTN = BN / 2, FM = WTM / 16, FN = WTN / 16;
+    constexpr int SA = BM * 16, SB = BN * 16;   // doubles of one LDS stage per operand
+    extern __shared__ __align__(16) double lds64[];
+    double *sA = lds64, *sB = lds64 + 2 * SA;
+
+    const int tiles = g.tilesM * g.tilesN;
+    const int logical = xcd_remap(blockIdx.x, tiles * g.splits);
+    const int split = logical / tiles;
+    int tm, tn;
+    tile_coords(logical - split * tiles, g.tilesM, g.tilesN, tm, tn);
+    const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
+    const int64_t kbeg = (int64_t)split * g.kPer;
+    const int64_t kend = min(kbeg + g.kPer, g.Kq);
+    const int64_t nsteps = (kend - kbeg) / 16;
+
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6, wm = w >> 1, wn = w & 1;
+    Pk64Load<BM> la;
+    Pk64Load<BN> lb;
+    la.init(t, g.Kq);
+    lb.init(t, g.Kq);
+    const double *aB = g.A + m0 * g.Kq + kbeg * 16, *bB = g.B + n0 * g.Kq + kbeg * 16;
+
+    d4_t acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) acc[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
+
+    const int lr = lane & 15, lk = lane >> 4;
+    auto mma = [&](const double *stA, const double *stB) {
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+            const int ph = (4 * kk + lk) ^ lr;   // rows start at multiples of 16
+            double a[FM], b[FN];
+#pragma unroll
+            for (int i = 0; i < FM; ++i) a[i] = stA[(wm * WTM + i * 16 + lr) * 16 + ph];
+#pragma unroll
+            for (int j = 0; j < FN; ++j) b[j] = stB[(wn * WTN + j * 16 + lr) * 16 + ph];
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+    };
+
+    auto step = [&](int64_t s) { return 256 * (s < nsteps ? s : nsteps - 1); };
+    d2v_t ra[Pk64Load<BM>::C], rb[Pk64Load<BN>::C];
+    la.load(aB, ra);
+    lb.load(bB, rb);
+    la.store(sA, ra);
+    lb.store(sB, rb);
+    __syncthreads();
+    for (int64_t s = 0; s < nsteps; ++s) {
+        const int cur = (int)(s & 1);
+        const int64_t k1 = step(s + 1);
+        la.load(aB + k1, ra);
+        lb.load(bB + k1, rb);
+        mma(sA + cur * SA, sB + cur * SB);
+        __builtin_amdgcn_sched_barrier(0);
+        la.store(sA + (cur ^ 1) * SA, ra);
+        lb.store(sB + (cur ^ 1) * SB, rb);
+        __syncthreads();
+    }
+
+    // Epilogue: fragment (i, j), register v of lane l holds M row
+    // l / 16 + 4 v and N column l % 16 of the fragment; FP64 partials of a K
+    // slice, or C <- beta C_in + alpha sum, one fragment's C_in read before
+    // any of it is written.
+    double *__restrict__ C = g.C;
+    const bool rdC = g.beta != 0.0;
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+        const int64_t n = n0 + wn * WTN + j * 16 + lr;
+        const bool nok = n < g.N;
+        const int64_t ocn = nok ? g.offCN[n] : 0;
+#pragma unroll
+        for (int i = 0; i < FM; ++i) {
+            int64_t off[4];
+            bool ok[4];
+            double cin[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t m = m0 + wm * WTM + i * 16 + lk + 4 * v;
+                ok[v] = nok && m < g.M;
+                if (g.ws) {
+                    if (ok[v]) g.ws[((int64_t)split * g.M + m) * g.N + n] = acc[i][j][v];
+                    ok[v] = false;
+                    continue;
+                }
+                off[v] = ok[v] ? g.offCM[m] + ocn : 0;
+                cin[v] = (rdC && ok[v]) ? C[off[v]] : 0.0;
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                if (!ok[v]) continue;
+                const double r = acc[i][j][v];
+                C[off[v]] = rdC ? g.beta * cin[v] + g.alpha * r : g.alpha * r;
+            }
+        }
+    }
+}
+
 }  // namespace
 
-int launch_bf3_pack(const float *X, const int64_t *offR, const int32_t *rowMap, int64_t R,
-                    const int64_t *offK, int64_t K, int64_t Kq, bool rowsFast, uint16_t *P,
-                    int64_t plane, hipStream_t s) {
+int launch_pack(bool f64, const void *X, const int64_t *offR, const int32_t *rowMap, int64_t R,
+                const int64_t *offK, int64_t K, int64_t Kq, bool rowsFast, void *P, int64_t plane,
+                hipStream_t s) {
     if (R == 0) return 0;
     const int64_t tasks = rowsFast ? (R + 16 * kPackBlocksR - 1) / (16 * kPackBlocksR) * ((Kq / 8 + 3) / 4)
                                    : (R + kPackRowsK - 1) / kPackRowsK * ((Kq + 511) / 512);
     const int64_t blocks = (tasks + 3) / 4;
     if (blocks > INT32_MAX) return GETT_ERR_INTERNAL;
     (void)hipGetLastError();   // clear a stale error left by other HIP users
-    if (rowsFast)
-        hipLaunchKernelGGL(bf3_pack_rows_kernel, dim3((unsigned)blocks), dim3(256), 0, s, X, offR,
-                           rowMap, R, offK, K, Kq, P, plane);
-    else
-        hipLaunchKernelGGL(bf3_pack_k_kernel, dim3((unsigned)blocks), dim3(256), 0, s, X, offR, R,
-                           offK, K, Kq, P, plane);
+    if (f64) {
+        const double *Xd = static_cast<const double *>(X);
+        if (rowsFast)
+            hipLaunchKernelGGL(pack_rows_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, s, Xd,
+                               offR, rowMap, R, offK, K, Kq, P, plane);
+        else
+            hipLaunchKernelGGL(pack_k_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, s, Xd,
+                               offR, R, offK, K, Kq, P, plane);
+    } else {
+        const float *Xf = static_cast<const float *>(X);
+        if (rowsFast)
+            hipLaunchKernelGGL(pack_rows_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, s,
+                               Xf, offR, rowMap, R, offK, K, Kq, P, plane);
+        else
+            hipLaunchKernelGGL(pack_k_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, s, Xf,
+                               offR, R, offK, K, Kq, P, plane);
+    }
     return launch_status();
 }
 
@@ -577,6 +763,24 @@ template <int BM, int BN> static int launch_gemm8(const Bf3Packed &g, hipStream_
     (void)hipGetLastError();   // clear a stale error left by other HIP users
     auto kern = bf3_packed_gemm8_kernel<BM, BN>;
     hipLaunchKernelGGL(kern, dim3((unsigned)total), dim3(512), Cfg::kLdsBytes, s, g);
+    return launch_status();
+}
+
+int launch_f64_packed_gemm(const F64Packed &g, hipStream_t s) {
+    constexpr int BM = 128, BN = 128;
+    constexpr int kLds = 2 * (BM + BN) * 16 * (int)sizeof(double);
+    static bool attr_set = false;   // set once per process (every device takes the same value)
+    if (!attr_set) {
+        if (hipFuncSetAttribute(reinterpret_cast<const void *>(f64_packed_gemm_kernel<BM, BN>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, kLds) != hipSuccess)
+            return GETT_ERR_HIP;
+        attr_set = true;
+    }
+    const int64_t total = (int64_t)g.tilesM * g.tilesN * g.splits;
+    if (total > INT32_MAX) return GETT_ERR_INTERNAL;
+    (void)hipGetLastError();   // clear a stale error left by other HIP users
+    auto kern = f64_packed_gemm_kernel<BM, BN>;
+    hipLaunchKernelGGL(kern, dim3((unsigned)total), dim3(256), kLds, s, g);
     return launch_status();
 }
 

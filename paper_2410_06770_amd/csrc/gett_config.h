@@ -66,19 +66,21 @@ constexpr int kTablePad = 256;      // M/N tables padded to a multiple of this
 // addr32: when both operands' addressed spans fit 4 GB, the tile loads
 // through a uniform 64-bit base plus 32-bit lane offsets (fewer VALU
 // instructions per value; real precisions, measured per tile).
-// packed (BF16x3 only): the entry is the packed form -- a pass splits each
-// operand element once into dense bfloat16 hi/lo rows, then a GEMM kernel
-// runs on those rows (its own kernels; the other flags do not apply).
+// packed (BF16x3, FP64): the entry is the packed form -- a pass writes each
+// operand element once into dense rows (BF16x3: split into bfloat16 hi/lo),
+// then a GEMM kernel runs on those rows (its own kernels; the other flags do
+// not apply).
 struct TileShape { int bm, bn, bk; bool load_fence; int depth; bool addr32; bool packed; };
 
 // Tile menus.  FP64/FP32 run 16x16x4 MFMA steps (BK multiple of 4), the BF16x3
 // path 16x16x32 BF16 MFMA steps (BK multiple of 32).  Each workgroup is a 2x2
 // grid of waves, so BM and BN are multiples of 32.  BF16x3 entries 1 and 4
-// are the packed form (GEMM tiles on packed rows, 32 positions a step).
+// and FP64 entry 4 are the packed forms (GEMM tiles on packed rows, 32
+// (BF16x3) or 16 (FP64) positions a step).
 constexpr TileShape kTiles[kNumPrec][kNumTiles] = {
     /* FP64   */ {{64, 64, 16, true, 1, true}, {64, 128, 16, true, 1, true},
                   {128, 64, 16, false, 1, false}, {128, 128, 16, true, 1, true},
-                  {128, 64, 8, true, 1, false}},
+                  {128, 128, 16, true, 1, false, true}},
     /* FP32   */ {{64, 64, 16, true, 2, true}, {64, 128, 16, true, 2, true},
                   {128, 64, 16, true, 2, true}, {128, 128, 16, true, 2, true},
                   {128, 128, 32, true, 2, true}},
@@ -96,8 +98,9 @@ constexpr TileShape kTiles[kNumPrec][kNumTiles] = {
                   {128, 128, 8, true, 1, false}},
 };
 
-// The direct BF16x3 tile of the packed entry's shape: it runs in the packed
-// form's place when the packed rows would not fit the workspace cap.
+// The direct 128 x 128 tile (entry 3 of the BF16x3 and FP64 menus): it runs
+// in a packed entry's place when the packed rows would not fit the
+// workspace cap, and in the allocation-free entry.
 constexpr int kPackedFallbackTile = 3;
 
 // Flag of the menu entry with this shape (first match).

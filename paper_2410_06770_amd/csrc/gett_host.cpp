@@ -117,7 +117,7 @@ static Sched heuristic(int prec, int64_t M, int64_t N, int64_t K, int64_t H = 1)
     // Relative per-CU throughput of each tile once the chip is full, from
     // timings of the menu on large strided and dense contractions.
     static const double kSpeed[kNumPrec][kNumTiles] = {
-        {0.88, 0.92, 1.0, 0.80, 0.96},  // FP64: the 128x64 tiles run 3-4 workgroups per CU
+        {0.88, 0.92, 1.0, 0.95, 0.85},  // FP64: the 128x64 tile runs 3-4 workgroups per CU; 4 packed
         {0.8, 0.9, 0.9, 1.0, 0.95},     // FP32
         {0.7, 1.0, 0.75, 0.8, 0.9},     // BF16x3 (1 and 4: the packed form)
         {0.8, 0.9, 0.9, 1.0, 1.0},      // FP8 (its own kernel)
@@ -467,15 +467,17 @@ static int run_packed(const Plan &pl, const TileParams &p, hipStream_t s, bool *
     *fallback = false;
     TableSet &t = *pl.tab;
     const Canon &c = t.cn;
+    const bool f64 = pl.prec == kF64;
     const int64_t M = c.M, N = c.N, K = c.K;
     const TileShape ts = kTiles[pl.prec][pl.sched.tile];
-    const int64_t Kq = round_up(std::max<int64_t>(K, 1), kPackedBK);
+    const int bk = f64 ? kPacked64BK : kPackedBK;
+    const int64_t Kq = round_up(std::max<int64_t>(K, 1), bk);
     const int64_t Mq = round_up(std::max<int64_t>(M, 1), ts.bm);
     const int64_t Nq = round_up(std::max<int64_t>(N, 1), ts.bn);
     const int64_t tilesM = Mq / ts.bm, tilesN = Nq / ts.bn;
     int64_t per = 0;
-    const int S = split_count(pl.sched.split, tilesM * tilesN, Kq, kPackedBK, &per);
-    const int64_t pk = 4 * (Mq + Nq) * Kq;
+    const int S = split_count(pl.sched.split, tilesM * tilesN, Kq, bk, &per);
+    const int64_t pk = (f64 ? 8 : 4) * (Mq + Nq) * Kq;   // BF16x3: hi and lo bfloat16
     const int64_t wsb = S > 1 ? (int64_t)S * M * N * (int64_t)sizeof(double) : 0;
     if (Kq > kPackedMaxKq || tilesM * tilesN * S > INT32_MAX || pk + wsb > g_max_ws.load()) {
         *fallback = true;
@@ -488,20 +490,37 @@ static int run_packed(const Plan &pl, const TileParams &p, hipStream_t s, bool *
         *fallback = true;
         return 0;
     }
-    uint16_t *PA = static_cast<uint16_t *>(buf);
-    uint16_t *PB = PA + 2 * Mq * Kq;
+    char *PA = static_cast<char *>(buf);
+    char *PB = PA + (f64 ? 8 : 4) * Mq * Kq;
     double *ws = wsb ? reinterpret_cast<double *>(static_cast<char *>(buf) + pk) : nullptr;
-    const float *XA = static_cast<const float *>(p.A), *XB = static_cast<const float *>(p.B);
-    rc = launch_bf3_pack(XA, c.aFastK ? p.offAM : t.d_pkRows, c.aFastK ? nullptr : t.d_pkMap, M,
-                         p.offAK, K, Kq, !c.aFastK, PA, Mq * Kq, s);
+    rc = launch_pack(f64, p.A, c.aFastK ? p.offAM : t.d_pkRows, c.aFastK ? nullptr : t.d_pkMap, M,
+                     p.offAK, K, Kq, !c.aFastK, PA, Mq * Kq, s);
     if (!rc)
-        rc = launch_bf3_pack(XB, c.bFastK ? p.offBN : t.d_pkRows + M,
-                             c.bFastK ? nullptr : t.d_pkMap + M, N, p.offBK, K, Kq, !c.bFastK,
-                             PB, Nq * Kq, s);
-    if (!rc) {
+        rc = launch_pack(f64, p.B, c.bFastK ? p.offBN : t.d_pkRows + M,
+                         c.bFastK ? nullptr : t.d_pkMap + M, N, p.offBK, K, Kq, !c.bFastK, PB,
+                         Nq * Kq, s);
+    if (!rc && f64) {
+        F64Packed g{};
+        g.A = reinterpret_cast<const double *>(PA);
+        g.B = reinterpret_cast<const double *>(PB);
+        g.Kq = Kq;
+        g.kPer = per;
+        g.tilesM = (int32_t)tilesM;
+        g.tilesN = (int32_t)tilesN;
+        g.splits = S;
+        g.C = static_cast<double *>(p.C);
+        g.offCM = p.offCM;
+        g.offCN = p.offCN;
+        g.M = M;
+        g.N = N;
+        g.ws = ws;
+        g.alpha = p.alpha[0];
+        g.beta = p.beta[0];
+        rc = launch_f64_packed_gemm(g, s);
+    } else if (!rc) {
         Bf3Packed g{};
-        g.A = PA;
-        g.B = PB;
+        g.A = reinterpret_cast<const uint16_t *>(PA);
+        g.B = reinterpret_cast<const uint16_t *>(PB);
         g.planeA = Mq * Kq;
         g.planeB = Nq * Kq;
         g.Kq = Kq;
@@ -523,7 +542,7 @@ static int run_packed(const Plan &pl, const TileParams &p, hipStream_t s, bool *
         TileParams q = p;
         q.ws = ws;
         q.splits = S;
-        rc = launch_splitk_reduce(kBF3, q, s);
+        rc = launch_splitk_reduce(pl.prec, q, s);
     }
     const int frc = work_free(buf, s);
     return rc ? rc : frc;
@@ -1242,6 +1261,8 @@ static int run_noalloc(const Args &a, const double *A, const double *B, double *
     const int64_t forced = g_forced.load();
     Sched s = forced >= 0 ? sched_of(forced) : heuristic(kF64, probe.M, probe.N, probe.K);
     if (!sched_valid(kF64, s, probe.K)) return GETT_ERR_STATE;
+    // the packed form needs a workspace for its rows: its fallback tile runs
+    if (kTiles[kF64][s.tile].packed) s.tile = kPackedFallbackTile;
     const TileShape ts = kTiles[kF64][s.tile];
     // The plan, built on the stack: canonical form, padded table lengths and
     // address ranges as in a cached plan, tables in the scratch array.

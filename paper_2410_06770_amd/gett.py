@@ -29,10 +29,12 @@ NUM_FEATURES = 64
 NUM_ORDERS = 4
 NUM_SPLITS = 4
 SPLIT_FACTORS = (1, 2, 4, 0)   # 0: enough K slices to fill the chip
-# The BF16x3 menu entries that are the packed form (hi/lo rows packed once,
-# then a GEMM on them: 192 x 256 and 128 x 128 tiles); they take no Hadamard
-# modes.
+# The menu entries that are packed forms (each operand element written once
+# into dense rows, then a GEMM on them); they take no Hadamard modes.
+# BF16x3: 192 x 256 and 128 x 128 tiles (hi/lo bfloat16 rows); FP64: 128 x 128.
 BF16X3_PACKED_TILES = (1, 4)
+FP64_PACKED_TILES = (4,)
+PACKED_TILES = {GETT_BF16X3: BF16X3_PACKED_TILES, GETT_FP64: FP64_PACKED_TILES}
 
 _lib = None
 i64 = ct.c_int64

@@ -239,7 +239,7 @@ def test_hadamard_every_schedule(prec):
         S = gett.SPLIT_FACTORS[split]
         if (S > 1 and K < S * bk) or (S == 0 and K < 4 * bk):
             continue
-        if prec == gett.GETT_BF16X3 and tile in gett.BF16X3_PACKED_TILES:
+        if tile in gett.PACKED_TILES.get(prec, ()):
             continue          # the packed form takes no Hadamard modes (tests/test_gpu_packed.py)
         assert gett.gett_set_schedule(sid) == 0
         try:
