@@ -40,7 +40,8 @@ import time
 import numpy as np
 
 METRIC = "xGETT TFLOP/s & % MFMA peak: plain FP64/FP32 vs split-BF16 at stated rel err"
-PEAK = {"f64": 78.6, "f32": 157.3, "bf16": 2516.6, "fp8": 5033.2}   # dense MFMA TFLOP/s
+PEAK = {"f64": 78.6, "f32": 157.3, "bf16": 2516.6, "fp8": 5033.2,
+        "int8": 5033.2}   # dense MFMA TFLOP/s (TOP/s for INT8)
 WORKLOADS = {
     "strided_perm": ("config_strided_perm",
                      "strided_perm: C[b,e,a,d] = sum_{c,f} A[a,b,c,f] B[f,d,c,e]; "
@@ -61,7 +62,9 @@ def parse():
                     help="skip the PyTorch einsum / addmm context timings")
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--paths", default="f64,f32,bf16x3,fp8")
+    ap.add_argument("--paths", default="f64,f32,bf16x3,fp8,ozaki")
+    ap.add_argument("--ozaki-slices", type=int, default=8,
+                    help="slices per element of the INT8-emulated FP64 path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-unary", action="store_true",
                     help="skip the unary (transpose, reduction) legs")
@@ -155,7 +158,7 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": {"f64": "f64", "f32": "f32", "bf16x3": "bf16x3(f32 acc, f64 sum)",
-                  "fp8": "e4m3(f32 acc)"}[path],
+                  "fp8": "e4m3(f32 acc)", "ozaki": "int8 slices(i32 acc, f64 sum)"}[path],
         "data": wdata,
         "config": {"workload": wdesc,
                    "M": M, "N": N, "K": K, "flops_per_step": flops, "path": path},
@@ -185,12 +188,14 @@ def run_workload(args, workload, paths, gett, W, torch, stream, with_context):
     PyTorch context timings, the FP64 problem, the first path's (name, ms,
     TFLOP/s, peak, wall seconds))."""
     entry = {"f64": gett.dgett, "f32": gett.sgett, "bf16x3": gett.sgett_bf16x3,
-             "fp8": gett.sgett_fp8}
+             "fp8": gett.sgett_fp8,
+             "ozaki": lambda *a: gett.dgett_ozaki(*a, slices=args.ozaki_slices)}
+    f64_data = ("f64", "ozaki")
     results, context, problems = {}, {}, {}
     builder = WORKLOADS[workload][0]
     make = getattr(W, builder)
     for path in paths:
-        dtype = np.float64 if path == "f64" else np.float32
+        dtype = np.float64 if path in f64_data else np.float32
         if dtype not in problems:
             problems[dtype] = make(dtype=dtype)
     pr64 = problems.get(np.float64) or make(dtype=np.float64)
@@ -200,7 +205,7 @@ def run_workload(args, workload, paths, gett, W, torch, stream, with_context):
           flush=True)
     primary = None
     for path in paths:
-        dtype = np.float64 if path == "f64" else np.float32
+        dtype = np.float64 if path in f64_data else np.float32
         pr = problems[dtype]
         tdt = torch.float64 if dtype == np.float64 else torch.float32
         At = torch.from_numpy(pr.A.buf).to("cuda")
@@ -256,6 +261,10 @@ def run_workload(args, workload, paths, gett, W, torch, stream, with_context):
         # effective rate against the BF16 peak.
         if path == "bf16x3":
             peak, pct = PEAK["bf16"], 100 * 3 * tflops / PEAK["bf16"]
+        elif path == "ozaki":
+            # S (S + 1) / 2 INT8 products per term against the INT8 peak
+            S = args.ozaki_slices
+            peak, pct = PEAK["int8"], 100 * S * (S + 1) / 2 * tflops / PEAK["int8"]
         else:
             peak = {"f64": PEAK["f64"], "f32": PEAK["f32"], "fp8": PEAK["fp8"]}[path]
             pct = 100 * tflops / peak
@@ -263,6 +272,10 @@ def run_workload(args, workload, paths, gett, W, torch, stream, with_context):
                "ms_median": round(float(np.median(durs)), 4), "ms_cold": round(ms_cold, 4),
                "pct_peak": round(pct, 2), "peak_tflops": peak,
                "schedule": int(sched), "wall_ms_per_step": round(1e3 * wall / args.steps, 4)}
+        if path == "ozaki":
+            res["slices"] = args.ozaki_slices
+            res["pct_peak_basis"] = "S(S+1)/2 INT8 products per term vs the INT8 matrix peak"
+            res["effective_pct_of_f64_peak"] = round(100 * tflops / PEAK["f64"], 2)
         if path == "bf16x3":
             res["pct_peak_basis"] = "3 BF16 products per term vs the BF16 matrix peak"
             res["effective_pct_of_f32_peak"] = round(100 * tflops / PEAK["f32"], 2)

@@ -150,6 +150,24 @@ int sgett_fp8(int64_t ranka, const int64_t *exta, const int64_t *inca, const flo
               int64_t conts, const int64_t *conta, const int64_t *contb, const int64_t *perm,
               const int64_t *incc, float *C);
 
+/* DGETT emulated on INT8 MFMA (the Ozaki scheme: Ozaki, Ogita, Oishi and
+   Rump 2012; its INT8 form, Ootomo, Ozaki and Yokota 2024).  Same first 14
+   arguments and INFO codes as dgett; SLICES (3 .. 8, else GETT_ERR_STATE)
+   sets the precision.  Each canonical row of A and of B (as in sgett_fp8)
+   is scaled by 2^-e, e the binary exponent of its largest magnitude (frexp:
+   max = f 2^e, f in [0.5, 1)), and cut into SLICES 7-bit integer slices by
+   truncation (x <- 128 x, q = trunc(x), x <- x - q); the slice pairs
+   (s, t) with s + t <= SLICES + 1 are multiplied on the INT8 matrix cores
+   with exact INT32 sums (K slices of at most 16384 positions), and per output
+   v = sum over d = SLICES+1 .. 2 of ldexp(P_d, eA + eB - 7 d) in FP64, then
+   C <- C_in + v (with several K slices, their v are added to C_in in slice
+   order).  Error against the exact sum: at most K 2^(eA+eB) 3 2^-7 SLICES plus
+   the FP64 combination.  Finite inputs only. */
+int dgett_ozaki(int64_t ranka, const int64_t *exta, const int64_t *inca, const double *A,
+                int64_t rankb, const int64_t *extb, const int64_t *incb, const double *B,
+                int64_t conts, const int64_t *conta, const int64_t *contb, const int64_t *perm,
+                const int64_t *incc, double *C, int64_t slices);
+
 /* SGETT on FP8 with MX-style blocks: the same as sgett_fp8 with blocks of
    32 contracted positions instead of 128, so each 32 values of a row share a
    power-of-two scale (an E8M0 exponent, the block size of the OCP

@@ -23,12 +23,13 @@ CHECK_OBJ = os.path.join(HERE, "_build_check")
 CHECK_LIB = os.path.join(HERE, "libgett_check.so")
 
 SOURCES = ["gett_tile_f64.hip", "gett_tile_f32.hip", "gett_tile_bf3.hip", "gett_bf3pack.hip",
+           "gett_ozaki.hip",
            "gett_tile_z64.hip",
            "gett_tile_c32.hip", "gett_fp8.hip",
            "gett_mlp.hip", "gett_noalloc.hip", "gett_scale.hip", "gett_unary.hip",
            "gett_unary.cpp", "gett_dispatch.cpp", "gett_plan.cpp", "gett_host.cpp"]
-# Per-file code generation: the FP64, FP32, complex and packed BF16x3 kernels
-# keep their MFMA accumulators in ordinary VGPRs (no per-step copies to the
+# Per-file code generation: the FP64, FP32, complex, packed, Ozaki and FP8
+# kernels keep their MFMA accumulators in ordinary VGPRs (no per-step copies to the
 # accumulation registers, lower register totals and higher occupancy); the
 # direct BF16x3 tiles do better with the default form.
 FILE_FLAGS = {
@@ -37,6 +38,8 @@ FILE_FLAGS = {
     "gett_tile_z64.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
     "gett_tile_c32.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
     "gett_bf3pack.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+    "gett_ozaki.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+    "gett_fp8.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
 }
 ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}"]

@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "gett_bf3pack.h"
+#include "gett_ozaki.h"
 #include "gett.h"
 #include "gett_internal.h"
 #include "gett_noalloc.h"
@@ -1241,6 +1242,91 @@ static int run(int prec, const Args &a, const void *A, const void *B, void *C,
 }
 
 // ---------------------------------------------------------------------------
+// DGETT emulated on INT8 matrix cores (Ozaki scheme, gett_ozaki.hip)
+// ---------------------------------------------------------------------------
+static int run_ozaki(const Args &a, const double *A, const double *B, double *C, int slices) {
+    int info = validate(a, A, B, C);
+    if (info) return info;
+    if (slices < kOzMinSlices || slices > kOzMaxSlices) return GETT_ERR_STATE;
+    Canon probe = canonicalise(a, 0, 128);
+    if (probe.empty || probe.M == 0 || probe.N == 0 || probe.K == 0) return 0;
+    int dev = 0;
+    int rc = check_device(&dev);
+    if (rc) return rc;
+    hipStream_t s = t_stream;
+    Fp8Plan *pl = nullptr;   // the canonical rows and their walk orders
+    rc = get_fp8_plan(a, dev, &pl);
+    if (rc) return rc;
+    t_last_schedule = -1;
+    const int64_t M = pl->M, N = pl->N, K = pl->K;
+    const int64_t *rowsA = pl->d_tab, *kA = rowsA + M, *rowsB = kA + K, *kB = rowsB + N;
+    const int64_t *offCM = kB + K, *offCN = offCM + M;
+    const int64_t Kq = round_up(K, 64), Mq = round_up(M, 64), Nq = round_up(N, 64);
+    int64_t S = (Kq + kOzMaxKSlice - 1) / kOzMaxKSlice;
+    int64_t per = round_up((Kq + S - 1) / S, 64);
+    S = (Kq + per - 1) / per;
+    const int64_t tilesM = Mq / 64, tilesN = Nq / 64;
+    if (tilesM * tilesN * S > INT32_MAX) return GETT_ERR_INTERNAL;
+    const int64_t planeA = Mq * Kq, planeB = Nq * Kq;
+    const int64_t qbytes = round_up((int64_t)slices * (planeA + planeB), 256);
+    const int64_t ebytes = round_up((Mq + Nq) * (int64_t)sizeof(int32_t), 256);
+    const int64_t wsb = S > 1 ? S * M * N * (int64_t)sizeof(double) : 0;
+    void *ws = nullptr;
+    if (work_alloc(&ws, (size_t)(qbytes + ebytes + wsb), s)) return GETT_ERR_ALLOC;
+    uint8_t *QA = static_cast<uint8_t *>(ws);
+    uint8_t *QB = QA + slices * planeA;
+    int32_t *EA = reinterpret_cast<int32_t *>(static_cast<char *>(ws) + qbytes);
+    int32_t *EB = EA + Mq;
+    double *part = wsb ? reinterpret_cast<double *>(static_cast<char *>(ws) + qbytes + ebytes)
+                       : nullptr;
+    OzOperand oa{pl->swapped ? B : A, pl->aRowsFast ? pl->d_rowsOp[0] : rowsA, pl->d_rowMap[0],
+                 M, kA, K, pl->aRowsFast};
+    OzOperand ob{pl->swapped ? A : B, pl->bRowsFast ? pl->d_rowsOp[1] : rowsB, pl->d_rowMap[1],
+                 N, kB, K, pl->bRowsFast};
+    rc = launch_oz_exponents(oa, Kq, EA, Mq, s);
+    if (!rc) rc = launch_oz_exponents(ob, Kq, EB, Nq, s);
+    if (!rc) rc = launch_oz_slices(slices, oa, Kq, QA, planeA, EA, s);
+    if (!rc) rc = launch_oz_slices(slices, ob, Kq, QB, planeB, EB, s);
+    if (!rc) {
+        OzParams g{};
+        g.A = QA;
+        g.B = QB;
+        g.planeA = planeA;
+        g.planeB = planeB;
+        g.EA = EA;
+        g.EB = EB;
+        g.Kq = Kq;
+        g.kPer = per;
+        g.tilesM = (int32_t)tilesM;
+        g.tilesN = (int32_t)tilesN;
+        g.splits = (int32_t)S;
+        g.C = C;
+        g.offCM = offCM;
+        g.offCN = offCN;
+        g.M = M;
+        g.N = N;
+        g.ws = part;
+        rc = launch_oz_gemm(slices, g, s);
+    }
+    if (!rc && S > 1) {
+        // C <- C_in + sum of the K slices' FP64 values, in slice order
+        TileParams q{};
+        q.C = C;
+        q.offCM = offCM;
+        q.offCN = offCN;
+        q.M = M;
+        q.N = N;
+        q.splits = (int32_t)S;
+        q.H = 1;
+        q.ws = part;
+        q.alpha[0] = q.beta[0] = 1.0;
+        rc = launch_splitk_reduce(kF64, q, s);
+    }
+    if (work_free(ws, s) && !rc) rc = GETT_ERR_HIP;
+    return rc;
+}
+
+// ---------------------------------------------------------------------------
 // Allocation-free DGETT: tables and split-K partials in the device scratch
 // array (gett_noalloc.hip); no plan cache, no allocation of any kind on the
 // device.
@@ -1740,6 +1826,13 @@ int sgett_fp8(int64_t ranka, const int64_t *exta, const int64_t *inca, const flo
               int64_t conts, const int64_t *conta, const int64_t *contb, const int64_t *perm,
               const int64_t *incc, float *C) {
     return run(kFP8, GETT_ARGS_MAKE, A, B, C);
+}
+
+int dgett_ozaki(int64_t ranka, const int64_t *exta, const int64_t *inca, const double *A,
+                int64_t rankb, const int64_t *extb, const int64_t *incb, const double *B,
+                int64_t conts, const int64_t *conta, const int64_t *contb, const int64_t *perm,
+                const int64_t *incc, double *C, int64_t slices) {
+    return run_ozaki(GETT_ARGS_MAKE, A, B, C, (int)std::min<int64_t>(std::max<int64_t>(slices, 0), 64));
 }
 
 static int fp8_quantize_entry(int64_t rankx, const int64_t *extx, const int64_t *incx,

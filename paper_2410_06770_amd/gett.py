@@ -71,6 +71,8 @@ def lib():
                  "cgett", "sgett_mxfp8"):
         getattr(L, name).argtypes = a14
         getattr(L, name).restype = ct.c_int
+    L.dgett_ozaki.argtypes = a14 + [i64]
+    L.dgett_ozaki.restype = ct.c_int
     ex17 = [i64, I64P, I64P, vp, i64, I64P, I64P, vp, i64, I64P, I64P, i64, I64P, I64P, I64P,
             I64P]
     L.dgett_ex.argtypes = [ct.c_double] + ex17 + [ct.c_double, vp]
@@ -175,6 +177,14 @@ def sgett_fp8(ranka, exta, inca, A, rankb, extb, incb, B, conts, conta, contb, p
               C) -> int:
     return _call14("sgett_fp8", ranka, exta, inca, A, rankb, extb, incb, B, conts, conta,
                    contb, perm, incc, C)
+
+
+def dgett_ozaki(ranka, exta, inca, A, rankb, extb, incb, B, conts, conta, contb, perm, incc,
+                C, slices=8) -> int:
+    return lib().dgett_ozaki(int(ranka), _arr(exta), _arr(inca), vp(A) if A else None,
+                             int(rankb), _arr(extb), _arr(incb), vp(B) if B else None,
+                             int(conts), _arr(conta), _arr(contb), _arr(perm), _arr(incc),
+                             vp(C) if C else None, int(slices))
 
 
 def dgett_noalloc(ranka, exta, inca, A, rankb, extb, incb, B, conts, conta, contb, perm, incc,

@@ -97,6 +97,17 @@ def test_info_codes_agree_with_oracle_on_random_mutations():
     assert mismatches == 0
 
 
+@pytest.mark.parametrize("code,kw", BAD)
+def test_ozaki_info_codes(code, kw):
+    """The INT8-emulated DGETT checks its 14 arguments like dgett."""
+    assert call(lambda *a: gett.dgett_ozaki(*a, slices=8), **kw) == code
+
+
+@pytest.mark.parametrize("slices", [-1, 0, 2, 9, 64])
+def test_ozaki_slice_count_outside_3_to_8_is_refused(slices):
+    assert call(lambda *a: gett.dgett_ozaki(*a, slices=slices)) == gett.GETT_ERR_STATE
+
+
 def test_zero_extent_is_a_noop_without_hip():
     # zero extents return before any HIP call
     assert call(gett.dgett, exta=[0, 4]) == 0

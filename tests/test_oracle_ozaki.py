@@ -108,16 +108,20 @@ def test_two_slice_values_drop_exactly_the_lo_lo_term():
 
 @pytest.mark.parametrize("S", [3, 5, 8])
 def test_error_within_the_scheme_bound(S):
-    """|model - A B^T| <= K 2^(EA + EB) 3 2^-7S (slicing truncation of both
-    operands plus the dropped pairs) + (S + 2) u |A| |B|^T (the double
-    combination); with three slices the bound is also nearly reached."""
+    """|model - A B^T| <= K 2^(EA + EB) (S + 1) 2^-7S + (S + 2) u |A| |B|^T.
+    Per product: slices truncate toward zero, so slice s of a row is below
+    2^(E - 7(s - 1)) and the part of an element from slice j on is below
+    2^(E - 7(j - 1)); the S - 1 dropped diagonals s + t >= S + 2 (s >= 2)
+    each add less than 2^(EA + EB - 7S), the two truncation residuals less
+    than that again each; the double combination adds the last term.  With
+    three slices the bound is also nearly reached."""
     rng = np.random.default_rng(10 + S)
     A = rng.standard_normal((8, 96)) * 2.0 ** rng.integers(-3, 3, (8, 1))
     B = rng.standard_normal((6, 96))
     got, EA, EB = model(A, B, S)
     ref = exact_product(A, B)
     K = A.shape[1]
-    bound = K * 2.0 ** (EA[:, None] + EB[None, :]) * 3 * 2.0 ** (-7 * S) \
+    bound = K * 2.0 ** (EA[:, None] + EB[None, :]) * (S + 1) * 2.0 ** (-7 * S) \
         + (S + 2) * U64 * (np.abs(A) @ np.abs(B).T)
     err = np.abs(got - ref)
     assert np.all(err <= bound)
