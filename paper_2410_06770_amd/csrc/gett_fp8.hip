@@ -66,7 +66,8 @@ __device__ __forceinline__ unsigned e4m3_word(float a, float b, float c, float d
 // before its first block is reduced, so a run's blocks are in flight
 // together (one block per wave left the loads latency-bound).  The waves of
 // a workgroup take consecutive runs of one row (giving them neighbouring
-// rows of one run instead measured slower).  Loads past the run's last block repeat
+// rows of one run instead measured slower, and so did renumbering the
+// workgroups so that each XCD takes a contiguous range of rows).  Loads past the run's last block repeat
 // that block, and positions past K read position K - 1 again (the
 // contracted table holds exactly K offsets); both are discarded, so every
 // load stays inside the table and the operand.
@@ -218,12 +219,21 @@ __device__ __forceinline__ void fp8_load_block(const uint8_t *__restrict__ base,
     }
 }
 
-template <int CH, int LDK>
+// LDS rows of 128 bytes, unpadded; the eight 16-byte chunks of row r sit at
+// positions c ^ fp8_swz(r).  fp8_swz takes distinct values on any 8
+// consecutive rows and on the even and the odd rows of any 16, so the
+// operand reads (one chunk of each of 8 or 16 neighbouring rows per pass)
+// and the stores (a row's 8 chunks by 8 neighbouring lanes) each touch every
+// bank once, whether a 16-byte access is served 8 lanes at a time over 32
+// banks or 16 lanes over 64.
+__device__ __forceinline__ int fp8_swz(int r) { return ((r >> 1) ^ ((r & 1) << 2)) & 7; }
+
+template <int CH>
 __device__ __forceinline__ void fp8_store_block(uint8_t *s, int t, const u4_t (&r)[CH]) {
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
         const int idx = t + c * 256, row = idx >> 3, part = idx & 7;
-        *reinterpret_cast<u4_t *>(s + row * LDK + part * 16) = r[c];
+        *reinterpret_cast<u4_t *>(s + row * 128 + 16 * (part ^ fp8_swz(row))) = r[c];
     }
 }
 
@@ -235,22 +245,22 @@ __device__ __forceinline__ void fp8_store_block(uint8_t *s, int t, const u4_t (&
 // core reads as k = 16 g .. and 64 + 16 g ..), and supplies the scale of
 // block g of its row.
 template <int BS>
-__device__ __forceinline__ i8_t fp8_operand(const uint8_t *row, int lane) {
-    const int g = lane >> 4;
-    if constexpr (BS == 128) {
-        return *reinterpret_cast<const i8_t *>(row + 32 * g);
-    } else {
-        const u4_t lo = *reinterpret_cast<const u4_t *>(row + 16 * g);
-        const u4_t hi = *reinterpret_cast<const u4_t *>(row + 64 + 16 * g);
-        return i8_t{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w,
-                    (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
-    }
+__device__ __forceinline__ i8_t fp8_operand(const uint8_t *s, int r, int lane) {
+    const int g = lane >> 4, f = fp8_swz(r);
+    // BS 128: chunks 2g and 2g + 1 (32 consecutive codes); BS 32: chunks g
+    // and 4 + g (positions 16 g .. and 64 + 16 g ..)
+    const int c0 = BS == 128 ? 2 * g : g, c1 = BS == 128 ? 2 * g + 1 : 4 + g;
+    const uint8_t *row = s + r * 128;
+    const u4_t lo = *reinterpret_cast<const u4_t *>(row + 16 * (c0 ^ f));
+    const u4_t hi = *reinterpret_cast<const u4_t *>(row + 16 * (c1 ^ f));
+    return i8_t{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w,
+                (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
 }
 
 // One 128-block on the matrix cores: each wave's FM x FN fragments.  sE holds
 // the biased exponents of the tile's A rows, then of its B rows (one per row,
 // or four per row with blocks of 32).
-template <int FM, int FN, int WTM, int WTN, int LDK, int BM, int BS>
+template <int FM, int FN, int WTM, int WTN, int BM, int BS>
 __device__ __forceinline__ void fp8_mma_block(const uint8_t *sA, const uint8_t *sB,
                                               const int32_t *sE, int wm, int wn, int lane,
                                               f4_t (&acc)[FM][FN]) {
@@ -261,13 +271,13 @@ __device__ __forceinline__ void fp8_mma_block(const uint8_t *sA, const uint8_t *
 #pragma unroll
     for (int i = 0; i < FM; ++i) {
         const int r = wm * WTM + i * 16 + (lane & 15);
-        a[i] = fp8_operand<BS>(sA + r * LDK, lane);
+        a[i] = fp8_operand<BS>(sA, r, lane);
         sa[i] = sE[r * SUB + sub];
     }
 #pragma unroll
     for (int j = 0; j < FN; ++j) {
         const int r = wn * WTN + j * 16 + (lane & 15);
-        b[j] = fp8_operand<BS>(sB + r * LDK, lane);
+        b[j] = fp8_operand<BS>(sB, r, lane);
         sb[j] = sE[(BM + r) * SUB + sub];
     }
 #pragma unroll
@@ -302,10 +312,9 @@ __global__ __launch_bounds__(256) void fp8_gemm_kernel(const uint8_t *__restrict
                                                        int64_t M, int64_t N, int64_t K,
                                                        int tilesM, int tilesN) {
     constexpr int WTM = BM / 2, WTN = BN / 2, FM = WTM / 16, FN = WTN / 16;
-    constexpr int LDK = 128 + 16;            // bytes per LDS row (16-byte pad)
     constexpr int CA = BM * 8 / 256, CB = BN * 8 / 256;   // 16-byte chunks per thread
-    __shared__ __align__(16) uint8_t sA[2][BM * LDK];
-    __shared__ __align__(16) uint8_t sB[2][BN * LDK];
+    __shared__ __align__(16) uint8_t sA[2][BM * 128];
+    __shared__ __align__(16) uint8_t sB[2][BN * 128];
     constexpr int SUB = 128 / BS;            // scales per row and 128-block
     __shared__ __align__(16) int32_t sE[2][(BM + BN) * SUB];
     static_assert(BM + BN <= 256 && 256 % (BM + BN) == 0, "one row of scales per thread");
@@ -332,19 +341,20 @@ __global__ __launch_bounds__(256) void fp8_gemm_kernel(const uint8_t *__restrict
     const int sidx = t % (BM + BN);
     const int32_t *ex = sidx < BM ? EA + (m0 + sidx) * nbs : EB + (n0 + sidx - BM) * nbs;
     typedef int i4s_t __attribute__((ext_vector_type(4)));
-    // this row's exponents of block blk, biased for E8M0 (bias 127)
+    // this row's exponents of block blk, as stored
     auto scales = [&](int64_t blk) {
-        if constexpr (SUB == 1) {
-            return i4s_t{ex[blk] + 127, 0, 0, 0};
-        } else {
-            const i4s_t v = *reinterpret_cast<const i4s_t *>(ex + blk * 4);
-            return v + 127;
-        }
+        if constexpr (SUB == 1) return i4s_t{ex[blk], 0, 0, 0};
+        else return *reinterpret_cast<const i4s_t *>(ex + blk * 4);
     };
+    // ... biased for E8M0 (bias 127) only when they go to LDS, a block after
+    // their load: biasing them at the load made the loop wait for the load
+    // it had just issued (the add cannot cross the MFMA block's scheduling
+    // barrier), exposing a full memory latency in every block.
     auto put_scales = [&](int32_t *se, i4s_t v) {
-        if constexpr (SUB == 1) se[sidx] = v.x;
-        else *reinterpret_cast<i4s_t *>(se + sidx * 4) = v;
+        if constexpr (SUB == 1) se[sidx] = v.x + 127;
+        else *reinterpret_cast<i4s_t *>(se + sidx * 4) = v + 127;
     };
+    const i4s_t kZeroScale = i4s_t{-127, -127, -127, -127};   // E8M0 0 after the bias
     // Two register sets: the codes of block b + 2 load while block b runs on
     // the matrix cores and block b + 1 waits in the other set; loads past the
     // last block reload it (a valid address).  Blocks run in pairs; when their
@@ -359,8 +369,8 @@ __global__ __launch_bounds__(256) void fp8_gemm_kernel(const uint8_t *__restrict
     fp8_load_block<CA>(pa, Kp, b1, t, ra2);
     fp8_load_block<CB>(pb, Kp, b1, t, rb2);
     i4s_t xs2 = scales(b1);
-    fp8_store_block<CA, LDK>(sA[0], t, ra);
-    fp8_store_block<CB, LDK>(sB[0], t, rb);
+    fp8_store_block<CA>(sA[0], t, ra);
+    fp8_store_block<CB>(sB[0], t, rb);
     put_scales(sE[0], xs);
     __syncthreads();
     for (int64_t blk = 0; blk < nb; blk += 2) {
@@ -369,21 +379,21 @@ __global__ __launch_bounds__(256) void fp8_gemm_kernel(const uint8_t *__restrict
         fp8_load_block<CA>(pa, Kp, n2, t, ra);
         fp8_load_block<CB>(pb, Kp, n2, t, rb);
         xs = scales(n2);
-        fp8_mma_block<FM, FN, WTM, WTN, LDK, BM, BS>(sA[0], sB[0], sE[0], wm, wn, lane, acc);
+        fp8_mma_block<FM, FN, WTM, WTN, BM, BS>(sA[0], sB[0], sE[0], wm, wn, lane, acc);
         __builtin_amdgcn_sched_barrier(0);
-        fp8_store_block<CA, LDK>(sA[1], t, ra2);
-        fp8_store_block<CB, LDK>(sB[1], t, rb2);
-        put_scales(sE[1], blk + 1 < nb ? xs2 : i4s_t{0, 0, 0, 0});
+        fp8_store_block<CA>(sA[1], t, ra2);
+        fp8_store_block<CB>(sB[1], t, rb2);
+        put_scales(sE[1], blk + 1 < nb ? xs2 : kZeroScale);
         __syncthreads();
         // odd block: LDS stage 1, the next block waits in set 1
         const int64_t n3 = blk + 3 < nb ? blk + 3 : nb - 1;
         fp8_load_block<CA>(pa, Kp, n3, t, ra2);
         fp8_load_block<CB>(pb, Kp, n3, t, rb2);
         xs2 = scales(n3);
-        fp8_mma_block<FM, FN, WTM, WTN, LDK, BM, BS>(sA[1], sB[1], sE[1], wm, wn, lane, acc);
+        fp8_mma_block<FM, FN, WTM, WTN, BM, BS>(sA[1], sB[1], sE[1], wm, wn, lane, acc);
         __builtin_amdgcn_sched_barrier(0);
-        fp8_store_block<CA, LDK>(sA[0], t, ra);
-        fp8_store_block<CB, LDK>(sB[0], t, rb);
+        fp8_store_block<CA>(sA[0], t, ra);
+        fp8_store_block<CB>(sB[0], t, rb);
         put_scales(sE[0], xs);
         __syncthreads();
     }
