@@ -161,8 +161,8 @@ int sgett_fp8(int64_t ranka, const int64_t *exta, const int64_t *inca, const flo
    with exact INT32 sums (K slices of at most 16384 positions), and per output
    v = sum over d = SLICES+1 .. 2 of ldexp(P_d, eA + eB - 7 d) in FP64, then
    C <- C_in + v (with several K slices, their v are added to C_in in slice
-   order).  Error against the exact sum: at most K 2^(eA+eB) 3 2^-7 SLICES plus
-   the FP64 combination.  Finite inputs only. */
+   order).  Error against the exact sum: at most K 2^(eA+eB) (SLICES + 1)
+   2^-7 SLICES plus the FP64 combination.  Finite inputs only. */
 int dgett_ozaki(int64_t ranka, const int64_t *exta, const int64_t *inca, const double *A,
                 int64_t rankb, const int64_t *extb, const int64_t *incb, const double *B,
                 int64_t conts, const int64_t *conta, const int64_t *contb, const int64_t *perm,

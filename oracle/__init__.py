@@ -91,6 +91,14 @@ def lib():
         L.gett_ref_fp8_gemm.argtypes = [i64, i64, i64, vp, vp, vp, vp, vp]
         L.gett_ref_fp8_quantize_bs.argtypes = [vp, i64, vp, i64, vp, i64, vp, vp]
         L.gett_ref_fp8_gemm_bs.argtypes = [i64, i64, i64, i64, vp, vp, vp, vp, vp]
+        L.gett_ref_mx_decode.argtypes = [i64, i64]
+        L.gett_ref_mx_decode.restype = ct.c_double
+        L.gett_ref_mx_encode.argtypes = [i64, ct.c_double]
+        L.gett_ref_mx_encode.restype = i64
+        L.gett_ref_mx_scale_exp.argtypes = [i64, ct.c_double]
+        L.gett_ref_mx_scale_exp.restype = i64
+        L.gett_ref_mx_quantize.argtypes = [vp, i64, vp, i64, vp, i64, vp, vp]
+        L.gett_ref_mx_gemm.argtypes = [i64, i64, i64, i64, vp, vp, vp, vp, vp]
         L.gett_ref_ozaki_split.argtypes = [vp, i64, vp, i64, vp, i64, vp, vp]
         L.gett_ref_ozaki_gemm.argtypes = [i64, i64, i64, i64, vp, vp, vp, vp, vp]
         _lib = L
@@ -318,6 +326,49 @@ def fp8_gemm(QA, EA, QB, EB, K, block=128):
         lib().gett_ref_fp8_gemm(M, N, K, *args)
     else:
         lib().gett_ref_fp8_gemm_bs(M, N, K, block, *args)
+    return out.T
+
+
+MX_FORMATS = (4, 6)   # element widths: 4 = FP4 E2M1, 6 = FP6 E2M3
+
+
+def mx_decode(fmt: int, code: int) -> float:
+    return lib().gett_ref_mx_decode(fmt, code)
+
+
+def mx_encode(fmt: int, v: float) -> int:
+    return int(lib().gett_ref_mx_encode(fmt, v))
+
+
+def mx_scale_exp(fmt: int, amax: float) -> int:
+    return int(lib().gett_ref_mx_scale_exp(fmt, amax))
+
+
+def mx_quantize(X, rows_off, k_off, fmt):
+    """Quantise a float32 view's rows to MX FP4 (fmt 4) or FP6 (fmt 6) codes,
+    one per byte, with one power-of-two scale per row per 32 contracted
+    positions.  Returns (codes uint8 [rows, Kp], exponents int32
+    [rows, Kp / 32]), Kp = 128 ceil(K / 128)."""
+    assert fmt in MX_FORMATS
+    rows, K = len(rows_off), len(k_off)
+    Kp = (K + 127) // 128 * 128
+    Q = np.zeros((rows, Kp), dtype=np.uint8)
+    E = np.zeros((rows, Kp // 32), dtype=np.int32)
+    ro = np.ascontiguousarray(rows_off, dtype=np.int64)
+    ko = np.ascontiguousarray(k_off, dtype=np.int64)
+    lib().gett_ref_mx_quantize(_ptr(X.buf, X.base), rows, ro.ctypes.data, K, ko.ctypes.data, fmt,
+                               Q.ctypes.data, E.ctypes.data)
+    return Q, E
+
+
+def mx_gemm(QA, EA, QB, EB, K, fmt):
+    """Exact double value of the MX-quantised product, out[m, n]."""
+    M, N = QA.shape[0], QB.shape[0]
+    out = np.zeros((N, M), dtype=np.float64)
+    lib().gett_ref_mx_gemm(M, N, K, fmt, np.ascontiguousarray(QA).ctypes.data,
+                           np.ascontiguousarray(EA).ctypes.data,
+                           np.ascontiguousarray(QB).ctypes.data,
+                           np.ascontiguousarray(EB).ctypes.data, out.ctypes.data)
     return out.T
 
 

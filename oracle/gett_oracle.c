@@ -822,6 +822,104 @@ void gett_ref_fp8_gemm(int64_t M, int64_t N, int64_t K, const uint8_t *QA, const
 }
 
 /* ------------------------------------------------------------------------
+ * MX element formats FP4 (E2M1) and FP6 (E2M3) of the OCP Microscaling
+ * Formats specification v1.0, for the MX-style precision variants (blocks
+ * of 32 contracted positions sharing one power-of-two scale).  FMT is the
+ * element width: 4 = E2M1, 6 = E2M3.  A code is a sign bit, 2 exponent bits
+ * (bias 1) and M mantissa bits (M = 1 or 3), no infinities or NaNs:
+ * exponent field 0 gives m 2^-M (subnormal), field e > 0 gives
+ * (1 + m 2^-M) 2^(e - 1).  Largest magnitudes: 6 (E2M1), 7.5 (E2M3).
+ * ------------------------------------------------------------------------ */
+static int ref_mx_mbits(int64_t fmt) { return fmt == 4 ? 1 : 3; }
+
+double gett_ref_mx_decode(int64_t fmt, int64_t code) {
+    int M = ref_mx_mbits(fmt);
+    int s = (int)((code >> (2 + M)) & 1), e = (int)((code >> M) & 3);
+    int m = (int)(code & ((1 << M) - 1));
+    double v = e == 0 ? ldexp((double)m, -M) : ldexp((double)((1 << M) + m), e - 1 - M);
+    return s ? -v : v;
+}
+
+/* Encode a finite double whose magnitude does not exceed the format's
+   largest: the representable magnitude nearest to |v|, found by comparing
+   with every code; on a tie the code with an even mantissa (last bit 0).
+   The sign bit is the sign of v (signbit, so -0.0 keeps it). */
+int64_t gett_ref_mx_encode(int64_t fmt, double v) {
+    int M = ref_mx_mbits(fmt);
+    int ncodes = 1 << (2 + M);              /* codes of one sign */
+    double a = fabs(v), best_d = INFINITY;
+    int best = 0;
+    for (int c = 0; c < ncodes; ++c) {
+        double d = fabs(gett_ref_mx_decode(fmt, c) - a);
+        if (d < best_d || (d == best_d && (c & 1) == 0)) {
+            best_d = d;
+            best = c;
+        }
+    }
+    return (signbit(v) ? ncodes : 0) | best;
+}
+
+/* Scale exponent of one block: the smallest e >= -127 with amax / 2^e not
+   above the format's largest magnitude (e = 0 for an all-zero block), by
+   plain search. */
+int64_t gett_ref_mx_scale_exp(int64_t fmt, double amax) {
+    if (!(amax > 0)) return 0;
+    double vmax = fmt == 4 ? 6.0 : 7.5;
+    int e = -127;
+    while (ldexp(amax, -e) > vmax) ++e;
+    return e;
+}
+
+/* Quantise rows (as gett_ref_fp8_quantize_bs, blocks of 32): one code per
+   byte in Q (rows x Kp, Kp = 128 ceil(K / 128), zero codes in the padding),
+   exponents in E (rows x Kp / 32). */
+void gett_ref_mx_quantize(const float *X, int64_t rows, const int64_t *offR, int64_t K,
+                          const int64_t *offK, int64_t fmt, uint8_t *Q, int32_t *E) {
+    int64_t Kp = (K + 127) / 128 * 128;
+    int64_t nb = Kp / 32;
+#pragma omp parallel for
+    for (int64_t r = 0; r < rows; ++r) {
+        for (int64_t b = 0; b < nb; ++b) {
+            double amax = 0.0;
+            for (int64_t k = b * 32; k < K && k < b * 32 + 32; ++k) {
+                double v = fabs((double)X[offR[r] + offK[k]]);
+                if (v > amax) amax = v;
+            }
+            int e = (int)gett_ref_mx_scale_exp(fmt, amax);
+            E[r * nb + b] = e;
+            for (int64_t k = b * 32; k < b * 32 + 32; ++k) {
+                uint8_t q = 0;
+                if (k < K) q = (uint8_t)gett_ref_mx_encode(fmt, ldexp((double)X[offR[r] + offK[k]], -e));
+                Q[r * Kp + k] = q;
+            }
+        }
+    }
+}
+
+/* Exact value of the quantised product: out[m + M*n] = sum over blocks of
+   2^(EA+EB) * sum_k decode(QA) * decode(QB) over the block's 32 positions,
+   in double (a block's sum is exact). */
+void gett_ref_mx_gemm(int64_t M, int64_t N, int64_t K, int64_t fmt, const uint8_t *QA,
+                      const int32_t *EA, const uint8_t *QB, const int32_t *EB, double *out) {
+    int64_t Kp = (K + 127) / 128 * 128;
+    int64_t nb = Kp / 32;
+#pragma omp parallel for
+    for (int64_t n = 0; n < N; ++n) {
+        for (int64_t m = 0; m < M; ++m) {
+            double acc = 0.0;
+            for (int64_t b = 0; b < nb; ++b) {
+                double part = 0.0;
+                for (int64_t k = b * 32; k < b * 32 + 32; ++k)
+                    part += gett_ref_mx_decode(fmt, QA[m * Kp + k]) *
+                            gett_ref_mx_decode(fmt, QB[n * Kp + k]);
+                acc += ldexp(part, EA[m * nb + b] + EB[n * nb + b]);
+            }
+            out[m + M * n] = acc;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------
  * Ozaki-scheme splitting and product (Ozaki, Ogita, Oishi and Rump, 2012;
  * the INT8 form of Ootomo, Ozaki and Yokota, 2024), the emulated DGETT's
  * model.  Not in the paper; its precision variants are.
