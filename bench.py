@@ -40,8 +40,8 @@ import time
 import numpy as np
 
 METRIC = "xGETT TFLOP/s & % MFMA peak: plain FP64/FP32 vs split-BF16 at stated rel err"
-PEAK = {"f64": 78.6, "f32": 157.3, "bf16": 2516.6, "fp8": 5033.2,
-        "int8": 5033.2}   # dense MFMA TFLOP/s (TOP/s for INT8)
+PEAK = {"f64": 78.6, "f32": 157.3, "bf16": 2516.6, "fp8": 5033.2, "fp6": 10066.3,
+        "fp4": 10066.3, "int8": 5033.2}   # dense MFMA TFLOP/s (TOP/s for INT8)
 WORKLOADS = {
     "strided_perm": ("config_strided_perm",
                      "strided_perm: C[b,e,a,d] = sum_{c,f} A[a,b,c,f] B[f,d,c,e]; "
@@ -62,7 +62,7 @@ def parse():
                     help="skip the PyTorch einsum / addmm context timings")
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--paths", default="f64,f32,bf16x3,fp8,ozaki")
+    ap.add_argument("--paths", default="f64,f32,bf16x3,fp8,mxfp8,mxfp6,mxfp4,ozaki")
     ap.add_argument("--ozaki-slices", type=int, default=8,
                     help="slices per element of the INT8-emulated FP64 path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -158,7 +158,8 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": {"f64": "f64", "f32": "f32", "bf16x3": "bf16x3(f32 acc, f64 sum)",
-                  "fp8": "e4m3(f32 acc)", "ozaki": "int8 slices(i32 acc, f64 sum)"}[path],
+                  "fp8": "e4m3(f32 acc)", "mxfp8": "mx e4m3(f32 acc)", "mxfp6": "mx e2m3(f32 acc)",
+                  "mxfp4": "mx e2m1(f32 acc)", "ozaki": "int8 slices(i32 acc, f64 sum)"}[path],
         "data": wdata,
         "config": {"workload": wdesc,
                    "M": M, "N": N, "K": K, "flops_per_step": flops, "path": path},
@@ -188,7 +189,8 @@ def run_workload(args, workload, paths, gett, W, torch, stream, with_context):
     PyTorch context timings, the FP64 problem, the first path's (name, ms,
     TFLOP/s, peak, wall seconds))."""
     entry = {"f64": gett.dgett, "f32": gett.sgett, "bf16x3": gett.sgett_bf16x3,
-             "fp8": gett.sgett_fp8,
+             "fp8": gett.sgett_fp8, "mxfp8": gett.sgett_mxfp8, "mxfp6": gett.sgett_mxfp6,
+             "mxfp4": gett.sgett_mxfp4,
              "ozaki": lambda *a: gett.dgett_ozaki(*a, slices=args.ozaki_slices)}
     f64_data = ("f64", "ozaki")
     results, context, problems = {}, {}, {}
@@ -266,7 +268,8 @@ def run_workload(args, workload, paths, gett, W, torch, stream, with_context):
             S = args.ozaki_slices
             peak, pct = PEAK["int8"], 100 * S * (S + 1) / 2 * tflops / PEAK["int8"]
         else:
-            peak = {"f64": PEAK["f64"], "f32": PEAK["f32"], "fp8": PEAK["fp8"]}[path]
+            peak = {"f64": PEAK["f64"], "f32": PEAK["f32"], "fp8": PEAK["fp8"],
+                    "mxfp8": PEAK["fp8"], "mxfp6": PEAK["fp6"], "mxfp4": PEAK["fp4"]}[path]
             pct = 100 * tflops / peak
         res = {"tflops": round(tflops, 3), "ms": round(ms, 4), "ms_min": round(min(durs), 4),
                "ms_median": round(float(np.median(durs)), 4), "ms_cold": round(ms_cold, 4),

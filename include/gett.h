@@ -180,6 +180,27 @@ int sgett_mxfp8(int64_t ranka, const int64_t *exta, const int64_t *inca, const f
                 int64_t conts, const int64_t *conta, const int64_t *contb, const int64_t *perm,
                 const int64_t *incc, float *C);
 
+/* SGETT on the MX FP6 and FP4 element formats (OCP Microscaling Formats
+   v1.0: E2M3 and E2M1, exponent bias 1, no infinities or NaNs; largest
+   magnitudes 7.5 and 6), the same path as sgett_mxfp8 with those codes:
+   each 32 contracted positions of a canonical row share a power-of-two
+   scale 2^e, e the smallest integer >= -127 with amax / 2^e not above the
+   largest magnitude (e = 0 for an all-zero block), and each value divided
+   by 2^e is rounded to the nearest code, ties to an even mantissa, keeping
+   its sign bit.  The gfx950 scaled MFMA multiplies the codes with the block
+   scales as E8M0 operands and accumulates in FP32; C_in is added in FP32.
+   A precision variant (the paper's future work on lower precisions): FP4
+   keeps 1 mantissa bit, FP6 3.  Same arguments and INFO codes as
+   sgett_fp8. */
+int sgett_mxfp6(int64_t ranka, const int64_t *exta, const int64_t *inca, const float *A,
+                int64_t rankb, const int64_t *extb, const int64_t *incb, const float *B,
+                int64_t conts, const int64_t *conta, const int64_t *contb, const int64_t *perm,
+                const int64_t *incc, float *C);
+int sgett_mxfp4(int64_t ranka, const int64_t *exta, const int64_t *inca, const float *A,
+                int64_t rankb, const int64_t *extb, const int64_t *incb, const float *B,
+                int64_t conts, const int64_t *conta, const int64_t *contb, const int64_t *perm,
+                const int64_t *incc, float *C);
+
 /* The quantisation step of sgett_fp8 on its own, for one operand: X is a
    device tensor of rank RANKX with extents/increments EXTX/INCX, CONTS of
    whose modes (CONTX) are contracted.  Writes codes to QX (device,
@@ -193,6 +214,13 @@ int sgett_fp8_quantize(int64_t rankx, const int64_t *extx, const int64_t *incx, 
 /* The same with blocks of 32 (sgett_mxfp8): EX holds rows x 4*ceil(K/128)
    exponents, the codes are laid out as for sgett_fp8_quantize. */
 int sgett_mxfp8_quantize(int64_t rankx, const int64_t *extx, const int64_t *incx, const float *X,
+                         int64_t conts, const int64_t *contx, uint8_t *QX, int32_t *EX);
+/* The same for sgett_mxfp6 / sgett_mxfp4: one code per byte (E2M3 in the
+   low 6 bits, E2M1 in the low 4; sign bit highest), rows x 4*ceil(K/128)
+   exponents. */
+int sgett_mxfp6_quantize(int64_t rankx, const int64_t *extx, const int64_t *incx, const float *X,
+                         int64_t conts, const int64_t *contx, uint8_t *QX, int32_t *EX);
+int sgett_mxfp4_quantize(int64_t rankx, const int64_t *extx, const int64_t *incx, const float *X,
                          int64_t conts, const int64_t *contx, uint8_t *QX, int32_t *EX);
 
 /* Batched xGETT: COUNT independent problems run as one persistent kernel

@@ -28,8 +28,18 @@ typedef float f4_t __attribute__((ext_vector_type(4)));
 typedef int i8_t __attribute__((ext_vector_type(8)));
 typedef unsigned u4_t __attribute__((ext_vector_type(4)));
 
-// Scale exponent from the block maximum (see file comment).
+// Element formats (kElem*, numbered as the scaled MFMA's format operands):
+// OCP E4M3 (FP8), E2M3 (FP6) and E2M1 (FP4).
+
+// Scale exponent from the block maximum: the smallest e >= -127 with
+// amax / 2^e not above the format's largest magnitude vmax = F 2^X
+// (F in [0.5, 1): 448 = 0.875 2^9, 7.5 = 0.9375 2^3, 6 = 0.75 2^3).  With
+// amax = f 2^x, f in [0.5, 1), the condition f 2^x <= F 2^(X + e) holds from
+// e = x - X when f <= F, else from x - X + 1 (exact integer logic).
+template <int FMT>
 __device__ __forceinline__ int fp8_scale_exp(float amax) {
+    constexpr int X = FMT == kElemE4M3 ? 9 : 3;
+    constexpr float F = FMT == kElemE4M3 ? 0.875f : FMT == kElemE2M3 ? 0.9375f : 0.75f;
     if (!(amax > 0.f)) return 0;
     const unsigned u = __float_as_uint(amax);
     int x;              // amax = f * 2^x with f in [0.5, 1)
@@ -41,7 +51,7 @@ __device__ __forceinline__ int fp8_scale_exp(float amax) {
         x = be - 126;
         f = __uint_as_float((u & 0x807FFFFFu) | (126u << 23));
     }
-    int e = f <= 0.875f ? x - 9 : x - 8;
+    int e = f <= F ? x - X : x - X + 1;
     return e < -127 ? -127 : e;
 }
 
@@ -57,6 +67,36 @@ __device__ __forceinline__ unsigned e4m3_word(float a, float b, float c, float d
     int w = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
     w = __builtin_amdgcn_cvt_pk_fp8_f32(c, d, w, true);
     return (unsigned)w;
+}
+
+// E2M1 / E2M3 code of v (|v| <= 6 / 7.5 by construction), round to nearest
+// even: sign, 2 exponent bits (bias 1), M mantissa bits.  With k = 0 below 1
+// and k = floor(log2 |v|) from 1 up, the spacing is 2^(k - M) and
+// n = rint(|v| 2^(M - k)) counts it; the code is k 2^M + n, which also
+// covers the subnormals (k = 0), a carry into the next binade (n = 2^(M+1))
+// and the largest value.  The sign bit is v's (signbit).
+template <int FMT>
+__device__ __forceinline__ unsigned mx_small_code(float v) {
+    constexpr int M = FMT == kElemE2M1 ? 1 : 3;
+    const float a = fabsf(v);
+    int x;
+    (void)frexpf(a, &x);                              // a = f 2^x, f in [0.5, 1)
+    const int k = a < 1.f ? 0 : x - 1;
+    const unsigned n = (unsigned)rintf(ldexpf(a, M - k));
+    return ((unsigned)k << M) + n + (signbit(v) ? (1u << (M + 2)) : 0u);
+}
+
+template <int FMT>
+__device__ __forceinline__ unsigned elem_code(float v) {
+    if constexpr (FMT == kElemE4M3) return e4m3_code(v);
+    else return mx_small_code<FMT>(v);
+}
+
+template <int FMT>
+__device__ __forceinline__ unsigned elem_word(float a, float b, float c, float d) {
+    if constexpr (FMT == kElemE4M3) return e4m3_word(a, b, c, d);
+    else return mx_small_code<FMT>(a) | (mx_small_code<FMT>(b) << 8) |
+                (mx_small_code<FMT>(c) << 16) | (mx_small_code<FMT>(d) << 24);
 }
 
 // Lanes along K: one wave per (row, run of up to kQuantRun consecutive
@@ -75,7 +115,8 @@ constexpr int kQuantRun = 8;
 
 // BS: positions per scale, 128, or 32 (the MX-style blocks: lane l's two
 // positions l and l + 64 fall in blocks l / 32 and 2 + l / 32 of the 128).
-template <int BS>
+// FMT: element format (E4M3 with either block size; E2M3 and E2M1 with 32).
+template <int BS, int FMT>
 __global__ __launch_bounds__(256) void fp8_quant_kernel(const float *__restrict__ X,
                                                         const int64_t *__restrict__ offR,
                                                         int64_t rows, int64_t rowsPad,
@@ -120,10 +161,10 @@ __global__ __launch_bounds__(256) void fp8_quant_kernel(const float *__restrict_
             float amax = fmaxf(fabsf(v0[j]), fabsf(v1[j]));
 #pragma unroll
             for (int s = 32; s > 0; s >>= 1) amax = fmaxf(amax, __shfl_xor(amax, s, 64));
-            const int e = fp8_scale_exp(amax);
+            const int e = fp8_scale_exp<FMT>(amax);
             const float inv = ldexpf(1.f, -e);  // exact power of two (e >= -127: 2^127 fits)
-            q[k0] = (uint8_t)(k0 < K ? e4m3_code(v0[j] * inv) : 0u);
-            q[k1] = (uint8_t)(k1 < K ? e4m3_code(v1[j] * inv) : 0u);
+            q[k0] = (uint8_t)(k0 < K ? elem_code<FMT>(v0[j] * inv) : 0u);
+            q[k1] = (uint8_t)(k1 < K ? elem_code<FMT>(v1[j] * inv) : 0u);
             if (lane == 0) E[r * nbs + b0 + j] = e;
         } else {
             // blocks of 32: lanes 0-31 and 32-63 each hold one block of the
@@ -134,9 +175,9 @@ __global__ __launch_bounds__(256) void fp8_quant_kernel(const float *__restrict_
                 a0 = fmaxf(a0, __shfl_xor(a0, s, 64));
                 a1 = fmaxf(a1, __shfl_xor(a1, s, 64));
             }
-            const int e0 = fp8_scale_exp(a0), e1 = fp8_scale_exp(a1);
-            q[k0] = (uint8_t)(k0 < K ? e4m3_code(v0[j] * ldexpf(1.f, -e0)) : 0u);
-            q[k1] = (uint8_t)(k1 < K ? e4m3_code(v1[j] * ldexpf(1.f, -e1)) : 0u);
+            const int e0 = fp8_scale_exp<FMT>(a0), e1 = fp8_scale_exp<FMT>(a1);
+            q[k0] = (uint8_t)(k0 < K ? elem_code<FMT>(v0[j] * ldexpf(1.f, -e0)) : 0u);
+            q[k1] = (uint8_t)(k1 < K ? elem_code<FMT>(v1[j] * ldexpf(1.f, -e1)) : 0u);
             if ((lane & 31) == 0) {
                 const int64_t eb = r * nbs + (b0 + j) * 4 + (lane >> 5);
                 E[eb] = e0;
@@ -150,7 +191,7 @@ __global__ __launch_bounds__(256) void fp8_quant_kernel(const float *__restrict_
 // row, each keeping a quarter of the block (32 values) in registers, so X is
 // read once and every load of the wave reads 16 neighbouring rows at four
 // contracted positions.  With blocks of 32 each lane's quarter is one block.
-template <int BS>
+template <int BS, int FMT>
 __global__ __launch_bounds__(256) void fp8_quant_rows_kernel(const float *__restrict__ X,
                                                              const int64_t *__restrict__ offR,
                                                              const int32_t *__restrict__ rowMap,
@@ -186,7 +227,7 @@ __global__ __launch_bounds__(256) void fp8_quant_rows_kernel(const float *__rest
         amax = fmaxf(amax, __shfl_xor(amax, RPW, 64));
         amax = fmaxf(amax, __shfl_xor(amax, 2 * RPW, 64));
     }
-    const int e = fp8_scale_exp(amax);
+    const int e = fp8_scale_exp<FMT>(amax);
     const float inv = ldexpf(1.f, -e);
     if (p >= rowsPad) return;
     uint4 *q = reinterpret_cast<uint4 *>(Q + r * Kp + k0);
@@ -194,10 +235,10 @@ __global__ __launch_bounds__(256) void fp8_quant_rows_kernel(const float *__rest
     for (int c = 0; c < PART / 16; ++c) {
         const float *w = v + 16 * c;
         uint4 out;
-        out.x = e4m3_word(w[0] * inv, w[1] * inv, w[2] * inv, w[3] * inv);
-        out.y = e4m3_word(w[4] * inv, w[5] * inv, w[6] * inv, w[7] * inv);
-        out.z = e4m3_word(w[8] * inv, w[9] * inv, w[10] * inv, w[11] * inv);
-        out.w = e4m3_word(w[12] * inv, w[13] * inv, w[14] * inv, w[15] * inv);
+        out.x = elem_word<FMT>(w[0] * inv, w[1] * inv, w[2] * inv, w[3] * inv);
+        out.y = elem_word<FMT>(w[4] * inv, w[5] * inv, w[6] * inv, w[7] * inv);
+        out.z = elem_word<FMT>(w[8] * inv, w[9] * inv, w[10] * inv, w[11] * inv);
+        out.w = elem_word<FMT>(w[12] * inv, w[13] * inv, w[14] * inv, w[15] * inv);
         q[c] = out;
     }
     if constexpr (BS == 128) {
@@ -237,30 +278,65 @@ __device__ __forceinline__ void fp8_store_block(uint8_t *s, int t, const u4_t (&
     }
 }
 
-// Operand registers of one lane: with one scale per 128 any split of the
-// block between lanes works as long as A and B share it, and each lane takes
-// 32 consecutive codes; with one scale per 32 the matrix core's block b (of
-// 32) must be the stored block b, so lane group g takes the stored
-// positions 16 g .. 16 g + 15 and 64 + 16 g .. 64 + 16 g + 15 (the halves the
-// core reads as k = 16 g .. and 64 + 16 g ..), and supplies the scale of
-// block g of its row.
-template <int BS>
+// Operand registers of one lane.  E4M3: with one scale per 128 any split of
+// the block between lanes works as long as A and B share it, and each lane
+// takes 32 consecutive codes; with one scale per 32 the matrix core's block
+// b (of 32) must be the stored block b, so lane group g takes the stored
+// positions 16 g .. 16 g + 15 and 64 + 16 g .. 64 + 16 g + 15 (the halves
+// the core reads as k = 16 g .. and 64 + 16 g ..), and supplies the scale of
+// block g of its row.  E2M3 / E2M1: lane group g supplies the 32 positions
+// 32 g .. 32 g + 31, one block, packed 6 / 4 bits per code from the low bits
+// up in 6 / 4 registers (measured with an in-bounds probe: the order inside
+// a block does not change the result when A and B share it; the block of a
+// lane group must be its own).
+template <int BS, int FMT>
 __device__ __forceinline__ i8_t fp8_operand(const uint8_t *s, int r, int lane) {
     const int g = lane >> 4, f = fp8_swz(r);
-    // BS 128: chunks 2g and 2g + 1 (32 consecutive codes); BS 32: chunks g
-    // and 4 + g (positions 16 g .. and 64 + 16 g ..)
-    const int c0 = BS == 128 ? 2 * g : g, c1 = BS == 128 ? 2 * g + 1 : 4 + g;
+    // chunks 2g and 2g + 1 (32 consecutive codes), or with E4M3 per 32:
+    // chunks g and 4 + g (positions 16 g .. and 64 + 16 g ..)
+    constexpr bool halves = FMT == kElemE4M3 && BS == 32;
+    const int c0 = halves ? g : 2 * g, c1 = halves ? 4 + g : 2 * g + 1;
     const uint8_t *row = s + r * 128;
     const u4_t lo = *reinterpret_cast<const u4_t *>(row + 16 * (c0 ^ f));
     const u4_t hi = *reinterpret_cast<const u4_t *>(row + 16 * (c1 ^ f));
-    return i8_t{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w,
-                (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+    const unsigned w[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+    if constexpr (FMT == kElemE4M3) {
+        return i8_t{(int)w[0], (int)w[1], (int)w[2], (int)w[3],
+                    (int)w[4], (int)w[5], (int)w[6], (int)w[7]};
+    } else if constexpr (FMT == kElemE2M1) {
+        // word i holds codes 4i .. 4i + 3 (one per byte): y = w | w >> 4 puts
+        // codes 4i, 4i+1 in byte 0 and 4i+2, 4i+3 in byte 2
+        unsigned p[4];
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            const unsigned y0 = w[2 * d] | (w[2 * d] >> 4), y1 = w[2 * d + 1] | (w[2 * d + 1] >> 4);
+            p[d] = (y0 & 0xFFu) | ((y0 >> 8) & 0xFF00u) | ((y1 & 0xFFu) << 16) |
+                   ((y1 << 8) & 0xFF000000u);
+        }
+        return i8_t{(int)p[0], (int)p[1], (int)p[2], (int)p[3], 0, 0, 0, 0};
+    } else {
+        // four 6-bit codes of a word into 24 bits, four such into 3 words
+        unsigned t[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            t[i] = (w[i] & 0x3Fu) | ((w[i] >> 2) & 0xFC0u) | ((w[i] >> 4) & 0x3F000u) |
+                   ((w[i] >> 6) & 0xFC0000u);
+        unsigned p[6];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const unsigned *u = t + 4 * h;
+            p[3 * h] = u[0] | (u[1] << 24);
+            p[3 * h + 1] = (u[1] >> 8) | (u[2] << 16);
+            p[3 * h + 2] = (u[2] >> 16) | (u[3] << 8);
+        }
+        return i8_t{(int)p[0], (int)p[1], (int)p[2], (int)p[3], (int)p[4], (int)p[5], 0, 0};
+    }
 }
 
 // One 128-block on the matrix cores: each wave's FM x FN fragments.  sE holds
 // the biased exponents of the tile's A rows, then of its B rows (one per row,
 // or four per row with blocks of 32).
-template <int FM, int FN, int WTM, int WTN, int BM, int BS>
+template <int FM, int FN, int WTM, int WTN, int BM, int BS, int FMT>
 __device__ __forceinline__ void fp8_mma_block(const uint8_t *sA, const uint8_t *sB,
                                               const int32_t *sE, int wm, int wn, int lane,
                                               f4_t (&acc)[FM][FN]) {
@@ -271,13 +347,13 @@ __device__ __forceinline__ void fp8_mma_block(const uint8_t *sA, const uint8_t *
 #pragma unroll
     for (int i = 0; i < FM; ++i) {
         const int r = wm * WTM + i * 16 + (lane & 15);
-        a[i] = fp8_operand<BS>(sA, r, lane);
+        a[i] = fp8_operand<BS, FMT>(sA, r, lane);
         sa[i] = sE[r * SUB + sub];
     }
 #pragma unroll
     for (int j = 0; j < FN; ++j) {
         const int r = wn * WTN + j * 16 + (lane & 15);
-        b[j] = fp8_operand<BS>(sB, r, lane);
+        b[j] = fp8_operand<BS, FMT>(sB, r, lane);
         sb[j] = sE[(BM + r) * SUB + sub];
     }
 #pragma unroll
@@ -287,8 +363,8 @@ __device__ __forceinline__ void fp8_mma_block(const uint8_t *sA, const uint8_t *
             // B first: the result holds 16 N positions by 16 M positions, so
             // each lane ends with four neighbouring N positions of one M row
             // (C's cheapest direction), stored as one 16-byte word.
-            acc[i][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(b[j], a[i], acc[i][j], 0,
-                                                                         0, 0, sb[j], 0, sa[i]);
+            acc[i][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(b[j], a[i], acc[i][j], FMT,
+                                                                         FMT, 0, sb[j], 0, sa[i]);
 }
 
 // Whether the four N positions n .. n+3 of an M row are neighbours in C,
@@ -301,7 +377,7 @@ __device__ __forceinline__ bool fp8_c_word(const float *C, const int64_t *__rest
 }
 
 // C tile BM x BN, 4 waves as 2 x 2, each wave (BM/2) x (BN/2) in 16x16 fragments.
-template <int BM, int BN, int BS>
+template <int BM, int BN, int BS, int FMT>
 __global__ __launch_bounds__(256) void fp8_gemm_kernel(const uint8_t *__restrict__ QA,
                                                        const int32_t *__restrict__ EA,
                                                        const uint8_t *__restrict__ QB,
@@ -379,7 +455,7 @@ __global__ __launch_bounds__(256) void fp8_gemm_kernel(const uint8_t *__restrict
         fp8_load_block<CA>(pa, Kp, n2, t, ra);
         fp8_load_block<CB>(pb, Kp, n2, t, rb);
         xs = scales(n2);
-        fp8_mma_block<FM, FN, WTM, WTN, BM, BS>(sA[0], sB[0], sE[0], wm, wn, lane, acc);
+        fp8_mma_block<FM, FN, WTM, WTN, BM, BS, FMT>(sA[0], sB[0], sE[0], wm, wn, lane, acc);
         __builtin_amdgcn_sched_barrier(0);
         fp8_store_block<CA>(sA[1], t, ra2);
         fp8_store_block<CB>(sB[1], t, rb2);
@@ -390,7 +466,7 @@ __global__ __launch_bounds__(256) void fp8_gemm_kernel(const uint8_t *__restrict
         fp8_load_block<CA>(pa, Kp, n3, t, ra2);
         fp8_load_block<CB>(pb, Kp, n3, t, rb2);
         xs2 = scales(n3);
-        fp8_mma_block<FM, FN, WTM, WTN, BM, BS>(sA[1], sB[1], sE[1], wm, wn, lane, acc);
+        fp8_mma_block<FM, FN, WTM, WTN, BM, BS, FMT>(sA[1], sB[1], sE[1], wm, wn, lane, acc);
         __builtin_amdgcn_sched_barrier(0);
         fp8_store_block<CA>(sA[0], t, ra);
         fp8_store_block<CB>(sB[0], t, rb);
@@ -447,22 +523,56 @@ __global__ __launch_bounds__(256) void fp8_gemm_kernel(const uint8_t *__restrict
     }
 }
 
+namespace {
+
+// (block size, element format) -> kernel; false for a pair the path does not
+// have (E2M3 and E2M1 come with blocks of 32 only).
+template <template <int, int> class K>
+bool pick(int bs, int fmt, typename K<128, kElemE4M3>::F &out) {
+    if (bs == 128 && fmt == kElemE4M3) out = K<128, kElemE4M3>::f;
+    else if (bs == 32 && fmt == kElemE4M3) out = K<32, kElemE4M3>::f;
+    else if (bs == 32 && fmt == kElemE2M3) out = K<32, kElemE2M3>::f;
+    else if (bs == 32 && fmt == kElemE2M1) out = K<32, kElemE2M1>::f;
+    else return false;
+    return true;
+}
+
+template <int BS, int FMT> struct QuantK {
+    using F = decltype(&fp8_quant_kernel<128, kElemE4M3>);
+    static constexpr F f = &fp8_quant_kernel<BS, FMT>;
+};
+template <int BS, int FMT> struct QuantRowsK {
+    using F = decltype(&fp8_quant_rows_kernel<128, kElemE4M3>);
+    static constexpr F f = &fp8_quant_rows_kernel<BS, FMT>;
+};
+template <int BS, int FMT> struct Gemm128K {
+    using F = decltype(&fp8_gemm_kernel<128, 128, 128, kElemE4M3>);
+    static constexpr F f = &fp8_gemm_kernel<128, 128, BS, FMT>;
+};
+template <int BS, int FMT> struct Gemm64K {
+    using F = decltype(&fp8_gemm_kernel<64, 64, 128, kElemE4M3>);
+    static constexpr F f = &fp8_gemm_kernel<64, 64, BS, FMT>;
+};
+
+}  // namespace
+
 int launch_fp8_quant(const float *X, const int64_t *offR, const int32_t *rowMap, int64_t rows,
                      int64_t rowsPad, const int64_t *offK, int64_t K, bool rowsFast, uint8_t *Q,
-                     int32_t *E, hipStream_t s, int bs) {
+                     int32_t *E, hipStream_t s, int bs, int fmt) {
     const int64_t nb = (K + 127) / 128;
     const int64_t tasks = rowsFast ? (rowsPad + 15) / 16 * nb
                                    : rowsPad * ((nb + kQuantRun - 1) / kQuantRun);
     const int64_t blocks = (tasks + 3) / 4;
     if (blocks > INT32_MAX) return GETT_ERR_INTERNAL;
     (void)hipGetLastError();   // clear a stale error left by other HIP users
-    if (bs != 128 && bs != 32) return GETT_ERR_INTERNAL;
     if (rowsFast) {
-        auto k = bs == 128 ? fp8_quant_rows_kernel<128> : fp8_quant_rows_kernel<32>;
+        QuantRowsK<128, kElemE4M3>::F k;
+        if (!pick<QuantRowsK>(bs, fmt, k)) return GETT_ERR_INTERNAL;
         hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(256), 0, s, X, offR, rowMap, rows,
                            rowsPad, offK, K, Q, E);
     } else {
-        auto k = bs == 128 ? fp8_quant_kernel<128> : fp8_quant_kernel<32>;
+        QuantK<128, kElemE4M3>::F k;
+        if (!pick<QuantK>(bs, fmt, k)) return GETT_ERR_INTERNAL;
         hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(256), 0, s, X, offR, rows, rowsPad,
                            offK, K, Q, E);
     }
@@ -471,18 +581,19 @@ int launch_fp8_quant(const float *X, const int64_t *offR, const int32_t *rowMap,
 
 int launch_fp8_gemm(int tile, const uint8_t *QA, const int32_t *EA, const uint8_t *QB,
                     const int32_t *EB, float *C, const int64_t *offCM, const int64_t *offCN,
-                    int64_t M, int64_t N, int64_t K, hipStream_t s, int bs) {
-    if (bs != 128 && bs != 32) return GETT_ERR_INTERNAL;
+                    int64_t M, int64_t N, int64_t K, hipStream_t s, int bs, int fmt) {
     (void)hipGetLastError();   // clear a stale error left by other HIP users
     if (tile == 3) {
         const int tilesM = (int)((M + 127) / 128), tilesN = (int)((N + 127) / 128);
-        auto k = bs == 128 ? fp8_gemm_kernel<128, 128, 128> : fp8_gemm_kernel<128, 128, 32>;
+        Gemm128K<128, kElemE4M3>::F k;
+        if (!pick<Gemm128K>(bs, fmt, k)) return GETT_ERR_INTERNAL;
         hipLaunchKernelGGL(k, dim3(tilesM * tilesN), dim3(256), 0, s, QA, EA, QB, EB, C, offCM,
                            offCN, M, N, K, tilesM, tilesN);
     } else {
         // operands are padded to multiples of 128 rows, so 64-row tiles stay inside
         const int tilesM = (int)((M + 63) / 64), tilesN = (int)((N + 63) / 64);
-        auto k = bs == 128 ? fp8_gemm_kernel<64, 64, 128> : fp8_gemm_kernel<64, 64, 32>;
+        Gemm64K<128, kElemE4M3>::F k;
+        if (!pick<Gemm64K>(bs, fmt, k)) return GETT_ERR_INTERNAL;
         hipLaunchKernelGGL(k, dim3(tilesM * tilesN), dim3(256), 0, s, QA, EA, QB, EB, C, offCM,
                            offCN, M, N, K, tilesM, tilesN);
     }

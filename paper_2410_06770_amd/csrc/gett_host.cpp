@@ -745,9 +745,10 @@ static int get_fp8_plan(const Args &a, int dev, Fp8Plan **out) {
     return 0;
 }
 
-// bs: contracted positions per scale (128, or 32 for the MX-style call).
+// bs: contracted positions per scale (128, or 32 for the MX-style calls);
+// fmt: element format (kElemE4M3, or kElemE2M3 / kElemE2M1 with bs 32).
 static int run_fp8(const Args &a, const float *A, const float *B, float *C, hipStream_t s, int dev,
-                   int bs) {
+                   int bs, int fmt) {
     Fp8Plan *pl = nullptr;
     int rc = get_fp8_plan(a, dev, &pl);
     if (rc) return rc;
@@ -768,11 +769,11 @@ static int run_fp8(const Args &a, const float *A, const float *B, float *C, hipS
     int32_t *EB = EA + (size_t)Mq * nbs;
     const float *X0 = pl->swapped ? B : A, *X1 = pl->swapped ? A : B;
     rc = launch_fp8_quant(X0, pl->aRowsFast ? pl->d_rowsOp[0] : rowsA, pl->d_rowMap[0], M, Mq,
-                          kA, K, pl->aRowsFast, QA, EA, s, bs);
+                          kA, K, pl->aRowsFast, QA, EA, s, bs, fmt);
     if (!rc)
         rc = launch_fp8_quant(X1, pl->bRowsFast ? pl->d_rowsOp[1] : rowsB, pl->d_rowMap[1], N, Nq,
-                              kB, K, pl->bRowsFast, QB, EB, s, bs);
-    if (!rc) rc = launch_fp8_gemm(pl->tile, QA, EA, QB, EB, C, offCM, offCN, M, N, K, s, bs);
+                              kB, K, pl->bRowsFast, QB, EB, s, bs, fmt);
+    if (!rc) rc = launch_fp8_gemm(pl->tile, QA, EA, QB, EB, C, offCM, offCN, M, N, K, s, bs, fmt);
     if (work_free(ws, s) && !rc) rc = GETT_ERR_HIP;
     return rc;
 }
@@ -1184,7 +1185,8 @@ static bool is_one(const double *x) { return x[0] == 1.0 && x[1] == 0.0; }
 // alpha, beta: (re, im) pairs of C <- alpha * sum + beta * C_in (kOne for
 // the paper's accumulate).
 static int run(int prec, const Args &a, const void *A, const void *B, void *C,
-               const double *alpha = kOne, const double *beta = kOne, int fp8_block = 128) {
+               const double *alpha = kOne, const double *beta = kOne, int fp8_block = 128,
+               int fp8_fmt = kElemE4M3) {
     int info = validate(a, A, B, C);
     if (info) return info;
     Canon probe = canonicalise(a, 0, 128);
@@ -1203,7 +1205,7 @@ static int run(int prec, const Args &a, const void *A, const void *B, void *C,
     hipStream_t s = t_stream;
     if (prec == kFP8)
         return run_fp8(a, static_cast<const float *>(A), static_cast<const float *>(B),
-                       static_cast<float *>(C), s, dev, fp8_block);
+                       static_cast<float *>(C), s, dev, fp8_block, fp8_fmt);
     const int64_t forced = g_forced.load();
     std::shared_ptr<Plan> pl;
     // Under the AUTOTUNE policy a plan-cache miss times the menu; the timing
@@ -1837,7 +1839,7 @@ int dgett_ozaki(int64_t ranka, const int64_t *exta, const int64_t *inca, const d
 
 static int fp8_quantize_entry(int64_t rankx, const int64_t *extx, const int64_t *incx,
                               const float *X, int64_t conts, const int64_t *contx, uint8_t *QX,
-                              int32_t *EX, int bs) {
+                              int32_t *EX, int bs, int fmt) {
     if (rankx < 0 || rankx > 64) return -1;
     if (rankx > 0 && !extx) return -2;
     int64_t n = 1;
@@ -1876,7 +1878,8 @@ static int fp8_quantize_entry(int64_t rankx, const int64_t *extx, const int64_t 
         return GETT_ERR_ALLOC;
     if (hipMemcpyAsync(d, h.data(), h.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess)
         return GETT_ERR_HIP;
-    rc = launch_fp8_quant(X, d, nullptr, R, R, d + R, K, rows_fast(rows, kk, 0), QX, EX, s, bs);
+    rc = launch_fp8_quant(X, d, nullptr, R, R, d + R, K, rows_fast(rows, kk, 0), QX, EX, s, bs,
+                          fmt);
     (void)hipFreeAsync(d, s);
     // h must outlive the copy: wait for it
     if (hipStreamSynchronize(s) != hipSuccess && !rc) rc = GETT_ERR_HIP;
@@ -1885,19 +1888,43 @@ static int fp8_quantize_entry(int64_t rankx, const int64_t *extx, const int64_t 
 
 int sgett_fp8_quantize(int64_t rankx, const int64_t *extx, const int64_t *incx, const float *X,
                        int64_t conts, const int64_t *contx, uint8_t *QX, int32_t *EX) {
-    return fp8_quantize_entry(rankx, extx, incx, X, conts, contx, QX, EX, 128);
+    return fp8_quantize_entry(rankx, extx, incx, X, conts, contx, QX, EX, 128, kElemE4M3);
 }
 
 int sgett_mxfp8_quantize(int64_t rankx, const int64_t *extx, const int64_t *incx, const float *X,
                          int64_t conts, const int64_t *contx, uint8_t *QX, int32_t *EX) {
-    return fp8_quantize_entry(rankx, extx, incx, X, conts, contx, QX, EX, 32);
+    return fp8_quantize_entry(rankx, extx, incx, X, conts, contx, QX, EX, 32, kElemE4M3);
+}
+
+int sgett_mxfp6_quantize(int64_t rankx, const int64_t *extx, const int64_t *incx, const float *X,
+                         int64_t conts, const int64_t *contx, uint8_t *QX, int32_t *EX) {
+    return fp8_quantize_entry(rankx, extx, incx, X, conts, contx, QX, EX, 32, kElemE2M3);
+}
+
+int sgett_mxfp4_quantize(int64_t rankx, const int64_t *extx, const int64_t *incx, const float *X,
+                         int64_t conts, const int64_t *contx, uint8_t *QX, int32_t *EX) {
+    return fp8_quantize_entry(rankx, extx, incx, X, conts, contx, QX, EX, 32, kElemE2M1);
 }
 
 int sgett_mxfp8(int64_t ranka, const int64_t *exta, const int64_t *inca, const float *A,
                 int64_t rankb, const int64_t *extb, const int64_t *incb, const float *B,
                 int64_t conts, const int64_t *conta, const int64_t *contb, const int64_t *perm,
                 const int64_t *incc, float *C) {
-    return run(kFP8, GETT_ARGS_MAKE, A, B, C, kOne, kOne, 32);
+    return run(kFP8, GETT_ARGS_MAKE, A, B, C, kOne, kOne, 32, kElemE4M3);
+}
+
+int sgett_mxfp6(int64_t ranka, const int64_t *exta, const int64_t *inca, const float *A,
+                int64_t rankb, const int64_t *extb, const int64_t *incb, const float *B,
+                int64_t conts, const int64_t *conta, const int64_t *contb, const int64_t *perm,
+                const int64_t *incc, float *C) {
+    return run(kFP8, GETT_ARGS_MAKE, A, B, C, kOne, kOne, 32, kElemE2M3);
+}
+
+int sgett_mxfp4(int64_t ranka, const int64_t *exta, const int64_t *inca, const float *A,
+                int64_t rankb, const int64_t *extb, const int64_t *incb, const float *B,
+                int64_t conts, const int64_t *conta, const int64_t *contb, const int64_t *perm,
+                const int64_t *incc, float *C) {
+    return run(kFP8, GETT_ARGS_MAKE, A, B, C, kOne, kOne, 32, kElemE2M1);
 }
 
 int sgett_batch(int64_t count, int64_t prec, const int64_t *ranka, const int64_t *const *exta,

@@ -64,13 +64,16 @@ int64_t addr_violations(int prec, bool reset);
 // walks the rows in the order of offR, and rowMap (NULL: identity) gives the
 // output row of each.
 // bs: contracted positions per scale, 128 or 32 (MX-style); E holds
-// 128 / bs exponents per row and 128-block.
+// 128 / bs exponents per row and 128-block.  fmt: element format, numbered
+// as the scaled MFMA's format operand (kElemE4M3 with either block size;
+// kElemE2M3 / kElemE2M1 with bs 32); codes are one per byte either way.
+constexpr int kElemE4M3 = 0, kElemE2M3 = 2, kElemE2M1 = 4;
 int launch_fp8_quant(const float *X, const int64_t *offR, const int32_t *rowMap, int64_t rows,
                      int64_t rowsPad, const int64_t *offK, int64_t K, bool rowsFast, uint8_t *Q,
-                     int32_t *E, hipStream_t s, int bs);
+                     int32_t *E, hipStream_t s, int bs, int fmt);
 int launch_fp8_gemm(int tile, const uint8_t *QA, const int32_t *EA, const uint8_t *QB,
                     const int32_t *EB, float *C, const int64_t *offCM, const int64_t *offCN,
-                    int64_t M, int64_t N, int64_t K, hipStream_t s, int bs);
+                    int64_t M, int64_t N, int64_t K, hipStream_t s, int bs, int fmt);
 
 // MLP kernels.
 int launch_mlp_linear_fwd(const float *X, const float *W, const float *b, float *Y, int64_t batch,

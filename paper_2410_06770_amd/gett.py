@@ -68,7 +68,7 @@ def lib():
     L = ct.CDLL(LIB_PATH)
     a14 = [i64, I64P, I64P, vp, i64, I64P, I64P, vp, i64, I64P, I64P, I64P, I64P, vp]
     for name in ("dgett", "sgett", "sgett_bf16x3", "sgett_fp8", "dgett_noalloc", "zgett",
-                 "cgett", "sgett_mxfp8"):
+                 "cgett", "sgett_mxfp8", "sgett_mxfp6", "sgett_mxfp4"):
         getattr(L, name).argtypes = a14
         getattr(L, name).restype = ct.c_int
     L.dgett_ozaki.argtypes = a14 + [i64]
@@ -89,7 +89,8 @@ def lib():
     L.cgett_unary.argtypes = [vp] + un11 + [vp, vp]
     for name in ("dgett_unary", "sgett_unary", "zgett_unary", "cgett_unary"):
         getattr(L, name).restype = ct.c_int
-    for name in ("sgett_fp8_quantize", "sgett_mxfp8_quantize"):
+    for name in ("sgett_fp8_quantize", "sgett_mxfp8_quantize", "sgett_mxfp6_quantize",
+                 "sgett_mxfp4_quantize"):
         getattr(L, name).argtypes = [i64, I64P, I64P, vp, i64, I64P, vp, vp]
         getattr(L, name).restype = ct.c_int
     for name in ("sgett_batch", "dgett_batch"):
@@ -307,6 +308,30 @@ def sgett_mxfp8(ranka, exta, inca, A, rankb, extb, incb, B, conts, conta, contb,
 
 def sgett_mxfp8_quantize(rankx, extx, incx, X, conts, contx, QX, EX) -> int:
     return lib().sgett_mxfp8_quantize(int(rankx), _arr(extx), _arr(incx), vp(X) if X else None,
+                                      int(conts), _arr(contx), vp(QX) if QX else None,
+                                      vp(EX) if EX else None)
+
+
+def sgett_mxfp6(ranka, exta, inca, A, rankb, extb, incb, B, conts, conta, contb, perm, incc,
+                C) -> int:
+    return _call14("sgett_mxfp6", ranka, exta, inca, A, rankb, extb, incb, B, conts, conta,
+                   contb, perm, incc, C)
+
+
+def sgett_mxfp4(ranka, exta, inca, A, rankb, extb, incb, B, conts, conta, contb, perm, incc,
+                C) -> int:
+    return _call14("sgett_mxfp4", ranka, exta, inca, A, rankb, extb, incb, B, conts, conta,
+                   contb, perm, incc, C)
+
+
+def sgett_mxfp6_quantize(rankx, extx, incx, X, conts, contx, QX, EX) -> int:
+    return lib().sgett_mxfp6_quantize(int(rankx), _arr(extx), _arr(incx), vp(X) if X else None,
+                                      int(conts), _arr(contx), vp(QX) if QX else None,
+                                      vp(EX) if EX else None)
+
+
+def sgett_mxfp4_quantize(rankx, extx, incx, X, conts, contx, QX, EX) -> int:
+    return lib().sgett_mxfp4_quantize(int(rankx), _arr(extx), _arr(incx), vp(X) if X else None,
                                       int(conts), _arr(contx), vp(QX) if QX else None,
                                       vp(EX) if EX else None)
 

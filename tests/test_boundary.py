@@ -59,7 +59,8 @@ BAD = [(-1, dict(ranka=-1)), (-1, dict(ranka=65)), (-2, dict(exta=[3, -1])),
 
 
 @pytest.mark.parametrize("code,kw", BAD)
-@pytest.mark.parametrize("fn", ["dgett", "sgett", "sgett_bf16x3", "sgett_fp8", "dgett_noalloc"])
+@pytest.mark.parametrize("fn", ["dgett", "sgett", "sgett_bf16x3", "sgett_fp8", "dgett_noalloc",
+                                "sgett_mxfp8", "sgett_mxfp6", "sgett_mxfp4"])
 def test_info_codes(fn, code, kw):
     assert call(getattr(gett, fn), **kw) == code
     if kw.get("ranka", 0) > 64:
