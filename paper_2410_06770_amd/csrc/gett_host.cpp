@@ -951,16 +951,36 @@ static int time_schedule(int prec, const Args &a, const void *A, const void *B, 
     return 0;
 }
 
+// HBM bytes a schedule is modelled to move: each tile reads its A rows and
+// B columns over its K range (a panel is fetched again by every tile row or
+// column that needs it), C is read and written once, and a K split writes
+// and reads back its FP64 partials.
+static double modeled_bytes(int prec, const Canon &c, Sched s) {
+    const TileShape ts = kTiles[prec][s.tile];
+    const int64_t tm = (c.M + ts.bm - 1) / ts.bm, tn = (c.N + ts.bn - 1) / ts.bn;
+    const int S = split_count(s.split, tm * tn, std::max<int64_t>(c.K, 1), ts.bk, nullptr);
+    const double esz = (double)prec_bytes(prec), mn = (double)c.M * (double)c.N * (double)c.H;
+    double b = (double)tm * (double)tn * (double)(ts.bm + ts.bn) * (double)c.K * (double)c.H * esz +
+               2.0 * mn * esz;
+    if (S > 1) b += 2.0 * S * mn * (prec_complex(prec) ? 16.0 : 8.0);
+    return b;
+}
+
 // Two passes: every valid schedule once (after `warmup` untimed runs), then
 // the fastest few again, `reps` timed runs each after one untimed run; their
 // medians decide.  The second pass runs in rounds that time every candidate
 // once, so a drift of the clock or power state over the pass shifts all
 // candidates alike instead of favouring the ones timed first.  times[]
 // receives the median for re-timed schedules, the single time for the
-// others, and -1 for invalid ones.
+// others, and -1 for invalid ones.  With prefer_less_traffic the pick among
+// the re-timed schedules within kTieWindow of the fastest median is the one
+// with the fewest modelled HBM bytes (the medians of the best few often lie
+// within the timing noise of one another; the one that moves less data keeps
+// more of its speed under sustained load); otherwise the fastest median.
+constexpr double kTieWindow = 0.02;
 static int64_t autotune(int prec, const Args &a, const void *A, const void *B, void *C, int dev,
                         int warmup, int reps, double *times, int64_t ntimes, int *status,
-                        SchedFilter allow = nullptr) {
+                        SchedFilter allow = nullptr, bool prefer_less_traffic = false) {
     Canon c0 = canonicalise(a, 0, 128);
     *status = 0;
     std::vector<double> t1(kNumSched, -1.0);
@@ -1029,6 +1049,18 @@ static int64_t autotune(int prec, const Args &a, const void *A, const void *B, v
         if (us < best) {
             best = us;
             best_id = order[i];
+        }
+    }
+    if (prefer_less_traffic) {
+        double least = modeled_bytes(prec, c0, sched_of(best_id));
+        for (size_t i = 0; i < top; ++i) {
+            const int64_t id = order[i];
+            if (t1[id] > best * (1.0 + kTieWindow)) continue;
+            const double b = modeled_bytes(prec, c0, sched_of(id));
+            if (b < least) {
+                least = b;
+                best_id = id;
+            }
         }
     }
     if (times)
@@ -1130,7 +1162,7 @@ static Sched choose_schedule(int prec, const Args &a, int64_t M, int64_t N, int6
         std::vector<double> us(kNumSched, -1.0);
         const int64_t id = autotune(prec, a, t_tune_ptrs[0], t_tune_ptrs[1],
                                     const_cast<void *>(t_tune_ptrs[2]), t_tune_dev, 1, 5,
-                                    us.data(), kNumSched, &st);
+                                    us.data(), kNumSched, &st, nullptr, true);
         if (!st && id >= 0) {
             s = sched_of(id);
             *source = "autotuned";
