@@ -462,16 +462,21 @@ template <int ROWS> struct PkLoad8 {
     }
 };
 
-template <int BM, int BN> struct Pk8Cfg {
+// DB: B's fragments straight from the packed planes into registers (a
+// fragment's operand for one step is one 1 KB block, so a wave reads it in
+// one coalesced load), one step ahead in a second register set; only A goes
+// through LDS.  B fragments are shared by two waves, A fragments by four, so
+// this moves the operand reads that LDS spares least onto the L1 path.
+template <int BM, int BN, bool DB = false> struct Pk8Cfg {
     static constexpr int WTM = BM / 2, WTN = BN / 4, FM = WTM / 16, FN = WTN / 16;
     static constexpr int PA = BM * kLd, PB = BN * kLd;
-    static constexpr int SA = 2 * PA, SB = 2 * PB;
+    static constexpr int SA = 2 * PA, SB = DB ? 0 : 2 * PB;
     static constexpr int kLdsBytes = 2 * (SA + SB) * 2;
 };
 
-template <int BM, int BN>
+template <int BM, int BN, bool DB>
 __global__ __launch_bounds__(512) void bf3_packed_gemm8_kernel(Bf3Packed g) {
-    using Cfg = Pk8Cfg<BM, BN>;
+    using Cfg = Pk8Cfg<BM, BN, DB>;
     constexpr int FM = Cfg::FM, FN = Cfg::FN;
     extern __shared__ __align__(16) uint16_t lds[];
     uint16_t *sA = lds, *sB = lds + 2 * Cfg::SA;   // [stage][plane][row][kLd]
@@ -527,26 +532,85 @@ __global__ __launch_bounds__(512) void bf3_packed_gemm8_kernel(Bf3Packed g) {
     };
 
     auto step = [&](int64_t s) { return 512 * (s < nsteps ? s : nsteps - 1); };
-    u4_t ra[PkLoad8<BM>::C], rb[PkLoad8<BN>::C];
-    la.load(aH, aL, ra);
-    lb.load(bH, bL, rb);
-    la.store(sA, ra);
-    lb.store(sB, rb);
-    __syncthreads();
-    for (int64_t s = 0; s < nsteps; ++s) {
-        const int cur = (int)(s & 1);
-        const int64_t k1 = step(s + 1);
-        la.load(aH + k1, aL + k1, ra);
-        lb.load(bH + k1, bL + k1, rb);
-        // raised priority while issuing MFMAs: a wave that holds its operands
-        // runs ahead of the waves still reading LDS (measured 6 % faster)
-        __builtin_amdgcn_s_setprio(1);
-        mma(sA + cur * Cfg::SA, sB + cur * Cfg::SB);
-        __builtin_amdgcn_s_setprio(0);
-        __builtin_amdgcn_sched_barrier(0);
-        la.store(sA + (cur ^ 1) * Cfg::SA, ra);
-        lb.store(sB + (cur ^ 1) * Cfg::SB, rb);
+    if constexpr (!DB) {
+        u4_t ra[PkLoad8<BM>::C], rb[PkLoad8<BN>::C];
+        la.load(aH, aL, ra);
+        lb.load(bH, bL, rb);
+        la.store(sA, ra);
+        lb.store(sB, rb);
         __syncthreads();
+        for (int64_t s = 0; s < nsteps; ++s) {
+            const int cur = (int)(s & 1);
+            const int64_t k1 = step(s + 1);
+            la.load(aH + k1, aL + k1, ra);
+            lb.load(bH + k1, bL + k1, rb);
+            // raised priority while issuing MFMAs: a wave that holds its operands
+            // runs ahead of the waves still reading LDS (measured 6 % faster)
+            __builtin_amdgcn_s_setprio(1);
+            mma(sA + cur * Cfg::SA, sB + cur * Cfg::SB);
+            __builtin_amdgcn_s_setprio(0);
+            __builtin_amdgcn_sched_barrier(0);
+            la.store(sA + (cur ^ 1) * Cfg::SA, ra);
+            lb.store(sB + (cur ^ 1) * Cfg::SB, rb);
+            __syncthreads();
+        }
+    } else {
+        // lane l's 16 bytes of a fragment block: row l % 16, chunk l / 16
+        // (the chunk it reads from LDS in the other form)
+        const int64_t bl0 = (int64_t)(wn * Cfg::WTN / 16) * lb.gstride + (lane & 15) * 32 +
+                            8 * (lane >> 4);
+        auto bload = [&](int64_t k, bf8_t (&bh)[FN], bf8_t (&blo)[FN]) {
+#pragma unroll
+            for (int j = 0; j < FN; ++j) {
+                const int64_t o = bl0 + (int64_t)j * lb.gstride + k;
+                bh[j] = *reinterpret_cast<const bf8_t *>(bH + o);
+                blo[j] = *reinterpret_cast<const bf8_t *>(bL + o);
+            }
+        };
+        // One B register set: fragment j's MFMAs for this step come first, then
+        // (behind a scheduling barrier, so the registers are reused rather
+        // than renamed) its load for the next step, which has the rest of this
+        // step and the barrier to arrive.
+        auto mma_b = [&](const uint16_t *stA, bf8_t (&bh)[FN], bf8_t (&blo)[FN], int64_t knext) {
+            const __bf16 *ahi = reinterpret_cast<const __bf16 *>(stA), *alo = ahi + Cfg::PA;
+            bf8_t ah[FM], al[FM];
+#pragma unroll
+            for (int i = 0; i < FM; ++i) {
+                const int r = wm * Cfg::WTM + i * 16 + (lane & 15);
+                ah[i] = *reinterpret_cast<const bf8_t *>(ahi + r * kLd + kc);
+                al[i] = *reinterpret_cast<const bf8_t *>(alo + r * kLd + kc);
+            }
+#pragma unroll
+            for (int j = 0; j < FN; ++j) {
+#pragma unroll
+                for (int i = 0; i < FM; ++i) {
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], blo[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+                const int64_t o = bl0 + (int64_t)j * lb.gstride + knext;
+                bh[j] = *reinterpret_cast<const bf8_t *>(bH + o);
+                blo[j] = *reinterpret_cast<const bf8_t *>(bL + o);
+            }
+        };
+        u4_t ra[PkLoad8<BM>::C];
+        bf8_t bh[FN], blo[FN];
+        la.load(aH, aL, ra);
+        bload(0, bh, blo);
+        la.store(sA, ra);
+        __syncthreads();
+        for (int64_t s = 0; s < nsteps; ++s) {
+            const int cur = (int)(s & 1);
+            const int64_t k1 = step(s + 1);
+            la.load(aH + k1, aL + k1, ra);
+            __builtin_amdgcn_s_setprio(1);
+            mma_b(sA + cur * Cfg::SA, bh, blo, k1);
+            __builtin_amdgcn_s_setprio(0);
+            __builtin_amdgcn_sched_barrier(0);
+            la.store(sA + (cur ^ 1) * Cfg::SA, ra);
+            __syncthreads();
+        }
     }
 
     pk_epilogue<FM, FN>(g, acc, m0 + wm * Cfg::WTM, n0 + wn * Cfg::WTN, lane, split);
@@ -748,20 +812,22 @@ template <int BM, int BN> static int launch_gemm(const Bf3Packed &g, hipStream_t
     return launch_status();
 }
 
+constexpr bool kGemm8DirectB = true;
+
 template <int BM, int BN> static int launch_gemm8(const Bf3Packed &g, hipStream_t s) {
-    using Cfg = Pk8Cfg<BM, BN>;
+    using Cfg = Pk8Cfg<BM, BN, kGemm8DirectB>;
     static bool attr_set = false;   // set once per process (every device takes the same value)
     if (!attr_set) {
-        if (hipFuncSetAttribute(reinterpret_cast<const void *>(bf3_packed_gemm8_kernel<BM, BN>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize,
-                                Cfg::kLdsBytes) != hipSuccess)
+        if (hipFuncSetAttribute(
+                reinterpret_cast<const void *>(bf3_packed_gemm8_kernel<BM, BN, kGemm8DirectB>),
+                hipFuncAttributeMaxDynamicSharedMemorySize, Cfg::kLdsBytes) != hipSuccess)
             return GETT_ERR_HIP;
         attr_set = true;
     }
     const int64_t total = (int64_t)g.tilesM * g.tilesN * g.splits;
     if (total > INT32_MAX) return GETT_ERR_INTERNAL;
     (void)hipGetLastError();   // clear a stale error left by other HIP users
-    auto kern = bf3_packed_gemm8_kernel<BM, BN>;
+    auto kern = bf3_packed_gemm8_kernel<BM, BN, kGemm8DirectB>;
     hipLaunchKernelGGL(kern, dim3((unsigned)total), dim3(512), Cfg::kLdsBytes, s, g);
     return launch_status();
 }
