@@ -17,8 +17,9 @@
 // gemm:  a 64 x 64 tile, 8 waves as 2 x 4, each 32 x 16.  For every d = s + t
 //        (2 .. S + 1) one INT32 accumulator set sums the slice pairs (s, t)
 //        over the tile's positions -- exact: at most S pairs of at most 16384
-//        positions of 127^2, under 2^31 -- with all S A-slices and S B-slices
-//        of a step staged through LDS.  The epilogue combines in double, from
+//        positions of 127^2, under 2^31 -- with the S A-slices of a step
+//        staged through LDS and each wave's B-slice fragments loaded straight
+//        into registers.  The epilogue combines in double, from
 //        the smallest scale up: v = sum over d = S+1 .. 2 of
 //        ldexp(P_d, eA + eB - 7 d), then C <- C_in + v (one K slice) or the
 //        FP64 partial v (several K slices, reduced afterwards).
@@ -273,8 +274,8 @@ constexpr int kOzBM = 64, kOzBN = 64, kOzBK = 64;
 
 template <int S>
 __global__ __launch_bounds__(512) void oz_gemm_kernel(OzParams g) {
-    constexpr int PL = 2 * S;                       // planes per stage: A slices, then B slices
-    constexpr int kStage = PL * 64 * 64;            // bytes per stage
+    constexpr int kStage = S * 64 * 64;             // bytes per stage: the S A slices
+    constexpr int NP = (S + 1) / 2;                 // staging passes (two planes a pass)
     extern __shared__ __align__(16) uint8_t ozl[];
 
     const int tiles = g.tilesM * g.tilesN;
@@ -288,14 +289,20 @@ __global__ __launch_bounds__(512) void oz_gemm_kernel(OzParams g) {
     const int64_t nsteps = (kend - kbeg) / kOzBK;
 
     const int t = threadIdx.x, lane = t & 63, w = t >> 6, wm = w >> 2, wn = w & 3;
-    // staging: thread t moves chunk (t & 3) of row (t >> 2) & 63 of planes
-    // 2 i + (t >> 8), i < S (A slices 0 .. S-1, then B slices)
+    // staging of A: thread t moves chunk (t & 3) of row (t >> 2) & 63 of
+    // slice plane 2 i + (t >> 8), i < NP (past S in the last pass of odd S:
+    // nothing)
     const int srow = (t >> 2) & 63, sc = t & 3, spl = t >> 8;
     const int64_t rgs = g.Kq * 16;                  // bytes from one row group to the next
     const uint32_t goff = (uint32_t)((srow >> 4) * rgs + (srow & 15) * 64 + 16 * sc);
     const uint32_t soff = (uint32_t)(srow * 64 + 16 * (sc ^ oz_swz(srow)));
     // the tile's first row group at the slice's first step; step j at + 1024 j
-    const uint8_t *Ab = g.A + m0 * g.Kq + kbeg * 16, *Bb = g.B + n0 * g.Kq + kbeg * 16;
+    const uint8_t *Ab = g.A + m0 * g.Kq + kbeg * 16;
+    // B straight from the slice planes: a plane's block of 16 rows x 64
+    // positions is one MFMA operand fragment for one step, and lane l's 16
+    // bytes are row l % 16, positions 16 (l / 16) .. (the chunk the LDS
+    // layout of A hands the same lane)
+    const uint8_t *Bw = g.B + (n0 + wn * 16) * g.Kq + kbeg * 16 + (lane & 15) * 64 + 16 * (lane >> 4);
 
     v4i_t acc[S][2];
 #pragma unroll
@@ -303,52 +310,64 @@ __global__ __launch_bounds__(512) void oz_gemm_kernel(OzParams g) {
 #pragma unroll
         for (int i = 0; i < 2; ++i) acc[d][i] = v4i_t{0, 0, 0, 0};
 
-    auto gload = [&](int64_t s, v4i_t (&v)[S]) {
-        const int64_t st = 1024 * (s < nsteps ? s : nsteps - 1);
+    auto stepoff = [&](int64_t s) { return 1024 * (s < nsteps ? s : nsteps - 1); };
+    // every thread loads (plane S - 1 again past the last plane, so the loads
+    // stay unconditional and countable); only the LDS store is skipped
+    auto gload = [&](int64_t s, v4i_t (&v)[NP]) {
+        const int64_t st = stepoff(s);
 #pragma unroll
-        for (int i = 0; i < S; ++i) {
-            const int pl = 2 * i + spl;
-            const uint8_t *src = pl < S ? Ab + (int64_t)pl * g.planeA + goff
-                                        : Bb + (int64_t)(pl - S) * g.planeB + goff;
-            v[i] = *reinterpret_cast<const v4i_t *>(src + st);
+        for (int i = 0; i < NP; ++i) {
+            const int pl = min(2 * i + spl, S - 1);
+            v[i] = *reinterpret_cast<const v4i_t *>(Ab + (int64_t)pl * g.planeA + goff + st);
         }
     };
-    auto lstore = [&](uint8_t *stage, const v4i_t (&v)[S]) {
+    auto lstore = [&](uint8_t *stage, const v4i_t (&v)[NP]) {
 #pragma unroll
-        for (int i = 0; i < S; ++i)
-            *reinterpret_cast<v4i_t *>(stage + (2 * i + spl) * 4096 + soff) = v[i];
+        for (int i = 0; i < NP; ++i) {
+            const int pl = 2 * i + spl;
+            if (pl < S) *reinterpret_cast<v4i_t *>(stage + pl * 4096 + soff) = v[i];
+        }
+    };
+    auto bload = [&](int tt, int64_t st) {
+        return *reinterpret_cast<const v4i_t *>(Bw + (int64_t)tt * g.planeB + st);
     };
     const int kc = 16 * ((lane >> 4) ^ oz_swz(lane & 15));   // rows start at multiples of 16
-    auto mma = [&](const uint8_t *stage) {
-        v4i_t b[S];
+    // B slices outermost: slice tt's pairs run together, then (behind a
+    // scheduling barrier, so its registers are reused) its load for the next
+    // step, which uses B slice 0 first and so gives every load about a step
+    // to arrive; the A fragments of all slices stay in registers for the step
+    auto mma = [&](const uint8_t *stage, v4i_t (&b)[S], int64_t stnext) {
+        v4i_t a[S][2];
 #pragma unroll
-        for (int tt = 0; tt < S; ++tt)
-            b[tt] = *reinterpret_cast<const v4i_t *>(stage + (S + tt) * 4096 +
-                                                     (wn * 16 + (lane & 15)) * 64 + kc);
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-            v4i_t a[2];
+        for (int s = 0; s < S; ++s)
 #pragma unroll
             for (int i = 0; i < 2; ++i)
-                a[i] = *reinterpret_cast<const v4i_t *>(stage + s * 4096 +
-                                                        (wm * 32 + i * 16 + (lane & 15)) * 64 + kc);
+                a[s][i] = *reinterpret_cast<const v4i_t *>(stage + s * 4096 +
+                                                           (wm * 32 + i * 16 + (lane & 15)) * 64 + kc);
 #pragma unroll
-            for (int tt = 0; tt + s < S; ++tt)     // slices s + 1, tt + 1: d - 2 = s + tt
+        for (int tt = 0; tt < S; ++tt) {
+#pragma unroll
+            for (int s = 0; s + tt < S; ++s)       // slices s + 1, tt + 1: d - 2 = s + tt
 #pragma unroll
                 for (int i = 0; i < 2; ++i)
-                    acc[s + tt][i] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[i], b[tt], acc[s + tt][i], 0, 0, 0);
+                    acc[s + tt][i] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[s][i], b[tt], acc[s + tt][i], 0, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);
+            b[tt] = bload(tt, stnext);
         }
     };
 
-    v4i_t r[S];
+    v4i_t r[NP];
+    v4i_t b[S];
     gload(0, r);
+#pragma unroll
+    for (int tt = 0; tt < S; ++tt) b[tt] = bload(tt, 0);
     lstore(ozl, r);
     __syncthreads();
     for (int64_t s = 0; s < nsteps; ++s) {
         const int cur = (int)(s & 1);
         gload(s + 1, r);
         __builtin_amdgcn_s_setprio(1);
-        mma(ozl + cur * kStage);
+        mma(ozl + cur * kStage, b, stepoff(s + 1));
         __builtin_amdgcn_s_setprio(0);
         __builtin_amdgcn_sched_barrier(0);
         lstore(ozl + (cur ^ 1) * kStage, r);
@@ -406,7 +425,7 @@ template <int S> int launch_slices(const OzOperand &o, int64_t Kq, uint8_t *P, i
 }
 
 template <int S> int launch_gemm(const OzParams &g, hipStream_t s) {
-    constexpr int kLds = 2 * (2 * S * 64 * 64);
+    constexpr int kLds = 2 * (S * 64 * 64);
     static bool attr_set = false;   // set once per process (every device takes the same value)
     if (!attr_set) {
         if (hipFuncSetAttribute(reinterpret_cast<const void *>(oz_gemm_kernel<S>),
