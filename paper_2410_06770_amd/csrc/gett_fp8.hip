@@ -289,16 +289,16 @@ __device__ __forceinline__ void fp8_store_block(uint8_t *s, int t, const u4_t (&
 // up in 6 / 4 registers (measured with an in-bounds probe: the order inside
 // a block does not change the result when A and B share it; the block of a
 // lane group must be its own).
-template <int BS, int FMT>
-__device__ __forceinline__ i8_t fp8_operand(const uint8_t *s, int r, int lane) {
-    const int g = lane >> 4, f = fp8_swz(r);
-    // chunks 2g and 2g + 1 (32 consecutive codes), or with E4M3 per 32:
-    // chunks g and 4 + g (positions 16 g .. and 64 + 16 g ..)
+// The 16-byte chunks a lane supplies: 2g and 2g + 1 (32 consecutive codes),
+// or with E4M3 per 32: g and 4 + g (positions 16 g .. and 64 + 16 g ..).
+template <int BS, int FMT> __device__ __forceinline__ int fp8_chunk(int g, int h) {
     constexpr bool halves = FMT == kElemE4M3 && BS == 32;
-    const int c0 = halves ? g : 2 * g, c1 = halves ? 4 + g : 2 * g + 1;
-    const uint8_t *row = s + r * 128;
-    const u4_t lo = *reinterpret_cast<const u4_t *>(row + 16 * (c0 ^ f));
-    const u4_t hi = *reinterpret_cast<const u4_t *>(row + 16 * (c1 ^ f));
+    return halves ? (h ? 4 + g : g) : 2 * g + h;
+}
+
+// A lane's 32 codes (one per byte, eight words) as the MFMA operand.
+template <int FMT>
+__device__ __forceinline__ i8_t fp8_pack(const u4_t &lo, const u4_t &hi) {
     const unsigned w[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
     if constexpr (FMT == kElemE4M3) {
         return i8_t{(int)w[0], (int)w[1], (int)w[2], (int)w[3],
@@ -331,6 +331,26 @@ __device__ __forceinline__ i8_t fp8_operand(const uint8_t *s, int r, int lane) {
         }
         return i8_t{(int)p[0], (int)p[1], (int)p[2], (int)p[3], (int)p[4], (int)p[5], 0, 0};
     }
+}
+
+// Operand registers of one lane.  E4M3: with one scale per 128 any split of
+// the block between lanes works as long as A and B share it, and each lane
+// takes 32 consecutive codes; with one scale per 32 the matrix core's block
+// b (of 32) must be the stored block b, so lane group g takes the stored
+// positions 16 g .. 16 g + 15 and 64 + 16 g .. 64 + 16 g + 15 (the halves
+// the core reads as k = 16 g .. and 64 + 16 g ..), and supplies the scale of
+// block g of its row.  E2M3 / E2M1: lane group g supplies the 32 positions
+// 32 g .. 32 g + 31, one block, packed 6 / 4 bits per code from the low bits
+// up in 6 / 4 registers (measured with an in-bounds probe: the order inside
+// a block does not change the result when A and B share it; the block of a
+// lane group must be its own).  From the swizzled LDS rows:
+template <int BS, int FMT>
+__device__ __forceinline__ i8_t fp8_operand(const uint8_t *s, int r, int lane) {
+    const int g = lane >> 4, f = fp8_swz(r);
+    const uint8_t *row = s + r * 128;
+    const u4_t lo = *reinterpret_cast<const u4_t *>(row + 16 * (fp8_chunk<BS, FMT>(g, 0) ^ f));
+    const u4_t hi = *reinterpret_cast<const u4_t *>(row + 16 * (fp8_chunk<BS, FMT>(g, 1) ^ f));
+    return fp8_pack<FMT>(lo, hi);
 }
 
 // One 128-block on the matrix cores: each wave's FM x FN fragments.  sE holds
@@ -367,6 +387,46 @@ __device__ __forceinline__ void fp8_mma_block(const uint8_t *sA, const uint8_t *
                                                                          FMT, 0, sb[j], 0, sa[i]);
 }
 
+// The direct-B form of one block: A's fragments and scales from LDS as above;
+// B's fragment j arrives as its lane's two 16-byte chunks of the code row
+// (bl[j], bh[j]) and its raw exponent bs[j], both loaded a block earlier
+// straight from the quantised rows; after fragment j's MFMAs its chunks and
+// exponent for block `next` are loaded into the same registers (behind a
+// scheduling barrier, so the registers are reused rather than renamed).
+// zero_b: this block is the pair's padding block (B scale E8M0 0).
+template <int FM, int FN, int WTM, int WTN, int BS, int FMT>
+__device__ __forceinline__ void fp8_mma_block_db(const uint8_t *sA, const int32_t *sE, int wm,
+                                                 int lane, f4_t (&acc)[FM][FN],
+                                                 u4_t (&bl)[FN], u4_t (&bh)[FN], int (&bs)[FN],
+                                                 bool zero_b, const uint8_t *brow,
+                                                 const int32_t *bexp, int64_t rstep,
+                                                 int64_t estep, int64_t next) {
+    constexpr int SUB = 128 / BS;
+    const int sub = BS == 128 ? 0 : (lane >> 4), g = lane >> 4;
+    i8_t a[FM];
+    int sa[FM];
+#pragma unroll
+    for (int i = 0; i < FM; ++i) {
+        const int r = wm * WTM + i * 16 + (lane & 15);
+        a[i] = fp8_operand<BS, FMT>(sA, r, lane);
+        sa[i] = sE[r * SUB + sub];
+    }
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+        const i8_t b = fp8_pack<FMT>(bl[j], bh[j]);
+        const int sb = zero_b ? 0 : bs[j] + 127;
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+            acc[i][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(b, a[i], acc[i][j], FMT,
+                                                                         FMT, 0, sb, 0, sa[i]);
+        __builtin_amdgcn_sched_barrier(0);
+        const uint8_t *p = brow + j * rstep + next * 128;
+        bl[j] = *reinterpret_cast<const u4_t *>(p + 16 * fp8_chunk<BS, FMT>(g, 0));
+        bh[j] = *reinterpret_cast<const u4_t *>(p + 16 * fp8_chunk<BS, FMT>(g, 1));
+        bs[j] = bexp[j * estep + next * SUB + sub];
+    }
+}
+
 // Whether the four N positions n .. n+3 of an M row are neighbours in C,
 // all inside N, and start on a 16-byte boundary (one vector access).
 __device__ __forceinline__ bool fp8_c_word(const float *C, const int64_t *__restrict__ offCN,
@@ -376,8 +436,10 @@ __device__ __forceinline__ bool fp8_c_word(const float *C, const int64_t *__rest
     return (reinterpret_cast<uintptr_t>(C + ocm + o0) & 15) == 0;
 }
 
-// C tile BM x BN, 4 waves as 2 x 2, each wave (BM/2) x (BN/2) in 16x16 fragments.
-template <int BM, int BN, int BS, int FMT>
+// C tile BM x BN, 4 waves as 2 x 2, each wave (BM/2) x (BN/2) in 16x16
+// fragments.  DB: B's fragments straight from the quantised rows into
+// registers (fp8_mma_block_db), only A staged through LDS.
+template <int BM, int BN, int BS, int FMT, bool DB>
 __global__ __launch_bounds__(256) void fp8_gemm_kernel(const uint8_t *__restrict__ QA,
                                                        const int32_t *__restrict__ EA,
                                                        const uint8_t *__restrict__ QB,
@@ -389,11 +451,12 @@ __global__ __launch_bounds__(256) void fp8_gemm_kernel(const uint8_t *__restrict
                                                        int tilesM, int tilesN) {
     constexpr int WTM = BM / 2, WTN = BN / 2, FM = WTM / 16, FN = WTN / 16;
     constexpr int CA = BM * 8 / 256, CB = BN * 8 / 256;   // 16-byte chunks per thread
+    constexpr int ER = DB ? BM : BM + BN;    // rows whose scales go through LDS
     __shared__ __align__(16) uint8_t sA[2][BM * 128];
-    __shared__ __align__(16) uint8_t sB[2][BN * 128];
+    __shared__ __align__(16) uint8_t sB[2][DB ? 16 : BN * 128];
     constexpr int SUB = 128 / BS;            // scales per row and 128-block
-    __shared__ __align__(16) int32_t sE[2][(BM + BN) * SUB];
-    static_assert(BM + BN <= 256 && 256 % (BM + BN) == 0, "one row of scales per thread");
+    __shared__ __align__(16) int32_t sE[2][ER * SUB];
+    static_assert(ER <= 256 && 256 % ER == 0, "one row of scales per thread");
 
     const int64_t nb = (K + 127) / 128;
     const int64_t Kp = nb * 128;
@@ -412,9 +475,10 @@ __global__ __launch_bounds__(256) void fp8_gemm_kernel(const uint8_t *__restrict
 #pragma unroll
         for (int j = 0; j < FN; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
 
-    // Thread t carries the scales of tile row t mod (BM + BN) (A rows, then B
-    // rows; with fewer rows than threads, two threads carry the same ones).
-    const int sidx = t % (BM + BN);
+    // Thread t carries the scales of tile row t mod ER (A rows, then B rows
+    // unless B comes straight from memory; with fewer rows than threads, two
+    // threads carry the same ones).
+    const int sidx = t % ER;
     const int32_t *ex = sidx < BM ? EA + (m0 + sidx) * nbs : EB + (n0 + sidx - BM) * nbs;
     typedef int i4s_t __attribute__((ext_vector_type(4)));
     // this row's exponents of block blk, as stored
@@ -437,41 +501,93 @@ __global__ __launch_bounds__(256) void fp8_gemm_kernel(const uint8_t *__restrict
     // number is odd, the last pair's second block is such a reload staged with
     // both E8M0 scales 0 (2^-127 each): its 128-term products, at most
     // 2^25 * 2^-254, fall below FP32's smallest denormal and add exactly zero.
-    u4_t ra[CA], rb[CB], ra2[CA], rb2[CB];
-    fp8_load_block<CA>(pa, Kp, 0, t, ra);
-    fp8_load_block<CB>(pb, Kp, 0, t, rb);
-    i4s_t xs = scales(0);
-    const int64_t b1 = nb > 1 ? 1 : 0;
-    fp8_load_block<CA>(pa, Kp, b1, t, ra2);
-    fp8_load_block<CB>(pb, Kp, b1, t, rb2);
-    i4s_t xs2 = scales(b1);
-    fp8_store_block<CA>(sA[0], t, ra);
-    fp8_store_block<CB>(sB[0], t, rb);
-    put_scales(sE[0], xs);
-    __syncthreads();
-    for (int64_t blk = 0; blk < nb; blk += 2) {
-        // even block: LDS stage 0, the next block waits in set 2
-        const int64_t n2 = blk + 2 < nb ? blk + 2 : nb - 1;
-        fp8_load_block<CA>(pa, Kp, n2, t, ra);
-        fp8_load_block<CB>(pb, Kp, n2, t, rb);
-        xs = scales(n2);
-        fp8_mma_block<FM, FN, WTM, WTN, BM, BS, FMT>(sA[0], sB[0], sE[0], wm, wn, lane, acc);
-        __builtin_amdgcn_sched_barrier(0);
-        fp8_store_block<CA>(sA[1], t, ra2);
-        fp8_store_block<CB>(sB[1], t, rb2);
-        put_scales(sE[1], blk + 1 < nb ? xs2 : kZeroScale);
-        __syncthreads();
-        // odd block: LDS stage 1, the next block waits in set 1
-        const int64_t n3 = blk + 3 < nb ? blk + 3 : nb - 1;
-        fp8_load_block<CA>(pa, Kp, n3, t, ra2);
-        fp8_load_block<CB>(pb, Kp, n3, t, rb2);
-        xs2 = scales(n3);
-        fp8_mma_block<FM, FN, WTM, WTN, BM, BS, FMT>(sA[1], sB[1], sE[1], wm, wn, lane, acc);
-        __builtin_amdgcn_sched_barrier(0);
+    if constexpr (!DB) {
+        u4_t ra[CA], rb[CB], ra2[CA], rb2[CB];
+        fp8_load_block<CA>(pa, Kp, 0, t, ra);
+        fp8_load_block<CB>(pb, Kp, 0, t, rb);
+        i4s_t xs = scales(0);
+        const int64_t b1 = nb > 1 ? 1 : 0;
+        fp8_load_block<CA>(pa, Kp, b1, t, ra2);
+        fp8_load_block<CB>(pb, Kp, b1, t, rb2);
+        i4s_t xs2 = scales(b1);
         fp8_store_block<CA>(sA[0], t, ra);
         fp8_store_block<CB>(sB[0], t, rb);
         put_scales(sE[0], xs);
         __syncthreads();
+        for (int64_t blk = 0; blk < nb; blk += 2) {
+            // even block: LDS stage 0, the next block waits in set 2
+            const int64_t n2 = blk + 2 < nb ? blk + 2 : nb - 1;
+            fp8_load_block<CA>(pa, Kp, n2, t, ra);
+            fp8_load_block<CB>(pb, Kp, n2, t, rb);
+            xs = scales(n2);
+            fp8_mma_block<FM, FN, WTM, WTN, BM, BS, FMT>(sA[0], sB[0], sE[0], wm, wn, lane, acc);
+            __builtin_amdgcn_sched_barrier(0);
+            fp8_store_block<CA>(sA[1], t, ra2);
+            fp8_store_block<CB>(sB[1], t, rb2);
+            put_scales(sE[1], blk + 1 < nb ? xs2 : kZeroScale);
+            __syncthreads();
+            // odd block: LDS stage 1, the next block waits in set 1
+            const int64_t n3 = blk + 3 < nb ? blk + 3 : nb - 1;
+            fp8_load_block<CA>(pa, Kp, n3, t, ra2);
+            fp8_load_block<CB>(pb, Kp, n3, t, rb2);
+            xs2 = scales(n3);
+            fp8_mma_block<FM, FN, WTM, WTN, BM, BS, FMT>(sA[1], sB[1], sE[1], wm, wn, lane, acc);
+            __builtin_amdgcn_sched_barrier(0);
+            fp8_store_block<CA>(sA[0], t, ra);
+            fp8_store_block<CB>(sB[0], t, rb);
+            put_scales(sE[0], xs);
+            __syncthreads();
+        }
+    } else {
+        // B rows of this wave's fragments: row n0 + wn WTN + 16 j + lane % 16,
+        // fragment j 16 rows (rstep bytes, estep exponents) after fragment 0
+        const int64_t rb0 = n0 + wn * WTN + (lane & 15);
+        const uint8_t *brow = QB + rb0 * Kp;
+        const int32_t *bexp = EB + rb0 * nbs;
+        const int64_t rstep = 16 * Kp, estep = 16 * nbs;
+        u4_t bl[FN], bh[FN];
+        int bs[FN];
+        const int g = lane >> 4, sub = BS == 128 ? 0 : g;
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+            const uint8_t *p = brow + j * rstep;
+            bl[j] = *reinterpret_cast<const u4_t *>(p + 16 * fp8_chunk<BS, FMT>(g, 0));
+            bh[j] = *reinterpret_cast<const u4_t *>(p + 16 * fp8_chunk<BS, FMT>(g, 1));
+            bs[j] = bexp[j * estep + sub];
+        }
+        u4_t ra[CA], ra2[CA];
+        fp8_load_block<CA>(pa, Kp, 0, t, ra);
+        i4s_t xs = scales(0);
+        const int64_t b1 = nb > 1 ? 1 : 0;
+        fp8_load_block<CA>(pa, Kp, b1, t, ra2);
+        i4s_t xs2 = scales(b1);
+        fp8_store_block<CA>(sA[0], t, ra);
+        put_scales(sE[0], xs);
+        __syncthreads();
+        for (int64_t blk = 0; blk < nb; blk += 2) {
+            // even block: A in LDS stage 0, B's block blk in registers
+            const int64_t n2 = blk + 2 < nb ? blk + 2 : nb - 1;
+            fp8_load_block<CA>(pa, Kp, n2, t, ra);
+            xs = scales(n2);
+            fp8_mma_block_db<FM, FN, WTM, WTN, BS, FMT>(sA[0], sE[0], wm, lane, acc, bl, bh, bs,
+                                                        false, brow, bexp, rstep, estep,
+                                                        blk + 1 < nb ? blk + 1 : nb - 1);
+            __builtin_amdgcn_sched_barrier(0);
+            fp8_store_block<CA>(sA[1], t, ra2);
+            put_scales(sE[1], blk + 1 < nb ? xs2 : kZeroScale);
+            __syncthreads();
+            // odd block: A in stage 1, B's block blk + 1 (the last block again,
+            // with both scales 0, when blk + 1 == nb)
+            const int64_t n3 = blk + 3 < nb ? blk + 3 : nb - 1;
+            fp8_load_block<CA>(pa, Kp, n3, t, ra2);
+            xs2 = scales(n3);
+            fp8_mma_block_db<FM, FN, WTM, WTN, BS, FMT>(sA[1], sE[1], wm, lane, acc, bl, bh, bs,
+                                                        blk + 1 >= nb, brow, bexp, rstep, estep, n2);
+            __builtin_amdgcn_sched_barrier(0);
+            fp8_store_block<CA>(sA[0], t, ra);
+            put_scales(sE[0], xs);
+            __syncthreads();
+        }
     }
     // C_in of this lane's outputs.  Lane l holds M row (l % 16) and the four
     // N positions 4 (l / 16) .. + 3 of each fragment; where those four are
@@ -545,13 +661,20 @@ template <int BS, int FMT> struct QuantRowsK {
     using F = decltype(&fp8_quant_rows_kernel<128, kElemE4M3>);
     static constexpr F f = &fp8_quant_rows_kernel<BS, FMT>;
 };
+// B straight from the code rows only for E2M3: there the LDS form's operand
+// packing took it to 257 registers (one workgroup per CU) and the direct form
+// fits two (strided workload 304 -> 326 TFLOP/s, CC 220 -> 263); for E4M3 and
+// E2M1 it measured slower (485 -> 392 and 415 -> 342 on the strided one): a
+// code row is not blocked, so one fragment load touches 16 cache lines.
+template <int FMT> constexpr bool fp8_direct_b() { return FMT == kElemE2M3; }
+
 template <int BS, int FMT> struct Gemm128K {
-    using F = decltype(&fp8_gemm_kernel<128, 128, 128, kElemE4M3>);
-    static constexpr F f = &fp8_gemm_kernel<128, 128, BS, FMT>;
+    using F = decltype(&fp8_gemm_kernel<128, 128, 128, kElemE4M3, false>);
+    static constexpr F f = &fp8_gemm_kernel<128, 128, BS, FMT, fp8_direct_b<FMT>()>;
 };
 template <int BS, int FMT> struct Gemm64K {
-    using F = decltype(&fp8_gemm_kernel<64, 64, 128, kElemE4M3>);
-    static constexpr F f = &fp8_gemm_kernel<64, 64, BS, FMT>;
+    using F = decltype(&fp8_gemm_kernel<64, 64, 128, kElemE4M3, false>);
+    static constexpr F f = &fp8_gemm_kernel<64, 64, BS, FMT, fp8_direct_b<FMT>()>;
 };
 
 }  // namespace
