@@ -1296,15 +1296,16 @@ static int run_ozaki(const Args &a, const double *A, const double *B, double *C,
     const int64_t *rowsA = pl->d_tab, *kA = rowsA + M, *rowsB = kA + K, *kB = rowsB + N;
     const int64_t *offCM = kB + K, *offCN = offCM + M;
     const int64_t Kq = round_up(K, 64), Mq = round_up(M, 64), Nq = round_up(N, 64);
-    int64_t S = (Kq + kOzMaxKSlice - 1) / kOzMaxKSlice;
-    int64_t per = round_up((Kq + S - 1) / S, 64);
-    S = (Kq + per - 1) / per;
+    // K slices of at most kOzMaxKSlice positions (the INT32 sums stay exact)
+    int64_t nks = (Kq + kOzMaxKSlice - 1) / kOzMaxKSlice;
+    const int64_t per = round_up((Kq + nks - 1) / nks, 64);
+    nks = (Kq + per - 1) / per;
     const int64_t tilesM = Mq / 64, tilesN = Nq / 64;
-    if (tilesM * tilesN * S > INT32_MAX) return GETT_ERR_INTERNAL;
+    if (tilesM * tilesN * nks > INT32_MAX) return GETT_ERR_INTERNAL;
     const int64_t planeA = Mq * Kq, planeB = Nq * Kq;
     const int64_t qbytes = round_up((int64_t)slices * (planeA + planeB), 256);
     const int64_t ebytes = round_up((Mq + Nq) * (int64_t)sizeof(int32_t), 256);
-    const int64_t wsb = S > 1 ? S * M * N * (int64_t)sizeof(double) : 0;
+    const int64_t wsb = nks > 1 ? nks * M * N * (int64_t)sizeof(double) : 0;
     void *ws = nullptr;
     if (work_alloc(&ws, (size_t)(qbytes + ebytes + wsb), s)) return GETT_ERR_ALLOC;
     uint8_t *QA = static_cast<uint8_t *>(ws);
@@ -1333,7 +1334,7 @@ static int run_ozaki(const Args &a, const double *A, const double *B, double *C,
         g.kPer = per;
         g.tilesM = (int32_t)tilesM;
         g.tilesN = (int32_t)tilesN;
-        g.splits = (int32_t)S;
+        g.splits = (int32_t)nks;
         g.C = C;
         g.offCM = offCM;
         g.offCN = offCN;
@@ -1342,7 +1343,7 @@ static int run_ozaki(const Args &a, const double *A, const double *B, double *C,
         g.ws = part;
         rc = launch_oz_gemm(slices, g, s);
     }
-    if (!rc && S > 1) {
+    if (!rc && nks > 1) {
         // C <- C_in + sum of the K slices' FP64 values, in slice order
         TileParams q{};
         q.C = C;
@@ -1350,7 +1351,7 @@ static int run_ozaki(const Args &a, const double *A, const double *B, double *C,
         q.offCN = offCN;
         q.M = M;
         q.N = N;
-        q.splits = (int32_t)S;
+        q.splits = (int32_t)nks;
         q.H = 1;
         q.ws = part;
         q.alpha[0] = q.beta[0] = 1.0;
