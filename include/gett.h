@@ -100,7 +100,9 @@ extern "C" {
    append to one file; a later line for a signature wins. */
 #define GETT_HEURISTIC 0   /* built-in rules (default) */
 #define GETT_PREDICT   1   /* MLP schedule predictor (gett_load_predictor) */
-#define GETT_AUTOTUNE  2   /* time the whole schedule menu on a plan-cache miss */
+#define GETT_AUTOTUNE  2   /* time the whole schedule menu on a plan-cache miss; among
+                              the re-timed schedules within 2 % of the fastest median,
+                              the one with the fewest modelled HBM bytes */
 
 /* Runtime error codes (> 0). */
 #define GETT_ERR_HIP      1
@@ -453,8 +455,9 @@ int64_t gett_addr_violations(int reset);
    The AUTOTUNE policy uses WARMUP 1, REPS 5.  times_us[id] receives the
    median of the re-timed ones,
    the single time of the others and -1 for invalid schedules; returns the
-   best id (>= 0), or -1 with *status set to a negative INFO or a positive
-   runtime error. */
+   id with the fastest median (>= 0; the AUTOTUNE policy's tie-break on
+   modelled traffic is not applied here), or -1 with *status set to a
+   negative INFO or a positive runtime error. */
 int64_t gett_autotune(int prec, int64_t ranka, const int64_t *exta, const int64_t *inca,
                       const void *A, int64_t rankb, const int64_t *extb, const int64_t *incb,
                       const void *B, int64_t conts, const int64_t *conta, const int64_t *contb,
