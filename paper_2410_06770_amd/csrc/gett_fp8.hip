@@ -428,11 +428,12 @@ __device__ __forceinline__ void fp8_mma_block_db(const uint8_t *sA, const int32_
 }
 
 // Whether the four N positions n .. n+3 of an M row are neighbours in C,
-// all inside N, and start on a 16-byte boundary (one vector access).
-__device__ __forceinline__ bool fp8_c_word(const float *C, const int64_t *__restrict__ offCN,
-                                           int64_t ocm, int64_t o0, int64_t n, int64_t N) {
+// all inside N, and start on a 16-byte boundary (one vector access); on is
+// the tile's staged N offsets from position n on.
+__device__ __forceinline__ bool fp8_c_word(const float *C, const int64_t *on, int64_t ocm,
+                                           int64_t o0, int64_t n, int64_t N) {
     if (n + 3 >= N) return false;
-    if (offCN[n + 1] != o0 + 1 || offCN[n + 2] != o0 + 2 || offCN[n + 3] != o0 + 3) return false;
+    if (on[1] != o0 + 1 || on[2] != o0 + 2 || on[3] != o0 + 3) return false;
     return (reinterpret_cast<uintptr_t>(C + ocm + o0) & 15) == 0;
 }
 
@@ -465,6 +466,18 @@ __global__ __launch_bounds__(256) void fp8_gemm_kernel(const uint8_t *__restrict
     tile_coords(xcd_remap(blockIdx.x, gridDim.x), tilesM, tilesN, tm, tn);
     const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6, wm = w >> 1, wn = w & 1;
+    // The tile's C offsets (M rows, then N positions), requested before the
+    // first block's codes and staged in LDS at the first barrier: the
+    // epilogue then waits for C_in alone, not for the offset tables first.
+    __shared__ int64_t sOff[BM + BN];
+    static_assert(BM + BN <= 256, "one offset per thread");
+    int64_t myOff = 0;
+    if (t < BM) {
+        if (m0 + t < M) myOff = offCM[m0 + t];
+    } else if (t < BM + BN) {
+        if (n0 + t - BM < N) myOff = offCN[n0 + t - BM];
+    }
+    auto put_offs = [&]() { if (t < BM + BN) sOff[t] = myOff; };
 
     // Rows are padded to a multiple of 128 in both operands, so every tile
     // row exists in the quantised buffers.
@@ -513,6 +526,7 @@ __global__ __launch_bounds__(256) void fp8_gemm_kernel(const uint8_t *__restrict
         fp8_store_block<CA>(sA[0], t, ra);
         fp8_store_block<CB>(sB[0], t, rb);
         put_scales(sE[0], xs);
+        put_offs();
         __syncthreads();
         for (int64_t blk = 0; blk < nb; blk += 2) {
             // even block: LDS stage 0, the next block waits in set 2
@@ -563,6 +577,7 @@ __global__ __launch_bounds__(256) void fp8_gemm_kernel(const uint8_t *__restrict
         i4s_t xs2 = scales(b1);
         fp8_store_block<CA>(sA[0], t, ra);
         put_scales(sE[0], xs);
+        put_offs();
         __syncthreads();
         for (int64_t blk = 0; blk < nb; blk += 2) {
             // even block: A in LDS stage 0, B's block blk in registers
@@ -597,20 +612,23 @@ __global__ __launch_bounds__(256) void fp8_gemm_kernel(const uint8_t *__restrict
     const int lm = lane & 15, ln = 4 * (lane >> 4);
 #pragma unroll
     for (int i = 0; i < FM; ++i) {
-        const int64_t m = m0 + wm * WTM + i * 16 + lm;
-        const int64_t ocm = m < M ? offCM[m] : 0;
+        const int ml = wm * WTM + i * 16 + lm;
+        const int64_t m = m0 + ml;
+        const int64_t ocm = sOff[ml];
 #pragma unroll
         for (int j = 0; j < FN; ++j) {
-            const int64_t n = n0 + wn * WTN + j * 16 + ln;
+            const int nl = wn * WTN + j * 16 + ln;
+            const int64_t n = n0 + nl;
+            const int64_t *on = sOff + BM + nl;
             f4_t x = f4_t{0.f, 0.f, 0.f, 0.f};
             if (m < M) {
-                const int64_t o0 = n < N ? offCN[n] : 0;
-                if (fp8_c_word(C, offCN, ocm, o0, n, N)) {
+                const int64_t o0 = on[0];
+                if (fp8_c_word(C, on, ocm, o0, n, N)) {
                     x = *reinterpret_cast<const f4_t *>(C + ocm + o0);
                 } else {
 #pragma unroll
                     for (int v = 0; v < 4; ++v)
-                        if (n + v < N) x[v] = C[ocm + offCN[n + v]];
+                        if (n + v < N) x[v] = C[ocm + on[v]];
                 }
             }
             cin[i][j] = x;
@@ -619,21 +637,24 @@ __global__ __launch_bounds__(256) void fp8_gemm_kernel(const uint8_t *__restrict
     // add and store
 #pragma unroll
     for (int i = 0; i < FM; ++i) {
-        const int64_t m = m0 + wm * WTM + i * 16 + lm;
+        const int ml = wm * WTM + i * 16 + lm;
+        const int64_t m = m0 + ml;
         if (m >= M) continue;
-        const int64_t ocm = offCM[m];
+        const int64_t ocm = sOff[ml];
 #pragma unroll
         for (int j = 0; j < FN; ++j) {
-            const int64_t n = n0 + wn * WTN + j * 16 + ln;
+            const int nl = wn * WTN + j * 16 + ln;
+            const int64_t n = n0 + nl;
             if (n >= N) continue;
-            const int64_t o0 = offCN[n];
+            const int64_t *on = sOff + BM + nl;
+            const int64_t o0 = on[0];
             const f4_t y = cin[i][j] + acc[i][j];
-            if (fp8_c_word(C, offCN, ocm, o0, n, N)) {
+            if (fp8_c_word(C, on, ocm, o0, n, N)) {
                 *reinterpret_cast<f4_t *>(C + ocm + o0) = y;
             } else {
 #pragma unroll
                 for (int v = 0; v < 4; ++v)
-                    if (n + v < N) C[ocm + offCN[n + v]] = y[v];
+                    if (n + v < N) C[ocm + on[v]] = y[v];
             }
         }
     }
