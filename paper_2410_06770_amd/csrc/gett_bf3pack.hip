@@ -276,10 +276,33 @@ __device__ __forceinline__ void pk_mma(const uint16_t *sA, const uint16_t *sB, i
 // column of fragments at a time, its C_in read before any of it is written
 // (a store to C could alias a later load of C, so loads interleaved with
 // stores would wait out one another).
+// The tile's C offsets (its M rows, then its N positions), one per thread,
+// requested at kernel start and staged in LDS at the first barrier: the
+// epilogue then waits for C_in alone instead of for the offset tables first.
+// Split-K partials address the workspace directly and skip them.
+template <int BM, int BN>
+struct PkCOffs {
+    int64_t v = 0;
+    __device__ __forceinline__ void load(const Bf3Packed &g, int64_t m0, int64_t n0, int t) {
+        if (g.ws) return;
+        if (t < BM) {
+            if (m0 + t < g.M) v = g.offCM[m0 + t];
+        } else if (t < BM + BN) {
+            if (n0 + t - BM < g.N) v = g.offCN[n0 + t - BM];
+        }
+    }
+    __device__ __forceinline__ void put(int64_t *s, int t) const {
+        if (t < BM + BN) s[t] = v;
+    }
+};
+
 template <int FM, int FN>
 __device__ __forceinline__ void pk_epilogue(const Bf3Packed &g, const f4_t (&acc)[FM][FN],
-                                            int64_t mw, int64_t nw, int lane, int split) {
+                                            int64_t m0, int64_t n0, int mwl, int nwl, int lane,
+                                            int split, const int64_t *sOffM,
+                                            const int64_t *sOffN) {
     float *__restrict__ C = g.C;
+    const int64_t mw = m0 + mwl, nw = n0 + nwl;
     if (g.ws) {
 #pragma unroll
         for (int j = 0; j < FN; ++j) {
@@ -298,9 +321,10 @@ __device__ __forceinline__ void pk_epilogue(const Bf3Packed &g, const f4_t (&acc
     const bool rdC = g.beta != 0.0;
 #pragma unroll
     for (int j = 0; j < FN; ++j) {
-        const int64_t n = nw + j * 16 + (lane & 15);
+        const int nl = nwl + j * 16 + (lane & 15);
+        const int64_t n = n0 + nl;
         const bool nok = n < g.N;
-        const int64_t ocn = nok ? g.offCN[n] : 0;
+        const int64_t ocn = sOffN[nl];
         int64_t off[FM][4];
         bool ok[FM][4];
         float cin[FM][4];
@@ -308,9 +332,10 @@ __device__ __forceinline__ void pk_epilogue(const Bf3Packed &g, const f4_t (&acc
         for (int i = 0; i < FM; ++i)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int64_t m = mw + i * 16 + 4 * (lane >> 4) + v;
+                const int ml = mwl + i * 16 + 4 * (lane >> 4) + v;
+                const int64_t m = m0 + ml;
                 ok[i][v] = nok && m < g.M;
-                off[i][v] = ok[i][v] ? g.offCM[m] + ocn : 0;
+                off[i][v] = ok[i][v] ? sOffM[ml] + ocn : 0;
                 cin[i][v] = (rdC && ok[i][v]) ? C[off[i][v]] : 0.0f;
             }
 #pragma unroll
@@ -351,6 +376,10 @@ __global__ __launch_bounds__(256) void bf3_packed_gemm_kernel(Bf3Packed g) {
     const int64_t nsteps = (kend - kbeg) / 32;
 
     const int t = threadIdx.x, lane = t & 63, w = t >> 6, wm = w >> 1, wn = w & 1;
+    __shared__ int64_t sOff[BM + BN];
+    static_assert(BM + BN <= 256, "one C offset per thread");
+    PkCOffs<BM, BN> co;
+    co.load(g, m0, n0, t);
     PkLoad<BM> la;
     PkLoad<BN> lb;
     la.init(t, g.Kq);
@@ -374,6 +403,7 @@ __global__ __launch_bounds__(256) void bf3_packed_gemm_kernel(Bf3Packed g) {
         lb.load(bH + step(1), bL + step(1), rb1);
         la.store(sA, ra0);
         lb.store(sB, rb0);
+        co.put(sOff, t);
         __syncthreads();
         for (int64_t s = 0; s < nsteps; s += 2) {
             // even step: LDS stage 0, set 1 waits for stage 1
@@ -406,6 +436,7 @@ __global__ __launch_bounds__(256) void bf3_packed_gemm_kernel(Bf3Packed g) {
         lb.load(bH, bL, rb);
         la.store(sA, ra);
         lb.store(sB, rb);
+        co.put(sOff, t);
         __syncthreads();
         for (int64_t s = 0; s < nsteps; ++s) {
             const int cur = (int)(s & 1);
@@ -422,7 +453,8 @@ __global__ __launch_bounds__(256) void bf3_packed_gemm_kernel(Bf3Packed g) {
         }
     }
 
-    pk_epilogue<FM, FN>(g, acc, m0 + wm * Cfg::WTM, n0 + wn * Cfg::WTN, lane, split);
+    pk_epilogue<FM, FN>(g, acc, m0, n0, wm * Cfg::WTM, wn * Cfg::WTN, lane, split, sOff,
+                        sOff + BM);
 }
 
 // The large tiles: 8 waves (512 threads) as 2 x 4, each wave (BM / 2) x
@@ -492,6 +524,10 @@ __global__ __launch_bounds__(512) void bf3_packed_gemm8_kernel(Bf3Packed g) {
     const int64_t nsteps = (kend - kbeg) / 32;
 
     const int t = threadIdx.x, lane = t & 63, w = t >> 6, wm = w >> 2, wn = w & 3;
+    __shared__ int64_t sOff[BM + BN];
+    static_assert(BM + BN <= 512, "one C offset per thread");
+    PkCOffs<BM, BN> co;
+    co.load(g, m0, n0, t);
     PkLoad8<BM> la;
     PkLoad8<BN> lb;
     la.init(t, g.Kq);
@@ -538,6 +574,7 @@ __global__ __launch_bounds__(512) void bf3_packed_gemm8_kernel(Bf3Packed g) {
         lb.load(bH, bL, rb);
         la.store(sA, ra);
         lb.store(sB, rb);
+        co.put(sOff, t);
         __syncthreads();
         for (int64_t s = 0; s < nsteps; ++s) {
             const int cur = (int)(s & 1);
@@ -599,6 +636,7 @@ __global__ __launch_bounds__(512) void bf3_packed_gemm8_kernel(Bf3Packed g) {
         la.load(aH, aL, ra);
         bload(0, bh, blo);
         la.store(sA, ra);
+        co.put(sOff, t);
         __syncthreads();
         for (int64_t s = 0; s < nsteps; ++s) {
             const int cur = (int)(s & 1);
@@ -613,7 +651,8 @@ __global__ __launch_bounds__(512) void bf3_packed_gemm8_kernel(Bf3Packed g) {
         }
     }
 
-    pk_epilogue<FM, FN>(g, acc, m0 + wm * Cfg::WTM, n0 + wn * Cfg::WTN, lane, split);
+    pk_epilogue<FM, FN>(g, acc, m0, n0, wm * Cfg::WTM, wn * Cfg::WTN, lane, split, sOff,
+                        sOff + BM);
 }
 
 // ---------------------------------------------------------------------------
