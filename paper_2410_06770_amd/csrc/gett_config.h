@@ -29,6 +29,7 @@ constexpr int prec_bytes(int prec) {
 }
 
 constexpr int kThreads = 256;       // 4 waves of 64 per workgroup
+constexpr int kLdsPerCu = 160 * 1024;   // LDS of one CU (gfx950)
 constexpr int kNumTiles = 5;        // tile menu size per precision
 constexpr int kNumOrders = 4;
 constexpr int kNumSplits = 4;       // split-K options: 1, 2, 4 slices, or "fill"

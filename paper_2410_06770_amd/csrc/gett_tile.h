@@ -372,6 +372,29 @@ template <int PREC, int BM, int BN, int BK> struct TileCfg {
     static constexpr int kStageBytes = LA::kBytes + LB::kBytes;
     static constexpr int kLdsBytes = 2 * kStageBytes;
     static_assert(BK % (PREC == kBF3 ? 32 : 4) == 0, "BK");
+    // The tile's C offsets (BM + BN of them) can sit in LDS after the two
+    // stages; the tile kernel stages them there when that leaves the number
+    // of workgroups a CU's 160 KB of LDS holds unchanged.
+    static constexpr int kCOffBytes = (BM + BN) * 8;
+    static_assert(kLdsBytes % 8 == 0 && BM + BN <= kThreads, "C offset staging");
+    static constexpr bool kCOffFree =
+        kLdsPerCu / (kLdsBytes + kCOffBytes) == kLdsPerCu / kLdsBytes;
+    static constexpr int kLaunchLds = kLdsBytes + (kCOffFree ? kCOffBytes : 0);
+};
+
+// LDS of the batch kernel: the larger of its two tiles' stages, plus room
+// for the C offsets when that costs no workgroup per CU.
+template <int PREC> struct BatchLds {
+    using C0 = TileCfg<PREC, kTiles[PREC][kBatchTile[PREC][0]].bm, kTiles[PREC][kBatchTile[PREC][0]].bn,
+                       kTiles[PREC][kBatchTile[PREC][0]].bk>;
+    using C1 = TileCfg<PREC, kTiles[PREC][kBatchTile[PREC][1]].bm, kTiles[PREC][kBatchTile[PREC][1]].bn,
+                       kTiles[PREC][kBatchTile[PREC][1]].bk>;
+    static constexpr int kBase = C0::kLdsBytes > C1::kLdsBytes ? C0::kLdsBytes : C1::kLdsBytes;
+    static constexpr int kWith0 = C0::kLdsBytes + C0::kCOffBytes;
+    static constexpr int kWith1 = C1::kLdsBytes + C1::kCOffBytes;
+    static constexpr int kWith = kWith0 > kWith1 ? kWith0 : kWith1;
+    static constexpr bool kCOff = kLdsPerCu / kWith == kLdsPerCu / kBase;
+    static constexpr int kBytes = kCOff ? kWith : kBase;
 };
 
 // MFMA work of one staged K step for the FP64/FP32 tiles that load two
@@ -452,7 +475,7 @@ __device__ __forceinline__ void mma_stage_split(f4_t (&acc)[BM / 32][BN / 32],
 // pA and pB and updating C at pC (the call's pointers, moved to a Hadamard
 // position when there is one); `slice` numbers the tile's FP64 partial-sum
 // slab when K is split.
-template <int PREC, int BM, int BN, int BK, bool AFK, bool BFK, bool O32 = false>
+template <int PREC, int BM, int BN, int BK, bool AFK, bool BFK, bool O32 = false, bool CO = false>
 __device__ __forceinline__ void gett_tile(const TileParams &p, const void *pA, const void *pB,
                                           void *pC, int64_t m0, int64_t n0, int64_t kbeg,
                                           int64_t kend, int split, unsigned char *smem) {
@@ -473,6 +496,27 @@ __device__ __forceinline__ void gett_tile(const TileParams &p, const void *pA, c
     const int lane = lane_id();
     const int w = wave_id();
     const int wm = w >> 1, wn = w & 1;
+
+    // CO: the tile's C offsets (its M rows, then its N positions) are
+    // requested here and staged in LDS after the operand stages at the first
+    // barrier, so the epilogue waits for C_in alone instead of for the offset
+    // tables first.  K-split partials address the workspace and skip them.
+    int64_t *const sCOff = reinterpret_cast<int64_t *>(smem + Cfg::kLdsBytes);
+    int64_t myCOff = 0;
+    if constexpr (CO) {
+        if (!p.ws) {
+            if (t < BM) {
+                if (m0 + t < p.M) myCOff = p.offCM[m0 + t];
+            } else if (t < BM + BN) {
+                if (n0 + t - BM < p.N) myCOff = p.offCN[n0 + t - BM];
+            }
+        }
+    }
+    auto put_coffs = [&]() {
+        if constexpr (CO) {
+            if (t < BM + BN) sCOff[t] = myCOff;
+        }
+    };
 
     Gather<PREC, BM, BK, AFK, O32> ga;
     Gather<PREC, BN, BK, BFK, O32> gb;
@@ -526,6 +570,7 @@ __device__ __forceinline__ void gett_tile(const TileParams &p, const void *pA, c
         gb.load_koffs(p.offBK, kfirst + BK);
         ga.store(stageA(0), va);
         gb.store(stageB(0), vb);
+        put_coffs();
         __syncthreads();
 
         // One K step: issue the next step's loads first (they land while the
@@ -667,6 +712,7 @@ __device__ __forceinline__ void gett_tile(const TileParams &p, const void *pA, c
         gb.template load_with<true>(kob, kfirst + BK, kbeg, vb2);
         ga.store(stageA(0), va);
         gb.store(stageB(0), vb);
+        put_coffs();
         __syncthreads();
 
         for (int64_t s = 0; s < nsteps; s += 2) {
@@ -747,9 +793,10 @@ __device__ __forceinline__ void gett_tile(const TileParams &p, const void *pA, c
     static_assert(FM % EG == 0, "whole groups");
 #pragma unroll
     for (int j = 0; j < FN; ++j) {
-        const int64_t n = n0 + wn * Cfg::WTN + j * 16 + (lane & 15);
+        const int nl = wn * Cfg::WTN + j * 16 + (lane & 15);
+        const int64_t n = n0 + nl;
         const bool nok = n < p.N;
-        const int64_t ocn = p.offCN[n];
+        const int64_t ocn = CO ? sCOff[BM + nl] : p.offCN[n];
 #pragma unroll
         for (int i0 = 0; i0 < FM; i0 += EG) {
             int64_t off[EG][4];
@@ -760,9 +807,10 @@ __device__ __forceinline__ void gett_tile(const TileParams &p, const void *pA, c
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int rr = kF64Layout ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v;
-                    const int64_t m = m0 + wm * Cfg::WTM + (i0 + e) * 16 + rr;
+                    const int ml = wm * Cfg::WTM + (i0 + e) * 16 + rr;
+                    const int64_t m = m0 + ml;
                     ok[e][v] = nok && m < p.M;
-                    off[e][v] = ok[e][v] ? p.offCM[m] + ocn : 0;
+                    off[e][v] = ok[e][v] ? (CO ? sCOff[ml] : p.offCM[m]) + ocn : 0;
 #ifdef GETT_ADDR_CHECK
                     if (ok[e][v]) ok[e][v] = gett_check_c(off[e][v], p.cLo, p.cSpan);
 #endif
@@ -831,7 +879,8 @@ __global__ __launch_bounds__(kThreads) void gett_tile_kernel(TileParams p) {
         B += p.offBH[h];
         C += p.offCH[h];
     }
-    gett_tile<PREC, BM, BN, BK, AFK, BFK, O32>(p, A, B, C, (int64_t)tm * BM, (int64_t)tn * BN,
+    gett_tile<PREC, BM, BN, BK, AFK, BFK, O32, TileCfg<PREC, BM, BN, BK>::kCOffFree>(
+        p, A, B, C, (int64_t)tm * BM, (int64_t)tn * BN,
                                                kbeg, kend, h * p.splits + split, smem);
 }
 
@@ -911,13 +960,17 @@ __device__ __forceinline__ void batch_item(const TileParams &p, int aFastK, int 
     const int64_t kend = min(p.K, kbeg + p.kPerSplit);
     const int variant = aFastK * 2 + bFastK;
     if (variant == 0)
-        gett_tile<PREC, ts.bm, ts.bn, ts.bk, false, false>(p, p.A, p.B, p.C, m0, n0, kbeg, kend, split, smem);
+        gett_tile<PREC, ts.bm, ts.bn, ts.bk, false, false, false, BatchLds<PREC>::kCOff>(
+            p, p.A, p.B, p.C, m0, n0, kbeg, kend, split, smem);
     else if (variant == 1)
-        gett_tile<PREC, ts.bm, ts.bn, ts.bk, false, true>(p, p.A, p.B, p.C, m0, n0, kbeg, kend, split, smem);
+        gett_tile<PREC, ts.bm, ts.bn, ts.bk, false, true, false, BatchLds<PREC>::kCOff>(
+            p, p.A, p.B, p.C, m0, n0, kbeg, kend, split, smem);
     else if (variant == 2)
-        gett_tile<PREC, ts.bm, ts.bn, ts.bk, true, false>(p, p.A, p.B, p.C, m0, n0, kbeg, kend, split, smem);
+        gett_tile<PREC, ts.bm, ts.bn, ts.bk, true, false, false, BatchLds<PREC>::kCOff>(
+            p, p.A, p.B, p.C, m0, n0, kbeg, kend, split, smem);
     else
-        gett_tile<PREC, ts.bm, ts.bn, ts.bk, true, true>(p, p.A, p.B, p.C, m0, n0, kbeg, kend, split, smem);
+        gett_tile<PREC, ts.bm, ts.bn, ts.bk, true, true, false, BatchLds<PREC>::kCOff>(
+            p, p.A, p.B, p.C, m0, n0, kbeg, kend, split, smem);
 }
 
 template <int PREC>
@@ -978,13 +1031,13 @@ static int launch_one(const TileParams &p, hipStream_t s) {
     if (!attr_set) {
         if (hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                 hipFuncAttributeMaxDynamicSharedMemorySize,
-                                Cfg::kLdsBytes) != hipSuccess)
+                                Cfg::kLaunchLds) != hipSuccess)
             return GETT_ERR_HIP;
         attr_set = true;
     }
     const int total = p.tilesM * p.tilesN * p.splits * p.H;
     (void)hipGetLastError();   // clear a stale error left by other HIP users
-    hipLaunchKernelGGL(kern, dim3(total), dim3(kThreads), Cfg::kLdsBytes, s, p);
+    hipLaunchKernelGGL(kern, dim3(total), dim3(kThreads), Cfg::kLaunchLds, s, p);
     return launch_status();
 }
 
@@ -1024,13 +1077,7 @@ static int launch_prec(int tile, bool afk, bool bfk, const TileParams &p, hipStr
     return GETT_ERR_INTERNAL;
 }
 
-template <int PREC> static int batch_lds() {
-    constexpr TileShape t0 = kTiles[PREC][kBatchTile[PREC][0]];
-    constexpr TileShape t1 = kTiles[PREC][kBatchTile[PREC][1]];
-    constexpr int l0 = TileCfg<PREC, t0.bm, t0.bn, t0.bk>::kLdsBytes;
-    constexpr int l1 = TileCfg<PREC, t1.bm, t1.bn, t1.bk>::kLdsBytes;
-    return l0 > l1 ? l0 : l1;
-}
+template <int PREC> static int batch_lds() { return BatchLds<PREC>::kBytes; }
 
 template <int PREC> static int launch_splitk_reduce_prec(const TileParams &p, hipStream_t s) {
     const int64_t MN = p.M * p.N * p.H;
