@@ -289,6 +289,27 @@ __global__ __launch_bounds__(512) void oz_gemm_kernel(OzParams g) {
     const int64_t nsteps = (kend - kbeg) / kOzBK;
 
     const int t = threadIdx.x, lane = t & 63, w = t >> 6, wm = w >> 2, wn = w & 3;
+    // The tile's C offsets and scale exponents (its M rows, then its N
+    // positions), requested at kernel start and staged in LDS at the first
+    // barrier: the epilogue then waits for C_in alone.  Split-K partials
+    // address the workspace directly and take no C offsets.
+    __shared__ int64_t sOff[kOzBM + kOzBN];
+    __shared__ int sExp[kOzBM + kOzBN];
+    int64_t myOff = 0;
+    int myExp = 0;
+    if (t < kOzBM) {
+        const int64_t m = m0 + t;
+        if (m < g.M) {
+            myExp = max(g.EA[m], -4000);             // all-zero rows: any exponent
+            if (!g.ws) myOff = g.offCM[m];
+        }
+    } else if (t < kOzBM + kOzBN) {
+        const int64_t n = n0 + t - kOzBM;
+        if (n < g.N) {
+            myExp = max(g.EB[n], -4000);
+            if (!g.ws) myOff = g.offCN[n];
+        }
+    }
     // staging of A: thread t moves chunk (t & 3) of row (t >> 2) & 63 of
     // slice plane 2 i + (t >> 8), i < NP (past S in the last pass of odd S:
     // nothing)
@@ -362,6 +383,10 @@ __global__ __launch_bounds__(512) void oz_gemm_kernel(OzParams g) {
 #pragma unroll
     for (int tt = 0; tt < S; ++tt) b[tt] = bload(tt, 0);
     lstore(ozl, r);
+    if (t < kOzBM + kOzBN) {
+        sOff[t] = myOff;
+        sExp[t] = myExp;
+    }
     __syncthreads();
     for (int64_t s = 0; s < nsteps; ++s) {
         const int cur = (int)(s & 1);
@@ -377,10 +402,11 @@ __global__ __launch_bounds__(512) void oz_gemm_kernel(OzParams g) {
     // Epilogue: fragment i, register v of lane l holds M row 4 (l / 16) + v
     // and N column l % 16.  Combination in double from the smallest scale up.
     double *__restrict__ C = g.C;
-    const int64_t n = n0 + wn * 16 + (lane & 15);
+    const int nl = wn * 16 + (lane & 15);
+    const int64_t n = n0 + nl;
     const bool nok = n < g.N;
-    const int eb = nok ? max(g.EB[n], -4000) : 0;   // all-zero rows: any exponent
-    const int64_t ocn = nok ? g.offCN[n] : 0;
+    const int eb = sExp[kOzBM + nl];
+    const int64_t ocn = sOff[kOzBM + nl];
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
         double val[4], cin[4];
@@ -388,9 +414,10 @@ __global__ __launch_bounds__(512) void oz_gemm_kernel(OzParams g) {
         bool ok[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int64_t m = m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + v;
+            const int ml = wm * 32 + i * 16 + 4 * (lane >> 4) + v;
+            const int64_t m = m0 + ml;
             ok[v] = nok && m < g.M;
-            const int ea = ok[v] ? max(g.EA[m], -4000) : 0;
+            const int ea = ok[v] ? sExp[ml] : 0;
             double x = 0.0;
 #pragma unroll
             for (int d = S - 1; d >= 0; --d) x += ldexp((double)acc[d][i][v], ea + eb - 7 * (d + 2));
@@ -400,7 +427,7 @@ __global__ __launch_bounds__(512) void oz_gemm_kernel(OzParams g) {
                 ok[v] = false;
                 continue;
             }
-            off[v] = ok[v] ? g.offCM[m] + ocn : 0;
+            off[v] = ok[v] ? sOff[ml] + ocn : 0;
             cin[v] = ok[v] ? C[off[v]] : 0.0;
         }
 #pragma unroll
