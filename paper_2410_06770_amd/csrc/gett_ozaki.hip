@@ -407,33 +407,37 @@ __global__ __launch_bounds__(512) void oz_gemm_kernel(OzParams g) {
     const bool nok = n < g.N;
     const int eb = sExp[kOzBM + nl];
     const int64_t ocn = sOff[kOzBM + nl];
+    // Every value and C_in of the lane first (one round trip for C_in), then
+    // the stores.
+    double val[2][4], cin[2][4];
+    int64_t off[2][4];
+    bool ok[2][4];
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-        double val[4], cin[4];
-        int64_t off[4];
-        bool ok[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int ml = wm * 32 + i * 16 + 4 * (lane >> 4) + v;
             const int64_t m = m0 + ml;
-            ok[v] = nok && m < g.M;
-            const int ea = ok[v] ? sExp[ml] : 0;
+            ok[i][v] = nok && m < g.M;
+            const int ea = ok[i][v] ? sExp[ml] : 0;
             double x = 0.0;
 #pragma unroll
             for (int d = S - 1; d >= 0; --d) x += ldexp((double)acc[d][i][v], ea + eb - 7 * (d + 2));
-            val[v] = x;
+            val[i][v] = x;
             if (g.ws) {
-                if (ok[v]) g.ws[((int64_t)split * g.M + m) * g.N + n] = x;
-                ok[v] = false;
+                if (ok[i][v]) g.ws[((int64_t)split * g.M + m) * g.N + n] = x;
+                ok[i][v] = false;
                 continue;
             }
-            off[v] = ok[v] ? sOff[ml] + ocn : 0;
-            cin[v] = ok[v] ? C[off[v]] : 0.0;
+            off[i][v] = ok[i][v] ? sOff[ml] + ocn : 0;
+            cin[i][v] = ok[i][v] ? C[off[i][v]] : 0.0;
         }
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-            if (ok[v]) C[off[v]] = cin[v] + val[v];
-    }
+            if (ok[i][v]) C[off[i][v]] = cin[i][v] + val[i][v];
 }
 
 template <int S> int launch_slices(const OzOperand &o, int64_t Kq, uint8_t *P, int64_t plane,
