@@ -380,6 +380,13 @@ template <int PREC, int BM, int BN, int BK> struct TileCfg {
     static constexpr bool kCOffFree =
         kLdsPerCu / (kLdsBytes + kCOffBytes) == kLdsPerCu / kLdsBytes;
     static constexpr int kLaunchLds = kLdsBytes + (kCOffFree ? kCOffBytes : 0);
+    // BF16x3 tiles for which that room would cost a workgroup keep the
+    // offsets in the last 16 bytes of each row of stage 0's A hi plane
+    // (columns BK .. BK + 7, which neither the stores nor the MFMA reads
+    // touch): two a row, room for 2 BM of them.
+    static constexpr bool kCOffPad = !kCOffFree && PREC == kBF3 && BN <= BM;
+    // where the tile kernel stages its C offsets (kCOffNone / kCOffAfter / kCOffInPad)
+    static constexpr int kCOffMode = kCOffFree ? 1 : (kCOffPad ? 2 : 0);
 };
 
 // LDS of the batch kernel: the larger of its two tiles' stages, plus room
@@ -475,7 +482,7 @@ __device__ __forceinline__ void mma_stage_split(f4_t (&acc)[BM / 32][BN / 32],
 // pA and pB and updating C at pC (the call's pointers, moved to a Hadamard
 // position when there is one); `slice` numbers the tile's FP64 partial-sum
 // slab when K is split.
-template <int PREC, int BM, int BN, int BK, bool AFK, bool BFK, bool O32 = false, bool CO = false>
+template <int PREC, int BM, int BN, int BK, bool AFK, bool BFK, bool O32 = false, int COM = 0>
 __device__ __forceinline__ void gett_tile(const TileParams &p, const void *pA, const void *pB,
                                           void *pC, int64_t m0, int64_t n0, int64_t kbeg,
                                           int64_t kend, int split, unsigned char *smem) {
@@ -497,11 +504,19 @@ __device__ __forceinline__ void gett_tile(const TileParams &p, const void *pA, c
     const int w = wave_id();
     const int wm = w >> 1, wn = w & 1;
 
-    // CO: the tile's C offsets (its M rows, then its N positions) are
-    // requested here and staged in LDS after the operand stages at the first
-    // barrier, so the epilogue waits for C_in alone instead of for the offset
-    // tables first.  K-split partials address the workspace and skip them.
-    int64_t *const sCOff = reinterpret_cast<int64_t *>(smem + Cfg::kLdsBytes);
+    // COM 1 or 2: the tile's C offsets (its M rows, then its N positions)
+    // are requested here and staged in LDS at the first barrier, after the
+    // operand stages (1) or in the BF16x3 rows' unused tail bytes (2), so the
+    // epilogue waits for C_in alone instead of for the offset tables first.
+    // K-split partials address the workspace and skip them.
+    constexpr bool CO = COM != 0;
+    static_assert(COM != 2 || (PREC == kBF3 && BN <= BM), "row tails hold 2 BM offsets");
+    auto coff = [&](int i) -> int64_t & {
+        if constexpr (COM == 2)
+            return reinterpret_cast<int64_t *>(smem + (i >> 1) * (Cfg::LA::kLd * 2) + BK * 2)[i & 1];
+        else
+            return reinterpret_cast<int64_t *>(smem + Cfg::kLdsBytes)[i];
+    };
     int64_t myCOff = 0;
     if constexpr (CO) {
         if (!p.ws) {
@@ -514,7 +529,7 @@ __device__ __forceinline__ void gett_tile(const TileParams &p, const void *pA, c
     }
     auto put_coffs = [&]() {
         if constexpr (CO) {
-            if (t < BM + BN) sCOff[t] = myCOff;
+            if (t < BM + BN) coff(t) = myCOff;
         }
     };
 
@@ -796,7 +811,7 @@ __device__ __forceinline__ void gett_tile(const TileParams &p, const void *pA, c
         const int nl = wn * Cfg::WTN + j * 16 + (lane & 15);
         const int64_t n = n0 + nl;
         const bool nok = n < p.N;
-        const int64_t ocn = CO ? sCOff[BM + nl] : p.offCN[n];
+        const int64_t ocn = CO ? coff(BM + nl) : p.offCN[n];
 #pragma unroll
         for (int i0 = 0; i0 < FM; i0 += EG) {
             int64_t off[EG][4];
@@ -810,7 +825,7 @@ __device__ __forceinline__ void gett_tile(const TileParams &p, const void *pA, c
                     const int ml = wm * Cfg::WTM + (i0 + e) * 16 + rr;
                     const int64_t m = m0 + ml;
                     ok[e][v] = nok && m < p.M;
-                    off[e][v] = ok[e][v] ? (CO ? sCOff[ml] : p.offCM[m]) + ocn : 0;
+                    off[e][v] = ok[e][v] ? (CO ? coff(ml) : p.offCM[m]) + ocn : 0;
 #ifdef GETT_ADDR_CHECK
                     if (ok[e][v]) ok[e][v] = gett_check_c(off[e][v], p.cLo, p.cSpan);
 #endif
@@ -879,7 +894,7 @@ __global__ __launch_bounds__(kThreads) void gett_tile_kernel(TileParams p) {
         B += p.offBH[h];
         C += p.offCH[h];
     }
-    gett_tile<PREC, BM, BN, BK, AFK, BFK, O32, TileCfg<PREC, BM, BN, BK>::kCOffFree>(
+    gett_tile<PREC, BM, BN, BK, AFK, BFK, O32, TileCfg<PREC, BM, BN, BK>::kCOffMode>(
         p, A, B, C, (int64_t)tm * BM, (int64_t)tn * BN,
                                                kbeg, kend, h * p.splits + split, smem);
 }
@@ -960,16 +975,16 @@ __device__ __forceinline__ void batch_item(const TileParams &p, int aFastK, int 
     const int64_t kend = min(p.K, kbeg + p.kPerSplit);
     const int variant = aFastK * 2 + bFastK;
     if (variant == 0)
-        gett_tile<PREC, ts.bm, ts.bn, ts.bk, false, false, false, BatchLds<PREC>::kCOff>(
+        gett_tile<PREC, ts.bm, ts.bn, ts.bk, false, false, false, BatchLds<PREC>::kCOff ? 1 : 0>(
             p, p.A, p.B, p.C, m0, n0, kbeg, kend, split, smem);
     else if (variant == 1)
-        gett_tile<PREC, ts.bm, ts.bn, ts.bk, false, true, false, BatchLds<PREC>::kCOff>(
+        gett_tile<PREC, ts.bm, ts.bn, ts.bk, false, true, false, BatchLds<PREC>::kCOff ? 1 : 0>(
             p, p.A, p.B, p.C, m0, n0, kbeg, kend, split, smem);
     else if (variant == 2)
-        gett_tile<PREC, ts.bm, ts.bn, ts.bk, true, false, false, BatchLds<PREC>::kCOff>(
+        gett_tile<PREC, ts.bm, ts.bn, ts.bk, true, false, false, BatchLds<PREC>::kCOff ? 1 : 0>(
             p, p.A, p.B, p.C, m0, n0, kbeg, kend, split, smem);
     else
-        gett_tile<PREC, ts.bm, ts.bn, ts.bk, true, true, false, BatchLds<PREC>::kCOff>(
+        gett_tile<PREC, ts.bm, ts.bn, ts.bk, true, true, false, BatchLds<PREC>::kCOff ? 1 : 0>(
             p, p.A, p.B, p.C, m0, n0, kbeg, kend, split, smem);
 }
 
